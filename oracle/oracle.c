@@ -1,0 +1,357 @@
+/*
+ * FP64 CPU oracle for parallel-beam FBP, the matched projector pair and the
+ * TV solvers of PyHST2 (Mirone et al., NIM B).  TEST INFRASTRUCTURE ONLY: it is
+ * loaded by the tests, by the smoke check and by the bench's CPU-baseline leg,
+ * never by the reconstruction library.  It is written from the definitions
+ * (plain loops, double precision, no blocking, no FFT) and shares no code with
+ * the GPU path.
+ *
+ * Conventions (section 2.1, parallel geometry):
+ *   pixel (ix, iy) centre: x = ix - (n_x-1)/2, y = iy - (n_y-1)/2, pixel units
+ *   detector coordinate of that centre at projection k:
+ *       t = s*(x cos th_k + y sin th_k) + c + sigma_k     (bin j centred at j)
+ *   hat(d) = max(0, 1 - |d|)
+ *   backprojection  B: img[px]   = sum_k sum_j q[k][j] hat(t_k(px) - j)
+ *   projection      A: sino[k][j] = s^2 sum_px img[px] hat(t_k(px) - j)
+ * so A = s^2 B^T exactly.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_PI 3.14159265358979323846
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ---------------------------------------------------------------------------
+ * Dark / flat normalisation and -log (section 2.3; Beer-Lambert for
+ * absorption data).  Flats are interpolated linearly in the projection index
+ * between their acquisition positions and held constant outside them.
+ *   p = -ln(max((I - D)/(F_k - D), eps));  p = 0 where F_k - D <= 0.
+ * raw: [K][R][nb] (radiographs, as acquired), out: [R][K][nb] (sinograms).
+ * ------------------------------------------------------------------------- */
+void or_normalize(int K, int R, int nb, const double *raw, int n_flats, const double *flats,
+                  const double *flat_pos, const double *dark, double eps, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < K; ++k) {
+        int i0 = 0, i1 = 0;
+        double a = 0.0;
+        if (n_flats > 1) {
+            if (k <= flat_pos[0]) {
+                i0 = i1 = 0;
+            } else if (k >= flat_pos[n_flats - 1]) {
+                i0 = i1 = n_flats - 1;
+            } else {
+                int i = 0;
+                while (i + 1 < n_flats && !(k < flat_pos[i + 1])) ++i;
+                i0 = i;
+                i1 = i + 1;
+                a = (k - flat_pos[i0]) / (flat_pos[i1] - flat_pos[i0]);
+            }
+        }
+        for (int r = 0; r < R; ++r) {
+            for (int j = 0; j < nb; ++j) {
+                double d = dark[(size_t)r * nb + j];
+                double f = (1.0 - a) * flats[((size_t)i0 * R + r) * nb + j] + a * flats[((size_t)i1 * R + r) * nb + j];
+                double den = f - d;
+                double v = 0.0;
+                if (den > 0.0) {
+                    double ratio = (raw[((size_t)k * R + r) * nb + j] - d) / den;
+                    if (!(ratio >= eps)) ratio = eps;
+                    v = -log(ratio);
+                }
+                out[((size_t)r * K + k) * nb + j] = v;
+            }
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Ram-Lak ramp filter at unit bin spacing (Kak & Slaney ch. 3):
+ *   h[0] = 1/4, h[n odd] = -1/(pi^2 n^2), h[n even != 0] = 0.
+ * Linear convolution restricted to [0, L), zero outside the row, each row
+ * scaled by its weight:  q[n] = w_r * sum_{m=0}^{L-1} h[n - m] p[m].
+ * ------------------------------------------------------------------------- */
+static double ramlak(long n)
+{
+    if (n == 0) return 0.25;
+    if ((n & 1) == 0) return 0.0;
+    return -1.0 / (OR_PI * OR_PI * (double)n * (double)n);
+}
+
+void or_ramp_filter(int rows, int L, const double *in, const double *w, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int r = 0; r < rows; ++r) {
+        const double *p = in + (size_t)r * L;
+        double *q = out + (size_t)r * L;
+        for (int n = 0; n < L; ++n) {
+            double acc = 0.0;
+            for (int m = 0; m < L; ++m) acc += ramlak((long)n - m) * p[m];
+            q[n] = w[r] * acc;
+        }
+    }
+}
+
+/* Angle weights: mid-point rule with circular wrap over the scan period
+ * theta_span (pi or 2 pi), scaled by 'factor'.  Angles are visited in
+ * ascending order; a negative gap is clamped to zero. */
+void or_angle_weights(int K, const double *ang, double span, double factor, double *w)
+{
+    int *ord = (int *)malloc(sizeof(int) * (size_t)K);
+    for (int i = 0; i < K; ++i) ord[i] = i;
+    /* insertion sort: plain and stable */
+    for (int i = 1; i < K; ++i) {
+        int v = ord[i], j = i - 1;
+        while (j >= 0 && ang[ord[j]] > ang[v]) { ord[j + 1] = ord[j]; --j; }
+        ord[j + 1] = v;
+    }
+    for (int i = 0; i < K; ++i) {
+        double prev = (i == 0) ? ang[ord[K - 1]] - span : ang[ord[i - 1]];
+        double next = (i == K - 1) ? ang[ord[0]] + span : ang[ord[i + 1]];
+        double g0 = ang[ord[i]] - prev, g1 = next - ang[ord[i]];
+        if (g0 < 0) g0 = 0;
+        if (g1 < 0) g1 = 0;
+        if (K == 1) { g0 = span / 2; g1 = span / 2; }
+        w[ord[i]] = factor * 0.5 * (g0 + g1);
+    }
+    free(ord);
+}
+
+/* ---------------------------------------------------------------------------
+ * Backprojection (pixel driven, linear detector interpolation as hat weights).
+ * sino: [K][L], img: [n_y][n_x].  img = sum_k sum_{j in [0,L)} q hat(t - j).
+ * ------------------------------------------------------------------------- */
+void or_backproject(int n_x, int n_y, int K, int L, const double *ang, double axis, const double *shift,
+                    double s, const double *sino, double *img)
+{
+    double cx = 0.5 * (n_x - 1), cy = 0.5 * (n_y - 1);
+#pragma omp parallel for schedule(static)
+    for (int iy = 0; iy < n_y; ++iy) {
+        for (int ix = 0; ix < n_x; ++ix) {
+            double x = ix - cx, y = iy - cy, acc = 0.0;
+            for (int k = 0; k < K; ++k) {
+                double t = s * (x * cos(ang[k]) + y * sin(ang[k])) + axis + (shift ? shift[k] : 0.0);
+                long j0 = (long)floor(t);
+                for (long j = j0; j <= j0 + 1; ++j) {
+                    if (j < 0 || j >= L) continue;
+                    double h = 1.0 - fabs(t - (double)j);
+                    if (h > 0.0) acc += sino[(size_t)k * L + j] * h;
+                }
+            }
+            img[(size_t)iy * n_x + ix] = acc;
+        }
+    }
+}
+
+/* Forward projection, written as a scatter over pixels (the transpose of the
+ * backprojection above, times s^2).  sino: [K][L] (overwritten). */
+void or_forward_project(int n_x, int n_y, int K, int L, const double *ang, double axis, const double *shift,
+                        double s, const double *img, double *sino)
+{
+    double cx = 0.5 * (n_x - 1), cy = 0.5 * (n_y - 1);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < K; ++k) {
+        double *row = sino + (size_t)k * L;
+        double c = cos(ang[k]), sn = sin(ang[k]);
+        for (int j = 0; j < L; ++j) row[j] = 0.0;
+        for (int iy = 0; iy < n_y; ++iy) {
+            for (int ix = 0; ix < n_x; ++ix) {
+                double v = img[(size_t)iy * n_x + ix];
+                if (v == 0.0) continue;
+                double t = s * ((ix - cx) * c + (iy - cy) * sn) + axis + (shift ? shift[k] : 0.0);
+                long j0 = (long)floor(t);
+                for (long j = j0; j <= j0 + 1; ++j) {
+                    if (j < 0 || j >= L) continue;
+                    double h = 1.0 - fabs(t - (double)j);
+                    if (h > 0.0) row[j] += s * s * v * h;
+                }
+            }
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Discrete isotropic TV (eq. 2) with the discretisation of Chambolle (2004):
+ * forward differences, zero at the last column / row; div = -grad^T.
+ * Arrays are [n_y][n_x]; g1 is the x (column) component, g2 the y (row) one.
+ * ------------------------------------------------------------------------- */
+void or_grad(int n_y, int n_x, const double *x, double *g1, double *g2)
+{
+    for (int i = 0; i < n_y; ++i)
+        for (int j = 0; j < n_x; ++j) {
+            size_t o = (size_t)i * n_x + j;
+            g1[o] = (j + 1 < n_x) ? x[o + 1] - x[o] : 0.0;
+            g2[o] = (i + 1 < n_y) ? x[o + n_x] - x[o] : 0.0;
+        }
+}
+
+void or_div(int n_y, int n_x, const double *q1, const double *q2, double *d)
+{
+    for (int i = 0; i < n_y; ++i)
+        for (int j = 0; j < n_x; ++j) {
+            size_t o = (size_t)i * n_x + j;
+            double a, b;
+            if (j == 0) a = q1[o];
+            else if (j == n_x - 1) a = -q1[o - 1];
+            else a = q1[o] - q1[o - 1];
+            if (i == 0) b = q2[o];
+            else if (i == n_y - 1) b = -q2[o - n_x];
+            else b = q2[o] - q2[o - n_x];
+            if (n_x == 1) a = 0.0;
+            if (n_y == 1) b = 0.0;
+            d[o] = a + b;
+        }
+}
+
+double or_tv(int n_y, int n_x, const double *x)
+{
+    size_t n = (size_t)n_y * n_x;
+    double *g1 = (double *)malloc(n * sizeof(double)), *g2 = (double *)malloc(n * sizeof(double));
+    or_grad(n_y, n_x, x, g1, g2);
+    double s = 0.0;
+    for (size_t o = 0; o < n; ++o) s += sqrt(g1[o] * g1[o] + g2[o] * g2[o]);
+    free(g1);
+    free(g2);
+    return s;
+}
+
+/* ROF proximal map  u = argmin 1/2|u - g|^2 + lambda TV(u)  by the dual
+ * projection algorithm of Chambolle (2004), step tau = 1/8, p^0 = 0:
+ *   p <- (p + tau grad(div p - g/lambda)) / (1 + tau |grad(div p - g/lambda)|)
+ *   u = g - lambda div p                                                   */
+void or_tv_prox(int n_y, int n_x, const double *g, double lambda, int n_inner, double *u)
+{
+    size_t n = (size_t)n_y * n_x;
+    if (lambda <= 0.0 || n_inner <= 0) {
+        memcpy(u, g, n * sizeof(double));
+        return;
+    }
+    double *p1 = (double *)calloc(n, sizeof(double)), *p2 = (double *)calloc(n, sizeof(double));
+    double *v = (double *)malloc(n * sizeof(double));
+    double *a1 = (double *)malloc(n * sizeof(double)), *a2 = (double *)malloc(n * sizeof(double));
+    const double tau = 0.125;
+    for (int it = 0; it < n_inner; ++it) {
+        or_div(n_y, n_x, p1, p2, v);
+        for (size_t o = 0; o < n; ++o) v[o] -= g[o] / lambda;
+        or_grad(n_y, n_x, v, a1, a2);
+        for (size_t o = 0; o < n; ++o) {
+            double m = sqrt(a1[o] * a1[o] + a2[o] * a2[o]);
+            p1[o] = (p1[o] + tau * a1[o]) / (1.0 + tau * m);
+            p2[o] = (p2[o] + tau * a2[o]) / (1.0 + tau * m);
+        }
+    }
+    or_div(n_y, n_x, p1, p2, v);
+    for (size_t o = 0; o < n; ++o) u[o] = g[o] - lambda * v[o];
+    free(p1); free(p2); free(v); free(a1); free(a2);
+}
+
+/* ---------------------------------------------------------------------------
+ * Chambolle-Pock primal-dual iteration for eq. (3):
+ *     min_x 1/2 |A x - y|^2 + lambda TV(x),   K = [A; grad],  tau = sigma = 1/Lk
+ * with theta = 1 and x = xbar = p = q = 0 initially.  One iteration:
+ *     p  <- (p + sigma (A xbar - y)) / (1 + sigma)
+ *     q  <- q + sigma grad xbar, then q <- q / max(1, |q| / lambda) pointwise
+ *     x+ <- x - tau (A^T p - div q)
+ *     xbar <- 2 x+ - x,  x <- x+
+ * 'identity' != 0 replaces A by the identity (then y has the image shape).
+ * energy[i] (if non-NULL) = 1/2|A x - y|^2 + lambda TV(x) after iteration i.
+ * ------------------------------------------------------------------------- */
+static void apply_A(int identity, int n_x, int n_y, int K, int L, const double *ang, double axis,
+                    const double *shift, double s, const double *x, double *out)
+{
+    if (identity) memcpy(out, x, sizeof(double) * (size_t)n_x * n_y);
+    else or_forward_project(n_x, n_y, K, L, ang, axis, shift, s, x, out);
+}
+
+static void apply_AT(int identity, int n_x, int n_y, int K, int L, const double *ang, double axis,
+                     const double *shift, double s, const double *y, double *out)
+{
+    size_t n = (size_t)n_x * n_y;
+    if (identity) { memcpy(out, y, sizeof(double) * n); return; }
+    or_backproject(n_x, n_y, K, L, ang, axis, shift, s, y, out);
+    for (size_t o = 0; o < n; ++o) out[o] *= s * s;
+}
+
+void or_cp_tv(int identity, int n_x, int n_y, int K, int L, const double *ang, double axis, const double *shift,
+              double s, const double *y, double lambda, int n_iter, double Lk, double *x_out, double *energy)
+{
+    size_t n = (size_t)n_x * n_y, m = identity ? n : (size_t)K * L;
+    double *x = (double *)calloc(n, sizeof(double)), *xb = (double *)calloc(n, sizeof(double));
+    double *p = (double *)calloc(m, sizeof(double)), *ax = (double *)malloc(m * sizeof(double));
+    double *q1 = (double *)calloc(n, sizeof(double)), *q2 = (double *)calloc(n, sizeof(double));
+    double *g1 = (double *)malloc(n * sizeof(double)), *g2 = (double *)malloc(n * sizeof(double));
+    double *atp = (double *)malloc(n * sizeof(double)), *dv = (double *)malloc(n * sizeof(double));
+    double tau = 1.0 / Lk, sigma = 1.0 / Lk;
+    for (int it = 0; it < n_iter; ++it) {
+        apply_A(identity, n_x, n_y, K, L, ang, axis, shift, s, xb, ax);
+        for (size_t o = 0; o < m; ++o) p[o] = (p[o] + sigma * (ax[o] - y[o])) / (1.0 + sigma);
+        or_grad(n_y, n_x, xb, g1, g2);
+        for (size_t o = 0; o < n; ++o) {
+            double a = q1[o] + sigma * g1[o], b = q2[o] + sigma * g2[o];
+            double nrm = sqrt(a * a + b * b) / lambda;
+            double d = nrm > 1.0 ? nrm : 1.0;
+            if (lambda <= 0.0) { a = 0.0; b = 0.0; d = 1.0; }
+            q1[o] = a / d;
+            q2[o] = b / d;
+        }
+        apply_AT(identity, n_x, n_y, K, L, ang, axis, shift, s, p, atp);
+        or_div(n_y, n_x, q1, q2, dv);
+        for (size_t o = 0; o < n; ++o) {
+            double xn = x[o] - tau * (atp[o] - dv[o]);
+            xb[o] = 2.0 * xn - x[o];
+            x[o] = xn;
+        }
+        if (energy) {
+            apply_A(identity, n_x, n_y, K, L, ang, axis, shift, s, x, ax);
+            double r = 0.0;
+            for (size_t o = 0; o < m; ++o) r += (ax[o] - y[o]) * (ax[o] - y[o]);
+            energy[it] = 0.5 * r + lambda * or_tv(n_y, n_x, x);
+        }
+    }
+    memcpy(x_out, x, n * sizeof(double));
+    free(x); free(xb); free(p); free(ax); free(q1); free(q2); free(g1); free(g2); free(atp); free(dv);
+}
+
+/* Operator norm |K|_2 of K = [A; grad] by power iteration on K^T K from the
+ * caller's start vector x0 (n_y*n_x).  Returns sqrt of the Rayleigh quotient. */
+double or_opnorm(int n_x, int n_y, int K, int L, const double *ang, double axis, const double *shift, double s,
+                 const double *x0, int n_iter)
+{
+    size_t n = (size_t)n_x * n_y, m = (size_t)K * L;
+    double *x = (double *)malloc(n * sizeof(double)), *ax = (double *)malloc(m * sizeof(double));
+    double *g1 = (double *)malloc(n * sizeof(double)), *g2 = (double *)malloc(n * sizeof(double));
+    double *a = (double *)malloc(n * sizeof(double)), *b = (double *)malloc(n * sizeof(double));
+    memcpy(x, x0, n * sizeof(double));
+    double nrm = 0.0, lam = 0.0;
+    for (size_t o = 0; o < n; ++o) nrm += x[o] * x[o];
+    nrm = sqrt(nrm);
+    for (size_t o = 0; o < n; ++o) x[o] /= nrm;
+    for (int it = 0; it < n_iter; ++it) {
+        or_forward_project(n_x, n_y, K, L, ang, axis, shift, s, x, ax);
+        apply_AT(0, n_x, n_y, K, L, ang, axis, shift, s, ax, a);
+        or_grad(n_y, n_x, x, g1, g2);
+        or_div(n_y, n_x, g1, g2, b);
+        for (size_t o = 0; o < n; ++o) a[o] -= b[o];       /* K^T K x = A^T A x - div grad x */
+        double dot = 0.0, nn = 0.0;
+        for (size_t o = 0; o < n; ++o) { dot += a[o] * x[o]; nn += a[o] * a[o]; }
+        lam = dot;
+        nn = sqrt(nn);
+        for (size_t o = 0; o < n; ++o) x[o] = a[o] / nn;
+    }
+    free(x); free(ax); free(g1); free(g2); free(a); free(b);
+    return sqrt(lam);
+}

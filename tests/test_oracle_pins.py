@@ -1,0 +1,384 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+closed forms, exact identities, textbook special cases and brute force.
+
+Each test names the passage it checks.  A plausible mistake in the oracle (a
+wrong sign or centre in the geometry, a dropped term in the filter, a wrong
+boundary in the TV operators, a wrong step in the solvers) fails at least one.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import Geom, SCAN_180, SCAN_360, SCAN_360_HALF
+import synth
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# ------------------------------------------------------------------ projector geometry (section 2.3)
+
+def lerp_matrix(g: Geom) -> np.ndarray:
+    """Brute force: explicit (K*nb) x (n_y*n_x) matrix of linear detector interpolation,
+    entries written from the geometry with a floor/fraction split (not the hat form)."""
+    M = np.zeros((g.K * g.n_det, g.n_y * g.n_x))
+    cx, cy = (g.n_x - 1) / 2.0, (g.n_y - 1) / 2.0
+    for k in range(g.K):
+        c, s_ = math.cos(g.angles[k]), math.sin(g.angles[k])
+        sh = 0.0 if g.shifts is None else g.shifts[k]
+        for iy in range(g.n_y):
+            for ix in range(g.n_x):
+                t = g.pixel_size * ((ix - cx) * c + (iy - cy) * s_) + g.axis + sh
+                j0 = math.floor(t)
+                f = t - j0
+                col = iy * g.n_x + ix
+                if 0 <= j0 < g.n_det:
+                    M[k * g.n_det + j0, col] += 1.0 - f
+                if 0 <= j0 + 1 < g.n_det:
+                    M[k * g.n_det + j0 + 1, col] += f
+    return M
+
+
+@pytest.mark.parametrize("K,nb,axis,shift,s", [
+    (5, 12, 5.5, False, 1.0), (7, 14, 6.25, True, 1.0), (4, 10, 4.0, True, 0.7), (6, 20, 9.3, False, 1.6)])
+def test_bruteforce_8x8(K, nb, axis, shift, s):
+    rng = np.random.default_rng(K * 100 + nb)
+    ang = np.sort(rng.uniform(0, math.pi, K))
+    g = Geom(8, 8, nb, ang, axis, rng.normal(0, 0.5, K) if shift else None, pixel_size=s)
+    M = lerp_matrix(g)
+    x = rng.standard_normal((8, 8))
+    y = rng.standard_normal((K, nb))
+    np.testing.assert_allclose(oracle.forward_project(x, g).ravel(), s * s * (M @ x.ravel()), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(oracle.backproject(y, g).ravel(), M.T @ y.ravel(), rtol=0, atol=1e-12)
+
+
+def test_adjoint_identity():
+    rng = np.random.default_rng(3)
+    g = Geom(37, 29, 50, np.sort(rng.uniform(0, math.pi, 23)), 24.3, rng.normal(0, 0.5, 23), pixel_size=0.9)
+    x = rng.standard_normal((29, 37))
+    y = rng.standard_normal((23, 50))
+    lhs = float((oracle.forward_project(x, g) * y).sum())
+    rhs = g.pixel_size ** 2 * float((x * oracle.backproject(y, g)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_mass_conservation():
+    """Hats form a partition of unity: sum_j (A x)[k][j] = s^2 sum x when every pixel lands inside."""
+    rng = np.random.default_rng(4)
+    g = Geom(16, 16, 40, np.linspace(0, math.pi, 13, endpoint=False), 19.5, rng.normal(0, 0.3, 13), pixel_size=1.2)
+    x = rng.random((16, 16))
+    sums = oracle.forward_project(x, g).sum(axis=1)
+    np.testing.assert_allclose(sums, g.pixel_size ** 2 * x.sum(), rtol=1e-13)
+
+
+def test_projection_matches_analytic_radon():
+    """With pixels much smaller than bins, A(raster) tends to the exact Radon transform
+    (Kak & Slaney ch. 3) seen through the unit hat of linear interpolation."""
+    ell = np.array([[0.35, -0.2, 0.3, 0.15, 0.6, 1.0], [-0.3, 0.25, 0.2, 0.35, 2.0, 0.5]])
+    nb, K, sub = 64, 12, 32
+    ang = synth.uniform_angles(K)
+    axis = (nb - 1) / 2.0 + 0.3
+    errs = []
+    for s in (0.5, 0.25, 0.125):
+        N = int(round(nb / s))
+        g = Geom(N, N, nb, ang, axis, pixel_size=s)
+        num = oracle.forward_project(synth.ellipse_raster(ell, N, sub=4).numpy(), g)
+        # analytic projection on a fine grid x_i = -1 + (i + 1/2)/sub, then averaged against hat(x - j)
+        fine = synth.ellipse_sinogram(ell, ang, (nb + 2) * sub, (axis + 1) * sub - 0.5, N,
+                                      pixel_size=s * sub).numpy() / sub
+        x = -1.0 + (np.arange((nb + 2) * sub) + 0.5) / sub
+        hat = np.clip(1.0 - np.abs(x[None, :] - np.arange(nb)[:, None]), 0.0, None)   # [nb][fine]
+        ref = fine @ hat.T / sub
+        errs.append(rel(num, ref))
+    assert errs[2] < errs[1] < errs[0] and errs[2] < 4e-3, errs
+
+
+def test_projection_orientation():
+    """An off-centre disc projects to t = c + (N/2)(x0 cos th + y0 sin th) (sign and axis of x, y)."""
+    N = 128
+    x0, y0 = 0.45, -0.3
+    ell = synth.disc_params(0.06, 1.0, x0, y0)
+    ang = np.array([0.0, math.pi / 2, math.pi / 4, 2.3])
+    g = Geom(N, N, N, ang, 60.0, np.array([0.0, 1.5, -2.0, 0.5]))
+    sino = oracle.forward_project(synth.ellipse_raster(ell, N, sub=8).numpy(), g)
+    j = np.arange(N)
+    for k, th in enumerate(ang):
+        centroid = (sino[k] * j).sum() / sino[k].sum()
+        expect = g.axis + g.shifts[k] + (N / 2) * (x0 * math.cos(th) + y0 * math.sin(th))
+        assert abs(centroid - expect) < 0.05, (k, centroid, expect)
+
+
+# ------------------------------------------------------------------ ramp filter
+
+def test_ramlak_frequency_response():
+    """The Ram-Lak kernel samples the band-limited ramp: its DTFT is |w|/(2 pi) on [-pi, pi]."""
+    L = 4001
+    imp = np.zeros(L)
+    imp[L // 2] = 1.0
+    h = oracle.ramp_filter(imp[None], 1.0)[0]          # h[n - L//2]
+    n = np.arange(L) - L // 2
+    for w in (0.05, 0.4, 1.0, 2.0, 3.0):
+        H = float(np.sum(h * np.cos(w * n)))
+        assert abs(H - w / (2 * math.pi)) < 2e-4, (w, H)
+    # zero DC gain in the limit, approached from above like 1/(pi^2 M)
+    dc = float(h.sum())
+    assert 0.0 < dc < 1.05 / (math.pi ** 2 * (L // 2))
+
+
+def test_disc_filtered_projection_closed_form():
+    """The ramp-filtered projection of a disc is rho/pi inside and
+    (rho/pi)(1 - |u|/sqrt(u^2 - R^2)) outside (dtheta weight 1)."""
+    L, R, rho = 1024, 150.0, 0.7
+    u = np.arange(L) - 511.5
+    p = 2 * rho * np.sqrt(np.clip(R * R - u * u, 0, None))
+    q = oracle.ramp_filter(p[None], 1.0)[0]
+    inside = np.abs(u) < R - 20
+    assert np.max(np.abs(q[inside] * math.pi / rho - 1.0)) < 3e-3
+    out = (np.abs(u) > R + 20) & (np.abs(u) < 400)
+    ref = (rho / math.pi) * (1 - np.abs(u[out]) / np.sqrt(u[out] ** 2 - R * R))
+    assert np.max(np.abs(q[out] - ref)) < 2e-3 * rho
+
+
+def test_filter_fft_equals_direct():
+    """Zero-padded FFT convolution with P >= 2L-1 gives the same linear convolution."""
+    rng = np.random.default_rng(7)
+    L = 93
+    p = rng.standard_normal((3, L))
+    q = oracle.ramp_filter(p, 1.0)
+    P = 256
+    lag = np.arange(P)
+    lag = np.where(lag < P // 2, lag, lag - P).astype(float)
+    odd = (np.abs(lag) % 2) == 1
+    hc = np.where(lag == 0, 0.25, np.where(odd, -1.0 / (math.pi ** 2 * np.maximum(lag * lag, 1.0)), 0.0))
+    hc = np.where(np.abs(lag) < L, hc, 0.0)
+    H = np.fft.fft(hc)
+    assert np.max(np.abs(H.imag)) < 1e-12          # even kernel: real spectrum (two rows per complex FFT)
+    pad = np.zeros((3, P))
+    pad[:, :L] = p
+    ref = np.fft.ifft(np.fft.fft(pad) * H.real).real[:, :L]
+    np.testing.assert_allclose(q, ref, atol=1e-12)
+
+
+# ------------------------------------------------------------------ FBP
+
+@pytest.mark.parametrize("scan,s,K", [(SCAN_180, 1.0, 180), (SCAN_180, 0.5, 120), (SCAN_360, 1.0, 240)])
+def test_fbp_disc_interior(scan, s, K):
+    """FBP of an analytic disc returns rho inside it."""
+    N, rho = 96, 0.8
+    span = math.pi if scan == SCAN_180 else 2 * math.pi
+    ang = synth.uniform_angles(K, span)
+    nb = int(math.ceil(N * s)) + 8
+    axis = (nb - 1) / 2.0 + 1.25
+    shifts = np.random.default_rng(1).normal(0, 0.5, K)
+    g = Geom(N, N, nb, ang, axis, shifts, scan=scan, pixel_size=s)
+    sino = synth.ellipse_sinogram(synth.disc_params(0.6, rho, 0.1, -0.05), ang, nb, axis, N, pixel_size=s,
+                                  shifts=shifts).numpy()
+    r = oracle.fbp(sino[None], g)[0]
+    yy, xx = np.mgrid[0:N, 0:N]
+    xn = (xx - (N - 1) / 2) * 2 / N - 0.1
+    yn = (yy - (N - 1) / 2) * 2 / N + 0.05
+    inside = xn ** 2 + yn ** 2 < 0.45 ** 2
+    assert abs(r[inside].mean() / rho - 1) < 5e-3
+    assert np.max(np.abs(r[inside] / rho - 1)) < 0.03
+
+
+def test_fbp_ellipses_converges():
+    """FBP of the ellipse phantom approaches the phantom as N and K grow."""
+    errs = []
+    for N in (64, 128):
+        d = synth.cfg_single_slice(index=5, N=N, K=2 * N, noise_frac=0.0)
+        g = Geom(N, N, N, d["angles"], d["axis"])
+        r = oracle.fbp(d["sino"].double().numpy()[None], g)[0]
+        errs.append(rel(r, d["truth"].numpy()))
+    assert errs[1] < errs[0] < 0.5, errs
+
+
+# ------------------------------------------------------------------ normalisation (section 2.3)
+
+def test_normalize_noise_free_identity():
+    rng = np.random.default_rng(9)
+    R, K, nb = 3, 11, 17
+    p = torch.as_tensor(rng.random((R, K, nb)) * 2.0)
+    raw, flats, fpos, dark, kap = synth.raw_acquisition(p, seed=5, noise=False, rounding=False)
+    out = oracle.normalize(raw, flats, fpos, dark)
+    np.testing.assert_allclose(out, kap[:, None, None] * p.numpy(), rtol=0, atol=1e-12)
+
+
+def test_normalize_flat_interpolation_and_clamp():
+    """Flats interpolate linearly between acquisition positions; I <= D clamps to -ln(eps)."""
+    K, R, nb = 9, 1, 2
+    dark = np.array([[10.0, 10.0]])
+    flats = np.array([[[110.0, 210.0]], [[130.0, 250.0]], [[90.0, 90.0]]])
+    pos = np.array([2.0, 6.0, 8.0])
+    raw = np.zeros((K, R, nb))
+    raw[:, 0, 0] = 60.0
+    raw[:, 0, 1] = 5.0
+    out = oracle.normalize(raw, flats, pos, dark)
+    f = np.array([110, 110, 110, 115, 120, 125, 130, 110, 90.0])
+    np.testing.assert_allclose(out[0, :, 0], -np.log(50.0 / (f - 10.0)), rtol=1e-14)
+    np.testing.assert_allclose(out[0, :, 1], -math.log(1e-6), rtol=1e-14)
+
+
+# ------------------------------------------------------------------ angle weights / half acquisition (section 2.1)
+
+def test_angle_weights_uniform_and_jittered():
+    K = 36
+    for scan, span, expect in ((SCAN_180, math.pi, math.pi / K), (SCAN_360, 2 * math.pi, math.pi / K),
+                               (SCAN_360_HALF, 2 * math.pi, 2 * math.pi / K)):
+        g = Geom(8, 8, 8, synth.uniform_angles(K, span), 3.5, scan=scan)
+        np.testing.assert_allclose(oracle.angle_weights(g), expect, rtol=1e-14)
+    rng = np.random.default_rng(2)
+    ang = synth.uniform_angles(K) + rng.uniform(-0.02, 0.02, K)
+    perm = rng.permutation(K)
+    w = oracle.angle_weights(Geom(8, 8, 8, ang[perm], 3.5))
+    assert abs(w.sum() - math.pi) < 1e-14 and np.all(w > 0)
+
+
+@pytest.mark.parametrize("right", [True, False])
+def test_half_acq_weights_sum_to_one(right):
+    nb = 40
+    axis = 33.0 if right else 6.0
+    g = Geom(8, 8, nb, synth.uniform_angles(8, 2 * math.pi), axis, scan=SCAN_360_HALF)
+    lay = oracle.half_acq_layout(g)
+    w, c = lay["weights"], lay["axis"]
+    j = np.arange(lay["L"])
+    for jj in j:
+        mirror = 2 * c - jj
+        if abs(mirror - round(mirror)) < 1e-12 and 0 <= mirror < lay["L"]:
+            assert abs(w[jj] + w[int(round(mirror))] - 1.0) < 1e-14
+    lo, hi = lay["offset"], lay["offset"] + nb
+    assert np.all(w[:lo] == 0) if not right else True
+    assert np.all(w[hi:] == 0)
+
+
+@pytest.mark.parametrize("right,delta", [(True, 10.0), (False, 10.0), (True, 20.5), (False, 20.5)])
+def test_half_acq_mirror_consistency(right, delta):
+    """A 360 degree half-acquisition (detector virtually doubled, section 2.1) of noise-free
+    data reconstructs exactly what a 180 degree full-detector scan with the same bin
+    alignment does: the lines at (theta, u) and (theta + pi, -u) coincide and their
+    weights sum to one, so the identity holds to rounding when 2c is an integer."""
+    N = 96
+    ell = np.array([[0.2, 0.1, 0.35, 0.25, 0.3, 1.0], [-0.4, -0.2, 0.2, 0.15, 1.1, 0.6]])
+    nb = N // 2 + int(delta) + 1
+    axis = (nb - 1 - delta) if right else delta
+    full = Geom(N, N, 2 * N, synth.uniform_angles(180), axis + N / 2)
+    ref = oracle.fbp(synth.ellipse_sinogram(ell, full.angles, 2 * N, full.axis, N).numpy()[None], full)[0]
+    half = Geom(N, N, nb, synth.uniform_angles(360, 2 * math.pi), axis, scan=SCAN_360_HALF)
+    sino = synth.ellipse_sinogram(ell, half.angles, nb, axis, N).numpy()
+    r = oracle.fbp(sino[None], half)[0]
+    yy, xx = np.mgrid[0:N, 0:N]
+    fov = (xx - (N - 1) / 2) ** 2 + (yy - (N - 1) / 2) ** 2 < (0.48 * N) ** 2     # common field of view
+    assert rel(r[fov], ref[fov]) < 1e-12
+    truth = synth.ellipse_raster(ell, N).numpy()
+    assert rel(r[fov], truth[fov]) < 0.08
+
+
+# ------------------------------------------------------------------ TV (eq. 2, Chambolle 2004)
+
+def test_grad_div_adjoint():
+    rng = np.random.default_rng(11)
+    for ny, nx in ((13, 17), (1, 9), (7, 1)):
+        x = rng.standard_normal((ny, nx))
+        q1, q2 = rng.standard_normal((ny, nx)), rng.standard_normal((ny, nx))
+        g1, g2 = oracle.grad(x)
+        lhs = float((g1 * q1 + g2 * q2).sum())
+        rhs = -float((x * oracle.div(q1, q2)).sum())
+        assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+def test_tv_values():
+    n, h = 12, 2.5
+    step = np.zeros((n, n))
+    step[:, 5:] = h
+    assert abs(oracle.tv(step) - n * h) < 1e-12
+    assert oracle.tv(np.full((n, n), 3.0)) == 0.0
+    diag = np.zeros((4, 4))
+    diag[1, 1] = 1.0     # isotropic: one pixel gives sqrt(2) at itself plus 1 + 1 at its neighbours
+    assert abs(oracle.tv(diag) - (math.sqrt(2) + 2.0)) < 1e-12
+
+
+def test_tv_prox_step_closed_form():
+    """1-D ROF of a step of height J with plateaus a, b: the plateaus move by lambda/a and lambda/b."""
+    ny, a, b, J, lam = 4, 9, 15, 1.0, 1.2
+    g = np.zeros((ny, a + b))
+    g[:, :a] = J
+    u = oracle.tv_prox(g, lam, 6000)
+    np.testing.assert_allclose(u[:, :a], J - lam / a, atol=1e-6)
+    np.testing.assert_allclose(u[:, a:], lam / b, atol=1e-6)
+
+
+def test_tv_prox_special_cases():
+    rng = np.random.default_rng(12)
+    g = rng.standard_normal((10, 14))
+    np.testing.assert_array_equal(oracle.tv_prox(g, 0.0, 50), g)
+    np.testing.assert_allclose(oracle.tv_prox(np.full((6, 7), 2.0), 0.5, 100), 2.0, atol=1e-14)
+    u = oracle.tv_prox(g, 1e4, 20000)          # lambda -> infinity gives the mean
+    np.testing.assert_allclose(u, g.mean(), atol=2e-3)
+    u = oracle.tv_prox(g, 0.3, 200)
+    assert oracle.tv(u) < oracle.tv(g)
+    assert abs(u.mean() - g.mean()) < 1e-12      # div has zero mean: the prox keeps the mean
+
+
+# ------------------------------------------------------------------ Chambolle-Pock (eq. 3)
+
+def explicit_grad(ny, nx):
+    n = ny * nx
+    G = np.zeros((2 * n, n))
+    for i in range(ny):
+        for j in range(nx):
+            o = i * nx + j
+            if j + 1 < nx:
+                G[o, o + 1], G[o, o] = 1.0, -1.0
+            if i + 1 < ny:
+                G[n + o, o + nx], G[n + o, o] = 1.0, -1.0
+    return G
+
+
+def test_opnorm_matches_svd():
+    g = Geom(8, 8, 14, synth.uniform_angles(10), 6.7, pixel_size=1.0)
+    Kmat = np.vstack([lerp_matrix(g), explicit_grad(8, 8)])
+    ref = np.linalg.norm(Kmat, 2)
+    x0 = np.random.default_rng(0).standard_normal((8, 8))
+    assert abs(oracle.opnorm(g, x0, 400) / ref - 1) < 1e-8
+
+
+def test_cp_identity_equals_rof():
+    """With A = I, eq. (3) is the ROF problem: CP and Chambolle's projection reach the same minimiser."""
+    rng = np.random.default_rng(13)
+    y = rng.standard_normal((12, 12)) * 0.3 + np.kron(np.eye(2), np.ones((6, 6)))
+    lam = 0.2
+    Lk = math.sqrt(1 + 8)
+    x = oracle.cp_tv(y, None, lam, 4000, Lk, identity_shape=(12, 12))
+    u = oracle.tv_prox(y, lam, 20000)
+    assert rel(x, u) < 1e-4
+
+
+def test_cp_lambda0_is_least_squares():
+    """With beta = 0, eq. (3) is plain least squares: CP reaches numpy's lstsq solution."""
+    g = Geom(6, 6, 12, synth.uniform_angles(40), 5.7)
+    A = lerp_matrix(g)
+    rng = np.random.default_rng(14)
+    y = A @ rng.random(36) + 0.01 * rng.standard_normal(A.shape[0])
+    ref = np.linalg.lstsq(A, y, rcond=None)[0]
+    Lk = np.linalg.norm(np.vstack([A, explicit_grad(6, 6)]), 2)
+    x, E = oracle.cp_tv(y.reshape(g.K, g.n_det), g, 0.0, 5000, Lk, energy=True)
+    assert rel(x.ravel(), ref) < 1e-8
+    assert E[-1] <= E[100] <= E[0]
+    assert abs(E[-1] - 0.5 * np.sum((A @ ref - y) ** 2)) < 1e-12
+
+
+def test_cp_energy_decreases_and_recovers_disc():
+    N = 48
+    g = Geom(N, N, N, synth.uniform_angles(60), (N - 1) / 2)
+    y = synth.ellipse_sinogram(synth.disc_params(0.5, 1.0), g.angles, N, g.axis, N).numpy()
+    Lk = oracle.opnorm(g, np.random.default_rng(0).standard_normal((N, N)), 100) * 1.01
+    x, E = oracle.cp_tv(y, g, 0.05, 300, Lk, energy=True)
+    assert E[-1] < E[50] < E[5]
+    yy, xx = np.mgrid[0:N, 0:N]
+    inside = ((xx - (N - 1) / 2) ** 2 + (yy - (N - 1) / 2) ** 2) < (0.4 * N / 2) ** 2     # disc radius 0.5 N/2
+    assert abs(x[inside].mean() - 1.0) < 0.03
