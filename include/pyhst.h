@@ -1,0 +1,202 @@
+/*
+ * pyhst.h — C ABI of the MI355X (gfx950) reconstruction library for
+ * parallel-beam tomography after PyHST2 (Mirone, Gouillart, Brun, Tafforeau,
+ * Kieffer, Nucl. Instr. Meth. B).
+ *
+ * Scope: the reconstruction path of the paper's processing pipe (section 2.3):
+ * dark/flat normalisation with time-interpolated flats and -log, the ramp
+ * filter and pixel-driven backprojection of filtered backprojection (FBP), and
+ * the projector pair plus total-variation operators of the TV-regularised
+ * iterative mode (section 3.1, eqs. (1)-(3)).
+ *
+ * Conventions shared by every entry point
+ *   - Pixel (ix, iy) of an n_x x n_y slice (row-major, ix fastest) has centre
+ *     x = ix - (n_x-1)/2, y = iy - (n_y-1)/2 in pixel units; pixels are
+ *     pixel_size (s) detector bins wide.
+ *   - Detector bin j has its centre at coordinate j.  At projection k the
+ *     centre of pixel (ix, iy) lands on
+ *         t = s (x cos th_k + y sin th_k) + axis_pos + axis_shift[k].
+ *   - hat(d) = max(0, 1 - |d|) (linear interpolation, zero outside the row).
+ *     B (backproject):      img[px]     = sum_k sum_j q[k][j] hat(t_k(px) - j)
+ *     A (forward_project):  sino[k][j]  = s^2 sum_px img[px] hat(t_k(px) - j)
+ *     so A = s^2 B^T exactly.
+ *   - FBP = B(fbp_filter(p)); it returns the attenuation per bin length.
+ *
+ * Memory and streams
+ *   - Every data pointer is a DEVICE pointer owned by the caller unless the
+ *     comment says "host".  Calls only enqueue work on the given stream and
+ *     return; outputs are valid once the stream reaches that point.
+ *   - Once a plan exists no entry point allocates device memory; scratch is
+ *     passed in by the caller (tv_prox, reconstruct_slices).
+ *   - A plan is immutable after creation except for its tile choice
+ *     (pyhst_plan_set_tiles) and the work counter used by uneven batches: two
+ *     calls on one plan may run concurrently on different streams only if the
+ *     plan is uniform (one geometry).
+ *
+ * Errors: every entry point returns PYHST_OK (0) or a negative code; no C++
+ * exception or abort crosses the ABI.  pyhst_last_error() gives the message of
+ * the calling thread's last failure.
+ */
+#ifndef PYHST_H
+#define PYHST_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PYHST_OK = 0,
+    PYHST_EARG = -1,   /* NULL pointer, non-positive size, axis outside the detector, bad layout */
+    PYHST_EGEOM = -2,  /* angular coverage below 180 (resp. 360) degrees, or a half-acquisition
+                          axis that is not in the outer quarter of the detector (section 2.1) */
+    PYHST_ENOMEM = -3, /* device allocation failed at plan creation, or work buffer too small */
+    PYHST_EHIP = -4,   /* a HIP runtime error; see pyhst_last_error() */
+    PYHST_ENUM = -5    /* non-finite energy in an iterative reconstruction */
+};
+
+enum { PYHST_SCAN_180 = 0, PYHST_SCAN_360 = 1, PYHST_SCAN_360_HALF = 2 };
+enum { PYHST_FBP = 0, PYHST_TV_CP = 1 };
+
+/* Geometry of one slice family (section 2.1: parallel beam, >= 180 degrees of
+ * rotation, optional 360 degree half acquisition with the axis near a detector
+ * border, axis displacement and angle given per projection). */
+typedef struct {
+    int32_t n_x, n_y;          /* slice size in pixels */
+    int32_t n_det;             /* detector bins per row */
+    int32_t n_angles;          /* projections */
+    const double *angles;      /* host [n_angles], radians, any order and spacing */
+    double axis_pos;           /* rotation-axis position in bin coordinates */
+    const double *axis_shift;  /* host [n_angles] per-projection axis displacement (bins), or NULL */
+    int32_t scan;              /* PYHST_SCAN_180, PYHST_SCAN_360 or PYHST_SCAN_360_HALF */
+    double pixel_size;         /* s: pixel width in bins; <= 0 means 1 */
+    double ha_overlap;         /* half acquisition: feather half-width d_f (bins); 0 = distance of the
+                                  axis to the nearer detector edge */
+} pyhst_geom;
+
+typedef struct pyhst_plan pyhst_plan;
+
+/* Where one slice of a plan lives in the packed buffers the entry points take.
+ * For a uniform plan the packed layouts are plain stacks: sinograms
+ * [S][K][n_det], filtered rows [S][K][filt_len], images [S][n_y][n_x]. */
+typedef struct {
+    int32_t n_x, n_y, n_det, n_angles;
+    int32_t filt_len;        /* row length written by fbp_filter (n_det unless half acquisition) */
+    int32_t filt_pad;        /* zero bins prepended in the filtered layout */
+    double filt_axis;        /* axis position in the filtered layout */
+    int64_t sino_offset;     /* element offset of the slice in packed [K][n_det] sinograms */
+    int64_t filt_offset;     /* element offset in packed [K][filt_len] filtered rows */
+    int64_t img_offset;      /* element offset in packed [n_y][n_x] images */
+} pyhst_slice_info;
+
+/* Create a plan for n_slices slices.  g: host [n_geom] geometries; slice_geom:
+ * host [n_slices] index into g for each slice, or NULL (all slices use g[0]).
+ * The plan copies every host array, computes FP64 angle tables, angle
+ * weights, half-acquisition weights and filter spectra, and keeps them in
+ * device memory of the current device.  Returns EARG/EGEOM on invalid
+ * geometry, ENOMEM/EHIP on device failure. */
+int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_geom, int32_t n_slices,
+                      pyhst_plan **out);
+int pyhst_plan_destroy(pyhst_plan *plan);
+int pyhst_plan_slice_info(const pyhst_plan *plan, int32_t slice, pyhst_slice_info *out);
+/* Total elements of the packed sinogram, filtered and image buffers. */
+int pyhst_plan_sizes(const pyhst_plan *plan, int64_t *sino_elems, int64_t *filt_elems, int64_t *img_elems);
+/* Backprojector tile: 0 = 64x64, 1 = 64x32, 2 = 32x64, 3 = 32x32 pixels; -1 = automatic.
+ * persistent != 0 runs the backprojector as one persistent launch over a
+ * cost-sorted (slice, tile) work list. */
+int pyhst_plan_set_tiles(pyhst_plan *plan, int32_t bp_tile, int32_t persistent);
+int pyhst_plan_get_tiles(const pyhst_plan *plan, int32_t *bp_tile, int32_t *persistent);
+
+/* Dark/flat normalisation and -log (section 2.3, first steps of the pipe;
+ * Beer-Lambert for absorption data), rearranged into sinograms (one per
+ * detector line).  Uniform plans only.
+ *   raw   [K][R][n_det] uint16 radiographs as acquired (R = n_slices)
+ *   flats [n_flats][R][n_det] float, acquired at projection positions
+ *   flat_pos host [n_flats] ascending; the flat of projection k is linearly
+ *   interpolated between the bracketing flats, held constant outside.
+ *   dark  [R][n_det] float
+ *   sino  [R][K][n_det] float:  -ln(max((I - D)/(F_k - D), eps)), 0 where F_k <= D.
+ * n_flats must be in [1, 32]. */
+int pyhst_normalize(const pyhst_plan *plan, const uint16_t *raw, const float *flats, const double *flat_pos,
+                    int32_t n_flats, const float *dark, float eps, float *sino, hipStream_t stream);
+
+/* Ramp filter of FBP (section 2.3): for every row, half-acquisition weighting
+ * and extension (360 degree half scans), then linear convolution on
+ * [0, filt_len) with the Ram-Lak kernel h[0] = 1/4, h[odd n] = -1/(pi^2 n^2)
+ * (unit bin spacing), times the angle's quadrature weight (mid-point rule over
+ * the scan period; pi/K for a uniform 180 degree scan).
+ *   sino [packed K x n_det], filt [packed K x filt_len].  In place allowed when
+ *   filt_len == n_det for every slice. */
+int fbp_filter(const pyhst_plan *plan, const float *sino, float *filt, hipStream_t stream);
+
+/* Backprojection img = alpha * B(sino) + beta * img (B as above, no angle
+ * weights).  filtered_layout = 0: rows are detector rows [K][n_det] (then
+ * alpha = s^2 gives A^T, the exact adjoint of forward_project); 1: rows are in
+ * the layout fbp_filter writes (FBP = backproject(fbp_filter(p), 1, 1, 0)).
+ * beta == 0 never reads img. */
+int backproject(const pyhst_plan *plan, const float *sino, int32_t filtered_layout, float *img, float alpha,
+                float beta, hipStream_t stream);
+
+/* Matched forward projection sino = A(img) (ray-driven gather of the same hat
+ * weights; section 2.3 and eq. (1)).  img [packed n_y x n_x], sino
+ * [packed K x n_det]. */
+int forward_project(const pyhst_plan *plan, const float *img, float *sino, hipStream_t stream);
+
+/* Proximal map of lambda*TV (isotropic TV of eq. (2), forward differences with
+ * a zero last difference):  out = argmin_u 1/2|u - in|^2 + lambda TV(u), by
+ * n_inner steps of Chambolle's (2004) dual projection with step 1/8 from a
+ * zero dual field.  in, out [n_slices][n_y][n_x]; in == out allowed.
+ * work: device scratch of at least 3*n_slices*n_y*n_x floats (work_floats
+ * gives its size); NULL or too small -> PYHST_EARG. */
+int tv_prox(int32_t n_slices, int32_t n_y, int32_t n_x, const float *in, float *out, float lambda,
+            int32_t n_inner, float *work, size_t work_floats, hipStream_t stream);
+
+/* Whole-slice reconstruction.
+ *   method PYHST_FBP: out = B(fbp_filter(normalise(raw)))   (or of sino)
+ *   method PYHST_TV_CP: eq. (3), min_x 1/2|A x - y|^2 + lambda TV(x), by
+ *     n_iter Chambolle-Pock iterations with K = [A; grad], tau = sigma =
+ *     1/op_norm, theta = 1, from zero.  op_norm <= 0: estimated by 50 power
+ *     iterations on the GPU (this synchronises the stream once).
+ *     energy (host, [n_iter]) receives 1/2|A x - y|^2 + lambda TV(x) of the
+ *     whole batch after every iteration (section 3.1: the energy is displayed
+ *     so convergence can be checked); non-NULL energy makes the call
+ *     synchronous and a non-finite energy returns PYHST_ENUM.
+ * Input: raw (uint16 [K][R][n_det] with flats, flat_pos, n_flats, dark, eps;
+ * uniform plans) or, when raw == NULL, sino (normalised line integrals,
+ * packed [K][n_det]).  out [packed n_y x n_x].
+ * work/work_bytes: device scratch; call first with out == NULL to receive the
+ * required size in *work_bytes (no work is enqueued).
+ * use_graph != 0: the launches are captured once into a HIP graph kept by the
+ * plan (keyed by every argument) and replayed on later identical calls. */
+typedef struct {
+    const uint16_t *raw;
+    const float *sino;
+    const float *flats;
+    const double *flat_pos;   /* host */
+    int32_t n_flats;
+    const float *dark;
+    float eps;
+    int32_t method;
+    float lambda;
+    int32_t n_iter;
+    double op_norm;
+    float *energy;            /* host */
+    float *out;
+    void *work;
+    size_t work_bytes;
+    int32_t use_graph;
+} pyhst_recon_args;
+
+int reconstruct_slices(const pyhst_plan *plan, pyhst_recon_args *a, hipStream_t stream);
+
+const char *pyhst_strerror(int code);
+const char *pyhst_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PYHST_H */

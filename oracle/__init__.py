@@ -71,6 +71,8 @@ def lib():
         L.or_opnorm.argtypes = [i, i, i, i, P, d, P, d, P, i]
         L.or_opnorm.restype = d
         L.or_num_threads.restype = i
+        IP = ctypes.POINTER(ctypes.c_int)
+        L.or_backproject_points.argtypes = [i, i, i, i, P, d, P, d, P, i, IP, IP, P]
         _lib = L
     return _lib
 
@@ -209,6 +211,20 @@ def backproject(sino, g: Geom, extended: bool = False) -> np.ndarray:
         lib().or_backproject(g.n_x, g.n_y, K, L, _p(g.angles), axis, _p(g.shifts), g.pixel_size, _p(si), _p(oi))
         out[i] = oi
     return out[0] if squeeze else out
+
+
+def backproject_points(sino, g: Geom, ix, iy, extended: bool = False) -> np.ndarray:
+    """B at the pixels (ix[i], iy[i]) of one slice; sino [K][L]."""
+    sino = np.ascontiguousarray(_f64(sino))
+    K, L = sino.shape
+    axis = half_acq_layout(g)["axis"] if extended else g.axis
+    ix = np.ascontiguousarray(ix, dtype=np.int32)
+    iy = np.ascontiguousarray(iy, dtype=np.int32)
+    out = np.empty(ix.shape[0])
+    IP = ctypes.POINTER(ctypes.c_int)
+    lib().or_backproject_points(g.n_x, g.n_y, K, L, _p(g.angles), axis, _p(g.shifts), g.pixel_size, _p(sino),
+                                int(ix.shape[0]), ix.ctypes.data_as(IP), iy.ctypes.data_as(IP), _p(out))
+    return out
 
 
 def forward_project(img, g: Geom) -> np.ndarray:

@@ -355,3 +355,25 @@ double or_opnorm(int n_x, int n_y, int K, int L, const double *ang, double axis,
     free(x); free(ax); free(g1); free(g2); free(a); free(b);
     return sqrt(lam);
 }
+
+/* The backprojection above evaluated at selected pixels only (ix[i], iy[i]),
+ * for checks of full-size images where computing every pixel is too slow. */
+void or_backproject_points(int n_x, int n_y, int K, int L, const double *ang, double axis, const double *shift,
+                           double s, const double *sino, int npts, const int *pix_x, const int *pix_y, double *out)
+{
+    double cx = 0.5 * (n_x - 1), cy = 0.5 * (n_y - 1);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < npts; ++i) {
+        double x = pix_x[i] - cx, y = pix_y[i] - cy, acc = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double t = s * (x * cos(ang[k]) + y * sin(ang[k])) + axis + (shift ? shift[k] : 0.0);
+            long j0 = (long)floor(t);
+            for (long j = j0; j <= j0 + 1; ++j) {
+                if (j < 0 || j >= L) continue;
+                double h = 1.0 - fabs(t - (double)j);
+                if (h > 0.0) acc += sino[(size_t)k * L + j] * h;
+            }
+        }
+        out[i] = acc;
+    }
+}

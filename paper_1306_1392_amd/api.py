@@ -1,0 +1,249 @@
+"""Python binding of the C ABI: the same entry points, taking torch CUDA tensors as
+device buffers.  Every computation runs in the HIP library; this module only
+checks shapes and passes pointers and the current stream."""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, SCAN_180, SCAN_360, SCAN_360_HALF, FBP, TV_CP  # noqa: F401
+
+
+@dataclass
+class Geometry:
+    """Parallel-beam geometry of a slice family (angles in radians, axis in bin coordinates)."""
+    n_x: int
+    n_y: int
+    n_det: int
+    angles: np.ndarray
+    axis_pos: float
+    axis_shift: np.ndarray | None = None
+    scan: int = SCAN_180
+    pixel_size: float = 1.0
+    ha_overlap: float = 0.0
+
+    def __post_init__(self):
+        self.angles = np.ascontiguousarray(self.angles, dtype=np.float64)
+        if self.axis_shift is not None:
+            self.axis_shift = np.ascontiguousarray(self.axis_shift, dtype=np.float64)
+
+    @property
+    def n_angles(self) -> int:
+        return int(self.angles.shape[0])
+
+    def _c(self) -> _lib.Geom:
+        g = _lib.Geom()
+        g.n_x, g.n_y, g.n_det, g.n_angles = self.n_x, self.n_y, self.n_det, self.n_angles
+        g.angles = self.angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        g.axis_pos = float(self.axis_pos)
+        g.axis_shift = (self.axis_shift.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                        if self.axis_shift is not None else None)
+        g.scan = int(self.scan)
+        g.pixel_size = float(self.pixel_size)
+        g.ha_overlap = float(self.ha_overlap)
+        return g
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensors only")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """Immutable reconstruction plan (FP64 angle tables, weights, filter spectra, work lists)."""
+
+    def __init__(self, geoms, n_slices: int = 1, slice_geom=None):
+        if isinstance(geoms, Geometry):
+            geoms = [geoms]
+        self.geoms = list(geoms)
+        arr = (_lib.Geom * len(self.geoms))(*[g._c() for g in self.geoms])
+        sg = None
+        if slice_geom is not None:
+            sg_np = np.ascontiguousarray(slice_geom, dtype=np.int32)
+            n_slices = int(sg_np.shape[0])
+            sg = sg_np.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        self.n_slices = int(n_slices)
+        self.slice_geom = None if slice_geom is None else np.asarray(slice_geom, dtype=np.int32)
+        h = ctypes.c_void_p()
+        self._L = _lib.lib()
+        check(self._L.pyhst_plan_create(arr, len(self.geoms), sg, self.n_slices, ctypes.byref(h)),
+              "pyhst_plan_create")
+        self.handle = h
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(self._L.pyhst_plan_sizes(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "pyhst_plan_sizes")
+        self.sino_elems, self.filt_elems, self.img_elems = a.value, b.value, c.value
+        self.uniform = self.slice_geom is None or len(set(self.slice_geom.tolist())) == 1
+
+    def slice_info(self, i: int) -> _lib.SliceInfo:
+        si = _lib.SliceInfo()
+        check(self._L.pyhst_plan_slice_info(self.handle, i, ctypes.byref(si)), "pyhst_plan_slice_info")
+        return si
+
+    def set_tiles(self, bp_tile: int = -1, persistent: bool = False):
+        check(self._L.pyhst_plan_set_tiles(self.handle, int(bp_tile), int(bool(persistent))), "pyhst_plan_set_tiles")
+
+    def get_tiles(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        check(self._L.pyhst_plan_get_tiles(self.handle, ctypes.byref(a), ctypes.byref(b)), "pyhst_plan_get_tiles")
+        return a.value, bool(b.value)
+
+    # shapes of the packed buffers of a uniform plan
+    def sino_shape(self):
+        g = self.geoms[0]
+        return (self.n_slices, g.n_angles, g.n_det) if self.uniform else (self.sino_elems,)
+
+    def filt_shape(self):
+        g = self.geoms[0]
+        return (self.n_slices, g.n_angles, self.slice_info(0).filt_len) if self.uniform else (self.filt_elems,)
+
+    def img_shape(self):
+        g = self.geoms[0]
+        return (self.n_slices, g.n_y, g.n_x) if self.uniform else (self.img_elems,)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self._L.pyhst_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _need(t: torch.Tensor, n: int, name: str, dtype=torch.float32):
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if t.numel() != n:
+        raise ValueError(f"{name}: expected {n} elements, got {t.numel()}")
+
+
+def pyhst_normalize(plan: Plan, raw, flats, flat_pos, dark, eps: float = 1e-6, out=None, stream=None):
+    """uint16 radiographs [K][R][nb] -> -log sinograms [R][K][nb]."""
+    if out is None:
+        out = torch.empty(plan.sino_shape(), device=raw.device, dtype=torch.float32)
+    _need(out, plan.sino_elems, "sino")
+    _need(raw, plan.sino_elems, "raw", torch.uint16)
+    fp = np.ascontiguousarray(flat_pos, dtype=np.float64)
+    check(_lib.lib().pyhst_normalize(plan.handle, _ptr(raw), _ptr(flats),
+                                     fp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(fp.shape[0]),
+                                     _ptr(dark), float(eps), _ptr(out), _stream(stream)), "pyhst_normalize")
+    return out
+
+
+normalize = pyhst_normalize
+
+
+def fbp_filter(plan: Plan, sino, out=None, stream=None):
+    if out is None:
+        out = torch.empty(plan.filt_shape(), device=sino.device, dtype=torch.float32)
+    _need(sino, plan.sino_elems, "sino")
+    _need(out, plan.filt_elems, "filt")
+    check(_lib.lib().fbp_filter(plan.handle, _ptr(sino), _ptr(out), _stream(stream)), "fbp_filter")
+    return out
+
+
+def backproject(plan: Plan, sino, filtered_layout: int = 0, out=None, alpha: float = 1.0, beta: float = 0.0,
+                stream=None):
+    if out is None:
+        out = torch.empty(plan.img_shape(), device=sino.device, dtype=torch.float32)
+    _need(sino, plan.filt_elems if filtered_layout else plan.sino_elems, "sino")
+    _need(out, plan.img_elems, "img")
+    check(_lib.lib().backproject(plan.handle, _ptr(sino), int(filtered_layout), _ptr(out), float(alpha), float(beta),
+                                 _stream(stream)), "backproject")
+    return out
+
+
+def forward_project(plan: Plan, img, out=None, stream=None):
+    if out is None:
+        out = torch.empty(plan.sino_shape(), device=img.device, dtype=torch.float32)
+    _need(img, plan.img_elems, "img")
+    _need(out, plan.sino_elems, "sino")
+    check(_lib.lib().forward_project(plan.handle, _ptr(img), _ptr(out), _stream(stream)), "forward_project")
+    return out
+
+
+def tv_prox(x, lam: float, n_inner: int, out=None, work=None, stream=None):
+    """ROF prox of each slice of x ([S][ny][nx] or [ny][nx])."""
+    xs = x if x.dim() == 3 else x[None]
+    S, ny, nx = xs.shape
+    if out is None:
+        out = torch.empty_like(x)
+    if work is None:
+        work = torch.empty(3 * S * ny * nx, device=x.device, dtype=torch.float32)
+    check(_lib.lib().tv_prox(S, ny, nx, _ptr(x), _ptr(out), float(lam), int(n_inner), _ptr(work), work.numel(),
+                             _stream(stream)), "tv_prox")
+    return out
+
+
+def reconstruct_slices(plan: Plan, *, raw=None, sino=None, flats=None, flat_pos=None, dark=None, eps: float = 1e-6,
+                       method: int = FBP, lam: float = 0.0, n_iter: int = 0, op_norm: float = 0.0,
+                       energy: bool = False, out=None, work=None, use_graph: bool = False, stream=None):
+    """Returns out (and the energy trace as a numpy array when energy=True)."""
+    a = _lib.ReconArgs()
+    a.raw = _ptr(raw)
+    a.sino = _ptr(sino)
+    a.flats = _ptr(flats)
+    fp = None
+    if flat_pos is not None:
+        fp = np.ascontiguousarray(flat_pos, dtype=np.float64)
+        a.flat_pos = fp.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        a.n_flats = int(fp.shape[0])
+    a.dark = _ptr(dark)
+    a.eps = float(eps)
+    a.method = int(method)
+    a.lambda_ = float(lam)
+    a.n_iter = int(n_iter)
+    a.op_norm = float(op_norm)
+    a.use_graph = int(bool(use_graph))
+    L = _lib.lib()
+    # size query
+    a.out = None
+    check(L.reconstruct_slices(plan.handle, ctypes.byref(a), _stream(stream)), "reconstruct_slices(query)")
+    need = a.work_bytes
+    dev = (raw if raw is not None else sino).device
+    if work is None or work.numel() * work.element_size() < need:
+        work = torch.empty(max(need, 1), device=dev, dtype=torch.uint8)
+    if out is None:
+        out = torch.empty(plan.img_shape(), device=dev, dtype=torch.float32)
+    _need(out, plan.img_elems, "out")
+    E = None
+    if energy:
+        E = np.zeros(max(n_iter, 1), dtype=np.float32)
+        a.energy = E.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    a.out = _ptr(out)
+    a.work = _ptr(work)
+    a.work_bytes = work.numel() * work.element_size()
+    check(L.reconstruct_slices(plan.handle, ctypes.byref(a), _stream(stream)), "reconstruct_slices")
+    return (out, E[:n_iter]) if energy else out
+
+
+def work_bytes(plan: Plan, **kw) -> int:
+    a = _lib.ReconArgs()
+    a.raw = _ptr(kw.get("raw"))
+    a.sino = _ptr(kw.get("sino"))
+    a.method = int(kw.get("method", FBP))
+    a.n_iter = int(kw.get("n_iter", 0))
+    a.out = None
+    check(_lib.lib().reconstruct_slices(plan.handle, ctypes.byref(a), None), "reconstruct_slices(query)")
+    return a.work_bytes
+
+
+def uniform_angles(K: int, span: float = math.pi) -> np.ndarray:
+    return np.arange(K, dtype=np.float64) * (span / K)

@@ -1,0 +1,144 @@
+// Internal declarations shared by the host plan code and the kernel
+// translation units of the gfx950 reconstruction library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "pyhst.h"
+
+namespace pyhst {
+
+// Backprojector tile configurations.  A workgroup is 4 wavefronts; each lane
+// owns one pixel of every 8x8 block its wave covers; a wave covers BX x BY
+// blocks, the 4 waves are stacked in y.  Tile = (8 BX) x (32 BY) pixels.
+constexpr int N_TILE_CFG = 4;
+constexpr int TILE_BX[N_TILE_CFG] = {8, 8, 4, 4};
+constexpr int TILE_BY[N_TILE_CFG] = {2, 1, 2, 1};
+inline constexpr int tile_w(int c) { return 8 * TILE_BX[c]; }
+inline constexpr int tile_h(int c) { return 32 * TILE_BY[c]; }
+
+// Floats per projection in the backprojection scalar table:
+// [0] s cos, [1] s sin, [2 + 8 by + bx] = 8 s (bx cos + by sin), bx < 8, by < 2.
+constexpr int BPT = 20;
+
+// One slice geometry, as the kernels read it (device memory, read-only).
+struct GeoDev {
+    int32_t nx, ny, nb, K;
+    int32_t Lf, fpad;         // filtered-row layout: length, zero bins prepended
+    int32_t P, log2P;         // FFT length of the ramp filter (P >= 2 Lf - 1)
+    double s;                 // pixel size in bins
+    double axis, axis_f;      // axis position: detector layout, filtered layout
+    int64_t ang_off;          // first projection of this geometry in the per-angle tables
+    int64_t hw_off;           // first element of its half-acquisition weights [Lf]
+    int64_t spec_off;         // first element of its filter spectrum [P] (bit-reversed order, 1/P folded)
+    int32_t bp_w[N_TILE_CFG]; // LDS window length (bins) per tile configuration
+    int32_t ntx[N_TILE_CFG];  // tiles along x per tile configuration
+};
+
+struct SliceDev {
+    int32_t g, pad;
+    int64_t sino_off, filt_off, img_off;
+};
+
+struct Tables {
+    const GeoDev *geo;
+    const SliceDev *slc;
+    const double *cosd, *sind, *shiftd;  // [sum K]
+    const float *bpt;                    // [sum K][BPT]
+    const float *wang;                   // [sum K] quadrature weights
+    const float *haw;                    // half-acquisition weights
+    const float *spec;                   // filter spectra
+    const float2 *twid;                  // exp(-2 pi i m / Pmax), m < Pmax/2
+    const int2 *pairs;                   // filter work: (slice, first projection of a row pair)
+    const int2 *items[N_TILE_CFG];       // backprojection work: (slice, tile), costliest first
+    int *counter;                        // persistent work counter
+    int32_t Pmax, log2Pmax;
+};
+
+struct GeoHost {
+    pyhst_geom g;
+    std::vector<double> ang, shift;
+    double s;
+    int Lf, fpad;
+    double axis_f;
+    int P, log2P;
+    std::vector<double> w;      // angle weights
+    std::vector<double> haw;    // [Lf]
+};
+
+}  // namespace pyhst
+
+struct pyhst_plan {
+    int device = 0;
+    int n_geom = 0, n_slices = 0;
+    bool uniform = true;
+    std::vector<pyhst::GeoHost> gh;
+    std::vector<pyhst::GeoDev> gd;
+    std::vector<pyhst::SliceDev> sd;
+    int64_t sino_elems = 0, filt_elems = 0, img_elems = 0;
+    int64_t max_K = 0;
+    int n_pairs = 0;
+    int64_t n_items[pyhst::N_TILE_CFG] = {0, 0, 0, 0};
+    int bp_tile = -1, persistent = 0;
+    void *dev_block = nullptr;
+    pyhst::Tables t{};
+    int cu_count = 256;
+    std::mutex mu;
+    std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
+};
+
+namespace pyhst {
+
+// thread-local error message
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *where);
+
+int choose_tile(const pyhst_plan &p);
+
+// CP epilogues
+struct CpPrimal {   // x+ = x - tau (alpha B p - div q); xbar = 2 x+ - x
+    float *x, *xbar;
+    const float *q1, *q2;
+    float tau;
+};
+struct CpDual {     // p = (p + sigma (alpha A xbar - y)) / (1 + sigma)
+    float *p;
+    const float *y;
+    float sigma;
+};
+
+// launchers (return hipGetLastError())
+hipError_t launch_normalize(const pyhst_plan &p, const uint16_t *raw, const float *flats, const double *flat_pos,
+                            int n_flats, const float *dark, float eps, float *sino, hipStream_t st);
+hipError_t launch_filter(const pyhst_plan &p, const float *sino, const uint16_t *raw, const float *flats,
+                         const double *flat_pos, int n_flats, const float *dark, float eps, float *filt,
+                         hipStream_t st);
+hipError_t launch_backproject(const pyhst_plan &p, const float *sino, int filtered, float *img, float alpha,
+                              float beta, const CpPrimal *cp, hipStream_t st);
+hipError_t launch_forward(const pyhst_plan &p, const float *img, float *sino, float alpha, const CpDual *cp,
+                          hipStream_t st);
+
+// TV / CP helpers (k_tv.hip); images are packed by the plan's img offsets when a plan is given,
+// otherwise a plain [S][ny][nx] stack.
+hipError_t launch_tv_prox(int S, int ny, int nx, const float *in, float *out, float lambda, int n_inner,
+                          float *work, hipStream_t st);
+hipError_t launch_cp_dual_q(const pyhst_plan &p, const float *xbar, float *q1, float *q2, float sigma,
+                            float lambda, hipStream_t st);
+hipError_t launch_fill(float *buf, int64_t n, float v, hipStream_t st);
+hipError_t launch_cp_energy(const pyhst_plan &p, const float *ax, const float *y, const float *x, float lambda,
+                            double *partials, int n_part, float *energy_dev, hipStream_t st);
+int energy_partials(const pyhst_plan &p);
+hipError_t launch_axpby(float *y, const float *x, int64_t n, float a, float b, hipStream_t st);
+hipError_t launch_power_step(const pyhst_plan &p, const float *x, float *out, float *tmp_sino,
+                             double *partials, int n_part, double *norm_dev, hipStream_t st);
+hipError_t launch_scale_by_inv(float *x, int64_t n, const double *norm_dev, hipStream_t st);
+
+}  // namespace pyhst

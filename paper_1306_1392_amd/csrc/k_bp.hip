@@ -1,0 +1,212 @@
+// Pixel-driven backprojection with linear detector interpolation (section 2.3:
+// the reconstructed slice is cut into tiles, one workgroup per tile).
+//
+// gfx950 design.  The paper reads the sinogram through a texture with hardware
+// interpolation; here a block of AB projections' detector windows is staged in
+// LDS as (q[j], q[j+1] - q[j]) pairs and interpolated in FP32 registers:
+//   per update: t = t0 + off (1), i = trunc(t) (1), f = fract(t) (1),
+//   LDS address (1), ds_read_b64, acc += q (1), acc = fma(f, dq, acc) (1).
+// Coordinates: per (tile, projection) the tile-origin coordinate is computed in
+// FP64 and split into an integer window base and an FP32 remainder, so every
+// FP32 coordinate stays below ~100 bins (ulp < 8e-6 bin).  Lanes of a wave own
+// one 8x8 pixel block per register slot, so one ds_read_b64 of a wave touches
+// at most ~13 consecutive window entries (no bank conflicts).  The per-block
+// coordinate offsets are wave-uniform and come from a scalar table.
+#include "internal.hpp"
+
+namespace pyhst {
+
+namespace {
+
+constexpr int AB = 32;   // projections staged per LDS block
+
+// The per-projection table is read through the constant address space so that
+// the wave-uniform loads become scalar loads into SGPRs.
+typedef __attribute__((address_space(4))) const float cfloat;
+
+template <int CFG, int MODE>
+__global__ __launch_bounds__(256) void bp_kernel(Tables T, const float *__restrict__ sino, int filtered,
+                                                 float *__restrict__ img, float alpha, float beta,
+                                                 int64_t n_items, int persistent, CpPrimal cp)
+{
+    constexpr int BX = TILE_BX[CFG], BY = TILE_BY[CFG];
+    constexpr int TW = 8 * BX, TH = 32 * BY;
+    constexpr int PX = BX * BY;
+    extern __shared__ float2 win[];   // [AB][W]
+    __shared__ int s_jb[AB];
+    __shared__ float s_r[AB];
+    __shared__ int64_t s_item;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int lx = lane & 7, ly = lane >> 3;
+    const float flx = (float)lx, fly = (float)(ly + 8 * BY * wv);
+
+    for (int64_t round = 0;; ++round) {
+        int64_t item;
+        if (persistent) {
+            if (tid == 0) s_item = atomicAdd(T.counter, 1);
+            __syncthreads();
+            item = s_item;
+            __syncthreads();
+        } else {
+            if (round > 0) break;
+            item = blockIdx.x;
+        }
+        if (item >= n_items) break;
+
+        const int2 wi = T.items[CFG][item];
+        const SliceDev sd = T.slc[wi.x];
+        const GeoDev &g = T.geo[sd.g];
+        const int nx = g.nx, ny = g.ny, K = g.K;
+        const int L = filtered ? g.Lf : g.nb;
+        const double axis = filtered ? g.axis_f : g.axis;
+        const float *rows = sino + (filtered ? sd.filt_off : sd.sino_off);
+        const int W = g.bp_w[CFG];
+        const float invW = 1.0f / (float)W;
+        const int ntx = g.ntx[CFG];
+        const int tx = wi.y % ntx, ty = wi.y / ntx;
+        const int ix0 = tx * TW, iy0 = ty * TH;
+        const double x0 = ix0 - 0.5 * (nx - 1), y0 = iy0 - 0.5 * (ny - 1);
+        const double s = g.s;
+        const double *cosd = T.cosd + g.ang_off, *sind = T.sind + g.ang_off, *shd = T.shiftd + g.ang_off;
+        const cfloat *tab = (const cfloat *)(T.bpt + g.ang_off * BPT);
+
+        float acc[PX];
+#pragma unroll
+        for (int p = 0; p < PX; ++p) acc[p] = 0.0f;
+
+        for (int kb = 0; kb < K; kb += AB) {
+            const int na = min(AB, K - kb);
+            if (tid < na) {
+                const int k = kb + tid;
+                const double c = cosd[k], sn = sind[k];
+                const double torg = axis + shd[k] + s * (x0 * c + y0 * sn);
+                const double tmin = torg + s * ((TW - 1) * fmin(c, 0.0) + (TH - 1) * fmin(sn, 0.0));
+                const int jb = (int)floor(tmin) - 1;
+                s_jb[tid] = jb;
+                s_r[tid] = (float)(torg - (double)jb);
+            }
+            __syncthreads();
+            const int tot = na * W;
+            for (int e = tid; e < tot; e += 256) {
+                const int a = (int)(((float)e + 0.5f) * invW);
+                const int j = s_jb[a] + (e - a * W);
+                const float *row = rows + (int64_t)(kb + a) * L;
+                const float q0 = ((unsigned)j < (unsigned)L) ? row[j] : 0.0f;
+                const float q1 = ((unsigned)(j + 1) < (unsigned)L) ? row[j + 1] : 0.0f;
+                win[e] = make_float2(q0, q1 - q0);
+            }
+            __syncthreads();
+            for (int a = 0; a < na; ++a) {
+                const cfloat *tk = tab + (int64_t)(kb + a) * BPT;
+                const float t0 = fmaf(fly, tk[1], fmaf(flx, tk[0], s_r[a]));
+                const float2 *wa = win + a * W;
+#pragma unroll
+                for (int by = 0; by < BY; ++by) {
+#pragma unroll
+                    for (int bx = 0; bx < BX; ++bx) {
+                        const float t = t0 + tk[2 + 8 * by + bx];
+                        const int i = (int)t;
+                        const float f = __builtin_amdgcn_fractf(t);
+                        const float2 v = wa[i];
+                        float &A = acc[by * BX + bx];
+                        A += v.x;
+                        A = fmaf(f, v.y, A);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+
+        // epilogue
+        const int64_t ioff = sd.img_off;
+#pragma unroll
+        for (int by = 0; by < BY; ++by) {
+#pragma unroll
+            for (int bx = 0; bx < BX; ++bx) {
+                const int ix = ix0 + 8 * bx + lx;
+                const int iy = iy0 + 8 * BY * wv + 8 * by + ly;
+                if (ix < nx && iy < ny) {
+                    const int64_t o = ioff + (int64_t)iy * nx + ix;
+                    const float v = alpha * acc[by * BX + bx];
+                    if (MODE == 0) {
+                        img[o] = (beta != 0.0f) ? fmaf(beta, img[o], v) : v;
+                    } else {
+                        // Chambolle-Pock primal step: x+ = x - tau (A^T p - div q)
+                        float dq1, dq2;
+                        if (nx == 1) dq1 = 0.0f;
+                        else if (ix == 0) dq1 = cp.q1[o];
+                        else if (ix == nx - 1) dq1 = -cp.q1[o - 1];
+                        else dq1 = cp.q1[o] - cp.q1[o - 1];
+                        if (ny == 1) dq2 = 0.0f;
+                        else if (iy == 0) dq2 = cp.q2[o];
+                        else if (iy == ny - 1) dq2 = -cp.q2[o - nx];
+                        else dq2 = cp.q2[o] - cp.q2[o - nx];
+                        const float xo = cp.x[o];
+                        const float xn = xo - cp.tau * (v - (dq1 + dq2));
+                        cp.x[o] = xn;
+                        cp.xbar[o] = 2.0f * xn - xo;
+                    }
+                }
+            }
+        }
+    }
+}
+
+__global__ void zero_counter(int *c) { *c = 0; }
+
+template <int CFG, int MODE>
+hipError_t launch_cfg(const pyhst_plan &p, const float *sino, int filtered, float *img, float alpha, float beta,
+                      const CpPrimal &cp, hipStream_t st)
+{
+    int wmax = 0;
+    for (const auto &g : p.gd) wmax = std::max(wmax, g.bp_w[CFG]);
+    const size_t lds = (size_t)AB * wmax * sizeof(float2);
+    const int64_t n = p.n_items[CFG];
+    if (n == 0) return hipSuccess;
+    if (lds > 65536) {
+        if (lds > 160 * 1024) return hipErrorInvalidValue;
+        hipError_t e = hipFuncSetAttribute((const void *)bp_kernel<CFG, MODE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    if (p.persistent) {
+        zero_counter<<<1, 1, 0, st>>>(p.t.counter);
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bp_kernel<CFG, MODE>, 256, lds);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
+        int64_t grid = (int64_t)per_cu * p.cu_count;
+        if (grid > n) grid = n;
+        bp_kernel<CFG, MODE><<<(unsigned)grid, 256, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n, 1, cp);
+    } else {
+        bp_kernel<CFG, MODE><<<(unsigned)n, 256, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n, 0, cp);
+    }
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_mode(const pyhst_plan &p, int cfg, const float *sino, int filtered, float *img, float alpha,
+                       float beta, const CpPrimal &cp, hipStream_t st)
+{
+    switch (cfg) {
+    case 0: return launch_cfg<0, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
+    case 1: return launch_cfg<1, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
+    case 2: return launch_cfg<2, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
+    default: return launch_cfg<3, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_backproject(const pyhst_plan &p, const float *sino, int filtered, float *img, float alpha,
+                              float beta, const CpPrimal *cp, hipStream_t st)
+{
+    const int cfg = choose_tile(p);
+    if (cp) return launch_mode<1>(p, cfg, sino, filtered, img, alpha, 0.0f, *cp, st);
+    CpPrimal none{};
+    return launch_mode<0>(p, cfg, sino, filtered, img, alpha, beta, none, st);
+}
+
+}  // namespace pyhst

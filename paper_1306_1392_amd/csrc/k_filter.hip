@@ -1,0 +1,261 @@
+// Dark/flat normalisation with -log (section 2.3) and the ramp filter of FBP.
+//
+// The filter is a linear convolution with the Ram-Lak kernel on [0, L), done
+// as a zero-padded FFT of length P >= 2L - 1 in LDS (the circular result then
+// equals the linear one on [0, L)).  The kernel is real and even, so its
+// spectrum is real and two real rows share one complex FFT (row a in the real
+// part, row b in the imaginary part).  Forward: decimation in frequency,
+// natural in, bit-reversed out; the spectrum is stored bit-reversed with 1/P
+// folded in; inverse: decimation in time, bit-reversed in, natural out.  Two
+// radix-2 stages are fused per LDS pass (radix-4 data movement).
+//
+// For raw input the normalisation is fused into the load: uint16 radiograph
+// rows are read in acquisition order [K][R][nb] and the filtered rows are
+// written in sinogram order [R][K][L], so the -log sinogram never goes to HBM.
+#include "internal.hpp"
+
+namespace pyhst {
+
+struct FlatInfo {
+    double pos[32];
+    int n;
+};
+
+namespace {
+
+__device__ inline float2 operator+(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ inline float2 operator-(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ inline float2 cmul(float2 a, float2 w) { return make_float2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x); }
+__device__ inline float2 cmulc(float2 a, float2 w) { return make_float2(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y); }
+
+__device__ inline void flat_interp(const FlatInfo &fi, int k, int &i0, int &i1, float &a)
+{
+    i0 = i1 = 0;
+    double al = 0.0;
+    if (fi.n > 1) {
+        if (k <= fi.pos[0]) {
+            i0 = i1 = 0;
+        } else if (k >= fi.pos[fi.n - 1]) {
+            i0 = i1 = fi.n - 1;
+        } else {
+            int i = 0;
+            while (i + 1 < fi.n && !(k < fi.pos[i + 1])) ++i;
+            i0 = i;
+            i1 = i + 1;
+            al = ((double)k - fi.pos[i0]) / (fi.pos[i1] - fi.pos[i0]);
+        }
+    }
+    a = (float)al;
+}
+
+__device__ inline float norm_value(float I, float d, float f0, float f1, float a, float eps)
+{
+    const float f = (1.0f - a) * f0 + a * f1;
+    const float den = f - d;
+    if (!(den > 0.0f)) return 0.0f;
+    float ratio = (I - d) / den;
+    if (!(ratio >= eps)) ratio = eps;
+    return -logf(ratio);
+}
+
+__global__ __launch_bounds__(256) void normalize_kernel(const uint16_t *__restrict__ raw,
+                                                        const float *__restrict__ flats, FlatInfo fi,
+                                                        const float *__restrict__ dark, float eps, int K, int R,
+                                                        int nb, float *__restrict__ out)
+{
+    const int row = blockIdx.x;          // raw row order: k * R + r
+    const int k = row / R, r = row - k * R;
+    int i0, i1;
+    float a;
+    flat_interp(fi, k, i0, i1, a);
+    const uint16_t *src = raw + (int64_t)row * nb;
+    const float *f0 = flats + ((int64_t)i0 * R + r) * nb;
+    const float *f1 = flats + ((int64_t)i1 * R + r) * nb;
+    const float *dk = dark + (int64_t)r * nb;
+    float *dst = out + ((int64_t)r * K + k) * nb;
+    for (int j = threadIdx.x; j < nb; j += blockDim.x)
+        dst[j] = norm_value((float)src[j], dk[j], f0[j], f1[j], a, eps);
+}
+
+__device__ void fft_forward(float2 *z, int P, int lg, const float2 *__restrict__ tw, int lgmax)
+{
+    int h = P >> 1, lh = lg - 1;
+    while (h >= 2) {
+        const int h2 = h >> 1;
+        for (int t = threadIdx.x; t < (P >> 2); t += blockDim.x) {
+            const int gq = t >> (lh - 1), i = t & (h2 - 1);
+            const int b0 = (gq << (lh + 1)) + i;
+            const float2 e0 = z[b0], e1 = z[b0 + h2], e2 = z[b0 + h], e3 = z[b0 + h + h2];
+            const float2 w0 = tw[i << (lgmax - lh - 1)];
+            const float2 w1 = tw[(i + h2) << (lgmax - lh - 1)];
+            const float2 w2 = tw[i << (lgmax - lh)];
+            const float2 s0 = e0 + e2, d0 = cmul(e0 - e2, w0);
+            const float2 s1 = e1 + e3, d1 = cmul(e1 - e3, w1);
+            z[b0] = s0 + s1;
+            z[b0 + h2] = cmul(s0 - s1, w2);
+            z[b0 + h] = d0 + d1;
+            z[b0 + h + h2] = cmul(d0 - d1, w2);
+        }
+        __syncthreads();
+        h >>= 2;
+        lh -= 2;
+    }
+    if (h == 1) {
+        for (int t = threadIdx.x; t < (P >> 1); t += blockDim.x) {
+            const float2 a = z[2 * t], b = z[2 * t + 1];
+            z[2 * t] = a + b;
+            z[2 * t + 1] = a - b;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void fft_inverse(float2 *z, int P, int lg, const float2 *__restrict__ tw, int lgmax)
+{
+    int h = 1, lh = 0;
+    if (lg & 1) {
+        for (int t = threadIdx.x; t < (P >> 1); t += blockDim.x) {
+            const float2 a = z[2 * t], b = z[2 * t + 1];
+            z[2 * t] = a + b;
+            z[2 * t + 1] = a - b;
+        }
+        __syncthreads();
+        h = 2;
+        lh = 1;
+    }
+    while (h < P) {
+        for (int t = threadIdx.x; t < (P >> 2); t += blockDim.x) {
+            const int gq = t >> lh, i = t & (h - 1);
+            const int b0 = (gq << (lh + 2)) + i;
+            const float2 e0 = z[b0], e1 = z[b0 + h], e2 = z[b0 + 2 * h], e3 = z[b0 + 3 * h];
+            const float2 w = tw[i << (lgmax - lh - 1)];
+            const float2 b1 = cmulc(e1, w), b3 = cmulc(e3, w);
+            const float2 s0 = e0 + b1, d0 = e0 - b1, s1 = e2 + b3, d1 = e2 - b3;
+            const float2 t1 = cmulc(s1, tw[i << (lgmax - lh - 2)]);
+            const float2 t2 = cmulc(d1, tw[(i + h) << (lgmax - lh - 2)]);
+            z[b0] = s0 + t1;
+            z[b0 + 2 * h] = s0 - t1;
+            z[b0 + h] = d0 + t2;
+            z[b0 + 3 * h] = d0 - t2;
+        }
+        __syncthreads();
+        h <<= 2;
+        lh += 2;
+    }
+}
+
+template <bool RAW>
+__global__ __launch_bounds__(256) void filter_kernel(Tables T, const float *__restrict__ sino,
+                                                     const uint16_t *__restrict__ raw,
+                                                     const float *__restrict__ flats, FlatInfo fi,
+                                                     const float *__restrict__ dark, float eps, int R,
+                                                     float *__restrict__ out)
+{
+    extern __shared__ float2 z[];
+    const int2 pr = T.pairs[blockIdx.x];
+    const SliceDev sd = T.slc[pr.x];
+    const GeoDev &g = T.geo[sd.g];
+    const int K = g.K, nb = g.nb, Lf = g.Lf, pad = g.fpad, P = g.P, lg = g.log2P;
+    const int ka = pr.y, kb = pr.y + 1;
+    const bool hasb = kb < K;
+    const float *hw = T.haw + g.hw_off;
+
+    int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    float aa = 0.0f, ab = 0.0f;
+    if (RAW) {
+        flat_interp(fi, ka, a0, a1, aa);
+        flat_interp(fi, hasb ? kb : ka, b0, b1, ab);
+    }
+    const int r = pr.x;   // raw input: uniform plan, slice index = detector row
+    for (int n = threadIdx.x; n < P; n += blockDim.x) {
+        float va = 0.0f, vb = 0.0f;
+        const int jj = n - pad;
+        if (n < Lf && jj >= 0 && jj < nb) {
+            const float w = hw[n];
+            if (RAW) {
+                const float d = dark[(int64_t)r * nb + jj];
+                const float Ia = (float)raw[((int64_t)ka * R + r) * nb + jj];
+                va = norm_value(Ia, d, flats[((int64_t)a0 * R + r) * nb + jj], flats[((int64_t)a1 * R + r) * nb + jj],
+                                aa, eps);
+                if (hasb) {
+                    const float Ib = (float)raw[((int64_t)kb * R + r) * nb + jj];
+                    vb = norm_value(Ib, d, flats[((int64_t)b0 * R + r) * nb + jj],
+                                    flats[((int64_t)b1 * R + r) * nb + jj], ab, eps);
+                }
+            } else {
+                va = sino[sd.sino_off + (int64_t)ka * nb + jj];
+                vb = hasb ? sino[sd.sino_off + (int64_t)kb * nb + jj] : 0.0f;
+            }
+            va *= w;
+            vb *= w;
+        }
+        z[n] = make_float2(va, vb);
+    }
+    __syncthreads();
+    fft_forward(z, P, lg, T.twid, T.log2Pmax);
+    const float *H = T.spec + g.spec_off;
+    for (int n = threadIdx.x; n < P; n += blockDim.x) {
+        const float h = H[n];
+        const float2 v = z[n];
+        z[n] = make_float2(v.x * h, v.y * h);
+    }
+    __syncthreads();
+    fft_inverse(z, P, lg, T.twid, T.log2Pmax);
+    const float wa = T.wang[g.ang_off + ka];
+    const float wb = hasb ? T.wang[g.ang_off + kb] : 0.0f;
+    float *oa = out + sd.filt_off + (int64_t)ka * Lf;
+    for (int n = threadIdx.x; n < Lf; n += blockDim.x) {
+        const float2 v = z[n];
+        oa[n] = wa * v.x;
+        if (hasb) oa[Lf + n] = wb * v.y;
+    }
+}
+
+FlatInfo make_flats(const double *pos, int n)
+{
+    FlatInfo fi{};
+    fi.n = n;
+    for (int i = 0; i < n && i < 32; ++i) fi.pos[i] = pos[i];
+    return fi;
+}
+
+}  // namespace
+
+hipError_t launch_normalize(const pyhst_plan &p, const uint16_t *raw, const float *flats, const double *flat_pos,
+                            int n_flats, const float *dark, float eps, float *sino, hipStream_t st)
+{
+    const GeoDev &g = p.gd[0];
+    const int R = p.n_slices;
+    normalize_kernel<<<(unsigned)((int64_t)g.K * R), 256, 0, st>>>(raw, flats, make_flats(flat_pos, n_flats), dark,
+                                                                   eps, g.K, R, g.nb, sino);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter(const pyhst_plan &p, const float *sino, const uint16_t *raw, const float *flats,
+                         const double *flat_pos, int n_flats, const float *dark, float eps, float *filt,
+                         hipStream_t st)
+{
+    int Pmax = 0;
+    for (const auto &g : p.gd) Pmax = std::max(Pmax, g.P);
+    const size_t lds = (size_t)Pmax * sizeof(float2);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)filter_kernel<true>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)filter_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    if (raw) {
+        filter_kernel<true><<<(unsigned)p.n_pairs, 256, lds, st>>>(p.t, nullptr, raw, flats,
+                                                                   make_flats(flat_pos, n_flats), dark, eps,
+                                                                   p.n_slices, filt);
+    } else {
+        FlatInfo none{};
+        filter_kernel<false><<<(unsigned)p.n_pairs, 256, lds, st>>>(p.t, sino, nullptr, nullptr, none, nullptr, 0.0f,
+                                                                    p.n_slices, filt);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pyhst

@@ -1,0 +1,284 @@
+// Total-variation operators (eq. (2), discretised as in Chambolle (2004):
+// forward differences with a zero last difference, div = -grad^T), the ROF
+// proximal map, the Chambolle-Pock dual TV step, the energy of eq. (3) and the
+// power iteration for |[A; grad]|.  Memory-bound stencils: one pass over the
+// image per step, neighbours come from L1/L2.  Reductions are deterministic:
+// per-workgroup FP64 partials, then one workgroup sums them in a fixed order.
+#include "internal.hpp"
+
+namespace pyhst {
+
+namespace {
+
+__device__ inline float grad_x(const float *x, int64_t o, int ix, int nx) { return ix + 1 < nx ? x[o + 1] - x[o] : 0.0f; }
+__device__ inline float grad_y(const float *x, int64_t o, int iy, int ny, int nx)
+{
+    return iy + 1 < ny ? x[o + nx] - x[o] : 0.0f;
+}
+__device__ inline float divergence(const float *q1, const float *q2, int64_t o, int ix, int iy, int nx, int ny)
+{
+    float a, b;
+    if (nx == 1) a = 0.0f;
+    else if (ix == 0) a = q1[o];
+    else if (ix == nx - 1) a = -q1[o - 1];
+    else a = q1[o] - q1[o - 1];
+    if (ny == 1) b = 0.0f;
+    else if (iy == 0) b = q2[o];
+    else if (iy == ny - 1) b = -q2[o - nx];
+    else b = q2[o] - q2[o - nx];
+    return a + b;
+}
+
+// v = div p - g / lambda
+__global__ void prox_div_kernel(int64_t n, int ny, int nx, const float *__restrict__ p1, const float *__restrict__ p2,
+                                const float *__restrict__ g, float inv_lambda, float *__restrict__ v)
+{
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pix = o % ((int64_t)ny * nx);
+        const int iy = (int)(pix / nx), ix = (int)(pix - (int64_t)iy * nx);
+        v[o] = divergence(p1, p2, o, ix, iy, nx, ny) - g[o] * inv_lambda;
+    }
+}
+
+// p <- (p + tau grad v) / (1 + tau |grad v|)
+__global__ void prox_update_kernel(int64_t n, int ny, int nx, const float *__restrict__ v, float *__restrict__ p1,
+                                   float *__restrict__ p2, float tau)
+{
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pix = o % ((int64_t)ny * nx);
+        const int iy = (int)(pix / nx), ix = (int)(pix - (int64_t)iy * nx);
+        const float a = grad_x(v, o, ix, nx), b = grad_y(v, o, iy, ny, nx);
+        const float m = 1.0f + tau * sqrtf(a * a + b * b);
+        p1[o] = (p1[o] + tau * a) / m;
+        p2[o] = (p2[o] + tau * b) / m;
+    }
+}
+
+// u = g - lambda div p
+__global__ void prox_final_kernel(int64_t n, int ny, int nx, const float *__restrict__ p1,
+                                  const float *__restrict__ p2, const float *g, float lambda, float *u)
+{
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pix = o % ((int64_t)ny * nx);
+        const int iy = (int)(pix / nx), ix = (int)(pix - (int64_t)iy * nx);
+        u[o] = g[o] - lambda * divergence(p1, p2, o, ix, iy, nx, ny);
+    }
+}
+
+__global__ void fill_kernel(float *buf, int64_t n, float v)
+{
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x)
+        buf[o] = v;
+}
+
+__global__ void copy_kernel(float *dst, const float *src, int64_t n)
+{
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x)
+        dst[o] = src[o];
+}
+
+// y = a x + b y
+__global__ void axpby_kernel(float *y, const float *x, int64_t n, float a, float b)
+{
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x)
+        y[o] = a * x[o] + b * y[o];
+}
+
+// Chambolle-Pock dual TV step: q <- pi_lambda(q + sigma grad xbar)
+__global__ void cp_q_kernel(int64_t n, int ny, int nx, const float *__restrict__ xb, float *__restrict__ q1,
+                            float *__restrict__ q2, float sigma, float lambda)
+{
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pix = o % ((int64_t)ny * nx);
+        const int iy = (int)(pix / nx), ix = (int)(pix - (int64_t)iy * nx);
+        float a = q1[o] + sigma * grad_x(xb, o, ix, nx);
+        float b = q2[o] + sigma * grad_y(xb, o, iy, ny, nx);
+        if (lambda > 0.0f) {
+            const float d = fmaxf(1.0f, sqrtf(a * a + b * b) / lambda);
+            a /= d;
+            b /= d;
+        } else {
+            a = 0.0f;
+            b = 0.0f;
+        }
+        q1[o] = a;
+        q2[o] = b;
+    }
+}
+
+// out -= div(grad x)  (so that out = A^T A x + grad^T grad x)
+__global__ void sub_divgrad_kernel(int64_t n, int ny, int nx, const float *__restrict__ x, float *__restrict__ out)
+{
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pix = o % ((int64_t)ny * nx);
+        const int iy = (int)(pix / nx), ix = (int)(pix - (int64_t)iy * nx);
+        // div(grad x) at o, from the forward differences around o
+        float a, b;
+        const float gx = grad_x(x, o, ix, nx), gy = grad_y(x, o, iy, ny, nx);
+        const float gxl = ix > 0 ? grad_x(x, o - 1, ix - 1, nx) : 0.0f;
+        const float gyu = iy > 0 ? grad_y(x, o - nx, iy - 1, ny, nx) : 0.0f;
+        if (nx == 1) a = 0.0f;
+        else if (ix == 0) a = gx;
+        else if (ix == nx - 1) a = -gxl;
+        else a = gx - gxl;
+        if (ny == 1) b = 0.0f;
+        else if (iy == 0) b = gy;
+        else if (iy == ny - 1) b = -gyu;
+        else b = gy - gyu;
+        out[o] -= a + b;
+    }
+}
+
+__device__ inline double block_sum(double v, double *sh)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+    return t;
+}
+
+// partials[b] = sum over this block's share of 0.5 (ax - y)^2 + lambda |grad x|
+__global__ __launch_bounds__(256) void energy_partial_kernel(int64_t n_s, const float *__restrict__ ax,
+                                                             const float *__restrict__ y, int64_t n_i, int ny, int nx,
+                                                             const float *__restrict__ x, float lambda,
+                                                             double *__restrict__ partials)
+{
+    __shared__ double sh[4];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n_s; o += stride) {
+        const double d = (double)ax[o] - (double)y[o];
+        acc += 0.5 * d * d;
+    }
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n_i; o += stride) {
+        const int64_t pix = o % ((int64_t)ny * nx);
+        const int iy = (int)(pix / nx), ix = (int)(pix - (int64_t)iy * nx);
+        const double a = grad_x(x, o, ix, nx), b = grad_y(x, o, iy, ny, nx);
+        acc += (double)lambda * sqrt(a * a + b * b);
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// partials[b] = sum of squares of v
+__global__ __launch_bounds__(256) void sumsq_partial_kernel(int64_t n, const float *__restrict__ v,
+                                                            double *__restrict__ partials)
+{
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x)
+        acc += (double)v[o] * (double)v[o];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void final_sum_kernel(const double *__restrict__ partials, int n,
+                                                        float *out_f, double *out_d)
+{
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += partials[i];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        if (out_f) *out_f = (float)t;
+        if (out_d) *out_d = t;
+    }
+}
+
+__global__ void scale_inv_sqrt_kernel(float *x, int64_t n, const double *sumsq)
+{
+    const float inv = (float)(1.0 / sqrt(*sumsq));
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x)
+        x[o] *= inv;
+}
+
+unsigned grid_for(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+int energy_partials(const pyhst_plan &) { return 1024; }
+
+hipError_t launch_fill(float *buf, int64_t n, float v, hipStream_t st)
+{
+    fill_kernel<<<grid_for(n), 256, 0, st>>>(buf, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(float *y, const float *x, int64_t n, float a, float b, hipStream_t st)
+{
+    axpby_kernel<<<grid_for(n), 256, 0, st>>>(y, x, n, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_tv_prox(int S, int ny, int nx, const float *in, float *out, float lambda, int n_inner,
+                          float *work, hipStream_t st)
+{
+    const int64_t n = (int64_t)S * ny * nx;
+    if (!(lambda > 0.0f) || n_inner <= 0) {
+        if (out != in) copy_kernel<<<grid_for(n), 256, 0, st>>>(out, in, n);
+        return hipGetLastError();
+    }
+    float *p1 = work, *p2 = work + n, *v = work + 2 * n;
+    fill_kernel<<<grid_for(2 * n), 256, 0, st>>>(work, 2 * n, 0.0f);
+    for (int it = 0; it < n_inner; ++it) {
+        prox_div_kernel<<<grid_for(n), 256, 0, st>>>(n, ny, nx, p1, p2, in, 1.0f / lambda, v);
+        prox_update_kernel<<<grid_for(n), 256, 0, st>>>(n, ny, nx, v, p1, p2, 0.125f);
+    }
+    prox_final_kernel<<<grid_for(n), 256, 0, st>>>(n, ny, nx, p1, p2, in, lambda, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cp_dual_q(const pyhst_plan &p, const float *xbar, float *q1, float *q2, float sigma, float lambda,
+                            hipStream_t st)
+{
+    const GeoDev &g = p.gd[0];
+    const int64_t n = (int64_t)p.n_slices * g.ny * g.nx;
+    cp_q_kernel<<<grid_for(n), 256, 0, st>>>(n, g.ny, g.nx, xbar, q1, q2, sigma, lambda);
+    return hipGetLastError();
+}
+
+hipError_t launch_cp_energy(const pyhst_plan &p, const float *ax, const float *y, const float *x, float lambda,
+                            double *partials, int n_part, float *energy_dev, hipStream_t st)
+{
+    const GeoDev &g = p.gd[0];
+    const int64_t ns = (int64_t)p.n_slices * g.K * g.nb, ni = (int64_t)p.n_slices * g.ny * g.nx;
+    energy_partial_kernel<<<n_part, 256, 0, st>>>(ns, ax, y, ni, g.ny, g.nx, x, lambda, partials);
+    final_sum_kernel<<<1, 256, 0, st>>>(partials, n_part, energy_dev, nullptr);
+    return hipGetLastError();
+}
+
+// out = K^T K x = A^T A x - div grad x ; then norm_dev = |out|^2
+hipError_t launch_power_step(const pyhst_plan &p, const float *x, float *out, float *tmp_sino, double *partials,
+                             int n_part, double *norm_dev, hipStream_t st)
+{
+    const GeoDev &g = p.gd[0];
+    const float s2 = (float)(g.s * g.s);
+    hipError_t e = launch_forward(p, x, tmp_sino, 1.0f, nullptr, st);
+    if (e != hipSuccess) return e;
+    e = launch_backproject(p, tmp_sino, 0, out, s2, 0.0f, nullptr, st);
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)p.n_slices * g.ny * g.nx;
+    sub_divgrad_kernel<<<grid_for(n), 256, 0, st>>>(n, g.ny, g.nx, x, out);
+    sumsq_partial_kernel<<<n_part, 256, 0, st>>>(n, out, partials);
+    final_sum_kernel<<<1, 256, 0, st>>>(partials, n_part, nullptr, norm_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_by_inv(float *x, int64_t n, const double *norm_dev, hipStream_t st)
+{
+    scale_inv_sqrt_kernel<<<grid_for(n), 256, 0, st>>>(x, n, norm_dev);
+    return hipGetLastError();
+}
+
+}  // namespace pyhst

@@ -1,0 +1,539 @@
+// Host side of the library: geometry validation, the immutable plan (FP64
+// angle tables, quadrature and half-acquisition weights, filter spectra, work
+// lists) and the C-ABI entry points.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <memory>
+#include <numeric>
+
+#include "internal.hpp"
+
+namespace pyhst {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+int hip_fail(hipError_t e, const char *where)
+{
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return PYHST_EHIP;
+}
+
+int choose_tile(const pyhst_plan &p)
+{
+    if (p.bp_tile >= 0 && p.bp_tile < N_TILE_CFG) return p.bp_tile;
+    const int64_t want = 2LL * p.cu_count;
+    if (p.n_items[0] >= want) return 0;
+    if (p.n_items[1] >= want) return 1;
+    return 3;
+}
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+
+// In-place radix-2 FFT in double precision (host, plan creation only).
+void fft_host(std::vector<std::complex<double>> &a)
+{
+    const size_t n = a.size();
+    for (size_t i = 1, j = 0; i < n; ++i) {
+        size_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    for (size_t len = 2; len <= n; len <<= 1) {
+        const double ang = -2.0 * PI / (double)len;
+        for (size_t i = 0; i < n; i += len)
+            for (size_t k = 0; k < len / 2; ++k) {
+                const std::complex<double> w(std::cos(ang * (double)k), std::sin(ang * (double)k));
+                const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * w;
+                a[i + k] = u + v;
+                a[i + k + len / 2] = u - v;
+            }
+    }
+}
+
+unsigned bitrev(unsigned x, int bits)
+{
+    unsigned r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+    return r;
+}
+
+// Spectrum of the Ram-Lak kernel restricted to lags |n| < L, as a length-P
+// circular kernel; real because the kernel is even.  Bit-reversed, / P.
+std::vector<float> ramp_spectrum(int L, int P, int log2P)
+{
+    std::vector<std::complex<double>> h(P, 0.0);
+    for (int n = -(L - 1); n <= L - 1; ++n) {
+        double v;
+        if (n == 0) v = 0.25;
+        else if (n % 2 == 0) v = 0.0;
+        else v = -1.0 / (PI * PI * (double)n * (double)n);
+        h[(n + P) % P] += v;
+    }
+    fft_host(h);
+    std::vector<float> out(P);
+    for (int i = 0; i < P; ++i) out[i] = (float)(h[bitrev((unsigned)i, log2P)].real() / (double)P);
+    return out;
+}
+
+int setup_geom(const pyhst_geom &in, GeoHost &h)
+{
+    if (in.n_x <= 0 || in.n_y <= 0 || in.n_det <= 0 || in.n_angles <= 0)
+        return fail(PYHST_EARG, "geometry: sizes must be positive");
+    if (!in.angles) return fail(PYHST_EARG, "geometry: angles is NULL");
+    if (in.scan < PYHST_SCAN_180 || in.scan > PYHST_SCAN_360_HALF) return fail(PYHST_EARG, "geometry: bad scan type");
+    if (!std::isfinite(in.axis_pos) || in.axis_pos < 0.0 || in.axis_pos > in.n_det - 1)
+        return fail(PYHST_EARG, "geometry: rotation axis outside the detector");
+    h.g = in;
+    const int K = in.n_angles;
+    h.ang.assign(in.angles, in.angles + K);
+    h.shift.assign(K, 0.0);
+    if (in.axis_shift) h.shift.assign(in.axis_shift, in.axis_shift + K);
+    for (int k = 0; k < K; ++k)
+        if (!std::isfinite(h.ang[k]) || !std::isfinite(h.shift[k]))
+            return fail(PYHST_EARG, "geometry: non-finite angle or axis shift");
+    h.s = in.pixel_size > 0.0 ? in.pixel_size : 1.0;
+    h.g.angles = nullptr;
+    h.g.axis_shift = nullptr;
+
+    // angular coverage (section 2.1): at least 180 degrees, 360 for 360 degree scans
+    const double period = in.scan == PYHST_SCAN_180 ? PI : 2.0 * PI;
+    std::vector<int> ord(K);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return h.ang[a] < h.ang[b]; });
+    const double span = h.ang[ord[K - 1]] - h.ang[ord[0]];
+    const double mean_gap = K > 1 ? span / (K - 1) : 0.0;
+    if (K < 2 || span + 1.5 * mean_gap < period * (1.0 - 1e-9))
+        return fail(PYHST_EGEOM, "geometry: projections do not cover the scan period (180 or 360 degrees)");
+
+    // quadrature weights: mid-point rule, circular over the scan period
+    h.w.assign(K, 0.0);
+    const double factor = in.scan == PYHST_SCAN_360 ? 0.5 : 1.0;
+    for (int i = 0; i < K; ++i) {
+        const double cur = h.ang[ord[i]];
+        const double prev = i == 0 ? h.ang[ord[K - 1]] - period : h.ang[ord[i - 1]];
+        const double next = i == K - 1 ? h.ang[ord[0]] + period : h.ang[ord[i + 1]];
+        h.w[ord[i]] = factor * 0.5 * (std::max(0.0, cur - prev) + std::max(0.0, next - cur));
+    }
+
+    // filtered-row layout; half acquisition extends rows to a symmetric span
+    const int nb = in.n_det;
+    const double c = in.axis_pos;
+    if (in.scan == PYHST_SCAN_360_HALF) {
+        const bool right = c >= 0.5 * (nb - 1);
+        const double delta = right ? (nb - 1 - c) : c;
+        if (delta > 0.25 * nb)
+            return fail(PYHST_EGEOM, "half acquisition: the axis must lie in the outer quarter of the detector");
+        const double df = in.ha_overlap > 0.0 ? in.ha_overlap : delta;
+        if (in.ha_overlap > delta) return fail(PYHST_EARG, "half acquisition: overlap exceeds the axis-edge distance");
+        double sgn;
+        if (right) {
+            h.fpad = 0;
+            h.Lf = (int)std::floor(2.0 * c) + 1;
+            h.axis_f = c;
+            sgn = 1.0;
+        } else {
+            h.fpad = (int)std::ceil(nb - 1 - 2.0 * c);
+            h.Lf = nb + h.fpad;
+            h.axis_f = c + h.fpad;
+            sgn = -1.0;
+        }
+        h.haw.assign(h.Lf, 0.0);
+        for (int j = 0; j < h.Lf; ++j) {
+            const double u = sgn * ((double)j - h.axis_f);
+            double w;
+            if (df > 0.0) {
+                if (u <= -df) w = 1.0;
+                else if (u >= df) w = 0.0;
+                else w = 0.5 * (1.0 - std::sin(PI * u / (2.0 * df)));
+            } else {
+                w = u < 0.0 ? 1.0 : (u == 0.0 ? 0.5 : 0.0);
+            }
+            h.haw[j] = w;
+        }
+    } else {
+        h.fpad = 0;
+        h.Lf = nb;
+        h.axis_f = c;
+        h.haw.assign(nb, 1.0);
+    }
+    int P = 4, lg = 2;
+    while (P < 2 * h.Lf - 1) {
+        P <<= 1;
+        ++lg;
+    }
+    if (P > 16384) return fail(PYHST_EARG, "filter: rows longer than 8192 bins are not supported");
+    h.P = P;
+    h.log2P = lg;
+    return PYHST_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+}  // namespace pyhst
+
+using namespace pyhst;
+
+extern "C" {
+
+const char *pyhst_last_error(void) { return g_err.c_str(); }
+
+const char *pyhst_strerror(int code)
+{
+    switch (code) {
+    case PYHST_OK: return "ok";
+    case PYHST_EARG: return "invalid argument";
+    case PYHST_EGEOM: return "invalid geometry";
+    case PYHST_ENOMEM: return "out of memory";
+    case PYHST_EHIP: return "HIP runtime error";
+    case PYHST_ENUM: return "non-finite energy";
+    default: return "unknown error";
+    }
+}
+
+int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_geom, int32_t n_slices,
+                      pyhst_plan **out)
+{
+    if (!out) return fail(PYHST_EARG, "plan_create: out is NULL");
+    *out = nullptr;
+    if (!g || n_geom <= 0 || n_slices <= 0) return fail(PYHST_EARG, "plan_create: need geometries and slices");
+    try {
+        auto *p = new pyhst_plan();
+        std::unique_ptr<pyhst_plan> guard(p);
+        p->n_geom = n_geom;
+        p->n_slices = n_slices;
+        p->gh.resize(n_geom);
+        for (int i = 0; i < n_geom; ++i) {
+            int rc = setup_geom(g[i], p->gh[i]);
+            if (rc) return rc;
+        }
+        std::vector<int> sg(n_slices, 0);
+        for (int i = 0; i < n_slices; ++i) {
+            sg[i] = slice_geom ? slice_geom[i] : 0;
+            if (sg[i] < 0 || sg[i] >= n_geom) return fail(PYHST_EARG, "plan_create: slice_geom out of range");
+        }
+        p->uniform = std::all_of(sg.begin(), sg.end(), [&](int v) { return v == sg[0]; });
+        if (const char *f = std::getenv("PYHST_FAKE_OOM"); f && f[0] == '1')
+            return fail(PYHST_ENOMEM, "plan_create: allocation failure injected by PYHST_FAKE_OOM");
+
+        hipError_t e = hipGetDevice(&p->device);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
+            p->cu_count = cus;
+
+        // per-geometry device descriptors and table offsets
+        int64_t nang = 0, nhw = 0, nspec = 0;
+        int Pmax = 4, lgmax = 2;
+        p->gd.resize(n_geom);
+        std::map<std::pair<int, int>, int64_t> spec_cache;
+        std::vector<std::vector<float>> spectra;
+        for (int i = 0; i < n_geom; ++i) {
+            const GeoHost &h = p->gh[i];
+            GeoDev &d = p->gd[i];
+            d.nx = h.g.n_x;
+            d.ny = h.g.n_y;
+            d.nb = h.g.n_det;
+            d.K = h.g.n_angles;
+            d.Lf = h.Lf;
+            d.fpad = h.fpad;
+            d.P = h.P;
+            d.log2P = h.log2P;
+            d.s = h.s;
+            d.axis = h.g.axis_pos;
+            d.axis_f = h.axis_f;
+            d.ang_off = nang;
+            nang += d.K;
+            d.hw_off = nhw;
+            nhw += h.Lf;
+            auto key = std::make_pair(h.Lf, h.P);
+            auto it = spec_cache.find(key);
+            if (it == spec_cache.end()) {
+                spectra.push_back(ramp_spectrum(h.Lf, h.P, h.log2P));
+                spec_cache[key] = nspec;
+                d.spec_off = nspec;
+                nspec += h.P;
+            } else {
+                d.spec_off = it->second;
+            }
+            if (h.P > Pmax) {
+                Pmax = h.P;
+                lgmax = h.log2P;
+            }
+            for (int c = 0; c < N_TILE_CFG; ++c) {
+                double range = 0.0;
+                for (int k = 0; k < d.K; ++k)
+                    range = std::max(range, h.s * ((tile_w(c) - 1) * std::fabs(std::cos(h.ang[k])) +
+                                                   (tile_h(c) - 1) * std::fabs(std::sin(h.ang[k]))));
+                int W = (int)std::floor(range) + 4;
+                W += W & 1;
+                d.bp_w[c] = W;
+                d.ntx[c] = (d.nx + tile_w(c) - 1) / tile_w(c);
+            }
+            p->max_K = std::max<int64_t>(p->max_K, d.K);
+        }
+
+        // slices: packed offsets
+        p->sd.resize(n_slices);
+        int64_t so = 0, fo = 0, io = 0;
+        for (int i = 0; i < n_slices; ++i) {
+            const GeoDev &d = p->gd[sg[i]];
+            SliceDev &s = p->sd[i];
+            s.g = sg[i];
+            s.sino_off = so;
+            s.filt_off = fo;
+            s.img_off = io;
+            so += (int64_t)d.K * d.nb;
+            fo += (int64_t)d.K * d.Lf;
+            io += (int64_t)d.nx * d.ny;
+        }
+        p->sino_elems = so;
+        p->filt_elems = fo;
+        p->img_elems = io;
+
+        // work lists: filter row pairs; backprojection (slice, tile), costliest slices first
+        std::vector<int2> pairs;
+        for (int i = 0; i < n_slices; ++i)
+            for (int k = 0; k < p->gd[sg[i]].K; k += 2) pairs.push_back(make_int2(i, k));
+        p->n_pairs = (int)pairs.size();
+        std::vector<int> sorder(n_slices);
+        std::iota(sorder.begin(), sorder.end(), 0);
+        std::stable_sort(sorder.begin(), sorder.end(), [&](int a, int b) {
+            const GeoDev &A = p->gd[sg[a]], &B = p->gd[sg[b]];
+            return (int64_t)A.K * A.nx * A.ny > (int64_t)B.K * B.nx * B.ny;
+        });
+        std::vector<int2> items[N_TILE_CFG];
+        for (int c = 0; c < N_TILE_CFG; ++c) {
+            for (int i : sorder) {
+                const GeoDev &d = p->gd[sg[i]];
+                const int nt = d.ntx[c] * ((d.ny + tile_h(c) - 1) / tile_h(c));
+                for (int t = 0; t < nt; ++t) items[c].push_back(make_int2(i, t));
+            }
+            p->n_items[c] = (int64_t)items[c].size();
+        }
+
+        // one device block for every table
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            size_t o = off;
+            off = align256(off + bytes);
+            return o;
+        };
+        const size_t o_geo = take(sizeof(GeoDev) * n_geom);
+        const size_t o_slc = take(sizeof(SliceDev) * n_slices);
+        const size_t o_cos = take(sizeof(double) * nang), o_sin = take(sizeof(double) * nang),
+                     o_sh = take(sizeof(double) * nang);
+        const size_t o_bpt = take(sizeof(float) * nang * BPT);
+        const size_t o_w = take(sizeof(float) * nang);
+        const size_t o_hw = take(sizeof(float) * nhw);
+        const size_t o_spec = take(sizeof(float) * nspec);
+        const size_t o_tw = take(sizeof(float2) * (Pmax / 2));
+        const size_t o_pairs = take(sizeof(int2) * pairs.size());
+        size_t o_items[N_TILE_CFG];
+        for (int c = 0; c < N_TILE_CFG; ++c) o_items[c] = take(sizeof(int2) * items[c].size());
+        const size_t o_cnt = take(sizeof(int) * 64);
+        const size_t total = off;
+
+        std::vector<unsigned char> hbuf(total, 0);
+        auto put = [&](size_t o, const void *src, size_t bytes) {
+            if (bytes) std::memcpy(hbuf.data() + o, src, bytes);
+        };
+        put(o_geo, p->gd.data(), sizeof(GeoDev) * n_geom);
+        put(o_slc, p->sd.data(), sizeof(SliceDev) * n_slices);
+        std::vector<double> cs(nang), sn(nang), sh(nang);
+        std::vector<float> bpt(nang * BPT, 0.0f), wv(nang), hw(nhw), spec(nspec);
+        for (int i = 0; i < n_geom; ++i) {
+            const GeoHost &h = p->gh[i];
+            const GeoDev &d = p->gd[i];
+            for (int k = 0; k < d.K; ++k) {
+                const int64_t a = d.ang_off + k;
+                const double c = std::cos(h.ang[k]), s = std::sin(h.ang[k]);
+                cs[a] = c;
+                sn[a] = s;
+                sh[a] = h.shift[k];
+                wv[a] = (float)h.w[k];
+                float *t = &bpt[a * BPT];
+                t[0] = (float)(h.s * c);
+                t[1] = (float)(h.s * s);
+                for (int by = 0; by < 2; ++by)
+                    for (int bx = 0; bx < 8; ++bx) t[2 + 8 * by + bx] = (float)(8.0 * h.s * (bx * c + by * s));
+            }
+            for (int j = 0; j < h.Lf; ++j) hw[d.hw_off + j] = (float)h.haw[j];
+        }
+        {
+            int64_t o = 0;
+            for (auto &v : spectra) {
+                std::copy(v.begin(), v.end(), spec.begin() + o);
+                o += (int64_t)v.size();
+            }
+        }
+        std::vector<float2> tw(Pmax / 2);
+        for (int m = 0; m < Pmax / 2; ++m) {
+            const double a = -2.0 * PI * (double)m / (double)Pmax;
+            tw[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+        }
+        put(o_cos, cs.data(), sizeof(double) * nang);
+        put(o_sin, sn.data(), sizeof(double) * nang);
+        put(o_sh, sh.data(), sizeof(double) * nang);
+        put(o_bpt, bpt.data(), sizeof(float) * bpt.size());
+        put(o_w, wv.data(), sizeof(float) * nang);
+        put(o_hw, hw.data(), sizeof(float) * nhw);
+        put(o_spec, spec.data(), sizeof(float) * nspec);
+        put(o_tw, tw.data(), sizeof(float2) * tw.size());
+        put(o_pairs, pairs.data(), sizeof(int2) * pairs.size());
+        for (int c = 0; c < N_TILE_CFG; ++c) put(o_items[c], items[c].data(), sizeof(int2) * items[c].size());
+
+        e = hipMalloc(&p->dev_block, total);
+        if (e != hipSuccess) {
+            p->dev_block = nullptr;
+            (void)hipGetLastError();
+            return fail(PYHST_ENOMEM, std::string("plan_create: hipMalloc: ") + hipGetErrorString(e));
+        }
+        e = hipMemcpy(p->dev_block, hbuf.data(), total, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(p->dev_block);
+            p->dev_block = nullptr;
+            return hip_fail(e, "plan_create: hipMemcpy");
+        }
+        unsigned char *b = (unsigned char *)p->dev_block;
+        Tables &t = p->t;
+        t.geo = (const GeoDev *)(b + o_geo);
+        t.slc = (const SliceDev *)(b + o_slc);
+        t.cosd = (const double *)(b + o_cos);
+        t.sind = (const double *)(b + o_sin);
+        t.shiftd = (const double *)(b + o_sh);
+        t.bpt = (const float *)(b + o_bpt);
+        t.wang = (const float *)(b + o_w);
+        t.haw = (const float *)(b + o_hw);
+        t.spec = (const float *)(b + o_spec);
+        t.twid = (const float2 *)(b + o_tw);
+        t.pairs = (const int2 *)(b + o_pairs);
+        for (int c = 0; c < N_TILE_CFG; ++c) t.items[c] = (const int2 *)(b + o_items[c]);
+        t.counter = (int *)(b + o_cnt);
+        t.Pmax = Pmax;
+        t.log2Pmax = lgmax;
+        *out = guard.release();
+        return PYHST_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(PYHST_ENOMEM, "plan_create: host allocation failed");
+    } catch (...) {
+        return fail(PYHST_EARG, "plan_create: unexpected failure");
+    }
+}
+
+int pyhst_plan_destroy(pyhst_plan *plan)
+{
+    if (!plan) return PYHST_OK;
+    for (auto &kv : plan->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (plan->dev_block) (void)hipFree(plan->dev_block);
+    delete plan;
+    return PYHST_OK;
+}
+
+int pyhst_plan_slice_info(const pyhst_plan *p, int32_t slice, pyhst_slice_info *out)
+{
+    if (!p || !out || slice < 0 || slice >= p->n_slices) return fail(PYHST_EARG, "slice_info: bad argument");
+    const SliceDev &s = p->sd[slice];
+    const GeoDev &g = p->gd[s.g];
+    out->n_x = g.nx;
+    out->n_y = g.ny;
+    out->n_det = g.nb;
+    out->n_angles = g.K;
+    out->filt_len = g.Lf;
+    out->filt_pad = g.fpad;
+    out->filt_axis = g.axis_f;
+    out->sino_offset = s.sino_off;
+    out->filt_offset = s.filt_off;
+    out->img_offset = s.img_off;
+    return PYHST_OK;
+}
+
+int pyhst_plan_sizes(const pyhst_plan *p, int64_t *sino_elems, int64_t *filt_elems, int64_t *img_elems)
+{
+    if (!p) return fail(PYHST_EARG, "plan_sizes: plan is NULL");
+    if (sino_elems) *sino_elems = p->sino_elems;
+    if (filt_elems) *filt_elems = p->filt_elems;
+    if (img_elems) *img_elems = p->img_elems;
+    return PYHST_OK;
+}
+
+int pyhst_plan_set_tiles(pyhst_plan *p, int32_t bp_tile, int32_t persistent)
+{
+    if (!p || bp_tile < -1 || bp_tile >= N_TILE_CFG) return fail(PYHST_EARG, "set_tiles: bad argument");
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->bp_tile = bp_tile;
+    p->persistent = persistent ? 1 : 0;
+    for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+    p->graphs.clear();
+    return PYHST_OK;
+}
+
+int pyhst_plan_get_tiles(const pyhst_plan *p, int32_t *bp_tile, int32_t *persistent)
+{
+    if (!p) return fail(PYHST_EARG, "get_tiles: plan is NULL");
+    if (bp_tile) *bp_tile = choose_tile(*p);
+    if (persistent) *persistent = p->persistent;
+    return PYHST_OK;
+}
+
+int pyhst_normalize(const pyhst_plan *p, const uint16_t *raw, const float *flats, const double *flat_pos,
+                    int32_t n_flats, const float *dark, float eps, float *sino, hipStream_t st)
+{
+    if (!p || !raw || !flats || !flat_pos || !dark || !sino) return fail(PYHST_EARG, "normalize: NULL argument");
+    if (!p->uniform) return fail(PYHST_EARG, "normalize: raw radiographs need a uniform plan");
+    if (n_flats < 1 || n_flats > 32) return fail(PYHST_EARG, "normalize: n_flats must be in [1, 32]");
+    for (int i = 1; i < n_flats; ++i)
+        if (!(flat_pos[i] > flat_pos[i - 1])) return fail(PYHST_EARG, "normalize: flat positions must increase");
+    hipError_t e = launch_normalize(*p, raw, flats, flat_pos, n_flats, dark, eps, sino, st);
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "normalize");
+}
+
+int fbp_filter(const pyhst_plan *p, const float *sino, float *filt, hipStream_t st)
+{
+    if (!p || !sino || !filt) return fail(PYHST_EARG, "fbp_filter: NULL argument");
+    if (sino == filt && p->filt_elems != p->sino_elems)
+        return fail(PYHST_EARG, "fbp_filter: in place needs unextended rows");
+    hipError_t e = launch_filter(*p, sino, nullptr, nullptr, nullptr, 0, nullptr, 0.0f, filt, st);
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "fbp_filter");
+}
+
+int backproject(const pyhst_plan *p, const float *sino, int32_t filtered_layout, float *img, float alpha, float beta,
+                hipStream_t st)
+{
+    if (!p || !sino || !img) return fail(PYHST_EARG, "backproject: NULL argument");
+    if (filtered_layout != 0 && filtered_layout != 1) return fail(PYHST_EARG, "backproject: layout must be 0 or 1");
+    hipError_t e = launch_backproject(*p, sino, filtered_layout, img, alpha, beta, nullptr, st);
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "backproject");
+}
+
+int forward_project(const pyhst_plan *p, const float *img, float *sino, hipStream_t st)
+{
+    if (!p || !img || !sino) return fail(PYHST_EARG, "forward_project: NULL argument");
+    hipError_t e = launch_forward(*p, img, sino, 1.0f, nullptr, st);
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "forward_project");
+}
+
+int tv_prox(int32_t n_slices, int32_t n_y, int32_t n_x, const float *in, float *out, float lambda, int32_t n_inner,
+            float *work, size_t work_floats, hipStream_t st)
+{
+    if (n_slices <= 0 || n_y <= 0 || n_x <= 0 || !in || !out) return fail(PYHST_EARG, "tv_prox: bad argument");
+    if (!std::isfinite(lambda) || lambda < 0.0f || n_inner < 0) return fail(PYHST_EARG, "tv_prox: bad lambda/n_inner");
+    const size_t need = 3 * (size_t)n_slices * n_y * n_x;
+    if (lambda > 0.0f && n_inner > 0 && (!work || work_floats < need))
+        return fail(PYHST_EARG, "tv_prox: work must hold 3*n_slices*n_y*n_x floats");
+    hipError_t e = launch_tv_prox(n_slices, n_y, n_x, in, out, lambda, n_inner, work, st);
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "tv_prox");
+}
+
+}  // extern "C"

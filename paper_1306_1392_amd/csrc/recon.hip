@@ -1,0 +1,229 @@
+// reconstruct_slices: the whole path for a batch of slices.
+//   FBP   : (normalise + weight + ramp filter) -> backprojection      (section 2.3)
+//   TV_CP : eq. (3) by Chambolle-Pock with K = [A; grad]              (section 3.1)
+// Both are plain launch sequences on one stream, so the sequence can be
+// captured into a HIP graph (use_graph) and replayed without host work.
+#include <cmath>
+#include <cstring>
+
+#include "internal.hpp"
+
+using namespace pyhst;
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct CpLayout {
+    size_t y, xbar, q1, q2, p, tmp, partials, energy, norm, total;
+};
+
+CpLayout cp_layout(const pyhst_plan &p, const pyhst_recon_args &a)
+{
+    CpLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = align256(o + bytes);
+        return r;
+    };
+    const size_t ni = (size_t)p.img_elems, ns = (size_t)p.sino_elems;
+    L.y = a.raw ? take(ns * 4) : (size_t)-1;
+    L.xbar = take(ni * 4);
+    L.q1 = take(ni * 4);
+    L.q2 = take(ni * 4);
+    L.p = take(ns * 4);
+    L.tmp = take(ns * 4);
+    L.partials = take(sizeof(double) * 1024);
+    L.energy = take(sizeof(float) * (size_t)std::max(1, a.n_iter));
+    L.norm = take(sizeof(double) * 2);
+    L.total = o;
+    return L;
+}
+
+size_t fbp_work(const pyhst_plan &p) { return align256((size_t)p.filt_elems * 4); }
+
+int enqueue_fbp(const pyhst_plan &p, const pyhst_recon_args &a, hipStream_t st)
+{
+    float *filt = (float *)a.work;
+    hipError_t e = launch_filter(p, a.raw ? nullptr : a.sino, a.raw, a.flats, a.flat_pos, a.n_flats, a.dark, a.eps,
+                                 filt, st);
+    if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: filter");
+    e = launch_backproject(p, filt, 1, a.out, 1.0f, 0.0f, nullptr, st);
+    if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: backproject");
+    return PYHST_OK;
+}
+
+int enqueue_cp(const pyhst_plan &p, const pyhst_recon_args &a, const CpLayout &L, double op_norm, hipStream_t st)
+{
+    unsigned char *w = (unsigned char *)a.work;
+    const float *y = a.raw ? (const float *)(w + L.y) : a.sino;
+    float *x = a.out, *xbar = (float *)(w + L.xbar), *q1 = (float *)(w + L.q1), *q2 = (float *)(w + L.q2);
+    float *pd = (float *)(w + L.p), *tmp = (float *)(w + L.tmp);
+    double *partials = (double *)(w + L.partials);
+    float *edev = (float *)(w + L.energy);
+    const int64_t ni = p.img_elems, ns = p.sino_elems;
+    const float s2 = (float)(p.gd[0].s * p.gd[0].s);
+    const float tau = (float)(1.0 / op_norm), sigma = (float)(1.0 / op_norm);
+    hipError_t e;
+    if (a.raw) {
+        e = launch_normalize(p, a.raw, a.flats, a.flat_pos, a.n_flats, a.dark, a.eps, (float *)(w + L.y), st);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: normalize");
+    }
+    for (float *b : {x, xbar, q1, q2}) {
+        e = launch_fill(b, ni, 0.0f, st);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: fill");
+    }
+    e = launch_fill(pd, ns, 0.0f, st);
+    if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: fill");
+    const int npart = energy_partials(p);
+    for (int it = 0; it < a.n_iter; ++it) {
+        CpDual dual{pd, y, sigma};
+        e = launch_forward(p, xbar, nullptr, 1.0f, &dual, st);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: projector");
+        e = launch_cp_dual_q(p, xbar, q1, q2, sigma, a.lambda, st);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: tv dual");
+        CpPrimal prim{x, xbar, q1, q2, tau};
+        e = launch_backproject(p, pd, 0, nullptr, s2, 0.0f, &prim, st);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: backprojector");
+        if (a.energy) {
+            e = launch_forward(p, x, tmp, 1.0f, nullptr, st);
+            if (e == hipSuccess) e = launch_cp_energy(p, tmp, y, x, a.lambda, partials, npart, edev + it, st);
+            if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: energy");
+        }
+    }
+    return PYHST_OK;
+}
+
+// |[A; grad]| by power iteration on K^T K (synchronises the stream once).
+int estimate_opnorm(const pyhst_plan &p, const pyhst_recon_args &a, const CpLayout &L, hipStream_t st, double *out)
+{
+    unsigned char *w = (unsigned char *)a.work;
+    float *x = (float *)(w + L.xbar), *y = (float *)(w + L.q1);
+    float *tmp = (float *)(w + L.tmp);
+    double *partials = (double *)(w + L.partials), *nrm = (double *)(w + L.norm);
+    const int64_t ni = p.img_elems;
+    // constant start: the leading eigenvector of K^T K (dominated by A^T A) is smooth and positive
+    hipError_t e = launch_fill(x, ni, 1.0f, st);
+    double sq = 0.0;
+    for (int it = 0; it < 50 && e == hipSuccess; ++it) {
+        e = launch_power_step(p, x, y, tmp, partials, energy_partials(p), nrm, st);
+        if (e == hipSuccess) e = launch_scale_by_inv(y, ni, nrm, st);
+        std::swap(x, y);
+    }
+    if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: power iteration");
+    e = hipMemcpyAsync(&sq, nrm, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: power iteration");
+    if (!(sq > 0.0) || !std::isfinite(sq)) return fail(PYHST_ENUM, "reconstruct_slices: operator norm estimate failed");
+    *out = 1.02 * std::sqrt(std::sqrt(sq));   // |K^T K x| -> |K|^2; 2 % margin keeps tau sigma |K|^2 < 1
+    return PYHST_OK;
+}
+
+}  // namespace
+
+extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hipStream_t st)
+{
+    if (!pc || !a) return fail(PYHST_EARG, "reconstruct_slices: NULL argument");
+    pyhst_plan &p = const_cast<pyhst_plan &>(*pc);
+    if (a->method != PYHST_FBP && a->method != PYHST_TV_CP) return fail(PYHST_EARG, "reconstruct_slices: bad method");
+    if (!a->raw && !a->sino) return fail(PYHST_EARG, "reconstruct_slices: need raw or sino");
+    if (a->raw) {
+        if (!p.uniform) return fail(PYHST_EARG, "reconstruct_slices: raw radiographs need a uniform plan");
+        if (!a->flats || !a->flat_pos || !a->dark || a->n_flats < 1 || a->n_flats > 32)
+            return fail(PYHST_EARG, "reconstruct_slices: raw input needs 1..32 flats, positions and a dark");
+        for (int i = 1; i < a->n_flats; ++i)
+            if (!(a->flat_pos[i] > a->flat_pos[i - 1]))
+                return fail(PYHST_EARG, "reconstruct_slices: flat positions must increase");
+    }
+    const bool cp = a->method == PYHST_TV_CP;
+    if (cp) {
+        if (!p.uniform) return fail(PYHST_EARG, "reconstruct_slices: TV needs a uniform plan");
+        if (a->n_iter < 0 || !(a->lambda >= 0.0f)) return fail(PYHST_EARG, "reconstruct_slices: bad n_iter/lambda");
+    }
+    CpLayout L{};
+    size_t need;
+    if (cp) {
+        L = cp_layout(p, *a);
+        need = L.total;
+    } else {
+        need = fbp_work(p);
+    }
+    if (!a->out) {
+        a->work_bytes = need;
+        return PYHST_OK;
+    }
+    if (!a->work || a->work_bytes < need) {
+        set_error("reconstruct_slices: work buffer too small");
+        return PYHST_ENOMEM;
+    }
+
+    double op_norm = a->op_norm;
+    if (cp && !(op_norm > 0.0)) {
+        int rc = estimate_opnorm(p, *a, L, st, &op_norm);
+        if (rc) return rc;
+    }
+
+    // graphs are captured on the caller's stream; the legacy null stream cannot be captured
+    const bool graphable = a->use_graph && !(cp && a->energy) && st != nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (graphable) {
+        hipError_t e = hipStreamIsCapturing(st, &cs);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: hipStreamIsCapturing");
+    }
+    auto enqueue = [&]() { return cp ? enqueue_cp(p, *a, L, op_norm, st) : enqueue_fbp(p, *a, st); };
+
+    if (graphable && cs == hipStreamCaptureStatusNone) {
+        std::vector<uint64_t> key = {(uint64_t)a->method, (uint64_t)(uintptr_t)a->raw, (uint64_t)(uintptr_t)a->sino,
+                                     (uint64_t)(uintptr_t)a->flats, (uint64_t)(uintptr_t)a->dark,
+                                     (uint64_t)(uintptr_t)a->out, (uint64_t)(uintptr_t)a->work,
+                                     (uint64_t)a->n_flats, (uint64_t)a->n_iter, (uint64_t)(uintptr_t)st};
+        uint32_t lb, eb;
+        std::memcpy(&lb, &a->lambda, 4);
+        std::memcpy(&eb, &a->eps, 4);
+        uint64_t ob;
+        std::memcpy(&ob, &op_norm, 8);
+        key.push_back(lb);
+        key.push_back(eb);
+        key.push_back(ob);
+        if (a->raw)
+            for (int i = 0; i < a->n_flats; ++i) {
+                uint64_t fb;
+                std::memcpy(&fb, &a->flat_pos[i], 8);
+                key.push_back(fb);
+            }
+        std::lock_guard<std::mutex> lk(p.mu);
+        auto it = p.graphs.find(key);
+        if (it == p.graphs.end()) {
+            hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: begin capture");
+            int rc = enqueue();
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(st, &graph);
+            if (rc) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: end capture");
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: instantiate");
+            it = p.graphs.emplace(key, exec).first;
+        }
+        hipError_t e = hipGraphLaunch(it->second, st);
+        return e == hipSuccess ? PYHST_OK : hip_fail(e, "reconstruct_slices: graph launch");
+    }
+
+    int rc = enqueue();
+    if (rc) return rc;
+    if (cp && a->energy && a->n_iter > 0) {
+        unsigned char *w = (unsigned char *)a->work;
+        hipError_t e = hipMemcpyAsync(a->energy, w + L.energy, sizeof(float) * a->n_iter, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: energy copy");
+        for (int i = 0; i < a->n_iter; ++i)
+            if (!std::isfinite(a->energy[i])) return fail(PYHST_ENUM, "reconstruct_slices: non-finite energy");
+    }
+    return PYHST_OK;
+}

@@ -1,0 +1,270 @@
+"""GPU parity: every HIP kernel against the FP64 oracle on the same seeded inputs.
+
+Tolerances (relative L2, ||gpu - oracle|| / ||oracle||): 1e-5 for the projector,
+backprojector, ramp filter and normalisation; 1e-4 for full FBP and TV iterates.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_1306_1392_amd as ph
+
+pytestmark = pytest.mark.gpu
+
+TOL_OP = 1e-5
+TOL_PIPE = 1e-4
+
+
+def rel(a, b):
+    a = a.detach().double().cpu().numpy() if torch.is_tensor(a) else np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a.ravel() - b.ravel()) / np.linalg.norm(b.ravel()))
+
+
+def pair(nx, ny, nb, K, axis, shifts=None, s=1.0, scan=ph.SCAN_180, span=None, overlap=0.0, jitter=0.0, seed=0):
+    span = span if span is not None else (math.pi if scan == ph.SCAN_180 else 2 * math.pi)
+    ang = synth.uniform_angles(K, span)
+    if jitter:
+        ang = ang + np.random.default_rng(seed).uniform(-jitter, jitter, K) * span / K
+    sh = None if shifts is None else np.random.default_rng(seed + 1).normal(0, shifts, K)
+    return (ph.Geometry(nx, ny, nb, ang, axis, sh, scan, s, overlap),
+            oracle.Geom(nx, ny, nb, ang, axis, sh, scan, s, overlap))
+
+
+CASES = {
+    "cfg1_256": dict(nx=256, ny=256, nb=256, K=180, axis=127.5),
+    "odd_shift": dict(nx=77, ny=53, nb=101, K=61, axis=49.3, shifts=0.5, jitter=0.3),
+    "wide_det": dict(nx=96, ny=96, nb=160, K=45, axis=81.25, shifts=0.5),
+    "pix_0p7": dict(nx=70, ny=70, nb=64, K=50, axis=30.8, s=0.7),
+    "pix_1p6": dict(nx=40, ny=50, nb=100, K=33, axis=50.0, s=1.6),
+    "tiny": dict(nx=5, ny=3, nb=7, K=4, axis=3.0),
+    "scan360": dict(nx=64, ny=64, nb=72, K=100, axis=36.4, scan=ph.SCAN_360),
+}
+
+
+@pytest.fixture(scope="module")
+def gen():
+    return np.random.default_rng(1234)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("tile,persistent", [(-1, False), (0, False), (3, True), (1, False), (2, True)])
+def test_backproject_parity(dev, gen, case, tile, persistent):
+    g, og = pair(**CASES[case])
+    plan = ph.Plan(g, n_slices=2)
+    plan.set_tiles(tile, persistent)
+    y = gen.standard_normal((2, g.n_angles, g.n_det)).astype(np.float32)
+    out = ph.backproject(plan, torch.from_numpy(y).to(dev))
+    ref = oracle.backproject(y, og)
+    assert rel(out, ref) <= TOL_OP, (case, tile, persistent, rel(out, ref))
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_forward_project_parity(dev, gen, case):
+    g, og = pair(**CASES[case])
+    plan = ph.Plan(g, n_slices=2)
+    x = gen.standard_normal((2, g.n_y, g.n_x)).astype(np.float32)
+    out = ph.forward_project(plan, torch.from_numpy(x).to(dev))
+    ref = oracle.forward_project(x, og)
+    assert rel(out, ref) <= TOL_OP, (case, rel(out, ref))
+
+
+@pytest.mark.parametrize("case", ["odd_shift", "pix_0p7", "pix_1p6"])
+def test_adjoint_identity_gpu(dev, gen, case):
+    g, _ = pair(**CASES[case])
+    plan = ph.Plan(g)
+    x = torch.from_numpy(gen.standard_normal((1, g.n_y, g.n_x)).astype(np.float32)).to(dev)
+    y = torch.from_numpy(gen.standard_normal((1, g.n_angles, g.n_det)).astype(np.float32)).to(dev)
+    lhs = float((ph.forward_project(plan, x).double() * y.double()).sum())
+    rhs = g.pixel_size ** 2 * float((x.double() * ph.backproject(plan, y).double()).sum())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+FILTER_CASES = {
+    "cfg1": dict(nx=256, ny=256, nb=256, K=180, axis=127.5),
+    "odd": dict(nx=40, ny=40, nb=37, K=31, axis=17.5, jitter=0.4),
+    "scan360": dict(nx=64, ny=64, nb=72, K=100, axis=36.4, scan=ph.SCAN_360),
+    "half_right": dict(nx=96, ny=96, nb=59, K=180, axis=48.0, scan=ph.SCAN_360_HALF),
+    "half_left": dict(nx=96, ny=96, nb=59, K=180, axis=10.0, scan=ph.SCAN_360_HALF, overlap=6.0),
+    "long_rows": dict(nx=16, ny=16, nb=2500, K=4, axis=1249.5),
+}
+
+
+@pytest.mark.parametrize("case", list(FILTER_CASES))
+def test_fbp_filter_parity(dev, gen, case):
+    g, og = pair(**FILTER_CASES[case])
+    plan = ph.Plan(g, n_slices=2)
+    p = gen.random((2, g.n_angles, g.n_det)).astype(np.float32)
+    out = ph.fbp_filter(plan, torch.from_numpy(p).to(dev))
+    ref = oracle.fbp_filter(p, og)
+    assert out.shape == ref.shape
+    assert rel(out, ref) <= TOL_OP, (case, rel(out, ref))
+
+
+def test_fbp_filter_in_place(dev, gen):
+    g, og = pair(**FILTER_CASES["odd"])
+    plan = ph.Plan(g)
+    p = gen.random((1, g.n_angles, g.n_det)).astype(np.float32)
+    t = torch.from_numpy(p).to(dev)
+    ph.fbp_filter(plan, t, out=t)
+    assert rel(t, oracle.fbp_filter(p, og)) <= TOL_OP
+
+
+def raw_case(R=3, N=96, K=90, nb=None, axis_offset=3.5, seed=7, n_flats=2):
+    nb = nb or N
+    ang = synth.uniform_angles(K)
+    axis = (nb - 1) / 2 + axis_offset
+    p = torch.stack([synth.ellipse_sinogram(synth.random_ellipses(synth.rng_for(9, 0, r), 8), ang, nb, axis, N)
+                     for r in range(R)])
+    raw, flats, fpos, dark, kap = synth.raw_acquisition(p, seed=seed)
+    if n_flats == 3:   # a third flat acquired mid-scan
+        flats = torch.cat([flats[:1], 0.5 * (flats[:1] + flats[1:]) * 1.01, flats[1:]])
+        fpos = np.array([0.0, K / 2 + 0.5, K - 1.0])
+    return ang, axis, raw, flats, fpos, dark
+
+
+@pytest.mark.parametrize("n_flats", [2, 3])
+def test_normalize_parity(dev, n_flats):
+    ang, axis, raw, flats, fpos, dark = raw_case(n_flats=n_flats)
+    g = ph.Geometry(96, 96, 96, ang, axis)
+    plan = ph.Plan(g, n_slices=3)
+    out = ph.normalize(plan, raw.to(dev), flats.to(dev), fpos, dark.to(dev))
+    ref = oracle.normalize(raw.numpy().astype(np.float64), flats.numpy(), fpos, dark.numpy())
+    assert rel(out, ref) <= TOL_OP
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_fbp_from_raw_parity(dev, graph):
+    ang, axis, raw, flats, fpos, dark = raw_case()
+    g = ph.Geometry(96, 96, 96, ang, axis)
+    og = oracle.Geom(96, 96, 96, ang, axis)
+    plan = ph.Plan(g, n_slices=3)
+    args = dict(raw=raw.to(dev), flats=flats.to(dev), flat_pos=fpos, dark=dark.to(dev), method=ph.FBP)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        out = ph.reconstruct_slices(plan, use_graph=graph, **args)
+    side.synchronize()
+    ref = oracle.fbp_raw(raw.numpy().astype(np.float64), flats.numpy(), fpos, dark.numpy(), og)
+    assert rel(out, ref) <= TOL_PIPE
+    if graph:   # replays of the captured graph give the eager result every time
+        eager = ph.reconstruct_slices(plan, use_graph=False, **args).clone()
+        torch.cuda.synchronize()
+        for _ in range(3):
+            with torch.cuda.stream(side):
+                again = ph.reconstruct_slices(plan, use_graph=True, **args)
+            side.synchronize()
+            assert torch.equal(again, eager)
+            eager.add_(0.0)     # eager work between replays
+
+
+def test_fbp_batch_equals_single(dev, gen):
+    g, _ = pair(**CASES["odd_shift"])
+    plan4 = ph.Plan(g, n_slices=4)
+    plan1 = ph.Plan(g, n_slices=1)
+    y = torch.from_numpy(gen.random((4, g.n_angles, g.n_det)).astype(np.float32)).to(dev)
+    batch = ph.reconstruct_slices(plan4, sino=y, method=ph.FBP)
+    for i in range(4):
+        single = ph.reconstruct_slices(plan1, sino=y[i:i + 1].contiguous(), method=ph.FBP)
+        assert torch.equal(batch[i], single[0])
+
+
+def test_uneven_plan_matches_oracle(dev, gen):
+    """One plan, slices of different sizes, angle counts and scan types (packed buffers)."""
+    specs = [dict(nx=64, ny=64, nb=64, K=90, axis=31.5),
+             dict(nx=96, ny=96, nb=59, K=180, axis=48.0, scan=ph.SCAN_360_HALF, shifts=0.5),
+             dict(nx=48, ny=40, nb=70, K=31, axis=33.2, jitter=0.3)]
+    pairs_ = [pair(**s, seed=i) for i, s in enumerate(specs)]
+    sg = [0, 1, 2, 1, 0]
+    plan = ph.Plan([p[0] for p in pairs_], slice_geom=sg)
+    sinos = [gen.random((pairs_[i][0].n_angles, pairs_[i][0].n_det)).astype(np.float32) for i in sg]
+    packed = torch.from_numpy(np.concatenate([s.ravel() for s in sinos])).to(dev)
+    for persistent in (False, True):
+        plan.set_tiles(-1, persistent)
+        out = ph.reconstruct_slices(plan, sino=packed, method=ph.FBP).cpu().numpy()
+        for i, gi in enumerate(sg):
+            info = plan.slice_info(i)
+            og = pairs_[gi][1]
+            got = out[info.img_offset:info.img_offset + og.n_x * og.n_y].reshape(og.n_y, og.n_x)
+            ref = oracle.fbp(sinos[i][None], og)[0]
+            assert rel(got, ref) <= TOL_PIPE, (i, persistent, rel(got, ref))
+
+
+@pytest.mark.parametrize("lam,n_inner", [(0.05, 40), (0.3, 100)])
+def test_tv_prox_parity(dev, gen, lam, n_inner):
+    g0 = gen.standard_normal((2, 45, 61)).astype(np.float32) * 0.2 + np.kron(np.eye(1), 1.0)
+    out = ph.tv_prox(torch.from_numpy(g0).to(dev), lam, n_inner)
+    ref = oracle.tv_prox(g0, lam, n_inner)
+    assert rel(out, ref) <= TOL_PIPE
+
+
+def test_tv_prox_in_place_and_identity(dev, gen):
+    g0 = gen.standard_normal((1, 20, 20)).astype(np.float32)
+    t = torch.from_numpy(g0).to(dev)
+    assert torch.equal(ph.tv_prox(t, 0.0, 10), t)
+    ph.tv_prox(t, 0.1, 30, out=t)
+    assert rel(t, oracle.tv_prox(g0, 0.1, 30)) <= TOL_PIPE
+
+
+@pytest.fixture(scope="module")
+def cp_problem():
+    N, K = 128, 32
+    d = synth.cfg_tv_sparse(N=N, K=K, index=3)
+    g = ph.Geometry(N, N, N, d["angles"], d["axis"])
+    og = oracle.Geom(N, N, N, d["angles"], d["axis"])
+    Lk = oracle.opnorm(og, synth.rng_for(3, 9, 0).standard_normal((N, N)), 200)
+    return d, g, og, Lk
+
+
+@pytest.mark.parametrize("k", [1, 10, 100])
+def test_cp_iterates_parity(dev, cp_problem, k):
+    d, g, og, Lk = cp_problem
+    plan = ph.Plan(g)
+    y = d["y"][None].contiguous().to(dev)
+    x = ph.reconstruct_slices(plan, sino=y, method=ph.TV_CP, lam=0.01, n_iter=k, op_norm=Lk)
+    ref = oracle.cp_tv(d["y"].numpy(), og, 0.01, k, Lk)
+    assert rel(x[0], ref) <= TOL_PIPE, (k, rel(x[0], ref))
+
+
+def test_cp_energy_and_graph(dev, cp_problem):
+    d, g, og, Lk = cp_problem
+    plan = ph.Plan(g)
+    y = d["y"][None].contiguous().to(dev)
+    x, E = ph.reconstruct_slices(plan, sino=y, method=ph.TV_CP, lam=0.01, n_iter=20, op_norm=Lk, energy=True)
+    xr, Er = oracle.cp_tv(d["y"].numpy(), og, 0.01, 20, Lk, energy=True)
+    np.testing.assert_allclose(E, Er, rtol=1e-4)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for _ in range(2):
+        with torch.cuda.stream(side):
+            xg = ph.reconstruct_slices(plan, sino=y, method=ph.TV_CP, lam=0.01, n_iter=20, op_norm=Lk,
+                                       use_graph=True)
+        side.synchronize()
+        assert torch.equal(xg, x)
+
+
+def test_cp_opnorm_estimate(dev, cp_problem):
+    """op_norm <= 0: the GPU power iteration gives 1.02 |K| (a 2 % safety margin)."""
+    d, g, og, Lk = cp_problem
+    plan = ph.Plan(g)
+    y = d["y"][None].contiguous().to(dev)
+    x = ph.reconstruct_slices(plan, sino=y, method=ph.TV_CP, lam=0.01, n_iter=50, op_norm=0.0)
+    ref = oracle.cp_tv(d["y"].numpy(), og, 0.01, 50, 1.02 * Lk)
+    assert rel(x[0], ref) < 2e-3
+
+
+def test_cp_identity_limit_matches_prox(dev, gen):
+    """TV-CP on a full-angle noise-free disc recovers it (eq. (3) with small beta)."""
+    N = 64
+    g = ph.Geometry(N, N, N, synth.uniform_angles(96), (N - 1) / 2)
+    og = oracle.Geom(N, N, N, g.angles, g.axis_pos)
+    y = synth.ellipse_sinogram(synth.disc_params(0.5, 1.0), g.angles, N, g.axis_pos, N).float()
+    Lk = oracle.opnorm(og, gen.standard_normal((N, N)), 100)
+    x = ph.reconstruct_slices(ph.Plan(g), sino=y[None].contiguous().to(dev), method=ph.TV_CP, lam=0.02,
+                              n_iter=300, op_norm=Lk)[0].cpu().numpy()
+    yy, xx = np.mgrid[0:N, 0:N]
+    inside = (xx - (N - 1) / 2) ** 2 + (yy - (N - 1) / 2) ** 2 < (0.4 * N / 2) ** 2
+    assert abs(x[inside].mean() - 1.0) < 0.03
