@@ -185,8 +185,11 @@ def tv_prox(x, lam: float, n_inner: int, out=None, work=None, stream=None):
     S, ny, nx = xs.shape
     if out is None:
         out = torch.empty_like(x)
+    _need(x, S * ny * nx, "x")
+    _need(out, S * ny * nx, "out")
     if work is None:
         work = torch.empty(3 * S * ny * nx, device=x.device, dtype=torch.float32)
+    _need(work, work.numel(), "work")
     check(_lib.lib().tv_prox(S, ny, nx, _ptr(x), _ptr(out), float(lam), int(n_inner), _ptr(work), work.numel(),
                              _stream(stream)), "tv_prox")
     return out
@@ -212,6 +215,12 @@ def reconstruct_slices(plan: Plan, *, raw=None, sino=None, flats=None, flat_pos=
     a.n_iter = int(n_iter)
     a.op_norm = float(op_norm)
     a.use_graph = int(bool(use_graph))
+    if raw is not None:
+        _need(raw, plan.sino_elems, "raw", torch.uint16)
+        _need(flats, flats.numel(), "flats")
+        _need(dark, dark.numel(), "dark")
+    if sino is not None:
+        _need(sino, plan.sino_elems, "sino")
     L = _lib.lib()
     # size query
     a.out = None
