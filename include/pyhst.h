@@ -104,7 +104,7 @@ int pyhst_plan_destroy(pyhst_plan *plan);
 int pyhst_plan_slice_info(const pyhst_plan *plan, int32_t slice, pyhst_slice_info *out);
 /* Total elements of the packed sinogram, filtered and image buffers. */
 int pyhst_plan_sizes(const pyhst_plan *plan, int64_t *sino_elems, int64_t *filt_elems, int64_t *img_elems);
-/* Backprojector tile: 0 = 64x64, 1 = 64x32, 2 = 32x64, 3 = 32x32 pixels; -1 = automatic.
+/* Backprojector tile: 0 = 64x64, 1 = 64x32, 2 = 32x64, 3 = 32x32, 4 = 64x128 pixels; -1 = automatic.
  * persistent != 0 runs the backprojector as one persistent launch over a
  * cost-sorted (slice, tile) work list. */
 int pyhst_plan_set_tiles(pyhst_plan *plan, int32_t bp_tile, int32_t persistent);
@@ -191,6 +191,16 @@ typedef struct {
 } pyhst_recon_args;
 
 int reconstruct_slices(const pyhst_plan *plan, pyhst_recon_args *a, hipStream_t stream);
+
+/* Roofline measurement kernels (not part of the reconstruction path).
+ * kind 0: independent FP32 FMA chains, 8 lane-ops per thread and iteration;
+ * kind 1: the backprojector's per-update VALU sequence without LDS, 8 updates x
+ *         8 lane-ops per thread and iteration;
+ * kind 2: LDS ds_read_b64 in a conflict-free pattern, 8 x 8 bytes per thread
+ *         and iteration.
+ * blocks x 256 threads; sink: device float buffer of blocks*256 elements (only
+ * written if a result takes an impossible value, which keeps the work live). */
+int pyhst_microbench(int32_t kind, int32_t blocks, int32_t iters, float *sink, hipStream_t stream);
 
 const char *pyhst_strerror(int code);
 const char *pyhst_last_error(void);

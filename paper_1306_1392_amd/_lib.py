@@ -16,7 +16,8 @@ FBP, TV_CP = 0, 1
 
 EXPORTS = ["pyhst_plan_create", "pyhst_plan_destroy", "pyhst_plan_slice_info", "pyhst_plan_sizes",
            "pyhst_plan_set_tiles", "pyhst_plan_get_tiles", "pyhst_normalize", "fbp_filter", "backproject",
-           "forward_project", "tv_prox", "reconstruct_slices", "pyhst_strerror", "pyhst_last_error"]
+           "forward_project", "tv_prox", "reconstruct_slices", "pyhst_microbench", "pyhst_strerror",
+           "pyhst_last_error"]
 
 
 class Geom(ctypes.Structure):
@@ -65,6 +66,7 @@ def lib(path: str = LIB_PATH):
     L.forward_project.argtypes = [P, P, P, P]
     L.tv_prox.argtypes = [c_int32, c_int32, c_int32, P, P, c_float, c_int32, P, c_size_t, P]
     L.reconstruct_slices.argtypes = [P, ctypes.POINTER(ReconArgs), P]
+    L.pyhst_microbench.argtypes = [c_int32, c_int32, c_int32, P, P]
     L.pyhst_strerror.argtypes = [c_int32]
     L.pyhst_strerror.restype = ctypes.c_char_p
     L.pyhst_last_error.restype = ctypes.c_char_p

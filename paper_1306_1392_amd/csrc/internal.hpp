@@ -18,15 +18,15 @@ namespace pyhst {
 // Backprojector tile configurations.  A workgroup is 4 wavefronts; each lane
 // owns one pixel of every 8x8 block its wave covers; a wave covers BX x BY
 // blocks, the 4 waves are stacked in y.  Tile = (8 BX) x (32 BY) pixels.
-constexpr int N_TILE_CFG = 4;
-constexpr int TILE_BX[N_TILE_CFG] = {8, 8, 4, 4};
-constexpr int TILE_BY[N_TILE_CFG] = {2, 1, 2, 1};
+constexpr int N_TILE_CFG = 5;
+constexpr int TILE_BX[N_TILE_CFG] = {8, 8, 4, 4, 8};
+constexpr int TILE_BY[N_TILE_CFG] = {2, 1, 2, 1, 4};
 inline constexpr int tile_w(int c) { return 8 * TILE_BX[c]; }
 inline constexpr int tile_h(int c) { return 32 * TILE_BY[c]; }
 
 // Floats per projection in the backprojection scalar table:
-// [0] s cos, [1] s sin, [2 + 8 by + bx] = 8 s (bx cos + by sin), bx < 8, by < 2.
-constexpr int BPT = 20;
+// [0] s cos, [1] s sin, [2 + 8 by + bx] = 8 s (bx cos + by sin), bx < 8, by < 4.
+constexpr int BPT = 36;
 
 // One slice geometry, as the kernels read it (device memory, read-only).
 struct GeoDev {
@@ -85,7 +85,7 @@ struct pyhst_plan {
     int64_t sino_elems = 0, filt_elems = 0, img_elems = 0;
     int64_t max_K = 0;
     int n_pairs = 0;
-    int64_t n_items[pyhst::N_TILE_CFG] = {0, 0, 0, 0};
+    int64_t n_items[pyhst::N_TILE_CFG] = {};
     int bp_tile = -1, persistent = 0;
     void *dev_block = nullptr;
     pyhst::Tables t{};

@@ -194,7 +194,8 @@ hipError_t launch_mode(const pyhst_plan &p, int cfg, const float *sino, int filt
     case 0: return launch_cfg<0, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
     case 1: return launch_cfg<1, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
     case 2: return launch_cfg<2, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
-    default: return launch_cfg<3, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
+    case 3: return launch_cfg<3, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
+    default: return launch_cfg<4, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
     }
 }
 

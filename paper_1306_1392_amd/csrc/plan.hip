@@ -366,7 +366,7 @@ int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_
                 float *t = &bpt[a * BPT];
                 t[0] = (float)(h.s * c);
                 t[1] = (float)(h.s * s);
-                for (int by = 0; by < 2; ++by)
+                for (int by = 0; by < 4; ++by)
                     for (int bx = 0; bx < 8; ++bx) t[2 + 8 * by + bx] = (float)(8.0 * h.s * (bx * c + by * s));
             }
             for (int j = 0; j < h.Lf; ++j) hw[d.hw_off + j] = (float)h.haw[j];

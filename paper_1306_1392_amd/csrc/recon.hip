@@ -128,14 +128,6 @@ extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hip
     pyhst_plan &p = const_cast<pyhst_plan &>(*pc);
     if (a->method != PYHST_FBP && a->method != PYHST_TV_CP) return fail(PYHST_EARG, "reconstruct_slices: bad method");
     if (!a->raw && !a->sino) return fail(PYHST_EARG, "reconstruct_slices: need raw or sino");
-    if (a->raw) {
-        if (!p.uniform) return fail(PYHST_EARG, "reconstruct_slices: raw radiographs need a uniform plan");
-        if (!a->flats || !a->flat_pos || !a->dark || a->n_flats < 1 || a->n_flats > 32)
-            return fail(PYHST_EARG, "reconstruct_slices: raw input needs 1..32 flats, positions and a dark");
-        for (int i = 1; i < a->n_flats; ++i)
-            if (!(a->flat_pos[i] > a->flat_pos[i - 1]))
-                return fail(PYHST_EARG, "reconstruct_slices: flat positions must increase");
-    }
     const bool cp = a->method == PYHST_TV_CP;
     if (cp) {
         if (!p.uniform) return fail(PYHST_EARG, "reconstruct_slices: TV needs a uniform plan");
@@ -152,6 +144,14 @@ extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hip
     if (!a->out) {
         a->work_bytes = need;
         return PYHST_OK;
+    }
+    if (a->raw) {
+        if (!p.uniform) return fail(PYHST_EARG, "reconstruct_slices: raw radiographs need a uniform plan");
+        if (!a->flats || !a->flat_pos || !a->dark || a->n_flats < 1 || a->n_flats > 32)
+            return fail(PYHST_EARG, "reconstruct_slices: raw input needs 1..32 flats, positions and a dark");
+        for (int i = 1; i < a->n_flats; ++i)
+            if (!(a->flat_pos[i] > a->flat_pos[i - 1]))
+                return fail(PYHST_EARG, "reconstruct_slices: flat positions must increase");
     }
     if (!a->work || a->work_bytes < need) {
         set_error("reconstruct_slices: work buffer too small");
