@@ -27,6 +27,9 @@ METRIC = "backprojection GUPS (voxel·angle/s) + slices/s at 2048²; learned vs 
 # one VALU lane-op per FMA slot gives 78.6 T lane-ops/s.
 VALU_LANE_OPS_PEAK = 157.3e12 / 2
 BP_OPS_PER_UPDATE = 6   # t = t0 + off, trunc, fract, LDS address, acc += q, acc = fma(f, dq, acc)
+BP_LDS_BYTES_PER_UPDATE = 8   # one ds_read_b64 of (q[j], q[j+1] - q[j])
+# LDS read port: 128 B/clk/CU x 256 CU x 2.4 GHz
+LDS_PEAK_GBS = 128 * 256 * 2.4
 
 
 def log(*a):
@@ -115,6 +118,229 @@ def ctypes_stream(s):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def run_uneven(args):
+    """Uneven batch: 500 slices of 512^2 / 1024^2 / 2048^2, 90..3600 projections, half of them
+    360 degree half-acquisition scans, per-projection axis shifts; one plan, autotuned
+    backprojector, the whole FBP of the batch replayed as one HIP graph."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1306_1392_amd as ph
+    dev = torch.device("cuda:0")
+    n = args.uneven_slices
+    log(f"bench(uneven): generating {n} slices ...")
+    d = synth.configs.cfg_uneven(n_slices=n, device=dev)
+    geos = [ph.Geometry(s["N"], s["N"], s["nb"], s["angles"], s["axis"], s["shifts"], s["scan"])
+            for s in d["specs"]]
+    plan = ph.Plan(geos, slice_geom=np.arange(n))
+    sino = torch.cat([x.reshape(-1) for x in d["sinos"]]).contiguous()
+    del d["sinos"]
+    U = float(sum(s["N"] ** 2 * s["K"] for s in d["specs"]))
+    img = torch.empty(plan.img_elems, device=dev)
+    filt = torch.empty(plan.filt_elems, device=dev)
+    ph.fbp_filter(plan, sino, out=filt)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    t_default = None
+    plan.set_tiles(-1, False)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e[0].record(stream)
+    ph.backproject(plan, filt, 1, out=img, stream=stream)
+    e[1].record(stream)
+    stream.synchronize()
+    t_default = e[0].elapsed_time(e[1])
+    best_ms = plan.autotune(filt, img, reps=2, stream=stream)
+    tile, pers = plan.get_tiles()
+    work = torch.empty(ph.work_bytes(plan, sino=sino, method=ph.FBP), device=dev, dtype=torch.uint8)
+
+    def step():
+        ph.reconstruct_slices(plan, sino=sino, method=ph.FBP, out=img, work=work, use_graph=True, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    stream.synchronize()
+    e[0].record(stream)
+    for _ in range(args.steps):
+        step()
+    e[1].record(stream)
+    stream.synchronize()
+    ms = e[0].elapsed_time(e[1]) / args.steps
+    classes = {}
+    for s in d["specs"]:
+        key = f"{s['N']}{'_half' if s['scan'] == 2 else ''}"
+        c = classes.setdefault(key, {"slices": 0, "updates": 0.0})
+        c["slices"] += 1
+        c["updates"] += s["N"] ** 2 * s["K"]
+    res = {"metric": "uneven-batch FBP aggregate GUPS", "value": round(U / (ms * 1e-3) / 1e9, 2), "unit": "GUPS",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{n} slices, N in {{512,1024,2048}}, K in 90..3600, half of them 360-degree "
+                                  f"half acquisition, axis shifts N(0,0.5^2); one plan, one HIP graph per step",
+                      "updates": U, "classes": classes},
+           "slices_per_s": round(n / (ms * 1e-3), 2),
+           "autotune": {"tile": tile, "persistent": pers, "bp_ms_tuned": round(best_ms, 3),
+                        "bp_ms_default": round(t_default, 3)}}
+    print(json.dumps(res), flush=True)
+
+
+def run_tv(args):
+    """TV-regularised sparse-angle reconstruction: 1024^2, 128 projections, Poisson data at 1e4
+    photons, 300 Chambolle-Pock iterations (lambda 0.01) replayed as one HIP graph."""
+    import torch
+    import synth
+    import paper_1306_1392_amd as ph
+    dev = torch.device("cuda:0")
+    d = synth.cfg_tv_sparse(N=1024, K=128, device=dev)
+    g = ph.Geometry(1024, 1024, 1024, d["angles"], d["axis"])
+    plan = ph.Plan(g)
+    y = d["y"][None].contiguous()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    work = torch.empty(ph.work_bytes(plan, sino=y, method=ph.TV_CP, n_iter=300), device=dev, dtype=torch.uint8)
+    out = torch.empty(plan.img_shape(), device=dev)
+    # operator norm once per geometry (GPU power iteration inside the library, synchronous)
+    ph.reconstruct_slices(plan, sino=y, method=ph.TV_CP, lam=0.01, n_iter=1, op_norm=0.0, out=out, work=work,
+                          stream=stream)
+    stream.synchronize()
+    Lk = plan.last_op_norm
+
+    def run():
+        ph.reconstruct_slices(plan, sino=y, method=ph.TV_CP, lam=0.01, n_iter=300, op_norm=Lk, out=out, work=work,
+                              use_graph=True, stream=stream)
+
+    run()
+    stream.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = max(1, args.steps // 5)
+    e[0].record(stream)
+    for _ in range(reps):
+        run()
+    e[1].record(stream)
+    stream.synchronize()
+    ms = e[0].elapsed_time(e[1]) / reps
+    U = 2.0 * 1024 * 1024 * 128 * 300
+    res = {"metric": "TV-CP reconstruction time (300 iterations)", "value": round(ms / 1e3, 4), "unit": "s",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "1024x1024, 1024 bins, 128 angles, Poisson 1e4 photons, 300 Chambolle-Pock "
+                                  "iterations, lambda 0.01, one HIP graph", "op_norm": Lk},
+           "gups_in_projectors": round(U / (ms * 1e-3) / 1e9, 2), "slices_per_s": round(1e3 / ms, 3)}
+    print(json.dumps(res), flush=True)
+
+
+PROFILE_CMDS = {
+    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/prof_trace -o bench -- "
+             "python -u bench.py --steps 5 --warmup 2 --no-cpu-baseline --quick-data",
+    "pmc": "rocprofv3 --pmc <COUNTERS> --output-format csv -d <dir>/pmc_<name> -o pmc -- "
+           "python -u bench.py --steps 1 --warmup 1 --no-cpu-baseline --quick-data --calib-copy",
+}
+
+
+def summarize_profiles(d):
+    """Turn rocprofv3 CSV output under d into the text summaries and the traffic record in profiles/."""
+    import csv
+    import collections
+    out_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+
+    def short(name):
+        for key in ("bp_kernel", "filter_kernel", "normalize_kernel", "copyBuffer", "fp_kernel"):
+            if key in name:
+                return name.replace("pyhst::(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+        return None
+
+    lines = []
+    ks = os.path.join(d, "prof_trace", "bench_kernel_stats.csv")
+    if os.path.exists(ks):
+        lines.append("# kernel time summary: " + PROFILE_CMDS["trace"].replace("<dir>", d))
+        lines.append(f"{'kernel':40s} {'calls':>6s} {'avg_ms':>10s} {'min_ms':>10s} {'max_ms':>10s} {'pct':>6s}")
+        for r in csv.DictReader(open(ks)):
+            n = short(r["Name"])
+            if n:
+                lines.append(f"{n:40s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e6:10.3f} "
+                             f"{float(r['MinNs']) / 1e6:10.3f} {float(r['MaxNs']) / 1e6:10.3f} "
+                             f"{float(r['Percentage']):6.2f}")
+    counters = collections.defaultdict(list)
+    for sub in sorted(os.listdir(d)):
+        f = os.path.join(d, sub, "pmc_counter_collection.csv")
+        if sub.startswith("pmc_") and os.path.exists(f):
+            for r in csv.DictReader(open(f)):
+                n = short(r["Kernel_Name"])
+                if n:
+                    counters[(n, r["Counter_Name"])].append(float(r["Counter_Value"]))
+    if counters:
+        lines.append("")
+        lines.append("# counters per dispatch (mean over dispatches): " + PROFILE_CMDS["pmc"].replace("<dir>", d))
+        for (n, c), v in sorted(counters.items()):
+            lines.append(f"{n:40s} {c:24s} {sum(v) / len(v):14.6g}  (n={len(v)})")
+    txt = os.path.join(out_dir, "bp_fbp2048_rocprof.txt")
+    open(txt, "w").write("\n".join(lines) + "\n")
+    log(f"wrote {txt}")
+    # traffic: FETCH_SIZE / WRITE_SIZE (KiB) scaled by the same counters on a 2 GiB device copy
+    cp = [k for k in counters if "copyBuffer" in k[0]]
+    bp = [k for k in counters if "bp_kernel" in k[0]]
+    if cp and bp:
+        copy_bytes = 2 * 2 ** 29 * 4
+        cf = sum(counters[(cp[0][0], "FETCH_SIZE")]) / len(counters[(cp[0][0], "FETCH_SIZE")]) * 1024
+        cw = sum(counters[(cp[0][0], "WRITE_SIZE")]) / len(counters[(cp[0][0], "WRITE_SIZE")]) * 1024
+        f_scale, w_scale = (copy_bytes / 2) / cf, (copy_bytes / 2) / cw
+        bname = bp[0][0]
+        bf = sum(counters[(bname, "FETCH_SIZE")]) / len(counters[(bname, "FETCH_SIZE")]) * 1024
+        bw = sum(counters[(bname, "WRITE_SIZE")]) / len(counters[(bname, "WRITE_SIZE")]) * 1024
+        rec = {"kernel": bname, "source_sha256_16": source_hash(os.path.join(ROOT, "paper_1306_1392_amd", "csrc",
+                                                                             "k_bp.hip")),
+               "fetch_scale": f_scale, "write_scale": w_scale,
+               "fetch_bytes_per_launch": bf * f_scale, "write_bytes_per_launch": bw * w_scale,
+               "hbm_bytes_per_launch": bf * f_scale + bw * w_scale,
+               "calibration": "a device copy of 2 GiB reads 2 GiB and writes 2 GiB; scale = true bytes / counter bytes",
+               "command": PROFILE_CMDS["pmc"].replace("<dir>", d)}
+        jf = os.path.join(out_dir, "bp_fbp2048_traffic.json")
+        json.dump(rec, open(jf, "w"), indent=1)
+        log(f"wrote {jf}: {rec['hbm_bytes_per_launch'] / 1e9:.2f} GB per launch")
+
+
+def run_cnn(args):
+    """U-Net corrector throughput at the learned workload's shape: 512^2 slices, batch 32,
+    4 levels, 32 base channels (BF16 MFMA, FP32 accumulate).  Times one training step
+    (forward + MSE + backward + Adam) and inference."""
+    import torch
+    from paper_1306_1392_amd.cnn import UNet, init_params
+    dev = torch.device("cuda:0")
+    B, H = 32, 512
+    net = UNet(B, H, H, 32, 4)
+    net.set_params(init_params(32, 4, 0))
+    g = torch.Generator(device=dev)
+    g.manual_seed(1)
+    x = torch.rand((B, H, H), device=dev, generator=g)
+    t = torch.rand((B, H, H), device=dev, generator=g)
+    out = torch.empty_like(x)
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        net.train_step(x, t, 1e-4)
+        net.forward(x, out=out)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    reps = max(2, args.steps // 2)
+    e[0].record(st)
+    for _ in range(reps):
+        net.train_step(x, t, 1e-4)
+    e[1].record(st)
+    for _ in range(reps):
+        net.forward(x, out=out)
+    e[2].record(st)
+    torch.cuda.synchronize()
+    train_ms = e[0].elapsed_time(e[1]) / reps
+    infer_ms = e[1].elapsed_time(e[2]) / reps
+    fwd_flop = 73.4e9 * B   # 3x3 convs + transposed convs of the 4-level, 32-base U-Net at 512^2
+    res = {"metric": "U-Net corrector throughput", "value": round(B / (infer_ms * 1e-3), 1), "unit": "slices/s",
+           "higher_is_better": True, "n_gpus": 1, "dtype": "bf16 (fp32 accumulate)", "data": "synthetic",
+           "config": {"workload": "U-Net 4 levels, 32 base channels, batch 32 of 512x512"},
+           "train_step_ms": round(train_ms, 3), "infer_ms": round(infer_ms, 3),
+           "infer_tflops": round(fwd_flop / (infer_ms * 1e-3) / 1e12, 1),
+           "train_tflops": round(3 * fwd_flop / (train_ms * 1e-3) / 1e12, 1),
+           "mfma_bf16_peak_tflops": 2500.0}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,7 +357,13 @@ def main():
                     help="also run a plain 2 GiB device copy (reference kernel for HBM byte counters)")
     ap.add_argument("--tile-sweep", action="store_true", help="time the backprojector for every tile shape")
     ap.add_argument("--peaks", action="store_true", help="run the roofline microbenchmarks")
+    ap.add_argument("--workload", default="fbp2048", choices=["fbp2048", "uneven", "tv", "cnn"],
+                    help="fbp2048: the headline batch; uneven / tv: the other measured workloads")
+    ap.add_argument("--uneven-slices", type=int, default=500)
+    ap.add_argument("--summarize", metavar="DIR", help="write profiles/ summaries from rocprofv3 output in DIR")
     args = ap.parse_args()
+    if args.summarize:
+        return summarize_profiles(args.summarize)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (the slices of a batch are independent; "
               "DESIGN.md describes how the path shards across GPUs)", file=sys.stderr)
@@ -142,6 +374,12 @@ def main():
     import paper_1306_1392_amd as ph
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "uneven":
+        return run_uneven(args)
+    if args.workload == "tv":
+        return run_tv(args)
+    if args.workload == "cnn":
+        return run_cnn(args)
     dev = torch.device("cuda:0")
     R, N, K = args.slices, args.n, args.angles
     log(f"bench: generating {R} x {N}^2 slices, {K} angles, raw uint16 ...")
@@ -237,16 +475,21 @@ def main():
     stream.synchronize()
     filt_ms = ev2[0].elapsed_time(ev2[1]) / nbp
     del sino_f
-    achieved = U * BP_OPS_PER_UPDATE / (bp_ms * 1e-3) / 1e12
-    peak = VALU_LANE_OPS_PEAK / 1e12
-    res["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "Tops/s",
-                       "frac": round(achieved / peak, 4),
+    # roofline: the backprojector reads one 8-byte (q, dq) pair from LDS per update; the LDS
+    # read port (128 B/clk/CU) is the binding resource, the VALU mix (6 lane-ops/update) the next one
+    lds_achieved = BP_LDS_BYTES_PER_UPDATE * U / (bp_ms * 1e-3) / 1e9
+    valu_achieved = U * BP_OPS_PER_UPDATE / (bp_ms * 1e-3) / 1e12
+    res["roofline"] = {"bound": "lds", "achieved": round(lds_achieved, 1), "peak": round(LDS_PEAK_GBS, 1),
+                       "unit": "GB/s", "frac": round(lds_achieved / LDS_PEAK_GBS, 4),
                        "traffic": traffic_for(os.path.join(ROOT, "paper_1306_1392_amd", "csrc", "k_bp.hip"),
                                               "hbm_bytes_per_launch"),
+                       "algorithmic_hbm_bytes": (plan.filt_elems + plan.img_elems) * 4,
                        "kernel": "bp_kernel (backprojection)", "kernel_ms": round(bp_ms, 3),
-                       "ops_per_update": BP_OPS_PER_UPDATE, "updates_per_launch": U,
+                       "lds_bytes_per_update": BP_LDS_BYTES_PER_UPDATE, "updates_per_launch": U,
                        "bp_gups": round(U / (bp_ms * 1e-3) / 1e9, 2),
-                       "lds_tbytes_per_s": round(8.0 * U / (bp_ms * 1e-3) / 1e12, 2)}
+                       "valu": {"achieved_tops": round(valu_achieved, 2), "ops_per_update": BP_OPS_PER_UPDATE,
+                                "peak_tops": round(VALU_LANE_OPS_PEAK / 1e12, 2),
+                                "frac": round(valu_achieved / (VALU_LANE_OPS_PEAK / 1e12), 4)}}
     res["filter_ms"] = round(filt_ms, 3)
     res["filter_hbm_gbs"] = round((plan.sino_elems * 4 + plan.filt_elems * 4) / (filt_ms * 1e-3) / 1e9, 1)
     if args.peaks:

@@ -109,6 +109,13 @@ int pyhst_plan_sizes(const pyhst_plan *plan, int64_t *sino_elems, int64_t *filt_
  * cost-sorted (slice, tile) work list. */
 int pyhst_plan_set_tiles(pyhst_plan *plan, int32_t bp_tile, int32_t persistent);
 int pyhst_plan_get_tiles(const pyhst_plan *plan, int32_t *bp_tile, int32_t *persistent);
+/* Autotuner: times the backprojector of this plan for every tile shape, with
+ * and without the persistent work queue (reps launches each, HIP events on
+ * `stream`), on filt (filtered layout) -> img, and keeps the fastest.  Writes
+ * img; synchronises the stream; *best_ms (may be NULL) receives the time of one
+ * launch with the chosen setting. */
+int pyhst_plan_autotune(pyhst_plan *plan, const float *filt, float *img, int32_t reps, float *best_ms,
+                        hipStream_t stream);
 
 /* Dark/flat normalisation and -log (section 2.3, first steps of the pipe;
  * Beer-Lambert for absorption data), rearranged into sinograms (one per
@@ -159,7 +166,8 @@ int tv_prox(int32_t n_slices, int32_t n_y, int32_t n_x, const float *in, float *
  *   method PYHST_TV_CP: eq. (3), min_x 1/2|A x - y|^2 + lambda TV(x), by
  *     n_iter Chambolle-Pock iterations with K = [A; grad], tau = sigma =
  *     1/op_norm, theta = 1, from zero.  op_norm <= 0: estimated by 50 power
- *     iterations on the GPU (this synchronises the stream once).
+ *     iterations on the GPU (this synchronises the stream once) and written
+ *     back into op_norm.
  *     energy (host, [n_iter]) receives 1/2|A x - y|^2 + lambda TV(x) of the
  *     whole batch after every iteration (section 3.1: the energy is displayed
  *     so convergence can be checked); non-NULL energy makes the call
@@ -191,6 +199,44 @@ typedef struct {
 } pyhst_recon_args;
 
 int reconstruct_slices(const pyhst_plan *plan, pyhst_recon_args *a, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned sparse-angle corrector (not part of the paper, whose learned prior
+ * is an overlapping-patch dictionary, section 3.2): a U-Net applied to FBP
+ * slices as x_hat = x + f(x).  `levels` resolution levels (the last one is the
+ * bottleneck), base*2^l channels at level l, two 3x3 conv + ReLU per level,
+ * 2x2 max-pool down, 2x2 stride-2 transposed conv + ReLU up, skip
+ * concatenation [encoder | upsampled], 1x1 linear head.  BF16 activations and
+ * weights, FP32 accumulation (MFMA), FP32 master weights and Adam moments.
+ * Flat FP32 parameter order: per level l = 0..levels-1 the two encoder convs,
+ * then per level l = levels-2..0 the transposed conv and the two decoder
+ * convs, then the head; each layer stores its weights then its bias.  Conv
+ * weights are [c_out][3 ty + tx][c_in] (the first conv has c_in = 8, of which
+ * only channel 0 carries the image), transposed-conv weights [2 dy + dx][c_out][c_in],
+ * head weights [base] then one bias.
+ * Inputs/targets: device FP32 [n][height][width], n <= batch.  The network
+ * object owns its activation, gradient and optimizer buffers (allocated once
+ * at creation); later calls allocate nothing and only enqueue on `stream`. */
+typedef struct pyhst_unet pyhst_unet;
+int pyhst_unet_create(int32_t batch, int32_t height, int32_t width, int32_t base, int32_t levels,
+                      pyhst_unet **out);
+int pyhst_unet_destroy(pyhst_unet *net);
+int pyhst_unet_num_params(const pyhst_unet *net, int64_t *n);
+/* Load master weights (device FP32 [n_params]); resets the Adam state. */
+int pyhst_unet_set_params(pyhst_unet *net, const float *params, hipStream_t stream);
+int pyhst_unet_get_params(const pyhst_unet *net, float *params, hipStream_t stream);
+/* Gradients of the last pyhst_unet_backward (device FP32 [n_params]). */
+int pyhst_unet_get_grads(const pyhst_unet *net, float *grads, hipStream_t stream);
+int pyhst_unet_forward(pyhst_unet *net, const float *in, int32_t n, float *out, hipStream_t stream);
+/* Forward, mean-squared-error loss against target (device float *loss, may be
+ * NULL) and backward into the gradient buffer. */
+int pyhst_unet_backward(pyhst_unet *net, const float *in, const float *target, int32_t n, float *loss,
+                        hipStream_t stream);
+/* Adam step (bias-corrected) on the stored gradients, then refresh of the BF16 weight copies. */
+int pyhst_unet_adam(pyhst_unet *net, float lr, float beta1, float beta2, float eps, hipStream_t stream);
+/* backward + Adam (beta1 0.9, beta2 0.999, eps 1e-8). */
+int pyhst_unet_train_step(pyhst_unet *net, const float *in, const float *target, int32_t n, float lr, float *loss,
+                          hipStream_t stream);
 
 /* Roofline measurement kernels (not part of the reconstruction path).
  * kind 0: independent FP32 FMA chains, 8 lane-ops per thread and iteration;

@@ -17,7 +17,9 @@ FBP, TV_CP = 0, 1
 EXPORTS = ["pyhst_plan_create", "pyhst_plan_destroy", "pyhst_plan_slice_info", "pyhst_plan_sizes",
            "pyhst_plan_set_tiles", "pyhst_plan_get_tiles", "pyhst_normalize", "fbp_filter", "backproject",
            "forward_project", "tv_prox", "reconstruct_slices", "pyhst_microbench", "pyhst_strerror",
-           "pyhst_last_error"]
+           "pyhst_last_error", "pyhst_unet_create", "pyhst_unet_destroy", "pyhst_unet_num_params",
+           "pyhst_unet_set_params", "pyhst_unet_get_params", "pyhst_unet_get_grads", "pyhst_unet_forward",
+           "pyhst_unet_backward", "pyhst_unet_adam", "pyhst_unet_train_step", "pyhst_plan_autotune"]
 
 
 class Geom(ctypes.Structure):
@@ -67,6 +69,17 @@ def lib(path: str = LIB_PATH):
     L.tv_prox.argtypes = [c_int32, c_int32, c_int32, P, P, c_float, c_int32, P, c_size_t, P]
     L.reconstruct_slices.argtypes = [P, ctypes.POINTER(ReconArgs), P]
     L.pyhst_microbench.argtypes = [c_int32, c_int32, c_int32, P, P]
+    L.pyhst_unet_create.argtypes = [c_int32, c_int32, c_int32, c_int32, c_int32, ctypes.POINTER(c_void_p)]
+    L.pyhst_unet_destroy.argtypes = [P]
+    L.pyhst_unet_num_params.argtypes = [P, ctypes.POINTER(c_int64)]
+    L.pyhst_unet_set_params.argtypes = [P, P, P]
+    L.pyhst_unet_get_params.argtypes = [P, P, P]
+    L.pyhst_unet_get_grads.argtypes = [P, P, P]
+    L.pyhst_unet_forward.argtypes = [P, P, c_int32, P, P]
+    L.pyhst_unet_backward.argtypes = [P, P, P, c_int32, P, P]
+    L.pyhst_unet_adam.argtypes = [P, c_float, c_float, c_float, c_float, P]
+    L.pyhst_unet_train_step.argtypes = [P, P, P, c_int32, c_float, P, P]
+    L.pyhst_plan_autotune.argtypes = [P, P, P, c_int32, ctypes.POINTER(c_float), P]
     L.pyhst_strerror.argtypes = [c_int32]
     L.pyhst_strerror.restype = ctypes.c_char_p
     L.pyhst_last_error.restype = ctypes.c_char_p

@@ -115,6 +115,15 @@ class Plan:
         g = self.geoms[0]
         return (self.n_slices, g.n_y, g.n_x) if self.uniform else (self.img_elems,)
 
+    def autotune(self, filt, img, reps: int = 3, stream=None) -> float:
+        """Pick the fastest backprojector tile / scheduling for this plan on these buffers."""
+        _need(filt, self.filt_elems, "filt")
+        _need(img, self.img_elems, "img")
+        ms = ctypes.c_float()
+        check(self._L.pyhst_plan_autotune(self.handle, _ptr(filt), _ptr(img), int(reps), ctypes.byref(ms),
+                                          _stream(stream)), "pyhst_plan_autotune")
+        return ms.value
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             self._L.pyhst_plan_destroy(self.handle)
@@ -240,6 +249,7 @@ def reconstruct_slices(plan: Plan, *, raw=None, sino=None, flats=None, flat_pos=
     a.work = _ptr(work)
     a.work_bytes = work.numel() * work.element_size()
     check(L.reconstruct_slices(plan.handle, ctypes.byref(a), _stream(stream)), "reconstruct_slices")
+    plan.last_op_norm = a.op_norm
     return (out, E[:n_iter]) if energy else out
 
 

@@ -1,0 +1,756 @@
+// Learned sparse-angle corrector: a U-Net (encoder-decoder with skip
+// connections) applied as x_hat = x + f(x) to FBP slices, trained and run with
+// the MFMA BF16 implicit-GEMM kernels of cnn_gemm.hpp.  Not part of the paper
+// (its learned prior is an overlapping-patch dictionary); it serves the same
+// purpose: reconstruction quality from reduced data.
+//
+// Layout: activations NHWC BF16; master weights, gradients and Adam moments
+// FP32 in one flat array.  Conv weights [co][tap][ci] (tap = 3 ty + tx),
+// transposed-conv weights [d][co][ci] (d = 2 dy + dx), head [c] then bias.
+// Every conv and transposed conv is followed by ReLU; the head is linear.
+// Gradients of activations are BF16 and already multiplied by the ReLU mask of
+// the activation they belong to; weight gradients are split-K partial sums
+// reduced in a fixed order (deterministic).
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "cnn_gemm.hpp"
+#include "internal.hpp"
+
+using namespace pyhst;
+using namespace pyhst::cnn;
+
+namespace {
+
+struct Conv {
+    int cin, cout;          // cin as stored (first layer: 8, of which 1 is real)
+    int64_t w, b;           // offsets in the flat parameter array
+    bf16_t *wf, *wb;        // [co][tap][ci], [ci][8 - tap][co]
+};
+struct Up {
+    int cin, cout;
+    int64_t w, b;
+    bf16_t *uf, *ub;        // [(d, co)][ci], [ci][(d, co)]
+};
+struct Buf {                // an activation and its gradient, same layout
+    bf16_t *a, *g;
+    int H, W, C;            // C = channel stride
+};
+
+int tn_for(int n) { return n >= 128 ? 128 : (n >= 64 ? 64 : 32); }
+
+}  // namespace
+
+struct pyhst_unet {
+    int B, H, W, base, L;
+    int64_t n_params = 0;
+    float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
+    int *step = nullptr;
+    std::vector<Conv> enc_a, enc_b, dec_a, dec_b;   // enc: levels 0..L-1 (L-1 = bottleneck); dec: 0..L-2
+    std::vector<Up> up;                             // up[l]: level l+1 -> l
+    int64_t head_w = 0, head_b = 0;
+    Buf x8;
+    std::vector<Buf> ea, cat, pool, da, db;         // ea[l]: enc conv a out; cat[l]: [enc b out | up out]
+    Buf bott_b;                                     // bottleneck conv b out
+    float *out = nullptr, *dout = nullptr;
+    float *part = nullptr;                          // split-K partials / reduction partials
+    size_t part_floats = 0;
+    double *dpart = nullptr;
+    void *block = nullptr;
+};
+
+namespace {
+
+// ---------------------------------------------------------------- small kernels
+unsigned blocks_for(int64_t n, int64_t cap = 16384)
+{
+    int64_t b = (n + 255) / 256;
+    return (unsigned)std::max<int64_t>(1, std::min(b, cap));
+}
+
+#define GRID_LOOP(i, n) for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+__global__ void input_pad_kernel(const float *x, int64_t npix, bf16_t *x8)
+{
+    GRID_LOOP(p, npix)
+    {
+        uint4 v = make_uint4(f2bf(x[p]), 0, 0, 0);
+        *(uint4 *)(x8 + p * 8) = v;
+    }
+}
+
+// 2x2 max pool: in [b][H][W] (channels c at cs/co) -> out [b][H/2][W/2]
+__global__ void pool_fwd_kernel(Act in, int C, bf16_t *out, int ocs, int64_t n)
+{
+    const int h = in.H >> 1, w = in.W >> 1;
+    GRID_LOOP(i, n)
+    {
+        const int c = (int)(i % C);
+        const int64_t p = i / C;
+        const int x = (int)(p % w), y = (int)((p / w) % h), b = (int)(p / ((int64_t)w * h));
+        const bf16_t *base = in.p + ((int64_t)(b * in.H + 2 * y) * in.W + 2 * x) * in.cs + in.co + c;
+        float mx = bf2f(base[0]);
+        mx = fmaxf(mx, bf2f(base[in.cs]));
+        mx = fmaxf(mx, bf2f(base[(int64_t)in.W * in.cs]));
+        mx = fmaxf(mx, bf2f(base[(int64_t)in.W * in.cs + in.cs]));
+        out[p * ocs + c] = f2bf(mx);
+    }
+}
+
+// route the pooled gradient to the first maximum (row-major in the 2x2 window), adding to dE
+__global__ void pool_bwd_kernel(Act e, bf16_t *de, const bf16_t *dp, int pcs, int C, int64_t n)
+{
+    const int h = e.H >> 1, w = e.W >> 1;
+    GRID_LOOP(i, n)
+    {
+        const int c = (int)(i % C);
+        const int64_t p = i / C;
+        const int x = (int)(p % w), y = (int)((p / w) % h), b = (int)(p / ((int64_t)w * h));
+        const float g = bf2f(dp[p * pcs + c]);
+        const int64_t o0 = ((int64_t)(b * e.H + 2 * y) * e.W + 2 * x) * e.cs + e.co + c;
+        const int64_t off[4] = {0, e.cs, (int64_t)e.W * e.cs, (int64_t)e.W * e.cs + e.cs};
+        int arg = 0;
+        float mx = bf2f(e.p[o0]);
+        for (int q = 1; q < 4; ++q) {
+            const float v = bf2f(e.p[o0 + off[q]]);
+            if (v > mx) {
+                mx = v;
+                arg = q;
+            }
+        }
+        if (mx > 0.0f && g != 0.0f) de[o0 + off[arg]] = f2bf(bf2f(de[o0 + off[arg]]) + g);
+    }
+}
+
+// out = x + bh + sum_c D[p][c] wh[c]   (FP32 accumulation of the BF16 activations)
+__global__ void head_fwd_kernel(const bf16_t *d, int C, const float *wh, const float *bh, const float *x, float *out,
+                                int64_t npix)
+{
+    GRID_LOOP(p, npix)
+    {
+        float s = 0.0f;
+        for (int c = 0; c < C; ++c) s = fmaf(bf2f(d[p * C + c]), wh[c], s);
+        out[p] = x[p] + (bh[0] + s);
+    }
+}
+
+__device__ inline double block_sum_d(double v, double *sh)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+    return t;
+}
+
+// loss partials: sum (out - t)^2 per block; dout = 2 (out - t) / n
+__global__ __launch_bounds__(256) void mse_kernel(const float *out, const float *t, float *dout, int64_t n,
+                                                  double *partials)
+{
+    __shared__ double sh[4];
+    double acc = 0.0;
+    const float sc = 2.0f / (float)n;
+    GRID_LOOP(p, n)
+    {
+        const float d = out[p] - t[p];
+        acc += (double)d * d;
+        dout[p] = sc * d;
+    }
+    const double s = block_sum_d(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void final_mean_kernel(const double *partials, int nb, int64_t n, float *loss)
+{
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += partials[i];
+    const double s = block_sum_d(acc, sh);
+    if (threadIdx.x == 0 && loss) *loss = (float)(s / (double)n);
+}
+
+// dD[p][c] = bf16(dout[p] wh[c]) where D > 0 (C <= 256 threads per pixel chunk)
+__global__ void head_bwd_data_kernel(const bf16_t *d, int C, const float *wh, const float *dout, bf16_t *dd,
+                                     int64_t n)
+{
+    GRID_LOOP(i, n)
+    {
+        const int c = (int)(i % C);
+        const int64_t p = i / C;
+        dd[i] = f2bf(bf2f(d[i]) > 0.0f ? dout[p] * wh[c] : 0.0f);
+    }
+}
+
+// per-block partial sums over pixels of v[p][c] * (s ? s[p] : 1), channel c = threadIdx.x (< C)
+__global__ __launch_bounds__(256) void chan_partial_kernel(const bf16_t *v, int cs, int co, int C, const float *s,
+                                                           int64_t npix, int64_t chunk, float *part)
+{
+    const int64_t p0 = blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        float acc = 0.0f;
+        for (int64_t p = p0; p < p1; ++p) {
+            const float x = bf2f(v[p * cs + co + c]);
+            acc = s ? fmaf(x, s[p], acc) : acc + x;
+        }
+        part[(int64_t)blockIdx.x * C + c] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void dout_partial_kernel(const float *d, int64_t npix, int64_t chunk, float *part)
+{
+    __shared__ double sh[4];
+    const int64_t p0 = blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
+    double acc = 0.0;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) acc += d[p];
+    const double s = block_sum_d(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = (float)s;
+}
+
+// dst[c] = sum over nb blocks of part[blk][c] (fixed order)
+__global__ void reduce_rows_kernel(const float *part, int nb, int C, float *dst)
+{
+    GRID_LOOP(c, C)
+    {
+        double s = 0.0;
+        for (int i = 0; i < nb; ++i) s += part[(int64_t)i * C + c];
+        dst[c] = (float)s;
+    }
+}
+
+// dst[n * M + m] = sum_s part[s][m][n]
+__global__ void reduce_splitk_T_kernel(const float *part, int splits, int M, int N, float *dst)
+{
+    GRID_LOOP(i, (int64_t)M * N)
+    {
+        const int n = (int)(i / M), m = (int)(i - (int64_t)n * M);
+        double s = 0.0;
+        for (int k = 0; k < splits; ++k) s += part[((int64_t)k * M + m) * N + n];
+        dst[i] = (float)s;
+    }
+}
+
+__global__ void adam_kernel(float *p, const float *g, float *m, float *v, int64_t n, const int *step, float lr,
+                            float b1, float b2, float eps)
+{
+    const int t = *step + 1;
+    const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+    GRID_LOOP(i, n)
+    {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+__global__ void step_inc_kernel(int *step) { *step += 1; }
+
+// master W[co][tap][ci] -> wf (same layout) and wb[ci][8 - tap][co]
+__global__ void cast_conv_kernel(const float *w, int cin, int cout, bf16_t *wf, bf16_t *wb)
+{
+    GRID_LOOP(i, (int64_t)cout * 9 * cin)
+    {
+        const int ci = (int)(i % cin), tap = (int)((i / cin) % 9), co = (int)(i / (9 * (int64_t)cin));
+        const bf16_t b = f2bf(w[i]);
+        wf[i] = b;
+        wb[((int64_t)ci * 9 + (8 - tap)) * cout + co] = b;
+    }
+}
+
+// master U[d][co][ci] -> uf (same layout) and ub[ci][(d, co)]
+__global__ void cast_up_kernel(const float *u, int cin, int cout, bf16_t *uf, bf16_t *ub)
+{
+    GRID_LOOP(i, (int64_t)4 * cout * cin)
+    {
+        const int ci = (int)(i % cin);
+        const int64_t dco = i / cin;
+        const bf16_t b = f2bf(u[i]);
+        uf[i] = b;
+        ub[(int64_t)ci * 4 * cout + dco] = b;
+    }
+}
+
+__global__ void fill_f32_kernel(float *p, int64_t n, float v)
+{
+    GRID_LOOP(i, n) p[i] = v;
+}
+__global__ void fill_i32_kernel(int *p, int v) { *p = v; }
+
+// ---------------------------------------------------------------- layer drivers
+Act act(const Buf &b, int n, int co = 0, bool grad = false) { return Act{grad ? b.g : b.a, n, b.H, b.W, b.C, co}; }
+
+hipError_t conv_fwd(const pyhst_unet &net, const Conv &L, Act in, bf16_t *out, int ocs, int oco, hipStream_t st)
+{
+    const int M = in.B * in.H * in.W;
+    Im2colA A{in, L.cin};
+    WeightB Bw{L.wf, 9 * L.cin};
+    StoreAct E{out, ocs, oco, net.params + L.b, 1};
+    switch (tn_for(L.cout)) {
+    case 128: return run_gemm<Im2colA, WeightB, StoreAct, 128>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
+    case 64: return run_gemm<Im2colA, WeightB, StoreAct, 64>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
+    default: return run_gemm<Im2colA, WeightB, StoreAct, 32>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
+    }
+}
+
+hipError_t up_fwd(const pyhst_unet &net, const Up &L, Act in, bf16_t *out, int H2, int W2, int ocs, int oco,
+                  hipStream_t st)
+{
+    const int M = in.B * in.H * in.W;
+    PlainA A{in};
+    WeightB Bw{L.uf, L.cin};
+    StoreUp E{out, H2, W2, ocs, oco, L.cout, net.params + L.b};
+    return run_gemm<PlainA, WeightB, StoreUp, 128>(A, Bw, E, M, 4 * L.cout, L.cin, 1, st);
+}
+
+// splits for a split-K weight gradient so that the grid has about 2048 workgroups
+int splits_for(int M, int N, int TN, int K, size_t part_cap)
+{
+    const int tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+    int s = std::max(1, 2048 / tiles);
+    s = std::min(s, std::max(1, K / (4 * TK)));
+    while (s > 1 && (size_t)s * M * N > part_cap) --s;
+    int ks = (K + s - 1) / s;
+    ks = (ks + TK - 1) / TK * TK;
+    return (K + ks - 1) / ks;
+}
+
+hipError_t chan_sum(const pyhst_unet &net, Act g, int C, const float *scale, float *dst, hipStream_t st)
+{
+    const int64_t npix = (int64_t)g.B * g.H * g.W;
+    const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, npix / 64));
+    const int64_t chunk = (npix + nb - 1) / nb;
+    chan_partial_kernel<<<nb, 256, 0, st>>>(g.p, g.cs, g.co, C, scale, npix, chunk, net.part);
+    reduce_rows_kernel<<<blocks_for(C), 256, 0, st>>>(net.part, nb, C, dst);
+    return hipGetLastError();
+}
+
+// dZ = gradient at this conv's (ReLU'd) output.  Writes dW, db; if dx != nullptr also dX (masked by X > 0).
+hipError_t conv_bwd(const pyhst_unet &net, const Conv &L, Act x, Act dz, bf16_t *dx, int dxcs, int dxco,
+                    hipStream_t st)
+{
+    const int npix = x.B * x.H * x.W;
+    hipError_t e;
+    // weight gradient: C[m = (tap, ci)][n = co] = sum_pix X[pix + off][ci] dZ[pix][co]
+    {
+        const int M = 9 * L.cin, N = L.cout, tn = tn_for(N);
+        const int s = splits_for(M, N, tn, npix, net.part_floats);
+        Im2colT A{x, L.cin};
+        PlainT Bz{dz};
+        StorePartial E{net.part, M, N};
+        int ks = (npix + s - 1) / s;
+        ks = (ks + TK - 1) / TK * TK;
+        const int sp = (npix + ks - 1) / ks;
+        dim3 grid((M + TM - 1) / TM, (N + tn - 1) / tn, sp);
+        if (tn == 128) gemm_kernel<Im2colT, PlainT, StorePartial, 128><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
+        else if (tn == 64) gemm_kernel<Im2colT, PlainT, StorePartial, 64><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
+        else gemm_kernel<Im2colT, PlainT, StorePartial, 32><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
+        reduce_splitk_T_kernel<<<blocks_for((int64_t)M * N), 256, 0, st>>>(net.part, sp, M, N, net.grads + L.w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = chan_sum(net, dz, L.cout, nullptr, net.grads + L.b, st)) != hipSuccess) return e;
+    if (dx) {
+        // dX[pix][ci] = sum_{tap', co} dZ[pix + off(tap')][co] Wb[ci][tap'][co], masked by X > 0
+        const int M = npix, N = L.cin;
+        Im2colA A{dz, L.cout};
+        WeightB Bw{L.wb, 9 * L.cout};
+        StoreMasked E{dx, dxcs, dxco, x.p, x.cs, x.co};
+        switch (tn_for(N)) {
+        case 128: e = run_gemm<Im2colA, WeightB, StoreMasked, 128>(A, Bw, E, M, N, 9 * L.cout, 1, st); break;
+        case 64: e = run_gemm<Im2colA, WeightB, StoreMasked, 64>(A, Bw, E, M, N, 9 * L.cout, 1, st); break;
+        default: e = run_gemm<Im2colA, WeightB, StoreMasked, 32>(A, Bw, E, M, N, 9 * L.cout, 1, st); break;
+        }
+    }
+    return e;
+}
+
+// transposed conv backward.  x: low-res input, dy: high-res gradient (channels at its co), dx: input gradient
+hipError_t up_bwd(const pyhst_unet &net, const Up &L, Act x, Act dy, bf16_t *dx, int dxcs, hipStream_t st)
+{
+    const int npix = x.B * x.H * x.W;
+    hipError_t e;
+    {
+        const int M = L.cin, N = 4 * L.cout, tn = tn_for(N);
+        const int s = splits_for(M, N, tn, npix, net.part_floats);
+        PlainT A{x};
+        UpGatherT Bz{dy, L.cout};
+        StorePartial E{net.part, M, N};
+        int ks = (npix + s - 1) / s;
+        ks = (ks + TK - 1) / TK * TK;
+        const int sp = (npix + ks - 1) / ks;
+        dim3 grid((M + TM - 1) / TM, (N + tn - 1) / tn, sp);
+        if (tn == 128) gemm_kernel<PlainT, UpGatherT, StorePartial, 128><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
+        else if (tn == 64) gemm_kernel<PlainT, UpGatherT, StorePartial, 64><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
+        else gemm_kernel<PlainT, UpGatherT, StorePartial, 32><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
+        reduce_splitk_T_kernel<<<blocks_for((int64_t)M * N), 256, 0, st>>>(net.part, sp, M, N, net.grads + L.w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = chan_sum(net, dy, L.cout, nullptr, net.grads + L.b, st)) != hipSuccess) return e;
+    const int M = npix, N = L.cin;
+    UpGatherA A{dy, L.cout};
+    WeightB Bw{L.ub, 4 * L.cout};
+    StoreMasked E{dx, dxcs, 0, x.p, x.cs, x.co};
+    switch (tn_for(N)) {
+    case 128: return run_gemm<UpGatherA, WeightB, StoreMasked, 128>(A, Bw, E, M, N, 4 * L.cout, 1, st);
+    case 64: return run_gemm<UpGatherA, WeightB, StoreMasked, 64>(A, Bw, E, M, N, 4 * L.cout, 1, st);
+    default: return run_gemm<UpGatherA, WeightB, StoreMasked, 32>(A, Bw, E, M, N, 4 * L.cout, 1, st);
+    }
+}
+
+hipError_t cast_all(const pyhst_unet &net, hipStream_t st)
+{
+    auto cc = [&](const Conv &c) {
+        cast_conv_kernel<<<blocks_for((int64_t)c.cout * 9 * c.cin), 256, 0, st>>>(net.params + c.w, c.cin, c.cout,
+                                                                                  c.wf, c.wb);
+    };
+    for (auto &c : net.enc_a) cc(c);
+    for (auto &c : net.enc_b) cc(c);
+    for (auto &c : net.dec_a) cc(c);
+    for (auto &c : net.dec_b) cc(c);
+    for (auto &u : net.up)
+        cast_up_kernel<<<blocks_for((int64_t)4 * u.cout * u.cin), 256, 0, st>>>(net.params + u.w, u.cin, u.cout,
+                                                                                u.uf, u.ub);
+    return hipGetLastError();
+}
+
+hipError_t forward(pyhst_unet &net, const float *in, int n, float *out, hipStream_t st)
+{
+    const int L = net.L;
+    hipError_t e;
+    input_pad_kernel<<<blocks_for((int64_t)n * net.H * net.W), 256, 0, st>>>(in, (int64_t)n * net.H * net.W,
+                                                                             net.x8.a);
+    Act cur = act(net.x8, n);
+    for (int l = 0; l < L; ++l) {
+        const bool bott = l == L - 1;
+        if ((e = conv_fwd(net, net.enc_a[l], cur, net.ea[l].a, net.ea[l].C, 0, st)) != hipSuccess) return e;
+        Act a = act(net.ea[l], n);
+        if (bott) {
+            if ((e = conv_fwd(net, net.enc_b[l], a, net.bott_b.a, net.bott_b.C, 0, st)) != hipSuccess) return e;
+        } else {
+            if ((e = conv_fwd(net, net.enc_b[l], a, net.cat[l].a, net.cat[l].C, 0, st)) != hipSuccess) return e;
+            const int c = net.enc_b[l].cout;
+            const int64_t np = (int64_t)n * net.pool[l].H * net.pool[l].W * c;
+            pool_fwd_kernel<<<blocks_for(np), 256, 0, st>>>(act(net.cat[l], n), c, net.pool[l].a, net.pool[l].C, np);
+            cur = act(net.pool[l], n);
+        }
+    }
+    Act below = act(net.bott_b, n);
+    for (int l = L - 2; l >= 0; --l) {
+        const Up &u = net.up[l];
+        if ((e = up_fwd(net, u, below, net.cat[l].a, net.cat[l].H, net.cat[l].W, net.cat[l].C, u.cout, st)) !=
+            hipSuccess)
+            return e;
+        if ((e = conv_fwd(net, net.dec_a[l], act(net.cat[l], n), net.da[l].a, net.da[l].C, 0, st)) != hipSuccess)
+            return e;
+        if ((e = conv_fwd(net, net.dec_b[l], act(net.da[l], n), net.db[l].a, net.db[l].C, 0, st)) != hipSuccess)
+            return e;
+        below = act(net.db[l], n);
+    }
+    const int64_t npix = (int64_t)n * net.H * net.W;
+    head_fwd_kernel<<<blocks_for(npix), 256, 0, st>>>(net.db[0].a, net.db[0].C, net.params + net.head_w,
+                                                      net.params + net.head_b, in, out, npix);
+    return hipGetLastError();
+}
+
+hipError_t backward(pyhst_unet &net, const float *in, const float *target, int n, float *loss, hipStream_t st)
+{
+    hipError_t e = forward(net, in, n, net.out, st);
+    if (e != hipSuccess) return e;
+    const int L = net.L;
+    const int64_t npix = (int64_t)n * net.H * net.W;
+    const int nb = (int)blocks_for(npix, 1024);
+    mse_kernel<<<nb, 256, 0, st>>>(net.out, target, net.dout, npix, net.dpart);
+    final_mean_kernel<<<1, 256, 0, st>>>(net.dpart, nb, npix, loss);
+    // head
+    {
+        const int C = net.db[0].C;
+        head_bwd_data_kernel<<<blocks_for(npix * C), 256, 0, st>>>(net.db[0].a, C, net.params + net.head_w,
+                                                                   net.dout, net.db[0].g, npix * C);
+        Act d0 = act(net.db[0], n);
+        if ((e = chan_sum(net, d0, C, net.dout, net.grads + net.head_w, st)) != hipSuccess) return e;
+        const int pb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, npix / 256));
+        const int64_t chunk = (npix + pb - 1) / pb;
+        dout_partial_kernel<<<pb, 256, 0, st>>>(net.dout, npix, chunk, net.part);
+        reduce_rows_kernel<<<1, 256, 0, st>>>(net.part, pb, 1, net.grads + net.head_b);
+    }
+    // decoder, top (level 0) to bottom
+    for (int l = 0; l <= L - 2; ++l) {
+        // dec b: input da[l], grad at output db[l].g
+        if ((e = conv_bwd(net, net.dec_b[l], act(net.da[l], n), act(net.db[l], n, 0, true), net.da[l].g,
+                          net.da[l].C, 0, st)) != hipSuccess)
+            return e;
+        // dec a: input cat[l] -> gradient into cat[l].g (both halves, masked)
+        if ((e = conv_bwd(net, net.dec_a[l], act(net.cat[l], n), act(net.da[l], n, 0, true), net.cat[l].g,
+                          net.cat[l].C, 0, st)) != hipSuccess)
+            return e;
+        // up[l]: input = level l+1 output (bott_b or db[l+1]); its gradient is in cat[l].g channels [c, 2c)
+        const Up &u = net.up[l];
+        Buf &below = (l + 1 == L - 1) ? net.bott_b : net.db[l + 1];
+        if ((e = up_bwd(net, u, act(below, n), act(net.cat[l], n, u.cout, true), below.g, below.C, st)) !=
+            hipSuccess)
+            return e;
+    }
+    // bottleneck and encoder, bottom to top
+    for (int l = L - 1; l >= 0; --l) {
+        const bool bott = l == L - 1;
+        Act a = act(net.ea[l], n);
+        Act dz_b = bott ? act(net.bott_b, n, 0, true) : act(net.cat[l], n, 0, true);
+        if ((e = conv_bwd(net, net.enc_b[l], a, dz_b, net.ea[l].g, net.ea[l].C, 0, st)) != hipSuccess) return e;
+        Act in = l == 0 ? act(net.x8, n) : act(net.pool[l - 1], n);
+        bf16_t *din = l == 0 ? nullptr : net.pool[l - 1].g;
+        if ((e = conv_bwd(net, net.enc_a[l], in, act(net.ea[l], n, 0, true), din, l == 0 ? 0 : net.pool[l - 1].C, 0,
+                          st)) != hipSuccess)
+            return e;
+        if (l > 0) {
+            // pool of level l-1: add its gradient into the encoder output of level l-1 (cat[l-1] channels [0, c))
+            const int c = net.enc_b[l - 1].cout;
+            const int64_t np = (int64_t)n * net.pool[l - 1].H * net.pool[l - 1].W * c;
+            pool_bwd_kernel<<<blocks_for(np), 256, 0, st>>>(act(net.cat[l - 1], n), net.cat[l - 1].g,
+                                                            net.pool[l - 1].g, net.pool[l - 1].C, c, np);
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+int pyhst_unet_create(int32_t batch, int32_t height, int32_t width, int32_t base, int32_t levels, pyhst_unet **out)
+{
+    if (!out) return fail(PYHST_EARG, "unet_create: out is NULL");
+    *out = nullptr;
+    if (batch <= 0 || levels < 2 || levels > 6 || base <= 0 || base % 8 != 0)
+        return fail(PYHST_EARG, "unet_create: need batch > 0, 2 <= levels <= 6, base a multiple of 8");
+    const int div = 1 << (levels - 1);
+    if (height <= 0 || width <= 0 || height % div || width % div)
+        return fail(PYHST_EARG, "unet_create: height and width must be divisible by 2^(levels-1)");
+    auto *net = new pyhst_unet();
+    net->B = batch;
+    net->H = height;
+    net->W = width;
+    net->base = base;
+    net->L = levels;
+    const int L = levels;
+    int64_t np = 0;
+    auto conv = [&](int cin, int cout) {
+        Conv c{cin, cout, np, 0, nullptr, nullptr};
+        np += (int64_t)cout * 9 * cin;
+        c.b = np;
+        np += cout;
+        return c;
+    };
+    auto upl = [&](int cin, int cout) {
+        Up u{cin, cout, np, 0, nullptr, nullptr};
+        np += (int64_t)4 * cout * cin;
+        u.b = np;
+        np += cout;
+        return u;
+    };
+    for (int l = 0; l < L; ++l) {
+        const int c = base << l, cin = l == 0 ? 8 : (base << (l - 1));
+        net->enc_a.push_back(conv(cin, c));
+        net->enc_b.push_back(conv(c, c));
+    }
+    net->up.resize(L - 1);
+    net->dec_a.resize(L - 1);
+    net->dec_b.resize(L - 1);
+    for (int l = L - 2; l >= 0; --l) {
+        const int c = base << l;
+        net->up[l] = upl(2 * c, c);
+        net->dec_a[l] = conv(2 * c, c);
+        net->dec_b[l] = conv(c, c);
+    }
+    net->head_w = np;
+    np += base;
+    net->head_b = np;
+    np += 1;
+    net->n_params = np;
+
+    // memory plan
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = (off + bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    struct Pending {
+        Buf *b;
+        size_t oa, og;
+    };
+    std::vector<Pending> bufs;
+    auto buf = [&](Buf &b, int H, int W, int C) {
+        b.H = H;
+        b.W = W;
+        b.C = C;
+        const size_t bytes = (size_t)batch * H * W * C * sizeof(bf16_t);
+        bufs.push_back({&b, take(bytes), take(bytes)});
+    };
+    net->ea.resize(L);
+    net->cat.resize(L - 1);
+    net->pool.resize(L - 1);
+    net->da.resize(L - 1);
+    net->db.resize(L - 1);
+    buf(net->x8, height, width, 8);
+    for (int l = 0; l < L; ++l) {
+        const int H = height >> l, W = width >> l, c = base << l;
+        buf(net->ea[l], H, W, c);
+        if (l < L - 1) {
+            buf(net->cat[l], H, W, 2 * c);
+            buf(net->pool[l], H >> 1, W >> 1, c);
+            buf(net->da[l], H, W, c);
+            buf(net->db[l], H, W, c);
+        } else {
+            buf(net->bott_b, H, W, c);
+        }
+    }
+    const size_t o_params = take(4 * np), o_grads = take(4 * np), o_m = take(4 * np), o_v = take(4 * np);
+    const size_t o_step = take(64);
+    const size_t o_out = take((size_t)4 * batch * height * width), o_dout = take((size_t)4 * batch * height * width);
+    // partial buffer: the largest split-K partial set, and reduction partials
+    size_t part = 0;
+    auto need = [&](int M, int N, int K) {
+        const int tn = tn_for(N);
+        const int tiles = ((M + TM - 1) / TM) * ((N + tn - 1) / tn);
+        int s = std::max(1, 2048 / tiles);
+        s = std::min(s, std::max(1, K / (4 * TK)));
+        part = std::max(part, (size_t)s * M * N);
+    };
+    for (int l = 0; l < L; ++l) {
+        const int npix = batch * (height >> l) * (width >> l);
+        need(9 * net->enc_a[l].cin, net->enc_a[l].cout, npix);
+        need(9 * net->enc_b[l].cin, net->enc_b[l].cout, npix);
+        if (l < L - 1) {
+            need(9 * net->dec_a[l].cin, net->dec_a[l].cout, npix);
+            need(9 * net->dec_b[l].cin, net->dec_b[l].cout, npix);
+            need(net->up[l].cin, 4 * net->up[l].cout, npix / 4);
+        }
+    }
+    part = std::max<size_t>(part, (size_t)1024 * 512);
+    net->part_floats = part;
+    const size_t o_part = take(4 * part), o_dpart = take(8 * 4096);
+    std::vector<std::pair<bf16_t **, size_t>> wbufs;
+    auto wb = [&](bf16_t **p, int64_t n) { wbufs.push_back({p, take(2 * n)}); };
+    for (auto *vec : {&net->enc_a, &net->enc_b, &net->dec_a, &net->dec_b})
+        for (auto &c : *vec) {
+            wb(&c.wf, (int64_t)c.cout * 9 * c.cin);
+            wb(&c.wb, (int64_t)c.cout * 9 * c.cin);
+        }
+    for (auto &u : net->up) {
+        wb(&u.uf, (int64_t)4 * u.cout * u.cin);
+        wb(&u.ub, (int64_t)4 * u.cout * u.cin);
+    }
+    hipError_t e = hipMalloc(&net->block, off);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete net;
+        return fail(PYHST_ENOMEM, "unet_create: hipMalloc failed");
+    }
+    e = hipMemset(net->block, 0, off);
+    if (e != hipSuccess) {
+        (void)hipFree(net->block);
+        delete net;
+        return hip_fail(e, "unet_create: hipMemset");
+    }
+    unsigned char *b = (unsigned char *)net->block;
+    for (auto &p : bufs) {
+        p.b->a = (bf16_t *)(b + p.oa);
+        p.b->g = (bf16_t *)(b + p.og);
+    }
+    for (auto &p : wbufs) *p.first = (bf16_t *)(b + p.second);
+    net->params = (float *)(b + o_params);
+    net->grads = (float *)(b + o_grads);
+    net->m = (float *)(b + o_m);
+    net->v = (float *)(b + o_v);
+    net->step = (int *)(b + o_step);
+    net->out = (float *)(b + o_out);
+    net->dout = (float *)(b + o_dout);
+    net->part = (float *)(b + o_part);
+    net->dpart = (double *)(b + o_dpart);
+    *out = net;
+    return PYHST_OK;
+}
+
+int pyhst_unet_destroy(pyhst_unet *net)
+{
+    if (!net) return PYHST_OK;
+    if (net->block) (void)hipFree(net->block);
+    delete net;
+    return PYHST_OK;
+}
+
+int pyhst_unet_num_params(const pyhst_unet *net, int64_t *n)
+{
+    if (!net || !n) return fail(PYHST_EARG, "unet_num_params: NULL argument");
+    *n = net->n_params;
+    return PYHST_OK;
+}
+
+int pyhst_unet_set_params(pyhst_unet *net, const float *params, hipStream_t st)
+{
+    if (!net || !params) return fail(PYHST_EARG, "unet_set_params: NULL argument");
+    hipError_t e = hipMemcpyAsync(net->params, params, 4 * net->n_params, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "unet_set_params");
+    fill_f32_kernel<<<blocks_for(net->n_params), 256, 0, st>>>(net->m, net->n_params, 0.0f);
+    fill_f32_kernel<<<blocks_for(net->n_params), 256, 0, st>>>(net->v, net->n_params, 0.0f);
+    fill_i32_kernel<<<1, 1, 0, st>>>(net->step, 0);
+    e = cast_all(*net, st);
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "unet_set_params");
+}
+
+int pyhst_unet_get_params(const pyhst_unet *net, float *params, hipStream_t st)
+{
+    if (!net || !params) return fail(PYHST_EARG, "unet_get_params: NULL argument");
+    hipError_t e = hipMemcpyAsync(params, net->params, 4 * net->n_params, hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "unet_get_params");
+}
+
+int pyhst_unet_get_grads(const pyhst_unet *net, float *grads, hipStream_t st)
+{
+    if (!net || !grads) return fail(PYHST_EARG, "unet_get_grads: NULL argument");
+    hipError_t e = hipMemcpyAsync(grads, net->grads, 4 * net->n_params, hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "unet_get_grads");
+}
+
+int pyhst_unet_forward(pyhst_unet *net, const float *in, int32_t n, float *out, hipStream_t st)
+{
+    if (!net || !in || !out) return fail(PYHST_EARG, "unet_forward: NULL argument");
+    if (n <= 0 || n > net->B) return fail(PYHST_EARG, "unet_forward: n must be in [1, batch]");
+    hipError_t e = forward(*net, in, n, out, st);
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "unet_forward");
+}
+
+int pyhst_unet_backward(pyhst_unet *net, const float *in, const float *target, int32_t n, float *loss,
+                        hipStream_t st)
+{
+    if (!net || !in || !target) return fail(PYHST_EARG, "unet_backward: NULL argument");
+    if (n <= 0 || n > net->B) return fail(PYHST_EARG, "unet_backward: n must be in [1, batch]");
+    hipError_t e = backward(*net, in, target, n, loss, st);
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "unet_backward");
+}
+
+int pyhst_unet_adam(pyhst_unet *net, float lr, float beta1, float beta2, float eps, hipStream_t st)
+{
+    if (!net || !(lr >= 0.0f)) return fail(PYHST_EARG, "unet_adam: bad argument");
+    adam_kernel<<<blocks_for(net->n_params), 256, 0, st>>>(net->params, net->grads, net->m, net->v, net->n_params,
+                                                           net->step, lr, beta1, beta2, eps);
+    step_inc_kernel<<<1, 1, 0, st>>>(net->step);
+    hipError_t e = cast_all(*net, st);
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "unet_adam");
+}
+
+int pyhst_unet_train_step(pyhst_unet *net, const float *in, const float *target, int32_t n, float lr, float *loss,
+                          hipStream_t st)
+{
+    int rc = pyhst_unet_backward(net, in, target, n, loss, st);
+    if (rc) return rc;
+    return pyhst_unet_adam(net, lr, 0.9f, 0.999f, 1e-8f, st);
+}
+
+}  // extern "C"

@@ -11,7 +11,8 @@
 // FP32 coordinate stays below ~100 bins (ulp < 8e-6 bin).  Lanes of a wave own
 // one 8x8 pixel block per register slot, so one ds_read_b64 of a wave touches
 // at most ~13 consecutive window entries (no bank conflicts).  The per-block
-// coordinate offsets are wave-uniform and come from a scalar table.
+// coordinate offsets are wave-uniform and come from a scalar table.  The bound
+// is the LDS read port: 8 B per update against 128 B/clk/CU.
 #include "internal.hpp"
 
 namespace pyhst {
@@ -27,7 +28,7 @@ typedef __attribute__((address_space(4))) const float cfloat;
 template <int CFG, int MODE>
 __global__ __launch_bounds__(256) void bp_kernel(Tables T, const float *__restrict__ sino, int filtered,
                                                  float *__restrict__ img, float alpha, float beta,
-                                                 int64_t n_items, int persistent, CpPrimal cp)
+                                                 int64_t n_items, int persistent, int xcd_remap, CpPrimal cp)
 {
     constexpr int BX = TILE_BX[CFG], BY = TILE_BY[CFG];
     constexpr int TW = 8 * BX, TH = 32 * BY;
@@ -51,7 +52,16 @@ __global__ __launch_bounds__(256) void bp_kernel(Tables T, const float *__restri
             __syncthreads();
         } else {
             if (round > 0) break;
+            // Workgroups are dealt round-robin to the 8 XCDs.  For a uniform batch give each
+            // XCD a contiguous range of the work list (whole slices) so a slice's sinogram is
+            // fetched into one XCD's L2 rather than into all eight.  (Uneven batches keep the
+            // cost-sorted order, which round-robin spreads evenly over the XCDs.)
             item = blockIdx.x;
+            if (xcd_remap) {
+                const int64_t b = blockIdx.x, q = n_items >> 3, r = n_items & 7;
+                const int64_t x = b & 7;
+                item = x * q + min(x, r) + (b >> 3);
+            }
         }
         if (item >= n_items) break;
 
@@ -179,9 +189,10 @@ hipError_t launch_cfg(const pyhst_plan &p, const float *sino, int filtered, floa
         if (per_cu < 1) per_cu = 1;
         int64_t grid = (int64_t)per_cu * p.cu_count;
         if (grid > n) grid = n;
-        bp_kernel<CFG, MODE><<<(unsigned)grid, 256, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n, 1, cp);
+        bp_kernel<CFG, MODE><<<(unsigned)grid, 256, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n, 1, 0, cp);
     } else {
-        bp_kernel<CFG, MODE><<<(unsigned)n, 256, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n, 0, cp);
+        bp_kernel<CFG, MODE><<<(unsigned)n, 256, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n, 0,
+                                                            p.uniform ? 1 : 0, cp);
     }
     return hipGetLastError();
 }

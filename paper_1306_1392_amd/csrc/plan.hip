@@ -30,6 +30,7 @@ int choose_tile(const pyhst_plan &p)
 {
     if (p.bp_tile >= 0 && p.bp_tile < N_TILE_CFG) return p.bp_tile;
     const int64_t want = 2LL * p.cu_count;
+    if (p.n_items[4] >= want) return 4;
     if (p.n_items[0] >= want) return 0;
     if (p.n_items[1] >= want) return 1;
     return 3;
@@ -537,3 +538,53 @@ int tv_prox(int32_t n_slices, int32_t n_y, int32_t n_x, const float *in, float *
 }
 
 }  // extern "C"
+
+// Backprojector autotuner: time every tile shape, with and without the
+// persistent work queue, on the caller's buffers, keep the fastest.
+extern "C" int pyhst_plan_autotune(pyhst_plan *p, const float *filt, float *img, int32_t reps, float *best_ms,
+                                   hipStream_t st)
+{
+    if (!p || !filt || !img || reps <= 0) return fail(PYHST_EARG, "autotune: bad argument");
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_fail(e, "autotune: event");
+    float best = 1e30f;
+    int bt = 0, bp = 0;
+    const int keep_tile = p->bp_tile, keep_pers = p->persistent;
+    for (int pers = 0; pers < 2 && e == hipSuccess; ++pers) {
+        for (int t = 0; t < N_TILE_CFG && e == hipSuccess; ++t) {
+            p->bp_tile = t;
+            p->persistent = pers;
+            e = launch_backproject(*p, filt, 1, img, 1.0f, 0.0f, nullptr, st);   // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            for (int r = 0; r < reps && e == hipSuccess; ++r)
+                e = launch_backproject(*p, filt, 1, img, 1.0f, 0.0f, nullptr, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms / reps < best) {
+                best = ms / reps;
+                bt = t;
+                bp = pers;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) {
+        p->bp_tile = keep_tile;
+        p->persistent = keep_pers;
+        return hip_fail(e, "autotune");
+    }
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        p->bp_tile = bt;
+        p->persistent = bp;
+        for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+        p->graphs.clear();
+    }
+    if (best_ms) *best_ms = best;
+    return PYHST_OK;
+}

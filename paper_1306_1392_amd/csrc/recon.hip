@@ -162,6 +162,7 @@ extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hip
     if (cp && !(op_norm > 0.0)) {
         int rc = estimate_opnorm(p, *a, L, st, &op_norm);
         if (rc) return rc;
+        a->op_norm = op_norm;   // report the estimate to the caller
     }
 
     // graphs are captured on the caller's stream; the legacy null stream cannot be captured

@@ -135,3 +135,37 @@ def perlin_texture(rng: np.random.Generator, n_pix: int, octaves: int = 3, base_
         tot += amp
         amp *= 0.5
     return out / tot
+
+
+def perlin_texture_torch(rng: np.random.Generator, n_pix: int, octaves: int = 3, base_freq: int = 8,
+                         device="cpu") -> torch.Tensor:
+    """Device version of perlin_texture (same lattice, fade and gradient set), float32 [n][n]."""
+    perm = torch.as_tensor(rng.permutation(256).astype(np.int64), device=device)
+    grads = torch.tensor([[1, 1], [-1, 1], [1, -1], [-1, -1], [1, 0], [-1, 0], [0, 1], [0, -1]],
+                         dtype=torch.float32, device=device)
+    out = torch.zeros(n_pix, n_pix, device=device)
+    amp, tot = 1.0, 0.0
+    for o in range(octaves):
+        freq = base_freq << o
+        xs = (torch.arange(n_pix, device=device, dtype=torch.float32) + 0.5) * freq / n_pix
+        xi = torch.floor(xs).to(torch.int64)
+        xf = xs - xi
+        X0, Y0 = xi[None, :].expand(n_pix, n_pix), xi[:, None].expand(n_pix, n_pix)
+        FX, FY = xf[None, :].expand(n_pix, n_pix), xf[:, None].expand(n_pix, n_pix)
+
+        def corner(ox, oy):
+            h = perm[(perm[(X0 + ox) & 255] + Y0 + oy) & 255] & 7
+            g = grads[h]
+            return g[..., 0] * (FX - ox) + g[..., 1] * (FY - oy)
+
+        def fade(t):
+            return t * t * t * (t * (t * 6.0 - 15.0) + 10.0)
+
+        u, v = fade(FX), fade(FY)
+        n00, n10, n01, n11 = corner(0, 0), corner(1, 0), corner(0, 1), corner(1, 1)
+        nx0 = n00 + u * (n10 - n00)
+        nx1 = n01 + u * (n11 - n01)
+        out += amp * (nx0 + v * (nx1 - nx0))
+        tot += amp
+        amp *= 0.5
+    return out / tot
