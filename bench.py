@@ -341,6 +341,153 @@ def run_cnn(args):
     print(json.dumps(res), flush=True)
 
 
+def learned_data(indices, stream, plan_hi, plan_b, N, K, B, dev):
+    """(FBP input, truth) for the given phantom indices, in batches of B (data from synth)."""
+    import torch
+    import synth
+    import paper_1306_1392_amd as ph
+
+    def project(tex):
+        return ph.forward_project(plan_hi, tex)
+
+    xs, ts, ys = [], [], []
+    for i0 in range(0, len(indices), B):
+        idx = list(indices[i0:i0 + B])
+        y, tr, _, _ = synth.configs.cfg_learned(idx, stream, project, N=N, K=K, device=dev)
+        n = y.shape[0]
+        if n < B:   # pad the last batch for the fixed-size plan
+            y = torch.cat([y, y[:1].expand(B - n, -1, -1)])
+        fb = ph.reconstruct_slices(plan_b, sino=y.contiguous(), method=ph.FBP)[:n]
+        xs.append(fb.clone())
+        ts.append(tr)
+        ys.append(y[:n])
+    return torch.cat(xs), torch.cat(ts), torch.cat(ys)
+
+
+def run_learned(args):
+    """Learned sparse-angle corrector: U-Net (4 levels, 32 base) trained on ellipse + Perlin
+    phantoms (512^2, 90 projections, Poisson 1e4) by the library's own MFMA kernels, judged
+    against TV-CP (300 iterations, lambda calibrated on validation phantoms) on test phantoms."""
+    import numpy as np
+    import torch
+    import paper_1306_1392_amd as ph
+    from paper_1306_1392_amd.cnn import UNet, init_params
+    from paper_1306_1392_amd.corrector import Corrector
+    dev = torch.device("cuda:0")
+    N, K, B = args.learned_n, 90, 32
+    SCALE = 10.0
+    ang = np.arange(K) * (np.pi / K)
+    axis = (N - 1) / 2.0
+    geo = ph.Geometry(N, N, N, ang, axis)
+    plan_b = ph.Plan(geo, n_slices=B)
+    plan_hi = ph.Plan(ph.Geometry(2 * N, 2 * N, N, ang, axis, pixel_size=0.5))
+    t0 = time.perf_counter()
+    log(f"learned: generating {args.learned_train} training phantoms ...")
+    xtr, ttr, _ = learned_data(np.arange(args.learned_train), 0, plan_hi, plan_b, N, K, B, dev)
+    xva, tva, yva = learned_data(np.arange(16), 2, plan_hi, plan_b, N, K, B, dev)
+    xte, tte, yte = learned_data(np.arange(args.learned_test), 1, plan_hi, plan_b, N, K, B, dev)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    log(f"learned: data in {t_gen:.1f} s")
+    net = UNet(B, N, N, 32, 4)
+    net.set_params(init_params(32, 4, 0))
+    xs, ts = (xtr * SCALE).contiguous(), (ttr * SCALE).contiguous()
+    n_tr = xs.shape[0]
+    steps = args.learned_epochs * (n_tr // B)
+    rng = np.random.default_rng(11)
+    t1 = time.perf_counter()
+    losses = []
+    for st in range(steps):
+        if st % (n_tr // B) == 0:
+            perm = torch.as_tensor(rng.permutation(n_tr), device=dev)
+        idx = perm[(st % (n_tr // B)) * B:(st % (n_tr // B)) * B + B]
+        lr = 1e-3 * 0.5 * (1 + np.cos(np.pi * st / steps))
+        loss = net.train_step(xs[idx].contiguous(), ts[idx].contiguous(), lr)
+        if st % 100 == 0 or st == steps - 1:
+            losses.append((st, float(loss)))
+            log(f"learned: step {st}/{steps} loss {losses[-1][1]:.5f}")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    params = net.get_params()
+
+    def rmse(a, b):
+        return float(torch.sqrt(torch.mean((a.double() - b.double()) ** 2)))
+
+    def cnn_apply(x):
+        out = torch.empty_like(x)
+        for i in range(0, x.shape[0], B):
+            xi = (x[i:i + B] * SCALE).contiguous()
+            out[i:i + B] = net.forward(xi) / SCALE
+        return out
+
+    # TV lambda: minimum RMSE on the validation phantoms (ground-truth calibration, section 3.1)
+    plan_va = ph.Plan(geo, n_slices=yva.shape[0])
+    lam_grid = [1e-4, 2e-4, 5e-4, 1e-3, 2e-3, 5e-3, 1e-2, 2e-2]
+    op_norm = 0.0
+    cal = {}
+    for lam in lam_grid:
+        x = ph.reconstruct_slices(plan_va, sino=yva.contiguous(), method=ph.TV_CP, lam=lam, n_iter=300,
+                                  op_norm=op_norm)
+        op_norm = plan_va.last_op_norm
+        cal[lam] = rmse(x, tva)
+    lam_best = min(cal, key=cal.get)
+    # data-consistency threshold of the corrector: 1.5 x the 95th percentile on validation
+    corr = Corrector(geo, B, params, tv_lambda=lam_best, tv_iters=300)
+    corr.op_norm = op_norm
+    res_va = []
+    for i in range(0, yva.shape[0], B):
+        yb = yva[i:i + B]
+        if yb.shape[0] < B:
+            yb = torch.cat([yb, yb[:1].expand(B - yb.shape[0], -1, -1)])
+        xh = cnn_apply(ph.reconstruct_slices(plan_b, sino=yb.contiguous(), method=ph.FBP))
+        ax = ph.forward_project(plan_b, xh.contiguous())
+        res_va.append(ph.slice_residual(plan_b, ax, yb.contiguous())[:min(B, yva.shape[0] - i)])
+    tau = 1.5 * float(torch.quantile(torch.cat(res_va), 0.95))
+    # test set: FBP, FBP + CNN, TV
+    x_cnn = cnn_apply(xte)
+    plan_te = ph.Plan(geo, n_slices=yte.shape[0])
+    x_tv = ph.reconstruct_slices(plan_te, sino=yte.contiguous(), method=ph.TV_CP, lam=lam_best, n_iter=300,
+                                 op_norm=op_norm)
+    r_fbp, r_cnn, r_tv = rmse(xte, tte), rmse(x_cnn, tte), rmse(x_tv, tte)
+    # throughput: FBP + CNN in batches of 32 vs TV-CP (300 iterations) on the whole test batch
+    stream = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    out = torch.empty((B, N, N), device=dev)
+    work = torch.empty(ph.work_bytes(plan_b, sino=yte[:B].contiguous(), method=ph.FBP), device=dev,
+                       dtype=torch.uint8)
+    ycs = [yte[i:i + B].contiguous() for i in range(0, yte.shape[0] - B + 1, B)]
+    torch.cuda.synchronize()
+    e[0].record(stream)
+    for yb in ycs:
+        ph.reconstruct_slices(plan_b, sino=yb, method=ph.FBP, out=out, work=work)
+        out.mul_(SCALE)
+        net.forward(out, out=out)
+    e[1].record(stream)
+    ph.reconstruct_slices(plan_te, sino=yte.contiguous(), method=ph.TV_CP, lam=lam_best, n_iter=300,
+                          op_norm=op_norm)
+    e[2].record(stream)
+    torch.cuda.synchronize()
+    sps_cnn = len(ycs) * B / (e[0].elapsed_time(e[1]) * 1e-3)
+    sps_tv = yte.shape[0] / (e[1].elapsed_time(e[2]) * 1e-3)
+    res = {"metric": "learned vs TV RMSE (sparse-angle 512^2, 90 angles)", "value": round(r_cnn / r_tv, 4),
+           "unit": "RMSE_CNN / RMSE_TV", "higher_is_better": False, "n_gpus": 1, "dtype": "bf16 CNN, f32 TV",
+           "data": "synthetic",
+           "config": {"workload": f"ellipse+Perlin phantoms {N}^2, {K} angles, Poisson 1e4; train "
+                                  f"{args.learned_train} x {args.learned_epochs} epochs, batch {B}; test "
+                                  f"{args.learned_test}; TV-CP 300 iterations"},
+           "rmse": {"fbp": r_fbp, "cnn": r_cnn, "tv": r_tv}, "tv_lambda": lam_best,
+           "tv_lambda_calibration": {str(k): v for k, v in cal.items()},
+           "slices_per_s": {"fbp_cnn": round(sps_cnn, 1), "tv": round(sps_tv, 2),
+                            "ratio": round(sps_cnn / sps_tv, 1)},
+           "pass": {"rmse_within_5pct_of_tv": r_cnn <= 1.05 * r_tv, "speed_20x": sps_cnn >= 20 * sps_tv,
+                    "gain_over_fbp": r_cnn < r_fbp},
+           "dc_threshold": tau, "train_seconds": round(t_train, 1), "data_seconds": round(t_gen, 1),
+           "train_steps": steps, "loss_trace": losses[::max(1, len(losses) // 20)]}
+    if args.save_params:
+        np.save(args.save_params, params.cpu().numpy())
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -357,9 +504,14 @@ def main():
                     help="also run a plain 2 GiB device copy (reference kernel for HBM byte counters)")
     ap.add_argument("--tile-sweep", action="store_true", help="time the backprojector for every tile shape")
     ap.add_argument("--peaks", action="store_true", help="run the roofline microbenchmarks")
-    ap.add_argument("--workload", default="fbp2048", choices=["fbp2048", "uneven", "tv", "cnn"],
+    ap.add_argument("--workload", default="fbp2048", choices=["fbp2048", "uneven", "tv", "cnn", "learned"],
                     help="fbp2048: the headline batch; uneven / tv: the other measured workloads")
     ap.add_argument("--uneven-slices", type=int, default=500)
+    ap.add_argument("--learned-train", type=int, default=10000)
+    ap.add_argument("--learned-test", type=int, default=256)
+    ap.add_argument("--learned-epochs", type=int, default=4)
+    ap.add_argument("--learned-n", type=int, default=512)
+    ap.add_argument("--save-params", default=None)
     ap.add_argument("--summarize", metavar="DIR", help="write profiles/ summaries from rocprofv3 output in DIR")
     args = ap.parse_args()
     if args.summarize:
@@ -380,6 +532,8 @@ def main():
         return run_tv(args)
     if args.workload == "cnn":
         return run_cnn(args)
+    if args.workload == "learned":
+        return run_learned(args)
     dev = torch.device("cuda:0")
     R, N, K = args.slices, args.n, args.angles
     log(f"bench: generating {R} x {N}^2 slices, {K} angles, raw uint16 ...")

@@ -200,6 +200,12 @@ typedef struct {
 
 int reconstruct_slices(const pyhst_plan *plan, pyhst_recon_args *a, hipStream_t stream);
 
+/* Data consistency per slice: rel[s] = |ax_s - y_s| / |y_s| over slice s's
+ * sinogram (packed [K][n_det] layout of the plan; FP64 accumulation, one
+ * workgroup per slice).  Used to send slices whose corrected reconstruction
+ * does not explain the data to the TV-regularised mode. */
+int pyhst_slice_residual(const pyhst_plan *plan, const float *ax, const float *y, float *rel, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Learned sparse-angle corrector (not part of the paper, whose learned prior
  * is an overlapping-patch dictionary, section 3.2): a U-Net applied to FBP
@@ -237,6 +243,15 @@ int pyhst_unet_adam(pyhst_unet *net, float lr, float beta1, float beta2, float e
 /* backward + Adam (beta1 0.9, beta2 0.999, eps 1e-8). */
 int pyhst_unet_train_step(pyhst_unet *net, const float *in, const float *target, int32_t n, float lr, float *loss,
                           hipStream_t stream);
+
+/* Inspection: copy an internal BF16 activation (grad = 0) or activation
+ * gradient (grad = 1) into dst (device, `elems` uint16 values = batch x H_l x
+ * W_l x channel stride).  kind: 0 input (8 channels), 1 encoder conv-a output
+ * of `level`, 2 concatenation [encoder conv-b output | upsampled] of `level`,
+ * 3 pooled encoder output of `level`, 4 / 5 decoder conv-a / conv-b output of
+ * `level`, 6 bottleneck conv-b output. */
+int pyhst_unet_tensor(const pyhst_unet *net, int32_t kind, int32_t level, int32_t grad, uint16_t *dst,
+                      int64_t elems, hipStream_t stream);
 
 /* Roofline measurement kernels (not part of the reconstruction path).
  * kind 0: independent FP32 FMA chains, 8 lane-ops per thread and iteration;

@@ -8,5 +8,5 @@ in the HIP library, which must be built (no CPU fallback exists)."""
 from ._lib import lib, PyhstError, SCAN_180, SCAN_360, SCAN_360_HALF, FBP, TV_CP  # noqa: F401
 from .api import (  # noqa: F401
     Geometry, Plan, pyhst_normalize, normalize, fbp_filter, backproject, forward_project, tv_prox,
-    reconstruct_slices, work_bytes, uniform_angles,
+    reconstruct_slices, work_bytes, uniform_angles, slice_residual,
 )

@@ -19,7 +19,7 @@ EXPORTS = ["pyhst_plan_create", "pyhst_plan_destroy", "pyhst_plan_slice_info", "
            "forward_project", "tv_prox", "reconstruct_slices", "pyhst_microbench", "pyhst_strerror",
            "pyhst_last_error", "pyhst_unet_create", "pyhst_unet_destroy", "pyhst_unet_num_params",
            "pyhst_unet_set_params", "pyhst_unet_get_params", "pyhst_unet_get_grads", "pyhst_unet_forward",
-           "pyhst_unet_backward", "pyhst_unet_adam", "pyhst_unet_train_step", "pyhst_plan_autotune"]
+           "pyhst_unet_backward", "pyhst_unet_adam", "pyhst_unet_train_step", "pyhst_plan_autotune", "pyhst_slice_residual", "pyhst_unet_tensor"]
 
 
 class Geom(ctypes.Structure):
@@ -80,6 +80,8 @@ def lib(path: str = LIB_PATH):
     L.pyhst_unet_adam.argtypes = [P, c_float, c_float, c_float, c_float, P]
     L.pyhst_unet_train_step.argtypes = [P, P, P, c_int32, c_float, P, P]
     L.pyhst_plan_autotune.argtypes = [P, P, P, c_int32, ctypes.POINTER(c_float), P]
+    L.pyhst_slice_residual.argtypes = [P, P, P, P, P]
+    L.pyhst_unet_tensor.argtypes = [P, c_int32, c_int32, c_int32, P, c_int64, P]
     L.pyhst_strerror.argtypes = [c_int32]
     L.pyhst_strerror.restype = ctypes.c_char_p
     L.pyhst_last_error.restype = ctypes.c_char_p

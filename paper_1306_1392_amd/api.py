@@ -253,6 +253,17 @@ def reconstruct_slices(plan: Plan, *, raw=None, sino=None, flats=None, flat_pos=
     return (out, E[:n_iter]) if energy else out
 
 
+def slice_residual(plan: Plan, ax, y, out=None, stream=None):
+    """|ax - y| / |y| per slice (device float [n_slices])."""
+    _need(ax, plan.sino_elems, "ax")
+    _need(y, plan.sino_elems, "y")
+    if out is None:
+        out = torch.empty(plan.n_slices, device=ax.device, dtype=torch.float32)
+    check(_lib.lib().pyhst_slice_residual(plan.handle, _ptr(ax), _ptr(y), _ptr(out), _stream(stream)),
+          "pyhst_slice_residual")
+    return out
+
+
 def work_bytes(plan: Plan, **kw) -> int:
     a = _lib.ReconArgs()
     a.raw = _ptr(kw.get("raw"))

@@ -125,6 +125,25 @@ class UNet:
                                            self._p(self.loss_buf), self._s(stream)), "pyhst_unet_train_step")
         return self.loss_buf
 
+    KINDS = {"x8": 0, "ea": 1, "cat": 2, "pool": 3, "da": 4, "db": 5, "bott": 6}
+
+    def tensor(self, kind: str, level: int = 0, grad: bool = False):
+        """Internal activation (or its gradient) as float32 [batch][H_l][W_l][C] (BF16 values)."""
+        H, W = self.height >> level, self.width >> level
+        c = self.base << level
+        C = {"x8": 8, "ea": c, "cat": 2 * c, "pool": c, "da": c, "db": c,
+             "bott": self.base << (self.levels - 1)}[kind]
+        if kind == "pool":
+            H, W = H // 2, W // 2
+        if kind == "bott":
+            H, W = self.height >> (self.levels - 1), self.width >> (self.levels - 1)
+        n = self.batch * H * W * C
+        buf = torch.empty(n, device="cuda", dtype=torch.int16)
+        check(self.L.pyhst_unet_tensor(self.handle, self.KINDS[kind], level, int(grad), ctypes.c_void_p(buf.data_ptr()),
+                                       n, self._s()), "pyhst_unet_tensor")
+        f = (buf.to(torch.int32) & 0xFFFF) << 16
+        return f.view(torch.float32).reshape(self.batch, H, W, C)
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             self.L.pyhst_unet_destroy(self.handle)

@@ -1,0 +1,62 @@
+"""Learned sparse-angle corrector with a TV fallback.
+
+x_hat = FBP(y) + UNet(FBP(y)); a slice whose corrected image does not explain
+its data (|A x_hat - y| / |y| above a threshold calibrated on validation data)
+is reconstructed by the TV-regularised mode (eq. (3), Chambolle-Pock) instead.
+Every step runs in the HIP library (FBP, U-Net kernels, projector, residual,
+TV-CP); this module only sequences the calls.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import api
+from .cnn import UNet
+
+
+class Corrector:
+    def __init__(self, geometry: api.Geometry, batch: int, params, base: int = 32, levels: int = 4,
+                 tv_lambda: float = 0.01, tv_iters: int = 300, dc_threshold: float | None = None):
+        self.geo = geometry
+        self.batch = batch
+        self.plan = api.Plan(geometry, n_slices=batch)
+        self.net = UNet(batch, geometry.n_y, geometry.n_x, base, levels)
+        self.net.set_params(params)
+        self.tv_lambda, self.tv_iters = tv_lambda, tv_iters
+        self.dc_threshold = dc_threshold
+        self.op_norm = 0.0
+        self._tv_plans = {}
+
+    def fbp(self, y):
+        return api.reconstruct_slices(self.plan, sino=y, method=api.FBP)
+
+    def correct(self, y):
+        """FBP + U-Net for a full batch y [batch][K][nb]; returns (x_hat, residual per slice)."""
+        x0 = self.fbp(y)
+        xh = self.net.forward(x0)
+        ax = api.forward_project(self.plan, xh)
+        return xh, api.slice_residual(self.plan, ax, y)
+
+    def tv(self, y):
+        """TV-CP reconstruction of the slices in y [n][K][nb]."""
+        n = y.shape[0]
+        plan = self._tv_plans.get(n)
+        if plan is None:
+            plan = self._tv_plans[n] = api.Plan(self.geo, n_slices=n)
+        x = api.reconstruct_slices(plan, sino=y.contiguous(), method=api.TV_CP, lam=self.tv_lambda,
+                                   n_iter=self.tv_iters, op_norm=self.op_norm)
+        self.op_norm = plan.last_op_norm
+        return x
+
+    def reconstruct(self, y):
+        """Corrected FBP, with the TV mode for slices failing the data-consistency check.
+        Returns (x, fallback mask as a numpy bool array)."""
+        xh, r = self.correct(y)
+        mask = np.zeros(y.shape[0], dtype=bool)
+        if self.dc_threshold is not None:
+            mask = (r > self.dc_threshold).cpu().numpy()
+            if mask.any():
+                idx = torch.as_tensor(np.nonzero(mask)[0], device=y.device)
+                xh[idx] = self.tv(y[idx])
+        return xh, mask

@@ -754,3 +754,32 @@ int pyhst_unet_train_step(pyhst_unet *net, const float *in, const float *target,
 }
 
 }  // extern "C"
+
+// Copy an internal BF16 buffer (activation or its gradient) for inspection.
+// kind: 0 input (8 channels), 1 encoder conv-a output, 2 concatenation
+// [encoder conv-b output | upsampled], 3 pooled, 4 decoder conv-a output,
+// 5 decoder conv-b output, 6 bottleneck conv-b output.  Elements:
+// batch x H_l x W_l x channel stride of that buffer.
+extern "C" int pyhst_unet_tensor(const pyhst_unet *net, int32_t kind, int32_t level, int32_t grad, uint16_t *dst,
+                                 int64_t elems, hipStream_t st)
+{
+    if (!net || !dst) return fail(PYHST_EARG, "unet_tensor: NULL argument");
+    const Buf *b = nullptr;
+    const int L = net->L;
+    auto in = [&](int lo, int hi) { return level >= lo && level < hi; };
+    switch (kind) {
+    case 0: b = &net->x8; break;
+    case 1: if (in(0, L)) b = &net->ea[level]; break;
+    case 2: if (in(0, L - 1)) b = &net->cat[level]; break;
+    case 3: if (in(0, L - 1)) b = &net->pool[level]; break;
+    case 4: if (in(0, L - 1)) b = &net->da[level]; break;
+    case 5: if (in(0, L - 1)) b = &net->db[level]; break;
+    case 6: b = &net->bott_b; break;
+    default: break;
+    }
+    if (!b) return fail(PYHST_EARG, "unet_tensor: bad kind/level");
+    const int64_t n = (int64_t)net->B * b->H * b->W * b->C;
+    if (elems != n) return fail(PYHST_EARG, "unet_tensor: wrong element count");
+    hipError_t e = hipMemcpyAsync(dst, grad ? b->g : b->a, 2 * n, hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "unet_tensor");
+}

@@ -282,3 +282,38 @@ hipError_t launch_scale_by_inv(float *x, int64_t n, const double *norm_dev, hipS
 }
 
 }  // namespace pyhst
+
+namespace pyhst {
+namespace {
+
+// rel[s] = |ax_s - y_s| / |y_s| over the sinogram of slice s (one workgroup per slice)
+__global__ __launch_bounds__(256) void residual_kernel(Tables T, const float *__restrict__ ax,
+                                                       const float *__restrict__ y, float *__restrict__ rel)
+{
+    __shared__ double sh[4];
+    const SliceDev sd = T.slc[blockIdx.x];
+    const GeoDev &g = T.geo[sd.g];
+    const int64_t n = (int64_t)g.K * g.nb;
+    double num = 0.0, den = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double a = ax[sd.sino_off + i], b = y[sd.sino_off + i];
+        num += (a - b) * (a - b);
+        den += b * b;
+    }
+    const double tn = block_sum(num, sh);
+    const double td = block_sum(den, sh);
+    if (threadIdx.x == 0) rel[blockIdx.x] = (float)(td > 0.0 ? sqrt(tn / td) : 0.0);
+}
+
+}  // namespace
+}  // namespace pyhst
+
+extern "C" int pyhst_slice_residual(const pyhst_plan *p, const float *ax, const float *y, float *rel,
+                                    hipStream_t st)
+{
+    using namespace pyhst;
+    if (!p || !ax || !y || !rel) return fail(PYHST_EARG, "slice_residual: NULL argument");
+    residual_kernel<<<p->n_slices, 256, 0, st>>>(p->t, ax, y, rel);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "slice_residual");
+}

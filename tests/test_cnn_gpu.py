@@ -12,7 +12,8 @@ from oracle.cnn import UNetOracle, layers
 from paper_1306_1392_amd.cnn import UNet, init_params
 
 pytestmark = pytest.mark.gpu
-TOL = 2e-3
+TOL = 2e-3        # one layer: FP32 vs FP64 accumulation flips isolated BF16 roundings
+TOL_NET = 1e-2    # whole network: those flips compound through up to 18 BF16 layers
 
 
 def rel(a, b):
@@ -47,7 +48,7 @@ def test_forward_and_gradients_match_oracle(dev, base, levels, B, H):
     out = net.forward(xt).cpu().numpy()
     orc = UNetOracle(base, levels, "bf16")
     ref = orc.forward(p, x)
-    assert rel(out - x, ref - x) <= TOL, rel(out - x, ref - x)
+    assert rel(out - x, ref - x) <= TOL_NET, rel(out - x, ref - x)
     loss = net.backward(xt, tt)
     g = net.get_grads().cpu().numpy()
     lref, gref = orc.loss_and_grad(p, x, t)
@@ -60,8 +61,8 @@ def test_forward_and_gradients_match_oracle(dev, base, levels, B, H):
         if d["name"] == "enc0a":     # only input channel 0 is live
             gw = g[w].reshape(d["cout"], 9, 8)
             assert np.all(gw[:, :, 1:] == 0)
-        assert rel(g[w], gref[w]) <= TOL, (d["name"], "w", rel(g[w], gref[w]))
-        assert rel(g[b], gref[b]) <= TOL, (d["name"], "b", rel(g[b], gref[b]))
+        assert rel(g[w], gref[w]) <= TOL_NET, (d["name"], "w", rel(g[w], gref[w]))
+        assert rel(g[b], gref[b]) <= TOL_NET, (d["name"], "b", rel(g[b], gref[b]))
 
 
 def test_adam_step_matches_oracle(dev):
@@ -93,3 +94,106 @@ def test_training_overfits_a_fixed_batch(dev):
     xt, tt = torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev)
     losses = [float(net.train_step(xt, tt, lr=2e-3)) for _ in range(150)]
     assert losses[-1] < 0.2 * losses[0], (losses[0], losses[-1])
+
+
+def test_every_layer_teacher_forced(dev):
+    """Each layer of the GPU U-Net against the oracle's layer fed with the GPU's own BF16
+    inputs (no compounding of rounding differences across layers): forward activations,
+    activation gradients and weight / bias gradients of the 4-level, 32-base network."""
+    from oracle.cnn import to_bf16
+    base, levels, B, H = 32, 4, 2, 64
+    L = levels
+    p = params_with_bias(base, levels, 3).astype(np.float64)
+    rng = np.random.default_rng(8)
+    x = rng.random((B, H, H)).astype(np.float32)
+    t = (x + 0.1 * rng.standard_normal((B, H, H))).astype(np.float32)
+    net = UNet(B, H, H, base, levels)
+    net.set_params(p.astype(np.float32))
+    xt, tt = torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev)
+    out = net.forward(xt).cpu().numpy().astype(np.float64)
+    net.backward(xt, tt)
+    g = net.get_grads().cpu().numpy().astype(np.float64)
+    orc = UNetOracle(base, levels, "bf16")
+    lay, _ = layers(base, levels)
+
+    def T(kind, l=0, grad=False):
+        return net.tensor(kind, l, grad).double().cpu().numpy()
+
+    relu = lambda a: np.maximum(a, 0.0)
+    checks = []
+
+    def cmp(name, got, ref, tol=TOL):
+        r = rel(got, ref)
+        checks.append((name, r))
+        assert r <= tol, (name, r)
+
+    def cmp_grads(name, dW, db):
+        d = lay[name]
+        nb = d["cout"] if d["kind"] != "head" else 1
+        cmp(name + ".dW", g[d["w"]:d["b"]], dW.ravel())
+        cmp(name + ".db", g[d["b"]:d["b"] + nb], db)
+
+    # forward
+    for l in range(L):
+        c = base << l
+        xin = T("x8") if l == 0 else T("pool", l - 1)
+        Wa, ba = orc.weights(p, f"enc{l}a")
+        cmp(f"enc{l}a", T("ea", l), to_bf16(relu(orc.conv(xin, Wa, ba))))
+        Wb, bb = orc.weights(p, f"enc{l}b")
+        eb = T("cat", l)[..., :c] if l < L - 1 else T("bott")
+        cmp(f"enc{l}b", eb, to_bf16(relu(orc.conv(T("ea", l), Wb, bb))))
+        if l < L - 1:
+            assert np.array_equal(T("pool", l), orc.pool(eb)[0])
+    for l in range(L - 2, -1, -1):
+        c = base << l
+        below = T("bott") if l == L - 2 else T("db", l + 1)
+        U, bu = orc.weights(p, f"up{l}")
+        cmp(f"up{l}", T("cat", l)[..., c:], to_bf16(relu(orc.up(below, U, bu))))
+        Wa, ba = orc.weights(p, f"dec{l}a")
+        cmp(f"dec{l}a", T("da", l), to_bf16(relu(orc.conv(T("cat", l), Wa, ba))))
+        Wb, bb = orc.weights(p, f"dec{l}b")
+        cmp(f"dec{l}b", T("db", l), to_bf16(relu(orc.conv(T("da", l), Wb, bb))))
+    wh, bh = orc.weights(p, "head")
+    cmp("head", out - x, bh[0] + T("db", 0) @ wh, tol=1e-5)
+
+    # backward
+    n = out.size
+    dout = (2.0 * (out - t) / n)
+    d0 = T("db", 0)
+    cmp("head.dD", T("db", 0, True), to_bf16(np.where(d0 > 0, dout[..., None] * wh, 0.0)))
+    cmp_grads("head", (d0 * dout[..., None]).reshape(-1, base).sum(0), np.array([dout.sum()]))
+
+    def conv_layer(name, xin, dz, dx_gpu=None):
+        W, _ = orc.weights(p, name)
+        dW, db, dx = orc.conv_bwd(xin, W, dz)
+        cmp_grads(name, dW, db)
+        if dx_gpu is not None:
+            cmp(name + ".dX", dx_gpu, to_bf16(np.where(xin > 0, dx, 0.0)))
+
+    for l in range(L - 1):
+        c = base << l
+        conv_layer(f"dec{l}b", T("da", l), T("db", l, True), T("da", l, True))
+        dcat = T("cat", l, True)
+        W, _ = orc.weights(p, f"dec{l}a")
+        dW, db, dx = orc.conv_bwd(T("cat", l), W, T("da", l, True))
+        cmp_grads(f"dec{l}a", dW, db)
+        ref = to_bf16(np.where(T("cat", l) > 0, dx, 0.0))
+        cmp(f"dec{l}a.dX(up half)", dcat[..., c:], ref[..., c:])
+        below = T("bott") if l == L - 2 else T("db", l + 1)
+        dbelow = T("bott", 0, True) if l == L - 2 else T("db", l + 1, True)
+        U, _ = orc.weights(p, f"up{l}")
+        dU, dbu, dxu = orc.up_bwd(below, U, dcat[..., c:])
+        cmp_grads(f"up{l}", dU, dbu)
+        cmp(f"up{l}.dX", dbelow, to_bf16(np.where(below > 0, dxu, 0.0)))
+        if l == 0:
+            # skip half of level 0 plus the pooled gradient routed back by pool 0
+            add = orc.unpool_add(ref[..., :c], T("pool", 0, True), orc.pool(T("cat", 0)[..., :c])[1],
+                                 T("pool", 0))
+            cmp("cat0.dX(skip + pool)", dcat[..., :c], np.where(add != 0, to_bf16(ref[..., :c] + add), ref[..., :c]))
+    for l in range(L - 1, -1, -1):
+        c = base << l
+        dz = T("bott", 0, True) if l == L - 1 else T("cat", l, True)[..., :c]
+        conv_layer(f"enc{l}b", T("ea", l), dz, T("ea", l, True))
+        xin = T("x8") if l == 0 else T("pool", l - 1)
+        conv_layer(f"enc{l}a", xin, T("ea", l, True), None if l == 0 else T("pool", l - 1, True))
+    assert len(checks) > 40
