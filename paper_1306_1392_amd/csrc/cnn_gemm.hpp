@@ -37,6 +37,25 @@ __device__ __host__ inline float bf2f(bf16_t b)
 
 constexpr int TM = 128, TK = 32, LDK = TK + 8;   // LDS row stride 80 B keeps 16 B alignment
 
+// floor(n / d) for 0 <= n < 2^31 by multiply and shift: m = ceil(2^(32+l) / d), l = ceil(log2 d)
+// (Granlund & Montgomery); exact in this range because n e / (d 2^(32+l)) < 1/d for e = m d - 2^(32+l) < d.
+struct FastDiv {
+    uint64_t m;
+    uint32_t l, d;
+};
+inline FastDiv make_fastdiv(uint32_t d)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    const unsigned __int128 num = (unsigned __int128)1 << (32 + l);
+    const uint64_t m = (uint64_t)((num + d - 1) / d);
+    return FastDiv{m, l, d};
+}
+__device__ inline uint32_t fdiv(uint32_t n, const FastDiv &f)
+{
+    return (uint32_t)(((unsigned __int128)n * f.m) >> (32 + f.l));
+}
+
 template <int TN>
 struct WaveGrid {
     static constexpr int WM = TN >= 128 ? 2 : 4;
