@@ -289,7 +289,7 @@ Act act(const Buf &b, int n, int co = 0, bool grad = false) { return Act{grad ? 
 hipError_t conv_fwd(const pyhst_unet &net, const Conv &L, Act in, bf16_t *out, int ocs, int oco, hipStream_t st)
 {
     const int M = in.B * in.H * in.W;
-    Im2colA A{in, L.cin};
+    Im2colA A = im2col_a(in, L.cin);
     WeightB Bw{L.wf, 9 * L.cin};
     StoreAct E{out, ocs, oco, net.params + L.b, 1};
     switch (tn_for(L.cout)) {
@@ -341,7 +341,7 @@ hipError_t conv_bwd(const pyhst_unet &net, const Conv &L, Act x, Act dz, bf16_t 
     {
         const int M = 9 * L.cin, N = L.cout, tn = tn_for(N);
         const int s = splits_for(M, N, tn, npix, net.part_floats);
-        Im2colT A{x, L.cin};
+        Im2colT A = im2col_t(x, L.cin);
         PlainT Bz{dz};
         StorePartial E{net.part, M, N};
         int ks = (npix + s - 1) / s;
@@ -358,7 +358,7 @@ hipError_t conv_bwd(const pyhst_unet &net, const Conv &L, Act x, Act dz, bf16_t 
     if (dx) {
         // dX[pix][ci] = sum_{tap', co} dZ[pix + off(tap')][co] Wb[ci][tap'][co], masked by X > 0
         const int M = npix, N = L.cin;
-        Im2colA A{dz, L.cout};
+        Im2colA A = im2col_a(dz, L.cout);
         WeightB Bw{L.wb, 9 * L.cout};
         StoreMasked E{dx, dxcs, dxco, x.p, x.cs, x.co};
         switch (tn_for(N)) {
@@ -379,7 +379,7 @@ hipError_t up_bwd(const pyhst_unet &net, const Up &L, Act x, Act dy, bf16_t *dx,
         const int M = L.cin, N = 4 * L.cout, tn = tn_for(N);
         const int s = splits_for(M, N, tn, npix, net.part_floats);
         PlainT A{x};
-        UpGatherT Bz{dy, L.cout};
+        UpGatherT Bz = upgather_t(dy, L.cout);
         StorePartial E{net.part, M, N};
         int ks = (npix + s - 1) / s;
         ks = (ks + TK - 1) / TK * TK;
@@ -393,7 +393,7 @@ hipError_t up_bwd(const pyhst_unet &net, const Up &L, Act x, Act dy, bf16_t *dx,
     }
     if ((e = chan_sum(net, dy, L.cout, nullptr, net.grads + L.b, st)) != hipSuccess) return e;
     const int M = npix, N = L.cin;
-    UpGatherA A{dy, L.cout};
+    UpGatherA A = upgather_a(dy, L.cout);
     WeightB Bw{L.ub, 4 * L.cout};
     StoreMasked E{dx, dxcs, 0, x.p, x.cs, x.co};
     switch (tn_for(N)) {
@@ -526,8 +526,10 @@ int pyhst_unet_create(int32_t batch, int32_t height, int32_t width, int32_t base
 {
     if (!out) return fail(PYHST_EARG, "unet_create: out is NULL");
     *out = nullptr;
-    if (batch <= 0 || levels < 2 || levels > 6 || base <= 0 || base % 8 != 0)
-        return fail(PYHST_EARG, "unet_create: need batch > 0, 2 <= levels <= 6, base a multiple of 8");
+    if (batch <= 0 || levels < 2 || levels > 6 || base < 8 || (base & (base - 1)) != 0)
+        return fail(PYHST_EARG, "unet_create: need batch > 0, 2 <= levels <= 6, base a power of two >= 8");
+    if ((int64_t)batch * height * width >= (1ll << 31))
+        return fail(PYHST_EARG, "unet_create: batch x height x width must stay below 2^31");
     const int div = 1 << (levels - 1);
     if (height <= 0 || width <= 0 || height % div || width % div)
         return fail(PYHST_EARG, "unet_create: height and width must be divisible by 2^(levels-1)");

@@ -53,7 +53,7 @@ inline FastDiv make_fastdiv(uint32_t d)
 }
 __device__ inline uint32_t fdiv(uint32_t n, const FastDiv &f)
 {
-    return (uint32_t)(((unsigned __int128)n * f.m) >> (32 + f.l));
+    return (uint32_t)(((uint64_t)n * f.m) >> (32 + f.l));   // n < 2^31, m < 2^33: no overflow
 }
 
 template <int TN>
@@ -63,8 +63,11 @@ struct WaveGrid {
 };
 
 // ---------------------------------------------------------------- operand loaders
-// VK = true: load(row, k) returns the 8 elements [row][k..k+7] (vector along K).
-// VK = false: loadv(row8, k) returns [row8..row8+7][k] (vector along M or N).
+// Each loader has a per-thread context prepared once per output tile (prep) and a
+// load(ctx, k, kend) for every K tile.  VK = true: the context is a row m (or n)
+// and load returns [row][k..k+7] (vector along K).  VK = false: the context is a
+// group of 8 rows and load returns [row8..row8+7][k] (vector along M or N).
+// Channel counts are powers of two (shifts); pixel indices are decoded with FastDiv.
 struct Act {          // NHWC activation view: channel stride cs, channel offset co
     const bf16_t *p;
     int B, H, W, cs, co;
@@ -72,60 +75,109 @@ struct Act {          // NHWC activation view: channel stride cs, channel offset
 
 __device__ inline uint4 ld8(const bf16_t *p) { return *(const uint4 *)p; }
 __device__ inline uint4 zero8() { return make_uint4(0, 0, 0, 0); }
+__device__ inline int tap_row(int tap) { return (tap * 11) >> 5; }   // tap / 3 for tap in [0, 9)
+
+inline int ilog2(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
 
 // A[m = pixel][k = (tap, c)] = X[pixel + (ty-1, tx-1)][c], zero outside the image
 struct Im2colA {
     static constexpr bool VK = true;
     Act x;
-    int C;
-    __device__ uint4 load(int m, int k, int M, int kend) const
+    int lgC;
+    FastDiv fhw, fw;
+    struct Ctx {
+        int64_t base;
+        int y, xx;
+        bool ok;
+    };
+    __device__ Ctx prep(int m, int M) const
     {
-        if (m >= M || k >= kend) return zero8();
-        const int tap = k / C, c = k - tap * C;
-        const int hw = x.H * x.W;
-        const int b = m / hw, r = m - b * hw;
-        const int y = r / x.W + tap / 3 - 1, xx = r % x.W + tap % 3 - 1;
-        if ((unsigned)y >= (unsigned)x.H || (unsigned)xx >= (unsigned)x.W) return zero8();
-        return ld8(x.p + ((int64_t)(b * x.H + y) * x.W + xx) * x.cs + x.co + c);
+        Ctx c;
+        c.ok = m < M;
+        const uint32_t mm = c.ok ? (uint32_t)m : 0u;
+        const uint32_t b = fdiv(mm, fhw), r = mm - b * fhw.d;
+        const uint32_t y = fdiv(r, fw);
+        c.y = (int)y;
+        c.xx = (int)(r - y * fw.d);
+        c.base = (int64_t)mm * x.cs + x.co;
+        return c;
+    }
+    __device__ uint4 load(const Ctx &c, int k, int kend) const
+    {
+        if (!c.ok || k >= kend) return zero8();
+        const int tap = k >> lgC, ch = k & ((1 << lgC) - 1);
+        const int ty = tap_row(tap), tx = tap - 3 * ty;
+        if ((unsigned)(c.y + ty - 1) >= (unsigned)x.H || (unsigned)(c.xx + tx - 1) >= (unsigned)x.W) return zero8();
+        return ld8(x.p + c.base + ((int64_t)(ty - 1) * x.W + (tx - 1)) * x.cs + ch);
     }
 };
+inline Im2colA im2col_a(Act x, int C) { return Im2colA{x, ilog2(C), make_fastdiv(x.H * x.W), make_fastdiv(x.W)}; }
 
 // A[m = pixel][k] = X[pixel][k]
 struct PlainA {
     static constexpr bool VK = true;
     Act x;
-    __device__ uint4 load(int m, int k, int M, int kend) const
+    struct Ctx {
+        int64_t base;
+        bool ok;
+    };
+    __device__ Ctx prep(int m, int M) const { return Ctx{(int64_t)(m < M ? m : 0) * x.cs + x.co, m < M}; }
+    __device__ uint4 load(const Ctx &c, int k, int kend) const
     {
-        if (m >= M || k >= kend) return zero8();
-        return ld8(x.p + (int64_t)m * x.cs + x.co + k);
+        return (c.ok && k < kend) ? ld8(x.p + c.base + k) : zero8();
     }
 };
 
-// A[m = low-res pixel (b,y,x)][k = (d, co)] = dY[(b, 2y+dy, 2x+dx)][co]  (dY at 2H x 2W)
+// A[m = low-res pixel (b,y,x)][k = (d, co)] = dY[(b, 2y+dy, 2x+dx)][co]  (dY at 2h x 2w)
 struct UpGatherA {
     static constexpr bool VK = true;
     Act dy;     // high-resolution tensor
-    int Cout;
-    __device__ uint4 load(int m, int k, int M, int kend) const
+    int lgCout;
+    FastDiv fhw, fw;   // low-resolution h*w and w
+    struct Ctx {
+        int64_t base;
+        bool ok;
+    };
+    __device__ Ctx prep(int m, int M) const
     {
-        if (m >= M || k >= kend) return zero8();
-        const int d = k / Cout, co = k - d * Cout;
-        const int h = dy.H >> 1, w = dy.W >> 1;
-        const int b = m / (h * w), r = m - b * (h * w);
-        const int y = 2 * (r / w) + (d >> 1), xx = 2 * (r % w) + (d & 1);
-        return ld8(dy.p + ((int64_t)(b * dy.H + y) * dy.W + xx) * dy.cs + dy.co + co);
+        Ctx c;
+        c.ok = m < M;
+        const uint32_t mm = c.ok ? (uint32_t)m : 0u;
+        const uint32_t b = fdiv(mm, fhw), r = mm - b * fhw.d;
+        const uint32_t y = fdiv(r, fw), xx = r - y * fw.d;
+        c.base = ((int64_t)(b * dy.H + 2 * y) * dy.W + 2 * xx) * dy.cs + dy.co;
+        return c;
+    }
+    __device__ uint4 load(const Ctx &c, int k, int kend) const
+    {
+        if (!c.ok || k >= kend) return zero8();
+        const int d = k >> lgCout, co = k & ((1 << lgCout) - 1);
+        return ld8(dy.p + c.base + ((int64_t)(d >> 1) * dy.W + (d & 1)) * dy.cs + co);
     }
 };
+inline UpGatherA upgather_a(Act dy, int Cout)
+{
+    return UpGatherA{dy, ilog2(Cout), make_fastdiv((dy.H >> 1) * (dy.W >> 1)), make_fastdiv(dy.W >> 1)};
+}
 
 // B[k][n] = Wt[n][k] (weights stored n-major, k contiguous)
 struct WeightB {
     static constexpr bool VK = true;
     const bf16_t *w;
     int K;
-    __device__ uint4 load(int n, int k, int N, int kend) const
+    struct Ctx {
+        int64_t base;
+        bool ok;
+    };
+    __device__ Ctx prep(int n, int N) const { return Ctx{(int64_t)(n < N ? n : 0) * K, n < N}; }
+    __device__ uint4 load(const Ctx &c, int k, int kend) const
     {
-        if (n >= N || k >= kend) return zero8();
-        return ld8(w + (int64_t)n * K + k);
+        return (c.ok && k < kend) ? ld8(w + c.base + k) : zero8();
     }
 };
 
@@ -133,27 +185,47 @@ struct WeightB {
 struct Im2colT {
     static constexpr bool VK = false;
     Act x;
-    int C;
-    __device__ uint4 loadv(int m8, int k, int M, int kend) const
+    int lgC;
+    FastDiv fhw, fw;
+    struct Ctx {
+        int dy, dx, ch;
+        bool ok;
+    };
+    __device__ Ctx prep(int m8, int M) const
     {
-        if (m8 >= M || k >= kend) return zero8();
-        const int tap = m8 / C, c = m8 - tap * C;
-        const int hw = x.H * x.W;
-        const int b = k / hw, r = k - b * hw;
-        const int y = r / x.W + tap / 3 - 1, xx = r % x.W + tap % 3 - 1;
+        Ctx c;
+        c.ok = m8 < M;
+        const int mm = c.ok ? m8 : 0;
+        const int tap = mm >> lgC;
+        c.ch = mm & ((1 << lgC) - 1);
+        c.dy = tap_row(tap) - 1;
+        c.dx = tap - 3 * (c.dy + 1) - 1;
+        return c;
+    }
+    __device__ uint4 load(const Ctx &c, int k, int kend) const
+    {
+        if (!c.ok || k >= kend) return zero8();
+        const uint32_t b = fdiv((uint32_t)k, fhw), r = (uint32_t)k - b * fhw.d;
+        const uint32_t y0 = fdiv(r, fw);
+        const int y = (int)y0 + c.dy, xx = (int)(r - y0 * fw.d) + c.dx;
         if ((unsigned)y >= (unsigned)x.H || (unsigned)xx >= (unsigned)x.W) return zero8();
-        return ld8(x.p + ((int64_t)(b * x.H + y) * x.W + xx) * x.cs + x.co + c);
+        return ld8(x.p + ((int64_t)(b * x.H + y) * x.W + xx) * x.cs + x.co + c.ch);
     }
 };
+inline Im2colT im2col_t(Act x, int C) { return Im2colT{x, ilog2(C), make_fastdiv(x.H * x.W), make_fastdiv(x.W)}; }
 
 // [row8..+7 = channels][k = pixel] of a plain NHWC tensor
 struct PlainT {
     static constexpr bool VK = false;
     Act x;
-    __device__ uint4 loadv(int n8, int k, int N, int kend) const
+    struct Ctx {
+        int off;
+        bool ok;
+    };
+    __device__ Ctx prep(int n8, int N) const { return Ctx{x.co + (n8 < N ? n8 : 0), n8 < N}; }
+    __device__ uint4 load(const Ctx &c, int k, int kend) const
     {
-        if (n8 >= N || k >= kend) return zero8();
-        return ld8(x.p + (int64_t)k * x.cs + x.co + n8);
+        return (c.ok && k < kend) ? ld8(x.p + (int64_t)k * x.cs + c.off) : zero8();
     }
 };
 
@@ -161,48 +233,92 @@ struct PlainT {
 struct UpGatherT {
     static constexpr bool VK = false;
     Act dy;
-    int Cout;
-    __device__ uint4 loadv(int n8, int k, int N, int kend) const
+    int lgCout;
+    FastDiv fhw, fw;
+    struct Ctx {
+        int ddy, ddx, co;
+        bool ok;
+    };
+    __device__ Ctx prep(int n8, int N) const
     {
-        if (n8 >= N || k >= kend) return zero8();
-        const int d = n8 / Cout, co = n8 - d * Cout;
-        const int h = dy.H >> 1, w = dy.W >> 1;
-        const int b = k / (h * w), r = k - b * (h * w);
-        const int y = 2 * (r / w) + (d >> 1), xx = 2 * (r % w) + (d & 1);
-        return ld8(dy.p + ((int64_t)(b * dy.H + y) * dy.W + xx) * dy.cs + dy.co + co);
+        Ctx c;
+        c.ok = n8 < N;
+        const int nn = c.ok ? n8 : 0;
+        const int d = nn >> lgCout;
+        c.co = nn & ((1 << lgCout) - 1);
+        c.ddy = d >> 1;
+        c.ddx = d & 1;
+        return c;
+    }
+    __device__ uint4 load(const Ctx &c, int k, int kend) const
+    {
+        if (!c.ok || k >= kend) return zero8();
+        const uint32_t b = fdiv((uint32_t)k, fhw), r = (uint32_t)k - b * fhw.d;
+        const uint32_t y = fdiv(r, fw), xx = r - y * fw.d;
+        return ld8(dy.p + ((int64_t)(b * dy.H + 2 * y + c.ddy) * dy.W + 2 * xx + c.ddx) * dy.cs + dy.co + c.co);
+    }
+};
+inline UpGatherT upgather_t(Act dy, int Cout)
+{
+    return UpGatherT{dy, ilog2(Cout), make_fastdiv((dy.H >> 1) * (dy.W >> 1)), make_fastdiv(dy.W >> 1)};
+}
+
+// Register staging of one operand tile: SLOTS vectors of 8 BF16 per thread.
+template <class L, int ROWS>
+struct Stager {
+    static constexpr int NV = ROWS * TK / 8;
+    static constexpr int SLOTS = (NV + 255) / 256;
+    typename L::Ctx ctx[SLOTS];
+    uint4 v[SLOTS];
+    int row[SLOTS], kl[SLOTS];
+    __device__ void prep(const L &ld, int row0, int R)
+    {
+#pragma unroll
+        for (int j = 0; j < SLOTS; ++j) {
+            const int idx = threadIdx.x + 256 * j;
+            if constexpr (L::VK) {
+                row[j] = idx >> 2;
+                kl[j] = (idx & 3) * 8;
+            } else {
+                constexpr int R8 = ROWS / 8;
+                kl[j] = idx / R8;
+                row[j] = (idx - kl[j] * R8) * 8;
+            }
+            ctx[j] = ld.prep(row0 + row[j], idx < NV ? R : 0);
+        }
+    }
+    __device__ void load(const L &ld, int k0, int kend)
+    {
+#pragma unroll
+        for (int j = 0; j < SLOTS; ++j) v[j] = ld.load(ctx[j], k0 + kl[j], kend);
+    }
+    __device__ void store(bf16_t *s) const
+    {
+#pragma unroll
+        for (int j = 0; j < SLOTS; ++j) {
+            if (threadIdx.x + 256 * j >= NV) continue;
+            if constexpr (L::VK) {
+                *(uint4 *)&s[row[j] * LDK + kl[j]] = v[j];
+            } else {
+                const bf16_t *e = (const bf16_t *)&v[j];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) s[(row[j] + q) * LDK + kl[j]] = e[q];
+            }
+        }
     }
 };
 
-template <class L, int ROWS>
-__device__ inline void stage(const L &ld, bf16_t *s, int row0, int k0, int R, int kend)
-{
-    constexpr int NV = ROWS * TK / 8;
-    if constexpr (L::VK) {
-        for (int idx = threadIdx.x; idx < NV; idx += 256) {
-            const int r = idx >> 2, kq = (idx & 3) * 8;
-            *(uint4 *)&s[r * LDK + kq] = ld.load(row0 + r, k0 + kq, R, kend);
-        }
-    } else {
-        constexpr int R8 = ROWS / 8;
-        for (int idx = threadIdx.x; idx < NV; idx += 256) {
-            const int k = idx / R8, r8 = (idx - k * R8) * 8;
-            const uint4 v = ld.loadv(row0 + r8, k0 + k, R, kend);
-            const bf16_t *e = (const bf16_t *)&v;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) s[(r8 + j) * LDK + k] = e[j];
-        }
-    }
-}
-
 // One workgroup: a TM x TN tile of C over the K range [kz * k_split, (kz+1) * k_split).
+// The next K tile is fetched into registers while the current one is multiplied from
+// LDS; two LDS buffers, one barrier per K tile.
 template <class AL, class BL, class EP, int TN>
 __global__ __launch_bounds__(256) void gemm_kernel(AL A, BL B, EP E, int M, int N, int K, int k_split)
 {
     constexpr int WMW = WaveGrid<TN>::WM, WNW = WaveGrid<TN>::WN;
     constexpr int WTM = TM / WMW, WTN = TN / WNW;
     constexpr int BM = WTM / 32, BN = WTN / 32;
-    __shared__ __attribute__((aligned(16))) bf16_t sA[TM * LDK];
-    __shared__ __attribute__((aligned(16))) bf16_t sB[TN * LDK];
+    __shared__ __attribute__((aligned(16))) bf16_t sA[2][TM * LDK];
+    __shared__ __attribute__((aligned(16))) bf16_t sB[2][TN * LDK];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WNW, wn = wave % WNW;
     const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
@@ -216,26 +332,39 @@ __global__ __launch_bounds__(256) void gemm_kernel(AL A, BL B, EP E, int M, int 
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-    for (int k0 = kbeg; k0 < kend; k0 += TK) {
-        stage<AL, TM>(A, sA, m0, k0, M, kend);
-        stage<BL, TN>(B, sB, n0, k0, N, kend);
+    Stager<AL, TM> ga;
+    Stager<BL, TN> gb;
+    ga.prep(A, m0, M);
+    gb.prep(B, n0, N);
+    if (kbeg < kend) {
+        ga.load(A, kbeg, kend);
+        gb.load(B, kbeg, kend);
+    }
+    int buf = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += TK, buf ^= 1) {
+        ga.store(sA[buf]);
+        gb.store(sB[buf]);
         __syncthreads();
+        if (k0 + TK < kend) {
+            ga.load(A, k0 + TK, kend);
+            gb.load(B, k0 + TK, kend);
+        }
+        const bf16_t *a = sA[buf], *bsm = sB[buf];
 #pragma unroll
         for (int kk = 0; kk < TK; kk += 16) {
             bf16x8 af[BM], bfr[BN];
 #pragma unroll
             for (int i = 0; i < BM; ++i)
-                af[i] = *(const bf16x8 *)&sA[(wm * WTM + i * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
+                af[i] = *(const bf16x8 *)&a[(wm * WTM + i * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
 #pragma unroll
             for (int j = 0; j < BN; ++j)
-                bfr[j] = *(const bf16x8 *)&sB[(wn * WTN + j * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
+                bfr[j] = *(const bf16x8 *)&bsm[(wn * WTN + j * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
 #pragma unroll
             for (int i = 0; i < BM; ++i)
 #pragma unroll
                 for (int j = 0; j < BN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < BM; ++i)
