@@ -139,12 +139,14 @@ void or_backproject(int n_x, int n_y, int K, int L, const double *ang, double ax
                     double s, const double *sino, double *img)
 {
     double cx = 0.5 * (n_x - 1), cy = 0.5 * (n_y - 1);
+    double *ct = (double *)malloc(sizeof(double) * (size_t)K), *st = (double *)malloc(sizeof(double) * (size_t)K);
+    for (int k = 0; k < K; ++k) { ct[k] = cos(ang[k]); st[k] = sin(ang[k]); }
 #pragma omp parallel for schedule(static)
     for (int iy = 0; iy < n_y; ++iy) {
         for (int ix = 0; ix < n_x; ++ix) {
             double x = ix - cx, y = iy - cy, acc = 0.0;
             for (int k = 0; k < K; ++k) {
-                double t = s * (x * cos(ang[k]) + y * sin(ang[k])) + axis + (shift ? shift[k] : 0.0);
+                double t = s * (x * ct[k] + y * st[k]) + axis + (shift ? shift[k] : 0.0);
                 long j0 = (long)floor(t);
                 for (long j = j0; j <= j0 + 1; ++j) {
                     if (j < 0 || j >= L) continue;
@@ -155,6 +157,8 @@ void or_backproject(int n_x, int n_y, int K, int L, const double *ang, double ax
             img[(size_t)iy * n_x + ix] = acc;
         }
     }
+    free(ct);
+    free(st);
 }
 
 /* Forward projection, written as a scatter over pixels (the transpose of the
@@ -362,11 +366,13 @@ void or_backproject_points(int n_x, int n_y, int K, int L, const double *ang, do
                            double s, const double *sino, int npts, const int *pix_x, const int *pix_y, double *out)
 {
     double cx = 0.5 * (n_x - 1), cy = 0.5 * (n_y - 1);
+    double *ct = (double *)malloc(sizeof(double) * (size_t)K), *st = (double *)malloc(sizeof(double) * (size_t)K);
+    for (int k = 0; k < K; ++k) { ct[k] = cos(ang[k]); st[k] = sin(ang[k]); }
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < npts; ++i) {
         double x = pix_x[i] - cx, y = pix_y[i] - cy, acc = 0.0;
         for (int k = 0; k < K; ++k) {
-            double t = s * (x * cos(ang[k]) + y * sin(ang[k])) + axis + (shift ? shift[k] : 0.0);
+            double t = s * (x * ct[k] + y * st[k]) + axis + (shift ? shift[k] : 0.0);
             long j0 = (long)floor(t);
             for (long j = j0; j <= j0 + 1; ++j) {
                 if (j < 0 || j >= L) continue;
@@ -376,4 +382,6 @@ void or_backproject_points(int n_x, int n_y, int K, int L, const double *ang, do
         }
         out[i] = acc;
     }
+    free(ct);
+    free(st);
 }

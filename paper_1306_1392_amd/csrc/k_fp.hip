@@ -9,8 +9,9 @@
 // per line can touch the bin.  Their positions are anchored in FP64 per line
 // (t reaches ~2000 bins, where FP32 would lose 2e-4 bin); the weights are FP32.
 //
-// Launch: workgroup = 4 wavefronts = 4 consecutive projections x 64 bins;
-// consecutive projections read overlapping image spans, which stay in L1/L2.
+// Launch: workgroup = one projection x 64 bins; its 4 wavefronts take every
+// fourth image line and their partial sums are added in a fixed order (LDS),
+// so one slice already gives nb/64 x K workgroups and the result is deterministic.
 #include "internal.hpp"
 
 namespace pyhst {
@@ -21,13 +22,15 @@ template <int MODE>
 __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restrict__ img, float *__restrict__ out,
                                                  float alpha, CpDual cp)
 {
+    __shared__ float part[3][64];
     const int slice = blockIdx.z;
     const SliceDev sd = T.slc[slice];
     const GeoDev &g = T.geo[sd.g];
     const int K = g.K, nb = g.nb, nx = g.nx, ny = g.ny;
-    const int k = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-    if (k >= K || blockIdx.x * 64 >= nb) return;
+    const int k = blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
+    if (k >= K || blockIdx.x * 64 >= nb) return;   // uniform over the workgroup
 
     const double c = T.cosd[g.ang_off + k], sn = T.sind[g.ang_off + k];
     const double s = g.s;
@@ -37,14 +40,16 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
     float acc = 0.0f;
 
     if (fabs(c) >= fabs(sn)) {
-        // walk rows: along a row, t - j = s c (ix - cx) + B(iy), B(iy) = off + s sn (iy - cy)
+        // walk rows (the 4 wavefronts take rows wv, wv + 4, ...): along a row
+        // t - j = s c (ix - cx) + B(iy), B(iy) = off + s sn (iy - cy)
         const double sc = s * c;
         const double rho = 1.0 / fabs(sc);
         const int ncand = (int)ceil(2.0 * rho);
         const double du = -(s * sn) / sc;                 // change of the crossing position per row
-        double u = cx - (off - s * sn * cy) / sc;         // crossing ix (real) of row 0
+        const double u0 = cx - (off - s * sn * cy) / sc;  // crossing ix (real) of row 0
         const float scf = (float)sc;
-        for (int iy = 0; iy < ny; ++iy, u += du) {
+        for (int iy = wv; iy < ny; iy += 4) {
+            const double u = fma((double)iy, du, u0);
             const double fl = floor(u - rho);
             const int i0 = (int)fl + 1;
             float d = (float)((fl + 1.0) - u) * scf;      // t - j at pixel i0
@@ -61,9 +66,10 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
         const double rho = 1.0 / fabs(ss);
         const int ncand = (int)ceil(2.0 * rho);
         const double dv = -(s * c) / ss;
-        double v = cy - (off - s * c * cx) / ss;
+        const double v0 = cy - (off - s * c * cx) / ss;
         const float ssf = (float)ss;
-        for (int ix = 0; ix < nx; ++ix, v += dv) {
+        for (int ix = wv; ix < nx; ix += 4) {
+            const double v = fma((double)ix, dv, v0);
             const double fl = floor(v - rho);
             const int i0 = (int)fl + 1;
             float d = (float)((fl + 1.0) - v) * ssf;
@@ -74,7 +80,11 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
             }
         }
     }
-    if (j >= nb) return;
+    // fixed-order reduction of the four partial sums
+    if (wv > 0) part[wv - 1][lane] = acc;
+    __syncthreads();
+    if (wv > 0 || j >= nb) return;
+    acc = ((acc + part[0][lane]) + part[1][lane]) + part[2][lane];
     const int64_t o = sd.sino_off + (int64_t)k * nb + j;
     const float v = alpha * (float)(s * s) * acc;   // A = s^2 B^T
     if (MODE == 0) {
@@ -91,7 +101,7 @@ hipError_t launch_forward(const pyhst_plan &p, const float *img, float *sino, fl
 {
     int maxnb = 0;
     for (const auto &g : p.gd) maxnb = std::max(maxnb, g.nb);
-    dim3 grid((maxnb + 63) / 64, (unsigned)((p.max_K + 3) / 4), p.n_slices);
+    dim3 grid((maxnb + 63) / 64, (unsigned)p.max_K, p.n_slices);
     if (cp) {
         fp_kernel<1><<<grid, 256, 0, st>>>(p.t, img, nullptr, alpha, *cp);
     } else {

@@ -13,7 +13,7 @@ from paper_1306_1392_amd.cnn import UNet, init_params
 
 pytestmark = pytest.mark.gpu
 TOL = 2e-3        # one layer: FP32 vs FP64 accumulation flips isolated BF16 roundings
-TOL_NET = 1e-2    # whole network: those flips compound through up to 18 BF16 layers
+TOL_NET = 2e-2    # whole network: those flips compound through up to 18 BF16 layers and back
 
 
 def rel(a, b):
