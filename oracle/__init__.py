@@ -68,7 +68,8 @@ def lib():
         L.or_tv.restype = d
         L.or_tv_prox.argtypes = [i, i, P, d, i, P]
         L.or_cp_tv.argtypes = [i, i, i, i, i, P, d, P, d, P, d, i, d, P, P]
-        L.or_opnorm.argtypes = [i, i, i, i, P, d, P, d, P, i]
+        L.or_opnorm.argtypes = [i, i, i, i, P, d, P, d, P, i, i]
+        L.or_fista_tv.argtypes = [i, i, i, i, i, i, P, d, P, d, P, d, i, d, i, P, P]
         L.or_opnorm.restype = d
         L.or_num_threads.restype = i
         IP = ctypes.POINTER(ctypes.c_int)
@@ -308,7 +309,26 @@ def cp_tv(y, g: Geom | None, lam: float, n_iter: int, op_norm: float, energy: bo
     return (x, E[:n_iter]) if energy else x
 
 
-def opnorm(g: Geom, x0, n_iter: int = 200) -> float:
+def opnorm(g: Geom, x0, n_iter: int = 200, with_grad: bool = True) -> float:
+    """|[A; grad]|_2 (with_grad) or |A|_2 by power iteration from x0."""
     x0 = _f64(x0)
     return lib().or_opnorm(g.n_x, g.n_y, g.K, g.n_det, _p(g.angles), g.axis, _p(g.shifts), g.pixel_size,
-                           _p(x0), n_iter)
+                           _p(x0), n_iter, int(bool(with_grad)))
+
+
+def fista_tv(y, g: Geom | None, lam: float, n_iter: int, lipschitz: float, n_inner: int, fast: bool = True,
+             energy: bool = False, identity_shape=None):
+    """ISTA (fast=False) or FISTA iterate x_{n_iter} for eq. (3), step 1/lipschitz, inner ROF prox of
+    n_inner dual iterations (and the energy trace).  g=None with identity_shape replaces A by the identity."""
+    y = _f64(y)
+    E = np.empty(max(n_iter, 1)) if energy else None
+    if g is None:
+        ny, nx = identity_shape
+        x = np.empty((ny, nx))
+        lib().or_fista_tv(int(fast), 1, nx, ny, 0, 0, None, 0.0, None, 1.0, _p(y), lam, n_iter, lipschitz,
+                          n_inner, _p(x), _p(E))
+    else:
+        x = np.empty((g.n_y, g.n_x))
+        lib().or_fista_tv(int(fast), 0, g.n_x, g.n_y, g.K, g.n_det, _p(g.angles), g.axis, _p(g.shifts),
+                          g.pixel_size, _p(y), lam, n_iter, lipschitz, n_inner, _p(x), _p(E))
+    return (x, E[:n_iter]) if energy else x

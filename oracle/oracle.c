@@ -330,10 +330,62 @@ void or_cp_tv(int identity, int n_x, int n_y, int K, int L, const double *ang, d
     free(x); free(xb); free(p); free(ax); free(q1); free(q2); free(g1); free(g2); free(atp); free(dv);
 }
 
-/* Operator norm |K|_2 of K = [A; grad] by power iteration on K^T K from the
- * caller's start vector x0 (n_y*n_x).  Returns sqrt of the Rayleigh quotient. */
+/* ---------------------------------------------------------------------------
+ * ISTA and FISTA for eq. (3), the solvers the paper names for the TV mode
+ * (section 3.1; Daubechies et al. 2004, Beck & Teboulle 2009).  With
+ * f(x) = 1/2|A x - y|^2, whose gradient A^T (A x - y) is La-Lipschitz for
+ * La >= |A|^2, every iteration takes a gradient step of length 1/La from z and
+ * then the proximal map of (lambda/La) TV:
+ *     x_k = prox_{(lambda/La) TV}( z - (1/La) A^T (A z - y) )
+ * The proximal map is or_tv_prox with n_inner dual iterations from zero.
+ *     ISTA : z <- x_k
+ *     FISTA: t' = (1 + sqrt(1 + 4 t^2)) / 2,  z <- x_k + ((t - 1) / t') (x_k - x_{k-1}),  t <- t'
+ * starting from x_0 = z = 0, t = 1.  'identity' replaces A by the identity.
+ * energy[i] (if non-NULL) = 1/2|A x_i - y|^2 + lambda TV(x_i) after iteration i.
+ * ------------------------------------------------------------------------- */
+void or_fista_tv(int fast, int identity, int n_x, int n_y, int K, int L, const double *ang, double axis,
+                 const double *shift, double s, const double *y, double lambda, int n_iter, double La,
+                 int n_inner, double *x_out, double *energy)
+{
+    size_t n = (size_t)n_x * n_y, m = identity ? n : (size_t)K * L;
+    double *x = (double *)calloc(n, sizeof(double)), *xprev = (double *)calloc(n, sizeof(double));
+    double *z = (double *)calloc(n, sizeof(double)), *v = (double *)malloc(n * sizeof(double));
+    double *r = (double *)malloc(m * sizeof(double)), *atr = (double *)malloc(n * sizeof(double));
+    double t = 1.0;
+    for (int it = 0; it < n_iter; ++it) {
+        /* gradient step from z */
+        apply_A(identity, n_x, n_y, K, L, ang, axis, shift, s, z, r);
+        for (size_t o = 0; o < m; ++o) r[o] -= y[o];
+        apply_AT(identity, n_x, n_y, K, L, ang, axis, shift, s, r, atr);
+        for (size_t o = 0; o < n; ++o) v[o] = z[o] - atr[o] / La;
+        /* proximal step */
+        memcpy(xprev, x, n * sizeof(double));
+        or_tv_prox(n_y, n_x, v, lambda / La, n_inner, x);
+        /* next extrapolation point */
+        if (fast) {
+            double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+            double mom = (t - 1.0) / tn;
+            for (size_t o = 0; o < n; ++o) z[o] = x[o] + mom * (x[o] - xprev[o]);
+            t = tn;
+        } else {
+            memcpy(z, x, n * sizeof(double));
+        }
+        if (energy) {
+            apply_A(identity, n_x, n_y, K, L, ang, axis, shift, s, x, r);
+            double e = 0.0;
+            for (size_t o = 0; o < m; ++o) e += (r[o] - y[o]) * (r[o] - y[o]);
+            energy[it] = 0.5 * e + lambda * or_tv(n_y, n_x, x);
+        }
+    }
+    memcpy(x_out, x, n * sizeof(double));
+    free(x); free(xprev); free(z); free(v); free(r); free(atr);
+}
+
+/* Operator norm |K|_2 of K = [A; grad] (with_grad != 0) or of A alone
+ * (with_grad == 0) by power iteration on K^T K (or A^T A) from the caller's
+ * start vector x0 (n_y*n_x).  Returns sqrt of the Rayleigh quotient. */
 double or_opnorm(int n_x, int n_y, int K, int L, const double *ang, double axis, const double *shift, double s,
-                 const double *x0, int n_iter)
+                 const double *x0, int n_iter, int with_grad)
 {
     size_t n = (size_t)n_x * n_y, m = (size_t)K * L;
     double *x = (double *)malloc(n * sizeof(double)), *ax = (double *)malloc(m * sizeof(double));
@@ -347,9 +399,11 @@ double or_opnorm(int n_x, int n_y, int K, int L, const double *ang, double axis,
     for (int it = 0; it < n_iter; ++it) {
         or_forward_project(n_x, n_y, K, L, ang, axis, shift, s, x, ax);
         apply_AT(0, n_x, n_y, K, L, ang, axis, shift, s, ax, a);
-        or_grad(n_y, n_x, x, g1, g2);
-        or_div(n_y, n_x, g1, g2, b);
-        for (size_t o = 0; o < n; ++o) a[o] -= b[o];       /* K^T K x = A^T A x - div grad x */
+        if (with_grad) {
+            or_grad(n_y, n_x, x, g1, g2);
+            or_div(n_y, n_x, g1, g2, b);
+            for (size_t o = 0; o < n; ++o) a[o] -= b[o];   /* K^T K x = A^T A x - div grad x */
+        }
         double dot = 0.0, nn = 0.0;
         for (size_t o = 0; o < n; ++o) { dot += a[o] * x[o]; nn += a[o] * a[o]; }
         lam = dot;

@@ -382,3 +382,121 @@ def test_cp_energy_decreases_and_recovers_disc():
     yy, xx = np.mgrid[0:N, 0:N]
     inside = ((xx - (N - 1) / 2) ** 2 + (yy - (N - 1) / 2) ** 2) < (0.4 * N / 2) ** 2     # disc radius 0.5 N/2
     assert abs(x[inside].mean() - 1.0) < 0.03
+
+
+# --------------------------------------------------------------------------- ISTA / FISTA (section 3.1)
+def test_opnorm_of_A_alone_matches_svd():
+    g = Geom(8, 8, 14, synth.uniform_angles(10), 6.7, pixel_size=0.9)
+    ref = np.linalg.norm(lerp_matrix(g) * 0.81, 2)          # A = s^2 B^T
+    x0 = np.random.default_rng(1).standard_normal((8, 8))
+    assert abs(oracle.opnorm(g, x0, 400, with_grad=False) / ref - 1) < 1e-8
+
+
+def test_ista_identity_one_step_is_rof():
+    """A = I, step 1 (|I|^2 = 1), x_0 = 0: the first ISTA/FISTA iterate is prox_{lambda TV}(y)."""
+    rng = np.random.default_rng(21)
+    y = rng.standard_normal((10, 12))
+    for fast in (False, True):
+        x = oracle.fista_tv(y, None, 0.3, 1, 1.0, 50, fast=fast, identity_shape=(10, 12))
+        assert rel(x, oracle.tv_prox(y, 0.3, 50)) < 1e-14
+
+
+def test_ista_lambda0_is_landweber_closed_form():
+    """beta = 0: ISTA is the Landweber iteration x_k = sum_{j<k} (I - A^T A/La)^j A^T y / La, whose closed
+    form in the eigenbasis of A^T A (eigenvalues e) is V diag((1 - (1 - e/La)^k) / e) V^T A^T y."""
+    g = Geom(6, 6, 11, synth.uniform_angles(9), 5.2, shifts=np.linspace(-0.3, 0.4, 9))
+    A = lerp_matrix(g)
+    rng = np.random.default_rng(22)
+    y = rng.standard_normal(A.shape[0])
+    e, V = np.linalg.eigh(A.T @ A)
+    La = 1.1 * e[-1]
+    b = V.T @ (A.T @ y)
+    for k in (1, 2, 7, 40):
+        fac = np.where(e > 1e-12 * e[-1], (1 - (1 - e / La) ** k) / np.maximum(e, 1e-300), k / La)
+        ref = V @ (fac * b)
+        x = oracle.fista_tv(y.reshape(g.K, g.n_det), g, 0.0, k, La, 5, fast=False)
+        assert rel(x.ravel(), ref) < 1e-12, k
+
+
+def test_fista_rate_bound_and_limit():
+    """beta = 0 (exact prox): Beck & Teboulle's bounds F(x_k) - F* <= 2 La |x* - x_0|^2 / (k+1)^2 for FISTA
+    and La |x* - x_0|^2 / (2k) for ISTA hold at every k, FISTA ends far below ISTA, and both tend to the
+    least-squares solution (numpy lstsq)."""
+    g = Geom(8, 8, 12, synth.uniform_angles(6), 5.6)
+    A = lerp_matrix(g)
+    rng = np.random.default_rng(23)
+    y = A @ rng.random(64) + 0.01 * rng.standard_normal(A.shape[0])
+    xs = np.linalg.lstsq(A, y, rcond=None)[0]
+    Fs = 0.5 * np.sum((A @ xs - y) ** 2)
+    La = np.linalg.norm(A, 2) ** 2
+    n = 400
+    _, Ef = oracle.fista_tv(y.reshape(g.K, g.n_det), g, 0.0, n, La, 1, fast=True, energy=True)
+    _, Ei = oracle.fista_tv(y.reshape(g.K, g.n_det), g, 0.0, n, La, 1, fast=False, energy=True)
+    k = np.arange(1, n + 1)
+    R2 = np.sum(xs ** 2)
+    assert np.all(Ef - Fs <= 2 * La * R2 / (k + 1) ** 2 * (1 + 1e-9) + 1e-12)
+    assert np.all(Ei - Fs <= La * R2 / (2 * k) * (1 + 1e-9) + 1e-12)
+    assert np.all(np.diff(Ei) <= 1e-12)                  # ISTA is monotone
+    assert Ef[-1] - Fs < 0.5 * (Ei[-1] - Fs)
+    # the iterates themselves approach lstsq (condition number ~5e3 here)
+    g = Geom(6, 6, 12, synth.uniform_angles(40), 5.7)
+    A = lerp_matrix(g)
+    y = A @ rng.random(36) + 0.01 * rng.standard_normal(A.shape[0])
+    xs = np.linalg.lstsq(A, y, rcond=None)[0]
+    La = np.linalg.norm(A, 2) ** 2
+    xf = oracle.fista_tv(y.reshape(g.K, g.n_det), g, 0.0, 3000, La, 1, fast=True)
+    xi = oracle.fista_tv(y.reshape(g.K, g.n_det), g, 0.0, 3000, La, 1, fast=False)
+    assert rel(xf.ravel(), xs) < 2e-3
+    assert rel(xf.ravel(), xs) < 0.05 * rel(xi.ravel(), xs)
+
+
+def test_fista_and_ista_reach_the_cp_minimiser():
+    """beta > 0 on a sparse-angle problem: FISTA, ISTA (accurate inner prox) and Chambolle-Pock, three
+    iterations written independently, reach the same energy; FISTA gets there much faster than ISTA."""
+    N = 12
+    g = Geom(N, N, 16, synth.uniform_angles(8), 7.4)
+    A = lerp_matrix(g)
+    rng = np.random.default_rng(24)
+    img = np.kron(np.array([[1.0, 0.2], [0.5, 0.0]]), np.ones((N // 2, N // 2)))
+    y = (A @ img.ravel() + 0.02 * rng.standard_normal(A.shape[0])).reshape(g.K, g.n_det)
+    lam = 0.05
+    La = np.linalg.norm(A, 2) ** 2
+    Lk = np.linalg.norm(np.vstack([A, explicit_grad(N, N)]), 2)
+    _, Ec = oracle.cp_tv(y, g, lam, 20000, Lk, energy=True)
+    _, Ef = oracle.fista_tv(y, g, lam, 1500, La, 300, fast=True, energy=True)
+    _, Ei = oracle.fista_tv(y, g, lam, 60, La, 300, fast=False, energy=True)
+    Fs = min(Ec[-1], Ef.min())
+    assert abs(Ef[-1] - Ec[-1]) < 1e-6 * Ec[-1]
+    assert Ef[59] - Fs < 0.5 * (Ei[59] - Fs)              # the accelerated scheme converges faster
+    assert np.all(np.diff(Ei) <= 1e-9 * Ei[0])           # ISTA decreases the energy monotonically
+
+
+def test_fista_third_iterate_by_hand():
+    """A = I, beta = 0, step 1/2 (La = 2): the gradient step is v = (z + y)/2, so x_1 = y/2, z_2 = x_1
+    (t_1 = 1 gives no momentum), x_2 = 3y/4, z_3 = x_2 + m_2 (x_2 - x_1), x_3 = (z_3 + y)/2 = y (7 + m_2)/8,
+    with t_2 = (1 + sqrt 5)/2, t_3 = (1 + sqrt(1 + 4 t_2^2))/2 = 2.1935270..., m_2 = (t_2 - 1)/t_3 = 0.2817535...
+    ISTA gives x_3 = 7y/8."""
+    y = np.random.default_rng(25).standard_normal((5, 7))
+    x3 = oracle.fista_tv(y, None, 0.0, 3, 2.0, 1, fast=True, identity_shape=(5, 7))
+    assert rel(x3, y * (7 + 0.2817535251) / 8) < 1e-8
+    x3i = oracle.fista_tv(y, None, 0.0, 3, 2.0, 1, fast=False, identity_shape=(5, 7))
+    assert rel(x3i, y * 7 / 8) < 1e-15
+
+
+def test_fista_lyapunov_function_decreases():
+    """Beck & Teboulle's proof: with t_k of FISTA, t_k^2 (F(x_k) - F*) + La/2 |t_k x_k - (t_k - 1) x_{k-1} - x*|^2
+    does not increase (beta = 0, exact prox; iterates x_k from separate runs of k iterations)."""
+    g = Geom(6, 6, 10, synth.uniform_angles(5), 4.6)
+    A = lerp_matrix(g)
+    rng = np.random.default_rng(26)
+    y = A @ rng.random(36) + 0.01 * rng.standard_normal(A.shape[0])
+    xs = np.linalg.lstsq(A, y, rcond=None)[0]
+    Fs = 0.5 * np.sum((A @ xs - y) ** 2)
+    La = np.linalg.norm(A, 2) ** 2
+    X = [np.zeros(36)] + [oracle.fista_tv(y.reshape(g.K, g.n_det), g, 0.0, k, La, 1).ravel() for k in range(1, 61)]
+    t, V = 1.0, []
+    for k in range(1, 61):
+        u = t * X[k] - (t - 1) * X[k - 1] - xs
+        V.append(t * t * (0.5 * np.sum((A @ X[k] - y) ** 2) - Fs) + 0.5 * La * np.sum(u * u))
+        t = 0.5 * (1 + math.sqrt(1 + 4 * t * t))
+    assert np.all(np.diff(V) <= 1e-10 * V[0])
