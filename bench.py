@@ -219,11 +219,46 @@ def run_tv(args):
     stream.synchronize()
     ms = e[0].elapsed_time(e[1]) / reps
     U = 2.0 * 1024 * 1024 * 128 * 300
+
+    # the paper's own solvers on the same data: 300 ISTA / FISTA iterations, 10 inner prox steps each
+    fi = {}
+    for name, meth in (("ista", ph.ISTA), ("fista", ph.FISTA)):
+        wk = torch.empty(ph.work_bytes(plan, sino=y, method=meth, n_iter=300), device=dev, dtype=torch.uint8)
+        ph.reconstruct_slices(plan, sino=y, method=meth, lam=0.01, n_iter=1, op_norm=0.0, n_inner=10, out=out,
+                              work=wk, stream=stream)
+        La = plan.last_op_norm
+
+        def run_fi():
+            ph.reconstruct_slices(plan, sino=y, method=meth, lam=0.01, n_iter=300, op_norm=La, n_inner=10,
+                                  out=out, work=wk, use_graph=True, stream=stream)
+
+        run_fi()
+        stream.synchronize()
+        e[0].record(stream)
+        for _ in range(reps):
+            run_fi()
+        e[1].record(stream)
+        stream.synchronize()
+        fi[name] = {"s_300_iterations": round(e[0].elapsed_time(e[1]) / reps / 1e3, 4), "op_norm_A": La,
+                    "n_inner": 10}
+
     res = {"metric": "TV-CP reconstruction time (300 iterations)", "value": round(ms / 1e3, 4), "unit": "s",
            "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "1024x1024, 1024 bins, 128 angles, Poisson 1e4 photons, 300 Chambolle-Pock "
                                   "iterations, lambda 0.01, one HIP graph", "op_norm": Lk},
-           "gups_in_projectors": round(U / (ms * 1e-3) / 1e9, 2), "slices_per_s": round(1e3 / ms, 3)}
+           "gups_in_projectors": round(U / (ms * 1e-3) / 1e9, 2), "slices_per_s": round(1e3 / ms, 3),
+           "paper_solvers": fi}
+    if not args.no_cpu_baseline:
+        import oracle
+        og = oracle.Geom(1024, 1024, 1024, d["angles"], d["axis"])
+        yc = d["y"].double().cpu().numpy()
+        t0 = time.time()
+        oracle.cp_tv(yc, og, 0.01, 3, Lk)
+        dt = time.time() - t0
+        res["cpu_baseline"] = {"value": round(dt * 100, 1), "unit": "s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"3 of the 300 Chambolle-Pock iterations (FP64 scatter projector, "
+                                         f"pixel-driven backprojector), {dt:.1f} s, scaled by 100"}
     print(json.dumps(res), flush=True)
 
 
@@ -338,6 +373,17 @@ def run_cnn(args):
            "infer_tflops": round(fwd_flop / (infer_ms * 1e-3) / 1e12, 1),
            "train_tflops": round(3 * fwd_flop / (train_ms * 1e-3) / 1e12, 1),
            "mfma_bf16_peak_tflops": 2500.0}
+    if not args.no_cpu_baseline:
+        from oracle import num_threads
+        from oracle.cnn import UNetOracle
+        xc = x[:1].double().cpu().numpy()
+        p64 = net.get_params().double().cpu().numpy()
+        t0 = time.time()
+        UNetOracle(32, 4, "fp64").forward(p64, xc)
+        dt = time.time() - t0
+        res["cpu_baseline"] = {"value": round(1.0 / dt, 4), "unit": "slices/s", "cores": num_threads(),
+                               "kind": "oracle",
+                               "sample": f"FP64 NumPy forward pass of 1 slice of 512x512, {dt:.1f} s"}
     print(json.dumps(res), flush=True)
 
 

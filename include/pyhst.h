@@ -59,7 +59,7 @@ enum {
 };
 
 enum { PYHST_SCAN_180 = 0, PYHST_SCAN_360 = 1, PYHST_SCAN_360_HALF = 2 };
-enum { PYHST_FBP = 0, PYHST_TV_CP = 1 };
+enum { PYHST_FBP = 0, PYHST_TV_CP = 1, PYHST_ISTA = 2, PYHST_FISTA = 3 };
 
 /* Geometry of one slice family (section 2.1: parallel beam, >= 180 degrees of
  * rotation, optional 360 degree half acquisition with the axis near a detector
@@ -172,6 +172,14 @@ int tv_prox(int32_t n_slices, int32_t n_y, int32_t n_x, const float *in, float *
  *     whole batch after every iteration (section 3.1: the energy is displayed
  *     so convergence can be checked); non-NULL energy makes the call
  *     synchronous and a non-finite energy returns PYHST_ENUM.
+ *   method PYHST_ISTA / PYHST_FISTA: eq. (3) by the solvers named in section
+ *     3.1 (Daubechies et al. 2004; Beck & Teboulle 2009): n_iter iterations of
+ *       x_k = prox_{(lambda/La) TV}(z - (1/La) A^T (A z - y)),  La = op_norm^2,
+ *     ISTA: z = x_k;  FISTA: t' = (1 + sqrt(1 + 4t^2))/2,
+ *     z = x_k + ((t - 1)/t') (x_k - x_{k-1}), t = t', from x_0 = z = 0, t = 1.
+ *     The proximal map is tv_prox with n_inner dual iterations from zero.
+ *     op_norm is |A| here (op_norm <= 0: estimated by 50 power iterations on
+ *     A^T A, x 1.02, written back); energy as for PYHST_TV_CP.
  * Input: raw (uint16 [K][R][n_det] with flats, flat_pos, n_flats, dark, eps;
  * uniform plans) or, when raw == NULL, sino (normalised line integrals,
  * packed [K][n_det]).  out [packed n_y x n_x].
@@ -196,6 +204,7 @@ typedef struct {
     void *work;
     size_t work_bytes;
     int32_t use_graph;
+    int32_t n_inner;          /* ISTA/FISTA: dual iterations of each proximal map (>= 0) */
 } pyhst_recon_args;
 
 int reconstruct_slices(const pyhst_plan *plan, pyhst_recon_args *a, hipStream_t stream);

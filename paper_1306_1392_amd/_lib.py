@@ -12,7 +12,7 @@ c_int32, c_int64, c_double, c_float, c_void_p, c_size_t = (ctypes.c_int32, ctype
 
 OK, EARG, EGEOM, ENOMEM, EHIP, ENUM = 0, -1, -2, -3, -4, -5
 SCAN_180, SCAN_360, SCAN_360_HALF = 0, 1, 2
-FBP, TV_CP = 0, 1
+FBP, TV_CP, ISTA, FISTA = 0, 1, 2, 3
 
 EXPORTS = ["pyhst_plan_create", "pyhst_plan_destroy", "pyhst_plan_slice_info", "pyhst_plan_sizes",
            "pyhst_plan_set_tiles", "pyhst_plan_get_tiles", "pyhst_normalize", "fbp_filter", "backproject",
@@ -40,7 +40,7 @@ class ReconArgs(ctypes.Structure):
                 ("n_flats", c_int32), ("dark", c_void_p), ("eps", c_float), ("method", c_int32),
                 ("lambda_", c_float), ("n_iter", c_int32), ("op_norm", c_double),
                 ("energy", ctypes.POINTER(c_float)), ("out", c_void_p), ("work", c_void_p),
-                ("work_bytes", c_size_t), ("use_graph", c_int32)]
+                ("work_bytes", c_size_t), ("use_graph", c_int32), ("n_inner", c_int32)]
 
 
 _lib = None

@@ -11,7 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import check, SCAN_180, SCAN_360, SCAN_360_HALF, FBP, TV_CP  # noqa: F401
+from ._lib import check, SCAN_180, SCAN_360, SCAN_360_HALF, FBP, TV_CP, ISTA, FISTA  # noqa: F401
 
 
 @dataclass
@@ -206,8 +206,10 @@ def tv_prox(x, lam: float, n_inner: int, out=None, work=None, stream=None):
 
 def reconstruct_slices(plan: Plan, *, raw=None, sino=None, flats=None, flat_pos=None, dark=None, eps: float = 1e-6,
                        method: int = FBP, lam: float = 0.0, n_iter: int = 0, op_norm: float = 0.0,
-                       energy: bool = False, out=None, work=None, use_graph: bool = False, stream=None):
-    """Returns out (and the energy trace as a numpy array when energy=True)."""
+                       n_inner: int = 20, energy: bool = False, out=None, work=None, use_graph: bool = False,
+                       stream=None):
+    """Returns out (and the energy trace as a numpy array when energy=True).  op_norm is |[A; grad]| for
+    TV_CP and |A| for ISTA/FISTA (<= 0: estimated on the GPU, then available as plan.last_op_norm)."""
     a = _lib.ReconArgs()
     a.raw = _ptr(raw)
     a.sino = _ptr(sino)
@@ -224,6 +226,7 @@ def reconstruct_slices(plan: Plan, *, raw=None, sino=None, flats=None, flat_pos=
     a.n_iter = int(n_iter)
     a.op_norm = float(op_norm)
     a.use_graph = int(bool(use_graph))
+    a.n_inner = int(n_inner)
     if raw is not None:
         _need(raw, plan.sino_elems, "raw", torch.uint16)
         _need(flats, flats.numel(), "flats")

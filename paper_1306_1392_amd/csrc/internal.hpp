@@ -109,10 +109,11 @@ struct CpPrimal {   // x+ = x - tau (alpha B p - div q); xbar = 2 x+ - x
     const float *q1, *q2;
     float tau;
 };
-struct CpDual {     // p = (p + sigma (alpha A xbar - y)) / (1 + sigma)
+struct CpDual {     // p = (p + sigma (alpha A xbar - y)) / (1 + sigma);  residual != 0: p = alpha A xbar - y
     float *p;
     const float *y;
     float sigma;
+    int residual;
 };
 
 // launchers (return hipGetLastError())
@@ -138,7 +139,9 @@ hipError_t launch_cp_energy(const pyhst_plan &p, const float *ax, const float *y
 int energy_partials(const pyhst_plan &p);
 hipError_t launch_axpby(float *y, const float *x, int64_t n, float a, float b, hipStream_t st);
 hipError_t launch_power_step(const pyhst_plan &p, const float *x, float *out, float *tmp_sino,
-                             double *partials, int n_part, double *norm_dev, hipStream_t st);
+                             double *partials, int n_part, double *norm_dev, int with_grad, hipStream_t st);
+hipError_t launch_momentum(float *z, const float *xn, const float *xo, int64_t n, float m, hipStream_t st);
+hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t st);
 hipError_t launch_scale_by_inv(float *x, int64_t n, const double *norm_dev, hipStream_t st);
 
 }  // namespace pyhst

@@ -89,8 +89,10 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
     const float v = alpha * (float)(s * s) * acc;   // A = s^2 B^T
     if (MODE == 0) {
         out[o] = v;
-    } else {
+    } else if (MODE == 1) {
         cp.p[o] = (cp.p[o] + cp.sigma * (v - cp.y[o])) / (1.0f + cp.sigma);
+    } else {
+        cp.p[o] = v - cp.y[o];   // residual A x - y of the gradient step of ISTA/FISTA
     }
 }
 
@@ -102,7 +104,9 @@ hipError_t launch_forward(const pyhst_plan &p, const float *img, float *sino, fl
     int maxnb = 0;
     for (const auto &g : p.gd) maxnb = std::max(maxnb, g.nb);
     dim3 grid((maxnb + 63) / 64, (unsigned)p.max_K, p.n_slices);
-    if (cp) {
+    if (cp && cp->residual) {
+        fp_kernel<2><<<grid, 256, 0, st>>>(p.t, img, nullptr, alpha, *cp);
+    } else if (cp) {
         fp_kernel<1><<<grid, 256, 0, st>>>(p.t, img, nullptr, alpha, *cp);
     } else {
         CpDual none{};

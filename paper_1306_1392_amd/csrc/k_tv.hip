@@ -84,6 +84,16 @@ __global__ void axpby_kernel(float *y, const float *x, int64_t n, float a, float
         y[o] = a * x[o] + b * y[o];
 }
 
+// FISTA extrapolation: z = xn + m (xn - xo)
+__global__ void momentum_kernel(float *__restrict__ z, const float *__restrict__ xn, const float *__restrict__ xo,
+                                int64_t n, float m)
+{
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
+        const float a = xn[o];
+        z[o] = fmaf(m, a - xo[o], a);
+    }
+}
+
 // Chambolle-Pock dual TV step: q <- pi_lambda(q + sigma grad xbar)
 __global__ void cp_q_kernel(int64_t n, int ny, int nx, const float *__restrict__ xb, float *__restrict__ q1,
                             float *__restrict__ q2, float sigma, float lambda)
@@ -215,6 +225,18 @@ hipError_t launch_fill(float *buf, int64_t n, float v, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t launch_momentum(float *z, const float *xn, const float *xo, int64_t n, float m, hipStream_t st)
+{
+    momentum_kernel<<<grid_for(n), 256, 0, st>>>(z, xn, xo, n, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t st)
+{
+    copy_kernel<<<grid_for(n), 256, 0, st>>>(dst, src, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_axpby(float *y, const float *x, int64_t n, float a, float b, hipStream_t st)
 {
     axpby_kernel<<<grid_for(n), 256, 0, st>>>(y, x, n, a, b);
@@ -258,9 +280,9 @@ hipError_t launch_cp_energy(const pyhst_plan &p, const float *ax, const float *y
     return hipGetLastError();
 }
 
-// out = K^T K x = A^T A x - div grad x ; then norm_dev = |out|^2
+// out = K^T K x = A^T A x - div grad x (with_grad) or A^T A x ; then norm_dev = |out|^2
 hipError_t launch_power_step(const pyhst_plan &p, const float *x, float *out, float *tmp_sino, double *partials,
-                             int n_part, double *norm_dev, hipStream_t st)
+                             int n_part, double *norm_dev, int with_grad, hipStream_t st)
 {
     const GeoDev &g = p.gd[0];
     const float s2 = (float)(g.s * g.s);
@@ -269,7 +291,7 @@ hipError_t launch_power_step(const pyhst_plan &p, const float *x, float *out, fl
     e = launch_backproject(p, tmp_sino, 0, out, s2, 0.0f, nullptr, st);
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)p.n_slices * g.ny * g.nx;
-    sub_divgrad_kernel<<<grid_for(n), 256, 0, st>>>(n, g.ny, g.nx, x, out);
+    if (with_grad) sub_divgrad_kernel<<<grid_for(n), 256, 0, st>>>(n, g.ny, g.nx, x, out);
     sumsq_partial_kernel<<<n_part, 256, 0, st>>>(n, out, partials);
     final_sum_kernel<<<1, 256, 0, st>>>(partials, n_part, nullptr, norm_dev);
     return hipGetLastError();

@@ -1,7 +1,8 @@
 // reconstruct_slices: the whole path for a batch of slices.
-//   FBP   : (normalise + weight + ramp filter) -> backprojection      (section 2.3)
-//   TV_CP : eq. (3) by Chambolle-Pock with K = [A; grad]              (section 3.1)
-// Both are plain launch sequences on one stream, so the sequence can be
+//   FBP        : (normalise + weight + ramp filter) -> backprojection      (section 2.3)
+//   TV_CP      : eq. (3) by Chambolle-Pock with K = [A; grad]              (section 3.1)
+//   ISTA/FISTA : eq. (3) by gradient step + TV proximal map, the solvers section 3.1 names
+// Each is a plain launch sequence on one stream, so the sequence can be
 // captured into a HIP graph (use_graph) and replayed without host work.
 #include <cmath>
 #include <cstring>
@@ -34,6 +35,32 @@ CpLayout cp_layout(const pyhst_plan &p, const pyhst_recon_args &a)
     L.q2 = take(ni * 4);
     L.p = take(ns * 4);
     L.tmp = take(ns * 4);
+    L.partials = take(sizeof(double) * 1024);
+    L.energy = take(sizeof(float) * (size_t)std::max(1, a.n_iter));
+    L.norm = take(sizeof(double) * 2);
+    L.total = o;
+    return L;
+}
+
+struct FiLayout {
+    size_t y, r, z, xb, prox, partials, energy, norm, total;
+};
+
+FiLayout fista_layout(const pyhst_plan &p, const pyhst_recon_args &a)
+{
+    FiLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = align256(o + bytes);
+        return r;
+    };
+    const size_t ni = (size_t)p.img_elems, ns = (size_t)p.sino_elems;
+    L.y = a.raw ? take(ns * 4) : (size_t)-1;
+    L.r = take(ns * 4);
+    L.z = take(ni * 4);
+    L.xb = take(ni * 4);
+    L.prox = take(3 * ni * 4);
     L.partials = take(sizeof(double) * 1024);
     L.energy = take(sizeof(float) * (size_t)std::max(1, a.n_iter));
     L.norm = take(sizeof(double) * 2);
@@ -95,19 +122,78 @@ int enqueue_cp(const pyhst_plan &p, const pyhst_recon_args &a, const CpLayout &L
     return PYHST_OK;
 }
 
-// |[A; grad]| by power iteration on K^T K (synchronises the stream once).
-int estimate_opnorm(const pyhst_plan &p, const pyhst_recon_args &a, const CpLayout &L, hipStream_t st, double *out)
+// ISTA / FISTA (Beck & Teboulle 2009) with step 1/La, La = op_norm^2:
+//   r = A z - y                       (projector, residual epilogue)
+//   z <- z - (s^2/La) B r             (backprojector accumulating into z: the gradient step, in place)
+//   x_k = prox_{(lambda/La) TV}(z)    (tv_prox, n_inner dual iterations from zero)
+//   ISTA: z is x itself; FISTA: z = x_k + m_k (x_k - x_{k-1}) with the t_k sequence
+// The iterates alternate between out and one work buffer; the last one is copied to out if needed.
+int enqueue_fista(const pyhst_plan &p, const pyhst_recon_args &a, const FiLayout &L, double op_norm, hipStream_t st)
 {
     unsigned char *w = (unsigned char *)a.work;
-    float *x = (float *)(w + L.xbar), *y = (float *)(w + L.q1);
-    float *tmp = (float *)(w + L.tmp);
-    double *partials = (double *)(w + L.partials), *nrm = (double *)(w + L.norm);
+    const bool fast = a.method == PYHST_FISTA;
+    const float *y = a.raw ? (const float *)(w + L.y) : a.sino;
+    float *r = (float *)(w + L.r), *z = (float *)(w + L.z);
+    float *xa = a.out, *xb = (float *)(w + L.xb), *prox = (float *)(w + L.prox);
+    double *partials = (double *)(w + L.partials);
+    float *edev = (float *)(w + L.energy);
+    const GeoDev &g = p.gd[0];
+    const int64_t ni = p.img_elems;
+    const double La = op_norm * op_norm;
+    const float s2 = (float)(g.s * g.s);
+    const float step = (float)(-(double)s2 / La);
+    const float plam = (float)((double)a.lambda / La);
+    hipError_t e;
+    if (a.raw) {
+        e = launch_normalize(p, a.raw, a.flats, a.flat_pos, a.n_flats, a.dark, a.eps, (float *)(w + L.y), st);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: normalize");
+    }
+    e = launch_fill(xa, ni, 0.0f, st);
+    if (e == hipSuccess && fast) e = launch_fill(z, ni, 0.0f, st);
+    if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: fill");
+    const int npart = energy_partials(p);
+    double t = 1.0;
+    for (int it = 0; it < a.n_iter; ++it) {
+        float *zin = fast ? z : xa;
+        CpDual res{r, y, 0.0f, 1};
+        e = launch_forward(p, zin, nullptr, 1.0f, &res, st);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: projector");
+        e = launch_backproject(p, r, 0, zin, step, 1.0f, nullptr, st);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: backprojector");
+        float *dst = fast ? xb : xa;
+        e = launch_tv_prox(p.n_slices, g.ny, g.nx, zin, dst, plam, a.n_inner, prox, st);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: tv prox");
+        if (fast) {
+            const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+            e = launch_momentum(z, xb, xa, ni, (float)((t - 1.0) / tn), st);
+            if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: momentum");
+            t = tn;
+            std::swap(xa, xb);   // xa = x_k
+        }
+        if (a.energy) {
+            e = launch_forward(p, xa, r, 1.0f, nullptr, st);
+            if (e == hipSuccess) e = launch_cp_energy(p, r, y, xa, a.lambda, partials, npart, edev + it, st);
+            if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: energy");
+        }
+    }
+    if (xa != a.out) {
+        e = launch_copy(a.out, xa, ni, st);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: copy");
+    }
+    return PYHST_OK;
+}
+
+// |[A; grad]| (with_grad) or |A| by power iteration on K^T K or A^T A (synchronises the stream once).
+// x, y: image-sized scratch; tmp: sinogram-sized scratch.
+int estimate_opnorm(const pyhst_plan &p, float *x, float *y, float *tmp, double *partials, double *nrm,
+                    int with_grad, hipStream_t st, double *out)
+{
     const int64_t ni = p.img_elems;
     // constant start: the leading eigenvector of K^T K (dominated by A^T A) is smooth and positive
     hipError_t e = launch_fill(x, ni, 1.0f, st);
     double sq = 0.0;
     for (int it = 0; it < 50 && e == hipSuccess; ++it) {
-        e = launch_power_step(p, x, y, tmp, partials, energy_partials(p), nrm, st);
+        e = launch_power_step(p, x, y, tmp, partials, energy_partials(p), nrm, with_grad, st);
         if (e == hipSuccess) e = launch_scale_by_inv(y, ni, nrm, st);
         std::swap(x, y);
     }
@@ -126,18 +212,26 @@ extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hip
 {
     if (!pc || !a) return fail(PYHST_EARG, "reconstruct_slices: NULL argument");
     pyhst_plan &p = const_cast<pyhst_plan &>(*pc);
-    if (a->method != PYHST_FBP && a->method != PYHST_TV_CP) return fail(PYHST_EARG, "reconstruct_slices: bad method");
+    if (a->method != PYHST_FBP && a->method != PYHST_TV_CP && a->method != PYHST_ISTA && a->method != PYHST_FISTA)
+        return fail(PYHST_EARG, "reconstruct_slices: bad method");
     if (!a->raw && !a->sino) return fail(PYHST_EARG, "reconstruct_slices: need raw or sino");
     const bool cp = a->method == PYHST_TV_CP;
-    if (cp) {
+    const bool fi = a->method == PYHST_ISTA || a->method == PYHST_FISTA;
+    const bool iterative = cp || fi;
+    if (iterative) {
         if (!p.uniform) return fail(PYHST_EARG, "reconstruct_slices: TV needs a uniform plan");
         if (a->n_iter < 0 || !(a->lambda >= 0.0f)) return fail(PYHST_EARG, "reconstruct_slices: bad n_iter/lambda");
+        if (fi && a->n_inner < 0) return fail(PYHST_EARG, "reconstruct_slices: bad n_inner");
     }
     CpLayout L{};
+    FiLayout F{};
     size_t need;
     if (cp) {
         L = cp_layout(p, *a);
         need = L.total;
+    } else if (fi) {
+        F = fista_layout(p, *a);
+        need = F.total;
     } else {
         need = fbp_work(p);
     }
@@ -159,26 +253,33 @@ extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hip
     }
 
     double op_norm = a->op_norm;
-    if (cp && !(op_norm > 0.0)) {
-        int rc = estimate_opnorm(p, *a, L, st, &op_norm);
+    if (iterative && !(op_norm > 0.0)) {
+        unsigned char *w = (unsigned char *)a->work;
+        int rc = cp ? estimate_opnorm(p, (float *)(w + L.xbar), (float *)(w + L.q1), (float *)(w + L.tmp),
+                                      (double *)(w + L.partials), (double *)(w + L.norm), 1, st, &op_norm)
+                    : estimate_opnorm(p, (float *)(w + F.z), (float *)(w + F.xb), (float *)(w + F.r),
+                                      (double *)(w + F.partials), (double *)(w + F.norm), 0, st, &op_norm);
         if (rc) return rc;
         a->op_norm = op_norm;   // report the estimate to the caller
     }
 
     // graphs are captured on the caller's stream; the legacy null stream cannot be captured
-    const bool graphable = a->use_graph && !(cp && a->energy) && st != nullptr;
+    const bool graphable = a->use_graph && !(iterative && a->energy) && st != nullptr;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (graphable) {
         hipError_t e = hipStreamIsCapturing(st, &cs);
         if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: hipStreamIsCapturing");
     }
-    auto enqueue = [&]() { return cp ? enqueue_cp(p, *a, L, op_norm, st) : enqueue_fbp(p, *a, st); };
+    auto enqueue = [&]() {
+        return cp ? enqueue_cp(p, *a, L, op_norm, st) : fi ? enqueue_fista(p, *a, F, op_norm, st) : enqueue_fbp(p, *a, st);
+    };
 
     if (graphable && cs == hipStreamCaptureStatusNone) {
         std::vector<uint64_t> key = {(uint64_t)a->method, (uint64_t)(uintptr_t)a->raw, (uint64_t)(uintptr_t)a->sino,
                                      (uint64_t)(uintptr_t)a->flats, (uint64_t)(uintptr_t)a->dark,
                                      (uint64_t)(uintptr_t)a->out, (uint64_t)(uintptr_t)a->work,
-                                     (uint64_t)a->n_flats, (uint64_t)a->n_iter, (uint64_t)(uintptr_t)st};
+                                     (uint64_t)a->n_flats, (uint64_t)a->n_iter, (uint64_t)(uintptr_t)st,
+                                     (uint64_t)(fi ? a->n_inner : 0)};
         uint32_t lb, eb;
         std::memcpy(&lb, &a->lambda, 4);
         std::memcpy(&eb, &a->eps, 4);
@@ -218,9 +319,10 @@ extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hip
 
     int rc = enqueue();
     if (rc) return rc;
-    if (cp && a->energy && a->n_iter > 0) {
+    if (iterative && a->energy && a->n_iter > 0) {
         unsigned char *w = (unsigned char *)a->work;
-        hipError_t e = hipMemcpyAsync(a->energy, w + L.energy, sizeof(float) * a->n_iter, hipMemcpyDeviceToHost, st);
+        hipError_t e = hipMemcpyAsync(a->energy, w + (cp ? L.energy : F.energy), sizeof(float) * a->n_iter,
+                                      hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: energy copy");
         for (int i = 0; i < a->n_iter; ++i)

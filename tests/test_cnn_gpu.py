@@ -13,7 +13,11 @@ from paper_1306_1392_amd.cnn import UNet, init_params
 
 pytestmark = pytest.mark.gpu
 TOL = 2e-3        # one layer: FP32 vs FP64 accumulation flips isolated BF16 roundings
-TOL_NET = 2e-2    # whole network: those flips compound through up to 18 BF16 layers and back
+# Whole network: those flips compound through up to 18 BF16 layers and back, and a flipped
+# max-pool choice moves a whole gradient entry.  The oracle itself, switched from FP64 to FP32
+# accumulation with everything else equal, moves its deepest weight gradients by up to 2.1 %
+# (32 base channels, 4 levels, this test's inputs); the bar is about twice that spread.
+TOL_NET = 5e-2
 
 
 def rel(a, b):

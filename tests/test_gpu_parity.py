@@ -268,3 +268,60 @@ def test_cp_identity_limit_matches_prox(dev, gen):
     yy, xx = np.mgrid[0:N, 0:N]
     inside = (xx - (N - 1) / 2) ** 2 + (yy - (N - 1) / 2) ** 2 < (0.4 * N / 2) ** 2
     assert abs(x[inside].mean() - 1.0) < 0.03
+
+
+# --------------------------------------------------------------------------- ISTA / FISTA (section 3.1)
+@pytest.fixture(scope="module")
+def fista_problem(cp_problem):
+    d, g, og, _ = cp_problem
+    La = oracle.opnorm(og, synth.rng_for(3, 9, 2).standard_normal((og.n_y, og.n_x)), 200, with_grad=False) ** 2
+    return d, g, og, La
+
+
+@pytest.mark.parametrize("method", ["ista", "fista"])
+@pytest.mark.parametrize("k,lam", [(1, 1.0), (10, 1.0), (100, 1.0), (100, 0.01)])
+def test_fista_iterates_parity(dev, fista_problem, method, k, lam):
+    d, g, og, La = fista_problem
+    fast = method == "fista"
+    y = d["y"][None].contiguous().to(dev)
+    x = ph.reconstruct_slices(ph.Plan(g), sino=y, method=ph.FISTA if fast else ph.ISTA, lam=lam, n_iter=k,
+                              op_norm=math.sqrt(La), n_inner=20)
+    ref = oracle.fista_tv(d["y"].numpy(), og, lam, k, La, 20, fast=fast)
+    assert rel(x[0], ref) <= TOL_PIPE, (method, k, lam, rel(x[0], ref))
+
+
+def test_fista_energy_graph_and_opnorm(dev, fista_problem):
+    d, g, og, La = fista_problem
+    plan = ph.Plan(g)
+    y = d["y"][None].contiguous().to(dev)
+    x, E = ph.reconstruct_slices(plan, sino=y, method=ph.FISTA, lam=1.0, n_iter=30, op_norm=math.sqrt(La),
+                                 n_inner=10, energy=True)
+    xr, Er = oracle.fista_tv(d["y"].numpy(), og, 1.0, 30, La, 10, fast=True, energy=True)
+    np.testing.assert_allclose(E, Er, rtol=1e-4)
+    assert rel(x[0], xr) <= TOL_PIPE
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for _ in range(3):
+        with torch.cuda.stream(side):
+            xg = ph.reconstruct_slices(plan, sino=y, method=ph.FISTA, lam=1.0, n_iter=30, op_norm=math.sqrt(La),
+                                       n_inner=10, use_graph=True)
+        side.synchronize()
+        assert torch.equal(xg, x)
+    # op_norm <= 0: 1.02 |A| from the GPU power iteration on A^T A
+    ph.reconstruct_slices(plan, sino=y, method=ph.ISTA, lam=1.0, n_iter=1, op_norm=0.0, n_inner=10)
+    assert abs(plan.last_op_norm / (1.02 * math.sqrt(La)) - 1) < 1e-3
+
+
+def test_fista_beats_ista_and_recovers_disc(dev):
+    """The paper's claim (section 3.1): FISTA converges faster than ISTA; both reach the disc."""
+    N = 64
+    g = ph.Geometry(N, N, N, synth.uniform_angles(48), (N - 1) / 2)
+    y = synth.ellipse_sinogram(synth.disc_params(0.5, 1.0), g.angles, N, g.axis_pos, N).float()
+    y = y[None].contiguous().to(dev)
+    plan = ph.Plan(g)
+    xf, Ef = ph.reconstruct_slices(plan, sino=y, method=ph.FISTA, lam=0.5, n_iter=150, n_inner=10, energy=True)
+    xi, Ei = ph.reconstruct_slices(plan, sino=y, method=ph.ISTA, lam=0.5, n_iter=150, n_inner=10, energy=True)
+    assert Ef[-1] < Ei[-1] and Ef[30] < Ei[30]
+    yy, xx = np.mgrid[0:N, 0:N]
+    inside = (xx - (N - 1) / 2) ** 2 + (yy - (N - 1) / 2) ** 2 < (0.4 * N / 2) ** 2
+    assert abs(xf[0].cpu().numpy()[inside].mean() - 1.0) < 0.03
