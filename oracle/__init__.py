@@ -332,3 +332,29 @@ def fista_tv(y, g: Geom | None, lam: float, n_iter: int, lipschitz: float, n_inn
         lib().or_fista_tv(int(fast), 0, g.n_x, g.n_y, g.K, g.n_det, _p(g.angles), g.axis, _p(g.shifts),
                           g.pixel_size, _p(y), lam, n_iter, lipschitz, n_inner, _p(x), _p(E))
     return (x, E[:n_iter]) if energy else x
+
+
+# --------------------------------------------------------------------------- beta selection (section 3.1)
+def drop_angle(g: Geom, k: int) -> Geom:
+    """The geometry with projection k removed (the leave-one-angle-out reconstruction)."""
+    keep = np.arange(g.K) != k
+    return Geom(g.n_x, g.n_y, g.n_det, g.angles[keep], g.axis,
+                None if g.shifts is None else g.shifts[keep], g.scan, g.pixel_size, g.ha_overlap)
+
+
+def cv_error(x, y, g: Geom, k: int) -> float:
+    """Cross-validation estimator of section 3.1 for one excluded projection k: the squared distance
+    |(A x)_k - y_k|^2 between the projection at angle k of a reconstruction x (made without
+    projection k) and the measured row y_k.  x [n_y][n_x]; y [K][n_det] (the full data)."""
+    one = Geom(g.n_x, g.n_y, g.n_det, g.angles[k:k + 1], g.axis,
+               None if g.shifts is None else g.shifts[k:k + 1], g.scan, g.pixel_size, g.ha_overlap)
+    row = forward_project(x, one)[0]
+    d = row - _f64(y)[k]
+    return float(np.dot(d, d))
+
+
+def e_cohe(x_beta, x_zero) -> float:
+    """Decoherence estimator of section 3.1: the cosine between I(beta) - I(0+) and I(beta)."""
+    a = _f64(x_beta).ravel()
+    d = a - _f64(x_zero).ravel()
+    return float(np.dot(d, a) / (np.linalg.norm(d) * np.linalg.norm(a)))

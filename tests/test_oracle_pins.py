@@ -500,3 +500,40 @@ def test_fista_lyapunov_function_decreases():
         V.append(t * t * (0.5 * np.sum((A @ X[k] - y) ** 2) - Fs) + 0.5 * La * np.sum(u * u))
         t = 0.5 * (1 + math.sqrt(1 + 4 * t * t))
     assert np.all(np.diff(V) <= 1e-10 * V[0])
+
+
+# --------------------------------------------------------------------------- beta selection (section 3.1)
+def test_cv_error_is_the_excluded_row_of_the_projection_matrix():
+    """|(A x)_k - y_k|^2 with (A x)_k from the explicit interpolation matrix's rows of projection k."""
+    g = Geom(8, 8, 13, synth.uniform_angles(7), 6.1, shifts=np.linspace(-0.4, 0.2, 7), pixel_size=0.8)
+    A = lerp_matrix(g) * 0.64
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal(64)
+    y = rng.standard_normal((g.K, g.n_det))
+    for k in (0, 3, 6):
+        ref = np.sum((A[k * g.n_det:(k + 1) * g.n_det] @ x - y[k]) ** 2)
+        assert abs(oracle.cv_error(x.reshape(8, 8), y, g, k) / ref - 1) < 1e-12
+    gd = oracle.drop_angle(g, 3)
+    assert gd.K == 6 and not np.any(gd.angles == g.angles[3]) and np.all(gd.shifts == np.delete(g.shifts, 3))
+
+
+def test_cv_error_vanishes_on_consistent_data():
+    """Data that the image explains exactly (y = A x): zero cross-validation error at every angle."""
+    g = Geom(10, 10, 16, synth.uniform_angles(9), 7.3)
+    x = np.random.default_rng(32).random((10, 10))
+    y = oracle.forward_project(x, g)
+    assert max(oracle.cv_error(x, y, g, k) for k in range(g.K)) < 1e-24
+
+
+def test_e_cohe_values():
+    """cos(I(beta) - I(0+), I(beta)): 1 when I(0+) = 0; 0 when the removed part is orthogonal to I(beta);
+    -1 when I(0+) = 2 I(beta); -1/sqrt(2) for I(beta) = e1 + e2, I(0+) = e1 + 2 e2; invariant to a common
+    positive scale."""
+    e1, e2 = np.eye(4)[0], np.eye(4)[1]
+    assert abs(oracle.e_cohe(e1 + e2, np.zeros(4)) - 1) < 1e-15
+    assert abs(oracle.e_cohe(e1, e1 + e2)) < 1e-15
+    assert abs(oracle.e_cohe(e1, 2 * e1) + 1) < 1e-15
+    assert abs(oracle.e_cohe(e1 + e2, e1 + 2 * e2) + 1 / math.sqrt(2)) < 1e-15
+    rng = np.random.default_rng(33)
+    a, b = rng.standard_normal((2, 6, 6))
+    assert abs(oracle.e_cohe(3 * a, 3 * b) - oracle.e_cohe(a, b)) < 1e-14
