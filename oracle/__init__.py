@@ -58,6 +58,8 @@ def lib():
         P = ctypes.POINTER(ctypes.c_double)
         i, d = ctypes.c_int, ctypes.c_double
         L.or_normalize.argtypes = [i, i, i, P, i, P, P, P, d, P]
+        L.or_normalize_hotspot.argtypes = [i, i, i, P, i, P, P, P, d, d, P]
+        L.or_ring_filter.argtypes = [i, i, P, P, i]
         L.or_ramp_filter.argtypes = [i, i, P, P, P]
         L.or_angle_weights.argtypes = [i, P, d, d, P]
         L.or_backproject.argtypes = [i, i, i, i, P, d, P, d, P, P]
@@ -125,6 +127,41 @@ def normalize(raw, flats, flat_pos, dark, eps: float = 1e-6) -> np.ndarray:
     out = np.empty((R, K, nb))
     lib().or_normalize(K, R, nb, _p(raw), flats.shape[0], _p(flats), _p(fp), _p(dark), eps, _p(out))
     return out
+
+
+def normalize_hotspot(raw, flats, flat_pos, dark, thr: float, eps: float = 1e-6) -> np.ndarray:
+    """normalize() with the hot-spot median filter on the flat-field-corrected transmission:
+    a pixel exceeding its 3x3 neighbours' median by more than thr takes that median."""
+    raw, flats, dark = _f64(raw), _f64(flats), _f64(dark)
+    fp = _f64(np.asarray(flat_pos))
+    K, R, nb = raw.shape
+    out = np.empty((R, K, nb))
+    lib().or_normalize_hotspot(K, R, nb, _p(raw), flats.shape[0], _p(flats), _p(fp), _p(dark), eps, thr, _p(out))
+    return out
+
+
+def ring_filter(sino, width: int, obj=None) -> np.ndarray:
+    """Ring-artifact filter of each sinogram [S][K][L] (or [K][L]): subtract the high-pass part
+    (signal minus its (2 width + 1)-bin moving average) of the angle-averaged signal of
+    sino - obj.  Returns a new array."""
+    p = np.array(_f64(sino), copy=True)
+    squeeze = p.ndim == 2
+    if squeeze:
+        p = p[None]
+    o = None if obj is None else _f64(obj).reshape(p.shape)
+    for i in range(p.shape[0]):
+        pi = np.ascontiguousarray(p[i])
+        oi = None if o is None else np.ascontiguousarray(o[i])
+        lib().or_ring_filter(pi.shape[0], pi.shape[1], _p(pi), _p(oi), int(width))
+        p[i] = pi
+    return p[0] if squeeze else p
+
+
+def ring_object(sino, g: Geom, threshold: float) -> np.ndarray:
+    """Projection A(x [x > threshold]) of the thresholded FBP of sino [K][L] (the strongly absorbing
+    part of the object, removed from the data before the ring filter's average)."""
+    x = fbp(sino, g)
+    return forward_project(np.where(x > threshold, x, 0.0), g)
 
 
 # --------------------------------------------------------------------------- weights

@@ -80,6 +80,115 @@ void or_normalize(int K, int R, int nb, const double *raw, int n_flats, const do
 }
 
 /* ---------------------------------------------------------------------------
+ * Hot-spot removal (section 2.3, processing pipe): after the flat-field
+ * correction t = (I - D)/(F_k - D), a pixel whose neighbours' median is below
+ * t by more than thr is replaced by that median.  Neighbours: the up to 8
+ * pixels of the 3x3 window of the same radiograph (rows r +- 1 of the rows
+ * given, bins j +- 1), taken before any replacement; the median of an even
+ * count is the mean of the two middle values.  Dead pixels (F_k - D <= 0)
+ * count as t = 1 and stay p = 0.  Then p = -ln(max(t, eps)) as above.
+ * raw: [K][R][nb], out: [R][K][nb].
+ * ------------------------------------------------------------------------- */
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+void or_normalize_hotspot(int K, int R, int nb, const double *raw, int n_flats, const double *flats,
+                          const double *flat_pos, const double *dark, double eps, double thr, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < K; ++k) {
+        int i0 = 0, i1 = 0;
+        double a = 0.0;
+        if (n_flats > 1) {
+            if (k <= flat_pos[0]) {
+                i0 = i1 = 0;
+            } else if (k >= flat_pos[n_flats - 1]) {
+                i0 = i1 = n_flats - 1;
+            } else {
+                int i = 0;
+                while (i + 1 < n_flats && !(k < flat_pos[i + 1])) ++i;
+                i0 = i;
+                i1 = i + 1;
+                a = (k - flat_pos[i0]) / (flat_pos[i1] - flat_pos[i0]);
+            }
+        }
+        double *t = (double *)malloc(sizeof(double) * (size_t)R * nb);
+        char *dead = (char *)malloc((size_t)R * nb);
+        for (int r = 0; r < R; ++r)
+            for (int j = 0; j < nb; ++j) {
+                size_t o = (size_t)r * nb + j;
+                double d = dark[o];
+                double f = (1.0 - a) * flats[(size_t)i0 * R * nb + o] + a * flats[(size_t)i1 * R * nb + o];
+                dead[o] = !(f - d > 0.0);
+                t[o] = dead[o] ? 1.0 : (raw[(size_t)k * R * nb + o] - d) / (f - d);
+            }
+        for (int r = 0; r < R; ++r)
+            for (int j = 0; j < nb; ++j) {
+                size_t o = (size_t)r * nb + j;
+                double v = 0.0;
+                if (!dead[o]) {
+                    double nbv[8];
+                    int n = 0;
+                    for (int dr = -1; dr <= 1; ++dr)
+                        for (int dj = -1; dj <= 1; ++dj) {
+                            if (dr == 0 && dj == 0) continue;
+                            int rr = r + dr, jj = j + dj;
+                            if (rr < 0 || rr >= R || jj < 0 || jj >= nb) continue;
+                            nbv[n++] = t[(size_t)rr * nb + jj];
+                        }
+                    double tv = t[o];
+                    if (n > 0) {
+                        qsort(nbv, (size_t)n, sizeof(double), cmp_double);
+                        double med = (n & 1) ? nbv[n / 2] : 0.5 * (nbv[n / 2 - 1] + nbv[n / 2]);
+                        if (tv - med > thr) tv = med;
+                    }
+                    if (!(tv >= eps)) tv = eps;
+                    v = -log(tv);
+                }
+                out[((size_t)r * K + k) * nb + j] = v;
+            }
+        free(t);
+        free(dead);
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Ring-artifact filter (section 2.3): the sinogram is reduced to a 1-D signal
+ * by averaging over the projection angles, m[j] = (1/K) sum_k (p[k][j] - obj[k][j]),
+ * its high frequencies hp = m - (moving average of m over the 2w+1 bins
+ * j-w..j+w that exist) are extracted, and hp is subtracted from every row.
+ * obj (or NULL) is a sinogram of the object's strongly absorbing part (the
+ * projection of a thresholded first reconstruction), removed from the data
+ * before the average so that sharp object borders do not leak into hp.
+ * p: [K][L], modified in place.
+ * ------------------------------------------------------------------------- */
+void or_ring_filter(int K, int L, double *p, const double *obj, int w)
+{
+    double *m = (double *)calloc((size_t)L, sizeof(double));
+    double *hp = (double *)malloc(sizeof(double) * (size_t)L);
+    for (int k = 0; k < K; ++k)
+        for (int j = 0; j < L; ++j) m[j] += p[(size_t)k * L + j] - (obj ? obj[(size_t)k * L + j] : 0.0);
+    for (int j = 0; j < L; ++j) m[j] /= K;
+    for (int j = 0; j < L; ++j) {
+        double s = 0.0;
+        int n = 0;
+        for (int i = j - w; i <= j + w; ++i)
+            if (i >= 0 && i < L) {
+                s += m[i];
+                ++n;
+            }
+        hp[j] = m[j] - s / n;
+    }
+    for (int k = 0; k < K; ++k)
+        for (int j = 0; j < L; ++j) p[(size_t)k * L + j] -= hp[j];
+    free(m);
+    free(hp);
+}
+
+/* ---------------------------------------------------------------------------
  * Ram-Lak ramp filter at unit bin spacing (Kak & Slaney ch. 3):
  *   h[0] = 1/4, h[n odd] = -1/(pi^2 n^2), h[n even != 0] = 0.
  * Linear convolution restricted to [0, L), zero outside the row, each row
