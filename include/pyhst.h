@@ -130,6 +130,26 @@ int pyhst_plan_autotune(pyhst_plan *plan, const float *filt, float *img, int32_t
 int pyhst_normalize(const pyhst_plan *plan, const uint16_t *raw, const float *flats, const double *flat_pos,
                     int32_t n_flats, const float *dark, float eps, float *sino, hipStream_t stream);
 
+/* pyhst_normalize with the hot-spot filter of section 2.3 applied to the
+ * flat-field-corrected transmission t = (I - D)/(F_k - D) before the -log: a
+ * pixel whose 3x3 neighbours' median (the up to 8 neighbours inside the rows
+ * and bins given; mean of the middle two for an even count; taken before any
+ * replacement) is below t by more than threshold takes that median.  Dead
+ * pixels (F_k <= D) stay 0.  threshold < 0 or NaN -> PYHST_EARG. */
+int pyhst_normalize_hotspot(const pyhst_plan *plan, const uint16_t *raw, const float *flats, const double *flat_pos,
+                            int32_t n_flats, const float *dark, float eps, float threshold, float *sino,
+                            hipStream_t stream);
+
+/* Ring-artifact filter of section 2.3, in place on sinograms sino [R][K][n_det]
+ * of a uniform plan: per slice, m[j] = mean over projections of (sino - obj),
+ * hp = m - (mean of m over the bins j-width..j+width that exist), and hp[j] is
+ * subtracted from every row.  obj (same layout, or NULL) is the projection of
+ * the strongly absorbing part of the object (the thresholded first
+ * reconstruction), removed before the average so that its borders do not
+ * enter hp.  work: device scratch of >= 2 * R * n_det doubles. */
+int pyhst_ring_filter(const pyhst_plan *plan, float *sino, int32_t width, const float *obj, double *work,
+                      size_t work_doubles, hipStream_t stream);
+
 /* Ramp filter of FBP (section 2.3): for every row, half-acquisition weighting
  * and extension (360 degree half scans), then linear convolution on
  * [0, filt_len) with the Ram-Lak kernel h[0] = 1/4, h[odd n] = -1/(pi^2 n^2)
@@ -186,7 +206,10 @@ int tv_prox(int32_t n_slices, int32_t n_y, int32_t n_x, const float *in, float *
  * work/work_bytes: device scratch; call first with out == NULL to receive the
  * required size in *work_bytes (no work is enqueued).
  * use_graph != 0: the launches are captured once into a HIP graph kept by the
- * plan (keyed by every argument) and replayed on later identical calls. */
+ * plan (keyed by every argument) and replayed on later identical calls.
+ * Preprocessing (hot_spot, ring_width; uniform plans) runs before every method:
+ * the normalised sinogram then goes through a work buffer (the caller's sino is
+ * not modified) and FBP no longer fuses normalisation into the filter. */
 typedef struct {
     const uint16_t *raw;
     const float *sino;
@@ -205,6 +228,12 @@ typedef struct {
     size_t work_bytes;
     int32_t use_graph;
     int32_t n_inner;          /* ISTA/FISTA: dual iterations of each proximal map (>= 0) */
+    /* optional preprocessing of section 2.3 (zero = off) */
+    int32_t hot_spot;         /* raw input: hot-spot filter with hot_threshold (pyhst_normalize_hotspot) */
+    float hot_threshold;
+    int32_t ring_width;       /* > 0: ring filter of the sinograms (pyhst_ring_filter) with this half-width */
+    int32_t ring_object;      /* != 0: obj = A(x [x > ring_threshold]), x = FBP of the unfiltered data */
+    float ring_threshold;
 } pyhst_recon_args;
 
 int reconstruct_slices(const pyhst_plan *plan, pyhst_recon_args *a, hipStream_t stream);
@@ -214,6 +243,26 @@ int reconstruct_slices(const pyhst_plan *plan, pyhst_recon_args *a, hipStream_t 
  * workgroup per slice).  Used to send slices whose corrected reconstruction
  * does not explain the data to the TV-regularised mode. */
 int pyhst_slice_residual(const pyhst_plan *plan, const float *ax, const float *y, float *rel, hipStream_t stream);
+
+/* Choice of the regularisation weight beta of eq. (3) (section 3.1, the
+ * estimators evaluated after reconstructing at several beta):
+ *
+ * Cross-validation estimator for one excluded projection k: err[s] =
+ * |(A x_s)_k - y_s,k|^2, the squared distance between the projection at angle
+ * k of reconstruction x_s (made from the data without projection k, on a plan
+ * of the same image size) and the measured row k.  plan: the full plan (all
+ * projections; uniform), which supplies angle k, its axis shift and the
+ * layout of y [packed K x n_det].  x [packed n_y x n_x]; row: device scratch of
+ * n_slices * n_det floats (receives (A x)_k - y_k); err: device [n_slices].
+ * k outside [0, K) -> PYHST_EARG.  FP64 accumulation of the squares. */
+int pyhst_cv_error(const pyhst_plan *plan, const float *x, const float *y, int32_t k, float *row, float *err,
+                   hipStream_t stream);
+
+/* Decoherence estimator E_cohe of section 3.1: e[s] = cos(x_beta - x_zero,
+ * x_beta) per slice, where x_zero is the reconstruction at a very small beta
+ * (FP64 sums; 0 when either vector is zero).  Images [packed n_y x n_x];
+ * e: device [n_slices]. */
+int pyhst_decoherence(const pyhst_plan *plan, const float *x_beta, const float *x_zero, float *e, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Learned sparse-angle corrector (not part of the paper, whose learned prior

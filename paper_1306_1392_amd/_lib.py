@@ -19,7 +19,8 @@ EXPORTS = ["pyhst_plan_create", "pyhst_plan_destroy", "pyhst_plan_slice_info", "
            "forward_project", "tv_prox", "reconstruct_slices", "pyhst_microbench", "pyhst_strerror",
            "pyhst_last_error", "pyhst_unet_create", "pyhst_unet_destroy", "pyhst_unet_num_params",
            "pyhst_unet_set_params", "pyhst_unet_get_params", "pyhst_unet_get_grads", "pyhst_unet_forward",
-           "pyhst_unet_backward", "pyhst_unet_adam", "pyhst_unet_train_step", "pyhst_plan_autotune", "pyhst_slice_residual", "pyhst_unet_tensor"]
+           "pyhst_unet_backward", "pyhst_unet_adam", "pyhst_unet_train_step", "pyhst_plan_autotune", "pyhst_slice_residual", "pyhst_unet_tensor",
+           "pyhst_cv_error", "pyhst_decoherence", "pyhst_normalize_hotspot", "pyhst_ring_filter"]
 
 
 class Geom(ctypes.Structure):
@@ -40,7 +41,9 @@ class ReconArgs(ctypes.Structure):
                 ("n_flats", c_int32), ("dark", c_void_p), ("eps", c_float), ("method", c_int32),
                 ("lambda_", c_float), ("n_iter", c_int32), ("op_norm", c_double),
                 ("energy", ctypes.POINTER(c_float)), ("out", c_void_p), ("work", c_void_p),
-                ("work_bytes", c_size_t), ("use_graph", c_int32), ("n_inner", c_int32)]
+                ("work_bytes", c_size_t), ("use_graph", c_int32), ("n_inner", c_int32),
+                ("hot_spot", c_int32), ("hot_threshold", c_float), ("ring_width", c_int32),
+                ("ring_object", c_int32), ("ring_threshold", c_float)]
 
 
 _lib = None
@@ -81,6 +84,10 @@ def lib(path: str = LIB_PATH):
     L.pyhst_unet_train_step.argtypes = [P, P, P, c_int32, c_float, P, P]
     L.pyhst_plan_autotune.argtypes = [P, P, P, c_int32, ctypes.POINTER(c_float), P]
     L.pyhst_slice_residual.argtypes = [P, P, P, P, P]
+    L.pyhst_cv_error.argtypes = [P, P, P, c_int32, P, P, P]
+    L.pyhst_normalize_hotspot.argtypes = [P, P, P, ctypes.POINTER(c_double), c_int32, P, c_float, c_float, P, P]
+    L.pyhst_ring_filter.argtypes = [P, P, c_int32, P, P, c_size_t, P]
+    L.pyhst_decoherence.argtypes = [P, P, P, P, P]
     L.pyhst_unet_tensor.argtypes = [P, c_int32, c_int32, c_int32, P, c_int64, P]
     L.pyhst_strerror.argtypes = [c_int32]
     L.pyhst_strerror.restype = ctypes.c_char_p

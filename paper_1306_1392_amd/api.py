@@ -204,10 +204,49 @@ def tv_prox(x, lam: float, n_inner: int, out=None, work=None, stream=None):
     return out
 
 
+def _set_pre(a, hot_threshold, ring_width, ring_object_threshold):
+    """Optional preprocessing (section 2.3): hot-spot filter threshold (None = off), ring filter half-width
+    (0 = off) and the threshold of the object removed before the ring filter's average (None = off)."""
+    a.hot_spot = int(hot_threshold is not None)
+    a.hot_threshold = float(hot_threshold) if hot_threshold is not None else 0.0
+    a.ring_width = int(ring_width)
+    a.ring_object = int(ring_object_threshold is not None)
+    a.ring_threshold = float(ring_object_threshold) if ring_object_threshold is not None else 0.0
+
+
+def normalize_hotspot(plan: Plan, raw, flats, flat_pos, dark, threshold: float, eps: float = 1e-6, out=None,
+                      stream=None):
+    """normalize() with the hot-spot median filter (section 2.3) on the flat-field-corrected data."""
+    _need(raw, plan.sino_elems, "raw", torch.uint16)
+    fp = np.ascontiguousarray(flat_pos, dtype=np.float64)
+    if out is None:
+        out = torch.empty(plan.sino_shape(), device=raw.device, dtype=torch.float32)
+    _need(out, plan.sino_elems, "out")
+    check(_lib.lib().pyhst_normalize_hotspot(plan.handle, _ptr(raw), _ptr(flats),
+                                             fp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(fp.shape[0]),
+                                             _ptr(dark), float(eps), float(threshold), _ptr(out), _stream(stream)),
+          "pyhst_normalize_hotspot")
+    return out
+
+
+def ring_filter(plan: Plan, sino, width: int, obj=None, work=None, stream=None):
+    """Ring-artifact filter (section 2.3) of the sinograms, in place; returns sino."""
+    _need(sino, plan.sino_elems, "sino")
+    if obj is not None:
+        _need(obj, plan.sino_elems, "obj")
+    n = 2 * plan.n_slices * plan.geoms[0].n_det
+    if work is None:
+        work = torch.empty(n, device=sino.device, dtype=torch.float64)
+    check(_lib.lib().pyhst_ring_filter(plan.handle, _ptr(sino), int(width), _ptr(obj), _ptr(work), work.numel(),
+                                       _stream(stream)), "pyhst_ring_filter")
+    return sino
+
+
 def reconstruct_slices(plan: Plan, *, raw=None, sino=None, flats=None, flat_pos=None, dark=None, eps: float = 1e-6,
                        method: int = FBP, lam: float = 0.0, n_iter: int = 0, op_norm: float = 0.0,
                        n_inner: int = 20, energy: bool = False, out=None, work=None, use_graph: bool = False,
-                       stream=None):
+                       hot_threshold: float | None = None, ring_width: int = 0,
+                       ring_object_threshold: float | None = None, stream=None):
     """Returns out (and the energy trace as a numpy array when energy=True).  op_norm is |[A; grad]| for
     TV_CP and |A| for ISTA/FISTA (<= 0: estimated on the GPU, then available as plan.last_op_norm)."""
     a = _lib.ReconArgs()
@@ -227,6 +266,7 @@ def reconstruct_slices(plan: Plan, *, raw=None, sino=None, flats=None, flat_pos=
     a.op_norm = float(op_norm)
     a.use_graph = int(bool(use_graph))
     a.n_inner = int(n_inner)
+    _set_pre(a, hot_threshold, ring_width, ring_object_threshold)
     if raw is not None:
         _need(raw, plan.sino_elems, "raw", torch.uint16)
         _need(flats, flats.numel(), "flats")
@@ -267,12 +307,40 @@ def slice_residual(plan: Plan, ax, y, out=None, stream=None):
     return out
 
 
+def cv_error(plan: Plan, x, y, k: int, row=None, out=None, stream=None):
+    """Cross-validation estimator |(A x)_k - y_k|^2 per slice (device float [n_slices]); plan is the
+    full-data plan, x a reconstruction made without projection k."""
+    _need(x, plan.img_elems, "x")
+    _need(y, plan.sino_elems, "y")
+    nb = plan.geoms[0].n_det
+    if row is None:
+        row = torch.empty(plan.n_slices * nb, device=x.device, dtype=torch.float32)
+    _need(row, plan.n_slices * nb, "row")
+    if out is None:
+        out = torch.empty(plan.n_slices, device=x.device, dtype=torch.float32)
+    check(_lib.lib().pyhst_cv_error(plan.handle, _ptr(x), _ptr(y), int(k), _ptr(row), _ptr(out), _stream(stream)),
+          "pyhst_cv_error")
+    return out
+
+
+def decoherence(plan: Plan, x_beta, x_zero, out=None, stream=None):
+    """Decoherence estimator cos(x_beta - x_zero, x_beta) per slice (device float [n_slices])."""
+    _need(x_beta, plan.img_elems, "x_beta")
+    _need(x_zero, plan.img_elems, "x_zero")
+    if out is None:
+        out = torch.empty(plan.n_slices, device=x_beta.device, dtype=torch.float32)
+    check(_lib.lib().pyhst_decoherence(plan.handle, _ptr(x_beta), _ptr(x_zero), _ptr(out), _stream(stream)),
+          "pyhst_decoherence")
+    return out
+
+
 def work_bytes(plan: Plan, **kw) -> int:
     a = _lib.ReconArgs()
     a.raw = _ptr(kw.get("raw"))
     a.sino = _ptr(kw.get("sino"))
     a.method = int(kw.get("method", FBP))
     a.n_iter = int(kw.get("n_iter", 0))
+    _set_pre(a, kw.get("hot_threshold"), kw.get("ring_width", 0), kw.get("ring_object_threshold"))
     a.out = None
     check(_lib.lib().reconstruct_slices(plan.handle, ctypes.byref(a), None), "reconstruct_slices(query)")
     return a.work_bytes

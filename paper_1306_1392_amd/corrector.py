@@ -2,7 +2,7 @@
 
 x_hat = FBP(y) + UNet(FBP(y)); a slice whose corrected image does not explain
 its data (|A x_hat - y| / |y| above a threshold calibrated on validation data)
-is reconstructed by the TV-regularised mode (eq. (3), Chambolle-Pock) instead.
+is reconstructed by the TV-regularised mode (eq. (3), FISTA or Chambolle-Pock) instead.
 Every step runs in the HIP library (FBP, U-Net kernels, projector, residual,
 TV-CP); this module only sequences the calls.
 """
@@ -17,13 +17,15 @@ from .cnn import UNet
 
 class Corrector:
     def __init__(self, geometry: api.Geometry, batch: int, params, base: int = 32, levels: int = 4,
-                 tv_lambda: float = 0.01, tv_iters: int = 300, dc_threshold: float | None = None):
+                 tv_lambda: float = 0.01, tv_iters: int = 300, dc_threshold: float | None = None,
+                 tv_method: int = api.FISTA, tv_inner: int = 10):
         self.geo = geometry
         self.batch = batch
         self.plan = api.Plan(geometry, n_slices=batch)
         self.net = UNet(batch, geometry.n_y, geometry.n_x, base, levels)
         self.net.set_params(params)
         self.tv_lambda, self.tv_iters = tv_lambda, tv_iters
+        self.tv_method, self.tv_inner = tv_method, tv_inner
         self.dc_threshold = dc_threshold
         self.op_norm = 0.0
         self._tv_plans = {}
@@ -39,13 +41,13 @@ class Corrector:
         return xh, api.slice_residual(self.plan, ax, y)
 
     def tv(self, y):
-        """TV-CP reconstruction of the slices in y [n][K][nb]."""
+        """TV reconstruction (eq. (3); FISTA or Chambolle-Pock) of the slices in y [n][K][nb]."""
         n = y.shape[0]
         plan = self._tv_plans.get(n)
         if plan is None:
             plan = self._tv_plans[n] = api.Plan(self.geo, n_slices=n)
-        x = api.reconstruct_slices(plan, sino=y.contiguous(), method=api.TV_CP, lam=self.tv_lambda,
-                                   n_iter=self.tv_iters, op_norm=self.op_norm)
+        x = api.reconstruct_slices(plan, sino=y.contiguous(), method=self.tv_method, lam=self.tv_lambda,
+                                   n_iter=self.tv_iters, op_norm=self.op_norm, n_inner=self.tv_inner)
         self.op_norm = plan.last_op_norm
         return x
 

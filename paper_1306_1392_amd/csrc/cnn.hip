@@ -187,17 +187,38 @@ __global__ void head_bwd_data_kernel(const bf16_t *d, int C, const float *wh, co
 }
 
 // per-block partial sums over pixels of v[p][c] * (s ? s[p] : 1), channel c = threadIdx.x (< C)
+// part[blk][c] = sum over this block's pixel chunk of v[p][co + c] (times s[p] when s is given).
+// Thread t reads 8 channels (16 B) of one pixel per step: channel group t % G (G = C / 8), pixel
+// lane t / G; the pixel lanes' sums are then added in a fixed order through LDS.  C is a power of
+// two in [8, 2048]; cs and co are multiples of 8.
 __global__ __launch_bounds__(256) void chan_partial_kernel(const bf16_t *v, int cs, int co, int C, const float *s,
                                                            int64_t npix, int64_t chunk, float *part)
 {
+    __shared__ float red[256 * 8];
+    const int G = C >> 3;
+    const int lanes = G >= 256 ? 1 : 256 / G;
+    const int cg = threadIdx.x % G, pl = threadIdx.x / G;
     const int64_t p0 = blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        float acc = 0.0f;
-        for (int64_t p = p0; p < p1; ++p) {
-            const float x = bf2f(v[p * cs + co + c]);
-            acc = s ? fmaf(x, s[p], acc) : acc + x;
+    float acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
+    if (pl < lanes) {
+        for (int64_t p = p0 + pl; p < p1; p += lanes) {
+            const uint4 u = *(const uint4 *)(v + p * cs + co + 8 * cg);
+            const bf16_t *e = (const bf16_t *)&u;
+            const float w = s ? s[p] : 1.0f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] = fmaf(bf2f(e[q]), w, acc[q]);
         }
-        part[(int64_t)blockIdx.x * C + c] = acc;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red[threadIdx.x * 8 + q] = acc[q];
+    __syncthreads();
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        const int g = c >> 3, q = c & 7;
+        float t = 0.0f;
+        for (int l = 0; l < lanes; ++l) t += red[(l * G + g) * 8 + q];
+        part[(int64_t)blockIdx.x * C + c] = t;
     }
 }
 
@@ -211,26 +232,26 @@ __global__ __launch_bounds__(256) void dout_partial_kernel(const float *d, int64
     if (threadIdx.x == 0) part[blockIdx.x] = (float)s;
 }
 
-// dst[c] = sum over nb blocks of part[blk][c] (fixed order)
-__global__ void reduce_rows_kernel(const float *part, int nb, int C, float *dst)
+// dst[c] = sum over nb blocks of part[blk][c] (one workgroup per channel, fixed order)
+__global__ __launch_bounds__(256) void reduce_rows_kernel(const float *part, int nb, int C, float *dst)
 {
-    GRID_LOOP(c, C)
-    {
-        double s = 0.0;
-        for (int i = 0; i < nb; ++i) s += part[(int64_t)i * C + c];
-        dst[c] = (float)s;
-    }
+    __shared__ double sh[4];
+    const int c = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[(int64_t)i * C + c];
+    const double t = block_sum_d(acc, sh);
+    if (threadIdx.x == 0) dst[c] = (float)t;
 }
 
-// dst[n * M + m] = sum_s part[s][m][n]
+// dst[n * M + m] = sum_s part[s][m][n]  (consecutive threads read consecutive n)
 __global__ void reduce_splitk_T_kernel(const float *part, int splits, int M, int N, float *dst)
 {
     GRID_LOOP(i, (int64_t)M * N)
     {
-        const int n = (int)(i / M), m = (int)(i - (int64_t)n * M);
+        const int m = (int)(i / N), n = (int)(i - (int64_t)m * N);
         double s = 0.0;
-        for (int k = 0; k < splits; ++k) s += part[((int64_t)k * M + m) * N + n];
-        dst[i] = (float)s;
+        for (int k = 0; k < splits; ++k) s += part[(int64_t)k * M * N + i];
+        dst[(int64_t)n * M + m] = (float)s;
     }
 }
 
@@ -327,7 +348,7 @@ hipError_t chan_sum(const pyhst_unet &net, Act g, int C, const float *scale, flo
     const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, npix / 64));
     const int64_t chunk = (npix + nb - 1) / nb;
     chan_partial_kernel<<<nb, 256, 0, st>>>(g.p, g.cs, g.co, C, scale, npix, chunk, net.part);
-    reduce_rows_kernel<<<blocks_for(C), 256, 0, st>>>(net.part, nb, C, dst);
+    reduce_rows_kernel<<<C, 256, 0, st>>>(net.part, nb, C, dst);
     return hipGetLastError();
 }
 

@@ -211,6 +211,26 @@ struct Im2colT {
         if ((unsigned)y >= (unsigned)x.H || (unsigned)xx >= (unsigned)x.W) return zero8();
         return ld8(x.p + ((int64_t)(b * x.H + y) * x.W + xx) * x.cs + x.co + c.ch);
     }
+    // pixels k .. k+7: one division for the first, then the pixel walks along its row
+    __device__ void load8(const Ctx &c, int k, int kend, uint4 *v) const
+    {
+        const uint32_t k0 = (uint32_t)min(k, kend);
+        uint32_t b = fdiv(k0, fhw), r = k0 - b * fhw.d;
+        uint32_t y = fdiv(r, fw), xx = r - y * fw.d;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int yy = (int)y + c.dy, xs = (int)xx + c.dx;
+            const bool in = c.ok && k + i < kend && (unsigned)yy < (unsigned)x.H && (unsigned)xs < (unsigned)x.W;
+            v[i] = in ? ld8(x.p + ((int64_t)(b * x.H + yy) * x.W + xs) * x.cs + x.co + c.ch) : zero8();
+            if (++xx == (uint32_t)x.W) {
+                xx = 0;
+                if (++y == (uint32_t)x.H) {
+                    y = 0;
+                    ++b;
+                }
+            }
+        }
+    }
 };
 inline Im2colT im2col_t(Act x, int C) { return Im2colT{x, ilog2(C), make_fastdiv(x.H * x.W), make_fastdiv(x.W)}; }
 
@@ -226,6 +246,12 @@ struct PlainT {
     __device__ uint4 load(const Ctx &c, int k, int kend) const
     {
         return (c.ok && k < kend) ? ld8(x.p + (int64_t)k * x.cs + c.off) : zero8();
+    }
+    __device__ void load8(const Ctx &c, int k, int kend, uint4 *v) const
+    {
+        const bf16_t *q = x.p + (int64_t)k * x.cs + c.off;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (c.ok && k + i < kend) ? ld8(q + (int64_t)i * x.cs) : zero8();
     }
 };
 
@@ -257,15 +283,56 @@ struct UpGatherT {
         const uint32_t y = fdiv(r, fw), xx = r - y * fw.d;
         return ld8(dy.p + ((int64_t)(b * dy.H + 2 * y + c.ddy) * dy.W + 2 * xx + c.ddx) * dy.cs + dy.co + c.co);
     }
+    __device__ void load8(const Ctx &c, int k, int kend, uint4 *v) const
+    {
+        const uint32_t k0 = (uint32_t)min(k, kend);
+        const uint32_t h = fhw.d / fw.d, w = fw.d;
+        uint32_t b = fdiv(k0, fhw), r = k0 - b * fhw.d;
+        uint32_t y = fdiv(r, fw), xx = r - y * w;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            v[i] = (c.ok && k + i < kend)
+                       ? ld8(dy.p + ((int64_t)(b * dy.H + 2 * y + c.ddy) * dy.W + 2 * xx + c.ddx) * dy.cs + dy.co + c.co)
+                       : zero8();
+            if (++xx == w) {
+                xx = 0;
+                if (++y == h) {
+                    y = 0;
+                    ++b;
+                }
+            }
+        }
+    }
 };
 inline UpGatherT upgather_t(Act dy, int Cout)
 {
     return UpGatherT{dy, ilog2(Cout), make_fastdiv((dy.H >> 1) * (dy.W >> 1)), make_fastdiv(dy.W >> 1)};
 }
 
-// Register staging of one operand tile: SLOTS vectors of 8 BF16 per thread.
+// 8 x 8 transpose of 16-bit elements: out[q] element i = in[i] element q
+__device__ inline void transpose8(const uint4 *in, uint4 *out)
+{
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        uint32_t w[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const uint32_t a = ((const uint32_t *)&in[2 * d])[q >> 1], b = ((const uint32_t *)&in[2 * d + 1])[q >> 1];
+            w[d] = (q & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+        }
+        out[q] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+// Register staging of one operand tile, stored in LDS as [row][k] (k contiguous, stride LDK).
+//  VK loaders: SLOTS vectors of 8 consecutive k of one row per thread.
+//  Other loaders (vectors run along the rows): each of the first ROWS/8 * TK/8 threads loads an
+//  8-row x 8-k block as 8 vectors (one per k), transposes it in registers and stores 8 vectors.
+template <class L, int ROWS, bool VK = L::VK>
+struct Stager;
+
 template <class L, int ROWS>
-struct Stager {
+struct Stager<L, ROWS, true> {
     static constexpr int NV = ROWS * TK / 8;
     static constexpr int SLOTS = (NV + 255) / 256;
     typename L::Ctx ctx[SLOTS];
@@ -276,14 +343,8 @@ struct Stager {
 #pragma unroll
         for (int j = 0; j < SLOTS; ++j) {
             const int idx = threadIdx.x + 256 * j;
-            if constexpr (L::VK) {
-                row[j] = idx >> 2;
-                kl[j] = (idx & 3) * 8;
-            } else {
-                constexpr int R8 = ROWS / 8;
-                kl[j] = idx / R8;
-                row[j] = (idx - kl[j] * R8) * 8;
-            }
+            row[j] = idx >> 2;
+            kl[j] = (idx & 3) * 8;
             ctx[j] = ld.prep(row0 + row[j], idx < NV ? R : 0);
         }
     }
@@ -295,16 +356,37 @@ struct Stager {
     __device__ void store(bf16_t *s) const
     {
 #pragma unroll
-        for (int j = 0; j < SLOTS; ++j) {
-            if (threadIdx.x + 256 * j >= NV) continue;
-            if constexpr (L::VK) {
-                *(uint4 *)&s[row[j] * LDK + kl[j]] = v[j];
-            } else {
-                const bf16_t *e = (const bf16_t *)&v[j];
+        for (int j = 0; j < SLOTS; ++j)
+            if (threadIdx.x + 256 * j < NV) *(uint4 *)&s[row[j] * LDK + kl[j]] = v[j];
+    }
+};
+
+template <class L, int ROWS>
+struct Stager<L, ROWS, false> {
+    static constexpr int R8 = ROWS / 8, NBLK = R8 * (TK / 8);
+    static_assert(NBLK <= 256, "one 8x8 block per thread");
+    typename L::Ctx ctx;
+    uint4 v[8];
+    int row, kl;
+    bool act;
+    __device__ void prep(const L &ld, int row0, int R)
+    {
+        act = threadIdx.x < NBLK;
+        kl = (threadIdx.x / R8) * 8;
+        row = (threadIdx.x % R8) * 8;
+        ctx = ld.prep(row0 + row, act ? R : 0);
+    }
+    __device__ void load(const L &ld, int k0, int kend)
+    {
+        if (act) ld.load8(ctx, k0 + kl, kend, v);
+    }
+    __device__ void store(bf16_t *s) const
+    {
+        if (!act) return;
+        uint4 o[8];
+        transpose8(v, o);
 #pragma unroll
-                for (int q = 0; q < 8; ++q) s[(row[j] + q) * LDK + kl[j]] = e[q];
-            }
-        }
+        for (int q = 0; q < 8; ++q) *(uint4 *)&s[(row + q) * LDK + kl] = o[q];
     }
 };
 

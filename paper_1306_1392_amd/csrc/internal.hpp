@@ -119,6 +119,12 @@ struct CpDual {     // p = (p + sigma (alpha A xbar - y)) / (1 + sigma);  residu
 // launchers (return hipGetLastError())
 hipError_t launch_normalize(const pyhst_plan &p, const uint16_t *raw, const float *flats, const double *flat_pos,
                             int n_flats, const float *dark, float eps, float *sino, hipStream_t st);
+hipError_t launch_normalize_hotspot(const pyhst_plan &p, const uint16_t *raw, const float *flats,
+                                    const double *flat_pos, int n_flats, const float *dark, float eps, float thr,
+                                    float *sino, hipStream_t st);
+hipError_t launch_ring_filter(const pyhst_plan &p, float *sino, const float *obj, int width, double *work,
+                              hipStream_t st);
+hipError_t launch_threshold(float *dst, const float *src, int64_t n, float thr, hipStream_t st);
 hipError_t launch_filter(const pyhst_plan &p, const float *sino, const uint16_t *raw, const float *flats,
                          const double *flat_pos, int n_flats, const float *dark, float eps, float *filt,
                          hipStream_t st);
@@ -126,6 +132,8 @@ hipError_t launch_backproject(const pyhst_plan &p, const float *sino, int filter
                               float beta, const CpPrimal *cp, hipStream_t st);
 hipError_t launch_forward(const pyhst_plan &p, const float *img, float *sino, float alpha, const CpDual *cp,
                           hipStream_t st);
+hipError_t launch_forward_row(const pyhst_plan &p, const float *img, const float *y, int k, float *row,
+                              hipStream_t st);
 
 // TV / CP helpers (k_tv.hip); images are packed by the plan's img offsets when a plan is given,
 // otherwise a plain [S][ny][nx] stack.

@@ -77,6 +77,116 @@ __global__ __launch_bounds__(256) void normalize_kernel(const uint16_t *__restri
         dst[j] = norm_value((float)src[j], dk[j], f0[j], f1[j], a, eps);
 }
 
+// Hot-spot removal on the flat-field-corrected transmission (section 2.3): a pixel whose 3x3
+// neighbours' median (up to 8 neighbours of the same radiograph, mean of the middle two for an
+// even count) is below it by more than thr takes that median; then -log as above.  One thread per
+// pixel; the 9 transmissions are recomputed per thread (neighbours come from L1/L2).
+__device__ inline float transmission(const uint16_t *raw, const float *f0, const float *f1, const float *dk, float a,
+                                     int64_t o, bool &dead)
+{
+    const float d = dk[o];
+    const float den = ((1.0f - a) * f0[o] + a * f1[o]) - d;
+    dead = !(den > 0.0f);
+    return dead ? 1.0f : ((float)raw[o] - d) / den;
+}
+
+__device__ inline void cswap(float &a, float &b)
+{
+    const float lo = fminf(a, b), hi = fmaxf(a, b);
+    a = lo;
+    b = hi;
+}
+
+__global__ __launch_bounds__(256) void normalize_hotspot_kernel(const uint16_t *__restrict__ raw,
+                                                                const float *__restrict__ flats, FlatInfo fi,
+                                                                const float *__restrict__ dark, float eps, float thr,
+                                                                int K, int R, int nb, float *__restrict__ out)
+{
+    const int row = blockIdx.x;          // raw row order: k * R + r
+    const int k = row / R, r = row - k * R;
+    int i0, i1;
+    float a;
+    flat_interp(fi, k, i0, i1, a);
+    const uint16_t *img = raw + (int64_t)k * R * nb;      // radiograph k, [R][nb]
+    const float *f0 = flats + (int64_t)i0 * R * nb, *f1 = flats + (int64_t)i1 * R * nb;
+    float *dst = out + ((int64_t)r * K + k) * nb;
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+        bool dead;
+        float t = transmission(img, f0, f1, dark, a, (int64_t)r * nb + j, dead);
+        if (dead) {
+            dst[j] = 0.0f;
+            continue;
+        }
+        float v[8];
+        int n = 0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int dr = q / 3 - 1, dj = q % 3 - 1;
+            if (q == 4) continue;
+            const int rr = r + dr, jj = j + dj;
+            const bool in = rr >= 0 && rr < R && jj >= 0 && jj < nb;
+            bool dd;
+            const float tv = in ? transmission(img, f0, f1, dark, a, (int64_t)rr * nb + jj, dd) : INFINITY;
+            v[q < 4 ? q : q - 1] = tv;
+            n += in ? 1 : 0;
+        }
+        // sorting network for 8 values (absent neighbours are +inf and sort last)
+        cswap(v[0], v[1]); cswap(v[2], v[3]); cswap(v[4], v[5]); cswap(v[6], v[7]);
+        cswap(v[0], v[2]); cswap(v[1], v[3]); cswap(v[4], v[6]); cswap(v[5], v[7]);
+        cswap(v[1], v[2]); cswap(v[5], v[6]); cswap(v[0], v[4]); cswap(v[3], v[7]);
+        cswap(v[1], v[5]); cswap(v[2], v[6]);
+        cswap(v[1], v[4]); cswap(v[3], v[6]);
+        cswap(v[2], v[4]); cswap(v[3], v[5]);
+        cswap(v[3], v[4]);
+        float lo = v[0], hi = v[0];
+#pragma unroll
+        for (int q = 1; q < 8; ++q) {
+            if (q == (n - 1) / 2) lo = v[q];
+            if (q == n / 2) hi = v[q];
+        }
+        if (n > 0) {
+            const float med = (n & 1) ? hi : 0.5f * (lo + hi);
+            if (t - med > thr) t = med;
+        }
+        if (!(t >= eps)) t = eps;
+        dst[j] = -logf(t);
+    }
+}
+
+// Ring filter (section 2.3).  m[s][j] = mean_k (p - obj)[s][k][j] (FP64); one thread per bin.
+__global__ __launch_bounds__(256) void ring_mean_kernel(const float *__restrict__ p, const float *__restrict__ obj,
+                                                        int K, int L, double *__restrict__ m)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
+    if (j >= L) return;
+    const int64_t base = (int64_t)s * K * L + j;
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k) acc += (double)p[base + (int64_t)k * L] - (obj ? (double)obj[base + (int64_t)k * L] : 0.0);
+    m[(int64_t)s * L + j] = acc / K;
+}
+
+// hp[s][j] = m[j] - mean of m over the bins j-w..j+w that exist
+__global__ __launch_bounds__(256) void ring_highpass_kernel(const double *__restrict__ m, int L, int w,
+                                                            double *__restrict__ hp)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
+    if (j >= L) return;
+    const double *ms = m + (int64_t)s * L;
+    const int lo = max(0, j - w), hi = min(L - 1, j + w);
+    double acc = 0.0;
+    for (int i = lo; i <= hi; ++i) acc += ms[i];
+    hp[(int64_t)s * L + j] = ms[j] - acc / (hi - lo + 1);
+}
+
+// p[s][k][j] -= hp[s][j]
+__global__ __launch_bounds__(256) void ring_subtract_kernel(float *__restrict__ p, const double *__restrict__ hp,
+                                                            int K, int L)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, k = blockIdx.y, s = blockIdx.z;
+    if (j >= L) return;
+    p[((int64_t)s * K + k) * L + j] -= (float)hp[(int64_t)s * L + j];
+}
+
 __device__ void fft_forward(float2 *z, int P, int lg, const float2 *__restrict__ tw, int lgmax)
 {
     int h = P >> 1, lh = lg - 1;
@@ -220,6 +330,30 @@ FlatInfo make_flats(const double *pos, int n)
 }
 
 }  // namespace
+
+hipError_t launch_normalize_hotspot(const pyhst_plan &p, const uint16_t *raw, const float *flats,
+                                    const double *flat_pos, int n_flats, const float *dark, float eps, float thr,
+                                    float *sino, hipStream_t st)
+{
+    const GeoDev &g = p.gd[0];
+    const int R = p.n_slices;
+    normalize_hotspot_kernel<<<(unsigned)((int64_t)g.K * R), 256, 0, st>>>(
+        raw, flats, make_flats(flat_pos, n_flats), dark, eps, thr, g.K, R, g.nb, sino);
+    return hipGetLastError();
+}
+
+hipError_t launch_ring_filter(const pyhst_plan &p, float *sino, const float *obj, int width, double *work,
+                              hipStream_t st)
+{
+    const GeoDev &g = p.gd[0];
+    const int S = p.n_slices, K = g.K, L = g.nb;
+    double *m = work, *hp = work + (int64_t)S * L;
+    dim3 g2((L + 255) / 256, S);
+    ring_mean_kernel<<<g2, 256, 0, st>>>(sino, obj, K, L, m);
+    ring_highpass_kernel<<<g2, 256, 0, st>>>(m, L, width, hp);
+    ring_subtract_kernel<<<dim3((L + 255) / 256, K, S), 256, 0, st>>>(sino, hp, K, L);
+    return hipGetLastError();
+}
 
 hipError_t launch_normalize(const pyhst_plan &p, const uint16_t *raw, const float *flats, const double *flat_pos,
                             int n_flats, const float *dark, float eps, float *sino, hipStream_t st)

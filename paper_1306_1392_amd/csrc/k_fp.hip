@@ -20,14 +20,14 @@ namespace {
 
 template <int MODE>
 __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restrict__ img, float *__restrict__ out,
-                                                 float alpha, CpDual cp)
+                                                 float alpha, CpDual cp, int k0)
 {
     __shared__ float part[3][64];
     const int slice = blockIdx.z;
     const SliceDev sd = T.slc[slice];
     const GeoDev &g = T.geo[sd.g];
     const int K = g.K, nb = g.nb, nx = g.nx, ny = g.ny;
-    const int k = blockIdx.y;
+    const int k = blockIdx.y + k0;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int j = blockIdx.x * 64 + lane;
     if (k >= K || blockIdx.x * 64 >= nb) return;   // uniform over the workgroup
@@ -91,8 +91,10 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
         out[o] = v;
     } else if (MODE == 1) {
         cp.p[o] = (cp.p[o] + cp.sigma * (v - cp.y[o])) / (1.0f + cp.sigma);
-    } else {
+    } else if (MODE == 2) {
         cp.p[o] = v - cp.y[o];   // residual A x - y of the gradient step of ISTA/FISTA
+    } else {
+        cp.p[(int64_t)slice * nb + j] = v - cp.y[o];   // one projection's residual row per slice
     }
 }
 
@@ -105,13 +107,24 @@ hipError_t launch_forward(const pyhst_plan &p, const float *img, float *sino, fl
     for (const auto &g : p.gd) maxnb = std::max(maxnb, g.nb);
     dim3 grid((maxnb + 63) / 64, (unsigned)p.max_K, p.n_slices);
     if (cp && cp->residual) {
-        fp_kernel<2><<<grid, 256, 0, st>>>(p.t, img, nullptr, alpha, *cp);
+        fp_kernel<2><<<grid, 256, 0, st>>>(p.t, img, nullptr, alpha, *cp, 0);
     } else if (cp) {
-        fp_kernel<1><<<grid, 256, 0, st>>>(p.t, img, nullptr, alpha, *cp);
+        fp_kernel<1><<<grid, 256, 0, st>>>(p.t, img, nullptr, alpha, *cp, 0);
     } else {
         CpDual none{};
-        fp_kernel<0><<<grid, 256, 0, st>>>(p.t, img, sino, alpha, none);
+        fp_kernel<0><<<grid, 256, 0, st>>>(p.t, img, sino, alpha, none, 0);
     }
+    return hipGetLastError();
+}
+
+// row[s][j] = (A img_s)[k][j] - y_s[k][j] for one projection k of a uniform plan
+hipError_t launch_forward_row(const pyhst_plan &p, const float *img, const float *y, int k, float *row,
+                              hipStream_t st)
+{
+    const GeoDev &g = p.gd[0];
+    dim3 grid((g.nb + 63) / 64, 1, p.n_slices);
+    CpDual r{row, y, 0.0f, 1};
+    fp_kernel<3><<<grid, 256, 0, st>>>(p.t, img, nullptr, 1.0f, r, k);
     return hipGetLastError();
 }
 

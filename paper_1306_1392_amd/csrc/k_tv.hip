@@ -84,6 +84,15 @@ __global__ void axpby_kernel(float *y, const float *x, int64_t n, float a, float
         y[o] = a * x[o] + b * y[o];
 }
 
+// dst = src where src > thr, else 0 (the strongly absorbing part of a first reconstruction)
+__global__ void threshold_kernel(float *__restrict__ dst, const float *__restrict__ src, int64_t n, float thr)
+{
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
+        const float v = src[o];
+        dst[o] = v > thr ? v : 0.0f;
+    }
+}
+
 // FISTA extrapolation: z = xn + m (xn - xo)
 __global__ void momentum_kernel(float *__restrict__ z, const float *__restrict__ xn, const float *__restrict__ xo,
                                 int64_t n, float m)
@@ -231,6 +240,12 @@ hipError_t launch_momentum(float *z, const float *xn, const float *xo, int64_t n
     return hipGetLastError();
 }
 
+hipError_t launch_threshold(float *dst, const float *src, int64_t n, float thr, hipStream_t st)
+{
+    threshold_kernel<<<grid_for(n), 256, 0, st>>>(dst, src, n, thr);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t st)
 {
     copy_kernel<<<grid_for(n), 256, 0, st>>>(dst, src, n);
@@ -327,8 +342,65 @@ __global__ __launch_bounds__(256) void residual_kernel(Tables T, const float *__
     if (threadIdx.x == 0) rel[blockIdx.x] = (float)(td > 0.0 ? sqrt(tn / td) : 0.0);
 }
 
+// err[s] = sum_j row[s][j]^2 (one workgroup per slice)
+__global__ __launch_bounds__(256) void rowsq_kernel(const float *__restrict__ row, int nb, float *__restrict__ err)
+{
+    __shared__ double sh[4];
+    const float *r = row + (int64_t)blockIdx.x * nb;
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) acc += (double)r[j] * (double)r[j];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) err[blockIdx.x] = (float)t;
+}
+
+// e[s] = cos(xb_s - x0_s, xb_s) (one workgroup per slice, FP64 sums)
+__global__ __launch_bounds__(256) void decoherence_kernel(Tables T, const float *__restrict__ xb,
+                                                          const float *__restrict__ x0, float *__restrict__ e)
+{
+    __shared__ double sh[4];
+    const SliceDev sd = T.slc[blockIdx.x];
+    const GeoDev &g = T.geo[sd.g];
+    const int64_t n = (int64_t)g.ny * g.nx;
+    double da = 0.0, dd = 0.0, aa = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double a = xb[sd.img_off + i], d = a - (double)x0[sd.img_off + i];
+        da += d * a;
+        dd += d * d;
+        aa += a * a;
+    }
+    const double t_da = block_sum(da, sh);
+    const double t_dd = block_sum(dd, sh);
+    const double t_aa = block_sum(aa, sh);
+    if (threadIdx.x == 0) e[blockIdx.x] = (float)(t_dd > 0.0 && t_aa > 0.0 ? t_da / sqrt(t_dd * t_aa) : 0.0);
+}
+
 }  // namespace
 }  // namespace pyhst
+
+extern "C" int pyhst_cv_error(const pyhst_plan *p, const float *x, const float *y, int32_t k, float *row, float *err,
+                              hipStream_t st)
+{
+    using namespace pyhst;
+    if (!p || !x || !y || !row || !err) return fail(PYHST_EARG, "cv_error: NULL argument");
+    if (!p->uniform) return fail(PYHST_EARG, "cv_error: needs a uniform plan");
+    if (k < 0 || k >= p->gd[0].K) return fail(PYHST_EARG, "cv_error: projection index out of range");
+    hipError_t e = launch_forward_row(*p, x, y, k, row, st);
+    if (e == hipSuccess) {
+        rowsq_kernel<<<p->n_slices, 256, 0, st>>>(row, p->gd[0].nb, err);
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "cv_error");
+}
+
+extern "C" int pyhst_decoherence(const pyhst_plan *p, const float *x_beta, const float *x_zero, float *e_out,
+                                 hipStream_t st)
+{
+    using namespace pyhst;
+    if (!p || !x_beta || !x_zero || !e_out) return fail(PYHST_EARG, "decoherence: NULL argument");
+    decoherence_kernel<<<p->n_slices, 256, 0, st>>>(p->t, x_beta, x_zero, e_out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "decoherence");
+}
 
 extern "C" int pyhst_slice_residual(const pyhst_plan *p, const float *ax, const float *y, float *rel,
                                     hipStream_t st)

@@ -500,6 +500,33 @@ int pyhst_normalize(const pyhst_plan *p, const uint16_t *raw, const float *flats
     return e == hipSuccess ? PYHST_OK : hip_fail(e, "normalize");
 }
 
+int pyhst_normalize_hotspot(const pyhst_plan *p, const uint16_t *raw, const float *flats, const double *flat_pos,
+                            int32_t n_flats, const float *dark, float eps, float threshold, float *sino,
+                            hipStream_t st)
+{
+    if (!p || !raw || !flats || !flat_pos || !dark || !sino) return fail(PYHST_EARG, "normalize_hotspot: NULL argument");
+    if (!p->uniform) return fail(PYHST_EARG, "normalize_hotspot: raw radiographs need a uniform plan");
+    if (n_flats < 1 || n_flats > 32) return fail(PYHST_EARG, "normalize_hotspot: n_flats must be in [1, 32]");
+    for (int i = 1; i < n_flats; ++i)
+        if (!(flat_pos[i] > flat_pos[i - 1]))
+            return fail(PYHST_EARG, "normalize_hotspot: flat positions must increase");
+    if (!(threshold >= 0.0f)) return fail(PYHST_EARG, "normalize_hotspot: threshold must be >= 0");
+    hipError_t e = launch_normalize_hotspot(*p, raw, flats, flat_pos, n_flats, dark, eps, threshold, sino, st);
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "normalize_hotspot");
+}
+
+int pyhst_ring_filter(const pyhst_plan *p, float *sino, int32_t width, const float *obj, double *work,
+                      size_t work_doubles, hipStream_t st)
+{
+    if (!p || !sino) return fail(PYHST_EARG, "ring_filter: NULL argument");
+    if (!p->uniform) return fail(PYHST_EARG, "ring_filter: needs a uniform plan");
+    if (width < 0) return fail(PYHST_EARG, "ring_filter: width must be >= 0");
+    if (!work || work_doubles < 2 * (size_t)p->n_slices * p->gd[0].nb)
+        return fail(PYHST_EARG, "ring_filter: work needs 2 * n_slices * n_det doubles");
+    hipError_t e = launch_ring_filter(*p, sino, obj, width, work, st);
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "ring_filter");
+}
+
 int fbp_filter(const pyhst_plan *p, const float *sino, float *filt, hipStream_t st)
 {
     if (!p || !sino || !filt) return fail(PYHST_EARG, "fbp_filter: NULL argument");

@@ -19,17 +19,45 @@ struct CpLayout {
     size_t y, xbar, q1, q2, p, tmp, partials, energy, norm, total;
 };
 
-CpLayout cp_layout(const pyhst_plan &p, const pyhst_recon_args &a)
+// Optional preprocessing of section 2.3 (hot spots, rings): the data go through a work copy y.
+struct PreLayout {
+    bool on;
+    size_t y, ring, obj, img, filt, total;
+};
+
+PreLayout pre_layout(const pyhst_plan &p, const pyhst_recon_args &a)
 {
-    CpLayout L{};
+    PreLayout L{};
+    L.on = a.hot_spot != 0 || a.ring_width > 0;
+    if (!L.on) return L;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t r = o;
         o = align256(o + bytes);
         return r;
     };
+    L.y = take((size_t)p.sino_elems * 4);
+    if (a.ring_width > 0) L.ring = take((size_t)2 * p.n_slices * p.gd[0].nb * 8);
+    if (a.ring_width > 0 && a.ring_object) {
+        L.obj = take((size_t)p.sino_elems * 4);
+        L.img = take((size_t)p.img_elems * 4);
+        L.filt = take((size_t)p.filt_elems * 4);
+    }
+    L.total = o;
+    return L;
+}
+
+CpLayout cp_layout(const pyhst_plan &p, const pyhst_recon_args &a, size_t base, bool need_y)
+{
+    CpLayout L{};
+    size_t o = base;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = align256(o + bytes);
+        return r;
+    };
     const size_t ni = (size_t)p.img_elems, ns = (size_t)p.sino_elems;
-    L.y = a.raw ? take(ns * 4) : (size_t)-1;
+    L.y = need_y ? take(ns * 4) : (size_t)-1;
     L.xbar = take(ni * 4);
     L.q1 = take(ni * 4);
     L.q2 = take(ni * 4);
@@ -46,17 +74,17 @@ struct FiLayout {
     size_t y, r, z, xb, prox, partials, energy, norm, total;
 };
 
-FiLayout fista_layout(const pyhst_plan &p, const pyhst_recon_args &a)
+FiLayout fista_layout(const pyhst_plan &p, const pyhst_recon_args &a, size_t base, bool need_y)
 {
     FiLayout L{};
-    size_t o = 0;
+    size_t o = base;
     auto take = [&](size_t bytes) {
         size_t r = o;
         o = align256(o + bytes);
         return r;
     };
     const size_t ni = (size_t)p.img_elems, ns = (size_t)p.sino_elems;
-    L.y = a.raw ? take(ns * 4) : (size_t)-1;
+    L.y = need_y ? take(ns * 4) : (size_t)-1;
     L.r = take(ns * 4);
     L.z = take(ni * 4);
     L.xb = take(ni * 4);
@@ -68,23 +96,64 @@ FiLayout fista_layout(const pyhst_plan &p, const pyhst_recon_args &a)
     return L;
 }
 
-size_t fbp_work(const pyhst_plan &p) { return align256((size_t)p.filt_elems * 4); }
+size_t fbp_work(const pyhst_plan &p, size_t base) { return base + align256((size_t)p.filt_elems * 4); }
 
-int enqueue_fbp(const pyhst_plan &p, const pyhst_recon_args &a, hipStream_t st)
+// y = normalised (hot-spot filtered) data or a copy of sino, then the ring filter (with the
+// thresholded object removed from its average when asked).
+int enqueue_pre(const pyhst_plan &p, const pyhst_recon_args &a, const PreLayout &L, hipStream_t st)
 {
-    float *filt = (float *)a.work;
-    hipError_t e = launch_filter(p, a.raw ? nullptr : a.sino, a.raw, a.flats, a.flat_pos, a.n_flats, a.dark, a.eps,
-                                 filt, st);
+    unsigned char *w = (unsigned char *)a.work;
+    float *y = (float *)(w + L.y);
+    hipError_t e;
+    if (a.raw) {
+        e = a.hot_spot ? launch_normalize_hotspot(p, a.raw, a.flats, a.flat_pos, a.n_flats, a.dark, a.eps,
+                                                  a.hot_threshold, y, st)
+                       : launch_normalize(p, a.raw, a.flats, a.flat_pos, a.n_flats, a.dark, a.eps, y, st);
+    } else {
+        e = launch_copy(y, a.sino, p.sino_elems, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: preprocessing");
+    if (a.ring_width > 0) {
+        const float *obj = nullptr;
+        if (a.ring_object) {
+            float *filt = (float *)(w + L.filt), *img = (float *)(w + L.img), *ob = (float *)(w + L.obj);
+            e = launch_filter(p, y, nullptr, nullptr, nullptr, 0, nullptr, 0.0f, filt, st);
+            if (e == hipSuccess) e = launch_backproject(p, filt, 1, img, 1.0f, 0.0f, nullptr, st);
+            if (e == hipSuccess) e = launch_threshold(img, img, p.img_elems, a.ring_threshold, st);
+            if (e == hipSuccess) e = launch_forward(p, img, ob, 1.0f, nullptr, st);
+            if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: ring object");
+            obj = ob;
+        }
+        e = launch_ring_filter(p, y, obj, a.ring_width, (double *)(w + L.ring), st);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: ring filter");
+    }
+    return PYHST_OK;
+}
+
+int enqueue_fbp(const pyhst_plan &p, const pyhst_recon_args &a, const PreLayout &PL, hipStream_t st)
+{
+    float *filt = (float *)((unsigned char *)a.work + PL.total);
+    hipError_t e;
+    if (PL.on) {
+        int rc = enqueue_pre(p, a, PL, st);
+        if (rc) return rc;
+        e = launch_filter(p, (const float *)((unsigned char *)a.work + PL.y), nullptr, nullptr, nullptr, 0, nullptr,
+                          0.0f, filt, st);
+    } else {
+        e = launch_filter(p, a.raw ? nullptr : a.sino, a.raw, a.flats, a.flat_pos, a.n_flats, a.dark, a.eps, filt,
+                          st);
+    }
     if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: filter");
     e = launch_backproject(p, filt, 1, a.out, 1.0f, 0.0f, nullptr, st);
     if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: backproject");
     return PYHST_OK;
 }
 
-int enqueue_cp(const pyhst_plan &p, const pyhst_recon_args &a, const CpLayout &L, double op_norm, hipStream_t st)
+int enqueue_cp(const pyhst_plan &p, const pyhst_recon_args &a, const PreLayout &PL, const CpLayout &L,
+               double op_norm, hipStream_t st)
 {
     unsigned char *w = (unsigned char *)a.work;
-    const float *y = a.raw ? (const float *)(w + L.y) : a.sino;
+    const float *y = PL.on ? (const float *)(w + PL.y) : a.raw ? (const float *)(w + L.y) : a.sino;
     float *x = a.out, *xbar = (float *)(w + L.xbar), *q1 = (float *)(w + L.q1), *q2 = (float *)(w + L.q2);
     float *pd = (float *)(w + L.p), *tmp = (float *)(w + L.tmp);
     double *partials = (double *)(w + L.partials);
@@ -93,7 +162,10 @@ int enqueue_cp(const pyhst_plan &p, const pyhst_recon_args &a, const CpLayout &L
     const float s2 = (float)(p.gd[0].s * p.gd[0].s);
     const float tau = (float)(1.0 / op_norm), sigma = (float)(1.0 / op_norm);
     hipError_t e;
-    if (a.raw) {
+    if (PL.on) {
+        int rc = enqueue_pre(p, a, PL, st);
+        if (rc) return rc;
+    } else if (a.raw) {
         e = launch_normalize(p, a.raw, a.flats, a.flat_pos, a.n_flats, a.dark, a.eps, (float *)(w + L.y), st);
         if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: normalize");
     }
@@ -128,11 +200,12 @@ int enqueue_cp(const pyhst_plan &p, const pyhst_recon_args &a, const CpLayout &L
 //   x_k = prox_{(lambda/La) TV}(z)    (tv_prox, n_inner dual iterations from zero)
 //   ISTA: z is x itself; FISTA: z = x_k + m_k (x_k - x_{k-1}) with the t_k sequence
 // The iterates alternate between out and one work buffer; the last one is copied to out if needed.
-int enqueue_fista(const pyhst_plan &p, const pyhst_recon_args &a, const FiLayout &L, double op_norm, hipStream_t st)
+int enqueue_fista(const pyhst_plan &p, const pyhst_recon_args &a, const PreLayout &PL, const FiLayout &L,
+                  double op_norm, hipStream_t st)
 {
     unsigned char *w = (unsigned char *)a.work;
     const bool fast = a.method == PYHST_FISTA;
-    const float *y = a.raw ? (const float *)(w + L.y) : a.sino;
+    const float *y = PL.on ? (const float *)(w + PL.y) : a.raw ? (const float *)(w + L.y) : a.sino;
     float *r = (float *)(w + L.r), *z = (float *)(w + L.z);
     float *xa = a.out, *xb = (float *)(w + L.xb), *prox = (float *)(w + L.prox);
     double *partials = (double *)(w + L.partials);
@@ -144,7 +217,10 @@ int enqueue_fista(const pyhst_plan &p, const pyhst_recon_args &a, const FiLayout
     const float step = (float)(-(double)s2 / La);
     const float plam = (float)((double)a.lambda / La);
     hipError_t e;
-    if (a.raw) {
+    if (PL.on) {
+        int rc = enqueue_pre(p, a, PL, st);
+        if (rc) return rc;
+    } else if (a.raw) {
         e = launch_normalize(p, a.raw, a.flats, a.flat_pos, a.n_flats, a.dark, a.eps, (float *)(w + L.y), st);
         if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: normalize");
     }
@@ -223,17 +299,23 @@ extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hip
         if (a->n_iter < 0 || !(a->lambda >= 0.0f)) return fail(PYHST_EARG, "reconstruct_slices: bad n_iter/lambda");
         if (fi && a->n_inner < 0) return fail(PYHST_EARG, "reconstruct_slices: bad n_inner");
     }
+    if (a->ring_width < 0) return fail(PYHST_EARG, "reconstruct_slices: ring_width must be >= 0");
+    if (a->hot_spot && !a->raw) return fail(PYHST_EARG, "reconstruct_slices: the hot-spot filter needs raw input");
+    if (a->hot_spot && !(a->hot_threshold >= 0.0f))
+        return fail(PYHST_EARG, "reconstruct_slices: hot_threshold must be >= 0");
+    const PreLayout PL = pre_layout(p, *a);
+    if (PL.on && !p.uniform) return fail(PYHST_EARG, "reconstruct_slices: preprocessing needs a uniform plan");
     CpLayout L{};
     FiLayout F{};
     size_t need;
     if (cp) {
-        L = cp_layout(p, *a);
+        L = cp_layout(p, *a, PL.total, a->raw && !PL.on);
         need = L.total;
     } else if (fi) {
-        F = fista_layout(p, *a);
+        F = fista_layout(p, *a, PL.total, a->raw && !PL.on);
         need = F.total;
     } else {
-        need = fbp_work(p);
+        need = fbp_work(p, PL.total);
     }
     if (!a->out) {
         a->work_bytes = need;
@@ -271,7 +353,8 @@ extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hip
         if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: hipStreamIsCapturing");
     }
     auto enqueue = [&]() {
-        return cp ? enqueue_cp(p, *a, L, op_norm, st) : fi ? enqueue_fista(p, *a, F, op_norm, st) : enqueue_fbp(p, *a, st);
+        return cp ? enqueue_cp(p, *a, PL, L, op_norm, st)
+                  : fi ? enqueue_fista(p, *a, PL, F, op_norm, st) : enqueue_fbp(p, *a, PL, st);
     };
 
     if (graphable && cs == hipStreamCaptureStatusNone) {
@@ -279,7 +362,13 @@ extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hip
                                      (uint64_t)(uintptr_t)a->flats, (uint64_t)(uintptr_t)a->dark,
                                      (uint64_t)(uintptr_t)a->out, (uint64_t)(uintptr_t)a->work,
                                      (uint64_t)a->n_flats, (uint64_t)a->n_iter, (uint64_t)(uintptr_t)st,
-                                     (uint64_t)(fi ? a->n_inner : 0)};
+                                     (uint64_t)(fi ? a->n_inner : 0), (uint64_t)a->hot_spot,
+                                     (uint64_t)a->ring_width, (uint64_t)a->ring_object};
+        for (float f : {a->hot_threshold, a->ring_threshold}) {
+            uint32_t fb;
+            std::memcpy(&fb, &f, 4);
+            key.push_back(fb);
+        }
         uint32_t lb, eb;
         std::memcpy(&lb, &a->lambda, 4);
         std::memcpy(&eb, &a->eps, 4);

@@ -1,0 +1,104 @@
+"""Preprocessing extras of section 2.3 on the GPU against the oracle: the hot-spot median filter on
+flat-field-corrected radiographs, the ring-artifact filter (with and without the thresholded object),
+and both inside reconstruct_slices (FBP and Chambolle-Pock)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_1306_1392_amd as ph
+
+pytestmark = pytest.mark.gpu
+TOL_OP = 1e-5
+TOL_PIPE = 1e-4
+
+
+def rel(a, b):
+    a = a.detach().double().cpu().numpy() if torch.is_tensor(a) else np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def raw_with_spikes(R, N, K, seed):
+    """Raw radiographs of ellipse phantoms with 2 flats and a dark, plus hot pixels (+40 % counts)."""
+    ang = synth.uniform_angles(K)
+    axis = (N - 1) / 2 + 1.5
+    p = torch.stack([synth.ellipse_sinogram(synth.random_ellipses(synth.rng_for(10, seed, r), 6), ang, N, axis, N)
+                     for r in range(R)])
+    raw, flats, flat_pos, dark, _ = synth.raw_acquisition(p, seed=seed)
+    rng = synth.rng_for(10, seed, 999)
+    r16 = raw.numpy().astype(np.float64)
+    n_hot = K * R * N // 50
+    kk, rr, jj = rng.integers(0, K, n_hot), rng.integers(0, R, n_hot), rng.integers(0, N, n_hot)
+    r16[kk, rr, jj] = np.minimum(r16[kk, rr, jj] * 1.4, 65535)
+    raw = torch.from_numpy(r16.round().astype(np.uint16))
+    return raw, flats, flat_pos, dark, ang, axis
+
+
+# With these seeds every pixel's |t - median - threshold| is at least 2.7e-5 (checked in FP64), far
+# beyond FP32 rounding, so both sides take the same replacement decisions.
+def test_hotspot_normalize_parity(dev):
+    R, N, K = 5, 64, 40
+    raw, flats, flat_pos, dark, ang, axis = raw_with_spikes(R, N, K, 1)
+    plan = ph.Plan(ph.Geometry(N, N, N, ang, axis), n_slices=R)
+    got = ph.normalize_hotspot(plan, raw.to(dev), flats.to(dev), flat_pos, dark.to(dev), 0.1)
+    ref = oracle.normalize_hotspot(raw.numpy(), flats.numpy(), flat_pos, dark.numpy(), 0.1)
+    assert rel(got, ref) <= TOL_OP
+    plain = oracle.normalize(raw.numpy(), flats.numpy(), flat_pos, dark.numpy())
+    assert rel(plain, ref) > 1e-2                       # the spikes were there and were removed
+
+
+def test_ring_filter_parity(dev):
+    R, N, K = 3, 96, 60
+    g = ph.Geometry(N, N, N, synth.uniform_angles(K), (N - 1) / 2)
+    og = oracle.Geom(N, N, N, g.angles, g.axis_pos)
+    rng = synth.rng_for(10, 2, 0)
+    sino = np.stack([synth.ellipse_sinogram(synth.random_ellipses(synth.rng_for(10, 2, r), 5), g.angles, N,
+                                            g.axis_pos, N).numpy() for r in range(R)])
+    sino = (sino + 0.3 * rng.standard_normal((R, 1, N))).astype(np.float32)
+    plan = ph.Plan(g, n_slices=R)
+    for width in (0, 3, 20):
+        got = ph.ring_filter(plan, torch.from_numpy(sino).to(dev), width)
+        assert rel(got, oracle.ring_filter(sino, width)) <= TOL_OP, width
+    obj = np.stack([oracle.ring_object(sino[r], og, 0.3) for r in range(R)]).astype(np.float32)
+    got = ph.ring_filter(plan, torch.from_numpy(sino).to(dev), 12, obj=torch.from_numpy(obj).to(dev))
+    assert rel(got, oracle.ring_filter(sino, 12, obj=obj)) <= TOL_OP
+
+
+def test_fbp_with_hotspot_and_ring_object_parity(dev):
+    R, N, K = 3, 64, 90
+    raw, flats, flat_pos, dark, ang, axis = raw_with_spikes(R, N, K, 3)
+    # detector gain errors: the same per-bin factor in every projection -> rings
+    gain = 1 + 0.02 * synth.rng_for(10, 3, 7).standard_normal((1, R, N))
+    raw = torch.from_numpy(np.clip(np.round(raw.numpy() * gain), 0, 65535).astype(np.uint16))
+    g = ph.Geometry(N, N, N, ang, axis)
+    og = oracle.Geom(N, N, N, ang, axis)
+    plan = ph.Plan(g, n_slices=R)
+    args = dict(raw=raw.to(dev), flats=flats.to(dev), flat_pos=flat_pos, dark=dark.to(dev), method=ph.FBP)
+    x = ph.reconstruct_slices(plan, hot_threshold=0.1, ring_width=6, ring_object_threshold=0.5, **args)
+    y = oracle.normalize_hotspot(raw.numpy(), flats.numpy(), flat_pos, dark.numpy(), 0.1)
+    ref = []
+    for r in range(R):
+        obj = oracle.ring_object(y[r], og, 0.5)
+        ref.append(oracle.fbp(oracle.ring_filter(y[r], 6, obj=obj), og))
+    assert rel(x, np.stack(ref)) <= TOL_PIPE
+    # the caller's raw buffer is untouched and the plain path still matches its own oracle
+    x0 = ph.reconstruct_slices(plan, **args)
+    ref0 = oracle.fbp_raw(raw.numpy(), flats.numpy(), flat_pos, dark.numpy(), og)
+    assert rel(x0, ref0) <= TOL_PIPE
+
+
+def test_cp_with_ring_filter_parity(dev):
+    N, K = 64, 48
+    g = ph.Geometry(N, N, N, synth.uniform_angles(K), (N - 1) / 2)
+    og = oracle.Geom(N, N, N, g.angles, g.axis_pos)
+    y = synth.ellipse_sinogram(synth.random_ellipses(synth.rng_for(10, 4, 0), 5), g.angles, N, g.axis_pos, N).numpy()
+    y = (y + 0.2 * synth.rng_for(10, 4, 1).standard_normal((1, N))).astype(np.float32)
+    Lk = oracle.opnorm(og, synth.rng_for(10, 4, 2).standard_normal((N, N)), 200)
+    plan = ph.Plan(g)
+    yt = torch.from_numpy(y)[None].contiguous().to(dev)
+    x = ph.reconstruct_slices(plan, sino=yt, method=ph.TV_CP, lam=0.05, n_iter=10, op_norm=Lk, ring_width=5)
+    ref = oracle.cp_tv(oracle.ring_filter(y, 5), og, 0.05, 10, Lk)
+    assert rel(x[0], ref) <= TOL_PIPE
+    assert torch.equal(yt[0].cpu(), torch.from_numpy(y))   # input not modified
