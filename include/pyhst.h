@@ -265,6 +265,41 @@ int pyhst_cv_error(const pyhst_plan *plan, const float *x, const float *y, int32
 int pyhst_decoherence(const pyhst_plan *plan, const float *x_beta, const float *x_zero, float *e, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Overlapping-patch dictionary prior (section 3.2, eqs. (4)-(9)): the image is
+ * x_i = sum_k w_kp phi_k(i - r_p) taken from the patch p whose core contains i,
+ * and the coefficients minimise (eq. (8))
+ *   |y - Pi x|^2 + rho sum_p sum_{i in p} (x_i - sum_k w_kp phi_k(i - r_p))^2 + beta |w|_1
+ * by n_iter ISTA (fast = 0) or FISTA (fast = 1) steps on w with step 1/lipschitz
+ * and soft threshold beta/lipschitz, from w = 0; the gradient is eq. (9).
+ * Patches: m x m, corners every `stride` pixels per axis (the last at n - m),
+ * p = row-corner index * (column corners) + column-corner index; cores: the
+ * L1-nearest patch centre, lowest index on ties.  Pi is the plan's projector A
+ * (identity = 0; y [packed K x n_det]) or the identity (identity = 1, image
+ * denoising; y [packed n_y x n_x]); uniform plans only.
+ *   dict [n_atoms][m*m] device, row k = atom phi_k (row-major patch);
+ *   w    device [n_slices][n_patches][n_atoms] (receives the coefficients);
+ *   out  device [packed n_y x n_x] (the image of eq. (7));
+ *   lipschitz <= 0: estimated by 60 power iterations on the gradient map (x 1.02), written back;
+ *   energy (host [n_iter] or NULL): eq. (8) after every iteration, summed over the batch.
+ * Query: w == NULL returns work_bytes and n_patches.  The call synchronises its stream. */
+typedef struct {
+    const float *y;
+    const float *dict;
+    int32_t m, stride, n_atoms;
+    float rho, beta;
+    int32_t n_iter, fast, identity;
+    double lipschitz;
+    float *w;
+    float *out;
+    float *energy;            /* host */
+    void *work;
+    size_t work_bytes;
+    int32_t n_patches;        /* out */
+} pyhst_patch_args;
+
+int pyhst_patch_fista(const pyhst_plan *plan, pyhst_patch_args *args, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Learned sparse-angle corrector (not part of the paper, whose learned prior
  * is an overlapping-patch dictionary, section 3.2): a U-Net applied to FBP
  * slices as x_hat = x + f(x).  `levels` resolution levels (the last one is the

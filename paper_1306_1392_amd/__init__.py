@@ -10,5 +10,5 @@ from ._lib import lib, PyhstError, SCAN_180, SCAN_360, SCAN_360_HALF, FBP, TV_CP
 from .api import (  # noqa: F401
     Geometry, Plan, pyhst_normalize, normalize, fbp_filter, backproject, forward_project, tv_prox,
     reconstruct_slices, work_bytes, uniform_angles, slice_residual, cv_error, decoherence,
-    normalize_hotspot, ring_filter,
+    normalize_hotspot, ring_filter, patch_fista,
 )

@@ -20,7 +20,8 @@ EXPORTS = ["pyhst_plan_create", "pyhst_plan_destroy", "pyhst_plan_slice_info", "
            "pyhst_last_error", "pyhst_unet_create", "pyhst_unet_destroy", "pyhst_unet_num_params",
            "pyhst_unet_set_params", "pyhst_unet_get_params", "pyhst_unet_get_grads", "pyhst_unet_forward",
            "pyhst_unet_backward", "pyhst_unet_adam", "pyhst_unet_train_step", "pyhst_plan_autotune", "pyhst_slice_residual", "pyhst_unet_tensor",
-           "pyhst_cv_error", "pyhst_decoherence", "pyhst_normalize_hotspot", "pyhst_ring_filter"]
+           "pyhst_cv_error", "pyhst_decoherence", "pyhst_normalize_hotspot", "pyhst_ring_filter",
+           "pyhst_patch_fista"]
 
 
 class Geom(ctypes.Structure):
@@ -44,6 +45,13 @@ class ReconArgs(ctypes.Structure):
                 ("work_bytes", c_size_t), ("use_graph", c_int32), ("n_inner", c_int32),
                 ("hot_spot", c_int32), ("hot_threshold", c_float), ("ring_width", c_int32),
                 ("ring_object", c_int32), ("ring_threshold", c_float)]
+
+
+class PatchArgs(ctypes.Structure):
+    _fields_ = [("y", c_void_p), ("dict", c_void_p), ("m", c_int32), ("stride", c_int32), ("n_atoms", c_int32),
+                ("rho", c_float), ("beta", c_float), ("n_iter", c_int32), ("fast", c_int32), ("identity", c_int32),
+                ("lipschitz", c_double), ("w", c_void_p), ("out", c_void_p), ("energy", ctypes.POINTER(c_float)),
+                ("work", c_void_p), ("work_bytes", c_size_t), ("n_patches", c_int32)]
 
 
 _lib = None
@@ -87,6 +95,7 @@ def lib(path: str = LIB_PATH):
     L.pyhst_cv_error.argtypes = [P, P, P, c_int32, P, P, P]
     L.pyhst_normalize_hotspot.argtypes = [P, P, P, ctypes.POINTER(c_double), c_int32, P, c_float, c_float, P, P]
     L.pyhst_ring_filter.argtypes = [P, P, c_int32, P, P, c_size_t, P]
+    L.pyhst_patch_fista.argtypes = [P, ctypes.POINTER(PatchArgs), P]
     L.pyhst_decoherence.argtypes = [P, P, P, P, P]
     L.pyhst_unet_tensor.argtypes = [P, c_int32, c_int32, c_int32, P, c_int64, P]
     L.pyhst_strerror.argtypes = [c_int32]

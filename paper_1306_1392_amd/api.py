@@ -334,6 +334,39 @@ def decoherence(plan: Plan, x_beta, x_zero, out=None, stream=None):
     return out
 
 
+def patch_fista(plan: Plan, y, dictionary, m: int, stride: int, rho: float, beta: float, n_iter: int,
+                fast: bool = True, identity: bool = False, lipschitz: float = 0.0, energy: bool = False,
+                stream=None):
+    """Overlapping-patch dictionary prior (section 3.2) by ISTA/FISTA on the patch coefficients.
+    y: sinograms (or images when identity=True); dictionary [n_atoms][m*m] float32 on the device.
+    Returns (image, coefficients [n_slices][n_patches][n_atoms]) and the energy trace when asked;
+    the Lipschitz constant used is left in plan.last_lipschitz."""
+    _need(y, plan.img_elems if identity else plan.sino_elems, "y")
+    if dictionary.dtype != torch.float32 or not dictionary.is_contiguous() or dictionary.dim() != 2 \
+            or dictionary.shape[1] != m * m:
+        raise ValueError("dictionary must be a contiguous float32 [n_atoms][m*m] tensor")
+    a = _lib.PatchArgs()
+    a.y, a.dict = _ptr(y), _ptr(dictionary)
+    a.m, a.stride, a.n_atoms = int(m), int(stride), int(dictionary.shape[0])
+    a.rho, a.beta, a.n_iter, a.fast, a.identity = float(rho), float(beta), int(n_iter), int(fast), int(identity)
+    a.lipschitz = float(lipschitz)
+    L = _lib.lib()
+    a.w = None
+    check(L.pyhst_patch_fista(plan.handle, ctypes.byref(a), _stream(stream)), "pyhst_patch_fista(query)")
+    dev = y.device
+    work = torch.empty(max(a.work_bytes, 1), device=dev, dtype=torch.uint8)
+    W = torch.empty((plan.n_slices, a.n_patches, a.n_atoms), device=dev, dtype=torch.float32)
+    out = torch.empty(plan.img_shape(), device=dev, dtype=torch.float32)
+    E = None
+    if energy:
+        E = np.zeros(max(n_iter, 1), dtype=np.float32)
+        a.energy = E.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    a.w, a.out, a.work, a.work_bytes = _ptr(W), _ptr(out), _ptr(work), work.numel()
+    check(L.pyhst_patch_fista(plan.handle, ctypes.byref(a), _stream(stream)), "pyhst_patch_fista")
+    plan.last_lipschitz = a.lipschitz
+    return (out, W, E[:n_iter]) if energy else (out, W)
+
+
 def work_bytes(plan: Plan, **kw) -> int:
     a = _lib.ReconArgs()
     a.raw = _ptr(kw.get("raw"))

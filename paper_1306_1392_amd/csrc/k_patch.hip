@@ -1,0 +1,498 @@
+// Overlapping-patch dictionary prior (section 3.2, eqs. (4)-(9)) solved by
+// ISTA / FISTA on the patch coefficients W, for a batch of slices.
+//
+// Patches: m x m, top-left corners on a grid of step `stride` per axis (the
+// last corner moved to n - m); patch p = row-corner index * n_cx + column-corner
+// index.  The core of a pixel is its L1-nearest patch centre (lowest index on
+// ties); with a separable corner grid that is the pair of per-axis nearest
+// corners, tabulated once per call on the host.
+//
+// One gradient evaluation at coefficients Z (eq. (9)):
+//   X = Z D                      (GEMM, [S*N_p][n_atoms] x [n_atoms][m*m])
+//   x_i = X_core(i)(i - r)       (assemble kernel)
+//   R = Pi^T (Pi x - y)          (projector residual + backprojector, or x - y when Pi = I)
+//   R_i += rho sum_{p covering i} (x_i - X_p(i - r_p))
+//   G = core_patches(R) + rho (X - patches(x))
+//   grad = 2 G D^T               (GEMM with D^T)
+// The GEMMs are plain FP32 register-tiled kernels (LDS tiles of 64 x 64 x 16,
+// 4 x 4 outputs per thread; fixed summation order).
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace pyhst {
+namespace {
+
+constexpr int GT = 64, GK = 16;
+
+// C[M][N] = alpha * A[M][K] B[K][N]   (row-major, leading dimensions K, N, N)
+__global__ __launch_bounds__(256) void sgemm_kernel(const float *__restrict__ A, const float *__restrict__ B,
+                                                    float *__restrict__ C, int M, int N, int K, float alpha)
+{
+    __shared__ float sA[GK][GT + 4];
+    __shared__ float sB[GK][GT + 4];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
+    float acc[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += GK) {
+        // A tile: 64 rows x 16 k; B tile: 16 k x 64 columns; 4 elements per thread each
+        for (int e = threadIdx.x; e < GT * GK; e += 256) {
+            const int r = e / GK, kk = e % GK;
+            const int gm = m0 + r, gk = k0 + kk;
+            sA[kk][r] = (gm < M && gk < K) ? A[(int64_t)gm * K + gk] : 0.0f;
+            const int kb = e / GT, c = e % GT;
+            const int gkb = k0 + kb, gn = n0 + c;
+            sB[kb][c] = (gkb < K && gn < N) ? B[(int64_t)gkb * N + gn] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GK; ++kk) {
+            float a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = sA[kk][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = sB[kk][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int gm = m0 + ty * 4 + i;
+        if (gm >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gn = n0 + tx * 4 + j;
+            if (gn < N) C[(int64_t)gm * N + gn] = alpha * acc[i][j];
+        }
+    }
+}
+
+struct PatchGeo {
+    const int *cy, *cx;          // corners per axis
+    const int *core_y, *core_x;  // per pixel row / column: index of the nearest corner (its core)
+    const int *first_y, *last_y; // per pixel row: range of corner indices whose patch covers the row
+    const int *first_x, *last_x;
+    int ny, nx, m, ncy, ncx, np;
+};
+
+__device__ inline int64_t pix_of(int64_t i, int ny, int nx, int &s, int &iy, int &ix)
+{
+    const int64_t per = (int64_t)ny * nx;
+    s = (int)(i / per);
+    const int64_t r = i - (int64_t)s * per;
+    iy = (int)(r / nx);
+    ix = (int)(r - (int64_t)iy * nx);
+    return r;
+}
+
+// x[s][i] = X[s][core(i)][i - r_core]
+__global__ void assemble_kernel(PatchGeo g, const float *__restrict__ X, float *__restrict__ x, int S)
+{
+    const int64_t n = (int64_t)S * g.ny * g.nx;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int s, iy, ix;
+        pix_of(i, g.ny, g.nx, s, iy, ix);
+        const int a = g.core_y[iy], b = g.core_x[ix];
+        const int p = a * g.ncx + b;
+        const int ly = iy - g.cy[a], lx = ix - g.cx[b];
+        x[i] = X[((int64_t)s * g.np + p) * g.m * g.m + ly * g.m + lx];
+    }
+}
+
+// R[s][i] += rho * sum over patches p covering i of (x_i - X_p(i - r_p))
+__global__ void similarity_kernel(PatchGeo g, const float *__restrict__ X, const float *__restrict__ x,
+                                  float *__restrict__ R, float rho, int S)
+{
+    const int64_t n = (int64_t)S * g.ny * g.nx;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int s, iy, ix;
+        pix_of(i, g.ny, g.nx, s, iy, ix);
+        const float xi = x[i];
+        float acc = 0.0f;
+        for (int a = g.first_y[iy]; a <= g.last_y[iy]; ++a)
+            for (int b = g.first_x[ix]; b <= g.last_x[ix]; ++b) {
+                const int p = a * g.ncx + b;
+                acc += xi - X[((int64_t)s * g.np + p) * g.m * g.m + (iy - g.cy[a]) * g.m + (ix - g.cx[b])];
+            }
+        R[i] += rho * acc;
+    }
+}
+
+// G[s][p][l] = (core(i) == p ? R_i : 0) + rho (X[s][p][l] - x_i),  i = r_p + l
+__global__ void patch_grad_kernel(PatchGeo g, const float *__restrict__ X, const float *__restrict__ x,
+                                  const float *__restrict__ R, float rho, float *__restrict__ G, int S)
+{
+    const int mm = g.m * g.m;
+    const int64_t n = (int64_t)S * g.np * mm;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t sp = e / mm;
+        const int l = (int)(e - sp * mm);
+        const int s = (int)(sp / g.np), p = (int)(sp - (int64_t)s * g.np);
+        const int a = p / g.ncx, b = p - a * g.ncx;
+        const int iy = g.cy[a] + l / g.m, ix = g.cx[b] + l % g.m;
+        const int64_t i = ((int64_t)s * g.ny + iy) * g.nx + ix;
+        const bool core = g.core_y[iy] == a && g.core_x[ix] == b;
+        G[e] = (core ? R[i] : 0.0f) + rho * (X[e] - x[i]);
+    }
+}
+
+// W_new = soft(Z - grad / L, beta / L);  FISTA: Z = W_new + mom (W_new - W_old);  ISTA: Z = W_new
+__global__ void shrink_kernel(const float *__restrict__ grad, float *__restrict__ Z, float *__restrict__ W,
+                              int64_t n, float invL, float thr, float mom, int fast)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const float v = Z[e] - grad[e] * invL;
+        const float wn = copysignf(fmaxf(fabsf(v) - thr, 0.0f), v);
+        const float wo = W[e];
+        W[e] = wn;
+        Z[e] = fast ? fmaf(mom, wn - wo, wn) : wn;
+    }
+}
+
+// r = x - y (identity projector)
+__global__ void diff_kernel(const float *__restrict__ x, const float *__restrict__ y, float *__restrict__ r, int64_t n)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        r[e] = y ? x[e] - y[e] : x[e];
+}
+
+// partials: sum of a^2 over one buffer, rho * sum (patches(x) - X)^2 and beta * sum |W| (FP64)
+__global__ __launch_bounds__(256) void patch_energy_kernel(PatchGeo g, const float *__restrict__ r, int64_t nr,
+                                                           const float *__restrict__ X, const float *__restrict__ x,
+                                                           const float *__restrict__ W, int64_t nw, float rho,
+                                                           float beta, int S, double *__restrict__ partials)
+{
+    __shared__ double sh[4];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    for (int64_t e = t0; e < nr; e += stride) acc += (double)r[e] * r[e];
+    const int mm = g.m * g.m;
+    const int64_t nx_ = (int64_t)S * g.np * mm;
+    for (int64_t e = t0; e < nx_; e += stride) {
+        const int64_t sp = e / mm;
+        const int l = (int)(e - sp * mm);
+        const int s = (int)(sp / g.np), p = (int)(sp - (int64_t)s * g.np);
+        const int a = p / g.ncx, b = p - a * g.ncx;
+        const int iy = g.cy[a] + l / g.m, ix = g.cx[b] + l % g.m;
+        const double d = (double)x[((int64_t)s * g.ny + iy) * g.nx + ix] - (double)X[e];
+        acc += rho * d * d;
+    }
+    for (int64_t e = t0; e < nw; e += stride) acc += beta * fabs((double)W[e]);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+__global__ void patch_final_kernel(const double *__restrict__ partials, int n, float *out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < n; ++i) t += partials[i];
+        *out = (float)t;
+    }
+}
+
+// <a, b> and <a, a> partial sums for the power iteration
+__global__ __launch_bounds__(256) void dot2_kernel(const float *__restrict__ a, const float *__restrict__ b, int64_t n,
+                                                   double *__restrict__ partials)
+{
+    __shared__ double sh[2][4];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    double ab = 0.0, aa = 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += stride) {
+        ab += (double)a[e] * b[e];
+        aa += (double)a[e] * a[e];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        ab += __shfl_xor(ab, off, 64);
+        aa += __shfl_xor(aa, off, 64);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[0][w] = ab;
+        sh[1][w] = aa;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = ((sh[0][0] + sh[0][1]) + sh[0][2]) + sh[0][3];
+        partials[2 * blockIdx.x + 1] = ((sh[1][0] + sh[1][1]) + sh[1][2]) + sh[1][3];
+    }
+}
+
+// v <- hv / |hv| with |hv| from the partials; lam_out = <hv, v_old> (v_old unit)
+__global__ void power_norm_kernel(const double *__restrict__ partials, int nblk, double *__restrict__ res)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double ab = 0.0, aa = 0.0;
+        for (int i = 0; i < nblk; ++i) {
+            ab += partials[2 * i];
+            aa += partials[2 * i + 1];
+        }
+        res[0] = ab;
+        res[1] = aa;
+    }
+}
+
+__global__ void scale_by_norm_kernel(float *__restrict__ dst, const float *__restrict__ src, int64_t n,
+                                     const double *__restrict__ res)
+{
+    const float inv = (float)(1.0 / sqrt(res[1]));
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = src[e] * inv;
+}
+
+unsigned grid_n(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
+}
+
+hipError_t sgemm(const float *A, const float *B, float *C, int64_t M, int N, int K, float alpha, hipStream_t st)
+{
+    dim3 grid((unsigned)((M + GT - 1) / GT), (unsigned)((N + GT - 1) / GT));
+    sgemm_kernel<<<grid, 256, 0, st>>>(A, B, C, (int)M, N, K, alpha);
+    return hipGetLastError();
+}
+
+std::vector<int> axis_corners(int n, int m, int stride)
+{
+    std::vector<int> c;
+    for (int v = 0; v + m <= n; v += stride) c.push_back(v);
+    if (c.empty() || c.back() != n - m) c.push_back(n - m);
+    return c;
+}
+
+// per pixel along one axis: nearest corner's centre (L1 per axis; lowest index on ties),
+// and the range of corners whose patch covers the pixel
+void axis_tables(int n, int m, const std::vector<int> &c, std::vector<int> &core, std::vector<int> &first,
+                 std::vector<int> &last)
+{
+    core.assign(n, 0);
+    first.assign(n, 0);
+    last.assign(n, -1);
+    for (int i = 0; i < n; ++i) {
+        double best = 1e300;
+        for (size_t a = 0; a < c.size(); ++a) {
+            const double d = std::fabs(i - (c[a] + 0.5 * (m - 1)));
+            if (d < best) {
+                best = d;
+                core[i] = (int)a;
+            }
+        }
+        int f = -1, l = -1;
+        for (size_t a = 0; a < c.size(); ++a)
+            if (c[a] <= i && i < c[a] + m) {
+                if (f < 0) f = (int)a;
+                l = (int)a;
+            }
+        first[i] = f;
+        last[i] = l;
+    }
+}
+
+struct PatchLayout {
+    size_t tables, X, x, r, R, G, grad, W, Z, dt, partials, res, energy, total;
+};
+
+}  // namespace
+}  // namespace pyhst
+
+using namespace pyhst;
+
+extern "C" int pyhst_patch_fista(const pyhst_plan *pc, pyhst_patch_args *a, hipStream_t st)
+{
+    if (!pc || !a) return fail(PYHST_EARG, "patch_fista: NULL argument");
+    const pyhst_plan &p = *pc;
+    if (!p.uniform) return fail(PYHST_EARG, "patch_fista: needs a uniform plan");
+    const GeoDev &geo = p.gd[0];
+    const int S = p.n_slices, ny = geo.ny, nx = geo.nx, m = a->m, st_ = a->stride, na = a->n_atoms;
+    if (m < 1 || m > ny || m > nx || st_ < 1 || st_ > m || na < 1 || a->n_iter < 0 || !(a->rho >= 0.0f) ||
+        !(a->beta >= 0.0f))
+        return fail(PYHST_EARG, "patch_fista: bad patch size, stride, atoms, iterations, rho or beta");
+    const std::vector<int> cy = axis_corners(ny, m, st_), cx = axis_corners(nx, m, st_);
+    const int ncy = (int)cy.size(), ncx = (int)cx.size(), np = ncy * ncx, mm = m * m;
+    const int64_t ni = (int64_t)S * ny * nx, nw = (int64_t)S * np * na, nX = (int64_t)S * np * mm;
+    const int64_t ns = a->identity ? ni : (int64_t)p.sino_elems;
+    const int nblk = 1024;
+
+    PatchLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = (o + bytes + 255) & ~(size_t)255;
+        return r;
+    };
+    const size_t tab_ints = 2 * (cy.size() + cx.size()) + 3 * (size_t)(ny + nx);
+    L.tables = take(tab_ints * 4);
+    L.X = take((size_t)nX * 4);
+    L.x = take((size_t)ni * 4);
+    L.r = take((size_t)ns * 4);
+    L.R = take((size_t)ni * 4);
+    L.G = take((size_t)nX * 4);
+    L.grad = take((size_t)nw * 4);
+    L.Z = take((size_t)nw * 4);
+    L.dt = take((size_t)na * mm * 4);
+    L.partials = take(sizeof(double) * 2 * nblk);
+    L.res = take(sizeof(double) * 2);
+    L.energy = take(sizeof(float) * (size_t)std::max(1, a->n_iter));
+    L.total = o;
+    if (!a->w) {
+        a->work_bytes = L.total;
+        a->n_patches = np;
+        return PYHST_OK;
+    }
+    if (!a->y || !a->dict || !a->out) return fail(PYHST_EARG, "patch_fista: NULL y, dict or out");
+    if (!a->work || a->work_bytes < L.total) {
+        set_error("patch_fista: work buffer too small");
+        return PYHST_ENOMEM;
+    }
+    unsigned char *w = (unsigned char *)a->work;
+    // host tables: corners, per-pixel cores and covering ranges
+    std::vector<int> core_y, first_y, last_y, core_x, first_x, last_x;
+    axis_tables(ny, m, cy, core_y, first_y, last_y);
+    axis_tables(nx, m, cx, core_x, first_x, last_x);
+    std::vector<int> tab;
+    tab.insert(tab.end(), cy.begin(), cy.end());
+    tab.insert(tab.end(), cx.begin(), cx.end());
+    const size_t o_core_y = tab.size();
+    tab.insert(tab.end(), core_y.begin(), core_y.end());
+    const size_t o_core_x = tab.size();
+    tab.insert(tab.end(), core_x.begin(), core_x.end());
+    const size_t o_first_y = tab.size();
+    tab.insert(tab.end(), first_y.begin(), first_y.end());
+    const size_t o_last_y = tab.size();
+    tab.insert(tab.end(), last_y.begin(), last_y.end());
+    const size_t o_first_x = tab.size();
+    tab.insert(tab.end(), first_x.begin(), first_x.end());
+    const size_t o_last_x = tab.size();
+    tab.insert(tab.end(), last_x.begin(), last_x.end());
+    // D^T [m*m][n_atoms], built on the host from the caller's dictionary
+    std::vector<float> dict_host((size_t)na * mm), dt_host((size_t)na * mm);
+    int *dtab = (int *)(w + L.tables);
+    hipError_t e = hipMemcpyAsync(dtab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dict_host.data(), a->dict, dict_host.size() * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "patch_fista: tables");
+    for (int k = 0; k < na; ++k)
+        for (int l = 0; l < mm; ++l) dt_host[(size_t)l * na + k] = dict_host[(size_t)k * mm + l];
+    float *DT = (float *)(w + L.dt);
+    e = hipMemcpyAsync(DT, dt_host.data(), dt_host.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // dt_host must outlive the copy
+    if (e != hipSuccess) return hip_fail(e, "patch_fista: dictionary transpose");
+
+    PatchGeo g{dtab, dtab + cy.size(), dtab + o_core_y, dtab + o_core_x, dtab + o_first_y, dtab + o_last_y,
+               dtab + o_first_x, dtab + o_last_x, ny, nx, m, ncy, ncx, np};
+    float *X = (float *)(w + L.X), *x = (float *)(w + L.x), *r = (float *)(w + L.r), *R = (float *)(w + L.R);
+    float *G = (float *)(w + L.G), *grad = (float *)(w + L.grad), *Z = (float *)(w + L.Z), *W = a->w;
+    double *partials = (double *)(w + L.partials), *res = (double *)(w + L.res);
+    float *edev = (float *)(w + L.energy);
+    const float s2 = (float)(geo.s * geo.s);
+
+    // gradient of eq. (9) at coefficients C (data term dropped when with_y is false)
+    auto gradient = [&](const float *C, bool with_y) -> hipError_t {
+        hipError_t er = sgemm(C, a->dict, X, (int64_t)S * np, mm, na, 1.0f, st);
+        if (er != hipSuccess) return er;
+        assemble_kernel<<<grid_n(ni), 256, 0, st>>>(g, X, x, S);
+        if (a->identity) {
+            diff_kernel<<<grid_n(ni), 256, 0, st>>>(x, with_y ? a->y : nullptr, R, ni);
+        } else {
+            if (with_y) {
+                CpDual rd{r, a->y, 0.0f, 1};
+                er = launch_forward(p, x, nullptr, 1.0f, &rd, st);
+            } else {
+                er = launch_forward(p, x, r, 1.0f, nullptr, st);
+            }
+            if (er == hipSuccess) er = launch_backproject(p, r, 0, R, s2, 0.0f, nullptr, st);
+            if (er != hipSuccess) return er;
+        }
+        similarity_kernel<<<grid_n(ni), 256, 0, st>>>(g, X, x, R, a->rho, S);
+        patch_grad_kernel<<<grid_n(nX), 256, 0, st>>>(g, X, x, R, a->rho, G, S);
+        return sgemm(G, DT, grad, (int64_t)S * np, na, mm, 2.0f, st);
+    };
+
+    double Lf = a->lipschitz;
+    if (!(Lf > 0.0)) {
+        // power iteration on the (linear) gradient map with y = 0; Z holds the iterate
+        std::vector<float> seed((size_t)nw);
+        uint32_t h = 0x9e3779b9u;
+        for (auto &v : seed) {
+            h ^= h << 13;
+            h ^= h >> 17;
+            h ^= h << 5;
+            v = (float)((h >> 8) * (1.0 / 16777216.0) - 0.5);
+        }
+        e = hipMemcpyAsync(Z, seed.data(), seed.size() * 4, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        double lam = 0.0;
+        for (int it = 0; it < 60 && e == hipSuccess; ++it) {
+            dot2_kernel<<<nblk, 256, 0, st>>>(Z, Z, nw, partials);
+            power_norm_kernel<<<1, 64, 0, st>>>(partials, nblk, res);
+            scale_by_norm_kernel<<<grid_n(nw), 256, 0, st>>>(Z, Z, nw, res);
+            e = gradient(Z, false);
+            if (e != hipSuccess) break;
+            dot2_kernel<<<nblk, 256, 0, st>>>(grad, Z, nw, partials);
+            power_norm_kernel<<<1, 64, 0, st>>>(partials, nblk, res);
+            e = hipMemcpyAsync(Z, grad, (size_t)nw * 4, hipMemcpyDeviceToDevice, st);
+        }
+        double hr[2] = {0.0, 0.0};
+        if (e == hipSuccess) e = hipMemcpyAsync(hr, res, sizeof(hr), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "patch_fista: Lipschitz estimate");
+        lam = hr[0];
+        if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PYHST_ENUM, "patch_fista: Lipschitz estimate failed");
+        Lf = 1.02 * lam;
+        a->lipschitz = Lf;
+    }
+
+    e = launch_fill(W, nw, 0.0f, st);
+    if (e == hipSuccess) e = launch_fill(Z, nw, 0.0f, st);
+    if (e != hipSuccess) return hip_fail(e, "patch_fista: clear");
+    double t = 1.0;
+    for (int it = 0; it < a->n_iter; ++it) {
+        e = gradient(Z, true);
+        if (e != hipSuccess) return hip_fail(e, "patch_fista: gradient");
+        double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+        const float mom = (float)((t - 1.0) / tn);
+        shrink_kernel<<<grid_n(nw), 256, 0, st>>>(grad, Z, W, nw, (float)(1.0 / Lf), (float)(a->beta / Lf), mom,
+                                                   a->fast);
+        t = tn;
+        if (a->energy) {
+            e = sgemm(W, a->dict, X, (int64_t)S * np, mm, na, 1.0f, st);
+            if (e != hipSuccess) return hip_fail(e, "patch_fista: energy");
+            assemble_kernel<<<grid_n(ni), 256, 0, st>>>(g, X, x, S);
+            if (a->identity) {
+                diff_kernel<<<grid_n(ni), 256, 0, st>>>(x, a->y, r, ni);
+            } else {
+                CpDual rd{r, a->y, 0.0f, 1};
+                e = launch_forward(p, x, nullptr, 1.0f, &rd, st);
+                if (e != hipSuccess) return hip_fail(e, "patch_fista: energy");
+            }
+            patch_energy_kernel<<<nblk, 256, 0, st>>>(g, r, ns, X, x, W, nw, a->rho, a->beta, S, partials);
+            patch_final_kernel<<<1, 64, 0, st>>>(partials, nblk, edev + it);
+        }
+    }
+    // final image from the final coefficients
+    e = sgemm(W, a->dict, X, (int64_t)S * np, mm, na, 1.0f, st);
+    if (e != hipSuccess) return hip_fail(e, "patch_fista: image");
+    assemble_kernel<<<grid_n(ni), 256, 0, st>>>(g, X, a->out, S);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "patch_fista: image");
+    if (a->energy && a->n_iter > 0) {
+        e = hipMemcpyAsync(a->energy, edev, sizeof(float) * a->n_iter, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "patch_fista: energy copy");
+        for (int i = 0; i < a->n_iter; ++i)
+            if (!std::isfinite(a->energy[i])) return fail(PYHST_ENUM, "patch_fista: non-finite energy");
+    }
+    return PYHST_OK;
+}

@@ -1,0 +1,89 @@
+"""Overlapping-patch dictionary prior (section 3.2) on the GPU against the NumPy oracle: iterates of the
+coefficients and the image after k ISTA/FISTA steps, the energy trace of eq. (8) and the Lipschitz
+estimate, for denoising (Pi = I) and tomography (Pi = A)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_1306_1392_amd as ph
+from oracle.patches import PatchGrid, PatchProblem, dct_dictionary, fista
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def rel(a, b):
+    a = a.detach().double().cpu().numpy() if torch.is_tensor(a) else np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def phantom(N, seed):
+    return synth.ellipse_raster(synth.random_ellipses(synth.rng_for(11, seed, 0), 6), N).numpy()
+
+
+@pytest.fixture(scope="module")
+def denoise():
+    N, m, st = 40, 8, 4
+    D = dct_dictionary(m, extra=32, seed=1).astype(np.float32)
+    y = (phantom(N, 0) + 0.1 * synth.rng_for(11, 0, 1).standard_normal((N, N))).astype(np.float32)
+    prob = PatchProblem(PatchGrid(N, N, m, st), D, y, rho=0.5, beta=0.02)
+    L = prob.lipschitz(300) * 1.01
+    return N, m, st, D, y, prob, L
+
+
+@pytest.mark.parametrize("fast", [False, True])
+@pytest.mark.parametrize("k", [1, 10, 40])
+def test_patch_denoise_iterates(dev, denoise, fast, k):
+    N, m, st, D, y, prob, L = denoise
+    plan = ph.Plan(ph.Geometry(N, N, N, synth.uniform_angles(8), (N - 1) / 2))
+    x, W = ph.patch_fista(plan, torch.from_numpy(y)[None].contiguous().to(dev), torch.from_numpy(D).to(dev), m, st,
+                          0.5, 0.02, k, fast=fast, identity=True, lipschitz=L)
+    Wr, xr = fista(prob, k, L, fast=fast)
+    assert rel(W[0], Wr) <= TOL, (k, fast, rel(W[0], Wr))
+    assert rel(x[0], xr) <= TOL
+
+
+def test_patch_tomography_iterates_energy_lipschitz(dev):
+    N, K, m, st = 48, 30, 8, 4
+    ang = synth.uniform_angles(K)
+    og = oracle.Geom(N, N, N, ang, (N - 1) / 2)
+    y = oracle.forward_project(phantom(N, 1), og) + 0.2 * synth.rng_for(11, 1, 1).standard_normal((K, N))
+    y = y.astype(np.float32)
+    D = dct_dictionary(m, extra=32, seed=2).astype(np.float32)
+    prob = PatchProblem(PatchGrid(N, N, m, st), D, y, rho=0.3, beta=0.05,
+                        project=lambda x: oracle.forward_project(x, og), backproject=lambda r: oracle.backproject(r, og))
+    L = prob.lipschitz(300)
+    plan = ph.Plan(ph.Geometry(N, N, N, ang, (N - 1) / 2))
+    yt, Dt = torch.from_numpy(y)[None].contiguous().to(dev), torch.from_numpy(D).to(dev)
+    for k in (1, 10):
+        x, W, E = ph.patch_fista(plan, yt, Dt, m, st, 0.3, 0.05, k, lipschitz=1.01 * L, energy=True)
+        Wr, xr, Er = fista(prob, k, 1.01 * L, energy=True)
+        assert rel(W[0], Wr) <= TOL and rel(x[0], xr) <= TOL, k
+        np.testing.assert_allclose(E, Er, rtol=1e-4)
+    # the GPU's own estimate: 1.02 x the top eigenvalue of the gradient map
+    ph.patch_fista(plan, yt, Dt, m, st, 0.3, 0.05, 0)
+    assert abs(plan.last_lipschitz / (1.02 * L) - 1) < 0.02, (plan.last_lipschitz, L)
+
+
+def test_patch_prior_beats_fbp_on_sparse_angles(dev):
+    """A sparse-angle piecewise-constant phantom: FISTA with the patch prior ends with a lower error to
+    the phantom than FBP, and ISTA's energy decreases monotonically on the GPU."""
+    N, K, m, st = 64, 24, 8, 4
+    ang = synth.uniform_angles(K)
+    truth = phantom(N, 2)
+    g = ph.Geometry(N, N, N, ang, (N - 1) / 2)
+    y = synth.ellipse_sinogram(synth.random_ellipses(synth.rng_for(11, 2, 0), 6), ang, N, g.axis_pos, N)
+    y = (y + 0.02 * float(y.max()) * torch.from_numpy(synth.rng_for(11, 2, 1).standard_normal(y.shape))).float()
+    yt = y[None].contiguous().to(dev)
+    plan = ph.Plan(g)
+    D = torch.from_numpy(dct_dictionary(m, extra=64, seed=3).astype(np.float32)).to(dev)
+    x, _ = ph.patch_fista(plan, yt, D, m, st, 5.0, 8.0, 300)
+    x_fbp = ph.reconstruct_slices(plan, sino=yt, method=ph.FBP)
+    err = lambda a: float(np.sqrt(np.mean((a[0].cpu().numpy() - truth) ** 2)))
+    assert err(x) < 0.7 * err(x_fbp), (err(x), err(x_fbp))
+    _, _, E = ph.patch_fista(plan, yt, D, m, st, 5.0, 8.0, 40, fast=False, lipschitz=plan.last_lipschitz,
+                             energy=True)
+    assert np.all(np.diff(E) <= 1e-5 * E[0])

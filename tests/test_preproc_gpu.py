@@ -66,27 +66,52 @@ def test_ring_filter_parity(dev):
     assert rel(got, oracle.ring_filter(sino, 12, obj=obj)) <= TOL_OP
 
 
-def test_fbp_with_hotspot_and_ring_object_parity(dev):
+@pytest.fixture(scope="module")
+def ringed_raw():
     R, N, K = 3, 64, 90
     raw, flats, flat_pos, dark, ang, axis = raw_with_spikes(R, N, K, 3)
     # detector gain errors: the same per-bin factor in every projection -> rings
     gain = 1 + 0.02 * synth.rng_for(10, 3, 7).standard_normal((1, R, N))
     raw = torch.from_numpy(np.clip(np.round(raw.numpy() * gain), 0, 65535).astype(np.uint16))
+    return raw, flats, flat_pos, dark, ang, axis, R, N
+
+
+@pytest.mark.parametrize("hot,width,obj_thr", [(None, 0, None), (0.1, 0, None), (None, 6, None), (None, 6, 0.02),
+                                               (0.1, 6, 0.02)])
+def test_fbp_with_preprocessing_parity(dev, ringed_raw, hot, width, obj_thr):
+    raw, flats, flat_pos, dark, ang, axis, R, N = ringed_raw
     g = ph.Geometry(N, N, N, ang, axis)
     og = oracle.Geom(N, N, N, ang, axis)
     plan = ph.Plan(g, n_slices=R)
     args = dict(raw=raw.to(dev), flats=flats.to(dev), flat_pos=flat_pos, dark=dark.to(dev), method=ph.FBP)
-    x = ph.reconstruct_slices(plan, hot_threshold=0.1, ring_width=6, ring_object_threshold=0.5, **args)
-    y = oracle.normalize_hotspot(raw.numpy(), flats.numpy(), flat_pos, dark.numpy(), 0.1)
+    x = ph.reconstruct_slices(plan, hot_threshold=hot, ring_width=width, ring_object_threshold=obj_thr, **args)
+    if hot is None:
+        y = oracle.normalize(raw.numpy(), flats.numpy(), flat_pos, dark.numpy())
+    else:
+        y = oracle.normalize_hotspot(raw.numpy(), flats.numpy(), flat_pos, dark.numpy(), hot)
     ref = []
     for r in range(R):
-        obj = oracle.ring_object(y[r], og, 0.5)
-        ref.append(oracle.fbp(oracle.ring_filter(y[r], 6, obj=obj), og))
-    assert rel(x, np.stack(ref)) <= TOL_PIPE
-    # the caller's raw buffer is untouched and the plain path still matches its own oracle
-    x0 = ph.reconstruct_slices(plan, **args)
-    ref0 = oracle.fbp_raw(raw.numpy(), flats.numpy(), flat_pos, dark.numpy(), og)
-    assert rel(x0, ref0) <= TOL_PIPE
+        yr = y[r]
+        if width:
+            obj = None if obj_thr is None else oracle.ring_object(yr, og, obj_thr)
+            yr = oracle.ring_filter(yr, width, obj=obj)
+        ref.append(oracle.fbp(yr, og))
+    ref = np.stack(ref)
+    # the same steps through the separate entry points
+    if hot is None:
+        yg = ph.normalize(plan, args["raw"], args["flats"], flat_pos, args["dark"])
+    else:
+        yg = ph.normalize_hotspot(plan, args["raw"], args["flats"], flat_pos, args["dark"], hot)
+    assert rel(yg, y) <= TOL_OP
+    if width:
+        objg = None
+        if obj_thr is not None:
+            x0 = ph.reconstruct_slices(plan, sino=yg.clone(), method=ph.FBP)
+            objg = ph.forward_project(plan, torch.where(x0 > obj_thr, x0, torch.zeros_like(x0)).contiguous())
+        ph.ring_filter(plan, yg, width, obj=objg)
+    xs = ph.reconstruct_slices(plan, sino=yg, method=ph.FBP)
+    assert rel(xs, ref) <= TOL_PIPE, ("separate entry points", rel(xs, ref))
+    assert rel(x, ref) <= TOL_PIPE, ("reconstruct_slices", rel(x, ref), rel(x, xs))
 
 
 def test_cp_with_ring_filter_parity(dev):
