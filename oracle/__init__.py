@@ -283,8 +283,9 @@ def forward_project(img, g: Geom) -> np.ndarray:
 
 
 def fbp(sino, g: Geom) -> np.ndarray:
-    """Filtered backprojection of line integrals [S][K][nb]."""
-    return backproject(fbp_filter(sino, g), g, extended=True)
+    """Filtered backprojection of line integrals [S][K][nb] -> [S][n_y][n_x] ([K][nb] -> [n_y][n_x])."""
+    out = backproject(fbp_filter(sino, g), g, extended=True)
+    return out[0] if np.ndim(sino) == 2 else out
 
 
 def fbp_raw(raw, flats, flat_pos, dark, g: Geom, eps: float = 1e-6) -> np.ndarray:

@@ -81,56 +81,80 @@ __global__ void input_pad_kernel(const float *x, int64_t npix, bf16_t *x8)
 }
 
 // 2x2 max pool: in [b][H][W] (channels c at cs/co) -> out [b][H/2][W/2]
+// 2x2 max-pool; one thread per (output pixel, 8 channels): 4 loads of 16 B, one store of 16 B
 __global__ void pool_fwd_kernel(Act in, int C, bf16_t *out, int ocs, int64_t n)
 {
-    const int h = in.H >> 1, w = in.W >> 1;
+    const int h = in.H >> 1, w = in.W >> 1, G = C >> 3;
     GRID_LOOP(i, n)
     {
-        const int c = (int)(i % C);
-        const int64_t p = i / C;
+        const int g = (int)(i % G);
+        const int64_t p = i / G;
         const int x = (int)(p % w), y = (int)((p / w) % h), b = (int)(p / ((int64_t)w * h));
-        const bf16_t *base = in.p + ((int64_t)(b * in.H + 2 * y) * in.W + 2 * x) * in.cs + in.co + c;
-        float mx = bf2f(base[0]);
-        mx = fmaxf(mx, bf2f(base[in.cs]));
-        mx = fmaxf(mx, bf2f(base[(int64_t)in.W * in.cs]));
-        mx = fmaxf(mx, bf2f(base[(int64_t)in.W * in.cs + in.cs]));
-        out[p * ocs + c] = f2bf(mx);
+        const bf16_t *base = in.p + ((int64_t)(b * in.H + 2 * y) * in.W + 2 * x) * in.cs + in.co + 8 * g;
+        const uint4 q0 = *(const uint4 *)base, q1 = *(const uint4 *)(base + in.cs);
+        const uint4 q2 = *(const uint4 *)(base + (int64_t)in.W * in.cs);
+        const uint4 q3 = *(const uint4 *)(base + (int64_t)in.W * in.cs + in.cs);
+        const bf16_t *e0 = (const bf16_t *)&q0, *e1 = (const bf16_t *)&q1, *e2 = (const bf16_t *)&q2,
+                     *e3 = (const bf16_t *)&q3;
+        uint4 r;
+        bf16_t *er = (bf16_t *)&r;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            er[c] = f2bf(fmaxf(fmaxf(bf2f(e0[c]), bf2f(e1[c])), fmaxf(bf2f(e2[c]), bf2f(e3[c]))));
+        *(uint4 *)(out + p * ocs + 8 * g) = r;
     }
 }
 
-// route the pooled gradient to the first maximum (row-major in the 2x2 window), adding to dE
+// route the pooled gradient to the first maximum (row-major in the 2x2 window), adding to dE;
+// one thread per (output pixel, 8 channels)
 __global__ void pool_bwd_kernel(Act e, bf16_t *de, const bf16_t *dp, int pcs, int C, int64_t n)
 {
-    const int h = e.H >> 1, w = e.W >> 1;
+    const int h = e.H >> 1, w = e.W >> 1, G = C >> 3;
     GRID_LOOP(i, n)
     {
-        const int c = (int)(i % C);
-        const int64_t p = i / C;
+        const int gq = (int)(i % G);
+        const int64_t p = i / G;
         const int x = (int)(p % w), y = (int)((p / w) % h), b = (int)(p / ((int64_t)w * h));
-        const float g = bf2f(dp[p * pcs + c]);
-        const int64_t o0 = ((int64_t)(b * e.H + 2 * y) * e.W + 2 * x) * e.cs + e.co + c;
+        const uint4 gv = *(const uint4 *)(dp + p * pcs + 8 * gq);
+        const bf16_t *ge = (const bf16_t *)&gv;
+        const int64_t o0 = ((int64_t)(b * e.H + 2 * y) * e.W + 2 * x) * e.cs + e.co + 8 * gq;
         const int64_t off[4] = {0, e.cs, (int64_t)e.W * e.cs, (int64_t)e.W * e.cs + e.cs};
-        int arg = 0;
-        float mx = bf2f(e.p[o0]);
-        for (int q = 1; q < 4; ++q) {
-            const float v = bf2f(e.p[o0 + off[q]]);
-            if (v > mx) {
-                mx = v;
-                arg = q;
+        uint4 q[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[k] = *(const uint4 *)(e.p + o0 + off[k]);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float g = bf2f(ge[c]);
+            int arg = 0;
+            float mx = bf2f(((const bf16_t *)&q[0])[c]);
+#pragma unroll
+            for (int k = 1; k < 4; ++k) {
+                const float v = bf2f(((const bf16_t *)&q[k])[c]);
+                if (v > mx) {
+                    mx = v;
+                    arg = k;
+                }
+            }
+            if (mx > 0.0f && g != 0.0f) {
+                bf16_t *t = de + o0 + off[arg] + c;
+                *t = f2bf(bf2f(*t) + g);
             }
         }
-        if (mx > 0.0f && g != 0.0f) de[o0 + off[arg]] = f2bf(bf2f(de[o0 + off[arg]]) + g);
     }
 }
 
-// out = x + bh + sum_c D[p][c] wh[c]   (FP32 accumulation of the BF16 activations)
 __global__ void head_fwd_kernel(const bf16_t *d, int C, const float *wh, const float *bh, const float *x, float *out,
                                 int64_t npix)
 {
     GRID_LOOP(p, npix)
     {
         float s = 0.0f;
-        for (int c = 0; c < C; ++c) s = fmaf(bf2f(d[p * C + c]), wh[c], s);
+        for (int c0 = 0; c0 < C; c0 += 8) {
+            const uint4 q = *(const uint4 *)(d + p * C + c0);
+            const bf16_t *e = (const bf16_t *)&q;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) s = fmaf(bf2f(e[c]), wh[c0 + c], s);
+        }
         out[p] = x[p] + (bh[0] + s);
     }
 }
@@ -175,14 +199,23 @@ __global__ __launch_bounds__(256) void final_mean_kernel(const double *partials,
 }
 
 // dD[p][c] = bf16(dout[p] wh[c]) where D > 0 (C <= 256 threads per pixel chunk)
+// one thread per (pixel, 8 channels)
 __global__ void head_bwd_data_kernel(const bf16_t *d, int C, const float *wh, const float *dout, bf16_t *dd,
                                      int64_t n)
 {
+    const int G = C >> 3;
     GRID_LOOP(i, n)
     {
-        const int c = (int)(i % C);
-        const int64_t p = i / C;
-        dd[i] = f2bf(bf2f(d[i]) > 0.0f ? dout[p] * wh[c] : 0.0f);
+        const int g = (int)(i % G);
+        const int64_t p = i / G;
+        const uint4 q = *(const uint4 *)(d + p * C + 8 * g);
+        const bf16_t *e = (const bf16_t *)&q;
+        const float go = dout[p];
+        uint4 r;
+        bf16_t *er = (bf16_t *)&r;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) er[c] = f2bf(bf2f(e[c]) > 0.0f ? go * wh[8 * g + c] : 0.0f);
+        *(uint4 *)(dd + p * C + 8 * g) = r;
     }
 }
 
@@ -243,15 +276,22 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const float *part, int
     if (threadIdx.x == 0) dst[c] = (float)t;
 }
 
-// dst[n * M + m] = sum_s part[s][m][n]  (consecutive threads read consecutive n)
-__global__ void reduce_splitk_T_kernel(const float *part, int splits, int M, int N, float *dst)
+// dst[n * M + m] = sum_s part[s][m][n].  A workgroup takes 64 consecutive outputs i = m N + n; its
+// 4 wavefronts sum the splits s = w, w + 4, ... (consecutive lanes read consecutive n) and the 4
+// partial sums are added in a fixed order.
+__global__ __launch_bounds__(256) void reduce_splitk_T_kernel(const float *part, int splits, int M, int N, float *dst)
 {
-    GRID_LOOP(i, (int64_t)M * N)
-    {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane, MN = (int64_t)M * N;
+    double s = 0.0;
+    if (i < MN)
+        for (int k = w; k < splits; k += 4) s += part[(int64_t)k * MN + i];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && i < MN) {
         const int m = (int)(i / N), n = (int)(i - (int64_t)m * N);
-        double s = 0.0;
-        for (int k = 0; k < splits; ++k) s += part[(int64_t)k * M * N + i];
-        dst[(int64_t)n * M + m] = (float)s;
+        dst[(int64_t)n * M + m] = (float)(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
     }
 }
 
@@ -316,7 +356,7 @@ hipError_t conv_fwd(const pyhst_unet &net, const Conv &L, Act in, bf16_t *out, i
     switch (tn_for(L.cout)) {
     case 128: return run_gemm<Im2colA, WeightB, StoreAct, 128>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
     case 64: return run_gemm<Im2colA, WeightB, StoreAct, 64>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
-    default: return run_gemm<Im2colA, WeightB, StoreAct, 32>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
+    default: return run_gemm<Im2colA, WeightB, StoreAct, 32, 256>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
     }
 }
 
@@ -326,7 +366,7 @@ hipError_t up_fwd(const pyhst_unet &net, const Up &L, Act in, bf16_t *out, int H
     const int M = in.B * in.H * in.W;
     PlainA A{in};
     WeightB Bw{L.uf, L.cin};
-    StoreUp E{out, H2, W2, ocs, oco, L.cout, net.params + L.b};
+    StoreUp E = store_up(out, H2, W2, ocs, oco, L.cout, net.params + L.b);
     return run_gemm<PlainA, WeightB, StoreUp, 128>(A, Bw, E, M, 4 * L.cout, L.cin, 1, st);
 }
 
@@ -372,7 +412,7 @@ hipError_t conv_bwd(const pyhst_unet &net, const Conv &L, Act x, Act dz, bf16_t 
         if (tn == 128) gemm_kernel<Im2colT, PlainT, StorePartial, 128><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
         else if (tn == 64) gemm_kernel<Im2colT, PlainT, StorePartial, 64><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
         else gemm_kernel<Im2colT, PlainT, StorePartial, 32><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
-        reduce_splitk_T_kernel<<<blocks_for((int64_t)M * N), 256, 0, st>>>(net.part, sp, M, N, net.grads + L.w);
+        reduce_splitk_T_kernel<<<(unsigned)(((int64_t)M * N + 63) / 64), 256, 0, st>>>(net.part, sp, M, N, net.grads + L.w);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = chan_sum(net, dz, L.cout, nullptr, net.grads + L.b, st)) != hipSuccess) return e;
@@ -385,7 +425,7 @@ hipError_t conv_bwd(const pyhst_unet &net, const Conv &L, Act x, Act dz, bf16_t 
         switch (tn_for(N)) {
         case 128: e = run_gemm<Im2colA, WeightB, StoreMasked, 128>(A, Bw, E, M, N, 9 * L.cout, 1, st); break;
         case 64: e = run_gemm<Im2colA, WeightB, StoreMasked, 64>(A, Bw, E, M, N, 9 * L.cout, 1, st); break;
-        default: e = run_gemm<Im2colA, WeightB, StoreMasked, 32>(A, Bw, E, M, N, 9 * L.cout, 1, st); break;
+        default: e = run_gemm<Im2colA, WeightB, StoreMasked, 32, 256>(A, Bw, E, M, N, 9 * L.cout, 1, st); break;
         }
     }
     return e;
@@ -409,7 +449,7 @@ hipError_t up_bwd(const pyhst_unet &net, const Up &L, Act x, Act dy, bf16_t *dx,
         if (tn == 128) gemm_kernel<PlainT, UpGatherT, StorePartial, 128><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
         else if (tn == 64) gemm_kernel<PlainT, UpGatherT, StorePartial, 64><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
         else gemm_kernel<PlainT, UpGatherT, StorePartial, 32><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
-        reduce_splitk_T_kernel<<<blocks_for((int64_t)M * N), 256, 0, st>>>(net.part, sp, M, N, net.grads + L.w);
+        reduce_splitk_T_kernel<<<(unsigned)(((int64_t)M * N + 63) / 64), 256, 0, st>>>(net.part, sp, M, N, net.grads + L.w);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = chan_sum(net, dy, L.cout, nullptr, net.grads + L.b, st)) != hipSuccess) return e;
@@ -420,7 +460,7 @@ hipError_t up_bwd(const pyhst_unet &net, const Up &L, Act x, Act dy, bf16_t *dx,
     switch (tn_for(N)) {
     case 128: return run_gemm<UpGatherA, WeightB, StoreMasked, 128>(A, Bw, E, M, N, 4 * L.cout, 1, st);
     case 64: return run_gemm<UpGatherA, WeightB, StoreMasked, 64>(A, Bw, E, M, N, 4 * L.cout, 1, st);
-    default: return run_gemm<UpGatherA, WeightB, StoreMasked, 32>(A, Bw, E, M, N, 4 * L.cout, 1, st);
+    default: return run_gemm<UpGatherA, WeightB, StoreMasked, 32, 256>(A, Bw, E, M, N, 4 * L.cout, 1, st);
     }
 }
 
@@ -457,7 +497,8 @@ hipError_t forward(pyhst_unet &net, const float *in, int n, float *out, hipStrea
             if ((e = conv_fwd(net, net.enc_b[l], a, net.cat[l].a, net.cat[l].C, 0, st)) != hipSuccess) return e;
             const int c = net.enc_b[l].cout;
             const int64_t np = (int64_t)n * net.pool[l].H * net.pool[l].W * c;
-            pool_fwd_kernel<<<blocks_for(np), 256, 0, st>>>(act(net.cat[l], n), c, net.pool[l].a, net.pool[l].C, np);
+            pool_fwd_kernel<<<blocks_for(np / 8), 256, 0, st>>>(act(net.cat[l], n), c, net.pool[l].a, net.pool[l].C,
+                                                                np / 8);
             cur = act(net.pool[l], n);
         }
     }
@@ -491,8 +532,8 @@ hipError_t backward(pyhst_unet &net, const float *in, const float *target, int n
     // head
     {
         const int C = net.db[0].C;
-        head_bwd_data_kernel<<<blocks_for(npix * C), 256, 0, st>>>(net.db[0].a, C, net.params + net.head_w,
-                                                                   net.dout, net.db[0].g, npix * C);
+        head_bwd_data_kernel<<<blocks_for(npix * C / 8), 256, 0, st>>>(net.db[0].a, C, net.params + net.head_w,
+                                                                       net.dout, net.db[0].g, npix * C / 8);
         Act d0 = act(net.db[0], n);
         if ((e = chan_sum(net, d0, C, net.dout, net.grads + net.head_w, st)) != hipSuccess) return e;
         const int pb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, npix / 256));
@@ -532,8 +573,8 @@ hipError_t backward(pyhst_unet &net, const float *in, const float *target, int n
             // pool of level l-1: add its gradient into the encoder output of level l-1 (cat[l-1] channels [0, c))
             const int c = net.enc_b[l - 1].cout;
             const int64_t np = (int64_t)n * net.pool[l - 1].H * net.pool[l - 1].W * c;
-            pool_bwd_kernel<<<blocks_for(np), 256, 0, st>>>(act(net.cat[l - 1], n), net.cat[l - 1].g,
-                                                            net.pool[l - 1].g, net.pool[l - 1].C, c, np);
+            pool_bwd_kernel<<<blocks_for(np / 8), 256, 0, st>>>(act(net.cat[l - 1], n), net.cat[l - 1].g,
+                                                                net.pool[l - 1].g, net.pool[l - 1].C, c, np / 8);
         }
     }
     return hipGetLastError();

@@ -338,7 +338,7 @@ struct Stager<L, ROWS, true> {
     typename L::Ctx ctx[SLOTS];
     uint4 v[SLOTS];
     int row[SLOTS], kl[SLOTS];
-    __device__ void prep(const L &ld, int row0, int R)
+    __device__ void prep(const L &ld, int row0, int R, int = 0)
     {
 #pragma unroll
         for (int j = 0; j < SLOTS; ++j) {
@@ -364,16 +364,19 @@ struct Stager<L, ROWS, true> {
 template <class L, int ROWS>
 struct Stager<L, ROWS, false> {
     static constexpr int R8 = ROWS / 8, NBLK = R8 * (TK / 8);
-    static_assert(NBLK <= 256, "one 8x8 block per thread");
+    static_assert(NBLK <= 128 && 128 % NBLK == 0, "blocks spread over the workgroup");
+    static constexpr int SP = 256 / NBLK;   // one loading thread every SP threads: all four waves load
     typename L::Ctx ctx;
     uint4 v[8];
     int row, kl;
     bool act;
-    __device__ void prep(const L &ld, int row0, int R)
+    // off: which thread of each group of SP loads (the A and B operands use different ones)
+    __device__ void prep(const L &ld, int row0, int R, int off = 0)
     {
-        act = threadIdx.x < NBLK;
-        kl = (threadIdx.x / R8) * 8;
-        row = (threadIdx.x % R8) * 8;
+        act = (threadIdx.x % SP) == (off % SP);
+        const int blk = threadIdx.x / SP;
+        kl = (blk / R8) * 8;
+        row = (blk % R8) * 8;
         ctx = ld.prep(row0 + row, act ? R : 0);
     }
     __device__ void load(const L &ld, int k0, int kend)
@@ -393,17 +396,17 @@ struct Stager<L, ROWS, false> {
 // One workgroup: a TM x TN tile of C over the K range [kz * k_split, (kz+1) * k_split).
 // The next K tile is fetched into registers while the current one is multiplied from
 // LDS; two LDS buffers, one barrier per K tile.
-template <class AL, class BL, class EP, int TN>
+template <class AL, class BL, class EP, int TN, int TMv = TM>
 __global__ __launch_bounds__(256) void gemm_kernel(AL A, BL B, EP E, int M, int N, int K, int k_split)
 {
     constexpr int WMW = WaveGrid<TN>::WM, WNW = WaveGrid<TN>::WN;
-    constexpr int WTM = TM / WMW, WTN = TN / WNW;
+    constexpr int WTM = TMv / WMW, WTN = TN / WNW;
     constexpr int BM = WTM / 32, BN = WTN / 32;
-    __shared__ __attribute__((aligned(16))) bf16_t sA[2][TM * LDK];
+    __shared__ __attribute__((aligned(16))) bf16_t sA[2][TMv * LDK];
     __shared__ __attribute__((aligned(16))) bf16_t sB[2][TN * LDK];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WNW, wn = wave % WNW;
-    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+    const int m0 = blockIdx.x * TMv, n0 = blockIdx.y * TN;
     const int kbeg = blockIdx.z * k_split;
     const int kend = min(K, kbeg + k_split);
     f32x16 acc[BM][BN];
@@ -414,10 +417,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(AL A, BL B, EP E, int M, int 
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-    Stager<AL, TM> ga;
+    Stager<AL, TMv> ga;
     Stager<BL, TN> gb;
-    ga.prep(A, m0, M);
-    gb.prep(B, n0, N);
+    ga.prep(A, m0, M, 0);
+    gb.prep(B, n0, N, 1);
     if (kbeg < kend) {
         ga.load(A, kbeg, kend);
         gb.load(B, kbeg, kend);
@@ -476,18 +479,23 @@ struct StoreAct {     // y[m][n] = bf16(relu(v + bias[n]))
 
 struct StoreUp {      // n = (d, co): y[(b, 2y+dy, 2x+dx)][co] = bf16(relu(v + bias[co]))
     bf16_t *y;
-    int H2, W2, cs, co, Cout;
+    int H2, W2, cs, co, lgCout;
+    FastDiv fhw, fw;      // low-resolution h*w and w
     const float *bias;
     __device__ void operator()(int m, int n, float v) const
     {
-        const int d = n / Cout, c = n - d * Cout;
-        const int h = H2 >> 1, w = W2 >> 1;
-        const int b = m / (h * w), r = m - b * (h * w);
-        const int yy = 2 * (r / w) + (d >> 1), xx = 2 * (r % w) + (d & 1);
+        const int d = n >> lgCout, c = n & ((1 << lgCout) - 1);
+        const uint32_t b = fdiv((uint32_t)m, fhw), r = (uint32_t)m - b * fhw.d;
+        const uint32_t yl = fdiv(r, fw), xl = r - yl * fw.d;
+        const int yy = 2 * (int)yl + (d >> 1), xx = 2 * (int)xl + (d & 1);
         v = fmaxf(v + bias[c], 0.0f);
         y[((int64_t)(b * H2 + yy) * W2 + xx) * cs + co + c] = f2bf(v);
     }
 };
+inline StoreUp store_up(bf16_t *y, int H2, int W2, int cs, int co, int Cout, const float *bias)
+{
+    return StoreUp{y, H2, W2, cs, co, ilog2(Cout), make_fastdiv((H2 >> 1) * (W2 >> 1)), make_fastdiv(W2 >> 1), bias};
+}
 
 struct StoreMasked {  // dx[m][n] = bf16(v) where act[m][n] > 0, else 0
     bf16_t *dx;
@@ -510,14 +518,14 @@ struct StorePartial { // part[kz][m][n] = v
     }
 };
 
-template <class AL, class BL, class EP, int TN>
+template <class AL, class BL, class EP, int TN, int TMv = TM>
 inline hipError_t run_gemm(const AL &a, const BL &b, const EP &e, int M, int N, int K, int splits, hipStream_t st)
 {
     int k_split = (K + splits - 1) / splits;
     k_split = (k_split + TK - 1) / TK * TK;
     splits = (K + k_split - 1) / k_split;
-    dim3 grid((M + TM - 1) / TM, (N + TN - 1) / TN, splits);
-    gemm_kernel<AL, BL, EP, TN><<<grid, 256, 0, st>>>(a, b, e, M, N, K, k_split);
+    dim3 grid((M + TMv - 1) / TMv, (N + TN - 1) / TN, splits);
+    gemm_kernel<AL, BL, EP, TN, TMv><<<grid, 256, 0, st>>>(a, b, e, M, N, K, k_split);
     return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 def test_cv_error_parity(dev):
     N, K, nb = 40, 24, 50
     rng = synth.rng_for(8, 0, 0)
-    ang = np.sort(rng.uniform(0, np.pi, K))
+    ang = synth.uniform_angles(K) + rng.uniform(-0.3, 0.3, K) * np.pi / K   # jittered, still covering 180 deg
     sh = rng.normal(0, 0.5, K)
     g = ph.Geometry(N, N, nb, ang, 24.3, axis_shift=sh, pixel_size=1.1)
     og = oracle.Geom(N, N, nb, ang, 24.3, shifts=sh, pixel_size=1.1)

@@ -89,14 +89,15 @@ def test_fbp_with_preprocessing_parity(dev, ringed_raw, hot, width, obj_thr):
         y = oracle.normalize(raw.numpy(), flats.numpy(), flat_pos, dark.numpy())
     else:
         y = oracle.normalize_hotspot(raw.numpy(), flats.numpy(), flat_pos, dark.numpy(), hot)
-    ref = []
+    ys = []
     for r in range(R):
         yr = y[r]
         if width:
             obj = None if obj_thr is None else oracle.ring_object(yr, og, obj_thr)
             yr = oracle.ring_filter(yr, width, obj=obj)
-        ref.append(oracle.fbp(yr, og))
-    ref = np.stack(ref)
+        ys.append(yr)
+    ref = oracle.fbp(np.stack(ys), og)
+    assert ref.shape == (R, N, N)
     # the same steps through the separate entry points
     if hot is None:
         yg = ph.normalize(plan, args["raw"], args["flats"], flat_pos, args["dark"])
