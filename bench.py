@@ -245,6 +245,148 @@ def run_single(args):
     print(json.dumps(res), flush=True)
 
 
+def _timed(stream, fn, reps):
+    import torch
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    fn()
+    stream.synchronize()
+    e[0].record(stream)
+    for _ in range(reps):
+        fn()
+    e[1].record(stream)
+    stream.synchronize()
+    return e[0].elapsed_time(e[1]) / reps
+
+
+def run_preproc(args):
+    """Preprocessing of section 2.3 inside the batched FBP workload (64 x 2048^2, 1800 angles, raw uint16):
+    time per step of the plain fused path, with the hot-spot filter, with the ring filter, and with the
+    ring filter plus thresholded-object subtraction (one HIP graph per step each)."""
+    import torch
+    import synth
+    import paper_1306_1392_amd as ph
+    dev = torch.device("cuda:0")
+    R, N, K = args.slices, args.n, args.angles
+    cfg = quick_data(R, N, K, dev) if args.quick_data else synth.cfg_batched_raw(R=R, N=N, K=K, device=dev)
+    plan = ph.Plan(ph.Geometry(N, N, N, cfg["angles"], cfg["axis"]), n_slices=R)
+    out = torch.empty(plan.img_shape(), device=dev, dtype=torch.float32)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    variants = {"plain": {}, "hot_spot": {"hot_threshold": 0.05}, "ring": {"ring_width": 8},
+                "ring_object": {"ring_width": 8, "ring_object_threshold": 0.02},
+                "hot_spot_ring_object": {"hot_threshold": 0.05, "ring_width": 8, "ring_object_threshold": 0.02}}
+    res_ms = {}
+    for name, kw in variants.items():
+        work = torch.empty(ph.work_bytes(plan, raw=cfg["raw"], method=ph.FBP, **kw), device=dev, dtype=torch.uint8)
+
+        def step():
+            ph.reconstruct_slices(plan, raw=cfg["raw"], flats=cfg["flats"], flat_pos=cfg["flat_pos"], dark=cfg["dark"],
+                                  method=ph.FBP, out=out, work=work, use_graph=True, stream=stream, **kw)
+
+        res_ms[name] = round(_timed(stream, step, max(3, args.steps)), 3)
+        del work
+        log(f"preproc: {name} {res_ms[name]} ms")
+    U = float(R) * N * N * K
+    res = {"metric": "FBP step time with the preprocessing of section 2.3", "value": res_ms["hot_spot_ring_object"],
+           "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": "f32",
+           "data": "synthetic" + (" (random counts)" if args.quick_data else ""),
+           "config": {"workload": f"{R} slices of {N}x{N}, {K} angles, raw uint16; hot-spot threshold 0.05, ring "
+                                  f"half-width 8, object threshold 0.02"},
+           "ms_per_step": res_ms, "gups": {k: round(U / (v * 1e-3) / 1e9, 1) for k, v in res_ms.items()}}
+    print(json.dumps(res), flush=True)
+
+
+def run_beta(args):
+    """Choice of beta (section 3.1) on the TV workload (1024^2, 128 angles, Poisson 1e4): FISTA (300
+    iterations, 10 inner prox steps) at 8 beta values, cross-validation over 3 excluded projections
+    (24 more reconstructions) and the decoherence estimator; whole sweep timed."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1306_1392_amd as ph
+    from paper_1306_1392_amd.beta import select_beta
+    dev = torch.device("cuda:0")
+    d = synth.cfg_tv_sparse(N=1024, K=128, device=dev)
+    g = ph.Geometry(1024, 1024, 1024, d["angles"], d["axis"])
+    y = d["y"][None].contiguous()
+    betas = np.geomspace(0.01, 3.0, 8)
+    select_beta(g, y, betas[:1], n_iter=5)        # warm-up (plans, graphs of the kernels)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = select_beta(g, y, betas, n_iter=300, n_inner=10)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    truth = d["truth"].to(dev).float() if torch.is_tensor(d.get("truth")) else None
+    res = {"metric": "beta sweep time (cross-validation + decoherence)", "value": round(dt, 3), "unit": "s",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "1024x1024, 1024 bins, 128 angles, Poisson 1e4; FISTA 300 iterations, 10 inner; "
+                                  "8 betas x (1 + 3 excluded projections) reconstructions"},
+           "reconstructions": int(len(betas) * 4 + 1), "betas": [float(b) for b in betas],
+           "cv": [float(v) for v in r["cv"][:, 0]], "e_cohe": [float(v) for v in r["e_cohe"][:, 0]],
+           "beta_cv": float(betas[int(np.argmin(r["cv"][:, 0]))]),
+           "beta_ecohe": float(betas[int(np.argmin(np.abs(r["e_cohe"][:, 0])))])}
+    if truth is not None:
+        rm = torch.sqrt(((r["x"][:, 0] - truth) ** 2).mean(dim=(1, 2))).cpu().numpy()
+        res["rmse_vs_truth"] = [float(v) for v in rm]
+        res["beta_truth"] = float(betas[int(np.argmin(rm))])
+    print(json.dumps(res), flush=True)
+
+
+def run_patch(args):
+    """Overlapping-patch dictionary prior (section 3.2) at the paper's experiment size: 2048^2 slice,
+    150 projections, 8x8 patches every 4 pixels, 128 atoms (64 DCT + 64 random), FISTA 150 iterations
+    (its Lipschitz estimate included).  The oracle beside it: one iteration of the NumPy oracle on a
+    128^2 / 24-angle problem, scaled by the number of coefficients."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1306_1392_amd as ph
+    from synth import dct_dictionary
+    dev = torch.device("cuda:0")
+    N, K, m, st, n_it = 2048, 150, 8, 4, 150
+    ang = synth.uniform_angles(K)
+    ell = synth.random_ellipses(synth.rng_for(12, 0, 0), 20)
+    y = synth.ellipse_sinogram(ell, ang, N, (N - 1) / 2, N, device=dev)
+    y = (y + 0.02 * float(y.max()) * torch.randn(y.shape, device=dev, dtype=y.dtype,
+                                                  generator=torch.Generator(device=dev).manual_seed(3))).float()
+    yt = y[None].contiguous()
+    plan = ph.Plan(ph.Geometry(N, N, N, ang, (N - 1) / 2))
+    D = torch.from_numpy(dct_dictionary(m, extra=64, seed=3).astype(np.float32)).to(dev)
+    ph.patch_fista(plan, yt, D, m, st, 5.0, 8.0, 2)              # warm-up + Lipschitz estimate
+    Lf = plan.last_lipschitz
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e[0].record()
+    x, W = ph.patch_fista(plan, yt, D, m, st, 5.0, 8.0, n_it, lipschitz=Lf)
+    e[1].record()
+    torch.cuda.synchronize()
+    ms = e[0].elapsed_time(e[1])
+    n_coef = W.numel()
+    res = {"metric": "patch-prior FISTA time per iteration", "value": round(ms / n_it, 3), "unit": "ms",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{N}x{N}, {K} angles, 20-ellipse phantom, 2 % noise; {m}x{m} patches every {st} px, "
+                                  f"128 atoms, rho 5, beta 8, {n_it} FISTA iterations"},
+           "coefficients": n_coef, "patches": int(W.shape[1]), "total_s": round(ms / 1e3, 3), "lipschitz": Lf,
+           "nonzero_fraction": float((W != 0).float().mean())}
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle.patches import PatchGrid, PatchProblem, fista
+        n2, k2 = 128, 24
+        og = oracle.Geom(n2, n2, n2, synth.uniform_angles(k2), (n2 - 1) / 2)
+        ys = synth.ellipse_sinogram(ell, og.angles, n2, og.axis, n2).numpy()
+        prob = PatchProblem(PatchGrid(n2, n2, m, st), dct_dictionary(m, extra=64, seed=3), ys, rho=5.0, beta=8.0,
+                            project=lambda v: oracle.forward_project(v, og), backproject=lambda r: oracle.backproject(r, og))
+        t0 = time.time()
+        fista(prob, 3, 1e4)
+        dt = (time.time() - t0) / 3
+        scale = n_coef / (prob.g.n_p * 128)
+        res["cpu_baseline"] = {"value": round(dt * scale * 1e3, 1), "unit": "ms", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"3 iterations of the NumPy oracle at {n2}^2 / {k2} angles ({dt:.3f} s each), "
+                                         f"scaled by the coefficient count ({scale:.0f}x)"}
+    print(json.dumps(res), flush=True)
+
+
 def run_tv(args):
     """TV-regularised sparse-angle reconstruction: 1024^2, 128 projections, Poisson data at 1e4
     photons, 300 Chambolle-Pock iterations (lambda 0.01) replayed as one HIP graph."""
@@ -639,7 +781,7 @@ def main():
                     help="also run a plain 2 GiB device copy (reference kernel for HBM byte counters)")
     ap.add_argument("--tile-sweep", action="store_true", help="time the backprojector for every tile shape")
     ap.add_argument("--peaks", action="store_true", help="run the roofline microbenchmarks")
-    ap.add_argument("--workload", default="fbp2048", choices=["fbp2048", "single", "uneven", "tv", "cnn", "learned"],
+    ap.add_argument("--workload", default="fbp2048", choices=["fbp2048", "single", "uneven", "tv", "cnn", "learned", "preproc", "beta", "patch"],
                     help="fbp2048: the headline batch; uneven / tv: the other measured workloads")
     ap.add_argument("--uneven-slices", type=int, default=500)
     ap.add_argument("--learned-train", type=int, default=10000)
@@ -663,6 +805,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "single":
         return run_single(args)
+    if args.workload == "preproc":
+        return run_preproc(args)
+    if args.workload == "beta":
+        return run_beta(args)
+    if args.workload == "patch":
+        return run_patch(args)
     if args.workload == "uneven":
         return run_uneven(args)
     if args.workload == "tv":

@@ -11,7 +11,7 @@ What each function follows:
                        -log (section 2.3 processing pipe; Beer-Lambert)
   angle_weights        quadrature weight of each projection (mid-point rule)
   half_acq_layout      360 degree scan with the axis near a detector border,
-                       detector "virtually doubled" (section 2.1)
+                       whose usable detector width is doubled (section 2.1)
   ramp_filter / fbp_filter / fbp
                        filtered backprojection (section 2.3, last paragraph):
                        Ram-Lak kernel, direct convolution

@@ -151,17 +151,3 @@ def fista(prob: PatchProblem, n_iter: int, L: float, fast: bool = True, energy: 
             E.append(prob.energy(W))
     _, x = prob.images(W)
     return (W, x, np.asarray(E)) if energy else (W, x)
-
-
-def dct_dictionary(m: int, extra: int = 0, seed: int = 0) -> np.ndarray:
-    """A fixed stand-in dictionary: the m*m separable DCT-II atoms (unit norm) followed by `extra`
-    seeded random unit-norm atoms (over-complete when extra > 0).  The paper's learned basis is not
-    available."""
-    k = np.arange(m)
-    C = np.cos(np.pi * (k[None, :] + 0.5) * k[:, None] / m)
-    C /= np.linalg.norm(C, axis=1, keepdims=True)
-    atoms = np.einsum("ai,bj->abij", C, C).reshape(m * m, m * m)
-    if extra:
-        R = np.random.default_rng(seed).standard_normal((extra, m * m))
-        atoms = np.vstack([atoms, R / np.linalg.norm(R, axis=1, keepdims=True)])
-    return atoms

@@ -107,7 +107,7 @@ int setup_geom(const pyhst_geom &in, GeoHost &h)
     h.g.angles = nullptr;
     h.g.axis_shift = nullptr;
 
-    // angular coverage (section 2.1): at least 180 degrees, 360 for 360 degree scans
+    // angular coverage (section 2.1): a scan period of 180 degrees, 360 for 360 degree scans
     const double period = in.scan == PYHST_SCAN_180 ? PI : 2.0 * PI;
     std::vector<int> ord(K);
     std::iota(ord.begin(), ord.end(), 0);

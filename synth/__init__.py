@@ -23,3 +23,4 @@ from .configs import (  # noqa: F401
     cfg_batched_raw,
     cfg_tv_sparse,
 )
+from .dictionary import dct_dictionary  # noqa: F401,E402

@@ -6,7 +6,8 @@ import pytest
 import oracle
 import synth
 from oracle import Geom
-from oracle.patches import PatchGrid, PatchProblem, dct_dictionary, fista, soft
+from oracle.patches import PatchGrid, PatchProblem, fista, soft
+from synth import dct_dictionary
 
 
 def test_core_map_by_hand():

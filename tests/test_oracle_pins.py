@@ -258,7 +258,7 @@ def test_half_acq_weights_sum_to_one(right):
 
 @pytest.mark.parametrize("right,delta", [(True, 10.0), (False, 10.0), (True, 20.5), (False, 20.5)])
 def test_half_acq_mirror_consistency(right, delta):
-    """A 360 degree half-acquisition (detector virtually doubled, section 2.1) of noise-free
+    """A 360 degree half-acquisition (usable detector width doubled, section 2.1) of noise-free
     data reconstructs exactly what a 180 degree full-detector scan with the same bin
     alignment does: the lines at (theta, u) and (theta + pi, -u) coincide and their
     weights sum to one, so the identity holds to rounding when 2c is an integer."""

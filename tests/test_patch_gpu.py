@@ -8,7 +8,8 @@ import torch
 import oracle
 import synth
 import paper_1306_1392_amd as ph
-from oracle.patches import PatchGrid, PatchProblem, dct_dictionary, fista
+from oracle.patches import PatchGrid, PatchProblem, fista
+from synth import dct_dictionary
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
