@@ -350,13 +350,14 @@ Act act(const Buf &b, int n, int co = 0, bool grad = false) { return Act{grad ? 
 hipError_t conv_fwd(const pyhst_unet &net, const Conv &L, Act in, bf16_t *out, int ocs, int oco, hipStream_t st)
 {
     const int M = in.B * in.H * in.W;
+    StoreAct E{out, ocs, oco, net.params + L.b, 1};
+    if (conv3x3_direct(L.cin, L.cout)) return run_conv3x3(in, L.cin, L.wf, E, L.cout, st);
     Im2colA A = im2col_a(in, L.cin);
     WeightB Bw{L.wf, 9 * L.cin};
-    StoreAct E{out, ocs, oco, net.params + L.b, 1};
     switch (tn_for(L.cout)) {
     case 128: return run_gemm<Im2colA, WeightB, StoreAct, 128>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
     case 64: return run_gemm<Im2colA, WeightB, StoreAct, 64>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
-    default: return run_gemm<Im2colA, WeightB, StoreAct, 32, 256>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
+    default: return run_gemm<Im2colA, WeightB, StoreAct, 32>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
     }
 }
 
@@ -419,13 +420,14 @@ hipError_t conv_bwd(const pyhst_unet &net, const Conv &L, Act x, Act dz, bf16_t 
     if (dx) {
         // dX[pix][ci] = sum_{tap', co} dZ[pix + off(tap')][co] Wb[ci][tap'][co], masked by X > 0
         const int M = npix, N = L.cin;
+        StoreMasked E{dx, dxcs, dxco, x.p, x.cs, x.co};
+        if (conv3x3_direct(L.cout, N)) return run_conv3x3(dz, L.cout, L.wb, E, N, st);
         Im2colA A = im2col_a(dz, L.cout);
         WeightB Bw{L.wb, 9 * L.cout};
-        StoreMasked E{dx, dxcs, dxco, x.p, x.cs, x.co};
         switch (tn_for(N)) {
         case 128: e = run_gemm<Im2colA, WeightB, StoreMasked, 128>(A, Bw, E, M, N, 9 * L.cout, 1, st); break;
         case 64: e = run_gemm<Im2colA, WeightB, StoreMasked, 64>(A, Bw, E, M, N, 9 * L.cout, 1, st); break;
-        default: e = run_gemm<Im2colA, WeightB, StoreMasked, 32, 256>(A, Bw, E, M, N, 9 * L.cout, 1, st); break;
+        default: e = run_gemm<Im2colA, WeightB, StoreMasked, 32>(A, Bw, E, M, N, 9 * L.cout, 1, st); break;
         }
     }
     return e;
@@ -460,7 +462,7 @@ hipError_t up_bwd(const pyhst_unet &net, const Up &L, Act x, Act dy, bf16_t *dx,
     switch (tn_for(N)) {
     case 128: return run_gemm<UpGatherA, WeightB, StoreMasked, 128>(A, Bw, E, M, N, 4 * L.cout, 1, st);
     case 64: return run_gemm<UpGatherA, WeightB, StoreMasked, 64>(A, Bw, E, M, N, 4 * L.cout, 1, st);
-    default: return run_gemm<UpGatherA, WeightB, StoreMasked, 32, 256>(A, Bw, E, M, N, 4 * L.cout, 1, st);
+    default: return run_gemm<UpGatherA, WeightB, StoreMasked, 32>(A, Bw, E, M, N, 4 * L.cout, 1, st);
     }
 }
 
