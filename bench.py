@@ -296,6 +296,38 @@ def run_preproc(args):
     print(json.dumps(res), flush=True)
 
 
+def run_fp(args):
+    """Matched forward projector alone, next to the backprojector in the same launch configuration:
+    1024^2 x 128 angles (the TV workload) and 64 x 2048^2 x 1800 angles (the FBP batch).  Unit:
+    voxel-angle pairs per second (the same count as the backprojector's updates)."""
+    import torch
+    import synth
+    import paper_1306_1392_amd as ph
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    cases = {}
+    for name, (R, N, K) in {"tv1024": (1, 1024, 128), "fbp2048": (args.slices, 2048, 1800)}.items():
+        plan = ph.Plan(ph.Geometry(N, N, N, synth.uniform_angles(K), (N - 1) / 2 + 3.5), n_slices=R)
+        g = torch.Generator(device=dev)
+        g.manual_seed(7)
+        img = torch.rand(plan.img_shape(), device=dev, generator=g)
+        sino = torch.empty(plan.sino_shape(), device=dev)
+        reps = 20 if R == 1 else 3
+        fp_ms = _timed(stream, lambda: ph.forward_project(plan, img, out=sino, stream=stream), reps)
+        bp_ms = _timed(stream, lambda: ph.backproject(plan, sino, 0, out=img, stream=stream), reps)
+        U = float(R) * N * N * K
+        cases[name] = {"slices": R, "n": N, "angles": K, "fp_ms": round(fp_ms, 3), "bp_ms": round(bp_ms, 3),
+                       "fp_gups": round(U / (fp_ms * 1e-3) / 1e9, 1), "bp_gups": round(U / (bp_ms * 1e-3) / 1e9, 1)}
+        log(f"fp: {name} {cases[name]}")
+        del img, sino, plan
+    res = {"metric": "forward projector GUPS (voxel-angle pairs/s)", "value": cases["fbp2048"]["fp_gups"],
+           "unit": "GUPS", "higher_is_better": True, "n_gpus": 1, "dtype": "f32", "data": "synthetic (uniform random image)",
+           "config": {"workload": "A = s^2 B^T alone: 1024^2 x 128 angles and 64 x 2048^2 x 1800 angles"},
+           "cases": cases}
+    print(json.dumps(res), flush=True)
+
+
 def run_beta(args):
     """Choice of beta (section 3.1) on the TV workload (1024^2, 128 angles, Poisson 1e4): FISTA (300
     iterations, 10 inner prox steps) at 8 beta values, cross-validation over 3 excluded projections
@@ -781,7 +813,7 @@ def main():
                     help="also run a plain 2 GiB device copy (reference kernel for HBM byte counters)")
     ap.add_argument("--tile-sweep", action="store_true", help="time the backprojector for every tile shape")
     ap.add_argument("--peaks", action="store_true", help="run the roofline microbenchmarks")
-    ap.add_argument("--workload", default="fbp2048", choices=["fbp2048", "single", "uneven", "tv", "cnn", "learned", "preproc", "beta", "patch"],
+    ap.add_argument("--workload", default="fbp2048", choices=["fbp2048", "single", "uneven", "tv", "cnn", "learned", "preproc", "beta", "patch", "fp"],
                     help="fbp2048: the headline batch; uneven / tv: the other measured workloads")
     ap.add_argument("--uneven-slices", type=int, default=500)
     ap.add_argument("--learned-train", type=int, default=10000)
@@ -809,6 +841,8 @@ def main():
         return run_preproc(args)
     if args.workload == "beta":
         return run_beta(args)
+    if args.workload == "fp":
+        return run_fp(args)
     if args.workload == "patch":
         return run_patch(args)
     if args.workload == "uneven":

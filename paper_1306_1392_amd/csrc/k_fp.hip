@@ -1,90 +1,128 @@
-// Matched forward projection A = s^2 B^T, evaluated ray-driven as a gather
-// (section 2.3: the projector used inside the iterations; eq. (1)).
+// Matched forward projection A = s^2 B^T (section 2.3: the projector used
+// inside the iterations; eq. (1)), evaluated ray-driven as a gather so that
+// every bin is summed by one lane in a fixed order (deterministic).
 //
 // The paper projects an image held in a texture, which interpolates the image
-// along rays and is not the transpose of the pixel-driven backprojector.
-// Here every detector bin j of projection k sums exactly the pixels whose hat
-// weight hat(t_k(px) - j) is non-zero: walking the dominant image axis
-// (rows when |cos| >= |sin|, else columns), at most ceil(2 / (s |cos|)) pixels
-// per line can touch the bin.  Their positions are anchored in FP64 per line
-// (t reaches ~2000 bins, where FP32 would lose 2e-4 bin); the weights are FP32.
+// along rays and is not the transpose of the pixel-driven backprojector.  Here
+// bin j of projection k sums exactly the pixels whose hat weight
+// hat(t_k(px) - j) is non-zero.  Along an image line of the dominant axis
+// (rows when |cos| >= |sin|, else columns) t is linear in the position,
+// t - j = a (i - u_j), a = s cos (or s sin), so the bin touches the positions
+// i in (u_j - 1/|a|, u_j + 1/|a|): at most ceil(2/|a|) of them.
 //
-// Launch: workgroup = one projection x 64 bins; its 4 wavefronts take every
-// fourth image line and their partial sums are added in a fixed order (LDS),
-// so one slice already gives nb/64 x K workgroups and the result is deterministic.
+// gfx950 layout.  Workgroup = 4 wavefronts = 4 projections x 64 bins of one
+// slice; lane = bin.  A wavefront walks the lines of its projection in blocks
+// of RB: for each block it stages the covering segment of every line (SEG
+// positions, zero outside the image) in LDS with coalesced loads, then every
+// lane reads its 2-3 candidates per line from LDS.  Coordinates: per (lane,
+// line block) the crossing u of the block's first line is computed in FP64 and
+// split into an integer base and an FP32 remainder; inside the block u advances
+// by an FP32 slope, so every FP32 quantity stays below RB + 2 (ulp < 2e-6).
+// Per candidate: offset, |.|, max, LDS read, FMA.
 #include "internal.hpp"
 
 namespace pyhst {
 
 namespace {
 
+constexpr int RB = 16;   // lines per staged block
+
+// segment length (positions) that covers 64 bins x RB lines of one projection for pixel size s:
+// 63/|a| + (RB - 1) |slope| + 2/|a| + 4 with |a| >= s / sqrt(2) and |slope| <= 1
+inline int fp_seg(double s)
+{
+    const double ainv = 1.4142135623730951 / s;
+    int seg = (int)std::ceil(65.0 * ainv + (RB - 1) + 4.0);
+    return (seg + 3) & ~3;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restrict__ img, float *__restrict__ out,
-                                                 float alpha, CpDual cp, int k0)
+                                                 float alpha, CpDual cp, int k0, int seg_len)
 {
-    __shared__ float part[3][64];
+    extern __shared__ float stage[];   // [4 waves][RB][seg_len]
     const int slice = blockIdx.z;
     const SliceDev sd = T.slc[slice];
     const GeoDev &g = T.geo[sd.g];
     const int K = g.K, nb = g.nb, nx = g.nx, ny = g.ny;
-    const int k = blockIdx.y + k0;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int k = k0 + blockIdx.y * 4 + wv;
     const int j = blockIdx.x * 64 + lane;
-    if (k >= K || blockIdx.x * 64 >= nb) return;   // uniform over the workgroup
-
-    const double c = T.cosd[g.ang_off + k], sn = T.sind[g.ang_off + k];
-    const double s = g.s;
-    const double off = g.axis + T.shiftd[g.ang_off + k] - (double)j;   // t - j = s (x c + y sn) + off
-    const double cx = 0.5 * (nx - 1), cy = 0.5 * (ny - 1);
+    // MODE 3 projects the single projection k0 (wavefront 0 only)
+    const bool wave_on = k < K && (MODE != 3 || wv == 0) && blockIdx.x * 64 < nb;
+    float *seg = stage + wv * RB * seg_len;
     const float *im = img + sd.img_off;
-    float acc = 0.0f;
 
-    if (fabs(c) >= fabs(sn)) {
-        // walk rows (the 4 wavefronts take rows wv, wv + 4, ...): along a row
-        // t - j = s c (ix - cx) + B(iy), B(iy) = off + s sn (iy - cy)
-        const double sc = s * c;
-        const double rho = 1.0 / fabs(sc);
-        const int ncand = (int)ceil(2.0 * rho);
-        const double du = -(s * sn) / sc;                 // change of the crossing position per row
-        const double u0 = cx - (off - s * sn * cy) / sc;  // crossing ix (real) of row 0
-        const float scf = (float)sc;
-        for (int iy = wv; iy < ny; iy += 4) {
-            const double u = fma((double)iy, du, u0);
-            const double fl = floor(u - rho);
-            const int i0 = (int)fl + 1;
-            float d = (float)((fl + 1.0) - u) * scf;      // t - j at pixel i0
-            const float *rowp = im + (int64_t)iy * nx;
-            for (int n = 0; n < ncand; ++n, d += scf) {
-                const int ix = i0 + n;
-                const float w = fmaxf(0.0f, 1.0f - fabsf(d));
-                if ((unsigned)ix < (unsigned)nx) acc = fmaf(w, rowp[ix], acc);
+    // projection geometry (wave-uniform); t = s (x c + y sn) + axis + shift
+    const int kk = wave_on ? k : 0;
+    const double c = T.cosd[g.ang_off + kk], sn = T.sind[g.ang_off + kk];
+    const double s = g.s;
+    const double cx = 0.5 * (nx - 1), cy = 0.5 * (ny - 1);
+    const double t0 = g.axis + T.shiftd[g.ang_off + kk];
+    const bool rows = fabs(c) >= fabs(sn);
+    // along a line: t - j = a (i - u), u(line) = (j - t0 + a ci + bb cl - bb line) / a, where a and ci
+    // belong to the axis walked along the line and bb and cl to the other one
+    const double a = rows ? s * c : s * sn;
+    const double bb = rows ? s * sn : s * c;
+    const double ci = rows ? cx : cy, cl = rows ? cy : cx;
+    const int n_lines = rows ? ny : nx;
+    const double rho = 1.0 / fabs(a);
+    const int ncand = (int)ceil(2.0 * rho);
+    const double slope = -bb / a;                          // du per line
+    const double u_first = ((double)j - t0 + a * ci + bb * cl) / a;   // u at line 0
+    const float af = (float)a, rhof = (float)rho, slopef = (float)slope;
+    const int lines_max = max(nx, ny);
+
+    float acc = 0.0f;
+    for (int l0 = 0; l0 < lines_max; l0 += RB) {
+        const bool blk_on = wave_on && l0 < n_lines;
+        // lane's crossing at the block's first line: FP64, split into base + remainder
+        const double ub = fma((double)l0, slope, u_first);
+        const double ubase = floor(ub);
+        const float rem = (float)(ub - ubase);
+        // segment start: lowest candidate over the wave's 64 bins and RB lines
+        double lo = fmin(ub, ub + (RB - 1) * slope) - rho;
+        for (int off = 32; off > 0; off >>= 1) lo = fmin(lo, __shfl_xor(lo, off, 64));
+        const int seg0 = (int)floor(lo) - 1;
+        __syncthreads();   // the previous block's reads are done
+        if (blk_on) {
+            if (rows) {
+                for (int r = 0; r < RB; ++r) {
+                    const int line = l0 + r;
+                    const float *src = im + (int64_t)line * nx;
+                    for (int p = lane; p < seg_len; p += 64) {
+                        const int pos = seg0 + p;
+                        seg[r * seg_len + p] = (line < ny && (unsigned)pos < (unsigned)nx) ? src[pos] : 0.0f;
+                    }
+                }
+            } else {
+                // columns: 16 lanes read 16 neighbouring columns of one row (64 B), 4 rows per step
+                const int r = lane & 15;
+                const int line = l0 + r;
+                for (int p = lane >> 4; p < seg_len; p += 4) {
+                    const int pos = seg0 + p;
+                    seg[r * seg_len + p] =
+                        (line < nx && (unsigned)pos < (unsigned)ny) ? im[(int64_t)pos * nx + line] : 0.0f;
+                }
             }
         }
-    } else {
-        // walk columns: along a column, t - j = s sn (iy - cy) + C(ix), C(ix) = off + s c (ix - cx)
-        const double ss = s * sn;
-        const double rho = 1.0 / fabs(ss);
-        const int ncand = (int)ceil(2.0 * rho);
-        const double dv = -(s * c) / ss;
-        const double v0 = cy - (off - s * c * cx) / ss;
-        const float ssf = (float)ss;
-        for (int ix = wv; ix < nx; ix += 4) {
-            const double v = fma((double)ix, dv, v0);
-            const double fl = floor(v - rho);
-            const int i0 = (int)fl + 1;
-            float d = (float)((fl + 1.0) - v) * ssf;
-            for (int n = 0; n < ncand; ++n, d += ssf) {
-                const int iy = i0 + n;
-                const float w = fmaxf(0.0f, 1.0f - fabsf(d));
-                if ((unsigned)iy < (unsigned)ny) acc = fmaf(w, im[(int64_t)iy * nx + ix], acc);
+        __syncthreads();
+        if (blk_on) {
+            const int rel = (int)ubase - seg0;                 // base position inside the segment
+            const int nl = min(RB, n_lines - l0);
+            for (int r = 0; r < nl; ++r) {
+                const float u = rem + (float)r * slopef;       // crossing relative to ubase
+                const int i0 = (int)floorf(u - rhof) + 1;
+                const float *row = seg + r * seg_len + rel;
+                for (int n = 0; n < ncand; ++n) {
+                    const int i = i0 + n;
+                    const float w = fmaxf(0.0f, 1.0f - fabsf(af * ((float)i - u)));
+                    acc = fmaf(w, row[i], acc);
+                }
             }
         }
     }
-    // fixed-order reduction of the four partial sums
-    if (wv > 0) part[wv - 1][lane] = acc;
-    __syncthreads();
-    if (wv > 0 || j >= nb) return;
-    acc = ((acc + part[0][lane]) + part[1][lane]) + part[2][lane];
+    if (!wave_on || j >= nb) return;
     const int64_t o = sd.sino_off + (int64_t)k * nb + j;
     const float v = alpha * (float)(s * s) * acc;   // A = s^2 B^T
     if (MODE == 0) {
@@ -98,6 +136,29 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
     }
 }
 
+int plan_seg(const pyhst_plan &p)
+{
+    double smin = 1e300;
+    for (const auto &g : p.gd) smin = std::min(smin, g.s);
+    return fp_seg(smin);
+}
+
+template <int MODE>
+hipError_t launch_fp(const pyhst_plan &p, dim3 grid, const float *img, float *sino, float alpha, const CpDual &cp,
+                     int k0, hipStream_t st)
+{
+    const int seg = plan_seg(p);
+    const size_t lds = (size_t)4 * RB * seg * sizeof(float);
+    if (lds > 65536) {
+        if (lds > 160 * 1024) return hipErrorInvalidValue;
+        hipError_t e = hipFuncSetAttribute((const void *)fp_kernel<MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    fp_kernel<MODE><<<grid, 256, lds, st>>>(p.t, img, sino, alpha, cp, k0, seg);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_forward(const pyhst_plan &p, const float *img, float *sino, float alpha, const CpDual *cp,
@@ -105,16 +166,11 @@ hipError_t launch_forward(const pyhst_plan &p, const float *img, float *sino, fl
 {
     int maxnb = 0;
     for (const auto &g : p.gd) maxnb = std::max(maxnb, g.nb);
-    dim3 grid((maxnb + 63) / 64, (unsigned)p.max_K, p.n_slices);
-    if (cp && cp->residual) {
-        fp_kernel<2><<<grid, 256, 0, st>>>(p.t, img, nullptr, alpha, *cp, 0);
-    } else if (cp) {
-        fp_kernel<1><<<grid, 256, 0, st>>>(p.t, img, nullptr, alpha, *cp, 0);
-    } else {
-        CpDual none{};
-        fp_kernel<0><<<grid, 256, 0, st>>>(p.t, img, sino, alpha, none, 0);
-    }
-    return hipGetLastError();
+    dim3 grid((maxnb + 63) / 64, (unsigned)((p.max_K + 3) / 4), p.n_slices);
+    if (cp && cp->residual) return launch_fp<2>(p, grid, img, nullptr, alpha, *cp, 0, st);
+    if (cp) return launch_fp<1>(p, grid, img, nullptr, alpha, *cp, 0, st);
+    CpDual none{};
+    return launch_fp<0>(p, grid, img, sino, alpha, none, 0, st);
 }
 
 // row[s][j] = (A img_s)[k][j] - y_s[k][j] for one projection k of a uniform plan
@@ -124,8 +180,7 @@ hipError_t launch_forward_row(const pyhst_plan &p, const float *img, const float
     const GeoDev &g = p.gd[0];
     dim3 grid((g.nb + 63) / 64, 1, p.n_slices);
     CpDual r{row, y, 0.0f, 1};
-    fp_kernel<3><<<grid, 256, 0, st>>>(p.t, img, nullptr, 1.0f, r, k);
-    return hipGetLastError();
+    return launch_fp<3>(p, grid, img, nullptr, 1.0f, r, k, st);
 }
 
 }  // namespace pyhst
