@@ -176,8 +176,8 @@ int forward_project(const pyhst_plan *plan, const float *img, float *sino, hipSt
  * a zero last difference):  out = argmin_u 1/2|u - in|^2 + lambda TV(u), by
  * n_inner steps of Chambolle's (2004) dual projection with step 1/8 from a
  * zero dual field.  in, out [n_slices][n_y][n_x]; in == out allowed.
- * work: device scratch of at least 3*n_slices*n_y*n_x floats (work_floats
- * gives its size); NULL or too small -> PYHST_EARG. */
+ * work: device scratch of at least 4*n_slices*n_y*n_x floats (two copies of the
+ * dual field; work_floats gives its size); NULL or too small -> PYHST_EARG. */
 int tv_prox(int32_t n_slices, int32_t n_y, int32_t n_x, const float *in, float *out, float lambda,
             int32_t n_inner, float *work, size_t work_floats, hipStream_t stream);
 

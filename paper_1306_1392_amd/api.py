@@ -197,7 +197,7 @@ def tv_prox(x, lam: float, n_inner: int, out=None, work=None, stream=None):
     _need(x, S * ny * nx, "x")
     _need(out, S * ny * nx, "out")
     if work is None:
-        work = torch.empty(3 * S * ny * nx, device=x.device, dtype=torch.float32)
+        work = torch.empty(4 * S * ny * nx, device=x.device, dtype=torch.float32)
     _need(work, work.numel(), "work")
     check(_lib.lib().tv_prox(S, ny, nx, _ptr(x), _ptr(out), float(lam), int(n_inner), _ptr(work), work.numel(),
                              _stream(stream)), "tv_prox")

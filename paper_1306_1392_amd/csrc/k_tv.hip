@@ -29,28 +29,22 @@ __device__ inline float divergence(const float *q1, const float *q2, int64_t o, 
     return a + b;
 }
 
-// v = div p - g / lambda
-__global__ void prox_div_kernel(int64_t n, int ny, int nx, const float *__restrict__ p1, const float *__restrict__ p2,
-                                const float *__restrict__ g, float inv_lambda, float *__restrict__ v)
+// One fused inner step of the ROF dual projection:  q = (p + tau grad v) / (1 + tau |grad v|) with
+// v = div p - g / lambda evaluated at o and its +x / +y neighbours (p read, q written: ping-pong).
+__global__ void prox_step_kernel(int64_t n, int ny, int nx, const float *__restrict__ p1, const float *__restrict__ p2,
+                                 const float *__restrict__ g, float inv_lambda, float tau, float *__restrict__ q1,
+                                 float *__restrict__ q2)
 {
     for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
         const int64_t pix = o % ((int64_t)ny * nx);
         const int iy = (int)(pix / nx), ix = (int)(pix - (int64_t)iy * nx);
-        v[o] = divergence(p1, p2, o, ix, iy, nx, ny) - g[o] * inv_lambda;
-    }
-}
-
-// p <- (p + tau grad v) / (1 + tau |grad v|)
-__global__ void prox_update_kernel(int64_t n, int ny, int nx, const float *__restrict__ v, float *__restrict__ p1,
-                                   float *__restrict__ p2, float tau)
-{
-    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t pix = o % ((int64_t)ny * nx);
-        const int iy = (int)(pix / nx), ix = (int)(pix - (int64_t)iy * nx);
-        const float a = grad_x(v, o, ix, nx), b = grad_y(v, o, iy, ny, nx);
+        const float v0 = divergence(p1, p2, o, ix, iy, nx, ny) - g[o] * inv_lambda;
+        const float a = ix + 1 < nx ? (divergence(p1, p2, o + 1, ix + 1, iy, nx, ny) - g[o + 1] * inv_lambda) - v0 : 0.0f;
+        const float b =
+            iy + 1 < ny ? (divergence(p1, p2, o + nx, ix, iy + 1, nx, ny) - g[o + nx] * inv_lambda) - v0 : 0.0f;
         const float m = 1.0f + tau * sqrtf(a * a + b * b);
-        p1[o] = (p1[o] + tau * a) / m;
-        p2[o] = (p2[o] + tau * b) / m;
+        q1[o] = (p1[o] + tau * a) / m;
+        q2[o] = (p2[o] + tau * b) / m;
     }
 }
 
@@ -266,11 +260,12 @@ hipError_t launch_tv_prox(int S, int ny, int nx, const float *in, float *out, fl
         if (out != in) copy_kernel<<<grid_for(n), 256, 0, st>>>(out, in, n);
         return hipGetLastError();
     }
-    float *p1 = work, *p2 = work + n, *v = work + 2 * n;
+    float *p1 = work, *p2 = work + n, *q1 = work + 2 * n, *q2 = work + 3 * n;
     fill_kernel<<<grid_for(2 * n), 256, 0, st>>>(work, 2 * n, 0.0f);
     for (int it = 0; it < n_inner; ++it) {
-        prox_div_kernel<<<grid_for(n), 256, 0, st>>>(n, ny, nx, p1, p2, in, 1.0f / lambda, v);
-        prox_update_kernel<<<grid_for(n), 256, 0, st>>>(n, ny, nx, v, p1, p2, 0.125f);
+        prox_step_kernel<<<grid_for(n), 256, 0, st>>>(n, ny, nx, p1, p2, in, 1.0f / lambda, 0.125f, q1, q2);
+        std::swap(p1, q1);
+        std::swap(p2, q2);
     }
     prox_final_kernel<<<grid_for(n), 256, 0, st>>>(n, ny, nx, p1, p2, in, lambda, out);
     return hipGetLastError();

@@ -557,9 +557,9 @@ int tv_prox(int32_t n_slices, int32_t n_y, int32_t n_x, const float *in, float *
 {
     if (n_slices <= 0 || n_y <= 0 || n_x <= 0 || !in || !out) return fail(PYHST_EARG, "tv_prox: bad argument");
     if (!std::isfinite(lambda) || lambda < 0.0f || n_inner < 0) return fail(PYHST_EARG, "tv_prox: bad lambda/n_inner");
-    const size_t need = 3 * (size_t)n_slices * n_y * n_x;
+    const size_t need = 4 * (size_t)n_slices * n_y * n_x;
     if (lambda > 0.0f && n_inner > 0 && (!work || work_floats < need))
-        return fail(PYHST_EARG, "tv_prox: work must hold 3*n_slices*n_y*n_x floats");
+        return fail(PYHST_EARG, "tv_prox: work must hold 4*n_slices*n_y*n_x floats");
     hipError_t e = launch_tv_prox(n_slices, n_y, n_x, in, out, lambda, n_inner, work, st);
     return e == hipSuccess ? PYHST_OK : hip_fail(e, "tv_prox");
 }

@@ -88,7 +88,7 @@ FiLayout fista_layout(const pyhst_plan &p, const pyhst_recon_args &a, size_t bas
     L.r = take(ns * 4);
     L.z = take(ni * 4);
     L.xb = take(ni * 4);
-    L.prox = take(3 * ni * 4);
+    L.prox = take(4 * ni * 4);
     L.partials = take(sizeof(double) * 1024);
     L.energy = take(sizeof(float) * (size_t)std::max(1, a.n_iter));
     L.norm = take(sizeof(double) * 2);
