@@ -40,7 +40,14 @@ struct GeoDev {
     int64_t spec_off;         // first element of its filter spectrum [P] (bit-reversed order, 1/P folded)
     int32_t bp_w[N_TILE_CFG]; // LDS window length (bins) per tile configuration
     int32_t ntx[N_TILE_CFG];  // tiles along x per tile configuration
+    int32_t fp_blk_off;       // first forward-projection angle block of this geometry
+    int32_t fp_nblk;          // its number of angle blocks
 };
+
+// Forward projection: projections of one geometry grouped into blocks of at most FP_AMAX
+// whose staged line segments share one LDS segment of FP_SEG positions (see k_fp.hip).
+constexpr int FP_RB = 16, FP_AMAX = 32;
+int fp_seg_len(double s_min);
 
 struct SliceDev {
     int32_t g, pad;
@@ -59,6 +66,8 @@ struct Tables {
     const int2 *pairs;                   // filter work: (slice, first projection of a row pair)
     const int2 *items[N_TILE_CFG];       // backprojection work: (slice, tile), costliest first
     int *counter;                        // persistent work counter
+    const int *fp_ang;                   // forward-projection block members: projection index within its geometry
+    const int2 *fp_blk;                  // forward-projection blocks: (first member, count)
     int32_t Pmax, log2Pmax;
 };
 
@@ -85,6 +94,7 @@ struct pyhst_plan {
     int64_t sino_elems = 0, filt_elems = 0, img_elems = 0;
     int64_t max_K = 0;
     int n_pairs = 0;
+    int fp_seg = 0, fp_max_blocks = 0;
     int64_t n_items[pyhst::N_TILE_CFG] = {};
     int bp_tile = -1, persistent = 0;
     void *dev_block = nullptr;

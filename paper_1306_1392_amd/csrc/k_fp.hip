@@ -7,155 +7,176 @@
 // bin j of projection k sums exactly the pixels whose hat weight
 // hat(t_k(px) - j) is non-zero.  Along an image line of the dominant axis
 // (rows when |cos| >= |sin|, else columns) t is linear in the position,
-// t - j = a (i - u_j), a = s cos (or s sin), so the bin touches the positions
-// i in (u_j - 1/|a|, u_j + 1/|a|): at most ceil(2/|a|) of them.
+// t - j = a (i - u), a = s cos (or s sin), so the bin touches the positions
+// i in (u - 1/|a|, u + 1/|a|): at most ceil(2/|a|) of them.
 //
-// gfx950 layout.  Workgroup = 4 wavefronts = 4 projections x 64 bins of one
-// slice; lane = bin.  A wavefront walks the lines of its projection in blocks
-// of RB: for each block it stages the covering segment of every line (SEG
-// positions, zero outside the image) in LDS with coalesced loads, then every
-// lane reads its 2-3 candidates per line from LDS.  Coordinates: per (lane,
-// line block) the crossing u of the block's first line is computed in FP64 and
-// split into an integer base and an FP32 remainder; inside the block u advances
-// by an FP32 slope, so every FP32 quantity stays below RB + 2 (ulp < 2e-6).
-// Per candidate: offset, |.|, max, LDS read, FMA.
+// gfx950 layout, the transpose of the backprojector's: workgroup = one angle
+// block (up to 32 projections of similar direction, grouped by the plan so
+// that their candidate positions share one segment) x 64 bins x one slice.
+// The workgroup walks the image lines in blocks of 16; for each block it
+// stages the shared segment of every line (FP_SEG positions, zero outside the
+// image) in LDS once, and every wavefront then serves its projections (m = w,
+// w + 4, ...; lane = bin, one accumulator per projection) from LDS: a staged
+// value is read up to ~2 x 32 times.  Coordinates: per (lane, projection, line
+// block) the crossing u of the block's first line is computed in FP64 and split
+// into an integer base and an FP32 remainder; inside the block u advances by an
+// FP32 slope, so every FP32 offset stays below FP_RB + 2 positions.
 #include "internal.hpp"
 
 namespace pyhst {
 
-namespace {
-
-constexpr int RB = 16;   // lines per staged block
-
-// segment length (positions) that covers 64 bins x RB lines of one projection for pixel size s:
-// 63/|a| + (RB - 1) |slope| + 2/|a| + 4 with |a| >= s / sqrt(2) and |slope| <= 1
-inline int fp_seg(double s)
+// segment length that holds one projection's 64 bins x FP_RB lines (65/|a| + FP_RB - 1 positions,
+// |a| >= s / sqrt(2)) plus a drift allowance of 96 positions for the other members of a block
+int fp_seg_len(double s_min)
 {
-    const double ainv = 1.4142135623730951 / s;
-    int seg = (int)std::ceil(65.0 * ainv + (RB - 1) + 4.0);
+    const int seg = (int)std::ceil(65.0 * 1.4142135623730951 / s_min + (FP_RB - 1) + 8.0 + 96.0);
     return (seg + 3) & ~3;
 }
 
+namespace {
+
+constexpr int AW = FP_AMAX / 4;   // projections per wavefront
+
 template <int MODE>
 __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restrict__ img, float *__restrict__ out,
-                                                 float alpha, CpDual cp, int k0, int seg_len)
+                                                 float alpha, CpDual cp, int k_single, int seg_len)
 {
-    extern __shared__ float stage[];   // [4 waves][RB][seg_len]
+    extern __shared__ float stage[];   // [FP_RB][seg_len]
+    __shared__ double s_lo[4];
     const int slice = blockIdx.z;
     const SliceDev sd = T.slc[slice];
     const GeoDev &g = T.geo[sd.g];
-    const int K = g.K, nb = g.nb, nx = g.nx, ny = g.ny;
+    const int nb = g.nb, nx = g.nx, ny = g.ny;
+    int start = 0, count = 1;
+    if (MODE != 3) {
+        if ((int)blockIdx.y >= g.fp_nblk) return;            // whole workgroup
+        const int2 bk = T.fp_blk[g.fp_blk_off + blockIdx.y];
+        start = bk.x;
+        count = bk.y;
+    }
+    if ((int)blockIdx.x * 64 >= nb) return;                  // whole workgroup
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int k = k0 + blockIdx.y * 4 + wv;
     const int j = blockIdx.x * 64 + lane;
-    // MODE 3 projects the single projection k0 (wavefront 0 only)
-    const bool wave_on = k < K && (MODE != 3 || wv == 0) && blockIdx.x * 64 < nb;
-    float *seg = stage + wv * RB * seg_len;
-    const float *im = img + sd.img_off;
-
-    // projection geometry (wave-uniform); t = s (x c + y sn) + axis + shift
-    const int kk = wave_on ? k : 0;
-    const double c = T.cosd[g.ang_off + kk], sn = T.sind[g.ang_off + kk];
     const double s = g.s;
     const double cx = 0.5 * (nx - 1), cy = 0.5 * (ny - 1);
-    const double t0 = g.axis + T.shiftd[g.ang_off + kk];
-    const bool rows = fabs(c) >= fabs(sn);
-    // along a line: t - j = a (i - u), u(line) = (j - t0 + a ci + bb cl - bb line) / a, where a and ci
-    // belong to the axis walked along the line and bb and cl to the other one
-    const double a = rows ? s * c : s * sn;
-    const double bb = rows ? s * sn : s * c;
-    const double ci = rows ? cx : cy, cl = rows ? cy : cx;
+    const int k_first = MODE == 3 ? k_single : T.fp_ang[start];
+    const bool rows = fabs(T.cosd[g.ang_off + k_first]) >= fabs(T.sind[g.ang_off + k_first]);   // same for the block
     const int n_lines = rows ? ny : nx;
-    const double rho = 1.0 / fabs(a);
-    const int ncand = (int)ceil(2.0 * rho);
-    const double slope = -bb / a;                          // du per line
-    const double u_first = ((double)j - t0 + a * ci + bb * cl) / a;   // u at line 0
-    const float af = (float)a, rhof = (float)rho, slopef = (float)slope;
-    const int lines_max = max(nx, ny);
 
-    float acc = 0.0f;
-    for (int l0 = 0; l0 < lines_max; l0 += RB) {
-        const bool blk_on = wave_on && l0 < n_lines;
-        // lane's crossing at the block's first line: FP64, split into base + remainder
-        const double ub = fma((double)l0, slope, u_first);
-        const double ubase = floor(ub);
-        const float rem = (float)(ub - ubase);
-        // segment start: lowest candidate over the wave's 64 bins and RB lines
-        double lo = fmin(ub, ub + (RB - 1) * slope) - rho;
+    // this lane's projections: u = U0 + j / a + slope * line, candidates within rho of u
+    double u_first[AW], slope[AW];
+    float af[AW], rhof[AW], slopef[AW];
+    int ncand[AW], kk[AW];
+    int mine = 0;
+#pragma unroll
+    for (int i = 0; i < AW; ++i) {
+        const int m = wv + 4 * i;
+        const bool on = m < count;
+        const int k = MODE == 3 ? k_single : T.fp_ang[start + (on ? m : 0)];
+        const double c = T.cosd[g.ang_off + k], sn = T.sind[g.ang_off + k];
+        const double a = rows ? s * c : s * sn, bb = rows ? s * sn : s * c;
+        const double ci = rows ? cx : cy, cl = rows ? cy : cx;
+        const double t0 = g.axis + T.shiftd[g.ang_off + k];
+        const double rho = 1.0 / fabs(a);
+        kk[i] = k;
+        slope[i] = -bb / a;
+        u_first[i] = ((double)j - t0 + a * ci + bb * cl) / a;
+        af[i] = (float)a;
+        rhof[i] = (float)rho;
+        slopef[i] = (float)slope[i];
+        ncand[i] = on ? (int)ceil(2.0 * rho) : 0;
+        mine += on ? 1 : 0;
+    }
+
+    float acc[AW];
+#pragma unroll
+    for (int i = 0; i < AW; ++i) acc[i] = 0.0f;
+    const float *im = img + sd.img_off;
+    for (int l0 = 0; l0 < n_lines; l0 += FP_RB) {
+        // segment start: lowest candidate over the block's projections, 64 bins and FP_RB lines
+        double lo = 1e300;
+#pragma unroll
+        for (int i = 0; i < AW; ++i) {
+            if (i >= mine) break;
+            const double ub = fma((double)l0, slope[i], u_first[i]);
+            lo = fmin(lo, fmin(ub, ub + (FP_RB - 1) * slope[i]) - (double)rhof[i]);
+        }
         for (int off = 32; off > 0; off >>= 1) lo = fmin(lo, __shfl_xor(lo, off, 64));
-        const int seg0 = (int)floor(lo) - 1;
         __syncthreads();   // the previous block's reads are done
-        if (blk_on) {
-            if (rows) {
-                for (int r = 0; r < RB; ++r) {
-                    const int line = l0 + r;
-                    const float *src = im + (int64_t)line * nx;
-                    for (int p = lane; p < seg_len; p += 64) {
-                        const int pos = seg0 + p;
-                        seg[r * seg_len + p] = (line < ny && (unsigned)pos < (unsigned)nx) ? src[pos] : 0.0f;
-                    }
-                }
-            } else {
-                // columns: 16 lanes read 16 neighbouring columns of one row (64 B), 4 rows per step
-                const int r = lane & 15;
+        if (lane == 0) s_lo[wv] = lo;
+        __syncthreads();
+        const int seg0 = (int)floor(fmin(fmin(s_lo[0], s_lo[1]), fmin(s_lo[2], s_lo[3]))) - 1;
+        if (rows) {
+            for (int r = 0; r < FP_RB; ++r) {
                 const int line = l0 + r;
-                for (int p = lane >> 4; p < seg_len; p += 4) {
+                const float *src = im + (int64_t)line * nx;
+                for (int p = threadIdx.x; p < seg_len; p += 256) {
                     const int pos = seg0 + p;
-                    seg[r * seg_len + p] =
-                        (line < nx && (unsigned)pos < (unsigned)ny) ? im[(int64_t)pos * nx + line] : 0.0f;
+                    stage[r * seg_len + p] = (line < ny && (unsigned)pos < (unsigned)nx) ? src[pos] : 0.0f;
                 }
+            }
+        } else {
+            // columns: 16 threads read 16 neighbouring columns of one row (64 B), 16 rows per step
+            const int r = threadIdx.x & 15;
+            const int line = l0 + r;
+            for (int p = threadIdx.x >> 4; p < seg_len; p += 16) {
+                const int pos = seg0 + p;
+                stage[r * seg_len + p] = (line < nx && (unsigned)pos < (unsigned)ny) ? im[(int64_t)pos * nx + line] : 0.0f;
             }
         }
         __syncthreads();
-        if (blk_on) {
-            const int rel = (int)ubase - seg0;                 // base position inside the segment
-            const int nl = min(RB, n_lines - l0);
+        const int nl = min(FP_RB, n_lines - l0);
+#pragma unroll
+        for (int i = 0; i < AW; ++i) {
+            if (i >= mine) break;
+            const double ub = fma((double)l0, slope[i], u_first[i]);
+            const double ubase = floor(ub);
+            const float rem = (float)(ub - ubase);
+            const float *base = stage + ((int)ubase - seg0);
             for (int r = 0; r < nl; ++r) {
-                const float u = rem + (float)r * slopef;       // crossing relative to ubase
-                const int i0 = (int)floorf(u - rhof) + 1;
-                const float *row = seg + r * seg_len + rel;
-                for (int n = 0; n < ncand; ++n) {
-                    const int i = i0 + n;
-                    const float w = fmaxf(0.0f, 1.0f - fabsf(af * ((float)i - u)));
-                    acc = fmaf(w, row[i], acc);
+                const float u = fmaf((float)r, slopef[i], rem);       // crossing relative to ubase
+                const int i0 = (int)floorf(u - rhof[i]) + 1;
+                const float *row = base + r * seg_len;
+                for (int n = 0; n < ncand[i]; ++n) {
+                    const int q = i0 + n;
+                    const float w = fmaxf(0.0f, 1.0f - fabsf(af[i] * ((float)q - u)));
+                    acc[i] = fmaf(w, row[q], acc[i]);
                 }
             }
         }
     }
-    if (!wave_on || j >= nb) return;
-    const int64_t o = sd.sino_off + (int64_t)k * nb + j;
-    const float v = alpha * (float)(s * s) * acc;   // A = s^2 B^T
-    if (MODE == 0) {
-        out[o] = v;
-    } else if (MODE == 1) {
-        cp.p[o] = (cp.p[o] + cp.sigma * (v - cp.y[o])) / (1.0f + cp.sigma);
-    } else if (MODE == 2) {
-        cp.p[o] = v - cp.y[o];   // residual A x - y of the gradient step of ISTA/FISTA
-    } else {
-        cp.p[(int64_t)slice * nb + j] = v - cp.y[o];   // one projection's residual row per slice
+    if (j >= nb) return;
+    const float sc = alpha * (float)(s * s);   // A = s^2 B^T
+#pragma unroll
+    for (int i = 0; i < AW; ++i) {
+        if (i >= mine) break;
+        const int64_t o = sd.sino_off + (int64_t)kk[i] * nb + j;
+        const float v = sc * acc[i];
+        if (MODE == 0) {
+            out[o] = v;
+        } else if (MODE == 1) {
+            cp.p[o] = (cp.p[o] + cp.sigma * (v - cp.y[o])) / (1.0f + cp.sigma);
+        } else if (MODE == 2) {
+            cp.p[o] = v - cp.y[o];   // residual A x - y of the gradient step of ISTA/FISTA
+        } else {
+            cp.p[(int64_t)slice * nb + j] = v - cp.y[o];   // one projection's residual row per slice
+        }
     }
-}
-
-int plan_seg(const pyhst_plan &p)
-{
-    double smin = 1e300;
-    for (const auto &g : p.gd) smin = std::min(smin, g.s);
-    return fp_seg(smin);
 }
 
 template <int MODE>
 hipError_t launch_fp(const pyhst_plan &p, dim3 grid, const float *img, float *sino, float alpha, const CpDual &cp,
-                     int k0, hipStream_t st)
+                     int k_single, hipStream_t st)
 {
-    const int seg = plan_seg(p);
-    const size_t lds = (size_t)4 * RB * seg * sizeof(float);
+    const int seg = p.fp_seg;
+    const size_t lds = (size_t)FP_RB * seg * sizeof(float);
     if (lds > 65536) {
         if (lds > 160 * 1024) return hipErrorInvalidValue;
         hipError_t e = hipFuncSetAttribute((const void *)fp_kernel<MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
-    fp_kernel<MODE><<<grid, 256, lds, st>>>(p.t, img, sino, alpha, cp, k0, seg);
+    fp_kernel<MODE><<<grid, 256, lds, st>>>(p.t, img, sino, alpha, cp, k_single, seg);
     return hipGetLastError();
 }
 
@@ -166,7 +187,7 @@ hipError_t launch_forward(const pyhst_plan &p, const float *img, float *sino, fl
 {
     int maxnb = 0;
     for (const auto &g : p.gd) maxnb = std::max(maxnb, g.nb);
-    dim3 grid((maxnb + 63) / 64, (unsigned)((p.max_K + 3) / 4), p.n_slices);
+    dim3 grid((maxnb + 63) / 64, (unsigned)p.fp_max_blocks, p.n_slices);
     if (cp && cp->residual) return launch_fp<2>(p, grid, img, nullptr, alpha, *cp, 0, st);
     if (cp) return launch_fp<1>(p, grid, img, nullptr, alpha, *cp, 0, st);
     CpDual none{};

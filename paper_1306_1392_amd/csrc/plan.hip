@@ -203,6 +203,84 @@ const char *pyhst_strerror(int code)
     }
 }
 
+namespace pyhst {
+namespace {
+
+// Forward-projection angle blocks of one geometry.  Along the dominant image axis of
+// projection k (rows when |cos| >= |sin|), bin j crosses line l at position
+// u = U0_k + j / a_k + slope_k l, and touches the positions within 1/|a_k| of it.  Projections are
+// sorted by (walking axis, sign of a, slope) and grouped greedily; a block is kept while the union
+// of its members' candidate positions for any 64-bin chunk and FP_RB-line block fits in `seg`
+// positions.  The union's extent is a convex function of the chunk and block starts (a maximum of
+// linear functions minus a minimum of linear functions), so the four corners of that domain bound it.
+struct FpAng {
+    int k;
+    int rows, sgn;
+    double a, slope, U0, rho;
+};
+
+void build_fp_blocks(const GeoHost &h, const GeoDev &d, int seg, std::vector<int> &members,
+                     std::vector<int2> &blocks)
+{
+    const double cx = 0.5 * (d.nx - 1), cy = 0.5 * (d.ny - 1);
+    std::vector<FpAng> v(d.K);
+    for (int k = 0; k < d.K; ++k) {
+        const double c = std::cos(h.ang[k]), sn = std::sin(h.ang[k]);
+        const bool rows = std::fabs(c) >= std::fabs(sn);
+        const double a = rows ? h.s * c : h.s * sn, bb = rows ? h.s * sn : h.s * c;
+        const double ci = rows ? cx : cy, cl = rows ? cy : cx;
+        const double t0 = h.g.axis_pos + h.shift[k];
+        v[k] = FpAng{k, rows ? 1 : 0, a > 0 ? 1 : 0, a, -bb / a, (-t0 + a * ci + bb * cl) / a, 1.0 / std::fabs(a)};
+    }
+    std::stable_sort(v.begin(), v.end(), [](const FpAng &x, const FpAng &y) {
+        if (x.rows != y.rows) return x.rows > y.rows;
+        if (x.sgn != y.sgn) return x.sgn > y.sgn;
+        return x.slope < y.slope;
+    });
+    const int nchunk = (d.nb + 63) / 64;
+    const double jc[2] = {0.0, 64.0 * (nchunk - 1)};
+    auto extent = [&](const FpAng &x, double j0, double l0, double &lo, double &hi) {
+        // positions touched by bins j0..j0+63 on lines l0..l0+RB-1 (u linear in j and l)
+        double mn = 1e300, mx = -1e300;
+        for (int cj = 0; cj < 2; ++cj)
+            for (int cl = 0; cl < 2; ++cl) {
+                const double u = x.U0 + (j0 + 63.0 * cj) / x.a + x.slope * (l0 + (FP_RB - 1) * cl);
+                mn = std::min(mn, u);
+                mx = std::max(mx, u);
+            }
+        lo = mn - x.rho;
+        hi = mx + x.rho;
+    };
+    size_t i = 0;
+    while (i < v.size()) {
+        size_t e = i + 1;
+        const int nl = v[i].rows ? d.ny : d.nx;
+        const double lc[2] = {0.0, (double)(((nl - 1) / FP_RB) * FP_RB)};
+        while (e < v.size() && e - i < (size_t)FP_AMAX && v[e].rows == v[i].rows) {
+            bool ok = true;
+            for (int a = 0; a < 2 && ok; ++a)
+                for (int b = 0; b < 2 && ok; ++b) {
+                    double lo = 1e300, hi = -1e300;
+                    for (size_t m = i; m <= e; ++m) {
+                        double l1, h1;
+                        extent(v[m], jc[a], lc[b], l1, h1);
+                        lo = std::min(lo, l1);
+                        hi = std::max(hi, h1);
+                    }
+                    ok = (hi - lo) + 4.0 <= (double)seg;
+                }
+            if (!ok) break;
+            ++e;
+        }
+        blocks.push_back(make_int2((int)members.size(), (int)(e - i)));
+        for (size_t m = i; m < e; ++m) members.push_back(v[m].k);
+        i = e;
+    }
+}
+
+}  // namespace
+}  // namespace pyhst
+
 int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_geom, int32_t n_slices,
                       pyhst_plan **out)
 {
@@ -285,6 +363,24 @@ int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_
             p->max_K = std::max<int64_t>(p->max_K, d.K);
         }
 
+        // forward-projection angle blocks (segment length from the smallest pixel size)
+        double s_min = 1e300;
+        for (const auto &h : p->gh) s_min = std::min(s_min, h.s);
+        p->fp_seg = fp_seg_len(s_min);
+        std::vector<int> fp_members;
+        std::vector<int2> fp_blocks;
+        for (int i = 0; i < n_geom; ++i) {
+            GeoDev &d = p->gd[i];
+            d.fp_blk_off = (int)fp_blocks.size();
+            std::vector<int> mem;
+            std::vector<int2> blk;
+            build_fp_blocks(p->gh[i], d, p->fp_seg, mem, blk);
+            for (auto &b : blk) fp_blocks.push_back(make_int2(b.x + (int)fp_members.size(), b.y));
+            fp_members.insert(fp_members.end(), mem.begin(), mem.end());
+            d.fp_nblk = (int)blk.size();
+            p->fp_max_blocks = std::max(p->fp_max_blocks, d.fp_nblk);
+        }
+
         // slices: packed offsets
         p->sd.resize(n_slices);
         int64_t so = 0, fo = 0, io = 0;
@@ -344,6 +440,8 @@ int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_
         size_t o_items[N_TILE_CFG];
         for (int c = 0; c < N_TILE_CFG; ++c) o_items[c] = take(sizeof(int2) * items[c].size());
         const size_t o_cnt = take(sizeof(int) * 64);
+        const size_t o_fpa = take(sizeof(int) * fp_members.size());
+        const size_t o_fpb = take(sizeof(int2) * fp_blocks.size());
         const size_t total = off;
 
         std::vector<unsigned char> hbuf(total, 0);
@@ -394,6 +492,8 @@ int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_
         put(o_tw, tw.data(), sizeof(float2) * tw.size());
         put(o_pairs, pairs.data(), sizeof(int2) * pairs.size());
         for (int c = 0; c < N_TILE_CFG; ++c) put(o_items[c], items[c].data(), sizeof(int2) * items[c].size());
+        put(o_fpa, fp_members.data(), sizeof(int) * fp_members.size());
+        put(o_fpb, fp_blocks.data(), sizeof(int2) * fp_blocks.size());
 
         e = hipMalloc(&p->dev_block, total);
         if (e != hipSuccess) {
@@ -422,6 +522,8 @@ int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_
         t.pairs = (const int2 *)(b + o_pairs);
         for (int c = 0; c < N_TILE_CFG; ++c) t.items[c] = (const int2 *)(b + o_items[c]);
         t.counter = (int *)(b + o_cnt);
+        t.fp_ang = (const int *)(b + o_fpa);
+        t.fp_blk = (const int2 *)(b + o_fpb);
         t.Pmax = Pmax;
         t.log2Pmax = lgmax;
         *out = guard.release();
