@@ -351,7 +351,6 @@ hipError_t conv_fwd(const pyhst_unet &net, const Conv &L, Act in, bf16_t *out, i
 {
     const int M = in.B * in.H * in.W;
     StoreAct E{out, ocs, oco, net.params + L.b, 1};
-    if (conv3x3_direct(L.cin, L.cout)) return run_conv3x3(in, L.cin, L.wf, E, L.cout, st);
     Im2colA A = im2col_a(in, L.cin);
     WeightB Bw{L.wf, 9 * L.cin};
     switch (tn_for(L.cout)) {
@@ -421,7 +420,6 @@ hipError_t conv_bwd(const pyhst_unet &net, const Conv &L, Act x, Act dz, bf16_t 
         // dX[pix][ci] = sum_{tap', co} dZ[pix + off(tap')][co] Wb[ci][tap'][co], masked by X > 0
         const int M = npix, N = L.cin;
         StoreMasked E{dx, dxcs, dxco, x.p, x.cs, x.co};
-        if (conv3x3_direct(L.cout, N)) return run_conv3x3(dz, L.cout, L.wb, E, N, st);
         Im2colA A = im2col_a(dz, L.cout);
         WeightB Bw{L.wb, 9 * L.cout};
         switch (tn_for(N)) {

@@ -461,90 +461,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(AL A, BL B, EP E, int M, int 
             }
 }
 
-// Direct 3x3 convolution (stride 1, zero padding 1) for N = 32 * BN output channels:
-//   C[m = pixel][n] = sum_{tap, ci} X[pixel + off(tap)][ci] W[n][tap][ci]
-// Workgroup tile: 2 image rows x 64 pixels (wave w: row w / 2, pixels 32 (w % 2) .. + 31) and all N
-// channels.  Per chunk of 32 input channels the input halo (4 rows x 66 pixels) and the chunk's
-// weights are staged in LDS once; the 9 taps x 2 MFMA steps then read the A operand from the halo
-// at the tap's offset, so every input pixel is read from L2 about twice instead of nine times, and
-// a barrier pair serves 18 * BN MFMAs per wave.  LDS pitches of 80 B per pixel and 592 B per
-// output channel keep the 16 B reads of a wave free of bank conflicts.  Cin is a multiple of 32.
-template <class EP, int BN>
-__global__ __launch_bounds__(256) void conv3x3_kernel(Act x, int Cin, const bf16_t *__restrict__ w, EP E, int N)
-{
-    constexpr int CH = 32, TY = 2, TX = 64, HY = TY + 2, HX = TX + 2;
-    constexpr int PP = CH + 8, NN = 32 * BN, WP = 9 * CH + 8;
-    __shared__ __attribute__((aligned(16))) bf16_t sx[HY * HX * PP];
-    __shared__ __attribute__((aligned(16))) bf16_t sw[NN * WP];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tiles_x = (x.W + TX - 1) / TX, tiles_y = (x.H + TY - 1) / TY;
-    int t = blockIdx.x;
-    const int tx0 = (t % tiles_x) * TX;
-    t /= tiles_x;
-    const int ty0 = (t % tiles_y) * TY;
-    const int b = t / tiles_y;
-    const int K = 9 * Cin;
-    f32x16 acc[BN];
-#pragma unroll
-    for (int j = 0; j < BN; ++j)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[j][r] = 0.0f;
-    const int py = wave >> 1, pxl = (wave & 1) * 32 + (lane & 31), kg = 8 * (lane >> 5);
-    for (int c0 = 0; c0 < Cin; c0 += CH) {
-        for (int e = threadIdx.x; e < HY * HX * (CH / 8); e += 256) {
-            const int v = e & (CH / 8 - 1), pix = e / (CH / 8);
-            const int hx = pix % HX, hy = pix / HX;
-            const int iy = ty0 + hy - 1, ix = tx0 + hx - 1;
-            uint4 val = zero8();
-            if ((unsigned)iy < (unsigned)x.H && (unsigned)ix < (unsigned)x.W)
-                val = ld8(x.p + ((int64_t)(b * x.H + iy) * x.W + ix) * x.cs + x.co + c0 + 8 * v);
-            *(uint4 *)&sx[pix * PP + 8 * v] = val;
-        }
-        for (int e = threadIdx.x; e < NN * 9 * (CH / 8); e += 256) {
-            const int v = e & (CH / 8 - 1), r = e / (CH / 8);
-            const int tap = r % 9, n = r / 9;
-            uint4 val = zero8();
-            if (n < N) val = ld8(w + (int64_t)n * K + tap * Cin + c0 + 8 * v);
-            *(uint4 *)&sw[n * WP + tap * CH + 8 * v] = val;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int ty = tap / 3, tx = tap % 3;
-            const bf16_t *arow = sx + ((py + ty) * HX + (pxl + tx)) * PP + kg;
-#pragma unroll
-            for (int kk = 0; kk < CH; kk += 16) {
-                const bf16x8 af = *(const bf16x8 *)(arow + kk);
-#pragma unroll
-                for (int j = 0; j < BN; ++j) {
-                    const bf16x8 bfr = *(const bf16x8 *)(sw + (j * 32 + (lane & 31)) * WP + tap * CH + kk + kg);
-                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bfr, acc[j], 0, 0, 0);
-                }
-            }
-        }
-        __syncthreads();
-    }
-    const int gy = ty0 + py;
-#pragma unroll
-    for (int j = 0; j < BN; ++j)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int gx = tx0 + (wave & 1) * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            const int n = j * 32 + (lane & 31);
-            if (gx < x.W && gy < x.H && n < N) E((b * x.H + gy) * x.W + gx, n, acc[j][r]);
-        }
-}
-
-template <class EP>
-inline hipError_t run_conv3x3(Act x, int Cin, const bf16_t *w, const EP &e, int N, hipStream_t st)
-{
-    const int64_t tiles = (int64_t)x.B * ((x.H + 1) / 2) * ((x.W + 63) / 64);
-    if (N <= 32) conv3x3_kernel<EP, 1><<<(unsigned)tiles, 256, 0, st>>>(x, Cin, w, e, N);
-    else conv3x3_kernel<EP, 2><<<(unsigned)tiles, 256, 0, st>>>(x, Cin, w, e, N);
-    return hipGetLastError();
-}
-inline bool conv3x3_direct(int Cin, int N) { return Cin % 32 == 0 && (N == 32 || N == 64); }
-
 // ---------------------------------------------------------------- epilogues
 struct StoreAct {     // y[m][n] = bf16(relu(v + bias[n]))
     bf16_t *y;
