@@ -40,6 +40,10 @@ struct Buf {                // an activation and its gradient, same layout
 
 int tn_for(int n) { return n >= 128 ? 128 : (n >= 64 ? 64 : 32); }
 
+// K tile of the weight-gradient GEMMs (K = pixels, millions): deeper than the default to halve the
+// barriers per MFMA
+constexpr int TKW = 64;
+
 }  // namespace
 
 struct pyhst_unet {
@@ -406,12 +410,12 @@ hipError_t conv_bwd(const pyhst_unet &net, const Conv &L, Act x, Act dz, bf16_t 
         PlainT Bz{dz};
         StorePartial E{net.part, M, N};
         int ks = (npix + s - 1) / s;
-        ks = (ks + TK - 1) / TK * TK;
+        ks = (ks + TKW - 1) / TKW * TKW;
         const int sp = (npix + ks - 1) / ks;
         dim3 grid((M + TM - 1) / TM, (N + tn - 1) / tn, sp);
-        if (tn == 128) gemm_kernel<Im2colT, PlainT, StorePartial, 128><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
-        else if (tn == 64) gemm_kernel<Im2colT, PlainT, StorePartial, 64><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
-        else gemm_kernel<Im2colT, PlainT, StorePartial, 32><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
+        if (tn == 128) gemm_kernel<Im2colT, PlainT, StorePartial, 128, TM, TKW><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
+        else if (tn == 64) gemm_kernel<Im2colT, PlainT, StorePartial, 64, TM, TKW><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
+        else gemm_kernel<Im2colT, PlainT, StorePartial, 32, TM, TKW><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
         reduce_splitk_T_kernel<<<(unsigned)(((int64_t)M * N + 63) / 64), 256, 0, st>>>(net.part, sp, M, N, net.grads + L.w);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -443,12 +447,12 @@ hipError_t up_bwd(const pyhst_unet &net, const Up &L, Act x, Act dy, bf16_t *dx,
         UpGatherT Bz = upgather_t(dy, L.cout);
         StorePartial E{net.part, M, N};
         int ks = (npix + s - 1) / s;
-        ks = (ks + TK - 1) / TK * TK;
+        ks = (ks + TKW - 1) / TKW * TKW;
         const int sp = (npix + ks - 1) / ks;
         dim3 grid((M + TM - 1) / TM, (N + tn - 1) / tn, sp);
-        if (tn == 128) gemm_kernel<PlainT, UpGatherT, StorePartial, 128><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
-        else if (tn == 64) gemm_kernel<PlainT, UpGatherT, StorePartial, 64><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
-        else gemm_kernel<PlainT, UpGatherT, StorePartial, 32><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
+        if (tn == 128) gemm_kernel<PlainT, UpGatherT, StorePartial, 128, TM, TKW><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
+        else if (tn == 64) gemm_kernel<PlainT, UpGatherT, StorePartial, 64, TM, TKW><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
+        else gemm_kernel<PlainT, UpGatherT, StorePartial, 32, TM, TKW><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
         reduce_splitk_T_kernel<<<(unsigned)(((int64_t)M * N + 63) / 64), 256, 0, st>>>(net.part, sp, M, N, net.grads + L.w);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

@@ -328,12 +328,13 @@ __device__ inline void transpose8(const uint4 *in, uint4 *out)
 //  VK loaders: SLOTS vectors of 8 consecutive k of one row per thread.
 //  Other loaders (vectors run along the rows): each of the first ROWS/8 * TK/8 threads loads an
 //  8-row x 8-k block as 8 vectors (one per k), transposes it in registers and stores 8 vectors.
-template <class L, int ROWS, bool VK = L::VK>
+template <class L, int ROWS, int TKv = TK, bool VK = L::VK>
 struct Stager;
 
-template <class L, int ROWS>
-struct Stager<L, ROWS, true> {
-    static constexpr int NV = ROWS * TK / 8;
+template <class L, int ROWS, int TKv>
+struct Stager<L, ROWS, TKv, true> {
+    static constexpr int KV = TKv / 8, LDKv = TKv + 8;
+    static constexpr int NV = ROWS * KV;
     static constexpr int SLOTS = (NV + 255) / 256;
     typename L::Ctx ctx[SLOTS];
     uint4 v[SLOTS];
@@ -343,8 +344,8 @@ struct Stager<L, ROWS, true> {
 #pragma unroll
         for (int j = 0; j < SLOTS; ++j) {
             const int idx = threadIdx.x + 256 * j;
-            row[j] = idx >> 2;
-            kl[j] = (idx & 3) * 8;
+            row[j] = idx / KV;
+            kl[j] = (idx % KV) * 8;
             ctx[j] = ld.prep(row0 + row[j], idx < NV ? R : 0);
         }
     }
@@ -357,13 +358,13 @@ struct Stager<L, ROWS, true> {
     {
 #pragma unroll
         for (int j = 0; j < SLOTS; ++j)
-            if (threadIdx.x + 256 * j < NV) *(uint4 *)&s[row[j] * LDK + kl[j]] = v[j];
+            if (threadIdx.x + 256 * j < NV) *(uint4 *)&s[row[j] * LDKv + kl[j]] = v[j];
     }
 };
 
-template <class L, int ROWS>
-struct Stager<L, ROWS, false> {
-    static constexpr int R8 = ROWS / 8, NBLK = R8 * (TK / 8);
+template <class L, int ROWS, int TKv>
+struct Stager<L, ROWS, TKv, false> {
+    static constexpr int R8 = ROWS / 8, NBLK = R8 * (TKv / 8), LDKv = TKv + 8;
     static_assert(NBLK <= 256, "one 8x8 block per thread");
     typename L::Ctx ctx;
     uint4 v[8];
@@ -387,21 +388,22 @@ struct Stager<L, ROWS, false> {
         uint4 o[8];
         transpose8(v, o);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) *(uint4 *)&s[(row + q) * LDK + kl] = o[q];
+        for (int q = 0; q < 8; ++q) *(uint4 *)&s[(row + q) * LDKv + kl] = o[q];
     }
 };
 
 // One workgroup: a TM x TN tile of C over the K range [kz * k_split, (kz+1) * k_split).
 // The next K tile is fetched into registers while the current one is multiplied from
 // LDS; two LDS buffers, one barrier per K tile.
-template <class AL, class BL, class EP, int TN, int TMv = TM>
+template <class AL, class BL, class EP, int TN, int TMv = TM, int TKv = TK>
 __global__ __launch_bounds__(256) void gemm_kernel(AL A, BL B, EP E, int M, int N, int K, int k_split)
 {
+    constexpr int LDKv = TKv + 8;
     constexpr int WMW = WaveGrid<TN>::WM, WNW = WaveGrid<TN>::WN;
     constexpr int WTM = TMv / WMW, WTN = TN / WNW;
     constexpr int BM = WTM / 32, BN = WTN / 32;
-    __shared__ __attribute__((aligned(16))) bf16_t sA[2][TMv * LDK];
-    __shared__ __attribute__((aligned(16))) bf16_t sB[2][TN * LDK];
+    __shared__ __attribute__((aligned(16))) bf16_t sA[2][TMv * LDKv];
+    __shared__ __attribute__((aligned(16))) bf16_t sB[2][TN * LDKv];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WNW, wn = wave % WNW;
     const int m0 = blockIdx.x * TMv, n0 = blockIdx.y * TN;
@@ -415,8 +417,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(AL A, BL B, EP E, int M, int 
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-    Stager<AL, TMv> ga;
-    Stager<BL, TN> gb;
+    Stager<AL, TMv, TKv> ga;
+    Stager<BL, TN, TKv> gb;
     ga.prep(A, m0, M, 0);
     gb.prep(B, n0, N, 1);
     if (kbeg < kend) {
@@ -424,24 +426,24 @@ __global__ __launch_bounds__(256) void gemm_kernel(AL A, BL B, EP E, int M, int 
         gb.load(B, kbeg, kend);
     }
     int buf = 0;
-    for (int k0 = kbeg; k0 < kend; k0 += TK, buf ^= 1) {
+    for (int k0 = kbeg; k0 < kend; k0 += TKv, buf ^= 1) {
         ga.store(sA[buf]);
         gb.store(sB[buf]);
         __syncthreads();
-        if (k0 + TK < kend) {
-            ga.load(A, k0 + TK, kend);
-            gb.load(B, k0 + TK, kend);
+        if (k0 + TKv < kend) {
+            ga.load(A, k0 + TKv, kend);
+            gb.load(B, k0 + TKv, kend);
         }
         const bf16_t *a = sA[buf], *bsm = sB[buf];
 #pragma unroll
-        for (int kk = 0; kk < TK; kk += 16) {
+        for (int kk = 0; kk < TKv; kk += 16) {
             bf16x8 af[BM], bfr[BN];
 #pragma unroll
             for (int i = 0; i < BM; ++i)
-                af[i] = *(const bf16x8 *)&a[(wm * WTM + i * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
+                af[i] = *(const bf16x8 *)&a[(wm * WTM + i * 32 + (lane & 31)) * LDKv + kk + 8 * (lane >> 5)];
 #pragma unroll
             for (int j = 0; j < BN; ++j)
-                bfr[j] = *(const bf16x8 *)&bsm[(wn * WTN + j * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
+                bfr[j] = *(const bf16x8 *)&bsm[(wn * WTN + j * 32 + (lane & 31)) * LDKv + kk + 8 * (lane >> 5)];
 #pragma unroll
             for (int i = 0; i < BM; ++i)
 #pragma unroll

@@ -55,7 +55,8 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
         count = bk.y;
     }
     if ((int)blockIdx.x * 64 >= nb) return;                  // whole workgroup
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int j = blockIdx.x * 64 + lane;
     const double s = g.s;
     const double cx = 0.5 * (nx - 1), cy = 0.5 * (ny - 1);
@@ -136,11 +137,11 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
             for (int r = 0; r < nl; ++r) {
                 const float u = fmaf((float)r, slopef[i], rem);       // crossing relative to ubase
                 const int i0 = (int)floorf(u - rhof[i]) + 1;
-                const float *row = base + r * seg_len;
-                for (int n = 0; n < ncand[i]; ++n) {
-                    const int q = i0 + n;
-                    const float w = fmaxf(0.0f, 1.0f - fabsf(af[i] * ((float)q - u)));
-                    acc[i] = fmaf(w, row[q], acc[i]);
+                const float *row = base + r * seg_len + i0;
+                float d = af[i] * ((float)i0 - u);               // t - j at the first candidate
+                for (int n = 0; n < ncand[i]; ++n, d += af[i]) {
+                    const float w = fmaxf(0.0f, 1.0f - fabsf(d));
+                    acc[i] = fmaf(w, row[n], acc[i]);
                 }
             }
         }
@@ -164,10 +165,79 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
     }
 }
 
+// Small problems (few workgroups of angle blocks): one projection per workgroup, its 4 wavefronts
+// take every fourth image line and add their partial sums in a fixed order through LDS.  The
+// crossing position is anchored in FP64 per line; the candidates are read from global memory.
+template <int MODE>
+__global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__restrict__ img,
+                                                       float *__restrict__ out, float alpha, CpDual cp, int k0)
+{
+    __shared__ float part[3][64];
+    const int slice = blockIdx.z;
+    const SliceDev sd = T.slc[slice];
+    const GeoDev &g = T.geo[sd.g];
+    const int K = g.K, nb = g.nb, nx = g.nx, ny = g.ny;
+    const int k = k0 + blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
+    if (k >= K || blockIdx.x * 64 >= nb) return;   // uniform over the workgroup
+
+    const double c = T.cosd[g.ang_off + k], sn = T.sind[g.ang_off + k];
+    const double s = g.s;
+    const double cx = 0.5 * (nx - 1), cy = 0.5 * (ny - 1);
+    const double t0 = g.axis + T.shiftd[g.ang_off + k];
+    const bool rows = fabs(c) >= fabs(sn);
+    const double a = rows ? s * c : s * sn, bb = rows ? s * sn : s * c;
+    const double ci = rows ? cx : cy, cl = rows ? cy : cx;
+    const int n_lines = rows ? ny : nx, n_pos = rows ? nx : ny;
+    const int64_t step_line = rows ? nx : 1, step_pos = rows ? 1 : nx;
+    const double rho = 1.0 / fabs(a);
+    const int ncand = (int)ceil(2.0 * rho);
+    const double slope = -bb / a;
+    const double u_first = ((double)j - t0 + a * ci + bb * cl) / a;
+    const float af = (float)a;
+    const float *im = img + sd.img_off;
+    float acc = 0.0f;
+    for (int l = wv; l < n_lines; l += 4) {
+        const double u = fma((double)l, slope, u_first);
+        const double fl = floor(u - rho);
+        const int i0 = (int)fl + 1;
+        float d = (float)((fl + 1.0) - u) * af;         // t - j at position i0
+        const float *line = im + (int64_t)l * step_line;
+        for (int n = 0; n < ncand; ++n, d += af) {
+            const int q = i0 + n;
+            const float w = fmaxf(0.0f, 1.0f - fabsf(d));
+            if ((unsigned)q < (unsigned)n_pos) acc = fmaf(w, line[(int64_t)q * step_pos], acc);
+        }
+    }
+    if (wv > 0) part[wv - 1][lane] = acc;
+    __syncthreads();
+    if (wv > 0 || j >= nb) return;
+    acc = ((acc + part[0][lane]) + part[1][lane]) + part[2][lane];
+    const int64_t o = sd.sino_off + (int64_t)k * nb + j;
+    const float v = alpha * (float)(s * s) * acc;
+    if (MODE == 0) {
+        out[o] = v;
+    } else if (MODE == 1) {
+        cp.p[o] = (cp.p[o] + cp.sigma * (v - cp.y[o])) / (1.0f + cp.sigma);
+    } else if (MODE == 2) {
+        cp.p[o] = v - cp.y[o];
+    } else {
+        cp.p[(int64_t)slice * nb + j] = v - cp.y[o];
+    }
+}
+
+// angle-block kernel when it has enough workgroups to fill the chip, else the line-split kernel
 template <int MODE>
 hipError_t launch_fp(const pyhst_plan &p, dim3 grid, const float *img, float *sino, float alpha, const CpDual &cp,
                      int k_single, hipStream_t st)
 {
+    const int64_t wgs = (int64_t)grid.x * grid.y * grid.z;
+    if (MODE == 3 || wgs < 8 * (int64_t)p.cu_count) {
+        dim3 g2(grid.x, MODE == 3 ? 1u : (unsigned)p.max_K, grid.z);
+        fp_lines_kernel<MODE><<<g2, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
+        return hipGetLastError();
+    }
     const int seg = p.fp_seg;
     const size_t lds = (size_t)FP_RB * seg * sizeof(float);
     if (lds > 65536) {
