@@ -167,7 +167,8 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
 
 // Small problems (few workgroups of angle blocks): one projection per workgroup, its 4 wavefronts
 // take every fourth image line and add their partial sums in a fixed order through LDS.  The
-// crossing position is anchored in FP64 per line; the candidates are read from global memory.
+// crossing position is anchored in FP64 every 8 lines of a wavefront (FP32 offsets below 30
+// positions in between); the candidates are read from global memory (L2).
 template <int MODE>
 __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__restrict__ img,
                                                        float *__restrict__ out, float alpha, CpDual cp, int k0)
@@ -195,19 +196,27 @@ __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__
     const int ncand = (int)ceil(2.0 * rho);
     const double slope = -bb / a;
     const double u_first = ((double)j - t0 + a * ci + bb * cl) / a;
-    const float af = (float)a;
+    const float af = (float)a, rhof = (float)rho, slopef = (float)slope;
     const float *im = img + sd.img_off;
     float acc = 0.0f;
-    for (int l = wv; l < n_lines; l += 4) {
-        const double u = fma((double)l, slope, u_first);
-        const double fl = floor(u - rho);
-        const int i0 = (int)fl + 1;
-        float d = (float)((fl + 1.0) - u) * af;         // t - j at position i0
-        const float *line = im + (int64_t)l * step_line;
-        for (int n = 0; n < ncand; ++n, d += af) {
-            const int q = i0 + n;
-            const float w = fmaxf(0.0f, 1.0f - fabsf(d));
-            if ((unsigned)q < (unsigned)n_pos) acc = fmaf(w, line[(int64_t)q * step_pos], acc);
+    // this wavefront's lines wv, wv + 4, ...: an FP64 anchor every 8 of them, FP32 offsets in between
+    for (int la = wv; la < n_lines; la += 32) {
+        const double ub = fma((double)la, slope, u_first);
+        const double ubase = floor(ub);
+        const float rem = (float)(ub - ubase);
+        const int ib = (int)ubase;
+        for (int m = 0; m < 8; ++m) {
+            const int l = la + 4 * m;
+            if (l >= n_lines) break;
+            const float u = fmaf((float)(4 * m), slopef, rem);   // crossing relative to ubase
+            const int i0 = (int)floorf(u - rhof) + 1;
+            float d = af * ((float)i0 - u);                         // t - j at the first candidate
+            const float *line = im + (int64_t)l * step_line;
+            for (int n = 0; n < ncand; ++n, d += af) {
+                const int q = ib + i0 + n;
+                const float w = fmaxf(0.0f, 1.0f - fabsf(d));
+                if ((unsigned)q < (unsigned)n_pos) acc = fmaf(w, line[(int64_t)q * step_pos], acc);
+            }
         }
     }
     if (wv > 0) part[wv - 1][lane] = acc;
