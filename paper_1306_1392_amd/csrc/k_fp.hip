@@ -29,7 +29,7 @@ namespace pyhst {
 // |a| >= s / sqrt(2)) plus a drift allowance of 96 positions for the other members of a block
 int fp_seg_len(double s_min)
 {
-    const int seg = (int)std::ceil(65.0 * 1.4142135623730951 / s_min + (FP_RB - 1) + 8.0 + 96.0);
+    const int seg = (int)std::ceil(65.0 * 1.4142135623730951 / s_min + (FP_RB - 1) + 10.0 + 96.0);
     return (seg + 3) & ~3;
 }
 
@@ -37,7 +37,9 @@ namespace {
 
 constexpr int AW = FP_AMAX / 4;   // projections per wavefront
 
-template <int MODE>
+// NC > 0: a fixed number of candidates per line (the surplus ones get zero weight), so the reads of
+// a line are independent and issue together; NC == 0: the exact count, ceil(2/|a|), at run time.
+template <int MODE, int NC>
 __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restrict__ img, float *__restrict__ out,
                                                  float alpha, CpDual cp, int k_single, int seg_len)
 {
@@ -139,9 +141,11 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
                 const int i0 = (int)floorf(u - rhof[i]) + 1;
                 const float *row = base + r * seg_len + i0;
                 float d = af[i] * ((float)i0 - u);               // t - j at the first candidate
-                for (int n = 0; n < ncand[i]; ++n, d += af[i]) {
-                    const float w = fmaxf(0.0f, 1.0f - fabsf(d));
-                    acc[i] = fmaf(w, row[n], acc[i]);
+                if (NC > 0) {
+#pragma unroll
+                    for (int n = 0; n < NC; ++n, d += af[i]) acc[i] = fmaf(fmaxf(0.0f, 1.0f - fabsf(d)), row[n], acc[i]);
+                } else {
+                    for (int n = 0; n < ncand[i]; ++n, d += af[i]) acc[i] = fmaf(fmaxf(0.0f, 1.0f - fabsf(d)), row[n], acc[i]);
                 }
             }
         }
@@ -169,7 +173,7 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
 // take every fourth image line and add their partial sums in a fixed order through LDS.  The
 // crossing position is anchored in FP64 every 8 lines of a wavefront (FP32 offsets below 30
 // positions in between); the candidates are read from global memory (L2).
-template <int MODE>
+template <int MODE, int NC>
 __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__restrict__ img,
                                                        float *__restrict__ out, float alpha, CpDual cp, int k0)
 {
@@ -212,10 +216,14 @@ __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__
             const int i0 = (int)floorf(u - rhof) + 1;
             float d = af * ((float)i0 - u);                         // t - j at the first candidate
             const float *line = im + (int64_t)l * step_line;
-            for (int n = 0; n < ncand; ++n, d += af) {
+            const int nc = NC > 0 ? NC : ncand;
+#pragma unroll
+            for (int n = 0; n < (NC > 0 ? NC : 8); ++n, d += af) {
+                if (NC == 0 && n >= nc) break;
                 const int q = ib + i0 + n;
                 const float w = fmaxf(0.0f, 1.0f - fabsf(d));
-                if ((unsigned)q < (unsigned)n_pos) acc = fmaf(w, line[(int64_t)q * step_pos], acc);
+                const float v = (unsigned)q < (unsigned)n_pos ? line[(int64_t)q * step_pos] : 0.0f;
+                acc = fmaf(w, v, acc);
             }
         }
     }
@@ -236,27 +244,47 @@ __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__
     }
 }
 
-// angle-block kernel when it has enough workgroups to fill the chip, else the line-split kernel
-template <int MODE>
-hipError_t launch_fp(const pyhst_plan &p, dim3 grid, const float *img, float *sino, float alpha, const CpDual &cp,
-                     int k_single, hipStream_t st)
+// candidates per line for the plan's smallest pixel size: ceil(2 sqrt 2 / s) <= 3 or <= 6, else run time
+int fp_nc(const pyhst_plan &p)
+{
+    double s_min = 1e300;
+    for (const auto &g : p.gd) s_min = std::min(s_min, g.s);
+    const int need = (int)std::ceil(2.0 * 1.4142135623730951 / s_min - 1e-9);
+    return need <= 3 ? 3 : (need <= 6 ? 6 : 0);
+}
+
+template <int MODE, int NC>
+hipError_t launch_fp_nc(const pyhst_plan &p, dim3 grid, const float *img, float *sino, float alpha,
+                        const CpDual &cp, int k_single, hipStream_t st)
 {
     const int64_t wgs = (int64_t)grid.x * grid.y * grid.z;
-    if (MODE == 3 || wgs < 8 * (int64_t)p.cu_count) {
+    if (MODE == 3 || NC == 0 || wgs < 8 * (int64_t)p.cu_count) {
+        // angle-block kernel only when it has enough workgroups to fill the chip
         dim3 g2(grid.x, MODE == 3 ? 1u : (unsigned)p.max_K, grid.z);
-        fp_lines_kernel<MODE><<<g2, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
+        fp_lines_kernel<MODE, NC><<<g2, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
         return hipGetLastError();
     }
     const int seg = p.fp_seg;
     const size_t lds = (size_t)FP_RB * seg * sizeof(float);
     if (lds > 65536) {
         if (lds > 160 * 1024) return hipErrorInvalidValue;
-        hipError_t e = hipFuncSetAttribute((const void *)fp_kernel<MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
+        hipError_t e = hipFuncSetAttribute((const void *)fp_kernel<MODE, NC>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    fp_kernel<MODE><<<grid, 256, lds, st>>>(p.t, img, sino, alpha, cp, k_single, seg);
+    fp_kernel<MODE, NC><<<grid, 256, lds, st>>>(p.t, img, sino, alpha, cp, k_single, seg);
     return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_fp(const pyhst_plan &p, dim3 grid, const float *img, float *sino, float alpha, const CpDual &cp,
+                     int k_single, hipStream_t st)
+{
+    switch (fp_nc(p)) {
+    case 3: return launch_fp_nc<MODE, 3>(p, grid, img, sino, alpha, cp, k_single, st);
+    case 6: return launch_fp_nc<MODE, 6>(p, grid, img, sino, alpha, cp, k_single, st);
+    default: return launch_fp_nc<MODE, 0>(p, grid, img, sino, alpha, cp, k_single, st);
+    }
 }
 
 }  // namespace

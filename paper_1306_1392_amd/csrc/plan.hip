@@ -267,7 +267,7 @@ void build_fp_blocks(const GeoHost &h, const GeoDev &d, int seg, std::vector<int
                         lo = std::min(lo, l1);
                         hi = std::max(hi, h1);
                     }
-                    ok = (hi - lo) + 4.0 <= (double)seg;
+                    ok = (hi - lo) + 6.0 <= (double)seg;   // floor slack and up to 2 zero-weight reads
                 }
             if (!ok) break;
             ++e;
