@@ -209,7 +209,8 @@ __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__
         const double ubase = floor(ub);
         const float rem = (float)(ub - ubase);
         const int ib = (int)ubase;
-        for (int m = 0; m < 8; ++m) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {                             // unrolled: the 8 lines' loads overlap
             const int l = la + 4 * m;
             if (l >= n_lines) break;
             const float u = fmaf((float)(4 * m), slopef, rem);   // crossing relative to ubase
