@@ -307,23 +307,52 @@ def run_fp(args):
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
     cases = {}
-    for name, (R, N, K) in {"tv1024": (1, 1024, 128), "fbp2048": (args.slices, 2048, 1800)}.items():
+    kinds = {"blocks": ph.FP_BLOCKS, "staged": ph.FP_STAGED, "lines": ph.FP_LINES}
+    shapes = {"tv1024": (1, 1024, 128), "mid1024": (8, 1024, 720), "fbp2048": (args.slices, 2048, 1800)}
+    for name, (R, N, K) in shapes.items():
         plan = ph.Plan(ph.Geometry(N, N, N, synth.uniform_angles(K), (N - 1) / 2 + 3.5), n_slices=R)
         g = torch.Generator(device=dev)
         g.manual_seed(7)
         img = torch.rand(plan.img_shape(), device=dev, generator=g)
         sino = torch.empty(plan.sino_shape(), device=dev)
         reps = 20 if R == 1 else 3
+        U = float(R) * N * N * K
+        # every kernel forced in turn (the line-split one only where it finishes quickly), then automatic
+        per_kind = {}
+        for kn, kv in kinds.items():
+            if kn == "lines" and U > 2e10:
+                continue
+            plan.set_fp_kernel(kv)
+            per_kind[kn] = round(_timed(stream, lambda: ph.forward_project(plan, img, out=sino, stream=stream), reps), 3)
+        plan.set_fp_kernel(ph.FP_AUTO)
         fp_ms = _timed(stream, lambda: ph.forward_project(plan, img, out=sino, stream=stream), reps)
         bp_ms = _timed(stream, lambda: ph.backproject(plan, sino, 0, out=img, stream=stream), reps)
-        U = float(R) * N * N * K
         cases[name] = {"slices": R, "n": N, "angles": K, "fp_ms": round(fp_ms, 3), "bp_ms": round(bp_ms, 3),
-                       "fp_gups": round(U / (fp_ms * 1e-3) / 1e9, 1), "bp_gups": round(U / (bp_ms * 1e-3) / 1e9, 1)}
+                       "fp_gups": round(U / (fp_ms * 1e-3) / 1e9, 1), "bp_gups": round(U / (bp_ms * 1e-3) / 1e9, 1),
+                       "fp_ms_by_kernel": per_kind}
+        if R == 1:
+            # the backprojector as the solvers use it: accumulating (beta = 1), alternating with the projector,
+            # and for every tile shape
+            cases[name]["bp_ms_beta1"] = round(_timed(stream, lambda: ph.backproject(
+                plan, sino, 0, out=img, alpha=-1e-6, beta=1.0, stream=stream), reps), 3)
+
+            def pair():
+                ph.forward_project(plan, img, out=sino, stream=stream)
+                ph.backproject(plan, sino, 0, out=img, alpha=1e-6, beta=0.0, stream=stream)
+            cases[name]["fp_then_bp_ms"] = round(_timed(stream, pair, reps), 3)
+            by_tile = {}
+            for t in range(5):
+                for pers in (False, True):
+                    plan.set_tiles(t, pers)
+                    by_tile[f"{t}{'p' if pers else ''}"] = round(_timed(stream, lambda: ph.backproject(
+                        plan, sino, 0, out=img, stream=stream), reps), 3)
+            plan.set_tiles(-1, False)
+            cases[name]["bp_ms_by_tile"] = by_tile
         log(f"fp: {name} {cases[name]}")
         del img, sino, plan
     res = {"metric": "forward projector GUPS (voxel-angle pairs/s)", "value": cases["fbp2048"]["fp_gups"],
            "unit": "GUPS", "higher_is_better": True, "n_gpus": 1, "dtype": "f32", "data": "synthetic (uniform random image)",
-           "config": {"workload": "A = s^2 B^T alone: 1024^2 x 128 angles and 64 x 2048^2 x 1800 angles"},
+           "config": {"workload": "A = s^2 B^T alone: 1024^2 x 128 angles, 8 x 1024^2 x 720 angles and 64 x 2048^2 x 1800 angles"},
            "cases": cases}
     print(json.dumps(res), flush=True)
 

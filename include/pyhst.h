@@ -60,6 +60,10 @@ enum {
 
 enum { PYHST_SCAN_180 = 0, PYHST_SCAN_360 = 1, PYHST_SCAN_360_HALF = 2 };
 enum { PYHST_FBP = 0, PYHST_TV_CP = 1, PYHST_ISTA = 2, PYHST_FISTA = 3 };
+/* Largest slice count of a plan or of one tv_prox call (one grid dimension). */
+enum { PYHST_MAX_SLICES = 65535 };
+/* Forward-projector kernels (pyhst_plan_set_fp_kernel). */
+enum { PYHST_FP_AUTO = 0, PYHST_FP_BLOCKS = 1, PYHST_FP_STAGED = 2, PYHST_FP_LINES = 3 };
 
 /* Geometry of one slice family (section 2.1: parallel beam, >= 180 degrees of
  * rotation, optional 360 degree half acquisition with the axis near a detector
@@ -92,7 +96,7 @@ typedef struct {
     int64_t img_offset;      /* element offset in packed [n_y][n_x] images */
 } pyhst_slice_info;
 
-/* Create a plan for n_slices slices.  g: host [n_geom] geometries; slice_geom:
+/* Create a plan for n_slices (1 .. PYHST_MAX_SLICES) slices.  g: host [n_geom] geometries; slice_geom:
  * host [n_slices] index into g for each slice, or NULL (all slices use g[0]).
  * The plan copies every host array, computes FP64 angle tables, angle
  * weights, half-acquisition weights and filter spectra, and keeps them in
@@ -109,6 +113,17 @@ int pyhst_plan_sizes(const pyhst_plan *plan, int64_t *sino_elems, int64_t *filt_
  * cost-sorted (slice, tile) work list. */
 int pyhst_plan_set_tiles(pyhst_plan *plan, int32_t bp_tile, int32_t persistent);
 int pyhst_plan_get_tiles(const pyhst_plan *plan, int32_t *bp_tile, int32_t *persistent);
+/* Forward-projector kernel for every projection this plan makes (forward_project,
+ * the iterative solvers, pyhst_cv_error): PYHST_FP_AUTO (the default) picks
+ * angle blocks when they give at least 8 workgroups per compute unit, else
+ * one projection per workgroup; PYHST_FP_BLOCKS: up to 32 projections of
+ * similar direction per workgroup sharing LDS-staged line segments;
+ * PYHST_FP_STAGED: one projection per workgroup, line segments staged in LDS
+ * (pixel size >= 0.5 only: smaller pixels take PYHST_FP_LINES); PYHST_FP_LINES:
+ * one projection per workgroup read straight from global memory.  All four
+ * compute the same sums up to FP32 rounding order.  EARG for another value. */
+int pyhst_plan_set_fp_kernel(pyhst_plan *plan, int32_t kind);
+int pyhst_plan_get_fp_kernel(const pyhst_plan *plan, int32_t *kind);
 /* Autotuner: times the backprojector of this plan for every tile shape, with
  * and without the persistent work queue (reps launches each, HIP events on
  * `stream`), on filt (filtered layout) -> img, and keeps the fastest.  Writes
@@ -175,7 +190,8 @@ int forward_project(const pyhst_plan *plan, const float *img, float *sino, hipSt
 /* Proximal map of lambda*TV (isotropic TV of eq. (2), forward differences with
  * a zero last difference):  out = argmin_u 1/2|u - in|^2 + lambda TV(u), by
  * n_inner steps of Chambolle's (2004) dual projection with step 1/8 from a
- * zero dual field.  in, out [n_slices][n_y][n_x]; in == out allowed.
+ * zero dual field.  in, out [n_slices][n_y][n_x] (n_slices <= PYHST_MAX_SLICES,
+ * n_y <= 524280); in == out allowed.
  * work: device scratch of at least 4*n_slices*n_y*n_x floats (two copies of the
  * dual field; work_floats gives its size); NULL or too small -> PYHST_EARG. */
 int tv_prox(int32_t n_slices, int32_t n_y, int32_t n_x, const float *in, float *out, float lambda,

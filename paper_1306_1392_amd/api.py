@@ -102,6 +102,15 @@ class Plan:
         check(self._L.pyhst_plan_get_tiles(self.handle, ctypes.byref(a), ctypes.byref(b)), "pyhst_plan_get_tiles")
         return a.value, bool(b.value)
 
+    def set_fp_kernel(self, kind: int = 0):
+        """Forward-projector kernel: FP_AUTO, FP_BLOCKS, FP_STAGED or FP_LINES."""
+        check(self._L.pyhst_plan_set_fp_kernel(self.handle, int(kind)), "pyhst_plan_set_fp_kernel")
+
+    def get_fp_kernel(self) -> int:
+        k = ctypes.c_int32()
+        check(self._L.pyhst_plan_get_fp_kernel(self.handle, ctypes.byref(k)), "pyhst_plan_get_fp_kernel")
+        return k.value
+
     # shapes of the packed buffers of a uniform plan
     def sino_shape(self):
         g = self.geoms[0]

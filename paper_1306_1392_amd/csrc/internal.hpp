@@ -97,6 +97,7 @@ struct pyhst_plan {
     int fp_seg = 0, fp_max_blocks = 0;
     int64_t n_items[pyhst::N_TILE_CFG] = {};
     int bp_tile = -1, persistent = 0;
+    int fp_kernel = PYHST_FP_AUTO;
     void *dev_block = nullptr;
     pyhst::Tables t{};
     int cu_count = 256;

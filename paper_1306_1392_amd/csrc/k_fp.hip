@@ -245,6 +245,126 @@ __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__
     }
 }
 
+// Small problems, pixel size >= 0.5 (NC > 0): one projection per workgroup, staged through LDS.
+// The workgroup walks the image lines in blocks of FP_RB; the 64 bins of one projection touch, over
+// a block, a segment of at most 63/|a| + (FP_RB - 1)|slope| + 1/|a| + NC + 3 positions of every line
+// (< FPS_SEG), which 256 threads stage with 16-wide contiguous reads along the image rows in both
+// walking directions (so a column-walking projection reads rows of 16 neighbouring columns rather
+// than 64 separate rows).  The next block is loaded into registers while the current one is summed
+// from the other LDS buffer: one barrier per block.  Wavefront w sums lines w, w + 4, ... of every
+// block; the four partial sums are added in a fixed order through LDS.
+template <int NC> struct FpStaged {
+    static constexpr int SEG = NC == 3 ? 128 : 224;   // positions staged per line
+    static constexpr int LD = SEG + 17;               // LDS row stride: 17 mod 32 spreads the banks
+    static constexpr int PER = SEG / 16;              // staged values per thread and block
+};
+
+template <int MODE, int NC>
+__global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *__restrict__ img,
+                                                        float *__restrict__ out, float alpha, CpDual cp, int k0)
+{
+    using F = FpStaged<NC>;
+    __shared__ float stage[2][FP_RB * F::LD];
+    __shared__ float part[3][64];
+    const int slice = blockIdx.z;
+    const SliceDev sd = T.slc[slice];
+    const GeoDev &g = T.geo[sd.g];
+    const int K = g.K, nb = g.nb, nx = g.nx, ny = g.ny;
+    const int k = k0 + blockIdx.y;
+    const int j0 = blockIdx.x * 64;
+    if (k >= K || j0 >= nb) return;   // uniform over the workgroup
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int j = j0 + lane;
+
+    const double c = T.cosd[g.ang_off + k], sn = T.sind[g.ang_off + k];
+    const double s = g.s;
+    const double cx = 0.5 * (nx - 1), cy = 0.5 * (ny - 1);
+    const double t0 = g.axis + T.shiftd[g.ang_off + k];
+    const bool rows = fabs(c) >= fabs(sn);
+    const double a = rows ? s * c : s * sn, bb = rows ? s * sn : s * c;
+    const double ci = rows ? cx : cy, cl = rows ? cy : cx;
+    const int n_lines = rows ? ny : nx, n_pos = rows ? nx : ny;
+    const double rho = 1.0 / fabs(a);
+    const double slope = -bb / a;
+    const double u_c = -t0 + a * ci + bb * cl;
+    const double u_first = ((double)j + u_c) / a;
+    // lowest candidate of the workgroup's 64 bins over a block's FP_RB lines, relative to its first line
+    const double blk_lo = fmin(((double)j0 + u_c) / a, ((double)(j0 + 63) + u_c) / a) +
+                          fmin(0.0, (FP_RB - 1) * slope) - rho;
+    const float af = (float)a, rhof = (float)rho, slopef = (float)slope;
+    const float *im = img + sd.img_off;
+    // staging map: 16 consecutive threads read 16 consecutive floats of one image row
+    const int sr = rows ? tid >> 4 : tid & 15;     // staged line within the block
+    const int sp = rows ? tid & 15 : tid >> 4;     // first staged position of this thread
+    const int64_t step_line = rows ? nx : 1, step_pos = rows ? 1 : nx;
+    const int n_blk = (n_lines + FP_RB - 1) / FP_RB;
+
+    float v[F::PER];
+    auto load = [&](int b, int &seg0) {
+        const int l0 = b * FP_RB;
+        seg0 = (int)floor(fma((double)l0, slope, blk_lo)) - 2;
+        const int line = l0 + sr;
+        const bool lok = line < n_lines;
+        const float *src = im + (int64_t)(lok ? line : 0) * step_line;
+#pragma unroll
+        for (int i = 0; i < F::PER; ++i) {
+            const int pos = seg0 + sp + 16 * i;
+            v[i] = (lok && (unsigned)pos < (unsigned)n_pos) ? src[(int64_t)pos * step_pos] : 0.0f;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < F::PER; ++i) stage[buf][sr * F::LD + sp + 16 * i] = v[i];
+    };
+
+    float acc = 0.0f;
+    int seg_cur, seg_next = 0;
+    load(0, seg_cur);
+    store(0);
+    __syncthreads();
+    for (int b = 0; b < n_blk; ++b) {
+        const bool more = b + 1 < n_blk;
+        if (more) load(b + 1, seg_next);
+        const int l0 = b * FP_RB;
+        const double ub = fma((double)l0, slope, u_first);   // FP64 anchor of this lane and block
+        const double ubase = floor(ub);
+        const float rem = (float)(ub - ubase);
+        const float *base = stage[b & 1] + ((int)ubase - seg_cur);
+#pragma unroll
+        for (int m = 0; m < FP_RB / 4; ++m) {
+            const int r = wv + 4 * m;
+            if (l0 + r >= n_lines) break;                     // uniform
+            const float u = fmaf((float)r, slopef, rem);      // crossing relative to ubase
+            const int i0 = (int)floorf(u - rhof) + 1;
+            float d = af * ((float)i0 - u);                    // t - j at the first candidate
+            const float *row = base + r * F::LD + i0;
+#pragma unroll
+            for (int n = 0; n < NC; ++n, d += af) acc = fmaf(fmaxf(0.0f, 1.0f - fabsf(d)), row[n], acc);
+        }
+        if (more) {
+            store((b + 1) & 1);
+            seg_cur = seg_next;
+        }
+        __syncthreads();
+    }
+    if (wv > 0) part[wv - 1][lane] = acc;
+    __syncthreads();
+    if (wv > 0 || j >= nb) return;
+    acc = ((acc + part[0][lane]) + part[1][lane]) + part[2][lane];
+    const int64_t o = sd.sino_off + (int64_t)k * nb + j;
+    const float val = alpha * (float)(s * s) * acc;
+    if (MODE == 0) {
+        out[o] = val;
+    } else if (MODE == 1) {
+        cp.p[o] = (cp.p[o] + cp.sigma * (val - cp.y[o])) / (1.0f + cp.sigma);
+    } else if (MODE == 2) {
+        cp.p[o] = val - cp.y[o];
+    } else {
+        cp.p[(int64_t)slice * nb + j] = val - cp.y[o];
+    }
+}
+
 // candidates per line for the plan's smallest pixel size: ceil(2 sqrt 2 / s) <= 3 or <= 6, else run time
 int fp_nc(const pyhst_plan &p)
 {
@@ -258,10 +378,20 @@ template <int MODE, int NC>
 hipError_t launch_fp_nc(const pyhst_plan &p, dim3 grid, const float *img, float *sino, float alpha,
                         const CpDual &cp, int k_single, hipStream_t st)
 {
-    const int64_t wgs = (int64_t)grid.x * grid.y * grid.z;
-    if (MODE == 3 || NC == 0 || wgs < 8 * (int64_t)p.cu_count) {
-        // angle-block kernel only when it has enough workgroups to fill the chip
-        dim3 g2(grid.x, MODE == 3 ? 1u : (unsigned)p.max_K, grid.z);
+    int kind = p.fp_kernel;
+    if (kind == PYHST_FP_AUTO) {
+        // angle blocks only when they give enough workgroups to fill the chip; one projection per
+        // workgroup otherwise, staged through LDS when the candidate count is fixed
+        const int64_t wgs = (int64_t)grid.x * grid.y * grid.z;
+        kind = (MODE == 3 || wgs < 8 * (int64_t)p.cu_count) ? PYHST_FP_STAGED : PYHST_FP_BLOCKS;
+    }
+    if (kind == PYHST_FP_STAGED && NC == 0) kind = PYHST_FP_LINES;
+    const dim3 g2(grid.x, MODE == 3 ? 1u : (unsigned)p.max_K, grid.z);
+    if (kind == PYHST_FP_STAGED) {
+        if constexpr (NC > 0) fp_staged_kernel<MODE, NC><<<g2, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
+        return hipGetLastError();
+    }
+    if (kind == PYHST_FP_LINES) {
         fp_lines_kernel<MODE, NC><<<g2, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
         return hipGetLastError();
     }

@@ -29,33 +29,66 @@ __device__ inline float divergence(const float *q1, const float *q2, int64_t o, 
     return a + b;
 }
 
+// 2-D launch over images: workgroup = 64 x 8 pixels of one slice (256 threads, two rows each), so that
+// no thread divides a 64-bit index; grid (ceil(nx / 64), ceil(ny / 8), slices).
+constexpr int TTX = 64, TTY = 8;
+
 // One fused inner step of the ROF dual projection:  q = (p + tau grad v) / (1 + tau |grad v|) with
-// v = div p - g / lambda evaluated at o and its +x / +y neighbours (p read, q written: ping-pong).
-__global__ void prox_step_kernel(int64_t n, int ny, int nx, const float *__restrict__ p1, const float *__restrict__ p2,
-                                 const float *__restrict__ g, float inv_lambda, float tau, float *__restrict__ q1,
-                                 float *__restrict__ q2)
+// v = div p - g / lambda (p read, q written: ping-pong).  The workgroup evaluates v once per pixel of its
+// tile plus the row below and the column to the right into LDS, then takes the forward differences
+// from there.  ZERO: p = 0 (the first step), which is neither read nor needs clearing.
+template <bool ZERO>
+__global__ __launch_bounds__(256) void prox_step_kernel(int ny, int nx, const float *__restrict__ p1,
+                                                        const float *__restrict__ p2, const float *__restrict__ g,
+                                                        float inv_lambda, float tau, float *__restrict__ q1,
+                                                        float *__restrict__ q2)
 {
-    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t pix = o % ((int64_t)ny * nx);
-        const int iy = (int)(pix / nx), ix = (int)(pix - (int64_t)iy * nx);
-        const float v0 = divergence(p1, p2, o, ix, iy, nx, ny) - g[o] * inv_lambda;
-        const float a = ix + 1 < nx ? (divergence(p1, p2, o + 1, ix + 1, iy, nx, ny) - g[o + 1] * inv_lambda) - v0 : 0.0f;
-        const float b =
-            iy + 1 < ny ? (divergence(p1, p2, o + nx, ix, iy + 1, nx, ny) - g[o + nx] * inv_lambda) - v0 : 0.0f;
+    __shared__ float v[TTY + 1][TTX + 1];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int x0 = blockIdx.x * TTX, y0 = blockIdx.y * TTY;
+    const int64_t base = (int64_t)blockIdx.z * ny * nx;
+    auto v_at = [&](int x, int y) {
+        const int64_t o = base + (int64_t)y * nx + x;
+        const float d = ZERO ? 0.0f : divergence(p1, p2, o, x, y, nx, ny);
+        return d - g[o] * inv_lambda;
+    };
+#pragma unroll
+    for (int r = ty; r < TTY; r += 4)
+        if (x0 + tx < nx && y0 + r < ny) v[r][tx] = v_at(x0 + tx, y0 + r);
+    if (ty == 0) {
+        if (x0 + tx < nx && y0 + TTY < ny) v[TTY][tx] = v_at(x0 + tx, y0 + TTY);
+    } else if (ty == 1 && tx < TTY) {
+        if (x0 + TTX < nx && y0 + tx < ny) v[tx][TTX] = v_at(x0 + TTX, y0 + tx);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = ty; r < TTY; r += 4) {
+        const int x = x0 + tx, y = y0 + r;
+        if (x >= nx || y >= ny) continue;
+        const float v0 = v[r][tx];
+        const float a = x + 1 < nx ? v[r][tx + 1] - v0 : 0.0f;
+        const float b = y + 1 < ny ? v[r + 1][tx] - v0 : 0.0f;
         const float m = 1.0f + tau * sqrtf(a * a + b * b);
-        q1[o] = (p1[o] + tau * a) / m;
-        q2[o] = (p2[o] + tau * b) / m;
+        const int64_t o = base + (int64_t)y * nx + x;
+        q1[o] = ((ZERO ? 0.0f : p1[o]) + tau * a) / m;
+        q2[o] = ((ZERO ? 0.0f : p2[o]) + tau * b) / m;
     }
 }
 
 // u = g - lambda div p
-__global__ void prox_final_kernel(int64_t n, int ny, int nx, const float *__restrict__ p1,
-                                  const float *__restrict__ p2, const float *g, float lambda, float *u)
+__global__ __launch_bounds__(256) void prox_final_kernel(int ny, int nx, const float *__restrict__ p1,
+                                                         const float *__restrict__ p2, const float *g, float lambda,
+                                                         float *u)
 {
-    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t pix = o % ((int64_t)ny * nx);
-        const int iy = (int)(pix / nx), ix = (int)(pix - (int64_t)iy * nx);
-        u[o] = g[o] - lambda * divergence(p1, p2, o, ix, iy, nx, ny);
+    const int x = blockIdx.x * TTX + (threadIdx.x & 63);
+    if (x >= nx) return;
+    const int64_t base = (int64_t)blockIdx.z * ny * nx;
+#pragma unroll
+    for (int r = threadIdx.x >> 6; r < TTY; r += 4) {
+        const int y = blockIdx.y * TTY + r;
+        if (y >= ny) break;
+        const int64_t o = base + (int64_t)y * nx + x;
+        u[o] = g[o] - lambda * divergence(p1, p2, o, x, y, nx, ny);
     }
 }
 
@@ -98,12 +131,18 @@ __global__ void momentum_kernel(float *__restrict__ z, const float *__restrict__
 }
 
 // Chambolle-Pock dual TV step: q <- pi_lambda(q + sigma grad xbar)
-__global__ void cp_q_kernel(int64_t n, int ny, int nx, const float *__restrict__ xb, float *__restrict__ q1,
-                            float *__restrict__ q2, float sigma, float lambda)
+__global__ __launch_bounds__(256) void cp_q_kernel(int ny, int nx, const float *__restrict__ xb,
+                                                   float *__restrict__ q1, float *__restrict__ q2, float sigma,
+                                                   float lambda)
 {
-    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t pix = o % ((int64_t)ny * nx);
-        const int iy = (int)(pix / nx), ix = (int)(pix - (int64_t)iy * nx);
+    const int ix = blockIdx.x * TTX + (threadIdx.x & 63);
+    if (ix >= nx) return;
+    const int64_t base = (int64_t)blockIdx.z * ny * nx;
+#pragma unroll
+    for (int r = threadIdx.x >> 6; r < TTY; r += 4) {
+        const int iy = blockIdx.y * TTY + r;
+        if (iy >= ny) break;
+        const int64_t o = base + (int64_t)iy * nx + ix;
         float a = q1[o] + sigma * grad_x(xb, o, ix, nx);
         float b = q2[o] + sigma * grad_y(xb, o, iy, ny, nx);
         if (lambda > 0.0f) {
@@ -120,11 +159,17 @@ __global__ void cp_q_kernel(int64_t n, int ny, int nx, const float *__restrict__
 }
 
 // out -= div(grad x)  (so that out = A^T A x + grad^T grad x)
-__global__ void sub_divgrad_kernel(int64_t n, int ny, int nx, const float *__restrict__ x, float *__restrict__ out)
+__global__ __launch_bounds__(256) void sub_divgrad_kernel(int ny, int nx, const float *__restrict__ x,
+                                                          float *__restrict__ out)
 {
-    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t pix = o % ((int64_t)ny * nx);
-        const int iy = (int)(pix / nx), ix = (int)(pix - (int64_t)iy * nx);
+    const int ix = blockIdx.x * TTX + (threadIdx.x & 63);
+    if (ix >= nx) return;
+    const int64_t base = (int64_t)blockIdx.z * ny * nx;
+#pragma unroll
+    for (int r = threadIdx.x >> 6; r < TTY; r += 4) {
+        const int iy = blockIdx.y * TTY + r;
+        if (iy >= ny) break;
+        const int64_t o = base + (int64_t)iy * nx + ix;
         // div(grad x) at o, from the forward differences around o
         float a, b;
         const float gx = grad_x(x, o, ix, nx), gy = grad_y(x, o, iy, ny, nx);
@@ -210,6 +255,11 @@ __global__ void scale_inv_sqrt_kernel(float *x, int64_t n, const double *sumsq)
         x[o] *= inv;
 }
 
+dim3 grid_img(int S, int ny, int nx)
+{
+    return dim3((unsigned)((nx + TTX - 1) / TTX), (unsigned)((ny + TTY - 1) / TTY), (unsigned)S);
+}
+
 unsigned grid_for(int64_t n)
 {
     int64_t b = (n + 255) / 256;
@@ -261,13 +311,14 @@ hipError_t launch_tv_prox(int S, int ny, int nx, const float *in, float *out, fl
         return hipGetLastError();
     }
     float *p1 = work, *p2 = work + n, *q1 = work + 2 * n, *q2 = work + 3 * n;
-    fill_kernel<<<grid_for(2 * n), 256, 0, st>>>(work, 2 * n, 0.0f);
+    const dim3 gi = grid_img(S, ny, nx);
     for (int it = 0; it < n_inner; ++it) {
-        prox_step_kernel<<<grid_for(n), 256, 0, st>>>(n, ny, nx, p1, p2, in, 1.0f / lambda, 0.125f, q1, q2);
+        if (it == 0) prox_step_kernel<true><<<gi, 256, 0, st>>>(ny, nx, p1, p2, in, 1.0f / lambda, 0.125f, q1, q2);
+        else prox_step_kernel<false><<<gi, 256, 0, st>>>(ny, nx, p1, p2, in, 1.0f / lambda, 0.125f, q1, q2);
         std::swap(p1, q1);
         std::swap(p2, q2);
     }
-    prox_final_kernel<<<grid_for(n), 256, 0, st>>>(n, ny, nx, p1, p2, in, lambda, out);
+    prox_final_kernel<<<gi, 256, 0, st>>>(ny, nx, p1, p2, in, lambda, out);
     return hipGetLastError();
 }
 
@@ -275,8 +326,7 @@ hipError_t launch_cp_dual_q(const pyhst_plan &p, const float *xbar, float *q1, f
                             hipStream_t st)
 {
     const GeoDev &g = p.gd[0];
-    const int64_t n = (int64_t)p.n_slices * g.ny * g.nx;
-    cp_q_kernel<<<grid_for(n), 256, 0, st>>>(n, g.ny, g.nx, xbar, q1, q2, sigma, lambda);
+    cp_q_kernel<<<grid_img(p.n_slices, g.ny, g.nx), 256, 0, st>>>(g.ny, g.nx, xbar, q1, q2, sigma, lambda);
     return hipGetLastError();
 }
 
@@ -301,7 +351,7 @@ hipError_t launch_power_step(const pyhst_plan &p, const float *x, float *out, fl
     e = launch_backproject(p, tmp_sino, 0, out, s2, 0.0f, nullptr, st);
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)p.n_slices * g.ny * g.nx;
-    if (with_grad) sub_divgrad_kernel<<<grid_for(n), 256, 0, st>>>(n, g.ny, g.nx, x, out);
+    if (with_grad) sub_divgrad_kernel<<<grid_img(p.n_slices, g.ny, g.nx), 256, 0, st>>>(g.ny, g.nx, x, out);
     sumsq_partial_kernel<<<n_part, 256, 0, st>>>(n, out, partials);
     final_sum_kernel<<<1, 256, 0, st>>>(partials, n_part, nullptr, norm_dev);
     return hipGetLastError();

@@ -287,6 +287,8 @@ int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_
     if (!out) return fail(PYHST_EARG, "plan_create: out is NULL");
     *out = nullptr;
     if (!g || n_geom <= 0 || n_slices <= 0) return fail(PYHST_EARG, "plan_create: need geometries and slices");
+    if (n_slices > PYHST_MAX_SLICES)
+        return fail(PYHST_EARG, "plan_create: at most 65535 slices per plan (split larger stacks)");
     try {
         auto *p = new pyhst_plan();
         std::unique_ptr<pyhst_plan> guard(p);
@@ -582,6 +584,23 @@ int pyhst_plan_set_tiles(pyhst_plan *p, int32_t bp_tile, int32_t persistent)
     return PYHST_OK;
 }
 
+int pyhst_plan_set_fp_kernel(pyhst_plan *p, int32_t kind)
+{
+    if (!p || kind < PYHST_FP_AUTO || kind > PYHST_FP_LINES) return fail(PYHST_EARG, "set_fp_kernel: bad argument");
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->fp_kernel = kind;
+    for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+    p->graphs.clear();
+    return PYHST_OK;
+}
+
+int pyhst_plan_get_fp_kernel(const pyhst_plan *p, int32_t *kind)
+{
+    if (!p || !kind) return fail(PYHST_EARG, "get_fp_kernel: NULL argument");
+    *kind = p->fp_kernel;
+    return PYHST_OK;
+}
+
 int pyhst_plan_get_tiles(const pyhst_plan *p, int32_t *bp_tile, int32_t *persistent)
 {
     if (!p) return fail(PYHST_EARG, "get_tiles: plan is NULL");
@@ -658,6 +677,8 @@ int tv_prox(int32_t n_slices, int32_t n_y, int32_t n_x, const float *in, float *
             float *work, size_t work_floats, hipStream_t st)
 {
     if (n_slices <= 0 || n_y <= 0 || n_x <= 0 || !in || !out) return fail(PYHST_EARG, "tv_prox: bad argument");
+    if (n_slices > PYHST_MAX_SLICES || n_y > 8 * 65535)
+        return fail(PYHST_EARG, "tv_prox: at most 65535 slices of at most 524280 rows");
     if (!std::isfinite(lambda) || lambda < 0.0f || n_inner < 0) return fail(PYHST_EARG, "tv_prox: bad lambda/n_inner");
     const size_t need = 4 * (size_t)n_slices * n_y * n_x;
     if (lambda > 0.0f && n_inner > 0 && (!work || work_floats < need))

@@ -58,6 +58,8 @@ def test_invalid_geometry_rejected_on_host():
     assert _plan_rc(ph.Geometry(8, 8, 40, ang2, 20.0, scan=ph.SCAN_360_HALF)) == _lib.EGEOM
     assert _plan_rc(ph.Geometry(8, 8, 40, ang2, 35.0, scan=ph.SCAN_360_HALF, ha_overlap=6.0)) == _lib.EARG
     assert _plan_rc(ph.Geometry(8, 8, 8, ang, 3.5), n_slices=0) == _lib.EARG
+    assert _plan_rc(ph.Geometry(8, 8, 8, ang, 3.5), n_slices=65536) == _lib.EARG    # one grid dimension
+    assert b"65535" in ph.lib().pyhst_last_error()
     assert b"cover" in ph.lib().pyhst_last_error() or b"slices" in ph.lib().pyhst_last_error()
 
 
@@ -72,6 +74,8 @@ def test_null_arguments():
     assert L.backproject(None, None, 0, None, 1.0, 0.0, None) == _lib.EARG
     assert L.forward_project(None, None, None, None) == _lib.EARG
     assert L.tv_prox(1, 4, 4, None, None, 0.1, 10, None, 0, None) == _lib.EARG
+    # too many slices: rejected on the host before any pointer is used
+    assert L.tv_prox(65536, 4, 4, 16, 16, 0.1, 10, 16, 1 << 40, None) == _lib.EARG
     assert L.reconstruct_slices(None, None, None) == _lib.EARG
 
 

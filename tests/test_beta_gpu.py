@@ -12,7 +12,8 @@ from paper_1306_1392_amd.beta import select_beta
 pytestmark = pytest.mark.gpu
 
 
-def test_cv_error_parity(dev):
+@pytest.mark.parametrize("kind", [ph.FP_AUTO, ph.FP_BLOCKS, ph.FP_STAGED, ph.FP_LINES])
+def test_cv_error_parity(dev, kind):
     N, K, nb = 40, 24, 50
     rng = synth.rng_for(8, 0, 0)
     ang = synth.uniform_angles(K) + rng.uniform(-0.3, 0.3, K) * np.pi / K   # jittered, still covering 180 deg
@@ -22,6 +23,7 @@ def test_cv_error_parity(dev):
     x = rng.standard_normal((2, N, N)).astype(np.float32)
     y = (oracle.forward_project(x, og) * 0.9 + 0.3 * rng.standard_normal((2, K, nb))).astype(np.float32)
     plan = ph.Plan(g, n_slices=2)
+    plan.set_fp_kernel(kind)
     xt, yt = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
     for k in (0, 7, K - 1):
         got = ph.cv_error(plan, xt, yt, k).cpu().numpy()
