@@ -96,7 +96,8 @@ typedef struct {
     int64_t img_offset;      /* element offset in packed [n_y][n_x] images */
 } pyhst_slice_info;
 
-/* Create a plan for n_slices (1 .. PYHST_MAX_SLICES) slices.  g: host [n_geom] geometries; slice_geom:
+/* Create a plan for n_slices (1 .. PYHST_MAX_SLICES) slices of at most 2^31 - 1
+ * pixels each (n_x * n_y).  g: host [n_geom] geometries; slice_geom:
  * host [n_slices] index into g for each slice, or NULL (all slices use g[0]).
  * The plan copies every host array, computes FP64 angle tables, angle
  * weights, half-acquisition weights and filter spectra, and keeps them in

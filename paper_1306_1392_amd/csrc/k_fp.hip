@@ -37,9 +37,25 @@ namespace {
 
 constexpr int AW = FP_AMAX / 4;   // projections per wavefront
 
+// The NC candidates of one line: weights hat(d), hat(d + a), ... with d the signed offset t - j of the
+// first one.  With 2/3 <= |a| <= 1 (UNIT: pixel size in [0.943, 1], three candidates) the first candidate
+// lies in (u - 1/|a|, u - 1/|a| + 1], so |d| < 1 and |d + a| <= 1: only the third weight can be
+// clamped to zero, and the other two skip the max (they differ from the clamped form only by FP32
+// rounding at the hat's end points, where the weight is zero to within an ulp).
+template <int NC, bool UNIT>
+__device__ __forceinline__ float hat_line(const float *row, float d, float af, float acc)
+{
+#pragma unroll
+    for (int n = 0; n < NC; ++n, d += af) {
+        const float w = (UNIT && n < 2) ? 1.0f - fabsf(d) : fmaxf(0.0f, 1.0f - fabsf(d));
+        acc = fmaf(w, row[n], acc);
+    }
+    return acc;
+}
+
 // NC > 0: a fixed number of candidates per line (the surplus ones get zero weight), so the reads of
 // a line are independent and issue together; NC == 0: the exact count, ceil(2/|a|), at run time.
-template <int MODE, int NC>
+template <int MODE, int NC, bool UNIT>
 __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restrict__ img, float *__restrict__ out,
                                                  float alpha, CpDual cp, int k_single, int seg_len)
 {
@@ -141,9 +157,8 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
                 const int i0 = (int)floorf(u - rhof[i]) + 1;
                 const float *row = base + r * seg_len + i0;
                 float d = af[i] * ((float)i0 - u);               // t - j at the first candidate
-                if (NC > 0) {
-#pragma unroll
-                    for (int n = 0; n < NC; ++n, d += af[i]) acc[i] = fmaf(fmaxf(0.0f, 1.0f - fabsf(d)), row[n], acc[i]);
+                if constexpr (NC > 0) {
+                    acc[i] = hat_line<NC, UNIT>(row, d, af[i], acc[i]);
                 } else {
                     for (int n = 0; n < ncand[i]; ++n, d += af[i]) acc[i] = fmaf(fmaxf(0.0f, 1.0f - fabsf(d)), row[n], acc[i]);
                 }
@@ -173,7 +188,7 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
 // take every fourth image line and add their partial sums in a fixed order through LDS.  The
 // crossing position is anchored in FP64 every 8 lines of a wavefront (FP32 offsets below 30
 // positions in between); the candidates are read from global memory (L2).
-template <int MODE, int NC>
+template <int MODE, int NC, bool UNIT>
 __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__restrict__ img,
                                                        float *__restrict__ out, float alpha, CpDual cp, int k0)
 {
@@ -259,7 +274,7 @@ template <int NC> struct FpStaged {
     static constexpr int PER = SEG / 16;              // staged values per thread and block
 };
 
-template <int MODE, int NC>
+template <int MODE, int NC, bool UNIT>
 __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *__restrict__ img,
                                                         float *__restrict__ out, float alpha, CpDual cp, int k0)
 {
@@ -297,7 +312,8 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
     // staging map: 16 consecutive threads read 16 consecutive floats of one image row
     const int sr = rows ? tid >> 4 : tid & 15;     // staged line within the block
     const int sp = rows ? tid & 15 : tid >> 4;     // first staged position of this thread
-    const int64_t step_line = rows ? nx : 1, step_pos = rows ? 1 : nx;
+    // 32-bit offsets inside one slice (the plan keeps n_x n_y below 2^31)
+    const int step_line = rows ? nx : 1, step_pos = rows ? 1 : nx;
     const int n_blk = (n_lines + FP_RB - 1) / FP_RB;
 
     float v[F::PER];
@@ -305,12 +321,18 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
         const int l0 = b * FP_RB;
         seg0 = (int)floor(fma((double)l0, slope, blk_lo)) - 2;
         const int line = l0 + sr;
-        const bool lok = line < n_lines;
-        const float *src = im + (int64_t)(lok ? line : 0) * step_line;
+        if (line < n_lines && seg0 >= 0 && seg0 + F::SEG <= n_pos) {
+            // the whole staged segment lies inside the image (most blocks): no per-element test
+            const float *src = im + (line * step_line + (seg0 + sp) * step_pos);
+            const int d16 = 16 * step_pos;
 #pragma unroll
-        for (int i = 0; i < F::PER; ++i) {
-            const int pos = seg0 + sp + 16 * i;
-            v[i] = (lok && (unsigned)pos < (unsigned)n_pos) ? src[(int64_t)pos * step_pos] : 0.0f;
+            for (int i = 0; i < F::PER; ++i) v[i] = src[i * d16];
+        } else {
+#pragma unroll
+            for (int i = 0; i < F::PER; ++i) {
+                const int pos = seg0 + sp + 16 * i;
+                v[i] = (line < n_lines && (unsigned)pos < (unsigned)n_pos) ? im[line * step_line + pos * step_pos] : 0.0f;
+            }
         }
     };
     auto store = [&](int buf) {
@@ -338,9 +360,7 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
             const float u = fmaf((float)r, slopef, rem);      // crossing relative to ubase
             const int i0 = (int)floorf(u - rhof) + 1;
             float d = af * ((float)i0 - u);                    // t - j at the first candidate
-            const float *row = base + r * F::LD + i0;
-#pragma unroll
-            for (int n = 0; n < NC; ++n, d += af) acc = fmaf(fmaxf(0.0f, 1.0f - fabsf(d)), row[n], acc);
+            acc = hat_line<NC, UNIT>(base + r * F::LD + i0, d, af, acc);
         }
         if (more) {
             store((b + 1) & 1);
@@ -374,7 +394,15 @@ int fp_nc(const pyhst_plan &p)
     return need <= 3 ? 3 : (need <= 6 ? 6 : 0);
 }
 
-template <int MODE, int NC>
+// three candidates and no pixel wider than a bin: |a| in [2/3, 1] for every projection
+bool fp_unit(const pyhst_plan &p)
+{
+    double s_max = 0.0;
+    for (const auto &g : p.gd) s_max = std::max(s_max, g.s);
+    return fp_nc(p) == 3 && s_max <= 1.0;
+}
+
+template <int MODE, int NC, bool UNIT>
 hipError_t launch_fp_nc(const pyhst_plan &p, dim3 grid, const float *img, float *sino, float alpha,
                         const CpDual &cp, int k_single, hipStream_t st)
 {
@@ -388,22 +416,23 @@ hipError_t launch_fp_nc(const pyhst_plan &p, dim3 grid, const float *img, float 
     if (kind == PYHST_FP_STAGED && NC == 0) kind = PYHST_FP_LINES;
     const dim3 g2(grid.x, MODE == 3 ? 1u : (unsigned)p.max_K, grid.z);
     if (kind == PYHST_FP_STAGED) {
-        if constexpr (NC > 0) fp_staged_kernel<MODE, NC><<<g2, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
+        if constexpr (NC > 0)
+            fp_staged_kernel<MODE, NC, UNIT><<<g2, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
         return hipGetLastError();
     }
     if (kind == PYHST_FP_LINES) {
-        fp_lines_kernel<MODE, NC><<<g2, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
+        fp_lines_kernel<MODE, NC, false><<<g2, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
         return hipGetLastError();
     }
     const int seg = p.fp_seg;
     const size_t lds = (size_t)FP_RB * seg * sizeof(float);
     if (lds > 65536) {
         if (lds > 160 * 1024) return hipErrorInvalidValue;
-        hipError_t e = hipFuncSetAttribute((const void *)fp_kernel<MODE, NC>,
+        hipError_t e = hipFuncSetAttribute((const void *)fp_kernel<MODE, NC, UNIT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    fp_kernel<MODE, NC><<<grid, 256, lds, st>>>(p.t, img, sino, alpha, cp, k_single, seg);
+    fp_kernel<MODE, NC, UNIT><<<grid, 256, lds, st>>>(p.t, img, sino, alpha, cp, k_single, seg);
     return hipGetLastError();
 }
 
@@ -412,9 +441,11 @@ hipError_t launch_fp(const pyhst_plan &p, dim3 grid, const float *img, float *si
                      int k_single, hipStream_t st)
 {
     switch (fp_nc(p)) {
-    case 3: return launch_fp_nc<MODE, 3>(p, grid, img, sino, alpha, cp, k_single, st);
-    case 6: return launch_fp_nc<MODE, 6>(p, grid, img, sino, alpha, cp, k_single, st);
-    default: return launch_fp_nc<MODE, 0>(p, grid, img, sino, alpha, cp, k_single, st);
+    case 3:
+        if (fp_unit(p)) return launch_fp_nc<MODE, 3, true>(p, grid, img, sino, alpha, cp, k_single, st);
+        return launch_fp_nc<MODE, 3, false>(p, grid, img, sino, alpha, cp, k_single, st);
+    case 6: return launch_fp_nc<MODE, 6, false>(p, grid, img, sino, alpha, cp, k_single, st);
+    default: return launch_fp_nc<MODE, 0, false>(p, grid, img, sino, alpha, cp, k_single, st);
     }
 }
 

@@ -75,6 +75,107 @@ __global__ __launch_bounds__(256) void prox_step_kernel(int ny, int nx, const fl
     }
 }
 
+// Two fused inner steps (p -> p' -> q) on a 64 x 16 tile.  q on the tile needs p' on the tile grown
+// by one pixel on every side, which needs p on the tile grown by two; the workgroup stages p and g on
+// that region in LDS, updates p to p' in place where it is needed, and writes only q: the dual field
+// crosses HBM once per two steps.  Same operations in the same order as two single steps.
+constexpr int FTX = 64, FTY = 16;
+constexpr int FRX = FTX + 4, FRY = FTY + 4;   // staged region: x0 - 2 .. x0 + 65, y0 - 2 .. y0 + 17
+
+template <bool ZERO>
+__global__ __launch_bounds__(256) void prox_step2_kernel(int ny, int nx, const float *__restrict__ p1,
+                                                         const float *__restrict__ p2, const float *__restrict__ g,
+                                                         float inv_lambda, float tau, float *__restrict__ q1,
+                                                         float *__restrict__ q2)
+{
+    __shared__ float s1[FRY][FRX], s2[FRY][FRX], sg[FRY][FRX], sv[FRY][FRX];
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * FTX - 2, y0 = blockIdx.y * FTY - 2;   // image coordinates of region (0, 0)
+    const int64_t base = (int64_t)blockIdx.z * ny * nx;
+    auto inside = [&](int x, int y) { return (unsigned)x < (unsigned)nx && (unsigned)y < (unsigned)ny; };
+    for (int i = tid; i < FRX * FRY; i += 256) {
+        const int ry = i / FRX, rx = i - ry * FRX;
+        const int x = x0 + rx, y = y0 + ry;
+        const bool in = inside(x, y);
+        const int64_t o = base + (int64_t)y * nx + x;
+        s1[ry][rx] = (!ZERO && in) ? p1[o] : 0.0f;
+        s2[ry][rx] = (!ZERO && in) ? p2[o] : 0.0f;
+        sg[ry][rx] = in ? g[o] : 0.0f;
+    }
+    __syncthreads();
+    // v = div p - g / lambda at an image point whose region coordinates are (rx, ry)
+    auto v_at = [&](int rx, int ry, int x, int y) {
+        float a, b;
+        if (nx == 1) a = 0.0f;
+        else if (x == 0) a = s1[ry][rx];
+        else if (x == nx - 1) a = -s1[ry][rx - 1];
+        else a = s1[ry][rx] - s1[ry][rx - 1];
+        if (ny == 1) b = 0.0f;
+        else if (y == 0) b = s2[ry][rx];
+        else if (y == ny - 1) b = -s2[ry - 1][rx];
+        else b = s2[ry][rx] - s2[ry - 1][rx];
+        return (a + b) - sg[ry][rx] * inv_lambda;
+    };
+    // Region coordinates: the tile is [2, FRX - 2) x [2, FRY - 2).  q there needs v' on [2, FRX - 1) x
+    // [2, FRY - 1), which needs p' on [1, FRX - 1) x [1, FRY - 1), which needs v on [1, FRX) x [1, FRY),
+    // which needs p and g on the whole region.
+    // first step: v on [1, FRX) x [1, FRY)
+    for (int i = tid; i < (FRX - 1) * (FRY - 1); i += 256) {
+        const int ry = 1 + i / (FRX - 1), rx = 1 + i % (FRX - 1);
+        const int x = x0 + rx, y = y0 + ry;
+        if (inside(x, y)) sv[ry][rx] = v_at(rx, ry, x, y);
+    }
+    __syncthreads();
+    // p' on [1, FRX - 1) x [1, FRY - 1), held in registers until every read of p is done
+    constexpr int NP = (FRX - 2) * (FRY - 2);   // 1188 <= 5 * 256
+    float n1[5], n2[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int i = tid + 256 * k;
+        n1[k] = 0.0f;
+        n2[k] = 0.0f;
+        if (i >= NP) continue;
+        const int ry = 1 + i / (FRX - 2), rx = 1 + i % (FRX - 2);
+        const int x = x0 + rx, y = y0 + ry;
+        if (!inside(x, y)) continue;
+        const float v0 = sv[ry][rx];
+        const float a = x + 1 < nx ? sv[ry][rx + 1] - v0 : 0.0f;
+        const float b = y + 1 < ny ? sv[ry + 1][rx] - v0 : 0.0f;
+        const float m = 1.0f + tau * sqrtf(a * a + b * b);
+        n1[k] = (s1[ry][rx] + tau * a) / m;
+        n2[k] = (s2[ry][rx] + tau * b) / m;
+    }
+    __syncthreads();   // every read of p is done
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int i = tid + 256 * k;
+        if (i >= NP) continue;
+        const int ry = 1 + i / (FRX - 2), rx = 1 + i % (FRX - 2);
+        s1[ry][rx] = n1[k];
+        s2[ry][rx] = n2[k];
+    }
+    __syncthreads();
+    // second step: v' on [2, FRX - 1) x [2, FRY - 1), q on the tile [2, FRX - 2) x [2, FRY - 2)
+    for (int i = tid; i < (FRX - 3) * (FRY - 3); i += 256) {
+        const int ry = 2 + i / (FRX - 3), rx = 2 + i % (FRX - 3);
+        const int x = x0 + rx, y = y0 + ry;
+        if (inside(x, y)) sv[ry][rx] = v_at(rx, ry, x, y);
+    }
+    __syncthreads();
+    for (int i = tid; i < FTX * FTY; i += 256) {
+        const int ry = 2 + i / FTX, rx = 2 + i % FTX;
+        const int x = x0 + rx, y = y0 + ry;
+        if (!inside(x, y)) continue;
+        const float v0 = sv[ry][rx];
+        const float a = x + 1 < nx ? sv[ry][rx + 1] - v0 : 0.0f;
+        const float b = y + 1 < ny ? sv[ry + 1][rx] - v0 : 0.0f;
+        const float m = 1.0f + tau * sqrtf(a * a + b * b);
+        const int64_t o = base + (int64_t)y * nx + x;
+        q1[o] = (s1[ry][rx] + tau * a) / m;
+        q2[o] = (s2[ry][rx] + tau * b) / m;
+    }
+}
+
 // u = g - lambda div p
 __global__ __launch_bounds__(256) void prox_final_kernel(int ny, int nx, const float *__restrict__ p1,
                                                          const float *__restrict__ p2, const float *g, float lambda,
@@ -312,9 +413,18 @@ hipError_t launch_tv_prox(int S, int ny, int nx, const float *in, float *out, fl
     }
     float *p1 = work, *p2 = work + n, *q1 = work + 2 * n, *q2 = work + 3 * n;
     const dim3 gi = grid_img(S, ny, nx);
-    for (int it = 0; it < n_inner; ++it) {
-        if (it == 0) prox_step_kernel<true><<<gi, 256, 0, st>>>(ny, nx, p1, p2, in, 1.0f / lambda, 0.125f, q1, q2);
-        else prox_step_kernel<false><<<gi, 256, 0, st>>>(ny, nx, p1, p2, in, 1.0f / lambda, 0.125f, q1, q2);
+    const dim3 g2((unsigned)((nx + FTX - 1) / FTX), (unsigned)((ny + FTY - 1) / FTY), (unsigned)S);
+    const float il = 1.0f / lambda;
+    for (int it = 0; it < n_inner;) {
+        if (n_inner - it >= 2) {   // two steps per launch
+            if (it == 0) prox_step2_kernel<true><<<g2, 256, 0, st>>>(ny, nx, p1, p2, in, il, 0.125f, q1, q2);
+            else prox_step2_kernel<false><<<g2, 256, 0, st>>>(ny, nx, p1, p2, in, il, 0.125f, q1, q2);
+            it += 2;
+        } else {
+            if (it == 0) prox_step_kernel<true><<<gi, 256, 0, st>>>(ny, nx, p1, p2, in, il, 0.125f, q1, q2);
+            else prox_step_kernel<false><<<gi, 256, 0, st>>>(ny, nx, p1, p2, in, il, 0.125f, q1, q2);
+            it += 1;
+        }
         std::swap(p1, q1);
         std::swap(p2, q2);
     }

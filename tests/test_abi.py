@@ -58,6 +58,8 @@ def test_invalid_geometry_rejected_on_host():
     assert _plan_rc(ph.Geometry(8, 8, 40, ang2, 20.0, scan=ph.SCAN_360_HALF)) == _lib.EGEOM
     assert _plan_rc(ph.Geometry(8, 8, 40, ang2, 35.0, scan=ph.SCAN_360_HALF, ha_overlap=6.0)) == _lib.EARG
     assert _plan_rc(ph.Geometry(8, 8, 8, ang, 3.5), n_slices=0) == _lib.EARG
+    assert _plan_rc(ph.Geometry(46341, 46341, 8, ang, 3.5)) == _lib.EARG           # 2^31 pixels per slice
+    assert b"2^31" in ph.lib().pyhst_last_error()
     assert _plan_rc(ph.Geometry(8, 8, 8, ang, 3.5), n_slices=65536) == _lib.EARG    # one grid dimension
     assert b"65535" in ph.lib().pyhst_last_error()
     assert b"cover" in ph.lib().pyhst_last_error() or b"slices" in ph.lib().pyhst_last_error()
