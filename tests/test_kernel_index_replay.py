@@ -1,0 +1,165 @@
+"""CPU replays of the index arithmetic of two GPU kernels (host logic, no GPU).
+
+* fp_staged_kernel (one projection x 64 bins per workgroup, 16-line blocks staged in LDS): every
+  candidate a lane reads lies inside the staged segment of its line, [0, SEG) with SEG = 128 for three
+  candidates per line and 224 for six, over random geometries at the edges of both pixel-size classes.
+  The replay follows the kernel's FP64 block anchor and FP32 per-line offsets.
+* prox_step2_kernel (two fused ROF dual steps on a 64 x 16 tile with a two-pixel halo): its loops,
+  replayed with NaN-initialised LDS so that a read of an unset entry fails, equal two plain single steps
+  exactly, on ragged and degenerate image shapes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+F32 = np.float32
+RB = 16
+
+
+def staged_columns(nx, ny, nb, angles, axis, shifts, s):
+    """(lowest, highest) LDS column read by fp_staged_kernel, and the segment length, or None."""
+    need = math.ceil(2 * math.sqrt(2) / s - 1e-9)
+    nc = 3 if need <= 3 else (6 if need <= 6 else 0)
+    if nc == 0:
+        return None
+    seg_len = 128 if nc == 3 else 224
+    lo, hi = 10 ** 9, -10 ** 9
+    cx, cy = 0.5 * (nx - 1), 0.5 * (ny - 1)
+    r = np.arange(RB, dtype=F32)[:, None]
+    for k, th in enumerate(angles):
+        c, sn = math.cos(th), math.sin(th)
+        t0 = axis + shifts[k]
+        rows = abs(c) >= abs(sn)
+        a = s * c if rows else s * sn
+        bb = s * sn if rows else s * c
+        ci, cl = (cx, cy) if rows else (cy, cx)
+        n_lines = ny if rows else nx
+        rho, slope = 1.0 / abs(a), -bb / a
+        u_c = -t0 + a * ci + bb * cl
+        af, rhof, slopef = F32(a), F32(rho), F32(slope)
+        for j0 in range(0, nb, 64):
+            u_first = (np.arange(j0, j0 + 64, dtype=np.float64) + u_c) / a
+            blk_lo = min((j0 + u_c) / a, (j0 + 63 + u_c) / a) + min(0.0, (RB - 1) * slope) - rho
+            for b in range((n_lines + RB - 1) // RB):
+                l0 = b * RB
+                seg0 = math.floor(l0 * slope + blk_lo) - 2
+                ub = l0 * slope + u_first
+                ubase = np.floor(ub)
+                rem = (ub - ubase).astype(F32)
+                nl = min(RB, n_lines - l0)
+                u = (r[:nl] * slopef + rem[None]).astype(F32)
+                i0 = np.floor((u - rhof).astype(F32)).astype(np.int64) + 1
+                col = (ubase.astype(np.int64) - seg0)[None] + i0
+                lo, hi = min(lo, int(col.min())), max(hi, int(col.max()) + nc - 1)
+    return lo, hi, seg_len
+
+
+def test_fp_staging_bounds():
+    rng = np.random.default_rng(0)
+    cases = [(256, 256, 256, np.arange(180) * math.pi / 180, 127.5, np.zeros(180), 1.0),
+             (77, 53, 101, np.arange(61) * math.pi / 61 + rng.uniform(-.3, .3, 61) * math.pi / 61, 49.3,
+              rng.normal(0, .5, 61), 1.0),
+             (70, 70, 64, np.arange(50) * math.pi / 50, 30.8, np.zeros(50), 0.7),
+             (40, 50, 100, np.arange(33) * math.pi / 33, 50.0, np.zeros(33), 1.6),
+             (5, 3, 7, np.arange(4) * math.pi / 4, 3.0, np.zeros(4), 1.0)]
+    # edges of the two classes: 3 candidates for s >= 2 sqrt 2 / 3, 6 for s >= 2 sqrt 2 / 6
+    for s in (0.9429, 0.95, 1.0, 0.4715, 0.5, 0.94):
+        cases.append((130, 110, 300, rng.uniform(0, 2 * math.pi, 120), 150.3, rng.normal(0, 3, 120), s))
+    for cs in cases:
+        lo, hi, seg_len = staged_columns(*cs)
+        assert 0 <= lo and hi < seg_len, (cs[:3], cs[6], lo, hi, seg_len)
+
+
+# ------------------------------------------------------------------ fused ROF dual steps
+FTX, FTY = 64, 16
+FRX, FRY = FTX + 4, FTY + 4
+
+
+def _div(p1, p2):
+    ny, nx = p1.shape
+    a, b = np.zeros_like(p1), np.zeros_like(p1)
+    if nx > 1:
+        a[:, 0], a[:, 1:-1], a[:, -1] = p1[:, 0], p1[:, 1:-1] - p1[:, :-2], -p1[:, -2]
+    if ny > 1:
+        b[0], b[1:-1], b[-1] = p2[0], p2[1:-1] - p2[:-2], -p2[-2]
+    return a + b
+
+
+def _step(p1, p2, g, il, tau):
+    v = _div(p1, p2) - g * il
+    a, b = np.zeros_like(v), np.zeros_like(v)
+    a[:, :-1], b[:-1] = v[:, 1:] - v[:, :-1], v[1:] - v[:-1]
+    m = 1 + tau * np.sqrt(a * a + b * b)
+    return (p1 + tau * a) / m, (p2 + tau * b) / m
+
+
+def _fused(p1, p2, g, il, tau, zero):
+    ny, nx = g.shape
+    q1, q2 = np.full_like(g, np.nan), np.full_like(g, np.nan)
+
+    def inside(x, y):
+        return 0 <= x < nx and 0 <= y < ny
+    for by in range((ny + FTY - 1) // FTY):
+        for bx in range((nx + FTX - 1) // FTX):
+            x0, y0 = bx * FTX - 2, by * FTY - 2
+            s1 = np.full((FRY, FRX), np.nan)
+            s2, sg, sv = s1.copy(), s1.copy(), s1.copy()
+            for i in range(FRX * FRY):
+                ry, rx = divmod(i, FRX)
+                x, y = x0 + rx, y0 + ry
+                inn = inside(x, y)
+                s1[ry, rx] = p1[y, x] if (not zero and inn) else 0.0
+                s2[ry, rx] = p2[y, x] if (not zero and inn) else 0.0
+                sg[ry, rx] = g[y, x] if inn else 0.0
+
+            def v_at(rx, ry, x, y):
+                a = 0.0 if nx == 1 else (s1[ry, rx] if x == 0 else (-s1[ry, rx - 1] if x == nx - 1
+                                                                      else s1[ry, rx] - s1[ry, rx - 1]))
+                b = 0.0 if ny == 1 else (s2[ry, rx] if y == 0 else (-s2[ry - 1, rx] if y == ny - 1
+                                                                      else s2[ry, rx] - s2[ry - 1, rx]))
+                out = (a + b) - sg[ry, rx] * il
+                assert np.isfinite(out)
+                return out
+
+            def q_at(rx, ry, x, y):
+                v0 = sv[ry, rx]
+                a = sv[ry, rx + 1] - v0 if x + 1 < nx else 0.0
+                b = sv[ry + 1, rx] - v0 if y + 1 < ny else 0.0
+                assert np.isfinite(v0) and np.isfinite(a) and np.isfinite(b)
+                m = 1 + tau * np.sqrt(a * a + b * b)
+                return (s1[ry, rx] + tau * a) / m, (s2[ry, rx] + tau * b) / m
+            for i in range((FRX - 1) * (FRY - 1)):          # v on [1, FRX) x [1, FRY)
+                ry, rx = 1 + i // (FRX - 1), 1 + i % (FRX - 1)
+                if inside(x0 + rx, y0 + ry):
+                    sv[ry, rx] = v_at(rx, ry, x0 + rx, y0 + ry)
+            new = {}
+            assert (FRX - 2) * (FRY - 2) <= 5 * 256             # five register slots per thread
+            for i in range((FRX - 2) * (FRY - 2)):          # p' on [1, FRX - 1) x [1, FRY - 1)
+                ry, rx = 1 + i // (FRX - 2), 1 + i % (FRX - 2)
+                new[(ry, rx)] = q_at(rx, ry, x0 + rx, y0 + ry) if inside(x0 + rx, y0 + ry) else (0.0, 0.0)
+            for (ry, rx), (n1, n2) in new.items():
+                s1[ry, rx], s2[ry, rx] = n1, n2
+            for i in range((FRX - 3) * (FRY - 3)):          # v' on [2, FRX - 1) x [2, FRY - 1)
+                ry, rx = 2 + i // (FRX - 3), 2 + i % (FRX - 3)
+                if inside(x0 + rx, y0 + ry):
+                    sv[ry, rx] = v_at(rx, ry, x0 + rx, y0 + ry)
+            for i in range(FTX * FTY):                      # q on the tile
+                ry, rx = 2 + i // FTX, 2 + i % FTX
+                x, y = x0 + rx, y0 + ry
+                if inside(x, y):
+                    q1[y, x], q2[y, x] = q_at(rx, ry, x, y)
+    return q1, q2
+
+
+@pytest.mark.parametrize("ny,nx", [(37, 70), (16, 64), (1, 50), (33, 1), (2, 2), (17, 65)])
+def test_prox2_emulation(ny, nx):
+    rng = np.random.default_rng(ny * 1000 + nx)
+    g = rng.standard_normal((ny, nx))
+    p1, p2 = 0.3 * rng.standard_normal((ny, nx)), 0.3 * rng.standard_normal((ny, nx))
+    il, tau = 1 / 0.3, 0.125
+    for zero in (True, False):
+        a1, a2 = (np.zeros_like(g), np.zeros_like(g)) if zero else (p1, p2)
+        r1, r2 = _step(*_step(a1, a2, g, il, tau), g, il, tau)
+        k1, k2 = _fused(p1, p2, g, il, tau, zero)
+        assert np.array_equal(k1, r1) and np.array_equal(k2, r2)
