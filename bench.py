@@ -13,6 +13,7 @@ on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -121,7 +122,8 @@ def ctypes_stream(s):
 def run_uneven(args):
     """Uneven batch: 500 slices of 512^2 / 1024^2 / 2048^2, 90..3600 projections, half of them
     360 degree half-acquisition scans, per-projection axis shifts; one plan, autotuned
-    backprojector, the whole FBP of the batch replayed as one HIP graph."""
+    backprojector, the whole FBP of the batch replayed as one HIP graph, then the U-Net corrector
+    on the sparse-angle 512^2 slices (at most 180 projections) inside the same timed step."""
     import numpy as np
     import torch
     import synth
@@ -152,9 +154,28 @@ def run_uneven(args):
     best_ms = plan.autotune(filt, img, reps=2, stream=stream)
     tile, pers = plan.get_tiles()
     work = torch.empty(ph.work_bytes(plan, sino=sino, method=ph.FBP), device=dev, dtype=torch.uint8)
+    # the sparse-angle 512^2 slices (K <= 180) also go through the U-Net corrector, read in place from the
+    # packed FBP output (random-init weights of the corrector's architecture: throughput only)
+    from paper_1306_1392_amd.cnn import UNet, init_params
+    sub = [i for i, s in enumerate(d["specs"]) if s["N"] == 512 and s["K"] <= 180]
+    net = cnn_out = None
+    if sub:
+        net = UNet(1, 512, 512)
+        net.set_params(init_params(32, 4, seed=0))
+        cnn_out = torch.empty(len(sub), 512, 512, device=dev)
+        sub_ptrs = [ctypes.c_void_p(img.data_ptr() + 4 * plan.slice_info(i).img_offset) for i in sub]
+    sptr = ctypes.c_void_p(stream.cuda_stream)
+
+    def corrector():
+        for k, ptr in enumerate(sub_ptrs):
+            rc = net.L.pyhst_unet_forward(net.handle, ptr, 1, ctypes.c_void_p(cnn_out[k].data_ptr()), sptr)
+            if rc != 0:
+                raise RuntimeError(f"pyhst_unet_forward failed: {rc}")
 
     def step():
         ph.reconstruct_slices(plan, sino=sino, method=ph.FBP, out=img, work=work, use_graph=True, stream=stream)
+        if sub:
+            corrector()
 
     for _ in range(args.warmup):
         step()
@@ -165,6 +186,7 @@ def run_uneven(args):
     e[1].record(stream)
     stream.synchronize()
     ms = e[0].elapsed_time(e[1]) / args.steps
+    cnn_ms = _timed(stream, corrector, 3) if sub else 0.0
     classes = {}
     for s in d["specs"]:
         key = f"{s['N']}{'_half' if s['scan'] == 2 else ''}"
@@ -175,11 +197,14 @@ def run_uneven(args):
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{n} slices, N in {{512,1024,2048}}, K in 90..3600, half of them 360-degree "
-                                  f"half acquisition, axis shifts N(0,0.5^2); one plan, one HIP graph per step",
+                                  f"half acquisition, axis shifts N(0,0.5^2); one plan, one HIP graph per step; "
+                                  f"U-Net on the 512^2 slices with K <= 180",
                       "updates": U, "classes": classes},
            "slices_per_s": round(n / (ms * 1e-3), 2),
            "autotune": {"tile": tile, "persistent": pers, "bp_ms_tuned": round(best_ms, 3),
-                        "bp_ms_default": round(t_default, 3)}}
+                        "bp_ms_default": round(t_default, 3)},
+           "corrector": {"slices": len(sub), "ms_per_step": round(cnn_ms, 3),
+                         "rule": "512^2 slices with at most 180 projections: FBP + U-Net"}}
     print(json.dumps(res), flush=True)
 
 
