@@ -42,6 +42,8 @@ CASES = {
     "pix_0p7": dict(nx=70, ny=70, nb=64, K=50, axis=30.8, s=0.7),
     "pix_1p6": dict(nx=40, ny=50, nb=100, K=33, axis=50.0, s=1.6),
     "pix_0p4": dict(nx=60, ny=48, nb=50, K=37, axis=24.6, s=0.4, shifts=0.3),   # > 6 candidates per line
+    # wider than the 224-position staged segment of six candidates: interior blocks take 16-byte reads
+    "pix_0p7_wide": dict(nx=288, ny=264, nb=210, K=40, axis=104.5, s=0.7, shifts=0.3),
     "tiny": dict(nx=5, ny=3, nb=7, K=4, axis=3.0),
     "scan360": dict(nx=64, ny=64, nb=72, K=100, axis=36.4, scan=ph.SCAN_360),
 }
