@@ -10,12 +10,18 @@
 // t - j = a (i - u), a = s cos (or s sin), so the bin touches the positions
 // i in (u - 1/|a|, u + 1/|a|): at most ceil(2/|a|) of them.
 //
-// gfx950 layout, the transpose of the backprojector's: workgroup = one angle
-// block (up to 32 projections of similar direction, grouped by the plan so
+// Three kernels compute the same sums (up to FP32 rounding order):
+//   fp_kernel         angle blocks, for plans with enough of them to fill the chip;
+//   fp_staged_kernel  one projection per workgroup staged in LDS, for smaller plans;
+//   fp_lines_kernel   one projection per workgroup read from global memory, for pixels
+//                     below half a bin (no fixed candidate count) on smaller plans.
+//
+// gfx950 layout of fp_kernel, the transpose of the backprojector's: workgroup = one
+// angle block (up to 32 projections of similar direction, grouped by the plan so
 // that their candidate positions share one segment) x 64 bins x one slice.
 // The workgroup walks the image lines in blocks of 16; for each block it
-// stages the shared segment of every line (FP_SEG positions, zero outside the
-// image) in LDS once, and every wavefront then serves its projections (m = w,
+// stages the shared segment of every line (fp_seg_len positions, zero outside
+// the image) in LDS once, and every wavefront then serves its projections (m = w,
 // w + 4, ...; lane = bin, one accumulator per projection) from LDS: a staged
 // value is read up to ~2 x 32 times.  Coordinates: per (lane, projection, line
 // block) the crossing u of the block's first line is computed in FP64 and split
@@ -184,11 +190,11 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
     }
 }
 
-// Small problems (few workgroups of angle blocks): one projection per workgroup, its 4 wavefronts
-// take every fourth image line and add their partial sums in a fixed order through LDS.  The
-// crossing position is anchored in FP64 every 8 lines of a wavefront (FP32 offsets below 30
+// Smaller plans with pixels below half a bin (or when forced): one projection per workgroup, its 4
+// wavefronts take every fourth image line and add their partial sums in a fixed order through LDS.
+// The crossing position is anchored in FP64 every 8 lines of a wavefront (FP32 offsets below 30
 // positions in between); the candidates are read from global memory (L2).
-template <int MODE, int NC, bool UNIT>
+template <int MODE, int NC>
 __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__restrict__ img,
                                                        float *__restrict__ out, float alpha, CpDual cp, int k0)
 {
@@ -263,7 +269,7 @@ __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__
 // Small problems, pixel size >= 0.5 (NC > 0): one projection per workgroup, staged through LDS.
 // The workgroup walks the image lines in blocks of FP_RB; the 64 bins of one projection touch, over
 // a block, a segment of at most 63/|a| + (FP_RB - 1)|slope| + 1/|a| + NC + 3 positions of every line
-// (< FPS_SEG), which 256 threads stage with 16-wide contiguous reads along the image rows in both
+// (< FpStaged<NC>::SEG), which 256 threads stage with 16-wide contiguous reads along the image rows in both
 // walking directions (so a column-walking projection reads rows of 16 neighbouring columns rather
 // than 64 separate rows).  The next block is loaded into registers while the current one is summed
 // from the other LDS buffer: one barrier per block.  Wavefront w sums lines w, w + 4, ... of every
@@ -421,7 +427,7 @@ hipError_t launch_fp_nc(const pyhst_plan &p, dim3 grid, const float *img, float 
         return hipGetLastError();
     }
     if (kind == PYHST_FP_LINES) {
-        fp_lines_kernel<MODE, NC, false><<<g2, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
+        fp_lines_kernel<MODE, NC><<<g2, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
         return hipGetLastError();
     }
     const int seg = p.fp_seg;

@@ -1,8 +1,9 @@
 // Total-variation operators (eq. (2), discretised as in Chambolle (2004):
 // forward differences with a zero last difference, div = -grad^T), the ROF
 // proximal map, the Chambolle-Pock dual TV step, the energy of eq. (3) and the
-// power iteration for |[A; grad]|.  Memory-bound stencils: one pass over the
-// image per step, neighbours come from L1/L2.  Reductions are deterministic:
+// power iteration for |[A; grad]|.  Memory-bound stencils on 2-D tiles: the
+// ROF prox takes two dual steps per launch through LDS, the other stencils
+// read their neighbours from L1/L2.  Reductions are deterministic:
 // per-workgroup FP64 partials, then one workgroup sums them in a fixed order.
 #include "internal.hpp"
 
