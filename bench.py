@@ -227,23 +227,48 @@ def run_single(args):
     stream.wait_stream(torch.cuda.current_stream())
     e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
 
-    def timed(plan, sino, reps):
+    def timed(plan, sino, reps, graph=True):
         out = torch.empty(plan.img_shape(), device=dev)
         work = torch.empty(ph.work_bytes(plan, sino=sino, method=ph.FBP), device=dev, dtype=torch.uint8)
         for _ in range(3):
-            ph.reconstruct_slices(plan, sino=sino, method=ph.FBP, out=out, work=work, use_graph=True, stream=stream)
+            ph.reconstruct_slices(plan, sino=sino, method=ph.FBP, out=out, work=work, use_graph=graph, stream=stream)
         stream.synchronize()
         t0 = time.perf_counter()
         e[0].record(stream)
         for _ in range(reps):
-            ph.reconstruct_slices(plan, sino=sino, method=ph.FBP, out=out, work=work, use_graph=True, stream=stream)
+            ph.reconstruct_slices(plan, sino=sino, method=ph.FBP, out=out, work=work, use_graph=graph, stream=stream)
         e[1].record(stream)
         stream.synchronize()
         wall = (time.perf_counter() - t0) * 1e3 / reps
         return e[0].elapsed_time(e[1]) / reps, wall, out
 
+    def timed_c(plan, sino, reps):
+        # the same call made straight through the C ABI with a prepared argument block (no Python wrapper)
+        from paper_1306_1392_amd import _lib
+        L = _lib.lib()
+        out = torch.empty(plan.img_shape(), device=dev)
+        work = torch.empty(ph.work_bytes(plan, sino=sino, method=ph.FBP), device=dev, dtype=torch.uint8)
+        a = _lib.ReconArgs()
+        a.sino = ctypes.c_void_p(sino.data_ptr())
+        a.method, a.use_graph, a.eps, a.n_inner = ph.FBP, 1, 1e-6, 20
+        a.out = ctypes.c_void_p(out.data_ptr())
+        a.work = ctypes.c_void_p(work.data_ptr())
+        a.work_bytes = work.numel()
+        sp, pa = ctypes.c_void_p(stream.cuda_stream), ctypes.byref(a)
+        for _ in range(3):
+            assert L.reconstruct_slices(plan.handle, pa, sp) == 0
+        stream.synchronize()
+        e[0].record(stream)
+        for _ in range(reps):
+            L.reconstruct_slices(plan.handle, pa, sp)
+        e[1].record(stream)
+        stream.synchronize()
+        return e[0].elapsed_time(e[1]) / reps
+
     p1 = ph.Plan(g)
     lat_ms, lat_wall, out1 = timed(p1, sino1, 200)
+    lat_nograph_ms = timed(p1, sino1, 200, graph=False)[0]
+    lat_c_ms = timed_c(p1, sino1, 200)
     pB = ph.Plan(g, n_slices=R)
     pB.autotune(ph.fbp_filter(pB, sinoB), torch.empty(pB.img_shape(), device=dev), reps=2, stream=stream)
     bat_ms, _, outB = timed(pB, sinoB, max(args.steps, 5))
@@ -256,6 +281,8 @@ def run_single(args):
            "config": {"workload": "256x256, 256 bins, 180 angles over 180 deg, 10-ellipse phantoms, 1 % noise; "
                                   "batch of 1024 slices, one HIP graph per call"},
            "latency_ms_one_slice": round(lat_ms, 4), "latency_wall_ms_one_slice": round(lat_wall, 4),
+           "latency_ms_one_slice_direct_launches": round(lat_nograph_ms, 4),
+           "latency_ms_one_slice_c_call": round(lat_c_ms, 4),
            "batch_ms": round(bat_ms, 3), "gups_batch": round(R * U / (bat_ms * 1e-3) / 1e9, 1),
            "bp_tile": pB.get_tiles()[0], "parity_rel_l2_vs_oracle": par, "rmse_vs_phantom": rmse}
     if not args.no_cpu_baseline:
@@ -366,7 +393,7 @@ def run_fp(args):
                 ph.backproject(plan, sino, 0, out=img, alpha=1e-6, beta=0.0, stream=stream)
             cases[name]["fp_then_bp_ms"] = round(_timed(stream, pair, reps), 3)
             by_tile = {}
-            for t in range(5):
+            for t in range(6):
                 for pers in (False, True):
                     plan.set_tiles(t, pers)
                     by_tile[f"{t}{'p' if pers else ''}"] = round(_timed(stream, lambda: ph.backproject(

@@ -62,6 +62,10 @@ enum { PYHST_SCAN_180 = 0, PYHST_SCAN_360 = 1, PYHST_SCAN_360_HALF = 2 };
 enum { PYHST_FBP = 0, PYHST_TV_CP = 1, PYHST_ISTA = 2, PYHST_FISTA = 3 };
 /* Largest slice count of a plan or of one tv_prox call (one grid dimension). */
 enum { PYHST_MAX_SLICES = 65535 };
+/* A plan keeps at most this many executable HIP graphs (one per distinct
+ * reconstruct_slices call with use_graph: method, buffers, stream, parameters);
+ * once it holds them, further distinct calls run as plain launches. */
+enum { PYHST_MAX_GRAPHS = 64 };
 /* Forward-projector kernels (pyhst_plan_set_fp_kernel). */
 enum { PYHST_FP_AUTO = 0, PYHST_FP_BLOCKS = 1, PYHST_FP_STAGED = 2, PYHST_FP_LINES = 3 };
 
@@ -109,7 +113,9 @@ int pyhst_plan_destroy(pyhst_plan *plan);
 int pyhst_plan_slice_info(const pyhst_plan *plan, int32_t slice, pyhst_slice_info *out);
 /* Total elements of the packed sinogram, filtered and image buffers. */
 int pyhst_plan_sizes(const pyhst_plan *plan, int64_t *sino_elems, int64_t *filt_elems, int64_t *img_elems);
-/* Backprojector tile: 0 = 64x64, 1 = 64x32, 2 = 32x64, 3 = 32x32, 4 = 64x128 pixels; -1 = automatic.
+/* Backprojector tile: 0 = 64x64, 1 = 64x32, 2 = 32x64, 3 = 32x32, 4 = 64x128 pixels, 5 = 32x32 with
+ * the projections split over 4 angle groups (1024-thread workgroups, partial sums added in a fixed
+ * order; for slices too small to fill the chip with tiles); -1 = automatic.
  * persistent != 0 runs the backprojector as one persistent launch over a
  * cost-sorted (slice, tile) work list. */
 int pyhst_plan_set_tiles(pyhst_plan *plan, int32_t bp_tile, int32_t persistent);

@@ -15,12 +15,16 @@
 
 namespace pyhst {
 
-// Backprojector tile configurations.  A workgroup is 4 wavefronts; each lane
-// owns one pixel of every 8x8 block its wave covers; a wave covers BX x BY
-// blocks, the 4 waves are stacked in y.  Tile = (8 BX) x (32 BY) pixels.
-constexpr int N_TILE_CFG = 5;
-constexpr int TILE_BX[N_TILE_CFG] = {8, 8, 4, 4, 8};
-constexpr int TILE_BY[N_TILE_CFG] = {2, 1, 2, 1, 4};
+// Backprojector tile configurations.  A workgroup is 4 wavefronts per angle
+// group; each lane owns one pixel of every 8x8 block its wave covers; a wave
+// covers BX x BY blocks, the 4 waves are stacked in y.  Tile = (8 BX) x (32 BY)
+// pixels.  With AG > 1 angle groups (workgroup = 256 AG threads) each group sums
+// its share of the projections and the shares are added in a fixed order: for
+// slices too small to fill the chip with tiles alone.
+constexpr int N_TILE_CFG = 6;
+constexpr int TILE_BX[N_TILE_CFG] = {8, 8, 4, 4, 8, 4};
+constexpr int TILE_BY[N_TILE_CFG] = {2, 1, 2, 1, 4, 1};
+constexpr int TILE_AG[N_TILE_CFG] = {1, 1, 1, 1, 1, 4};
 inline constexpr int tile_w(int c) { return 8 * TILE_BX[c]; }
 inline constexpr int tile_h(int c) { return 32 * TILE_BY[c]; }
 

@@ -26,20 +26,24 @@ constexpr int AB = 32;   // projections staged per LDS block
 typedef __attribute__((address_space(4))) const float cfloat;
 
 template <int CFG, int MODE>
-__global__ __launch_bounds__(256) void bp_kernel(Tables T, const float *__restrict__ sino, int filtered,
-                                                 float *__restrict__ img, float alpha, float beta,
-                                                 int64_t n_items, int persistent, int xcd_remap, CpPrimal cp)
+__global__ __launch_bounds__(256 * TILE_AG[CFG]) void bp_kernel(Tables T, const float *__restrict__ sino,
+                                                                int filtered, float *__restrict__ img, float alpha,
+                                                                float beta, int64_t n_items, int persistent,
+                                                                int xcd_remap, CpPrimal cp)
 {
     constexpr int BX = TILE_BX[CFG], BY = TILE_BY[CFG];
     constexpr int TW = 8 * BX, TH = 32 * BY;
     constexpr int PX = BX * BY;
-    extern __shared__ float2 win[];   // [AB][W]
-    __shared__ int s_jb[AB];
-    __shared__ float s_r[AB];
+    constexpr int AG = TILE_AG[CFG];        // angle groups; a staged block holds AG x AB projections
+    constexpr int NT = 256 * AG;            // threads per workgroup
+    extern __shared__ float2 win[];   // [AG AB][W]
+    __shared__ int s_jb[AG * AB];
+    __shared__ float s_r[AG * AB];
     __shared__ int64_t s_item;
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wv = tid >> 6;
+    const int lane = tid & 63, wv = (tid >> 6) & 3;
+    const int ag = AG > 1 ? tid >> 8 : 0;   // this thread's angle group
     const int lx = lane & 7, ly = lane >> 3;
     const float flx = (float)lx, fly = (float)(ly + 8 * BY * wv);
 
@@ -86,8 +90,8 @@ __global__ __launch_bounds__(256) void bp_kernel(Tables T, const float *__restri
 #pragma unroll
         for (int p = 0; p < PX; ++p) acc[p] = 0.0f;
 
-        for (int kb = 0; kb < K; kb += AB) {
-            const int na = min(AB, K - kb);
+        for (int kb = 0; kb < K; kb += AG * AB) {
+            const int na = min(AG * AB, K - kb);
             if (tid < na) {
                 const int k = kb + tid;
                 const double c = cosd[k], sn = sind[k];
@@ -99,7 +103,7 @@ __global__ __launch_bounds__(256) void bp_kernel(Tables T, const float *__restri
             }
             __syncthreads();
             const int tot = na * W;
-            for (int e = tid; e < tot; e += 256) {
+            for (int e = tid; e < tot; e += NT) {
                 const int a = (int)(((float)e + 0.5f) * invW);
                 const int j = s_jb[a] + (e - a * W);
                 const float *row = rows + (int64_t)(kb + a) * L;
@@ -108,7 +112,9 @@ __global__ __launch_bounds__(256) void bp_kernel(Tables T, const float *__restri
                 win[e] = make_float2(q0, q1 - q0);
             }
             __syncthreads();
-            for (int a = 0; a < na; ++a) {
+            // angle group ag sums projections [ag AB, ag AB + AB) of the staged block
+            const int a_end = AG > 1 ? min(na, (ag + 1) * AB) : na;
+            for (int a = ag * AB; a < a_end; ++a) {
                 const cfloat *tk = tab + (int64_t)(kb + a) * BPT;
                 const float t0 = fmaf(fly, tk[1], fmaf(flx, tk[0], s_r[a]));
                 const float2 *wa = win + a * W;
@@ -127,6 +133,25 @@ __global__ __launch_bounds__(256) void bp_kernel(Tables T, const float *__restri
                 }
             }
             __syncthreads();
+        }
+
+        if constexpr (AG > 1) {
+            // add the groups' partial sums in a fixed order (group 0 + 1 + 2 + 3), through the window
+            // buffer, which the last barrier of the projection loop has freed
+            float *red = (float *)win;   // [AG - 1][PX][256]
+            if (ag > 0) {
+#pragma unroll
+                for (int q = 0; q < PX; ++q) red[((ag - 1) * PX + q) * 256 + (tid & 255)] = acc[q];
+            }
+            __syncthreads();
+            if (ag == 0) {
+#pragma unroll
+                for (int h = 0; h < AG - 1; ++h)
+#pragma unroll
+                    for (int q = 0; q < PX; ++q) acc[q] += red[(h * PX + q) * 256 + tid];
+            }
+            __syncthreads();   // the buffer is staged again by the next work item
+            if (ag > 0) continue;
         }
 
         // epilogue
@@ -172,7 +197,9 @@ hipError_t launch_cfg(const pyhst_plan &p, const float *sino, int filtered, floa
 {
     int wmax = 0;
     for (const auto &g : p.gd) wmax = std::max(wmax, g.bp_w[CFG]);
-    const size_t lds = (size_t)AB * wmax * sizeof(float2);
+    constexpr int AG = TILE_AG[CFG];
+    size_t lds = (size_t)AG * AB * wmax * sizeof(float2);
+    if (AG > 1) lds = std::max(lds, (size_t)(AG - 1) * TILE_BX[CFG] * TILE_BY[CFG] * 256 * sizeof(float));
     const int64_t n = p.n_items[CFG];
     if (n == 0) return hipSuccess;
     if (lds > 65536) {
@@ -184,15 +211,16 @@ hipError_t launch_cfg(const pyhst_plan &p, const float *sino, int filtered, floa
     if (p.persistent) {
         zero_counter<<<1, 1, 0, st>>>(p.t.counter);
         int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bp_kernel<CFG, MODE>, 256, lds);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bp_kernel<CFG, MODE>, 256 * AG, lds);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
         int64_t grid = (int64_t)per_cu * p.cu_count;
         if (grid > n) grid = n;
-        bp_kernel<CFG, MODE><<<(unsigned)grid, 256, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n, 1, 0, cp);
+        bp_kernel<CFG, MODE><<<(unsigned)grid, 256 * AG, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n, 1, 0,
+                                                                    cp);
     } else {
-        bp_kernel<CFG, MODE><<<(unsigned)n, 256, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n, 0,
-                                                            p.uniform ? 1 : 0, cp);
+        bp_kernel<CFG, MODE><<<(unsigned)n, 256 * AG, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n, 0,
+                                                                 p.uniform ? 1 : 0, cp);
     }
     return hipGetLastError();
 }
@@ -206,6 +234,7 @@ hipError_t launch_mode(const pyhst_plan &p, int cfg, const float *sino, int filt
     case 1: return launch_cfg<1, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
     case 2: return launch_cfg<2, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
     case 3: return launch_cfg<3, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
+    case 5: return launch_cfg<5, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
     default: return launch_cfg<4, MODE>(p, sino, filtered, img, alpha, beta, cp, st);
     }
 }

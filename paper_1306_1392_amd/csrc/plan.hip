@@ -35,6 +35,9 @@ int choose_tile(const pyhst_plan &p)
     if (p.n_items[4] >= want) return 4;
     if (p.n_items[0] >= want) return 0;
     if (p.n_items[1] >= want) return 1;
+    // too few 32x32 tiles for 2 workgroups per CU (a single 256^2 slice has 64): split the projections
+    // of each tile over 4 angle groups instead
+    if (p.n_items[3] < 2LL * p.cu_count) return 5;
     return 3;
 }
 

@@ -383,8 +383,14 @@ extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hip
                 std::memcpy(&fb, &a->flat_pos[i], 8);
                 key.push_back(fb);
             }
-        std::lock_guard<std::mutex> lk(p.mu);
+        std::unique_lock<std::mutex> lk(p.mu);
         auto it = p.graphs.find(key);
+        if (it == p.graphs.end() && p.graphs.size() >= (size_t)PYHST_MAX_GRAPHS) {
+            // bounded cache: a further distinct call runs as plain launches (cached graphs may still be
+            // in flight on other streams, so none is destroyed here)
+            lk.unlock();
+            return enqueue();
+        }
         if (it == p.graphs.end()) {
             hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: begin capture");

@@ -55,7 +55,8 @@ def gen():
 
 
 @pytest.mark.parametrize("case", list(CASES))
-@pytest.mark.parametrize("tile,persistent", [(-1, False), (0, False), (3, True), (1, False), (2, True)])
+@pytest.mark.parametrize("tile,persistent", [(-1, False), (0, False), (3, True), (1, False), (2, True), (5, False),
+                                             (5, True), (4, False)])
 def test_backproject_parity(dev, gen, case, tile, persistent):
     g, og = pair(**CASES[case])
     plan = ph.Plan(g, n_slices=2)
@@ -193,6 +194,46 @@ def test_fbp_batch_equals_single(dev, gen):
     for i in range(4):
         single = ph.reconstruct_slices(plan1, sino=y[i:i + 1].contiguous(), method=ph.FBP)
         assert torch.equal(batch[i], single[0])
+
+
+def test_uniform_plan_shared_by_two_streams(dev, gen):
+    """A uniform plan may serve two streams at once when each call has its own buffers: FBP and TV-CP
+    interleaved on two streams (graph and direct launches) equal the same calls made one at a time."""
+    g, _ = pair(**CASES["odd_shift"])
+    plan = ph.Plan(g, n_slices=2)
+    y = [torch.from_numpy(gen.standard_normal((2, g.n_angles, g.n_det)).astype(np.float32)).to(dev) for _ in range(2)]
+    kw = [dict(method=ph.FBP), dict(method=ph.TV_CP, lam=0.02, n_iter=15, op_norm=200.0)]   # 200 > |K| here
+    ref = [ph.reconstruct_slices(plan, sino=y[i], **kw[i]) for i in range(2)]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for st in streams:
+        st.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for rep in range(4):
+        for i, st in enumerate(streams):
+            with torch.cuda.stream(st):
+                outs.append((i, ph.reconstruct_slices(plan, sino=y[i], use_graph=(rep + i) % 2 == 0, stream=st,
+                                                      **kw[i])))
+    torch.cuda.synchronize()
+    for i, o in outs:
+        assert torch.equal(o, ref[i]), i
+
+
+def test_graph_cache_bound(dev, gen):
+    """More distinct graph calls than the plan caches (64): the surplus run as plain launches, same result."""
+    g, _ = pair(**CASES["tiny"])
+    plan = ph.Plan(g)
+    y = torch.from_numpy(gen.standard_normal((1, g.n_angles, g.n_det)).astype(np.float32)).to(dev)
+    ref = ph.reconstruct_slices(plan, sino=y, method=ph.FBP)
+    outs = [torch.empty_like(ref) for _ in range(70)]
+    side = torch.cuda.Stream()   # graphs are captured on a created stream (the null stream cannot be)
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(2):
+            for o in outs:
+                ph.reconstruct_slices(plan, sino=y, method=ph.FBP, out=o, use_graph=True, stream=side)
+    torch.cuda.synchronize()
+    assert all(torch.equal(o, ref) for o in outs)
 
 
 def test_uneven_plan_matches_oracle(dev, gen):
