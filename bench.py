@@ -907,8 +907,8 @@ def main():
     if args.summarize:
         return summarize_profiles(args.summarize)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (the slices of a batch are independent; "
-              "DESIGN.md describes how the path shards across GPUs)", file=sys.stderr)
+        print("bench.py: measures one GPU only; the slices of a batch are independent, so N GPUs would "
+              "each reconstruct 1/N of them with no exchange (no multi-GPU run is made here)", file=sys.stderr)
         sys.exit(2)
 
     import torch
