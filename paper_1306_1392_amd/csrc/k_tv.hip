@@ -69,10 +69,10 @@ __global__ __launch_bounds__(256) void prox_step_kernel(int ny, int nx, const fl
         const float v0 = v[r][tx];
         const float a = x + 1 < nx ? v[r][tx + 1] - v0 : 0.0f;
         const float b = y + 1 < ny ? v[r + 1][tx] - v0 : 0.0f;
-        const float m = 1.0f + tau * sqrtf(a * a + b * b);
+        const float im = 1.0f / (1.0f + tau * sqrtf(a * a + b * b));   // one division for both components
         const int64_t o = base + (int64_t)y * nx + x;
-        q1[o] = ((ZERO ? 0.0f : p1[o]) + tau * a) / m;
-        q2[o] = ((ZERO ? 0.0f : p2[o]) + tau * b) / m;
+        q1[o] = ((ZERO ? 0.0f : p1[o]) + tau * a) * im;
+        q2[o] = ((ZERO ? 0.0f : p2[o]) + tau * b) * im;
     }
 }
 
@@ -142,9 +142,9 @@ __global__ __launch_bounds__(256) void prox_step2_kernel(int ny, int nx, const f
         const float v0 = sv[ry][rx];
         const float a = x + 1 < nx ? sv[ry][rx + 1] - v0 : 0.0f;
         const float b = y + 1 < ny ? sv[ry + 1][rx] - v0 : 0.0f;
-        const float m = 1.0f + tau * sqrtf(a * a + b * b);
-        n1[k] = (s1[ry][rx] + tau * a) / m;
-        n2[k] = (s2[ry][rx] + tau * b) / m;
+        const float im = 1.0f / (1.0f + tau * sqrtf(a * a + b * b));
+        n1[k] = (s1[ry][rx] + tau * a) * im;
+        n2[k] = (s2[ry][rx] + tau * b) * im;
     }
     __syncthreads();   // every read of p is done
 #pragma unroll
@@ -170,10 +170,10 @@ __global__ __launch_bounds__(256) void prox_step2_kernel(int ny, int nx, const f
         const float v0 = sv[ry][rx];
         const float a = x + 1 < nx ? sv[ry][rx + 1] - v0 : 0.0f;
         const float b = y + 1 < ny ? sv[ry + 1][rx] - v0 : 0.0f;
-        const float m = 1.0f + tau * sqrtf(a * a + b * b);
+        const float im = 1.0f / (1.0f + tau * sqrtf(a * a + b * b));
         const int64_t o = base + (int64_t)y * nx + x;
-        q1[o] = (s1[ry][rx] + tau * a) / m;
-        q2[o] = (s2[ry][rx] + tau * b) / m;
+        q1[o] = (s1[ry][rx] + tau * a) * im;
+        q2[o] = (s2[ry][rx] + tau * b) * im;
     }
 }
 
@@ -249,8 +249,9 @@ __global__ __launch_bounds__(256) void cp_q_kernel(int ny, int nx, const float *
         float b = q2[o] + sigma * grad_y(xb, o, iy, ny, nx);
         if (lambda > 0.0f) {
             const float d = fmaxf(1.0f, sqrtf(a * a + b * b) / lambda);
-            a /= d;
-            b /= d;
+            const float id = 1.0f / d;
+            a *= id;
+            b *= id;
         } else {
             a = 0.0f;
             b = 0.0f;
