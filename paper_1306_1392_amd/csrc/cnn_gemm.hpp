@@ -35,7 +35,18 @@ __device__ __host__ inline float bf2f(bf16_t b)
     return f;
 }
 
-constexpr int TM = 128, TK = 32, LDK = TK + 8;   // LDS row stride 80 B keeps 16 B alignment
+constexpr int TM = 128, TK = 32;
+
+// LDS tiles are [row][k] with k contiguous and no padding; the 16-byte chunk c of row r is stored at
+// chunk swz(r, c).  With 32 banks and 8 lanes per 16-byte access, the XOR spreads over all banks the
+// MFMA operand reads (8 consecutive rows, one chunk), the row-major staging writes (whole rows) and
+// the transposed staging writes (rows 8 apart, one chunk); unswizzled, the last of these hit the same
+// 4 banks from every lane of a group.
+template <int KV>
+__device__ inline int swz(int r, int c)
+{
+    return c ^ (((r >> 3) ^ (r / (8 / KV))) & (KV - 1));
+}
 
 // floor(n / d) for 0 <= n < 2^31 by multiply and shift: m = ceil(2^(32+l) / d), l = ceil(log2 d)
 // (Granlund & Montgomery); exact in this range because n e / (d 2^(32+l)) < 1/d for e = m d - 2^(32+l) < d.
@@ -324,7 +335,7 @@ __device__ inline void transpose8(const uint4 *in, uint4 *out)
     }
 }
 
-// Register staging of one operand tile, stored in LDS as [row][k] (k contiguous, stride LDK).
+// Register staging of one operand tile, stored in LDS as [row][k] (k contiguous, chunks swizzled).
 //  VK loaders: SLOTS vectors of 8 consecutive k of one row per thread.
 //  Other loaders (vectors run along the rows): each of the first ROWS/8 * TK/8 threads loads an
 //  8-row x 8-k block as 8 vectors (one per k), transposes it in registers and stores 8 vectors.
@@ -333,7 +344,7 @@ struct Stager;
 
 template <class L, int ROWS, int TKv>
 struct Stager<L, ROWS, TKv, true> {
-    static constexpr int KV = TKv / 8, LDKv = TKv + 8;
+    static constexpr int KV = TKv / 8, LDKv = TKv;
     static constexpr int NV = ROWS * KV;
     static constexpr int SLOTS = (NV + 255) / 256;
     typename L::Ctx ctx[SLOTS];
@@ -358,13 +369,13 @@ struct Stager<L, ROWS, TKv, true> {
     {
 #pragma unroll
         for (int j = 0; j < SLOTS; ++j)
-            if (threadIdx.x + 256 * j < NV) *(uint4 *)&s[row[j] * LDKv + kl[j]] = v[j];
+            if (threadIdx.x + 256 * j < NV) *(uint4 *)&s[row[j] * LDKv + 8 * swz<KV>(row[j], kl[j] >> 3)] = v[j];
     }
 };
 
 template <class L, int ROWS, int TKv>
 struct Stager<L, ROWS, TKv, false> {
-    static constexpr int R8 = ROWS / 8, NBLK = R8 * (TKv / 8), LDKv = TKv + 8;
+    static constexpr int R8 = ROWS / 8, KV = TKv / 8, NBLK = R8 * KV, LDKv = TKv;
     static_assert(NBLK <= 256, "one 8x8 block per thread");
     typename L::Ctx ctx;
     uint4 v[8];
@@ -388,7 +399,7 @@ struct Stager<L, ROWS, TKv, false> {
         uint4 o[8];
         transpose8(v, o);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) *(uint4 *)&s[(row + q) * LDKv + kl] = o[q];
+        for (int q = 0; q < 8; ++q) *(uint4 *)&s[(row + q) * LDKv + 8 * swz<KV>(row + q, kl >> 3)] = o[q];
     }
 };
 
@@ -398,7 +409,7 @@ struct Stager<L, ROWS, TKv, false> {
 template <class AL, class BL, class EP, int TN, int TMv = TM, int TKv = TK>
 __global__ __launch_bounds__(256) void gemm_kernel(AL A, BL B, EP E, int M, int N, int K, int k_split)
 {
-    constexpr int LDKv = TKv + 8;
+    constexpr int LDKv = TKv, KV = TKv / 8;
     constexpr int WMW = WaveGrid<TN>::WM, WNW = WaveGrid<TN>::WN;
     constexpr int WTM = TMv / WMW, WTN = TN / WNW;
     constexpr int BM = WTM / 32, BN = WTN / 32;
@@ -440,10 +451,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(AL A, BL B, EP E, int M, int 
             bf16x8 af[BM], bfr[BN];
 #pragma unroll
             for (int i = 0; i < BM; ++i)
-                af[i] = *(const bf16x8 *)&a[(wm * WTM + i * 32 + (lane & 31)) * LDKv + kk + 8 * (lane >> 5)];
+            {
+                const int r = wm * WTM + i * 32 + (lane & 31);
+                af[i] = *(const bf16x8 *)&a[r * LDKv + 8 * swz<KV>(r, (kk >> 3) + (lane >> 5))];
+            }
 #pragma unroll
             for (int j = 0; j < BN; ++j)
-                bfr[j] = *(const bf16x8 *)&bsm[(wn * WTN + j * 32 + (lane & 31)) * LDKv + kk + 8 * (lane >> 5)];
+            {
+                const int r = wn * WTN + j * 32 + (lane & 31);
+                bfr[j] = *(const bf16x8 *)&bsm[r * LDKv + 8 * swz<KV>(r, (kk >> 3) + (lane >> 5))];
+            }
 #pragma unroll
             for (int i = 0; i < BM; ++i)
 #pragma unroll
