@@ -160,9 +160,9 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
             const float *base = stage + ((int)ubase - seg0);
             for (int r = 0; r < nl; ++r) {
                 const float u = fmaf((float)r, slopef[i], rem);       // crossing relative to ubase
-                const int i0 = (int)floorf(u - rhof[i]) + 1;
-                const float *row = base + r * seg_len + i0;
-                float d = af[i] * ((float)i0 - u);               // t - j at the first candidate
+                const float fl = floorf(u - rhof[i]);                 // first candidate = fl + 1
+                const float *row = base + r * seg_len + (int)fl + 1;
+                float d = fmaf(af[i], fl - u, af[i]);                 // t - j at the first candidate
                 if constexpr (NC > 0) {
                     acc[i] = hat_line<NC, UNIT>(row, d, af[i], acc[i]);
                 } else {
@@ -235,8 +235,9 @@ __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__
             const int l = la + 4 * m;
             if (l >= n_lines) break;
             const float u = fmaf((float)(4 * m), slopef, rem);   // crossing relative to ubase
-            const int i0 = (int)floorf(u - rhof) + 1;
-            float d = af * ((float)i0 - u);                         // t - j at the first candidate
+            const float fl = floorf(u - rhof);                      // first candidate = fl + 1
+            const int i0 = (int)fl + 1;
+            float d = fmaf(af, fl - u, af);                         // t - j at the first candidate
             const float *line = im + (int64_t)l * step_line;
             const int nc = NC > 0 ? NC : ncand;
 #pragma unroll
@@ -364,9 +365,9 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
             const int r = wv + 4 * m;
             if (l0 + r >= n_lines) break;                     // uniform
             const float u = fmaf((float)r, slopef, rem);      // crossing relative to ubase
-            const int i0 = (int)floorf(u - rhof) + 1;
-            float d = af * ((float)i0 - u);                    // t - j at the first candidate
-            acc = hat_line<NC, UNIT>(base + r * F::LD + i0, d, af, acc);
+            const float fl = floorf(u - rhof);                 // first candidate = fl + 1
+            const float d = fmaf(af, fl - u, af);              // t - j at the first candidate
+            acc = hat_line<NC, UNIT>(base + r * F::LD + (int)fl + 1, d, af, acc);
         }
         if (more) {
             store((b + 1) & 1);
