@@ -14,8 +14,9 @@
 //   R_i += rho sum_{p covering i} (x_i - X_p(i - r_p))
 //   G = core_patches(R) + rho (X - patches(x))
 //   grad = 2 G D^T               (GEMM with D^T)
-// The GEMMs are plain FP32 register-tiled kernels (LDS tiles of 64 x 64 x 16,
-// 4 x 4 outputs per thread; fixed summation order).
+// The GEMMs run on the FP32 matrix cores (v_mfma_f32_32x32x2f32) when N <= 128 and N, K are
+// multiples of 32 (the dictionary shapes in practice), else on an FP32 register-tiled kernel (LDS
+// tiles of 64 x 64 x 16, 4 x 4 outputs per thread).  Both sum in a fixed order.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -256,8 +257,81 @@ unsigned grid_n(int64_t n)
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
 }
 
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+// C[M][N] = alpha * A[M][K] B[K][N] on the matrix cores, N = 32 NB, K a multiple of 32.  Workgroup =
+// 128 rows (a wavefront per 32 rows, all N columns: NB accumulator blocks of 32 x 32).  K runs in
+// chunks of 32 staged in LDS; A rows padded to 34 floats and B rows to a stride of 32 mod 64 floats
+// keep the fragment reads of both lane halves on distinct banks.  Lane layout of the instruction:
+// lane l holds A[l % 32][l / 32] and B[l / 32][l % 32]; accumulator register i holds
+// C[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
+template <int NB>
+__global__ __launch_bounds__(256) void mfma_sgemm_kernel(const float *__restrict__ A, const float *__restrict__ B,
+                                                         float *__restrict__ C, int64_t M, int K, float alpha)
+{
+    constexpr int N = 32 * NB, LDA = 34, LDB = N + ((96 - N % 64) % 64);
+    __shared__ float sA[128 * LDA];
+    __shared__ float sB[32 * LDB];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t m0 = (int64_t)blockIdx.x * 128;
+    f32x16 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[nb][i] = 0.0f;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        // A chunk: 128 rows x 32 floats, 8 threads per row (16 B each)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q, r = e >> 3, c = (e & 7) * 4;
+            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (m0 + r < M) v = *(const float4 *)(A + (m0 + r) * K + k0 + c);
+            float *d = sA + r * LDA + c;
+            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        }
+        // B chunk: 32 rows x N floats
+        for (int e = tid; e < 8 * N; e += 256) {
+            const int r = e / (N / 4), c = (e % (N / 4)) * 4;
+            const float4 v = *(const float4 *)(B + (int64_t)(k0 + r) * N + c);
+            float *d = sB + r * LDB + c;
+            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 32; kk += 2) {
+            const float a = sA[(wv * 32 + (lane & 31)) * LDA + kk + (lane >> 5)];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const float b = sB[(kk + (lane >> 5)) * LDB + nb * 32 + (lane & 31)];
+                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[nb], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int64_t m = m0 + wv * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+            if (m < M) C[m * N + nb * 32 + (lane & 31)] = alpha * acc[nb][i];
+        }
+}
+
 hipError_t sgemm(const float *A, const float *B, float *C, int64_t M, int N, int K, float alpha, hipStream_t st)
 {
+    // the matrix-core kernel reads A and B with 16-byte loads: rows of K and N floats from 16-byte
+    // aligned bases
+    const bool aligned = (((uintptr_t)A | (uintptr_t)B) & 15) == 0;
+    if (aligned && K % 32 == 0 && N % 32 == 0 && N <= 128 && M > 0) {
+        const unsigned grid = (unsigned)((M + 127) / 128);
+        switch (N / 32) {
+        case 1: mfma_sgemm_kernel<1><<<grid, 256, 0, st>>>(A, B, C, M, K, alpha); break;
+        case 2: mfma_sgemm_kernel<2><<<grid, 256, 0, st>>>(A, B, C, M, K, alpha); break;
+        case 3: mfma_sgemm_kernel<3><<<grid, 256, 0, st>>>(A, B, C, M, K, alpha); break;
+        default: mfma_sgemm_kernel<4><<<grid, 256, 0, st>>>(A, B, C, M, K, alpha); break;
+        }
+        return hipGetLastError();
+    }
     dim3 grid((unsigned)((M + GT - 1) / GT), (unsigned)((N + GT - 1) / GT));
     sgemm_kernel<<<grid, 256, 0, st>>>(A, B, C, (int)M, N, K, alpha);
     return hipGetLastError();
