@@ -406,8 +406,11 @@ struct Stager<L, ROWS, TKv, false> {
 // One workgroup: a TM x TN tile of C over the K range [kz * k_split, (kz+1) * k_split).
 // The next K tile is fetched into registers while the current one is multiplied from
 // LDS; two LDS buffers, one barrier per K tile.
+// Row-major A loaders (forward and backward-data convolutions) fit 4 waves per SIMD with the
+// accumulators in VGPRs; the transposed loaders of the weight gradients would spill there.
 template <class AL, class BL, class EP, int TN, int TMv = TM, int TKv = TK>
-__global__ __launch_bounds__(256) void gemm_kernel(AL A, BL B, EP E, int M, int N, int K, int k_split)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AL::VK ? 4 : 1)))
+void gemm_kernel(AL A, BL B, EP E, int M, int N, int K, int k_split)
 {
     constexpr int LDKv = TKv, KV = TKv / 8;
     constexpr int WMW = WaveGrid<TN>::WM, WNW = WaveGrid<TN>::WN;
