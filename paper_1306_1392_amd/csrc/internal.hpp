@@ -50,7 +50,7 @@ struct GeoDev {
 
 // Forward projection: projections of one geometry grouped into blocks of at most FP_AMAX
 // whose staged line segments share one LDS segment of FP_SEG positions (see k_fp.hip).
-constexpr int FP_RB = 16, FP_AMAX = 32;
+constexpr int FP_RB = 16, FP_AMAX = 16;
 int fp_seg_len(double s_min);
 
 struct SliceDev {

@@ -17,13 +17,16 @@
 //                     below half a bin (no fixed candidate count) on smaller plans.
 //
 // gfx950 layout of fp_kernel, the transpose of the backprojector's: workgroup = one
-// angle block (up to 32 projections of similar direction, grouped by the plan so
-// that their candidate positions share one segment) x 64 bins x one slice.
+// angle block (up to FP_AMAX = 16 projections of similar direction, grouped by the
+// plan so that their candidate positions share one segment) x 64 bins x one slice.
 // The workgroup walks the image lines in blocks of 16; for each block it
 // stages the shared segment of every line (fp_seg_len positions, zero outside
 // the image) in LDS once, and every wavefront then serves its projections (m = w,
 // w + 4, ...; lane = bin, one accumulator per projection) from LDS: a staged
-// value is read up to ~2 x 32 times.  Coordinates: per (lane, projection, line
+// value is read up to ~2 x 16 times.  A wavefront's (up to 4) projections advance
+// together line by line, so each line issues independent LDS reads for all of
+// them; 16 rather than 32 projections per block keep that state within 128 VGPRs
+// (4 wavefronts per SIMD).  Coordinates: per (lane, projection, line
 // block) the crossing u of the block's first line is computed in FP64 and split
 // into an integer base and an FP32 remainder; inside the block u advances by an
 // FP32 slope, so every FP32 offset stays below FP_RB + 2 positions.
@@ -48,15 +51,60 @@ constexpr int AW = FP_AMAX / 4;   // projections per wavefront
 // lies in (u - 1/|a|, u - 1/|a| + 1], so |d| < 1 and |d + a| <= 1: only the third weight can be
 // clamped to zero, and the other two skip the max (they differ from the clamped form only by FP32
 // rounding at the hat's end points, where the weight is zero to within an ulp).
+// Since 1 - |d| never exceeds 1, max(0, 1 - |d|) is its clamp to [0, 1], which the subtraction applies
+// as an output modifier (no separate max).
 template <int NC, bool UNIT>
 __device__ __forceinline__ float hat_line(const float *row, float d, float af, float acc)
 {
 #pragma unroll
     for (int n = 0; n < NC; ++n, d += af) {
-        const float w = (UNIT && n < 2) ? 1.0f - fabsf(d) : fmaxf(0.0f, 1.0f - fabsf(d));
+        const float w = (UNIT && n < 2) ? 1.0f - fabsf(d) : __builtin_amdgcn_fmed3f(1.0f - fabsf(d), 0.0f, 1.0f);
         acc = fmaf(w, row[n], acc);
     }
     return acc;
+}
+
+// First candidate of one line from v = u - 1/|a| (u: the bin's crossing, in positions from the staged
+// base): the candidates are floor(v) + 1, + 2, ..., and the first one's offset is
+// t - j = a (floor(v) + 1 - u) = a - sign(a) - a fract(v) = fma(-a, fract(v), c0), c0 = a - sign(a).
+struct FirstCand {
+    int idx;   // floor(v) + 1
+    float d;   // t - j at idx
+};
+__device__ __forceinline__ FirstCand first_cand(float v, float af, float c0)
+{
+    int fl;   // floor(v) converted in one instruction (|v| stays below a few hundred positions)
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(fl) : "v"(v));
+    return {fl + 1, fmaf(-af, __builtin_amdgcn_fractf(v), c0)};
+}
+
+// One block of lines for the first MINE projection slots of a wavefront (NC > 0).  The slots advance
+// together line by line, so every line issues MINE independent groups of LDS reads and the wavefront
+// has that many accumulation chains in flight instead of one.
+template <int NC, bool UNIT, int MINE>
+__device__ __forceinline__ void fp_block_lines(const float *stage, int seg_len, int nl, int l0, int seg0,
+                                               const double *u_first, const double *slope, const float *af,
+                                               const float *rhof, const float *slopef, const float *c0f,
+                                               float *acc)
+{
+    float remv[MINE];
+    int boff[MINE];
+#pragma unroll
+    for (int i = 0; i < MINE; ++i) {
+        const double ub = fma((double)l0, slope[i], u_first[i]);
+        const double ubase = floor(ub);
+        remv[i] = (float)(ub - ubase - (double)rhof[i]);   // u - 1/|a| at the block's first line
+        boff[i] = (int)ubase - seg0;
+    }
+    float rf = 0.0f;
+    for (int r = 0; r < nl; ++r, rf += 1.0f) {
+        const float *line = stage + r * seg_len;
+#pragma unroll
+        for (int i = 0; i < MINE; ++i) {
+            const FirstCand fc = first_cand(fmaf(rf, slopef[i], remv[i]), af[i], c0f[i]);
+            acc[i] = hat_line<NC, UNIT>(line + boff[i] + fc.idx, fc.d, af[i], acc[i]);
+        }
+    }
 }
 
 // NC > 0: a fixed number of candidates per line (the surplus ones get zero weight), so the reads of
@@ -90,7 +138,7 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
 
     // this lane's projections: u = U0 + j / a + slope * line, candidates within rho of u
     double u_first[AW], slope[AW];
-    float af[AW], rhof[AW], slopef[AW];
+    float af[AW], rhof[AW], slopef[AW], c0f[AW];
     int ncand[AW], kk[AW];
     int mine = 0;
 #pragma unroll
@@ -107,6 +155,7 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
         slope[i] = -bb / a;
         u_first[i] = ((double)j - t0 + a * ci + bb * cl) / a;
         af[i] = (float)a;
+        c0f[i] = af[i] - copysignf(1.0f, af[i]);
         rhof[i] = (float)rho;
         slopef[i] = (float)slope[i];
         ncand[i] = on ? (int)ceil(2.0 * rho) : 0;
@@ -151,21 +200,35 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
         }
         __syncthreads();
         const int nl = min(FP_RB, n_lines - l0);
+        if constexpr (NC > 0) {
+#define FP_LINES_CASE(M)                                                                                  \
+    case M:                                                                                               \
+        fp_block_lines<NC, UNIT, M>(stage, seg_len, nl, l0, seg0, u_first, slope, af, rhof, slopef, c0f, acc); \
+        break;
+            switch (mine) {   // uniform over the wavefront
+                FP_LINES_CASE(8)
+                FP_LINES_CASE(7)
+                FP_LINES_CASE(6)
+                FP_LINES_CASE(5)
+                FP_LINES_CASE(4)
+                FP_LINES_CASE(3)
+                FP_LINES_CASE(2)
+                FP_LINES_CASE(1)
+                default: break;
+            }
+#undef FP_LINES_CASE
+        } else {
 #pragma unroll
-        for (int i = 0; i < AW; ++i) {
-            if (i >= mine) break;
-            const double ub = fma((double)l0, slope[i], u_first[i]);
-            const double ubase = floor(ub);
-            const float rem = (float)(ub - ubase);
-            const float *base = stage + ((int)ubase - seg0);
-            for (int r = 0; r < nl; ++r) {
-                const float u = fmaf((float)r, slopef[i], rem);       // crossing relative to ubase
-                const float fl = floorf(u - rhof[i]);                 // first candidate = fl + 1
-                const float *row = base + r * seg_len + (int)fl + 1;
-                float d = fmaf(af[i], fl - u, af[i]);                 // t - j at the first candidate
-                if constexpr (NC > 0) {
-                    acc[i] = hat_line<NC, UNIT>(row, d, af[i], acc[i]);
-                } else {
+            for (int i = 0; i < AW; ++i) {
+                if (i >= mine) break;
+                const double ub = fma((double)l0, slope[i], u_first[i]);
+                const double ubase = floor(ub);
+                const float remv = (float)(ub - ubase - (double)rhof[i]);   // u - 1/|a| at the block's first line
+                const float *base = stage + ((int)ubase - seg0);
+                for (int r = 0; r < nl; ++r) {
+                    const FirstCand fc = first_cand(fmaf((float)r, slopef[i], remv), af[i], c0f[i]);
+                    const float *row = base + r * seg_len + fc.idx;
+                    float d = fc.d;
                     for (int n = 0; n < ncand[i]; ++n, d += af[i]) acc[i] = fmaf(fmaxf(0.0f, 1.0f - fabsf(d)), row[n], acc[i]);
                 }
             }
@@ -314,7 +377,7 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
     // lowest candidate of the workgroup's 64 bins over a block's FP_RB lines, relative to its first line
     const double blk_lo = fmin(((double)j0 + u_c) / a, ((double)(j0 + 63) + u_c) / a) +
                           fmin(0.0, (FP_RB - 1) * slope) - rho;
-    const float af = (float)a, rhof = (float)rho, slopef = (float)slope;
+    const float af = (float)a, slopef = (float)slope, c0 = af - copysignf(1.0f, af);
     const float *im = img + sd.img_off;
     // staging map: 16 consecutive threads read 16 consecutive floats of one image row
     const int sr = rows ? tid >> 4 : tid & 15;     // staged line within the block
@@ -358,16 +421,28 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
         const int l0 = b * FP_RB;
         const double ub = fma((double)l0, slope, u_first);   // FP64 anchor of this lane and block
         const double ubase = floor(ub);
-        const float rem = (float)(ub - ubase);
-        const float *base = stage[b & 1] + ((int)ubase - seg_cur);
+        const float remv = (float)(ub - ubase - rho);          // u - 1/|a| at the block's first line
+        // this wavefront's first line; the others sit at constant LDS offsets from it
+        const float *base = stage[b & 1] + ((int)ubase - seg_cur) + wv * F::LD;
+        if (l0 + FP_RB <= n_lines) {
+            // a whole block: the wavefront's FP_RB / 4 lines have no branch between them, so their
+            // reads issue together (one partial sum per line, added in line order)
+            float part_l[FP_RB / 4];
 #pragma unroll
-        for (int m = 0; m < FP_RB / 4; ++m) {
-            const int r = wv + 4 * m;
-            if (l0 + r >= n_lines) break;                     // uniform
-            const float u = fmaf((float)r, slopef, rem);      // crossing relative to ubase
-            const float fl = floorf(u - rhof);                 // first candidate = fl + 1
-            const float d = fmaf(af, fl - u, af);              // t - j at the first candidate
-            acc = hat_line<NC, UNIT>(base + r * F::LD + (int)fl + 1, d, af, acc);
+            for (int m = 0; m < FP_RB / 4; ++m) {
+                const FirstCand fc = first_cand(fmaf((float)(wv + 4 * m), slopef, remv), af, c0);
+                part_l[m] = hat_line<NC, UNIT>(base + 4 * m * F::LD + fc.idx, fc.d, af, 0.0f);
+            }
+#pragma unroll
+            for (int m = 0; m < FP_RB / 4; ++m) acc += part_l[m];
+        } else {
+#pragma unroll
+            for (int m = 0; m < FP_RB / 4; ++m) {
+                const int r = wv + 4 * m;
+                if (l0 + r >= n_lines) break;                 // uniform
+                const FirstCand fc = first_cand(fmaf((float)r, slopef, remv), af, c0);
+                acc = hat_line<NC, UNIT>(base + 4 * m * F::LD + fc.idx, fc.d, af, acc);
+            }
         }
         if (more) {
             store((b + 1) & 1);

@@ -3,7 +3,9 @@
 * fp_staged_kernel (one projection x 64 bins per workgroup, 16-line blocks staged in LDS): every
   candidate a lane reads lies inside the staged segment of its line, [0, SEG) with SEG = 128 for three
   candidates per line and 224 for six, over random geometries at the edges of both pixel-size classes.
-  The replay follows the kernel's FP64 block anchor and FP32 per-line offsets.
+  The replay follows the kernel's FP64 block anchor and FP32 per-line offsets (first candidate
+  floor(v) + 1 and its offset a - sign(a) - a fract(v), v = u - 1/|a|), and checks both against FP64:
+  the offset to 2e-5, and no position outside the candidates has a hat weight above 1e-5.
 * prox_step2_kernel (two fused ROF dual steps on a 64 x 16 tile with a two-pixel halo): its loops,
   replayed with NaN-initialised LDS so that a read of an unset entry fails, equal two plain single steps
   exactly, on ragged and degenerate image shapes.
@@ -37,7 +39,8 @@ def staged_columns(nx, ny, nb, angles, axis, shifts, s):
         n_lines = ny if rows else nx
         rho, slope = 1.0 / abs(a), -bb / a
         u_c = -t0 + a * ci + bb * cl
-        af, rhof, slopef = F32(a), F32(rho), F32(slope)
+        af, slopef = F32(a), F32(slope)
+        c0 = F32(af - F32(math.copysign(1.0, a)))
         for j0 in range(0, nb, 64):
             u_first = (np.arange(j0, j0 + 64, dtype=np.float64) + u_c) / a
             blk_lo = min((j0 + u_c) / a, (j0 + 63 + u_c) / a) + min(0.0, (RB - 1) * slope) - rho
@@ -46,12 +49,22 @@ def staged_columns(nx, ny, nb, angles, axis, shifts, s):
                 seg0 = math.floor(l0 * slope + blk_lo) - 2
                 ub = l0 * slope + u_first
                 ubase = np.floor(ub)
-                rem = (ub - ubase).astype(F32)
+                remv = (ub - ubase - rho).astype(F32)          # u - 1/|a| at the block's first line
                 nl = min(RB, n_lines - l0)
-                u = (r[:nl] * slopef + rem[None]).astype(F32)
-                i0 = np.floor((u - rhof).astype(F32)).astype(np.int64) + 1
+                v = (r[:nl] * slopef + remv[None]).astype(F32)
+                i0 = np.floor(v).astype(np.int64) + 1            # first candidate
+                d0 = (-af * (v - np.floor(v)) + c0).astype(F32)  # its offset t - j, a - sign(a) - a fract(v)
                 col = (ubase.astype(np.int64) - seg0)[None] + i0
                 lo, hi = min(lo, int(col.min())), max(hi, int(col.max()) + nc - 1)
+                # against FP64: the offset of the first candidate, and every position with a hat
+                # weight above 1e-5 lies among the nc candidates
+                u64 = ub[None] + r[:nl].astype(np.float64) * slope
+                d64 = a * (ubase[None] + i0 - u64)
+                assert np.max(np.abs(d0 - d64)) < 2e-5
+                for q in range(-1, nc + 1):
+                    w = 1.0 - np.abs(d64 + q * a)
+                    outside = (q < 0) | (q >= nc)
+                    assert not np.any(outside & (w > 1e-5)), (k, j0, b, q)
     return lo, hi, seg_len
 
 
