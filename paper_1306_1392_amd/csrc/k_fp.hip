@@ -11,10 +11,12 @@
 // i in (u - 1/|a|, u + 1/|a|): at most ceil(2/|a|) of them.
 //
 // Three kernels compute the same sums (up to FP32 rounding order):
-//   fp_kernel         angle blocks, for plans with enough of them to fill the chip;
-//   fp_staged_kernel  one projection per workgroup staged in LDS, for smaller plans;
-//   fp_lines_kernel   one projection per workgroup read from global memory, for pixels
-//                     below half a bin (no fixed candidate count) on smaller plans.
+//   fp_staged_kernel  one or two projections per workgroup staged in LDS, whenever the
+//                     candidate count per line is fixed (pixels of at least half a bin);
+//   fp_kernel         angle blocks, for smaller pixels on plans with enough blocks to fill
+//                     the chip;
+//   fp_lines_kernel   one projection per workgroup read from global memory, for smaller
+//                     pixels on smaller plans.
 //
 // gfx950 layout of fp_kernel, the transpose of the backprojector's: workgroup = one
 // angle block (up to FP_AMAX = 16 projections of similar direction, grouped by the
@@ -40,6 +42,13 @@ int fp_seg_len(double s_min)
 {
     const int seg = (int)std::ceil(65.0 * 1.4142135623730951 / s_min + (FP_RB - 1) + 10.0 + 96.0);
     return (seg + 3) & ~3;
+}
+
+// candidates per line: ceil(2 sqrt 2 / s) <= 3 or <= 6, else counted at run time
+int fp_nc_for(double s_min)
+{
+    const int need = (int)std::ceil(2.0 * 1.4142135623730951 / s_min - 1e-9);
+    return need <= 3 ? 3 : (need <= 6 ? 6 : 0);
 }
 
 namespace {
@@ -330,54 +339,65 @@ __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__
     }
 }
 
-// Small problems, pixel size >= 0.5 (NC > 0): one projection per workgroup, staged through LDS.
-// The workgroup walks the image lines in blocks of FP_RB; the 64 bins of one projection touch, over
-// a block, a segment of at most 63/|a| + (FP_RB - 1)|slope| + 1/|a| + NC + 3 positions of every line
-// (< FpStaged<NC>::SEG), which 256 threads stage with 16-wide contiguous reads along the image rows in both
-// walking directions (so a column-walking projection reads rows of 16 neighbouring columns rather
-// than 64 separate rows).  The next block is loaded into registers while the current one is summed
-// from the other LDS buffer: one barrier per block.  Wavefront w sums lines w, w + 4, ... of every
-// block; the four partial sums are added in a fixed order through LDS.
+// Small problems, pixel size >= 0.5 (NC > 0): one or two projections per workgroup, staged through LDS.
+// The plan pairs neighbouring projections (similar direction) whose candidates share the staged
+// segment; a staged value then serves both.  The workgroup walks the image lines in blocks of FP_RB;
+// the 64 bins of one projection touch, over a block, a segment of at most 63/|a| + (FP_RB - 1)|slope|
+// + 1/|a| + NC + 3 positions of every line (< FpStaged<NC>::SEG; the plan checks the pair's union),
+// which 256 threads stage with 16-wide contiguous reads along the image rows in both walking
+// directions (so a column-walking projection reads rows of 16 neighbouring columns rather than 64
+// separate rows).  The next block is loaded into registers while the current one is summed from the
+// other LDS buffer: one barrier per block.  Wavefront w sums lines w, w + 4, ... of every block for
+// each projection of the group; the four partial sums are added in a fixed order through LDS.
 template <int NC> struct FpStaged {
-    static constexpr int SEG = NC == 3 ? 128 : 224;   // positions staged per line
+    static constexpr int SEG = NC == 3 ? FP_SSEG3 : FP_SSEG6;   // positions staged per line
     static constexpr int LD = SEG + 17;               // LDS row stride: 17 mod 32 spreads the banks
     static constexpr int PER = SEG / 16;              // staged values per thread and block
 };
 
-template <int MODE, int NC, bool UNIT>
-__global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *__restrict__ img,
-                                                        float *__restrict__ out, float alpha, CpDual cp, int k0)
-{
-    using F = FpStaged<NC>;
-    __shared__ float stage[2][FP_RB * F::LD];
-    __shared__ float part[3][64];
-    const int slice = blockIdx.z;
-    const SliceDev sd = T.slc[slice];
-    const GeoDev &g = T.geo[sd.g];
-    const int K = g.K, nb = g.nb, nx = g.nx, ny = g.ny;
-    const int k = k0 + blockIdx.y;
-    const int j0 = blockIdx.x * 64;
-    if (k >= K || j0 >= nb) return;   // uniform over the workgroup
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int j = j0 + lane;
+// One projection of a staged group, for this lane's bin j of the workgroup's chunk j0..j0+63.
+struct StagedProj {
+    double u_first, slope, rho, blk_lo;   // crossing at line 0, per line, 1/|a|; lowest first candidate
+    float af, slopef, c0;                 // a, slope, a - sign(a) in FP32
+    int k;
+};
 
+__device__ __forceinline__ StagedProj staged_proj(const Tables &T, const GeoDev &g, int k, int j, int j0,
+                                                  bool &rows)
+{
     const double c = T.cosd[g.ang_off + k], sn = T.sind[g.ang_off + k];
     const double s = g.s;
-    const double cx = 0.5 * (nx - 1), cy = 0.5 * (ny - 1);
+    const double cx = 0.5 * (g.nx - 1), cy = 0.5 * (g.ny - 1);
     const double t0 = g.axis + T.shiftd[g.ang_off + k];
-    const bool rows = fabs(c) >= fabs(sn);
+    rows = fabs(c) >= fabs(sn);
     const double a = rows ? s * c : s * sn, bb = rows ? s * sn : s * c;
     const double ci = rows ? cx : cy, cl = rows ? cy : cx;
-    const int n_lines = rows ? ny : nx, n_pos = rows ? nx : ny;
-    const double rho = 1.0 / fabs(a);
-    const double slope = -bb / a;
+    StagedProj q;
+    q.k = k;
+    q.rho = 1.0 / fabs(a);
+    q.slope = -bb / a;
     const double u_c = -t0 + a * ci + bb * cl;
-    const double u_first = ((double)j + u_c) / a;
-    // lowest candidate of the workgroup's 64 bins over a block's FP_RB lines, relative to its first line
-    const double blk_lo = fmin(((double)j0 + u_c) / a, ((double)(j0 + 63) + u_c) / a) +
-                          fmin(0.0, (FP_RB - 1) * slope) - rho;
-    const float af = (float)a, slopef = (float)slope, c0 = af - copysignf(1.0f, af);
+    q.u_first = ((double)j + u_c) / a;
+    // lowest first candidate of the chunk's 64 bins over a block's FP_RB lines, relative to its first line
+    q.blk_lo = fmin(((double)j0 + u_c) / a, ((double)(j0 + 63) + u_c) / a) + fmin(0.0, (FP_RB - 1) * q.slope) -
+               q.rho;
+    q.af = (float)a;
+    q.slopef = (float)q.slope;
+    q.c0 = q.af - copysignf(1.0f, q.af);
+    return q;
+}
+
+template <int MODE, int NC, bool UNIT, int P>
+__device__ __forceinline__ void fp_staged_body(const Tables &T, const SliceDev &sd, const GeoDev &g,
+                                               const StagedProj *pr, bool rows, int j, const float *img,
+                                               float *out, float alpha, const CpDual &cp, int slice,
+                                               float (*stage)[FP_RB * FpStaged<NC>::LD], float (*part)[3][64])
+{
+    using F = FpStaged<NC>;
+    const int nb = g.nb, nx = g.nx, ny = g.ny;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n_lines = rows ? ny : nx, n_pos = rows ? nx : ny;
     const float *im = img + sd.img_off;
     // staging map: 16 consecutive threads read 16 consecutive floats of one image row
     const int sr = rows ? tid >> 4 : tid & 15;     // staged line within the block
@@ -389,7 +409,10 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
     float v[F::PER];
     auto load = [&](int b, int &seg0) {
         const int l0 = b * FP_RB;
-        seg0 = (int)floor(fma((double)l0, slope, blk_lo)) - 2;
+        double lo = fma((double)l0, pr[0].slope, pr[0].blk_lo);
+#pragma unroll
+        for (int p = 1; p < P; ++p) lo = fmin(lo, fma((double)l0, pr[p].slope, pr[p].blk_lo));
+        seg0 = (int)floor(lo) - 2;
         const int line = l0 + sr;
         if (line < n_lines && seg0 >= 0 && seg0 + F::SEG <= n_pos) {
             // the whole staged segment lies inside the image (most blocks): no per-element test
@@ -410,7 +433,9 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
         for (int i = 0; i < F::PER; ++i) stage[buf][sr * F::LD + sp + 16 * i] = v[i];
     };
 
-    float acc = 0.0f;
+    float acc[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) acc[p] = 0.0f;
     int seg_cur, seg_next = 0;
     load(0, seg_cur);
     store(0);
@@ -419,30 +444,42 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
         const bool more = b + 1 < n_blk;
         if (more) load(b + 1, seg_next);
         const int l0 = b * FP_RB;
-        const double ub = fma((double)l0, slope, u_first);   // FP64 anchor of this lane and block
-        const double ubase = floor(ub);
-        const float remv = (float)(ub - ubase - rho);          // u - 1/|a| at the block's first line
-        // this wavefront's first line; the others sit at constant LDS offsets from it
-        const float *base = stage[b & 1] + ((int)ubase - seg_cur) + wv * F::LD;
+        // per projection: FP64 anchor of this lane and block, then this wavefront's first line (the
+        // others sit at constant LDS offsets from it)
+        float remv[P];
+        const float *base[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const double ub = fma((double)l0, pr[p].slope, pr[p].u_first);
+            const double ubase = floor(ub);
+            remv[p] = (float)(ub - ubase - pr[p].rho);         // u - 1/|a| at the block's first line
+            base[p] = stage[b & 1] + ((int)ubase - seg_cur) + wv * F::LD;
+        }
         if (l0 + FP_RB <= n_lines) {
-            // a whole block: the wavefront's FP_RB / 4 lines have no branch between them, so their
-            // reads issue together (one partial sum per line, added in line order)
-            float part_l[FP_RB / 4];
+            // a whole block: no branch between the lines, so the reads of all of them (and of both
+            // projections) issue together; one partial sum per line, added in line order
+            float part_l[P][FP_RB / 4];
 #pragma unroll
-            for (int m = 0; m < FP_RB / 4; ++m) {
-                const FirstCand fc = first_cand(fmaf((float)(wv + 4 * m), slopef, remv), af, c0);
-                part_l[m] = hat_line<NC, UNIT>(base + 4 * m * F::LD + fc.idx, fc.d, af, 0.0f);
-            }
+            for (int p = 0; p < P; ++p)
 #pragma unroll
-            for (int m = 0; m < FP_RB / 4; ++m) acc += part_l[m];
+                for (int m = 0; m < FP_RB / 4; ++m) {
+                    const FirstCand fc = first_cand(fmaf((float)(wv + 4 * m), pr[p].slopef, remv[p]), pr[p].af, pr[p].c0);
+                    part_l[p][m] = hat_line<NC, UNIT>(base[p] + 4 * m * F::LD + fc.idx, fc.d, pr[p].af, 0.0f);
+                }
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int m = 0; m < FP_RB / 4; ++m) acc[p] += part_l[p][m];
         } else {
 #pragma unroll
-            for (int m = 0; m < FP_RB / 4; ++m) {
-                const int r = wv + 4 * m;
-                if (l0 + r >= n_lines) break;                 // uniform
-                const FirstCand fc = first_cand(fmaf((float)r, slopef, remv), af, c0);
-                acc = hat_line<NC, UNIT>(base + 4 * m * F::LD + fc.idx, fc.d, af, acc);
-            }
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int m = 0; m < FP_RB / 4; ++m) {
+                    const int r = wv + 4 * m;
+                    if (l0 + r >= n_lines) break;             // uniform
+                    const FirstCand fc = first_cand(fmaf((float)r, pr[p].slopef, remv[p]), pr[p].af, pr[p].c0);
+                    acc[p] = hat_line<NC, UNIT>(base[p] + 4 * m * F::LD + fc.idx, fc.d, pr[p].af, acc[p]);
+                }
         }
         if (more) {
             store((b + 1) & 1);
@@ -450,30 +487,68 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
         }
         __syncthreads();
     }
-    if (wv > 0) part[wv - 1][lane] = acc;
+    if (wv > 0) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) part[p][wv - 1][lane] = acc[p];
+    }
     __syncthreads();
     if (wv > 0 || j >= nb) return;
-    acc = ((acc + part[0][lane]) + part[1][lane]) + part[2][lane];
-    const int64_t o = sd.sino_off + (int64_t)k * nb + j;
-    const float val = alpha * (float)(s * s) * acc;
-    if (MODE == 0) {
-        out[o] = val;
-    } else if (MODE == 1) {
-        cp.p[o] = (cp.p[o] + cp.sigma * (val - cp.y[o])) / (1.0f + cp.sigma);
-    } else if (MODE == 2) {
-        cp.p[o] = val - cp.y[o];
-    } else {
-        cp.p[(int64_t)slice * nb + j] = val - cp.y[o];
+    const float sc = alpha * (float)(g.s * g.s);   // A = s^2 B^T
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const float sum = ((acc[p] + part[p][0][lane]) + part[p][1][lane]) + part[p][2][lane];
+        const int64_t o = sd.sino_off + (int64_t)pr[p].k * nb + j;
+        const float val = sc * sum;
+        if (MODE == 0) {
+            out[o] = val;
+        } else if (MODE == 1) {
+            cp.p[o] = (cp.p[o] + cp.sigma * (val - cp.y[o])) / (1.0f + cp.sigma);
+        } else if (MODE == 2) {
+            cp.p[o] = val - cp.y[o];
+        } else {
+            cp.p[(int64_t)slice * nb + j] = val - cp.y[o];
+        }
     }
 }
 
-// candidates per line for the plan's smallest pixel size: ceil(2 sqrt 2 / s) <= 3 or <= 6, else run time
+// grid: (bin chunks, staged groups of the geometry with the most, slices); MODE 3: one projection k0
+template <int MODE, int NC, bool UNIT>
+__global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *__restrict__ img,
+                                                        float *__restrict__ out, float alpha, CpDual cp, int k0)
+{
+    __shared__ float stage[2][FP_RB * FpStaged<NC>::LD];
+    __shared__ float part[2][3][64];
+    const int slice = blockIdx.z;
+    const SliceDev sd = T.slc[slice];
+    const GeoDev &g = T.geo[sd.g];
+    const int j0 = blockIdx.x * 64;
+    int ka = k0, kb = -1;
+    if (MODE != 3) {
+        if ((int)blockIdx.y >= g.fp_npair) return;   // uniform over the workgroup
+        const int2 grp = T.fp_pair[g.fp_pair_off + blockIdx.y];
+        ka = grp.x;
+        kb = grp.y;
+    } else if (k0 >= g.K) {
+        return;
+    }
+    if (j0 >= g.nb) return;                          // uniform over the workgroup
+    const int j = j0 + (int)(threadIdx.x & 63);
+    bool rows, rows_b;
+    StagedProj pr[2];
+    pr[0] = staged_proj(T, g, ka, j, j0, rows);
+    if (kb >= 0) {
+        pr[1] = staged_proj(T, g, kb, j, j0, rows_b);   // same walking axis (the plan pairs only such)
+        fp_staged_body<MODE, NC, UNIT, 2>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
+    } else {
+        fp_staged_body<MODE, NC, UNIT, 1>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
+    }
+}
+
 int fp_nc(const pyhst_plan &p)
 {
     double s_min = 1e300;
     for (const auto &g : p.gd) s_min = std::min(s_min, g.s);
-    const int need = (int)std::ceil(2.0 * 1.4142135623730951 / s_min - 1e-9);
-    return need <= 3 ? 3 : (need <= 6 ? 6 : 0);
+    return fp_nc_for(s_min);
 }
 
 // three candidates and no pixel wider than a bin: |a| in [2/3, 1] for every projection
@@ -490,16 +565,18 @@ hipError_t launch_fp_nc(const pyhst_plan &p, dim3 grid, const float *img, float 
 {
     int kind = p.fp_kernel;
     if (kind == PYHST_FP_AUTO) {
-        // angle blocks only when they give enough workgroups to fill the chip; one projection per
-        // workgroup otherwise, staged through LDS when the candidate count is fixed
+        // a fixed candidate count: the staged kernel (one or two projections per workgroup), faster
+        // than the angle blocks at every measured size; otherwise angle blocks when they give enough
+        // workgroups to fill the chip, else one projection per workgroup read from global memory
         const int64_t wgs = (int64_t)grid.x * grid.y * grid.z;
-        kind = (MODE == 3 || wgs < 8 * (int64_t)p.cu_count) ? PYHST_FP_STAGED : PYHST_FP_BLOCKS;
+        kind = (NC > 0 || MODE == 3 || wgs < 8 * (int64_t)p.cu_count) ? PYHST_FP_STAGED : PYHST_FP_BLOCKS;
     }
     if (kind == PYHST_FP_STAGED && NC == 0) kind = PYHST_FP_LINES;
     const dim3 g2(grid.x, MODE == 3 ? 1u : (unsigned)p.max_K, grid.z);
     if (kind == PYHST_FP_STAGED) {
+        const dim3 gs(grid.x, MODE == 3 ? 1u : (unsigned)p.fp_max_pairs, grid.z);
         if constexpr (NC > 0)
-            fp_staged_kernel<MODE, NC, UNIT><<<g2, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
+            fp_staged_kernel<MODE, NC, UNIT><<<gs, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
         return hipGetLastError();
     }
     if (kind == PYHST_FP_LINES) {

@@ -1,8 +1,9 @@
 """CPU replays of the index arithmetic of two GPU kernels (host logic, no GPU).
 
-* fp_staged_kernel (one projection x 64 bins per workgroup, 16-line blocks staged in LDS): every
-  candidate a lane reads lies inside the staged segment of its line, [0, SEG) with SEG = 128 for three
-  candidates per line and 224 for six, over random geometries at the edges of both pixel-size classes.
+* fp_staged_kernel (one or two projections x 64 bins per workgroup, 16-line blocks staged in LDS;
+  the pairs chosen by the plan's rule, replayed here): every candidate a lane reads lies inside the
+  staged segment of its line, [0, SEG) with SEG = 128 for three candidates per line and 224 for six,
+  over random geometries at the edges of both pixel-size classes.
   The replay follows the kernel's FP64 block anchor and FP32 per-line offsets (first candidate
   floor(v) + 1 and its offset a - sign(a) - a fract(v), v = u - 1/|a|), and checks both against FP64:
   the offset to 2e-5, and no position outside the candidates has a hat weight above 1e-5.
@@ -19,53 +20,92 @@ F32 = np.float32
 RB = 16
 
 
+def _proj(k, th, s, nx, ny, axis, shift):
+    c, sn = math.cos(th), math.sin(th)
+    rows = abs(c) >= abs(sn)
+    a = s * c if rows else s * sn
+    bb = s * sn if rows else s * c
+    cx, cy = 0.5 * (nx - 1), 0.5 * (ny - 1)
+    ci, cl = (cx, cy) if rows else (cy, cx)
+    u_c = -(axis + shift) + a * ci + bb * cl
+    return dict(k=k, rows=rows, sgn=a > 0, a=a, slope=-bb / a, rho=1.0 / abs(a), u_c=u_c, U0=u_c / a)
+
+
+def staged_groups(P, nx, ny, nb, nc):
+    """The plan's staged groups: projections sorted by (walking axis, sign of a, slope); neighbours
+    paired when their first candidates span at most SEG - nc - 5 positions at every corner chunk and
+    line block."""
+    sseg = 128 if nc == 3 else 224
+    v = sorted(P, key=lambda q: (not q["rows"], not q["sgn"], q["slope"]))
+    nchunk = (nb + 63) // 64
+
+    def fits(x, y):
+        if x["rows"] != y["rows"]:
+            return False
+        nl = ny if x["rows"] else nx
+        for jc in (0.0, 64.0 * (nchunk - 1)):
+            for lc in (0.0, float(((nl - 1) // RB) * RB)):
+                w = [z["U0"] + (jc + 63.0 * cj) / z["a"] + z["slope"] * (lc + (RB - 1) * cl) - z["rho"]
+                     for z in (x, y) for cj in (0, 1) for cl in (0, 1)]
+                if max(w) - min(w) + nc + 5 > sseg:
+                    return False
+        return True
+    groups, i = [], 0
+    while i < len(v):
+        if i + 1 < len(v) and fits(v[i], v[i + 1]):
+            groups.append((v[i], v[i + 1]))
+            i += 2
+        else:
+            groups.append((v[i],))
+            i += 1
+    return groups
+
+
 def staged_columns(nx, ny, nb, angles, axis, shifts, s):
-    """(lowest, highest) LDS column read by fp_staged_kernel, and the segment length, or None."""
+    """(lowest, highest) LDS column read by fp_staged_kernel, the segment length and the number of
+    paired groups, or None."""
     need = math.ceil(2 * math.sqrt(2) / s - 1e-9)
     nc = 3 if need <= 3 else (6 if need <= 6 else 0)
     if nc == 0:
         return None
     seg_len = 128 if nc == 3 else 224
     lo, hi = 10 ** 9, -10 ** 9
-    cx, cy = 0.5 * (nx - 1), 0.5 * (ny - 1)
     r = np.arange(RB, dtype=F32)[:, None]
-    for k, th in enumerate(angles):
-        c, sn = math.cos(th), math.sin(th)
-        t0 = axis + shifts[k]
-        rows = abs(c) >= abs(sn)
-        a = s * c if rows else s * sn
-        bb = s * sn if rows else s * c
-        ci, cl = (cx, cy) if rows else (cy, cx)
-        n_lines = ny if rows else nx
-        rho, slope = 1.0 / abs(a), -bb / a
-        u_c = -t0 + a * ci + bb * cl
-        af, slopef = F32(a), F32(slope)
-        c0 = F32(af - F32(math.copysign(1.0, a)))
+    P = [_proj(k, th, s, nx, ny, axis, shifts[k]) for k, th in enumerate(angles)]
+    groups = staged_groups(P, nx, ny, nb, nc)
+    for grp in groups:
+        n_lines = ny if grp[0]["rows"] else nx
         for j0 in range(0, nb, 64):
-            u_first = (np.arange(j0, j0 + 64, dtype=np.float64) + u_c) / a
-            blk_lo = min((j0 + u_c) / a, (j0 + 63 + u_c) / a) + min(0.0, (RB - 1) * slope) - rho
+            for q in grp:
+                q["u_first"] = (np.arange(j0, j0 + 64, dtype=np.float64) + q["u_c"]) / q["a"]
+                q["blk_lo"] = (min((j0 + q["u_c"]) / q["a"], (j0 + 63 + q["u_c"]) / q["a"]) +
+                               min(0.0, (RB - 1) * q["slope"]) - q["rho"])
             for b in range((n_lines + RB - 1) // RB):
                 l0 = b * RB
-                seg0 = math.floor(l0 * slope + blk_lo) - 2
-                ub = l0 * slope + u_first
-                ubase = np.floor(ub)
-                remv = (ub - ubase - rho).astype(F32)          # u - 1/|a| at the block's first line
+                seg0 = math.floor(min(l0 * q["slope"] + q["blk_lo"] for q in grp)) - 2
                 nl = min(RB, n_lines - l0)
-                v = (r[:nl] * slopef + remv[None]).astype(F32)
-                i0 = np.floor(v).astype(np.int64) + 1            # first candidate
-                d0 = (-af * (v - np.floor(v)) + c0).astype(F32)  # its offset t - j, a - sign(a) - a fract(v)
-                col = (ubase.astype(np.int64) - seg0)[None] + i0
-                lo, hi = min(lo, int(col.min())), max(hi, int(col.max()) + nc - 1)
-                # against FP64: the offset of the first candidate, and every position with a hat
-                # weight above 1e-5 lies among the nc candidates
-                u64 = ub[None] + r[:nl].astype(np.float64) * slope
-                d64 = a * (ubase[None] + i0 - u64)
-                assert np.max(np.abs(d0 - d64)) < 2e-5
-                for q in range(-1, nc + 1):
-                    w = 1.0 - np.abs(d64 + q * a)
-                    outside = (q < 0) | (q >= nc)
-                    assert not np.any(outside & (w > 1e-5)), (k, j0, b, q)
-    return lo, hi, seg_len
+                for q in grp:
+                    a, rho = q["a"], q["rho"]
+                    af, slopef = F32(a), F32(q["slope"])
+                    c0 = F32(af - F32(math.copysign(1.0, a)))
+                    ub = l0 * q["slope"] + q["u_first"]
+                    ubase = np.floor(ub)
+                    remv = (ub - ubase - rho).astype(F32)          # u - 1/|a| at the block's first line
+                    v = (r[:nl] * slopef + remv[None]).astype(F32)
+                    i0 = np.floor(v).astype(np.int64) + 1            # first candidate
+                    d0 = (-af * (v - np.floor(v)) + c0).astype(F32)  # its offset t - j, a - sign(a) - a fract(v)
+                    col = (ubase.astype(np.int64) - seg0)[None] + i0
+                    lo, hi = min(lo, int(col.min())), max(hi, int(col.max()) + nc - 1)
+                    # against FP64: the offset of the first candidate, and every position with a hat
+                    # weight above 1e-5 lies among the nc candidates
+                    u64 = ub[None] + r[:nl].astype(np.float64) * q["slope"]
+                    d64 = a * (ubase[None] + i0 - u64)
+                    assert np.max(np.abs(d0 - d64)) < 2e-5
+                    for m in range(-1, nc + 1):
+                        w = 1.0 - np.abs(d64 + m * a)
+                        outside = (m < 0) | (m >= nc)
+                        assert not np.any(outside & (w > 1e-5)), (q["k"], j0, b, m)
+    return lo, hi, seg_len, sum(len(g) == 2 for g in groups)
 
 
 def test_fp_staging_bounds():
@@ -75,13 +115,17 @@ def test_fp_staging_bounds():
               rng.normal(0, .5, 61), 1.0),
              (70, 70, 64, np.arange(50) * math.pi / 50, 30.8, np.zeros(50), 0.7),
              (40, 50, 100, np.arange(33) * math.pi / 33, 50.0, np.zeros(33), 1.6),
-             (5, 3, 7, np.arange(4) * math.pi / 4, 3.0, np.zeros(4), 1.0)]
+             (5, 3, 7, np.arange(4) * math.pi / 4, 3.0, np.zeros(4), 1.0),
+             (1024, 1024, 1024, np.arange(128) * math.pi / 128, 511.5, np.zeros(128), 1.0)]   # TV workload
     # edges of the two classes: 3 candidates for s >= 2 sqrt 2 / 3, 6 for s >= 2 sqrt 2 / 6
     for s in (0.9429, 0.95, 1.0, 0.4715, 0.5, 0.94):
         cases.append((130, 110, 300, rng.uniform(0, 2 * math.pi, 120), 150.3, rng.normal(0, 3, 120), s))
+    paired = 0
     for cs in cases:
-        lo, hi, seg_len = staged_columns(*cs)
+        lo, hi, seg_len, n2 = staged_columns(*cs)
         assert 0 <= lo and hi < seg_len, (cs[:3], cs[6], lo, hi, seg_len)
+        paired += n2
+    assert paired > 100   # most cases pair most of their projections
 
 
 # ------------------------------------------------------------------ fused ROF dual steps
