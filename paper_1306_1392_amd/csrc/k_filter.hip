@@ -321,6 +321,194 @@ __global__ __launch_bounds__(256) void filter_kernel(Tables T, const float *__re
     }
 }
 
+// P = 4096 = 16^3 (2048-bin rows): the same filter with the FFT in registers.  Each of the 256 threads
+// holds 16 points and every pass is a 16-point DFT in registers (two radix-4 stages with constant
+// twiddles) followed by one twiddle multiply; the three passes of each direction exchange data
+// through LDS twice (instead of six radix-4 passes through LDS), and the twiddles come from the
+// plan's table (half circle) once per point and pass.
+//   forward, thread a:        x[a + 256 m] over m -> Y1[a][k1] = w^(a k1) DFT16_m(..)[k1]
+//   forward, thread (k1, c):  Y1[c + 16 d][k1] over d -> Y2[k1][c][b1] = w^(16 c b1) DFT16_d(..)[b1]
+//   forward, thread (k1, b1): Y2[k1][c][b1] over c -> X[k1 + 16 b1 + 256 b2] = DFT16_c(..)[b2]
+// with w = exp(-2 pi i / 4096); the inverse runs the same passes backwards with conjugate twiddles.
+// LDS: Y1 at k1 * 256 + a, Y2 at k1 * 272 + b1 * 17 + c (the pad spreads the stride-17 reads over
+// the banks).  Inside a 16-point DFT, input m sits at register m and output k at register
+// rev4(k) = (k >> 2) | ((k & 3) << 2).
+namespace f16 {
+
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }   // a * (-i)
+
+// 4-point DFT in place, exp(-+2 pi i / 4) per step (INV: inverse, +)
+template <bool INV>
+__device__ __forceinline__ void dft4(float2 &x0, float2 &x1, float2 &x2, float2 &x3)
+{
+    const float2 s02 = x0 + x2, d02 = x0 - x2, s13 = x1 + x3, d13 = x1 - x3;
+    const float2 r = mul_mi(d13);   // -i (x1 - x3)
+    x0 = s02 + s13;
+    x2 = s02 - s13;
+    x1 = INV ? d02 - r : d02 + r;
+    x3 = INV ? d02 + r : d02 - r;
+}
+
+constexpr int rev4(int k) { return (k >> 2) | ((k & 3) << 2); }
+
+// 16-point DFT of v[0..15] (input m at register m); output k at register rev4(k)
+template <bool INV>
+__device__ __forceinline__ void dft16(float2 (&v)[16])
+{
+    // cos / sin of 2 pi e / 16, e = 0..9
+    constexpr float C[10] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f, 0.0f,
+                             -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f, -1.0f,
+                             -0.92387953251128674f};
+    constexpr float S[10] = {0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f, 1.0f,
+                             0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f, 0.0f,
+                             -0.38268343236508977f};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dft4<INV>(v[q], v[q + 4], v[q + 8], v[q + 12]);   // over p, m = q + 4 p
+    // v[q + 4 r] *= exp(-+2 pi i q r / 16)
+#pragma unroll
+    for (int q = 1; q < 4; ++q)
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+            const float c = C[q * r], sn = INV ? S[q * r] : -S[q * r];
+            const float2 a = v[q + 4 * r];
+            v[q + 4 * r] = make_float2(a.x * c - a.y * sn, a.x * sn + a.y * c);
+        }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dft4<INV>(v[4 * r], v[4 * r + 1], v[4 * r + 2], v[4 * r + 3]);   // over q
+    // now X[r + 4 s] sits at register 4 r + s = rev4(r + 4 s)
+}
+
+// exp(-2 pi i e / 4096) for 0 <= e < 4096 from the table exp(-2 pi i m / Pmax), m < Pmax / 2
+__device__ __forceinline__ float2 w4096(const float2 *__restrict__ tw, int e, int sh)
+{
+    const float2 t = tw[(e & 2047) << sh];
+    return (e & 2048) ? make_float2(-t.x, -t.y) : t;
+}
+
+__device__ __forceinline__ float2 twiddle(float2 a, float2 w, bool conj)
+{
+    return conj ? cmulc(a, w) : cmul(a, w);
+}
+
+}  // namespace f16
+
+template <bool RAW>
+__global__ __launch_bounds__(256) void filter4096_kernel(Tables T, const float *__restrict__ sino,
+                                                         const uint16_t *__restrict__ raw,
+                                                         const float *__restrict__ flats, FlatInfo fi,
+                                                         const float *__restrict__ dark, float eps, int R,
+                                                         float *__restrict__ out)
+{
+    using namespace f16;
+    __shared__ float2 z[16 * 272];
+    const int2 pr = T.pairs[blockIdx.x];
+    const SliceDev sd = T.slc[pr.x];
+    const GeoDev &g = T.geo[sd.g];
+    const int K = g.K, nb = g.nb, Lf = g.Lf, pad = g.fpad;
+    const int ka = pr.y, kb = pr.y + 1;
+    const bool hasb = kb < K;
+    const float *hw = T.haw + g.hw_off;
+    const float2 *tw = T.twid;
+    const int sh = T.log2Pmax - 12;
+    const int t = threadIdx.x;
+
+    int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    float aa = 0.0f, ab = 0.0f;
+    if (RAW) {
+        flat_interp(fi, ka, a0, a1, aa);
+        flat_interp(fi, hasb ? kb : ka, b0, b1, ab);
+    }
+    const int r = pr.x;   // raw input: uniform plan, slice index = detector row
+    float2 v[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int n = t + 256 * m;
+        float va = 0.0f, vb = 0.0f;
+        const int jj = n - pad;
+        if (n < Lf && jj >= 0 && jj < nb) {
+            const float w = hw[n];
+            if (RAW) {
+                const float d = dark[(int64_t)r * nb + jj];
+                const float Ia = (float)raw[((int64_t)ka * R + r) * nb + jj];
+                va = norm_value(Ia, d, flats[((int64_t)a0 * R + r) * nb + jj], flats[((int64_t)a1 * R + r) * nb + jj],
+                                aa, eps);
+                if (hasb) {
+                    const float Ib = (float)raw[((int64_t)kb * R + r) * nb + jj];
+                    vb = norm_value(Ib, d, flats[((int64_t)b0 * R + r) * nb + jj],
+                                    flats[((int64_t)b1 * R + r) * nb + jj], ab, eps);
+                }
+            } else {
+                va = sino[sd.sino_off + (int64_t)ka * nb + jj];
+                vb = hasb ? sino[sd.sino_off + (int64_t)kb * nb + jj] : 0.0f;
+            }
+            va *= w;
+            vb *= w;
+        }
+        v[m] = make_float2(va, vb);
+    }
+
+    // forward pass 1 (thread a = t)
+    dft16<false>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) z[k1 * 256 + t] = twiddle(v[rev4(k1)], w4096(tw, t * k1, sh), false);
+    __syncthreads();
+    // forward pass 2 (thread (k1, c))
+    const int hi = t >> 4, lo = t & 15;
+#pragma unroll
+    for (int d = 0; d < 16; ++d) v[d] = z[hi * 256 + lo + 16 * d];
+    dft16<false>(v);
+    __syncthreads();   // every pass-2 read is done before the exchange is overwritten
+#pragma unroll
+    for (int b = 0; b < 16; ++b) z[hi * 272 + b * 17 + lo] = twiddle(v[rev4(b)], w4096(tw, 16 * lo * b, sh), false);
+    __syncthreads();
+    // forward pass 3 (thread (k1, b1)), spectrum (bit-reversed table, 1/P folded), inverse pass 3
+#pragma unroll
+    for (int c = 0; c < 16; ++c) v[c] = z[hi * 272 + lo * 17 + c];
+    dft16<false>(v);
+    const float *H = T.spec + g.spec_off;
+#pragma unroll
+    for (int b2 = 0; b2 < 16; ++b2) {
+        const int k = hi + 16 * lo + 256 * b2;
+        const float h = H[__brev((unsigned)k) >> 20];
+        const float2 x = v[rev4(b2)];
+        v[rev4(b2)] = make_float2(x.x * h, x.y * h);
+    }
+    {
+        float2 u[16];
+#pragma unroll
+        for (int b2 = 0; b2 < 16; ++b2) u[b2] = v[rev4(b2)];
+        dft16<true>(u);
+        __syncthreads();   // every pass-3 read is done
+#pragma unroll
+        for (int c = 0; c < 16; ++c) z[hi * 272 + lo * 17 + c] = u[rev4(c)];
+    }
+    __syncthreads();
+    // inverse pass 2 (thread (k1, c))
+#pragma unroll
+    for (int b = 0; b < 16; ++b) v[b] = twiddle(z[hi * 272 + b * 17 + lo], w4096(tw, 16 * lo * b, sh), true);
+    dft16<true>(v);
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < 16; ++d) z[hi * 256 + lo + 16 * d] = v[rev4(d)];
+    __syncthreads();
+    // inverse pass 1 (thread a = t)
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) v[k1] = twiddle(z[k1 * 256 + t], w4096(tw, t * k1, sh), true);
+    dft16<true>(v);
+    const float wa = T.wang[g.ang_off + ka];
+    const float wb = hasb ? T.wang[g.ang_off + kb] : 0.0f;
+    float *oa = out + sd.filt_off + (int64_t)ka * Lf;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int n = t + 256 * m;
+        if (n < Lf) {
+            const float2 x = v[rev4(m)];
+            oa[n] = wa * x.x;
+            if (hasb) oa[Lf + n] = wb * x.y;
+        }
+    }
+}
+
 FlatInfo make_flats(const double *pos, int n)
 {
     FlatInfo fi{};
@@ -379,6 +567,21 @@ hipError_t launch_filter(const pyhst_plan &p, const float *sino, const uint16_t 
             e = hipFuncSetAttribute((const void *)filter_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)lds);
         if (e != hipSuccess) return e;
+    }
+    bool all4096 = true;
+    for (const auto &g : p.gd) all4096 = all4096 && g.P == 4096;
+    if (all4096) {
+        // 2048-bin rows: the register FFT (the twiddle table covers Pmax >= 4096)
+        if (raw) {
+            filter4096_kernel<true><<<(unsigned)p.n_pairs, 256, 0, st>>>(p.t, nullptr, raw, flats,
+                                                                        make_flats(flat_pos, n_flats), dark, eps,
+                                                                        p.n_slices, filt);
+        } else {
+            FlatInfo none{};
+            filter4096_kernel<false><<<(unsigned)p.n_pairs, 256, 0, st>>>(p.t, sino, nullptr, nullptr, none, nullptr,
+                                                                         0.0f, p.n_slices, filt);
+        }
+        return hipGetLastError();
     }
     if (raw) {
         filter_kernel<true><<<(unsigned)p.n_pairs, 256, lds, st>>>(p.t, nullptr, raw, flats,

@@ -115,6 +115,12 @@ FILTER_CASES = {
     "half_right": dict(nx=96, ny=96, nb=59, K=180, axis=48.0, scan=ph.SCAN_360_HALF),
     "half_left": dict(nx=96, ny=96, nb=59, K=180, axis=10.0, scan=ph.SCAN_360_HALF, overlap=6.0),
     "long_rows": dict(nx=16, ny=16, nb=2500, K=4, axis=1249.5),
+    # FFT length 4096 (the register-FFT filter): full rows, shorter rows, extended half-acquisition rows
+    # on either side, odd projection counts (the last row pair has one row)
+    "rows_2048_oddK": dict(nx=16, ny=16, nb=2048, K=5, axis=1023.5),
+    "rows_1500": dict(nx=16, ny=16, nb=1500, K=4, axis=749.5, jitter=0.1),
+    "half_right_p4096": dict(nx=32, ny=32, nb=600, K=7, axis=590.0, scan=ph.SCAN_360_HALF),
+    "half_left_p4096": dict(nx=32, ny=32, nb=600, K=6, axis=9.0, scan=ph.SCAN_360_HALF, overlap=5.0),
 }
 
 
@@ -183,6 +189,19 @@ def test_fbp_from_raw_parity(dev, graph):
             side.synchronize()
             assert torch.equal(again, eager)
             eager.add_(0.0)     # eager work between replays
+
+
+def test_fbp_from_raw_parity_p4096(dev):
+    """2048-bin rows from raw (normalisation fused into the register-FFT filter, FFT length 4096), an odd
+    number of projections, two slices."""
+    ang, axis, raw, flats, fpos, dark = raw_case(R=2, N=32, K=7, nb=2048)
+    g = ph.Geometry(32, 32, 2048, ang, axis)
+    og = oracle.Geom(32, 32, 2048, ang, axis)
+    plan = ph.Plan(g, n_slices=2)
+    out = ph.reconstruct_slices(plan, raw=raw.to(dev), flats=flats.to(dev), flat_pos=fpos, dark=dark.to(dev),
+                                method=ph.FBP)
+    ref = oracle.fbp_raw(raw.numpy().astype(np.float64), flats.numpy(), fpos, dark.numpy(), og)
+    assert rel(out, ref) <= TOL_PIPE
 
 
 def test_fbp_batch_equals_single(dev, gen):

@@ -220,3 +220,84 @@ def test_prox2_emulation(ny, nx):
         r1, r2 = _step(*_step(a1, a2, g, il, tau), g, il, tau)
         k1, k2 = _fused(p1, p2, g, il, tau, zero)
         assert np.array_equal(k1, r1) and np.array_equal(k2, r2)
+
+
+# ------------------------------------------------------------------ register FFT of the P = 4096 filter
+def _rev4(k):
+    return (k >> 2) | ((k & 3) << 2)
+
+
+def _dft16(v, inv):
+    """filter4096_kernel's 16-point DFT on v[..., 16] (input m at m, output k at rev4(k))."""
+    v = v.copy()
+    s = 1.0 if inv else -1.0
+
+    def dft4(a, b, c, d):
+        s02, d02, s13, d13 = a + c, a - c, b + d, b - d
+        r = -1j * d13
+        return (s02 + s13, d02 - r if inv else d02 + r, s02 - s13, d02 + r if inv else d02 - r)
+    for q in range(4):
+        v[..., q], v[..., q + 4], v[..., q + 8], v[..., q + 12] = dft4(v[..., q], v[..., q + 4], v[..., q + 8],
+                                                                     v[..., q + 12])
+    for q in range(1, 4):
+        for r in range(1, 4):
+            v[..., q + 4 * r] *= np.exp(s * 2j * np.pi * q * r / 16)
+    for r in range(4):
+        v[..., 4 * r], v[..., 4 * r + 1], v[..., 4 * r + 2], v[..., 4 * r + 3] = dft4(
+            v[..., 4 * r], v[..., 4 * r + 1], v[..., 4 * r + 2], v[..., 4 * r + 3])
+    return v
+
+
+def _w4096(tw, e):
+    t = tw[e & 2047]
+    return np.where(e & 2048, -t, t)
+
+
+def test_fft4096_register_emulation():
+    """The three-pass register FFT of filter4096_kernel, replayed with its LDS layout (NaN-initialised,
+    so a read of an unset entry shows), its twiddle-table lookups and the bit-reversed spectrum table,
+    equals ifft(fft(x) H) for a random row pair and a random real spectrum."""
+    rng = np.random.default_rng(3)
+    P = 4096
+    x = rng.standard_normal(P) + 1j * rng.standard_normal(P)
+    Hnat = rng.standard_normal(P)
+    brev = np.array([int(f"{n:012b}"[::-1], 2) for n in range(P)])
+    H = Hnat[brev] / P                                   # the plan's table: bit-reversed, 1/P folded
+    tw = np.exp(-2j * np.pi * np.arange(P // 2) / P)     # half-circle table, Pmax = 4096
+    t = np.arange(256)
+    hi, lo = t >> 4, t & 15
+    z = np.full(16 * 272, np.nan + 0j)
+    v = x[t[:, None] + 256 * np.arange(16)[None, :]]     # thread a holds x[a + 256 m]
+    v = _dft16(v, False)
+    for k1 in range(16):
+        z[k1 * 256 + t] = v[:, _rev4(k1)] * _w4096(tw, t * k1)
+    v = np.stack([z[hi * 256 + lo + 16 * d] for d in range(16)], 1)
+    v = _dft16(v, False)
+    z[:] = np.nan
+    for b in range(16):
+        z[hi * 272 + b * 17 + lo] = v[:, _rev4(b)] * _w4096(tw, 16 * lo * b)
+    v = np.stack([z[hi * 272 + lo * 17 + c] for c in range(16)], 1)
+    v = _dft16(v, False)
+    X = np.empty(P, complex)
+    for b2 in range(16):
+        X[hi + 16 * lo + 256 * b2] = v[:, _rev4(b2)]
+    np.testing.assert_allclose(X, np.fft.fft(x), rtol=0, atol=1e-9 * np.abs(X).max())
+    for b2 in range(16):
+        v[:, _rev4(b2)] *= H[brev[hi + 16 * lo + 256 * b2]]
+    u = _dft16(np.stack([v[:, _rev4(b2)] for b2 in range(16)], 1), True)
+    z[:] = np.nan
+    for c in range(16):
+        z[hi * 272 + lo * 17 + c] = u[:, _rev4(c)]
+    v = np.stack([z[hi * 272 + b * 17 + lo] * np.conj(_w4096(tw, 16 * lo * b)) for b in range(16)], 1)
+    v = _dft16(v, True)
+    z[:] = np.nan
+    for d in range(16):
+        z[hi * 256 + lo + 16 * d] = v[:, _rev4(d)]
+    v = np.stack([z[k1 * 256 + t] * np.conj(_w4096(tw, t * k1)) for k1 in range(16)], 1)
+    v = _dft16(v, True)
+    y = np.empty(P, complex)
+    for m in range(16):
+        y[t + 256 * m] = v[:, _rev4(m)]
+    ref = np.fft.ifft(np.fft.fft(x) * Hnat)
+    assert not np.isnan(y).any()
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-10 * np.abs(ref).max())
