@@ -46,7 +46,7 @@ struct GeoDev {
     int32_t ntx[N_TILE_CFG];  // tiles along x per tile configuration
     int32_t fp_blk_off;       // first forward-projection angle block of this geometry
     int32_t fp_nblk;          // its number of angle blocks
-    int32_t fp_pair_off;      // first staged-projector group (one or two projections) of this geometry
+    int32_t fp_pair_off;      // first staged-projector group (one to FP_SGRP projections) of this geometry
     int32_t fp_npair;         // its number of staged-projector groups
 };
 
@@ -54,9 +54,9 @@ struct GeoDev {
 // whose staged line segments share one LDS segment of FP_SEG positions (see k_fp.hip).
 constexpr int FP_RB = 16, FP_AMAX = 16;
 int fp_seg_len(double s_min);
-// Staged projector (one workgroup per group of one or two projections and 64 bins): positions staged
-// per line for 3 and for 6 candidates per line.
-constexpr int FP_SSEG3 = 128, FP_SSEG6 = 224;
+// Staged projector (one workgroup per group of one to FP_SGRP projections and 64 bins): positions
+// staged per line for 3 and for 6 candidates per line.
+constexpr int FP_SSEG3 = 128, FP_SSEG6 = 224, FP_SGRP = 4;
 // candidates per line for the smallest pixel size s_min: 3, 6, or 0 (counted at run time)
 int fp_nc_for(double s_min);
 
@@ -79,7 +79,7 @@ struct Tables {
     int *counter;                        // persistent work counter
     const int *fp_ang;                   // forward-projection block members: projection index within its geometry
     const int2 *fp_blk;                  // forward-projection blocks: (first member, count)
-    const int2 *fp_pair;                 // staged-projector groups: (projection, second projection or -1)
+    const int4 *fp_pair;                 // staged-projector groups: up to FP_SGRP projections, -1 for none
     int32_t Pmax, log2Pmax;
 };
 
@@ -106,7 +106,7 @@ struct pyhst_plan {
     int64_t sino_elems = 0, filt_elems = 0, img_elems = 0;
     int64_t max_K = 0;
     int n_pairs = 0;
-    int fp_seg = 0, fp_max_blocks = 0, fp_max_pairs = 0;
+    int fp_seg = 0, fp_max_blocks = 0, fp_max_pairs = 0, fp_max_grp = 1;
     int64_t n_items[pyhst::N_TILE_CFG] = {};
     int bp_tile = -1, persistent = 0;
     int fp_kernel = PYHST_FP_AUTO;

@@ -11,7 +11,7 @@
 // i in (u - 1/|a|, u + 1/|a|): at most ceil(2/|a|) of them.
 //
 // Three kernels compute the same sums (up to FP32 rounding order):
-//   fp_staged_kernel  one or two projections per workgroup staged in LDS, whenever the
+//   fp_staged_kernel  one to four projections per workgroup staged in LDS, whenever the
 //                     candidate count per line is fixed (pixels of at least half a bin);
 //   fp_kernel         angle blocks, for smaller pixels on plans with enough blocks to fill
 //                     the chip;
@@ -339,11 +339,11 @@ __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__
     }
 }
 
-// Small problems, pixel size >= 0.5 (NC > 0): one or two projections per workgroup, staged through LDS.
-// The plan pairs neighbouring projections (similar direction) whose candidates share the staged
-// segment; a staged value then serves both.  The workgroup walks the image lines in blocks of FP_RB;
+// Pixel size >= 0.5 (NC > 0): one to FP_SGRP = 4 projections per workgroup, staged through LDS.
+// The plan groups neighbouring projections (similar direction) whose candidates share the staged
+// segment; a staged value then serves all of them.  The workgroup walks the image lines in blocks of FP_RB;
 // the 64 bins of one projection touch, over a block, a segment of at most 63/|a| + (FP_RB - 1)|slope|
-// + 1/|a| + NC + 3 positions of every line (< FpStaged<NC>::SEG; the plan checks the pair's union),
+// + 1/|a| + NC + 3 positions of every line (< FpStaged<NC>::SEG; the plan checks the group's union),
 // which 256 threads stage with 16-wide contiguous reads along the image rows in both walking
 // directions (so a column-walking projection reads rows of 16 neighbouring columns rather than 64
 // separate rows).  The next block is loaded into registers while the current one is summed from the
@@ -456,8 +456,8 @@ __device__ __forceinline__ void fp_staged_body(const Tables &T, const SliceDev &
             base[p] = stage[b & 1] + ((int)ubase - seg_cur) + wv * F::LD;
         }
         if (l0 + FP_RB <= n_lines) {
-            // a whole block: no branch between the lines, so the reads of all of them (and of both
-            // projections) issue together; one partial sum per line, added in line order
+            // a whole block: no branch between the lines, so the reads of all of them (and of every
+            // projection of the group) issue together; one partial sum per line, added in line order
             float part_l[P][FP_RB / 4];
 #pragma unroll
             for (int p = 0; p < P; ++p)
@@ -511,33 +511,44 @@ __device__ __forceinline__ void fp_staged_body(const Tables &T, const SliceDev &
     }
 }
 
-// grid: (bin chunks, staged groups of the geometry with the most, slices); MODE 3: one projection k0
-template <int MODE, int NC, bool UNIT>
+// grid: (bin chunks, staged groups of the geometry with the most, slices); MODE 3: one projection k0.
+// GMAX: the largest group the plan formed, 2 or 4 (the 4-wide build needs more VGPRs, so plans with
+// groups of at most two keep the occupancy of the 2-wide one).
+template <int MODE, int NC, bool UNIT, int GMAX>
 __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *__restrict__ img,
                                                         float *__restrict__ out, float alpha, CpDual cp, int k0)
 {
     __shared__ float stage[2][FP_RB * FpStaged<NC>::LD];
-    __shared__ float part[2][3][64];
+    __shared__ float part[FP_SGRP][3][64];
     const int slice = blockIdx.z;
     const SliceDev sd = T.slc[slice];
     const GeoDev &g = T.geo[sd.g];
     const int j0 = blockIdx.x * 64;
-    int ka = k0, kb = -1;
+    int kk[FP_SGRP] = {k0, -1, -1, -1};
     if (MODE != 3) {
         if ((int)blockIdx.y >= g.fp_npair) return;   // uniform over the workgroup
-        const int2 grp = T.fp_pair[g.fp_pair_off + blockIdx.y];
-        ka = grp.x;
-        kb = grp.y;
+        const int4 grp = T.fp_pair[g.fp_pair_off + blockIdx.y];
+        kk[0] = grp.x;
+        kk[1] = grp.y;
+        kk[2] = grp.z;
+        kk[3] = grp.w;
     } else if (k0 >= g.K) {
         return;
     }
     if (j0 >= g.nb) return;                          // uniform over the workgroup
     const int j = j0 + (int)(threadIdx.x & 63);
-    bool rows, rows_b;
-    StagedProj pr[2];
-    pr[0] = staged_proj(T, g, ka, j, j0, rows);
-    if (kb >= 0) {
-        pr[1] = staged_proj(T, g, kb, j, j0, rows_b);   // same walking axis (the plan pairs only such)
+    const int n = kk[1] < 0 ? 1 : (kk[2] < 0 ? 2 : (kk[3] < 0 ? 3 : 4));   // members (the plan fills in order)
+    bool rows, rows_m;
+    StagedProj pr[FP_SGRP];
+    pr[0] = staged_proj(T, g, kk[0], j, j0, rows);
+#pragma unroll
+    for (int m = 1; m < FP_SGRP; ++m)
+        if (m < n) pr[m] = staged_proj(T, g, kk[m], j, j0, rows_m);   // same walking axis (the plan groups only such)
+    if (GMAX > 2 && n == 4) {   // uniform over the workgroup
+        fp_staged_body<MODE, NC, UNIT, 4>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
+    } else if (GMAX > 2 && n == 3) {
+        fp_staged_body<MODE, NC, UNIT, 3>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
+    } else if (n == 2) {
         fp_staged_body<MODE, NC, UNIT, 2>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
     } else {
         fp_staged_body<MODE, NC, UNIT, 1>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
@@ -565,7 +576,7 @@ hipError_t launch_fp_nc(const pyhst_plan &p, dim3 grid, const float *img, float 
 {
     int kind = p.fp_kernel;
     if (kind == PYHST_FP_AUTO) {
-        // a fixed candidate count: the staged kernel (one or two projections per workgroup), faster
+        // a fixed candidate count: the staged kernel (one to four projections per workgroup), faster
         // than the angle blocks at every measured size; otherwise angle blocks when they give enough
         // workgroups to fill the chip, else one projection per workgroup read from global memory
         const int64_t wgs = (int64_t)grid.x * grid.y * grid.z;
@@ -575,8 +586,12 @@ hipError_t launch_fp_nc(const pyhst_plan &p, dim3 grid, const float *img, float 
     const dim3 g2(grid.x, MODE == 3 ? 1u : (unsigned)p.max_K, grid.z);
     if (kind == PYHST_FP_STAGED) {
         const dim3 gs(grid.x, MODE == 3 ? 1u : (unsigned)p.fp_max_pairs, grid.z);
-        if constexpr (NC > 0)
-            fp_staged_kernel<MODE, NC, UNIT><<<gs, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
+        if constexpr (NC > 0) {
+            if (MODE != 3 && p.fp_max_grp > 2)
+                fp_staged_kernel<MODE, NC, UNIT, 4><<<gs, 256, 0, st>>>(p.t, img, sino, alpha, cp, 0);
+            else
+                fp_staged_kernel<MODE, NC, UNIT, 2><<<gs, 256, 0, st>>>(p.t, img, sino, alpha, cp, MODE == 3 ? k_single : 0);
+        }
         return hipGetLastError();
     }
     if (kind == PYHST_FP_LINES) {

@@ -291,30 +291,31 @@ void build_fp_blocks(const GeoHost &h, const GeoDev &d, int seg, std::vector<int
     }
 }
 
-// Groups of the staged projector: neighbours in the sorted order are paired when, for every 64-bin
-// chunk and FP_RB-line block, the first candidates of both (u - 1/|a| over the chunk's bins and the
-// block's lines) span at most sseg - nc - 5 positions.  The staged kernel starts the segment 2
-// positions below the lowest first candidate and reads nc - 1 positions past the highest, so this
-// keeps every read inside the sseg staged positions with a margin of 2 for FP32 rounding.  Others
-// stay single.  Corners bound the span as in build_fp_blocks.
-void build_fp_pairs(const GeoHost &h, const GeoDev &d, int nc, std::vector<int2> &pairs)
+// Groups of the staged projector: neighbours in the sorted order are grouped greedily (up to
+// FP_SGRP) while, for every 64-bin chunk and FP_RB-line block, the first candidates of all members
+// (u - 1/|a| over the chunk's bins and the block's lines) span at most sseg - nc - 5 positions.  The
+// staged kernel starts the segment 2 positions below the lowest first candidate and reads nc - 1
+// positions past the highest, so this keeps every read inside the sseg staged positions with a
+// margin of 2 for FP32 rounding.  Corners bound the span as in build_fp_blocks.
+void build_fp_groups(const GeoHost &h, const GeoDev &d, int nc, int cap, std::vector<int4> &groups)
 {
     const std::vector<FpAng> v = fp_sorted(h, d);
     const int sseg = nc == 3 ? FP_SSEG3 : FP_SSEG6;
     const int nchunk = (d.nb + 63) / 64;
     const double jc[2] = {0.0, 64.0 * (nchunk - 1)};
-    auto fits = [&](const FpAng &x, const FpAng &y) {
-        if (x.rows != y.rows) return false;
-        const int nl = x.rows ? d.ny : d.nx;
+    auto fits = [&](size_t i, size_t e) {   // members v[i..e]
+        for (size_t m = i + 1; m <= e; ++m)
+            if (v[m].rows != v[i].rows) return false;
+        const int nl = v[i].rows ? d.ny : d.nx;
         const double lc[2] = {0.0, (double)(((nl - 1) / FP_RB) * FP_RB)};
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b) {
                 double lo = 1e300, hi = -1e300;
-                for (const FpAng *z : {&x, &y})
+                for (size_t m = i; m <= e; ++m)
                     for (int cj = 0; cj < 2; ++cj)
                         for (int cl = 0; cl < 2; ++cl) {
-                            const double w = z->U0 + (jc[a] + 63.0 * cj) / z->a +
-                                             z->slope * (lc[b] + (FP_RB - 1) * cl) - z->rho;
+                            const double w = v[m].U0 + (jc[a] + 63.0 * cj) / v[m].a +
+                                             v[m].slope * (lc[b] + (FP_RB - 1) * cl) - v[m].rho;
                             lo = std::min(lo, w);
                             hi = std::max(hi, w);
                         }
@@ -324,13 +325,12 @@ void build_fp_pairs(const GeoHost &h, const GeoDev &d, int nc, std::vector<int2>
     };
     size_t i = 0;
     while (i < v.size()) {
-        if (i + 1 < v.size() && fits(v[i], v[i + 1])) {
-            pairs.push_back(make_int2(v[i].k, v[i + 1].k));
-            i += 2;
-        } else {
-            pairs.push_back(make_int2(v[i].k, -1));
-            i += 1;
-        }
+        size_t e = i;   // last member
+        while (e + 1 < v.size() && e + 1 - i < (size_t)cap && fits(i, e + 1)) ++e;
+        int k[FP_SGRP] = {-1, -1, -1, -1};
+        for (size_t m = i; m <= e; ++m) k[m - i] = v[m].k;
+        groups.push_back(make_int4(k[0], k[1], k[2], k[3]));
+        i = e + 1;
     }
 }
 
@@ -438,17 +438,31 @@ int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_
             d.fp_nblk = (int)blk.size();
             p->fp_max_blocks = std::max(p->fp_max_blocks, d.fp_nblk);
         }
-        // staged-projector groups (the staged kernel needs a fixed candidate count)
+        // staged-projector groups (the staged kernel needs a fixed candidate count): up to FP_SGRP
+        // projections per group, or up to two when bigger groups would leave fewer than 16 workgroups
+        // per compute unit (few slices and angles: then occupancy and balance matter more than reuse)
         const int nc = fp_nc_for(s_min);
-        std::vector<int2> fp_pairs;
-        for (int i = 0; i < n_geom; ++i) {
-            GeoDev &d = p->gd[i];
-            d.fp_pair_off = (int)fp_pairs.size();
-            if (nc > 0) build_fp_pairs(p->gh[i], d, nc, fp_pairs);
-            d.fp_npair = (int)fp_pairs.size() - d.fp_pair_off;
-            p->fp_max_pairs = std::max(p->fp_max_pairs, d.fp_npair);
+        std::vector<int4> fp_pairs;
+        for (int cap : {FP_SGRP, 2}) {
+            fp_pairs.clear();
+            p->fp_max_pairs = 0;
+            for (int i = 0; i < n_geom; ++i) {
+                GeoDev &d = p->gd[i];
+                d.fp_pair_off = (int)fp_pairs.size();
+                if (nc > 0) build_fp_groups(p->gh[i], d, nc, cap, fp_pairs);
+                d.fp_npair = (int)fp_pairs.size() - d.fp_pair_off;
+                p->fp_max_pairs = std::max(p->fp_max_pairs, d.fp_npair);
+            }
+            int64_t wgs = 0;
+            for (int i = 0; i < n_slices; ++i) {
+                const GeoDev &d = p->gd[sg[i]];
+                wgs += (int64_t)((d.nb + 63) / 64) * d.fp_npair;
+            }
+            if (wgs >= 16LL * p->cu_count) break;
         }
-        if (fp_pairs.empty()) fp_pairs.push_back(make_int2(0, -1));   // keeps the table non-empty
+        for (const int4 &q : fp_pairs)
+            p->fp_max_grp = std::max(p->fp_max_grp, q.w >= 0 ? 4 : (q.z >= 0 ? 3 : (q.y >= 0 ? 2 : 1)));
+        if (fp_pairs.empty()) fp_pairs.push_back(make_int4(0, -1, -1, -1));   // keeps the table non-empty
 
         // slices: packed offsets
         p->sd.resize(n_slices);
@@ -511,7 +525,7 @@ int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_
         const size_t o_cnt = take(sizeof(int) * 64);
         const size_t o_fpa = take(sizeof(int) * fp_members.size());
         const size_t o_fpb = take(sizeof(int2) * fp_blocks.size());
-        const size_t o_fpp = take(sizeof(int2) * fp_pairs.size());
+        const size_t o_fpp = take(sizeof(int4) * fp_pairs.size());
         const size_t total = off;
 
         std::vector<unsigned char> hbuf(total, 0);
@@ -564,7 +578,7 @@ int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_
         for (int c = 0; c < N_TILE_CFG; ++c) put(o_items[c], items[c].data(), sizeof(int2) * items[c].size());
         put(o_fpa, fp_members.data(), sizeof(int) * fp_members.size());
         put(o_fpb, fp_blocks.data(), sizeof(int2) * fp_blocks.size());
-        put(o_fpp, fp_pairs.data(), sizeof(int2) * fp_pairs.size());
+        put(o_fpp, fp_pairs.data(), sizeof(int4) * fp_pairs.size());
 
         e = hipMalloc(&p->dev_block, total);
         if (e != hipSuccess) {
@@ -595,7 +609,7 @@ int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_
         t.counter = (int *)(b + o_cnt);
         t.fp_ang = (const int *)(b + o_fpa);
         t.fp_blk = (const int2 *)(b + o_fpb);
-        t.fp_pair = (const int2 *)(b + o_fpp);
+        t.fp_pair = (const int4 *)(b + o_fpp);
         t.Pmax = Pmax;
         t.log2Pmax = lgmax;
         *out = guard.release();

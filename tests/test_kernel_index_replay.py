@@ -1,7 +1,7 @@
 """CPU replays of the index arithmetic of two GPU kernels (host logic, no GPU).
 
-* fp_staged_kernel (one or two projections x 64 bins per workgroup, 16-line blocks staged in LDS;
-  the pairs chosen by the plan's rule, replayed here): every candidate a lane reads lies inside the
+* fp_staged_kernel (one to four projections x 64 bins per workgroup, 16-line blocks staged in LDS;
+  the groups chosen by the plan's rule, replayed here): every candidate a lane reads lies inside the
   staged segment of its line, [0, SEG) with SEG = 128 for three candidates per line and 224 for six,
   over random geometries at the edges of both pixel-size classes.
   The replay follows the kernel's FP64 block anchor and FP32 per-line offsets (first candidate
@@ -31,39 +31,38 @@ def _proj(k, th, s, nx, ny, axis, shift):
     return dict(k=k, rows=rows, sgn=a > 0, a=a, slope=-bb / a, rho=1.0 / abs(a), u_c=u_c, U0=u_c / a)
 
 
-def staged_groups(P, nx, ny, nb, nc):
+def staged_groups(P, nx, ny, nb, nc, cap=4):
     """The plan's staged groups: projections sorted by (walking axis, sign of a, slope); neighbours
-    paired when their first candidates span at most SEG - nc - 5 positions at every corner chunk and
-    line block."""
+    grouped greedily (up to cap: 4, or 2 for plans with few workgroups) while their first candidates
+    span at most SEG - nc - 5 positions at every corner chunk and line block."""
     sseg = 128 if nc == 3 else 224
     v = sorted(P, key=lambda q: (not q["rows"], not q["sgn"], q["slope"]))
     nchunk = (nb + 63) // 64
 
-    def fits(x, y):
-        if x["rows"] != y["rows"]:
+    def fits(grp):
+        if any(z["rows"] != grp[0]["rows"] for z in grp):
             return False
-        nl = ny if x["rows"] else nx
+        nl = ny if grp[0]["rows"] else nx
         for jc in (0.0, 64.0 * (nchunk - 1)):
             for lc in (0.0, float(((nl - 1) // RB) * RB)):
                 w = [z["U0"] + (jc + 63.0 * cj) / z["a"] + z["slope"] * (lc + (RB - 1) * cl) - z["rho"]
-                     for z in (x, y) for cj in (0, 1) for cl in (0, 1)]
+                     for z in grp for cj in (0, 1) for cl in (0, 1)]
                 if max(w) - min(w) + nc + 5 > sseg:
                     return False
         return True
     groups, i = [], 0
     while i < len(v):
-        if i + 1 < len(v) and fits(v[i], v[i + 1]):
-            groups.append((v[i], v[i + 1]))
-            i += 2
-        else:
-            groups.append((v[i],))
-            i += 1
+        e = i
+        while e + 1 < len(v) and e + 1 - i < cap and fits(v[i:e + 2]):
+            e += 1
+        groups.append(tuple(v[i:e + 1]))
+        i = e + 1
     return groups
 
 
-def staged_columns(nx, ny, nb, angles, axis, shifts, s):
+def staged_columns(nx, ny, nb, angles, axis, shifts, s, cap=4):
     """(lowest, highest) LDS column read by fp_staged_kernel, the segment length and the number of
-    paired groups, or None."""
+    projections that share a group with an earlier one, or None."""
     need = math.ceil(2 * math.sqrt(2) / s - 1e-9)
     nc = 3 if need <= 3 else (6 if need <= 6 else 0)
     if nc == 0:
@@ -72,7 +71,7 @@ def staged_columns(nx, ny, nb, angles, axis, shifts, s):
     lo, hi = 10 ** 9, -10 ** 9
     r = np.arange(RB, dtype=F32)[:, None]
     P = [_proj(k, th, s, nx, ny, axis, shifts[k]) for k, th in enumerate(angles)]
-    groups = staged_groups(P, nx, ny, nb, nc)
+    groups = staged_groups(P, nx, ny, nb, nc, cap)
     for grp in groups:
         n_lines = ny if grp[0]["rows"] else nx
         for j0 in range(0, nb, 64):
@@ -105,10 +104,11 @@ def staged_columns(nx, ny, nb, angles, axis, shifts, s):
                         w = 1.0 - np.abs(d64 + m * a)
                         outside = (m < 0) | (m >= nc)
                         assert not np.any(outside & (w > 1e-5)), (q["k"], j0, b, m)
-    return lo, hi, seg_len, sum(len(g) == 2 for g in groups)
+    return lo, hi, seg_len, sum(len(g) - 1 for g in groups)
 
 
-def test_fp_staging_bounds():
+@pytest.mark.parametrize("cap", [2, 4])
+def test_fp_staging_bounds(cap):
     rng = np.random.default_rng(0)
     cases = [(256, 256, 256, np.arange(180) * math.pi / 180, 127.5, np.zeros(180), 1.0),
              (77, 53, 101, np.arange(61) * math.pi / 61 + rng.uniform(-.3, .3, 61) * math.pi / 61, 49.3,
@@ -122,10 +122,10 @@ def test_fp_staging_bounds():
         cases.append((130, 110, 300, rng.uniform(0, 2 * math.pi, 120), 150.3, rng.normal(0, 3, 120), s))
     paired = 0
     for cs in cases:
-        lo, hi, seg_len, n2 = staged_columns(*cs)
+        lo, hi, seg_len, n2 = staged_columns(*cs, cap=cap)
         assert 0 <= lo and hi < seg_len, (cs[:3], cs[6], lo, hi, seg_len)
         paired += n2
-    assert paired > 100   # most cases pair most of their projections
+    assert paired > 100   # most cases group most of their projections
 
 
 # ------------------------------------------------------------------ fused ROF dual steps
