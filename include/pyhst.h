@@ -125,12 +125,12 @@ int pyhst_plan_get_tiles(const pyhst_plan *plan, int32_t *bp_tile, int32_t *pers
  * PYHST_FP_STAGED for pixel sizes >= 0.5; for smaller pixels, angle blocks when
  * they give at least 8 workgroups per compute unit, else PYHST_FP_LINES;
  * PYHST_FP_BLOCKS: up to 16 projections of similar direction per workgroup
- * sharing LDS-staged line segments; PYHST_FP_STAGED: one projection, or two
- * neighbouring ones whose candidates share the segment, per workgroup, line
- * segments staged in LDS (pixel size >= 0.5 only: smaller pixels take
- * PYHST_FP_LINES); PYHST_FP_LINES: one projection per workgroup read straight
- * from global memory.  All compute the same sums up to FP32 rounding order.
- * EARG for another value. */
+ * sharing LDS-staged line segments; PYHST_FP_STAGED: one to four neighbouring
+ * projections whose candidates share the segment per workgroup, line segments
+ * staged in LDS (pixel size >= 0.5 only: smaller pixels take PYHST_FP_LINES);
+ * PYHST_FP_LINES: one projection per workgroup read straight from global
+ * memory.  All compute the same sums up to FP32 rounding order.  EARG for
+ * another value. */
 int pyhst_plan_set_fp_kernel(pyhst_plan *plan, int32_t kind);
 int pyhst_plan_get_fp_kernel(const pyhst_plan *plan, int32_t *kind);
 /* Autotuner: times the backprojector of this plan for every tile shape, with

@@ -430,3 +430,26 @@ def test_fista_beats_ista_and_recovers_disc(dev):
     yy, xx = np.mgrid[0:N, 0:N]
     inside = (xx - (N - 1) / 2) ** 2 + (yy - (N - 1) / 2) ** 2 < (0.4 * N / 2) ** 2
     assert abs(xf[0].cpu().numpy()[inside].mean() - 1.0) < 0.03
+
+
+def test_fp_groups_of_four_parity(dev, gen):
+    """A plan big enough for the staged projector's groups of four (8 slices x 256^2 x 720 angles with
+    axis shifts: about 5800 workgroups, at least 16 per CU): the plain projection of every slice, and
+    two Chambolle-Pock iterations (dual update fused into the projector) of the first two slices,
+    against the oracle."""
+    import test_kernel_index_replay as rp
+    N, K, S = 256, 720, 8
+    g, og = pair(nx=N, ny=N, nb=N, K=K, axis=128.2, shifts=0.3)
+    # the plan's grouping rule, replayed: groups of up to four and enough workgroups to keep them
+    P = [rp._proj(k, th, 1.0, N, N, og.axis, og.shifts[k]) for k, th in enumerate(og.angles)]
+    groups = rp.staged_groups(P, N, N, N, 3, cap=4)
+    assert max(len(q) for q in groups) == 4 and S * (N // 64) * len(groups) >= 16 * 256
+    plan = ph.Plan(g, n_slices=S)
+    x = gen.standard_normal((S, N, N)).astype(np.float32)
+    out = ph.forward_project(plan, torch.from_numpy(x).to(dev))
+    assert rel(out, oracle.forward_project(x, og)) <= TOL_OP
+    y = gen.standard_normal((S, K, N)).astype(np.float32)
+    xs = ph.reconstruct_slices(plan, sino=torch.from_numpy(y).to(dev), method=ph.TV_CP, lam=0.01, n_iter=2,
+                               op_norm=400.0)
+    for s in range(2):
+        assert rel(xs[s], oracle.cp_tv(y[s], og, 0.01, 2, 400.0)) <= TOL_PIPE, s
