@@ -48,6 +48,7 @@ struct GeoDev {
     int32_t fp_nblk;          // its number of angle blocks
     int32_t fp_pair_off;      // first staged-projector group (one to FP_SGRP projections) of this geometry
     int32_t fp_npair;         // its number of staged-projector groups
+    int32_t half, pad2;       // 1: 360-degree half acquisition (weights other than 1 in the filter load)
 };
 
 // Forward projection: projections of one geometry grouped into blocks of at most FP_AMAX

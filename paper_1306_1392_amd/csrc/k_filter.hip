@@ -324,8 +324,9 @@ __global__ __launch_bounds__(256) void filter_kernel(Tables T, const float *__re
 // P = 4096 = 16^3 (2048-bin rows): the same filter with the FFT in registers.  Each of the 256 threads
 // holds 16 points and every pass is a 16-point DFT in registers (two radix-4 stages with constant
 // twiddles) followed by one twiddle multiply; the three passes of each direction exchange data
-// through LDS twice (instead of six radix-4 passes through LDS), and the twiddles come from the
-// plan's table (half circle) once per point and pass.
+// through LDS twice (instead of six radix-4 passes through LDS).  The twiddles are products of
+// eight values of the plan's table (half circle) per thread, loaded once: the kernel is bound by
+// the latency of its global loads, not by arithmetic.
 //   forward, thread a:        x[a + 256 m] over m -> Y1[a][k1] = w^(a k1) DFT16_m(..)[k1]
 //   forward, thread (k1, c):  Y1[c + 16 d][k1] over d -> Y2[k1][c][b1] = w^(16 c b1) DFT16_d(..)[b1]
 //   forward, thread (k1, b1): Y2[k1][c][b1] over c -> X[k1 + 16 b1 + 256 b2] = DFT16_c(..)[b2]
@@ -390,6 +391,21 @@ __device__ __forceinline__ float2 twiddle(float2 a, float2 w, bool conj)
     return conj ? cmulc(a, w) : cmul(a, w);
 }
 
+// w^k, 0 <= k < 16, from the bases w, w^2, w^4, w^8 (table values): a product of at most four of
+// them, so each twiddle stays within a few FP32 roundings of the table (k is a constant once unrolled)
+__device__ __forceinline__ float2 wpow(const float2 (&b)[4], int k)
+{
+    float2 r = make_float2(1.0f, 0.0f);
+    bool first = true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if ((k >> i) & 1) {
+            r = first ? b[i] : cmul(r, b[i]);
+            first = false;
+        }
+    return r;
+}
+
 }  // namespace f16
 
 template <bool RAW>
@@ -419,6 +435,8 @@ __global__ __launch_bounds__(256) void filter4096_kernel(Tables T, const float *
         flat_interp(fi, hasb ? kb : ka, b0, b1, ab);
     }
     const int r = pr.x;   // raw input: uniform plan, slice index = detector row
+    const bool half = g.half != 0;
+    const bool same_flats = a0 == b0 && a1 == b1;   // both rows between the same two flats (uniform)
     float2 v[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
@@ -426,16 +444,17 @@ __global__ __launch_bounds__(256) void filter4096_kernel(Tables T, const float *
         float va = 0.0f, vb = 0.0f;
         const int jj = n - pad;
         if (n < Lf && jj >= 0 && jj < nb) {
-            const float w = hw[n];
+            const float w = half ? hw[n] : 1.0f;
             if (RAW) {
                 const float d = dark[(int64_t)r * nb + jj];
                 const float Ia = (float)raw[((int64_t)ka * R + r) * nb + jj];
-                va = norm_value(Ia, d, flats[((int64_t)a0 * R + r) * nb + jj], flats[((int64_t)a1 * R + r) * nb + jj],
-                                aa, eps);
+                const float fa0 = flats[((int64_t)a0 * R + r) * nb + jj], fa1 = flats[((int64_t)a1 * R + r) * nb + jj];
+                va = norm_value(Ia, d, fa0, fa1, aa, eps);
                 if (hasb) {
                     const float Ib = (float)raw[((int64_t)kb * R + r) * nb + jj];
-                    vb = norm_value(Ib, d, flats[((int64_t)b0 * R + r) * nb + jj],
-                                    flats[((int64_t)b1 * R + r) * nb + jj], ab, eps);
+                    const float fb0 = same_flats ? fa0 : flats[((int64_t)b0 * R + r) * nb + jj];
+                    const float fb1 = same_flats ? fa1 : flats[((int64_t)b1 * R + r) * nb + jj];
+                    vb = norm_value(Ib, d, fb0, fb1, ab, eps);
                 }
             } else {
                 va = sino[sd.sino_off + (int64_t)ka * nb + jj];
@@ -447,19 +466,26 @@ __global__ __launch_bounds__(256) void filter4096_kernel(Tables T, const float *
         v[m] = make_float2(va, vb);
     }
 
+    // twiddle bases: w^(t k1) and w^(16 c b1) are products of these (w = exp(-2 pi i / 4096))
+    const int hi = t >> 4, lo = t & 15;
+    float2 b1w[4], b2w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        b1w[i] = w4096(tw, t << i, sh);
+        b2w[i] = w4096(tw, (16 * lo) << i, sh);
+    }
     // forward pass 1 (thread a = t)
     dft16<false>(v);
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) z[k1 * 256 + t] = twiddle(v[rev4(k1)], w4096(tw, t * k1, sh), false);
+    for (int k1 = 0; k1 < 16; ++k1) z[k1 * 256 + t] = twiddle(v[rev4(k1)], wpow(b1w, k1), false);
     __syncthreads();
     // forward pass 2 (thread (k1, c))
-    const int hi = t >> 4, lo = t & 15;
 #pragma unroll
     for (int d = 0; d < 16; ++d) v[d] = z[hi * 256 + lo + 16 * d];
     dft16<false>(v);
     __syncthreads();   // every pass-2 read is done before the exchange is overwritten
 #pragma unroll
-    for (int b = 0; b < 16; ++b) z[hi * 272 + b * 17 + lo] = twiddle(v[rev4(b)], w4096(tw, 16 * lo * b, sh), false);
+    for (int b = 0; b < 16; ++b) z[hi * 272 + b * 17 + lo] = twiddle(v[rev4(b)], wpow(b2w, b), false);
     __syncthreads();
     // forward pass 3 (thread (k1, b1)), spectrum (bit-reversed table, 1/P folded), inverse pass 3
 #pragma unroll
@@ -485,7 +511,7 @@ __global__ __launch_bounds__(256) void filter4096_kernel(Tables T, const float *
     __syncthreads();
     // inverse pass 2 (thread (k1, c))
 #pragma unroll
-    for (int b = 0; b < 16; ++b) v[b] = twiddle(z[hi * 272 + b * 17 + lo], w4096(tw, 16 * lo * b, sh), true);
+    for (int b = 0; b < 16; ++b) v[b] = twiddle(z[hi * 272 + b * 17 + lo], wpow(b2w, b), true);
     dft16<true>(v);
     __syncthreads();
 #pragma unroll
@@ -493,7 +519,7 @@ __global__ __launch_bounds__(256) void filter4096_kernel(Tables T, const float *
     __syncthreads();
     // inverse pass 1 (thread a = t)
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) v[k1] = twiddle(z[k1 * 256 + t], w4096(tw, t * k1, sh), true);
+    for (int k1 = 0; k1 < 16; ++k1) v[k1] = twiddle(z[k1 * 256 + t], wpow(b1w, k1), true);
     dft16<true>(v);
     const float wa = T.wang[g.ang_off + ka];
     const float wb = hasb ? T.wang[g.ang_off + kb] : 0.0f;

@@ -393,6 +393,7 @@ int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_
             d.ang_off = nang;
             nang += d.K;
             d.hw_off = nhw;
+            d.half = h.g.scan == PYHST_SCAN_360_HALF ? 1 : 0;
             nhw += h.Lf;
             auto key = std::make_pair(h.Lf, h.P);
             auto it = spec_cache.find(key);

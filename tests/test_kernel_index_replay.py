@@ -253,9 +253,19 @@ def _w4096(tw, e):
     return np.where(e & 2048, -t, t)
 
 
+def _wpow(bases, k):
+    """w^k from the bases w, w^2, w^4, w^8, as the kernel forms its twiddles."""
+    r = np.ones_like(bases[0])
+    for i in range(4):
+        if (k >> i) & 1:
+            r = r * bases[i]
+    return r
+
+
 def test_fft4096_register_emulation():
     """The three-pass register FFT of filter4096_kernel, replayed with its LDS layout (NaN-initialised,
-    so a read of an unset entry shows), its twiddle-table lookups and the bit-reversed spectrum table,
+    so a read of an unset entry shows), its twiddles (products of eight table values per thread) and
+    the bit-reversed spectrum table,
     equals ifft(fft(x) H) for a random row pair and a random real spectrum."""
     rng = np.random.default_rng(3)
     P = 4096
@@ -266,16 +276,18 @@ def test_fft4096_register_emulation():
     tw = np.exp(-2j * np.pi * np.arange(P // 2) / P)     # half-circle table, Pmax = 4096
     t = np.arange(256)
     hi, lo = t >> 4, t & 15
+    b1w = [_w4096(tw, t << i) for i in range(4)]          # twiddle bases, loaded once per thread
+    b2w = [_w4096(tw, (16 * lo) << i) for i in range(4)]
     z = np.full(16 * 272, np.nan + 0j)
     v = x[t[:, None] + 256 * np.arange(16)[None, :]]     # thread a holds x[a + 256 m]
     v = _dft16(v, False)
     for k1 in range(16):
-        z[k1 * 256 + t] = v[:, _rev4(k1)] * _w4096(tw, t * k1)
+        z[k1 * 256 + t] = v[:, _rev4(k1)] * _wpow(b1w, k1)
     v = np.stack([z[hi * 256 + lo + 16 * d] for d in range(16)], 1)
     v = _dft16(v, False)
     z[:] = np.nan
     for b in range(16):
-        z[hi * 272 + b * 17 + lo] = v[:, _rev4(b)] * _w4096(tw, 16 * lo * b)
+        z[hi * 272 + b * 17 + lo] = v[:, _rev4(b)] * _wpow(b2w, b)
     v = np.stack([z[hi * 272 + lo * 17 + c] for c in range(16)], 1)
     v = _dft16(v, False)
     X = np.empty(P, complex)
@@ -288,12 +300,12 @@ def test_fft4096_register_emulation():
     z[:] = np.nan
     for c in range(16):
         z[hi * 272 + lo * 17 + c] = u[:, _rev4(c)]
-    v = np.stack([z[hi * 272 + b * 17 + lo] * np.conj(_w4096(tw, 16 * lo * b)) for b in range(16)], 1)
+    v = np.stack([z[hi * 272 + b * 17 + lo] * np.conj(_wpow(b2w, b)) for b in range(16)], 1)
     v = _dft16(v, True)
     z[:] = np.nan
     for d in range(16):
         z[hi * 256 + lo + 16 * d] = v[:, _rev4(d)]
-    v = np.stack([z[k1 * 256 + t] * np.conj(_w4096(tw, t * k1)) for k1 in range(16)], 1)
+    v = np.stack([z[k1 * 256 + t] * np.conj(_wpow(b1w, k1)) for k1 in range(16)], 1)
     v = _dft16(v, True)
     y = np.empty(P, complex)
     for m in range(16):
