@@ -187,6 +187,10 @@ __global__ __launch_bounds__(256) void ring_subtract_kernel(float *__restrict__ 
     p[((int64_t)s * K + k) * L + j] -= (float)hp[(int64_t)s * L + j];
 }
 
+__device__ inline float2 times_mi(float2 a) { return make_float2(a.y, -a.x); }   // a * (-i)
+
+// One table load per radix-4 butterfly: of its three twiddles w^i, w^(i + h/2), w^(2i) (w a root of
+// unity of order 2h), the second is the first times -i exactly and the third is its square.
 __device__ void fft_forward(float2 *z, int P, int lg, const float2 *__restrict__ tw, int lgmax)
 {
     int h = P >> 1, lh = lg - 1;
@@ -197,8 +201,8 @@ __device__ void fft_forward(float2 *z, int P, int lg, const float2 *__restrict__
             const int b0 = (gq << (lh + 1)) + i;
             const float2 e0 = z[b0], e1 = z[b0 + h2], e2 = z[b0 + h], e3 = z[b0 + h + h2];
             const float2 w0 = tw[i << (lgmax - lh - 1)];
-            const float2 w1 = tw[(i + h2) << (lgmax - lh - 1)];
-            const float2 w2 = tw[i << (lgmax - lh)];
+            const float2 w1 = times_mi(w0);
+            const float2 w2 = cmul(w0, w0);
             const float2 s0 = e0 + e2, d0 = cmul(e0 - e2, w0);
             const float2 s1 = e1 + e3, d1 = cmul(e1 - e3, w1);
             z[b0] = s0 + s1;
@@ -238,11 +242,12 @@ __device__ void fft_inverse(float2 *z, int P, int lg, const float2 *__restrict__
             const int gq = t >> lh, i = t & (h - 1);
             const int b0 = (gq << (lh + 2)) + i;
             const float2 e0 = z[b0], e1 = z[b0 + h], e2 = z[b0 + 2 * h], e3 = z[b0 + 3 * h];
-            const float2 w = tw[i << (lgmax - lh - 1)];
+            const float2 u = tw[i << (lgmax - lh - 2)];   // u^i of order 4h: w = u^2, u^(i + h) = -i u^i
+            const float2 w = cmul(u, u);
             const float2 b1 = cmulc(e1, w), b3 = cmulc(e3, w);
             const float2 s0 = e0 + b1, d0 = e0 - b1, s1 = e2 + b3, d1 = e2 - b3;
-            const float2 t1 = cmulc(s1, tw[i << (lgmax - lh - 2)]);
-            const float2 t2 = cmulc(d1, tw[(i + h) << (lgmax - lh - 2)]);
+            const float2 t1 = cmulc(s1, u);
+            const float2 t2 = cmulc(d1, times_mi(u));
             z[b0] = s0 + t1;
             z[b0 + 2 * h] = s0 - t1;
             z[b0 + h] = d0 + t2;
@@ -277,20 +282,23 @@ __global__ __launch_bounds__(256) void filter_kernel(Tables T, const float *__re
         flat_interp(fi, hasb ? kb : ka, b0, b1, ab);
     }
     const int r = pr.x;   // raw input: uniform plan, slice index = detector row
+    const bool half = g.half != 0;
+    const bool same_flats = a0 == b0 && a1 == b1;   // both rows between the same two flats (uniform)
     for (int n = threadIdx.x; n < P; n += blockDim.x) {
         float va = 0.0f, vb = 0.0f;
         const int jj = n - pad;
         if (n < Lf && jj >= 0 && jj < nb) {
-            const float w = hw[n];
+            const float w = half ? hw[n] : 1.0f;
             if (RAW) {
                 const float d = dark[(int64_t)r * nb + jj];
                 const float Ia = (float)raw[((int64_t)ka * R + r) * nb + jj];
-                va = norm_value(Ia, d, flats[((int64_t)a0 * R + r) * nb + jj], flats[((int64_t)a1 * R + r) * nb + jj],
-                                aa, eps);
+                const float fa0 = flats[((int64_t)a0 * R + r) * nb + jj], fa1 = flats[((int64_t)a1 * R + r) * nb + jj];
+                va = norm_value(Ia, d, fa0, fa1, aa, eps);
                 if (hasb) {
                     const float Ib = (float)raw[((int64_t)kb * R + r) * nb + jj];
-                    vb = norm_value(Ib, d, flats[((int64_t)b0 * R + r) * nb + jj],
-                                    flats[((int64_t)b1 * R + r) * nb + jj], ab, eps);
+                    const float fb0 = same_flats ? fa0 : flats[((int64_t)b0 * R + r) * nb + jj];
+                    const float fb1 = same_flats ? fa1 : flats[((int64_t)b1 * R + r) * nb + jj];
+                    vb = norm_value(Ib, d, fb0, fb1, ab, eps);
                 }
             } else {
                 va = sino[sd.sino_off + (int64_t)ka * nb + jj];
