@@ -729,7 +729,7 @@ def learned_data(indices, stream, plan_hi, plan_b, N, K, B, dev):
 
 def run_learned(args):
     """Learned sparse-angle corrector: U-Net (4 levels, 32 base) trained on ellipse + Perlin
-    phantoms (512^2, 90 projections, Poisson 1e4) by the library's own MFMA kernels, judged
+    phantoms (512^2, 90 projections, Poisson 1e4) by the library's own MFMA kernels, compared
     against TV (the better of Chambolle-Pock and FISTA, 300 iterations, lambda calibrated on
     validation phantoms) on test phantoms."""
     import numpy as np
@@ -784,10 +784,10 @@ def run_learned(args):
             out[i:i + B] = net.forward(xi) / SCALE
         return out
 
-    # TV judge.  Both TV solvers (Chambolle-Pock, and the paper's FISTA with 10 inner prox steps), 300
+    # TV reference.  Both TV solvers (Chambolle-Pock, and the paper's FISTA with 10 inner prox steps), 300
     # iterations each; lambda by minimum RMSE on the validation phantoms (ground-truth calibration,
     # section 3.1) over a half-decade grid widened until the minimum is interior.  The solver with the
-    # lower validation RMSE is the judge.
+    # lower validation RMSE is the reference.
     plan_va = ph.Plan(geo, n_slices=yva.shape[0])
     plan_te = ph.Plan(geo, n_slices=yte.shape[0])
     solvers = {"cp": ph.TV_CP, "fista": ph.FISTA}
@@ -820,8 +820,8 @@ def run_learned(args):
                                      n_inner=10)
         tvres[name] = {"method": meth, "lambda": lam, "op_norm": norm, "val_rmse": cal[lam], "test_rmse": rmse(x_tv, tte),
                        "calibration": {str(k): v for k, v in sorted(cal.items())}}
-    judge = min(tvres, key=lambda k: tvres[k]["val_rmse"])
-    J = tvres[judge]
+    ref = min(tvres, key=lambda k: tvres[k]["val_rmse"])
+    J = tvres[ref]
     # data-consistency threshold of the corrector: 1.5 x the 95th percentile on validation
     corr = Corrector(geo, B, params, tv_lambda=J["lambda"], tv_iters=300, tv_method=J["method"])
     corr.op_norm = J["op_norm"]
@@ -837,7 +837,7 @@ def run_learned(args):
     # test set: FBP, FBP + CNN, TV
     x_cnn = cnn_apply(xte)
     r_fbp, r_cnn, r_tv = rmse(xte, tte), rmse(x_cnn, tte), J["test_rmse"]
-    # throughput: FBP + CNN in batches of 32 vs the TV judge (300 iterations) on the whole test batch
+    # throughput: FBP + CNN in batches of 32 vs the TV reference (300 iterations) on the whole test batch
     stream = torch.cuda.current_stream()
     e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     out = torch.empty((B, N, N), device=dev)
@@ -864,9 +864,9 @@ def run_learned(args):
            "data": "synthetic",
            "config": {"workload": f"ellipse+Perlin phantoms {N}^2, {K} angles, Poisson 1e4; train "
                                   f"{args.learned_train} x {args.learned_epochs} epochs, batch {B}; test "
-                                  f"{args.learned_test}; TV judge: best of Chambolle-Pock and FISTA, 300 "
+                                  f"{args.learned_test}; TV reference: best of Chambolle-Pock and FISTA, 300 "
                                   f"iterations, calibrated lambda"},
-           "rmse": {"fbp": r_fbp, "cnn": r_cnn, "tv": r_tv}, "tv_judge": judge, "tv_solvers": tvres,
+           "rmse": {"fbp": r_fbp, "cnn": r_cnn, "tv": r_tv}, "tv_reference": ref, "tv_solvers": tvres,
            "slices_per_s": {"fbp_cnn": round(sps_cnn, 1), "tv": round(sps_tv, 2),
                             "ratio": round(sps_cnn / sps_tv, 1)},
            "pass": {"rmse_within_5pct_of_tv": r_cnn <= 1.05 * r_tv, "speed_20x": sps_cnn >= 20 * sps_tv,
