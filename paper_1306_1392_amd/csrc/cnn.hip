@@ -283,19 +283,27 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const float *part, int
 // dst[n * M + m] = sum_s part[s][m][n].  A workgroup takes 64 consecutive outputs i = m N + n; its
 // 4 wavefronts sum the splits s = w, w + 4, ... (consecutive lanes read consecutive n) and the 4
 // partial sums are added in a fixed order.
-__global__ __launch_bounds__(256) void reduce_splitk_T_kernel(const float *part, int splits, int M, int N, float *dst)
+// 64 outputs per workgroup, its 16 wavefronts take every 16th split (the weight-gradient GEMMs of the
+// narrow layers have few outputs and many splits: the waves keep enough loads in flight); the 16
+// partial sums are added in a fixed order
+constexpr int RSK_WAVES = 16;
+__global__ __launch_bounds__(64 * RSK_WAVES) void reduce_splitk_T_kernel(const float *part, int splits, int M, int N,
+                                                                         float *dst)
 {
-    __shared__ double red[4][64];
+    __shared__ double red[RSK_WAVES][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * 64 + lane, MN = (int64_t)M * N;
     double s = 0.0;
     if (i < MN)
-        for (int k = w; k < splits; k += 4) s += part[(int64_t)k * MN + i];
+        for (int k = w; k < splits; k += RSK_WAVES) s += part[(int64_t)k * MN + i];
     red[w][lane] = s;
     __syncthreads();
     if (w == 0 && i < MN) {
+        double t = red[0][lane];
+#pragma unroll
+        for (int q = 1; q < RSK_WAVES; ++q) t += red[q][lane];
         const int m = (int)(i / N), n = (int)(i - (int64_t)m * N);
-        dst[(int64_t)n * M + m] = (float)(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
+        dst[(int64_t)n * M + m] = (float)t;
     }
 }
 
@@ -416,7 +424,7 @@ hipError_t conv_bwd(const pyhst_unet &net, const Conv &L, Act x, Act dz, bf16_t 
         if (tn == 128) gemm_kernel<Im2colT, PlainT, StorePartial, 128, TM, TKW><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
         else if (tn == 64) gemm_kernel<Im2colT, PlainT, StorePartial, 64, TM, TKW><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
         else gemm_kernel<Im2colT, PlainT, StorePartial, 32, TM, TKW><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
-        reduce_splitk_T_kernel<<<(unsigned)(((int64_t)M * N + 63) / 64), 256, 0, st>>>(net.part, sp, M, N, net.grads + L.w);
+        reduce_splitk_T_kernel<<<(unsigned)(((int64_t)M * N + 63) / 64), 64 * RSK_WAVES, 0, st>>>(net.part, sp, M, N, net.grads + L.w);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = chan_sum(net, dz, L.cout, nullptr, net.grads + L.b, st)) != hipSuccess) return e;
@@ -453,7 +461,7 @@ hipError_t up_bwd(const pyhst_unet &net, const Up &L, Act x, Act dy, bf16_t *dx,
         if (tn == 128) gemm_kernel<PlainT, UpGatherT, StorePartial, 128, TM, TKW><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
         else if (tn == 64) gemm_kernel<PlainT, UpGatherT, StorePartial, 64, TM, TKW><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
         else gemm_kernel<PlainT, UpGatherT, StorePartial, 32, TM, TKW><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
-        reduce_splitk_T_kernel<<<(unsigned)(((int64_t)M * N + 63) / 64), 256, 0, st>>>(net.part, sp, M, N, net.grads + L.w);
+        reduce_splitk_T_kernel<<<(unsigned)(((int64_t)M * N + 63) / 64), 64 * RSK_WAVES, 0, st>>>(net.part, sp, M, N, net.grads + L.w);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = chan_sum(net, dy, L.cout, nullptr, net.grads + L.b, st)) != hipSuccess) return e;
