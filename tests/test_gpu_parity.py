@@ -435,8 +435,8 @@ def test_fista_beats_ista_and_recovers_disc(dev):
 def test_fp_groups_of_four_parity(dev, gen):
     """A plan big enough for the staged projector's groups of four (8 slices x 256^2 x 720 angles with
     axis shifts: about 5800 workgroups, at least 16 per CU): the plain projection of every slice, and
-    two Chambolle-Pock iterations (dual update fused into the projector) of the first two slices,
-    against the oracle."""
+    two Chambolle-Pock iterations (dual update fused into the projector) and two FISTA iterations
+    (residual in the projector's epilogue) of the first two slices, against the oracle."""
     import test_kernel_index_replay as rp
     N, K, S = 256, 720, 8
     g, og = pair(nx=N, ny=N, nb=N, K=K, axis=128.2, shifts=0.3)
@@ -453,3 +453,8 @@ def test_fp_groups_of_four_parity(dev, gen):
                                op_norm=400.0)
     for s in range(2):
         assert rel(xs[s], oracle.cp_tv(y[s], og, 0.01, 2, 400.0)) <= TOL_PIPE, s
+    # FISTA: the residual A x - y computed in the projector's epilogue
+    xf = ph.reconstruct_slices(plan, sino=torch.from_numpy(y).to(dev), method=ph.FISTA, lam=0.5, n_iter=2,
+                               op_norm=400.0, n_inner=4)
+    for s in range(2):
+        assert rel(xf[s], oracle.fista_tv(y[s], og, 0.5, 2, 400.0 ** 2, 4, fast=True)) <= TOL_PIPE, s
