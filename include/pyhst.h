@@ -28,10 +28,14 @@
  *     return; outputs are valid once the stream reaches that point.
  *   - Once a plan exists no entry point allocates device memory; scratch is
  *     passed in by the caller (tv_prox, reconstruct_slices).
- *   - A plan is immutable after creation except for its tile choice
- *     (pyhst_plan_set_tiles) and the work counter used by uneven batches: two
- *     calls on one plan may run concurrently on different streams only if the
- *     plan is uniform (one geometry).
+ *   - A plan is immutable after creation except for its tile and projector
+ *     choices (pyhst_plan_set_tiles, pyhst_plan_set_fp_kernel, not to be called
+ *     while other calls use the plan) and its caches (graphs, stream slots),
+ *     which are guarded by a lock.  Calls on one plan may run concurrently on
+ *     different streams when each has its own output and work buffers; the
+ *     persistent backprojector's work counter belongs to the stream (a graph
+ *     captured on one stream must not be replayed concurrently with itself or
+ *     with other calls of that stream on another stream).
  *
  * Errors: every entry point returns PYHST_OK (0) or a negative code; no C++
  * exception or abort crosses the ABI.  pyhst_last_error() gives the message of
@@ -55,7 +59,7 @@ enum {
                           axis that is not in the outer quarter of the detector (section 2.1) */
     PYHST_ENOMEM = -3, /* device allocation failed at plan creation, or work buffer too small */
     PYHST_EHIP = -4,   /* a HIP runtime error; see pyhst_last_error() */
-    PYHST_ENUM = -5    /* non-finite energy in an iterative reconstruction */
+    PYHST_ENUM = -5    /* non-finite or zero estimate (pyhst_opnorm, pyhst_patch_lipschitz) */
 };
 
 enum { PYHST_SCAN_180 = 0, PYHST_SCAN_360 = 1, PYHST_SCAN_360_HALF = 2 };
@@ -66,6 +70,10 @@ enum { PYHST_MAX_SLICES = 65535 };
  * reconstruct_slices call with use_graph: method, buffers, stream, parameters);
  * once it holds them, further distinct calls run as plain launches. */
 enum { PYHST_MAX_GRAPHS = 64 };
+/* Persistent backprojection (pyhst_plan_set_tiles) takes its work counter from a
+ * per-plan slot owned by the calling stream; a plan has this many slots, and a
+ * call on a further stream runs the non-persistent kernel instead. */
+enum { PYHST_MAX_STREAMS = 64 };
 /* Forward-projector kernels (pyhst_plan_set_fp_kernel). */
 enum { PYHST_FP_AUTO = 0, PYHST_FP_BLOCKS = 1, PYHST_FP_STAGED = 2, PYHST_FP_LINES = 3 };
 
@@ -159,10 +167,15 @@ int pyhst_normalize(const pyhst_plan *plan, const uint16_t *raw, const float *fl
  * pixel whose 3x3 neighbours' median (the up to 8 neighbours inside the rows
  * and bins given; mean of the middle two for an even count; taken before any
  * replacement) is below t by more than threshold takes that median.  Dead
- * pixels (F_k <= D) stay 0.  threshold < 0 or NaN -> PYHST_EARG. */
+ * pixels (F_k <= D) stay 0.  threshold < 0 or NaN -> PYHST_EARG.
+ * Halo: raw, flats and dark hold R_in = halo_lo + R + halo_hi detector rows
+ * (raw [K][R_in][n_det], flats [n_flats][R_in][n_det], dark [R_in][n_det]);
+ * sino [R][K][n_det] receives rows halo_lo .. halo_lo + R - 1, and the halo
+ * rows (0 or 1 on each side, else PYHST_EARG) serve only as neighbours, so a
+ * volume filtered in chunks of rows equals the volume filtered whole. */
 int pyhst_normalize_hotspot(const pyhst_plan *plan, const uint16_t *raw, const float *flats, const double *flat_pos,
-                            int32_t n_flats, const float *dark, float eps, float threshold, float *sino,
-                            hipStream_t stream);
+                            int32_t n_flats, const float *dark, float eps, float threshold, int32_t halo_lo,
+                            int32_t halo_hi, float *sino, hipStream_t stream);
 
 /* Ring-artifact filter of section 2.3, in place on sinograms sino [R][K][n_det]
  * of a uniform plan: per slice, m[j] = mean over projections of (sino - obj),
@@ -191,10 +204,11 @@ int fbp_filter(const pyhst_plan *plan, const float *sino, float *filt, hipStream
 int backproject(const pyhst_plan *plan, const float *sino, int32_t filtered_layout, float *img, float alpha,
                 float beta, hipStream_t stream);
 
-/* Matched forward projection sino = A(img) (ray-driven gather of the same hat
- * weights; section 2.3 and eq. (1)).  img [packed n_y x n_x], sino
- * [packed K x n_det]. */
-int forward_project(const pyhst_plan *plan, const float *img, float *sino, hipStream_t stream);
+/* Matched forward projection sino = alpha * A(img) (ray-driven gather of the
+ * same hat weights; section 2.3 and eq. (1)).  img [packed n_y x n_x], sino
+ * [packed K x n_det].  alpha = 1 gives A; alpha = 1/s^2 gives B^T, the adjoint
+ * of backproject with alpha = 1.  Non-finite alpha -> PYHST_EARG. */
+int forward_project(const pyhst_plan *plan, const float *img, float *sino, float alpha, hipStream_t stream);
 
 /* Proximal map of lambda*TV (isotropic TV of eq. (2), forward differences with
  * a zero last difference):  out = argmin_u 1/2|u - in|^2 + lambda TV(u), by
@@ -209,27 +223,34 @@ int tv_prox(int32_t n_slices, int32_t n_y, int32_t n_x, const float *in, float *
 /* Whole-slice reconstruction.
  *   method PYHST_FBP: out = B(fbp_filter(normalise(raw)))   (or of sino)
  *   method PYHST_TV_CP: eq. (3), min_x 1/2|A x - y|^2 + lambda TV(x), by
- *     n_iter Chambolle-Pock iterations with K = [A; grad], tau = sigma =
- *     1/op_norm, theta = 1, from zero.  op_norm <= 0: estimated by 50 power
- *     iterations on the GPU (this synchronises the stream once) and written
- *     back into op_norm.
- *     energy (host, [n_iter]) receives 1/2|A x - y|^2 + lambda TV(x) of the
- *     whole batch after every iteration (section 3.1: the energy is displayed
- *     so convergence can be checked); non-NULL energy makes the call
- *     synchronous and a non-finite energy returns PYHST_ENUM.
+ *     n_iter Chambolle-Pock iterations with K = [A; mu grad] (mu = tv_mu, <= 0
+ *     means 1), tau = sigma = 1/op_norm, theta = 1, from zero:
+ *       p <- (p + sigma (A xbar - y)) / (1 + sigma)
+ *       q <- q + sigma mu grad xbar, each pixel's 2-vector projected on |q| <= lambda/mu
+ *       x' = x - tau (A^T p - mu div q),  xbar = 2 x' - x,  x = x'
+ *     (lambda TV(x) = (lambda/mu) sum |mu grad x|, so the minimiser does not
+ *     depend on mu; mu = |A|/|grad| balances the two blocks so that the TV
+ *     dual reaches its bound within a few hundred iterations).  op_norm must
+ *     be |K| (pyhst_opnorm with_grad = 1 and the same mu).
  *   method PYHST_ISTA / PYHST_FISTA: eq. (3) by the solvers named in section
  *     3.1 (Daubechies et al. 2004; Beck & Teboulle 2009): n_iter iterations of
  *       x_k = prox_{(lambda/La) TV}(z - (1/La) A^T (A z - y)),  La = op_norm^2,
  *     ISTA: z = x_k;  FISTA: t' = (1 + sqrt(1 + 4t^2))/2,
  *     z = x_k + ((t - 1)/t') (x_k - x_{k-1}), t = t', from x_0 = z = 0, t = 1.
  *     The proximal map is tv_prox with n_inner dual iterations from zero.
- *     op_norm is |A| here (op_norm <= 0: estimated by 50 power iterations on
- *     A^T A, x 1.02, written back); energy as for PYHST_TV_CP.
+ *     op_norm must be |A| (pyhst_opnorm with_grad = 0).
+ *   Iterative methods: op_norm <= 0 or non-finite -> PYHST_EARG.  energy
+ *     (DEVICE float [n_iter], or NULL) receives 1/2|A x - y|^2 + lambda TV(x)
+ *     of the whole batch after every iteration (section 3.1: the energy is
+ *     displayed so that convergence can be judged); it is written by kernels
+ *     of the same launch sequence (graph-capturable), FP64 sums rounded to
+ *     float; checking it for non-finite values is the caller's.
  * Input: raw (uint16 [K][R][n_det] with flats, flat_pos, n_flats, dark, eps;
  * uniform plans) or, when raw == NULL, sino (normalised line integrals,
  * packed [K][n_det]).  out [packed n_y x n_x].
  * work/work_bytes: device scratch; call first with out == NULL to receive the
  * required size in *work_bytes (no work is enqueued).
+ * The call never synchronises and never allocates device memory.
  * use_graph != 0: the launches are captured once into a HIP graph kept by the
  * plan (keyed by every argument) and replayed on later identical calls.
  * Preprocessing (hot_spot, ring_width; uniform plans) runs before every method:
@@ -246,8 +267,8 @@ typedef struct {
     int32_t method;
     float lambda;
     int32_t n_iter;
-    double op_norm;
-    float *energy;            /* host */
+    double op_norm;           /* iterative methods: |[A; mu grad]| (TV_CP) or |A| (ISTA/FISTA), > 0 */
+    float *energy;            /* device [n_iter] or NULL */
     float *out;
     void *work;
     size_t work_bytes;
@@ -259,9 +280,23 @@ typedef struct {
     int32_t ring_width;       /* > 0: ring filter of the sinograms (pyhst_ring_filter) with this half-width */
     int32_t ring_object;      /* != 0: obj = A(x [x > ring_threshold]), x = FBP of the unfiltered data */
     float ring_threshold;
+    double tv_mu;             /* TV_CP: scale mu of the gradient block (<= 0: 1) */
+    int32_t hot_halo_lo;      /* hot_spot: halo rows of raw/flats/dark before and after the plan's */
+    int32_t hot_halo_hi;      /*   rows (0 or 1 each; pyhst_normalize_hotspot), else 0 */
 } pyhst_recon_args;
 
 int reconstruct_slices(const pyhst_plan *plan, pyhst_recon_args *a, hipStream_t stream);
+
+/* Operator norm that the iterative methods of reconstruct_slices take as
+ * op_norm (uniform plans): with_grad = 0: |A|; with_grad != 0: |[A; mu grad]|
+ * (mu <= 0 means 1), by 50 power iterations on A^T A (+ mu^2 grad^T grad) of
+ * the whole batch from a constant image, times 1.02 so that
+ * tau sigma |K|^2 < 1 holds.  *norm (host) receives the estimate.  work:
+ * device scratch; work == NULL returns its size in *work_bytes (nothing is
+ * enqueued).  The call synchronises the stream (the result is a host value);
+ * non-finite or zero estimate -> PYHST_ENUM. */
+int pyhst_opnorm(const pyhst_plan *plan, int32_t with_grad, double mu, void *work, size_t *work_bytes, double *norm,
+                 hipStream_t stream);
 
 /* Data consistency per slice: rel[s] = |ax_s - y_s| / |y_s| over slice s's
  * sinogram (packed [K][n_det] layout of the plan; FP64 accumulation, one
@@ -278,10 +313,13 @@ int pyhst_slice_residual(const pyhst_plan *plan, const float *ax, const float *y
  * of the same image size) and the measured row k.  plan: the full plan (all
  * projections; uniform), which supplies angle k, its axis shift and the
  * layout of y [packed K x n_det].  x [packed n_y x n_x]; row: device scratch of
- * n_slices * n_det floats (receives (A x)_k - y_k); err: device [n_slices].
- * k outside [0, K) -> PYHST_EARG.  FP64 accumulation of the squares. */
+ * n_slices * n_det floats (receives (A x)_k - y_k); err: device [n_slices]
+ * receives weight * |(A x_s)_k - y_s,k|^2, added to its previous value when
+ * accumulate != 0 (the average over several excluded projections: weight =
+ * 1/count, accumulate from the second one on).  k outside [0, K) or
+ * non-finite weight -> PYHST_EARG.  FP64 sum of the squares. */
 int pyhst_cv_error(const pyhst_plan *plan, const float *x, const float *y, int32_t k, float *row, float *err,
-                   hipStream_t stream);
+                   float weight, int32_t accumulate, hipStream_t stream);
 
 /* Decoherence estimator E_cohe of section 3.1: e[s] = cos(x_beta - x_zero,
  * x_beta) per slice, where x_zero is the reconstruction at a very small beta
@@ -304,9 +342,11 @@ int pyhst_decoherence(const pyhst_plan *plan, const float *x_beta, const float *
  *   dict [n_atoms][m*m] device, row k = atom phi_k (row-major patch);
  *   w    device [n_slices][n_patches][n_atoms] (receives the coefficients);
  *   out  device [packed n_y x n_x] (the image of eq. (7));
- *   lipschitz <= 0: estimated by 60 power iterations on the gradient map (x 1.02), written back;
- *   energy (host [n_iter] or NULL): eq. (8) after every iteration, summed over the batch.
- * Query: w == NULL returns work_bytes and n_patches.  The call synchronises its stream. */
+ *   lipschitz: step 1/lipschitz, must be > 0 (pyhst_patch_lipschitz estimates it);
+ *   energy (device [n_iter] or NULL): eq. (8) after every iteration, summed over the batch.
+ * Query: w == NULL returns work_bytes and n_patches (nothing is enqueued).  The
+ * call only enqueues work (the patch tables and the transposed dictionary are
+ * built by kernels of the same sequence), so it can be captured in a HIP graph. */
 typedef struct {
     const float *y;
     const float *dict;
@@ -316,13 +356,20 @@ typedef struct {
     double lipschitz;
     float *w;
     float *out;
-    float *energy;            /* host */
+    float *energy;            /* device [n_iter] or NULL */
     void *work;
     size_t work_bytes;
     int32_t n_patches;        /* out */
 } pyhst_patch_args;
 
 int pyhst_patch_fista(const pyhst_plan *plan, pyhst_patch_args *args, hipStream_t stream);
+
+/* Lipschitz constant of eq. (9)'s gradient map for the problem in args (y,
+ * w, out, energy, n_iter unused; work as for pyhst_patch_fista): 60 power
+ * iterations from a hashed start vector, times 1.02, written to
+ * args->lipschitz.  Synchronises the stream (the result is a host value);
+ * non-finite or zero estimate -> PYHST_ENUM. */
+int pyhst_patch_lipschitz(const pyhst_plan *plan, pyhst_patch_args *args, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Learned sparse-angle corrector (not part of the paper, whose learned prior
@@ -346,6 +393,12 @@ int pyhst_unet_create(int32_t batch, int32_t height, int32_t width, int32_t base
                       pyhst_unet **out);
 int pyhst_unet_destroy(pyhst_unet *net);
 int pyhst_unet_num_params(const pyhst_unet *net, int64_t *n);
+/* Data scale c (> 0, default 1; it belongs with the trained weights): the
+ * network sees c x and returns x_hat = x + f(c x)/c; training compares
+ * c x + f(c x) with c target (loss in those units).  Non-positive or
+ * non-finite c -> PYHST_EARG. */
+int pyhst_unet_set_scale(pyhst_unet *net, float scale);
+int pyhst_unet_get_scale(const pyhst_unet *net, float *scale);
 /* Load master weights (device FP32 [n_params]); resets the Adam state. */
 int pyhst_unet_set_params(pyhst_unet *net, const float *params, hipStream_t stream);
 int pyhst_unet_get_params(const pyhst_unet *net, float *params, hipStream_t stream);

@@ -20,7 +20,10 @@ What each function follows:
                        interpolation and its exact transpose (section 2.3)
   grad / div / tv      isotropic TV, eq. (2), Chambolle (2004) discretisation
   tv_prox              ROF proximal map by Chambolle's dual projection
-  cp_tv / opnorm       eq. (3) solved by Chambolle-Pock; |[A; grad]|_2
+  cp_tv / opnorm       eq. (3) solved by Chambolle-Pock with K = [A; mu grad];
+                       |K|_2
+  backproject_points   the backprojection at chosen pixels only (checks of
+                       full-size images)
 """
 from __future__ import annotations
 
@@ -69,8 +72,8 @@ def lib():
         L.or_tv.argtypes = [i, i, P]
         L.or_tv.restype = d
         L.or_tv_prox.argtypes = [i, i, P, d, i, P]
-        L.or_cp_tv.argtypes = [i, i, i, i, i, P, d, P, d, P, d, i, d, P, P]
-        L.or_opnorm.argtypes = [i, i, i, i, P, d, P, d, P, i, i]
+        L.or_cp_tv.argtypes = [i, i, i, i, i, P, d, P, d, P, d, i, d, d, P, P]
+        L.or_opnorm.argtypes = [i, i, i, i, P, d, P, d, P, i, i, d]
         L.or_fista_tv.argtypes = [i, i, i, i, i, i, P, d, P, d, P, d, i, d, i, P, P]
         L.or_opnorm.restype = d
         L.or_num_threads.restype = i
@@ -331,27 +334,28 @@ def tv_prox(g, lam: float, n_inner: int) -> np.ndarray:
 
 
 def cp_tv(y, g: Geom | None, lam: float, n_iter: int, op_norm: float, energy: bool = False,
-          identity_shape=None):
-    """Chambolle-Pock iterate after n_iter iterations (and the energy trace).
-    g=None with identity_shape=(n_y, n_x) replaces A by the identity."""
+          identity_shape=None, mu: float = 1.0):
+    """Chambolle-Pock iterate after n_iter iterations (and the energy trace), K = [A; mu grad],
+    tau = sigma = 1/op_norm (op_norm >= |K|).  g=None with identity_shape=(n_y, n_x) replaces A by
+    the identity."""
     y = _f64(y)
     E = np.empty(max(n_iter, 1)) if energy else None
     if g is None:
         ny, nx = identity_shape
         x = np.empty((ny, nx))
-        lib().or_cp_tv(1, nx, ny, 0, 0, None, 0.0, None, 1.0, _p(y), lam, n_iter, op_norm, _p(x), _p(E))
+        lib().or_cp_tv(1, nx, ny, 0, 0, None, 0.0, None, 1.0, _p(y), lam, n_iter, op_norm, mu, _p(x), _p(E))
     else:
         x = np.empty((g.n_y, g.n_x))
         lib().or_cp_tv(0, g.n_x, g.n_y, g.K, g.n_det, _p(g.angles), g.axis, _p(g.shifts), g.pixel_size,
-                       _p(y), lam, n_iter, op_norm, _p(x), _p(E))
+                       _p(y), lam, n_iter, op_norm, mu, _p(x), _p(E))
     return (x, E[:n_iter]) if energy else x
 
 
-def opnorm(g: Geom, x0, n_iter: int = 200, with_grad: bool = True) -> float:
-    """|[A; grad]|_2 (with_grad) or |A|_2 by power iteration from x0."""
+def opnorm(g: Geom, x0, n_iter: int = 200, with_grad: bool = True, mu: float = 1.0) -> float:
+    """|[A; mu grad]|_2 (with_grad) or |A|_2 by power iteration from x0."""
     x0 = _f64(x0)
     return lib().or_opnorm(g.n_x, g.n_y, g.K, g.n_det, _p(g.angles), g.axis, _p(g.shifts), g.pixel_size,
-                           _p(x0), n_iter, int(bool(with_grad)))
+                           _p(x0), n_iter, int(bool(with_grad)), float(mu))
 
 
 def fista_tv(y, g: Geom | None, lam: float, n_iter: int, lipschitz: float, n_inner: int, fast: bool = True,

@@ -14,6 +14,14 @@ every conv / transposed-conv weight, every stored activation and every stored
 activation gradient is rounded to BF16 (round to nearest even) at the point
 where it is stored; sums are exact (FP64).
 
+acc "fp32" (either mode) instead forms every convolution, transposed
+convolution and their gradients as FP32 matrix products with FP32 results
+(the accumulation order is the BLAS library's); "fp32rev" does the same with
+the kernel taps (and transposed-conv phases) summed in reverse order.  The
+spread between these accumulations and the exact one measures how far two
+correct FP32-accumulating implementations may drift apart, which sets the
+whole-network tolerance of the GPU tests.
+
 Parameter layout (flat vector): per level l = 0..L-1 the encoder convs a and b,
 then per level l = L-2..0 the transposed conv and decoder convs a and b, then
 the head.  Conv weights [c_out][3 ty + tx][c_in] then bias; transposed conv
@@ -56,9 +64,11 @@ def layers(base: int, levels: int):
 
 
 class UNetOracle:
-    def __init__(self, base: int, levels: int, mode: str = "fp64"):
-        assert mode in ("fp64", "bf16")
+    def __init__(self, base: int, levels: int, mode: str = "fp64", acc: str = "fp64"):
+        assert mode in ("fp64", "bf16") and acc in ("fp64", "fp32", "fp32rev")
         self.base, self.L, self.mode = base, levels, mode
+        self.dt = np.float64 if acc == "fp64" else np.float32
+        self.taps = list(range(9))[::-1] if acc == "fp32rev" else list(range(9))
         self.lay, self.n_params = layers(base, levels)
 
     # rounding at storage points
@@ -78,52 +88,59 @@ class UNetOracle:
         return W, b
 
     # ---------------------------------------------------------------- layers
-    @staticmethod
-    def conv(x, W, b):
+    # (operands and sums in self.dt: FP64, or FP32 for the accumulation-spread measurement; results
+    # are returned as float64)
+    def conv(self, x, W, b):
         """x [B,H,W,Ci], W [Co,9,Ci] -> pre-activation [B,H,W,Co]."""
+        dt = self.dt
         B, H, Wd, _ = x.shape
-        xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (0, 0)))
-        out = np.zeros((B, H, Wd, W.shape[0])) + b
-        for ty in range(3):
-            for tx in range(3):
-                out += xp[:, ty:ty + H, tx:tx + Wd, :] @ W[:, 3 * ty + tx, :].T
-        return out
+        xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (0, 0))).astype(dt)
+        W = W.astype(dt)
+        out = np.zeros((B, H, Wd, W.shape[0]), dtype=dt) + b.astype(dt)
+        for t in self.taps:
+            ty, tx = divmod(t, 3)
+            out += xp[:, ty:ty + H, tx:tx + Wd, :] @ W[:, t, :].T
+        return out.astype(np.float64)
 
-    @staticmethod
-    def conv_bwd(x, W, dz):
+    def conv_bwd(self, x, W, dz):
         """dz at the conv output (already through the ReLU mask) -> (dW, db, dX before masking)."""
+        dt = self.dt
         B, H, Wd, Ci = x.shape
-        xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (0, 0)))
+        xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (0, 0))).astype(dt)
+        W, dz = W.astype(dt), dz.astype(dt)
         dW = np.zeros_like(W)
         dxp = np.zeros_like(xp)
         dz2 = dz.reshape(-1, dz.shape[-1])
-        for ty in range(3):
-            for tx in range(3):
-                t = 3 * ty + tx
-                dW[:, t, :] = dz2.T @ xp[:, ty:ty + H, tx:tx + Wd, :].reshape(-1, Ci)
-                dxp[:, ty:ty + H, tx:tx + Wd, :] += dz @ W[:, t, :]
-        return dW, dz2.sum(axis=0), dxp[:, 1:-1, 1:-1, :]
+        for t in self.taps:
+            ty, tx = divmod(t, 3)
+            dW[:, t, :] = dz2.T @ xp[:, ty:ty + H, tx:tx + Wd, :].reshape(-1, Ci)
+            dxp[:, ty:ty + H, tx:tx + Wd, :] += dz @ W[:, t, :]
+        f = np.float64
+        return dW.astype(f), dz2.sum(axis=0).astype(f), dxp[:, 1:-1, 1:-1, :].astype(f)
 
-    @staticmethod
-    def up(x, U, b):
+    def up(self, x, U, b):
+        dt = self.dt
         B, h, w, _ = x.shape
-        out = np.zeros((B, 2 * h, 2 * w, U.shape[1]))
+        x, U, b = x.astype(dt), U.astype(dt), b.astype(dt)
+        out = np.zeros((B, 2 * h, 2 * w, U.shape[1]), dtype=dt)
         for dy in range(2):
             for dx in range(2):
                 out[:, dy::2, dx::2, :] = x @ U[2 * dy + dx].T + b
-        return out
+        return out.astype(np.float64)
 
-    @staticmethod
-    def up_bwd(x, U, dy_):
+    def up_bwd(self, x, U, dy_):
+        dt = self.dt
         Ci = x.shape[-1]
+        x, U, dy_ = x.astype(dt), U.astype(dt), dy_.astype(dt)
         dU = np.zeros_like(U)
         dx = np.zeros_like(x)
-        for dy in range(2):
-            for dxx in range(2):
-                g = dy_[:, dy::2, dxx::2, :]
-                dU[2 * dy + dxx] = g.reshape(-1, g.shape[-1]).T @ x.reshape(-1, Ci)
-                dx += g @ U[2 * dy + dxx]
-        return dU, dy_.reshape(-1, dy_.shape[-1]).sum(axis=0), dx
+        for ph in (range(4) if self.taps[0] == 0 else range(3, -1, -1)):
+            dy, dxx = divmod(ph, 2)
+            g = dy_[:, dy::2, dxx::2, :]
+            dU[ph] = g.reshape(-1, g.shape[-1]).T @ x.reshape(-1, Ci)
+            dx += g @ U[ph]
+        f = np.float64
+        return dU.astype(f), dy_.reshape(-1, dy_.shape[-1]).sum(axis=0).astype(f), dx.astype(f)
 
     @staticmethod
     def pool(x):

@@ -374,11 +374,13 @@ void or_tv_prox(int n_y, int n_x, const double *g, double lambda, int n_inner, d
 
 /* ---------------------------------------------------------------------------
  * Chambolle-Pock primal-dual iteration for eq. (3):
- *     min_x 1/2 |A x - y|^2 + lambda TV(x),   K = [A; grad],  tau = sigma = 1/Lk
- * with theta = 1 and x = xbar = p = q = 0 initially.  One iteration:
+ *     min_x 1/2 |A x - y|^2 + lambda TV(x),   K = [A; mu grad],  tau = sigma = 1/Lk
+ * (lambda TV(x) = (lambda/mu) sum_i |(mu grad x)_i|, so the dual field of the
+ * second block lives in the ball of radius lambda/mu; mu = 1 is the plain
+ * operator) with theta = 1 and x = xbar = p = q = 0 initially.  One iteration:
  *     p  <- (p + sigma (A xbar - y)) / (1 + sigma)
- *     q  <- q + sigma grad xbar, then q <- q / max(1, |q| / lambda) pointwise
- *     x+ <- x - tau (A^T p - div q)
+ *     q  <- q + sigma mu grad xbar, then q <- q / max(1, |q| / (lambda/mu)) pointwise
+ *     x+ <- x - tau (A^T p - mu div q)
  *     xbar <- 2 x+ - x,  x <- x+
  * 'identity' != 0 replaces A by the identity (then y has the image shape).
  * energy[i] (if non-NULL) = 1/2|A x - y|^2 + lambda TV(x) after iteration i.
@@ -400,7 +402,8 @@ static void apply_AT(int identity, int n_x, int n_y, int K, int L, const double 
 }
 
 void or_cp_tv(int identity, int n_x, int n_y, int K, int L, const double *ang, double axis, const double *shift,
-              double s, const double *y, double lambda, int n_iter, double Lk, double *x_out, double *energy)
+              double s, const double *y, double lambda, int n_iter, double Lk, double mu, double *x_out,
+              double *energy)
 {
     size_t n = (size_t)n_x * n_y, m = identity ? n : (size_t)K * L;
     double *x = (double *)calloc(n, sizeof(double)), *xb = (double *)calloc(n, sizeof(double));
@@ -414,8 +417,8 @@ void or_cp_tv(int identity, int n_x, int n_y, int K, int L, const double *ang, d
         for (size_t o = 0; o < m; ++o) p[o] = (p[o] + sigma * (ax[o] - y[o])) / (1.0 + sigma);
         or_grad(n_y, n_x, xb, g1, g2);
         for (size_t o = 0; o < n; ++o) {
-            double a = q1[o] + sigma * g1[o], b = q2[o] + sigma * g2[o];
-            double nrm = sqrt(a * a + b * b) / lambda;
+            double a = q1[o] + sigma * mu * g1[o], b = q2[o] + sigma * mu * g2[o];
+            double nrm = sqrt(a * a + b * b) / (lambda / mu);
             double d = nrm > 1.0 ? nrm : 1.0;
             if (lambda <= 0.0) { a = 0.0; b = 0.0; d = 1.0; }
             q1[o] = a / d;
@@ -424,7 +427,7 @@ void or_cp_tv(int identity, int n_x, int n_y, int K, int L, const double *ang, d
         apply_AT(identity, n_x, n_y, K, L, ang, axis, shift, s, p, atp);
         or_div(n_y, n_x, q1, q2, dv);
         for (size_t o = 0; o < n; ++o) {
-            double xn = x[o] - tau * (atp[o] - dv[o]);
+            double xn = x[o] - tau * (atp[o] - mu * dv[o]);
             xb[o] = 2.0 * xn - x[o];
             x[o] = xn;
         }
@@ -490,11 +493,11 @@ void or_fista_tv(int fast, int identity, int n_x, int n_y, int K, int L, const d
     free(x); free(xprev); free(z); free(v); free(r); free(atr);
 }
 
-/* Operator norm |K|_2 of K = [A; grad] (with_grad != 0) or of A alone
+/* Operator norm |K|_2 of K = [A; mu grad] (with_grad != 0) or of A alone
  * (with_grad == 0) by power iteration on K^T K (or A^T A) from the caller's
  * start vector x0 (n_y*n_x).  Returns sqrt of the Rayleigh quotient. */
 double or_opnorm(int n_x, int n_y, int K, int L, const double *ang, double axis, const double *shift, double s,
-                 const double *x0, int n_iter, int with_grad)
+                 const double *x0, int n_iter, int with_grad, double mu)
 {
     size_t n = (size_t)n_x * n_y, m = (size_t)K * L;
     double *x = (double *)malloc(n * sizeof(double)), *ax = (double *)malloc(m * sizeof(double));
@@ -511,7 +514,7 @@ double or_opnorm(int n_x, int n_y, int K, int L, const double *ang, double axis,
         if (with_grad) {
             or_grad(n_y, n_x, x, g1, g2);
             or_div(n_y, n_x, g1, g2, b);
-            for (size_t o = 0; o < n; ++o) a[o] -= b[o];   /* K^T K x = A^T A x - div grad x */
+            for (size_t o = 0; o < n; ++o) a[o] -= mu * mu * b[o];   /* K^T K x = A^T A x - mu^2 div grad x */
         }
         double dot = 0.0, nn = 0.0;
         for (size_t o = 0; o < n; ++o) { dot += a[o] * x[o]; nn += a[o] * a[o]; }

@@ -22,7 +22,8 @@ EXPORTS = ["pyhst_plan_create", "pyhst_plan_destroy", "pyhst_plan_slice_info", "
            "pyhst_unet_set_params", "pyhst_unet_get_params", "pyhst_unet_get_grads", "pyhst_unet_forward",
            "pyhst_unet_backward", "pyhst_unet_adam", "pyhst_unet_train_step", "pyhst_plan_autotune", "pyhst_slice_residual", "pyhst_unet_tensor",
            "pyhst_cv_error", "pyhst_decoherence", "pyhst_normalize_hotspot", "pyhst_ring_filter",
-           "pyhst_patch_fista"]
+           "pyhst_patch_fista", "pyhst_patch_lipschitz", "pyhst_opnorm", "pyhst_unet_set_scale",
+           "pyhst_unet_get_scale"]
 
 
 class Geom(ctypes.Structure):
@@ -42,16 +43,17 @@ class ReconArgs(ctypes.Structure):
     _fields_ = [("raw", c_void_p), ("sino", c_void_p), ("flats", c_void_p), ("flat_pos", ctypes.POINTER(c_double)),
                 ("n_flats", c_int32), ("dark", c_void_p), ("eps", c_float), ("method", c_int32),
                 ("lambda_", c_float), ("n_iter", c_int32), ("op_norm", c_double),
-                ("energy", ctypes.POINTER(c_float)), ("out", c_void_p), ("work", c_void_p),
+                ("energy", c_void_p), ("out", c_void_p), ("work", c_void_p),
                 ("work_bytes", c_size_t), ("use_graph", c_int32), ("n_inner", c_int32),
                 ("hot_spot", c_int32), ("hot_threshold", c_float), ("ring_width", c_int32),
-                ("ring_object", c_int32), ("ring_threshold", c_float)]
+                ("ring_object", c_int32), ("ring_threshold", c_float), ("tv_mu", c_double),
+                ("hot_halo_lo", c_int32), ("hot_halo_hi", c_int32)]
 
 
 class PatchArgs(ctypes.Structure):
     _fields_ = [("y", c_void_p), ("dict", c_void_p), ("m", c_int32), ("stride", c_int32), ("n_atoms", c_int32),
                 ("rho", c_float), ("beta", c_float), ("n_iter", c_int32), ("fast", c_int32), ("identity", c_int32),
-                ("lipschitz", c_double), ("w", c_void_p), ("out", c_void_p), ("energy", ctypes.POINTER(c_float)),
+                ("lipschitz", c_double), ("w", c_void_p), ("out", c_void_p), ("energy", c_void_p),
                 ("work", c_void_p), ("work_bytes", c_size_t), ("n_patches", c_int32)]
 
 
@@ -79,7 +81,7 @@ def lib(path: str = LIB_PATH):
     L.pyhst_normalize.argtypes = [P, P, P, ctypes.POINTER(c_double), c_int32, P, c_float, P, P]
     L.fbp_filter.argtypes = [P, P, P, P]
     L.backproject.argtypes = [P, P, c_int32, P, c_float, c_float, P]
-    L.forward_project.argtypes = [P, P, P, P]
+    L.forward_project.argtypes = [P, P, P, c_float, P]
     L.tv_prox.argtypes = [c_int32, c_int32, c_int32, P, P, c_float, c_int32, P, c_size_t, P]
     L.reconstruct_slices.argtypes = [P, ctypes.POINTER(ReconArgs), P]
     L.pyhst_microbench.argtypes = [c_int32, c_int32, c_int32, P, P]
@@ -95,10 +97,15 @@ def lib(path: str = LIB_PATH):
     L.pyhst_unet_train_step.argtypes = [P, P, P, c_int32, c_float, P, P]
     L.pyhst_plan_autotune.argtypes = [P, P, P, c_int32, ctypes.POINTER(c_float), P]
     L.pyhst_slice_residual.argtypes = [P, P, P, P, P]
-    L.pyhst_cv_error.argtypes = [P, P, P, c_int32, P, P, P]
-    L.pyhst_normalize_hotspot.argtypes = [P, P, P, ctypes.POINTER(c_double), c_int32, P, c_float, c_float, P, P]
+    L.pyhst_cv_error.argtypes = [P, P, P, c_int32, P, P, c_float, c_int32, P]
+    L.pyhst_normalize_hotspot.argtypes = [P, P, P, ctypes.POINTER(c_double), c_int32, P, c_float, c_float, c_int32,
+                                          c_int32, P, P]
     L.pyhst_ring_filter.argtypes = [P, P, c_int32, P, P, c_size_t, P]
     L.pyhst_patch_fista.argtypes = [P, ctypes.POINTER(PatchArgs), P]
+    L.pyhst_patch_lipschitz.argtypes = [P, ctypes.POINTER(PatchArgs), P]
+    L.pyhst_opnorm.argtypes = [P, c_int32, c_double, P, ctypes.POINTER(c_size_t), ctypes.POINTER(c_double), P]
+    L.pyhst_unet_set_scale.argtypes = [P, c_float]
+    L.pyhst_unet_get_scale.argtypes = [P, ctypes.POINTER(c_float)]
     L.pyhst_decoherence.argtypes = [P, P, P, P, P]
     L.pyhst_unet_tensor.argtypes = [P, c_int32, c_int32, c_int32, P, c_int64, P]
     L.pyhst_strerror.argtypes = [c_int32]

@@ -88,6 +88,8 @@ class Plan:
         check(self._L.pyhst_plan_sizes(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "pyhst_plan_sizes")
         self.sino_elems, self.filt_elems, self.img_elems = a.value, b.value, c.value
         self.uniform = self.slice_geom is None or len(set(self.slice_geom.tolist())) == 1
+        # the geometry every slice of a uniform plan uses (slice_geom may name any one of geoms)
+        self.geom0 = self.geoms[int(self.slice_geom[0]) if self.slice_geom is not None else 0]
 
     def slice_info(self, i: int) -> _lib.SliceInfo:
         si = _lib.SliceInfo()
@@ -113,15 +115,15 @@ class Plan:
 
     # shapes of the packed buffers of a uniform plan
     def sino_shape(self):
-        g = self.geoms[0]
+        g = self.geom0
         return (self.n_slices, g.n_angles, g.n_det) if self.uniform else (self.sino_elems,)
 
     def filt_shape(self):
-        g = self.geoms[0]
+        g = self.geom0
         return (self.n_slices, g.n_angles, self.slice_info(0).filt_len) if self.uniform else (self.filt_elems,)
 
     def img_shape(self):
-        g = self.geoms[0]
+        g = self.geom0
         return (self.n_slices, g.n_y, g.n_x) if self.uniform else (self.img_elems,)
 
     def autotune(self, filt, img, reps: int = 3, stream=None) -> float:
@@ -146,10 +148,25 @@ class Plan:
 
 
 def _need(t: torch.Tensor, n: int, name: str, dtype=torch.float32):
+    if t is None:
+        raise ValueError(f"{name}: missing")
     if t.dtype != dtype:
         raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
     if t.numel() != n:
         raise ValueError(f"{name}: expected {n} elements, got {t.numel()}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+
+
+def _need_raw(plan: Plan, raw, flats, flat_pos, dark, rows: int | None = None):
+    """Raw radiographs [K][rows][n_det] uint16, flats [n_flats][rows][n_det] and dark [rows][n_det] float32
+    (rows = the plan's slices unless halo rows are given)."""
+    g = plan.geom0
+    rows = plan.n_slices if rows is None else rows
+    nf = int(np.asarray(flat_pos).shape[0])
+    _need(raw, g.n_angles * rows * g.n_det, "raw", torch.uint16)
+    _need(flats, nf * rows * g.n_det, "flats")
+    _need(dark, rows * g.n_det, "dark")
 
 
 def pyhst_normalize(plan: Plan, raw, flats, flat_pos, dark, eps: float = 1e-6, out=None, stream=None):
@@ -157,7 +174,7 @@ def pyhst_normalize(plan: Plan, raw, flats, flat_pos, dark, eps: float = 1e-6, o
     if out is None:
         out = torch.empty(plan.sino_shape(), device=raw.device, dtype=torch.float32)
     _need(out, plan.sino_elems, "sino")
-    _need(raw, plan.sino_elems, "raw", torch.uint16)
+    _need_raw(plan, raw, flats, flat_pos, dark)
     fp = np.ascontiguousarray(flat_pos, dtype=np.float64)
     check(_lib.lib().pyhst_normalize(plan.handle, _ptr(raw), _ptr(flats),
                                      fp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(fp.shape[0]),
@@ -188,13 +205,36 @@ def backproject(plan: Plan, sino, filtered_layout: int = 0, out=None, alpha: flo
     return out
 
 
-def forward_project(plan: Plan, img, out=None, stream=None):
+def forward_project(plan: Plan, img, out=None, alpha: float = 1.0, stream=None):
+    """sino = alpha * A img (alpha = 1/s^2 gives B^T, the adjoint of backproject)."""
     if out is None:
         out = torch.empty(plan.sino_shape(), device=img.device, dtype=torch.float32)
     _need(img, plan.img_elems, "img")
     _need(out, plan.sino_elems, "sino")
-    check(_lib.lib().forward_project(plan.handle, _ptr(img), _ptr(out), _stream(stream)), "forward_project")
+    check(_lib.lib().forward_project(plan.handle, _ptr(img), _ptr(out), float(alpha), _stream(stream)),
+          "forward_project")
     return out
+
+
+def opnorm(plan: Plan, with_grad: bool, mu: float = 1.0, stream=None) -> float:
+    """|[A; mu grad]| (with_grad) or |A| of the plan's batch by power iteration (x 1.02), the op_norm the
+    iterative methods take.  Synchronises the stream."""
+    L = _lib.lib()
+    nb = ctypes.c_size_t()
+    check(L.pyhst_opnorm(plan.handle, int(bool(with_grad)), float(mu), None, ctypes.byref(nb), None,
+                         _stream(stream)), "pyhst_opnorm(query)")
+    work = torch.empty(max(nb.value, 1), device="cuda", dtype=torch.uint8)
+    nb.value = work.numel()
+    v = ctypes.c_double()
+    check(L.pyhst_opnorm(plan.handle, int(bool(with_grad)), float(mu), _ptr(work), ctypes.byref(nb), ctypes.byref(v),
+                         _stream(stream)), "pyhst_opnorm")
+    return v.value
+
+
+def balanced_mu(plan: Plan, stream=None) -> float:
+    """mu = |A| / |grad| with |grad| = 2 sqrt(2) (its bound on any image): the gradient-block scale that
+    balances Chambolle-Pock's two dual blocks."""
+    return opnorm(plan, False, stream=stream) / 1.02 / (2.0 * math.sqrt(2.0))
 
 
 def tv_prox(x, lam: float, n_inner: int, out=None, work=None, stream=None):
@@ -224,16 +264,19 @@ def _set_pre(a, hot_threshold, ring_width, ring_object_threshold):
 
 
 def normalize_hotspot(plan: Plan, raw, flats, flat_pos, dark, threshold: float, eps: float = 1e-6, out=None,
-                      stream=None):
-    """normalize() with the hot-spot median filter (section 2.3) on the flat-field-corrected data."""
-    _need(raw, plan.sino_elems, "raw", torch.uint16)
+                      halo=(0, 0), stream=None):
+    """normalize() with the hot-spot median filter (section 2.3) on the flat-field-corrected data.
+    halo = (rows before, rows after) present in raw/flats/dark only as neighbours (0 or 1 each)."""
+    h0, h1 = int(halo[0]), int(halo[1])
+    _need_raw(plan, raw, flats, flat_pos, dark, plan.n_slices + h0 + h1)
     fp = np.ascontiguousarray(flat_pos, dtype=np.float64)
     if out is None:
         out = torch.empty(plan.sino_shape(), device=raw.device, dtype=torch.float32)
     _need(out, plan.sino_elems, "out")
     check(_lib.lib().pyhst_normalize_hotspot(plan.handle, _ptr(raw), _ptr(flats),
                                              fp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(fp.shape[0]),
-                                             _ptr(dark), float(eps), float(threshold), _ptr(out), _stream(stream)),
+                                             _ptr(dark), float(eps), float(threshold), h0, h1, _ptr(out),
+                                             _stream(stream)),
           "pyhst_normalize_hotspot")
     return out
 
@@ -243,7 +286,7 @@ def ring_filter(plan: Plan, sino, width: int, obj=None, work=None, stream=None):
     _need(sino, plan.sino_elems, "sino")
     if obj is not None:
         _need(obj, plan.sino_elems, "obj")
-    n = 2 * plan.n_slices * plan.geoms[0].n_det
+    n = 2 * plan.n_slices * plan.geom0.n_det
     if work is None:
         work = torch.empty(n, device=sino.device, dtype=torch.float64)
     check(_lib.lib().pyhst_ring_filter(plan.handle, _ptr(sino), int(width), _ptr(obj), _ptr(work), work.numel(),
@@ -255,9 +298,19 @@ def reconstruct_slices(plan: Plan, *, raw=None, sino=None, flats=None, flat_pos=
                        method: int = FBP, lam: float = 0.0, n_iter: int = 0, op_norm: float = 0.0,
                        n_inner: int = 20, energy: bool = False, out=None, work=None, use_graph: bool = False,
                        hot_threshold: float | None = None, ring_width: int = 0,
-                       ring_object_threshold: float | None = None, stream=None):
-    """Returns out (and the energy trace as a numpy array when energy=True).  op_norm is |[A; grad]| for
-    TV_CP and |A| for ISTA/FISTA (<= 0: estimated on the GPU, then available as plan.last_op_norm)."""
+                       ring_object_threshold: float | None = None, tv_mu: float = 1.0, halo=(0, 0), stream=None):
+    """Returns out (and the energy trace as a numpy array when energy=True).  op_norm is |[A; tv_mu grad]| for
+    TV_CP and |A| for ISTA/FISTA; <= 0: computed first by opnorm() (a separate, synchronising call), then
+    available as plan.last_op_norm.  halo: raw rows before / after the plan's (hot-spot filter only)."""
+    iterative = method in (TV_CP, ISTA, FISTA)
+    if raw is not None:
+        if flat_pos is None:
+            raise ValueError("raw input needs flat_pos")
+        _need_raw(plan, raw, flats, flat_pos, dark, plan.n_slices + int(halo[0]) + int(halo[1]))
+    if sino is not None:
+        _need(sino, plan.sino_elems, "sino")
+    if iterative and not op_norm > 0.0:
+        op_norm = opnorm(plan, method == TV_CP, tv_mu, stream=stream)
     a = _lib.ReconArgs()
     a.raw = _ptr(raw)
     a.sino = _ptr(sino)
@@ -273,36 +326,40 @@ def reconstruct_slices(plan: Plan, *, raw=None, sino=None, flats=None, flat_pos=
     a.lambda_ = float(lam)
     a.n_iter = int(n_iter)
     a.op_norm = float(op_norm)
+    a.tv_mu = float(tv_mu)
     a.use_graph = int(bool(use_graph))
     a.n_inner = int(n_inner)
+    a.hot_halo_lo, a.hot_halo_hi = int(halo[0]), int(halo[1])
     _set_pre(a, hot_threshold, ring_width, ring_object_threshold)
-    if raw is not None:
-        _need(raw, plan.sino_elems, "raw", torch.uint16)
-        _need(flats, flats.numel(), "flats")
-        _need(dark, dark.numel(), "dark")
-    if sino is not None:
-        _need(sino, plan.sino_elems, "sino")
+    dev = (raw if raw is not None else sino).device
+    E = None
+    if energy and iterative:
+        E = torch.zeros(max(n_iter, 1), device=dev, dtype=torch.float32)
+        a.energy = _ptr(E)
     L = _lib.lib()
     # size query
     a.out = None
     check(L.reconstruct_slices(plan.handle, ctypes.byref(a), _stream(stream)), "reconstruct_slices(query)")
     need = a.work_bytes
-    dev = (raw if raw is not None else sino).device
     if work is None or work.numel() * work.element_size() < need:
         work = torch.empty(max(need, 1), device=dev, dtype=torch.uint8)
     if out is None:
         out = torch.empty(plan.img_shape(), device=dev, dtype=torch.float32)
     _need(out, plan.img_elems, "out")
-    E = None
-    if energy:
-        E = np.zeros(max(n_iter, 1), dtype=np.float32)
-        a.energy = E.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
     a.out = _ptr(out)
     a.work = _ptr(work)
     a.work_bytes = work.numel() * work.element_size()
     check(L.reconstruct_slices(plan.handle, ctypes.byref(a), _stream(stream)), "reconstruct_slices")
     plan.last_op_norm = a.op_norm
-    return (out, E[:n_iter]) if energy else out
+    if not energy:
+        return out
+    if E is None:
+        return out, np.zeros(0, dtype=np.float32)
+    (torch.cuda.current_stream() if stream is None else stream).synchronize()
+    e = E[:n_iter].cpu().numpy()
+    if not np.all(np.isfinite(e)):
+        raise FloatingPointError("reconstruct_slices: non-finite energy")
+    return out, e
 
 
 def slice_residual(plan: Plan, ax, y, out=None, stream=None):
@@ -316,19 +373,23 @@ def slice_residual(plan: Plan, ax, y, out=None, stream=None):
     return out
 
 
-def cv_error(plan: Plan, x, y, k: int, row=None, out=None, stream=None):
-    """Cross-validation estimator |(A x)_k - y_k|^2 per slice (device float [n_slices]); plan is the
-    full-data plan, x a reconstruction made without projection k."""
+def cv_error(plan: Plan, x, y, k: int, row=None, out=None, weight: float = 1.0, accumulate: bool = False,
+             stream=None):
+    """Cross-validation estimator weight * |(A x)_k - y_k|^2 per slice (device float [n_slices]), added to
+    out when accumulate; plan is the full-data plan, x a reconstruction made without projection k."""
     _need(x, plan.img_elems, "x")
     _need(y, plan.sino_elems, "y")
-    nb = plan.geoms[0].n_det
+    nb = plan.geom0.n_det
     if row is None:
         row = torch.empty(plan.n_slices * nb, device=x.device, dtype=torch.float32)
     _need(row, plan.n_slices * nb, "row")
     if out is None:
+        if accumulate:
+            raise ValueError("cv_error: accumulate needs out")
         out = torch.empty(plan.n_slices, device=x.device, dtype=torch.float32)
-    check(_lib.lib().pyhst_cv_error(plan.handle, _ptr(x), _ptr(y), int(k), _ptr(row), _ptr(out), _stream(stream)),
-          "pyhst_cv_error")
+    _need(out, plan.n_slices, "out")
+    check(_lib.lib().pyhst_cv_error(plan.handle, _ptr(x), _ptr(y), int(k), _ptr(row), _ptr(out), float(weight),
+                                    int(bool(accumulate)), _stream(stream)), "pyhst_cv_error")
     return out
 
 
@@ -343,14 +404,9 @@ def decoherence(plan: Plan, x_beta, x_zero, out=None, stream=None):
     return out
 
 
-def patch_fista(plan: Plan, y, dictionary, m: int, stride: int, rho: float, beta: float, n_iter: int,
-                fast: bool = True, identity: bool = False, lipschitz: float = 0.0, energy: bool = False,
-                stream=None):
-    """Overlapping-patch dictionary prior (section 3.2) by ISTA/FISTA on the patch coefficients.
-    y: sinograms (or images when identity=True); dictionary [n_atoms][m*m] float32 on the device.
-    Returns (image, coefficients [n_slices][n_patches][n_atoms]) and the energy trace when asked;
-    the Lipschitz constant used is left in plan.last_lipschitz."""
-    _need(y, plan.img_elems if identity else plan.sino_elems, "y")
+def _patch_args(plan: Plan, y, dictionary, m, stride, rho, beta, n_iter, fast, identity, lipschitz):
+    if y is not None:
+        _need(y, plan.img_elems if identity else plan.sino_elems, "y")
     if dictionary.dtype != torch.float32 or not dictionary.is_contiguous() or dictionary.dim() != 2 \
             or dictionary.shape[1] != m * m:
         raise ValueError("dictionary must be a contiguous float32 [n_atoms][m*m] tensor")
@@ -359,21 +415,53 @@ def patch_fista(plan: Plan, y, dictionary, m: int, stride: int, rho: float, beta
     a.m, a.stride, a.n_atoms = int(m), int(stride), int(dictionary.shape[0])
     a.rho, a.beta, a.n_iter, a.fast, a.identity = float(rho), float(beta), int(n_iter), int(fast), int(identity)
     a.lipschitz = float(lipschitz)
-    L = _lib.lib()
     a.w = None
-    check(L.pyhst_patch_fista(plan.handle, ctypes.byref(a), _stream(stream)), "pyhst_patch_fista(query)")
+    check(_lib.lib().pyhst_patch_fista(plan.handle, ctypes.byref(a), None), "pyhst_patch_fista(query)")
+    return a
+
+
+def patch_lipschitz(plan: Plan, dictionary, m: int, stride: int, rho: float, identity: bool = False,
+                    stream=None) -> float:
+    """Lipschitz constant (x 1.02) of eq. (9)'s gradient map by power iteration; synchronises the stream."""
+    a = _patch_args(plan, None, dictionary, m, stride, rho, 0.0, 0, True, identity, 0.0)
+    work = torch.empty(max(a.work_bytes, 1), device=dictionary.device, dtype=torch.uint8)
+    a.work, a.work_bytes = _ptr(work), work.numel()
+    check(_lib.lib().pyhst_patch_lipschitz(plan.handle, ctypes.byref(a), _stream(stream)), "pyhst_patch_lipschitz")
+    return a.lipschitz
+
+
+def patch_fista(plan: Plan, y, dictionary, m: int, stride: int, rho: float, beta: float, n_iter: int,
+                fast: bool = True, identity: bool = False, lipschitz: float = 0.0, energy: bool = False,
+                out=None, w=None, work=None, stream=None):
+    """Overlapping-patch dictionary prior (section 3.2) by ISTA/FISTA on the patch coefficients.
+    y: sinograms (or images when identity=True); dictionary [n_atoms][m*m] float32 on the device.
+    Returns (image, coefficients [n_slices][n_patches][n_atoms]) and the energy trace when asked;
+    lipschitz <= 0: estimated first by patch_lipschitz() (a separate, synchronising call); the value used
+    is left in plan.last_lipschitz."""
+    if not lipschitz > 0.0:
+        lipschitz = patch_lipschitz(plan, dictionary, m, stride, rho, identity, stream=stream)
+    a = _patch_args(plan, y, dictionary, m, stride, rho, beta, n_iter, fast, identity, lipschitz)
     dev = y.device
-    work = torch.empty(max(a.work_bytes, 1), device=dev, dtype=torch.uint8)
-    W = torch.empty((plan.n_slices, a.n_patches, a.n_atoms), device=dev, dtype=torch.float32)
-    out = torch.empty(plan.img_shape(), device=dev, dtype=torch.float32)
+    if work is None or work.numel() < a.work_bytes:
+        work = torch.empty(max(a.work_bytes, 1), device=dev, dtype=torch.uint8)
+    W = torch.empty((plan.n_slices, a.n_patches, a.n_atoms), device=dev, dtype=torch.float32) if w is None else w
+    _need(W, plan.n_slices * a.n_patches * a.n_atoms, "w")
+    out = torch.empty(plan.img_shape(), device=dev, dtype=torch.float32) if out is None else out
+    _need(out, plan.img_elems, "out")
     E = None
     if energy:
-        E = np.zeros(max(n_iter, 1), dtype=np.float32)
-        a.energy = E.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        E = torch.zeros(max(n_iter, 1), device=dev, dtype=torch.float32)
+        a.energy = _ptr(E)
     a.w, a.out, a.work, a.work_bytes = _ptr(W), _ptr(out), _ptr(work), work.numel()
-    check(L.pyhst_patch_fista(plan.handle, ctypes.byref(a), _stream(stream)), "pyhst_patch_fista")
+    check(_lib.lib().pyhst_patch_fista(plan.handle, ctypes.byref(a), _stream(stream)), "pyhst_patch_fista")
     plan.last_lipschitz = a.lipschitz
-    return (out, W, E[:n_iter]) if energy else (out, W)
+    if not energy:
+        return out, W
+    (torch.cuda.current_stream() if stream is None else stream).synchronize()
+    e = E[:n_iter].cpu().numpy()
+    if not np.all(np.isfinite(e)):
+        raise FloatingPointError("patch_fista: non-finite energy")
+    return out, W, e
 
 
 def work_bytes(plan: Plan, **kw) -> int:
@@ -382,6 +470,8 @@ def work_bytes(plan: Plan, **kw) -> int:
     a.sino = _ptr(kw.get("sino"))
     a.method = int(kw.get("method", FBP))
     a.n_iter = int(kw.get("n_iter", 0))
+    if kw.get("energy"):
+        a.energy = ctypes.c_void_p(1)   # only its presence matters to the size query
     _set_pre(a, kw.get("hot_threshold"), kw.get("ring_width", 0), kw.get("ring_object_threshold"))
     a.out = None
     check(_lib.lib().reconstruct_slices(plan.handle, ctypes.byref(a), None), "reconstruct_slices(query)")

@@ -2,10 +2,12 @@
 
 Project(x) = A x with A = s^2 B^T (forward_project); its backward is A^T g =
 s^2 B g (backproject with alpha = s^2).  BackProject(q) = B q; its backward is
-B^T g = A g / s^2.  FBP(p) = B(F p) with F the (symmetric, row-weighted) ramp
-filter; its backward is F^T (B^T g), and F^T = F for full-detector scans
-because the Ram-Lak kernel is even and the row weights are diagonal.  No extra
-kernel exists for the backward passes: each is the adjoint call."""
+B^T g = A g / s^2 (forward_project with alpha = 1/s^2).  FBP(p) = B(F p) with F
+the row-weighted ramp filter; its backward is F^T (B^T g), and F^T = F for
+full-detector scans: the Ram-Lak kernel is even, so the convolution on [0, L)
+is a symmetric matrix, and each row's quadrature weight is one scalar, which
+commutes with it.  No extra kernel exists for the backward passes: each is the
+adjoint call, and every product runs in the library."""
 from __future__ import annotations
 
 import torch
@@ -14,7 +16,7 @@ from . import api
 
 
 def _s2(plan: api.Plan) -> float:
-    return float(plan.geoms[0].pixel_size) ** 2
+    return float(plan.geom0.pixel_size) ** 2
 
 
 class Project(torch.autograd.Function):
@@ -38,7 +40,7 @@ class BackProject(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         plan = ctx.plan
-        return api.forward_project(plan, g.contiguous()) / _s2(plan), None
+        return api.forward_project(plan, g.contiguous(), alpha=1.0 / _s2(plan)), None
 
 
 class FBP(torch.autograd.Function):
@@ -55,7 +57,7 @@ class FBP(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         plan = ctx.plan
-        bt = api.forward_project(plan, g.contiguous()) / _s2(plan)
+        bt = api.forward_project(plan, g.contiguous(), alpha=1.0 / _s2(plan))
         return api.fbp_filter(plan, bt), None
 
 

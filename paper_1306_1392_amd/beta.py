@@ -45,8 +45,10 @@ def select_beta(geo: api.Geometry, y, betas, *, excluded=None, beta0: float | No
         x = api.reconstruct_slices(full, sino=y, lam=float(b), op_norm=op_norm, **kw)
         xs.append(x)
         ec.append(api.decoherence(full, x, x0).cpu().numpy())
-    cv = np.zeros((len(betas), S))
-    for k in excluded:
+    # the library averages over the excluded projections: weight 1/count, accumulated after the first
+    cv = torch.zeros((len(betas), S), device=y.device, dtype=torch.float32)
+    wgt = 1.0 / len(excluded)
+    for n, k in enumerate(excluded):
         part = _drop(geo, int(k))
         plan_k = api.Plan(part, n_slices=S)
         keep = torch.as_tensor(np.nonzero(np.arange(geo.n_angles) != k)[0], device=y.device)
@@ -55,6 +57,6 @@ def select_beta(geo: api.Geometry, y, betas, *, excluded=None, beta0: float | No
         for i, b in enumerate(betas):
             xk = api.reconstruct_slices(plan_k, sino=yk, lam=float(b), op_norm=nk, **kw)
             nk = plan_k.last_op_norm
-            cv[i] += api.cv_error(full, xk, y, int(k)).cpu().numpy()
-    cv /= len(excluded)
-    return {"betas": betas, "cv": cv, "e_cohe": np.array(ec), "x": torch.stack(xs), "excluded": np.asarray(excluded)}
+            api.cv_error(full, xk, y, int(k), out=cv[i], weight=wgt, accumulate=n > 0)
+    return {"betas": betas, "cv": cv.cpu().numpy().astype(np.float64), "e_cohe": np.array(ec), "x": torch.stack(xs),
+            "excluded": np.asarray(excluded)}

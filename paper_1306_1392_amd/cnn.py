@@ -76,6 +76,16 @@ class UNet:
     def _s(stream=None):
         return ctypes.c_void_p((torch.cuda.current_stream() if stream is None else stream).cuda_stream)
 
+    def set_scale(self, scale: float):
+        """Data scale c: the network sees c x and returns x + f(c x)/c (it belongs with the weights)."""
+        check(self.L.pyhst_unet_set_scale(self.handle, float(scale)), "pyhst_unet_set_scale")
+
+    @property
+    def scale(self) -> float:
+        v = ctypes.c_float()
+        check(self.L.pyhst_unet_get_scale(self.handle, ctypes.byref(v)), "pyhst_unet_get_scale")
+        return v.value
+
     def set_params(self, params, stream=None):
         t = torch.as_tensor(params, dtype=torch.float32).to("cuda").contiguous()
         assert t.numel() == self.n_params

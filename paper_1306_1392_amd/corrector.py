@@ -15,14 +15,27 @@ from . import api
 from .cnn import UNet
 
 
+def save_weights(path: str, params, scale: float, base: int, levels: int):
+    """Trained corrector: master weights with the data scale and architecture they belong to (.npz)."""
+    p = params.detach().cpu().numpy() if torch.is_tensor(params) else np.asarray(params)
+    np.savez(path, params=p.astype(np.float32), scale=np.float32(scale), base=np.int32(base),
+             levels=np.int32(levels))
+
+
+def load_weights(path: str) -> dict:
+    with np.load(path, allow_pickle=False) as z:
+        return {"params": z["params"], "scale": float(z["scale"]), "base": int(z["base"]), "levels": int(z["levels"])}
+
+
 class Corrector:
     def __init__(self, geometry: api.Geometry, batch: int, params, base: int = 32, levels: int = 4,
                  tv_lambda: float = 0.01, tv_iters: int = 300, dc_threshold: float | None = None,
-                 tv_method: int = api.FISTA, tv_inner: int = 10):
+                 tv_method: int = api.FISTA, tv_inner: int = 10, scale: float = 1.0):
         self.geo = geometry
         self.batch = batch
         self.plan = api.Plan(geometry, n_slices=batch)
         self.net = UNet(batch, geometry.n_y, geometry.n_x, base, levels)
+        self.net.set_scale(scale)
         self.net.set_params(params)
         self.tv_lambda, self.tv_iters = tv_lambda, tv_iters
         self.tv_method, self.tv_inner = tv_method, tv_inner
@@ -33,12 +46,12 @@ class Corrector:
     def fbp(self, y):
         return api.reconstruct_slices(self.plan, sino=y, method=api.FBP)
 
-    def correct(self, y):
+    def correct(self, y, out=None, ax=None, res=None):
         """FBP + U-Net for a full batch y [batch][K][nb]; returns (x_hat, residual per slice)."""
         x0 = self.fbp(y)
-        xh = self.net.forward(x0)
-        ax = api.forward_project(self.plan, xh)
-        return xh, api.slice_residual(self.plan, ax, y)
+        xh = self.net.forward(x0, out=out)
+        ax = api.forward_project(self.plan, xh, out=ax)
+        return xh, api.slice_residual(self.plan, ax, y, out=res)
 
     def tv(self, y):
         """TV reconstruction (eq. (3); FISTA or Chambolle-Pock) of the slices in y [n][K][nb]."""

@@ -48,6 +48,7 @@ constexpr int TKW = 64;
 
 struct pyhst_unet {
     int B, H, W, base, L;
+    float scale = 1.0f;   // data scale: the network sees scale x and returns x + f(scale x) / scale
     int64_t n_params = 0;
     float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
     int *step = nullptr;
@@ -75,11 +76,12 @@ unsigned blocks_for(int64_t n, int64_t cap = 16384)
 
 #define GRID_LOOP(i, n) for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
-__global__ void input_pad_kernel(const float *x, int64_t npix, bf16_t *x8)
+// x8 = [scale x, 0, ..., 0] in BF16 (8 channels, only the first carries the image)
+__global__ void input_pad_kernel(const float *x, int64_t npix, bf16_t *x8, float scale)
 {
     GRID_LOOP(p, npix)
     {
-        uint4 v = make_uint4(f2bf(x[p]), 0, 0, 0);
+        uint4 v = make_uint4(f2bf(x[p] * scale), 0, 0, 0);
         *(uint4 *)(x8 + p * 8) = v;
     }
 }
@@ -147,8 +149,9 @@ __global__ void pool_bwd_kernel(Act e, bf16_t *de, const bf16_t *dp, int pcs, in
     }
 }
 
+// out = v / scale (unscale) or v, with v = scale x + head(d): the residual output in the network's units
 __global__ void head_fwd_kernel(const bf16_t *d, int C, const float *wh, const float *bh, const float *x, float *out,
-                                int64_t npix)
+                                int64_t npix, float scale, int unscale)
 {
     GRID_LOOP(p, npix)
     {
@@ -159,7 +162,8 @@ __global__ void head_fwd_kernel(const bf16_t *d, int C, const float *wh, const f
 #pragma unroll
             for (int c = 0; c < 8; ++c) s = fmaf(bf2f(e[c]), wh[c0 + c], s);
         }
-        out[p] = x[p] + (bh[0] + s);
+        const float v = x[p] * scale + (bh[0] + s);
+        out[p] = unscale ? v / scale : v;
     }
 }
 
@@ -176,16 +180,16 @@ __device__ inline double block_sum_d(double v, double *sh)
     return t;
 }
 
-// loss partials: sum (out - t)^2 per block; dout = 2 (out - t) / n
+// loss partials: sum (out - scale t)^2 per block; dout = 2 (out - scale t) / n
 __global__ __launch_bounds__(256) void mse_kernel(const float *out, const float *t, float *dout, int64_t n,
-                                                  double *partials)
+                                                  double *partials, float scale)
 {
     __shared__ double sh[4];
     double acc = 0.0;
     const float sc = 2.0f / (float)n;
     GRID_LOOP(p, n)
     {
-        const float d = out[p] - t[p];
+        const float d = out[p] - t[p] * scale;
         acc += (double)d * d;
         dout[p] = sc * d;
     }
@@ -492,12 +496,13 @@ hipError_t cast_all(const pyhst_unet &net, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t forward(pyhst_unet &net, const float *in, int n, float *out, hipStream_t st)
+// unscale = 1: out in the caller's units; 0: in the network's (scaled) units
+hipError_t forward(pyhst_unet &net, const float *in, int n, float *out, int unscale, hipStream_t st)
 {
     const int L = net.L;
     hipError_t e;
     input_pad_kernel<<<blocks_for((int64_t)n * net.H * net.W), 256, 0, st>>>(in, (int64_t)n * net.H * net.W,
-                                                                             net.x8.a);
+                                                                             net.x8.a, net.scale);
     Act cur = act(net.x8, n);
     for (int l = 0; l < L; ++l) {
         const bool bott = l == L - 1;
@@ -528,18 +533,18 @@ hipError_t forward(pyhst_unet &net, const float *in, int n, float *out, hipStrea
     }
     const int64_t npix = (int64_t)n * net.H * net.W;
     head_fwd_kernel<<<blocks_for(npix), 256, 0, st>>>(net.db[0].a, net.db[0].C, net.params + net.head_w,
-                                                      net.params + net.head_b, in, out, npix);
+                                                      net.params + net.head_b, in, out, npix, net.scale, unscale);
     return hipGetLastError();
 }
 
 hipError_t backward(pyhst_unet &net, const float *in, const float *target, int n, float *loss, hipStream_t st)
 {
-    hipError_t e = forward(net, in, n, net.out, st);
+    hipError_t e = forward(net, in, n, net.out, 0, st);
     if (e != hipSuccess) return e;
     const int L = net.L;
     const int64_t npix = (int64_t)n * net.H * net.W;
     const int nb = (int)blocks_for(npix, 1024);
-    mse_kernel<<<nb, 256, 0, st>>>(net.out, target, net.dout, npix, net.dpart);
+    mse_kernel<<<nb, 256, 0, st>>>(net.out, target, net.dout, npix, net.dpart, net.scale);
     final_mean_kernel<<<1, 256, 0, st>>>(net.dpart, nb, npix, loss);
     // head
     {
@@ -761,6 +766,20 @@ int pyhst_unet_destroy(pyhst_unet *net)
     return PYHST_OK;
 }
 
+int pyhst_unet_set_scale(pyhst_unet *net, float scale)
+{
+    if (!net || !(scale > 0.0f) || !std::isfinite(scale)) return fail(PYHST_EARG, "unet_set_scale: bad argument");
+    net->scale = scale;
+    return PYHST_OK;
+}
+
+int pyhst_unet_get_scale(const pyhst_unet *net, float *scale)
+{
+    if (!net || !scale) return fail(PYHST_EARG, "unet_get_scale: NULL argument");
+    *scale = net->scale;
+    return PYHST_OK;
+}
+
 int pyhst_unet_num_params(const pyhst_unet *net, int64_t *n)
 {
     if (!net || !n) return fail(PYHST_EARG, "unet_num_params: NULL argument");
@@ -798,7 +817,7 @@ int pyhst_unet_forward(pyhst_unet *net, const float *in, int32_t n, float *out, 
 {
     if (!net || !in || !out) return fail(PYHST_EARG, "unet_forward: NULL argument");
     if (n <= 0 || n > net->B) return fail(PYHST_EARG, "unet_forward: n must be in [1, batch]");
-    hipError_t e = forward(*net, in, n, out, st);
+    hipError_t e = forward(*net, in, n, out, 1, st);
     return e == hipSuccess ? PYHST_OK : hip_fail(e, "unet_forward");
 }
 

@@ -77,7 +77,7 @@ struct Tables {
     const float2 *twid;                  // exp(-2 pi i m / Pmax), m < Pmax/2
     const int2 *pairs;                   // filter work: (slice, first projection of a row pair)
     const int2 *items[N_TILE_CFG];       // backprojection work: (slice, tile), costliest first
-    int *counter;                        // persistent work counter
+    int *counter;                        // persistent work counters [PYHST_MAX_STREAMS]
     const int *fp_ang;                   // forward-projection block members: projection index within its geometry
     const int2 *fp_blk;                  // forward-projection blocks: (first member, count)
     const int4 *fp_pair;                 // staged-projector groups: up to FP_SGRP projections, -1 for none
@@ -114,8 +114,10 @@ struct pyhst_plan {
     void *dev_block = nullptr;
     pyhst::Tables t{};
     int cu_count = 256;
-    std::mutex mu;
-    std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
+    // caches filled by const entry points (guarded by mu)
+    mutable std::mutex mu;
+    mutable std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
+    mutable std::map<hipStream_t, int> counter_slot;   // persistent-work counter of each stream
 };
 
 namespace pyhst {
@@ -126,6 +128,8 @@ int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *where);
 
 int choose_tile(const pyhst_plan &p);
+// persistent-work counter of `st` on this plan (nullptr once every slot is taken)
+int *stream_counter(const pyhst_plan &p, hipStream_t st);
 
 // CP epilogues
 struct CpPrimal {   // x+ = x - tau (alpha B p - div q); xbar = 2 x+ - x
@@ -138,6 +142,8 @@ struct CpDual {     // p = (p + sigma (alpha A xbar - y)) / (1 + sigma);  residu
     const float *y;
     float sigma;
     int residual;
+    float *ax;      // optional: ax = ax_a (alpha A xbar) + ax_b ax
+    float ax_a, ax_b;
 };
 
 // launchers (return hipGetLastError())
@@ -145,7 +151,7 @@ hipError_t launch_normalize(const pyhst_plan &p, const uint16_t *raw, const floa
                             int n_flats, const float *dark, float eps, float *sino, hipStream_t st);
 hipError_t launch_normalize_hotspot(const pyhst_plan &p, const uint16_t *raw, const float *flats,
                                     const double *flat_pos, int n_flats, const float *dark, float eps, float thr,
-                                    float *sino, hipStream_t st);
+                                    int halo_lo, int halo_hi, float *sino, hipStream_t st);
 hipError_t launch_ring_filter(const pyhst_plan &p, float *sino, const float *obj, int width, double *work,
                               hipStream_t st);
 hipError_t launch_threshold(float *dst, const float *src, int64_t n, float thr, hipStream_t st);
@@ -171,7 +177,7 @@ hipError_t launch_cp_energy(const pyhst_plan &p, const float *ax, const float *y
 int energy_partials(const pyhst_plan &p);
 hipError_t launch_axpby(float *y, const float *x, int64_t n, float a, float b, hipStream_t st);
 hipError_t launch_power_step(const pyhst_plan &p, const float *x, float *out, float *tmp_sino,
-                             double *partials, int n_part, double *norm_dev, int with_grad, hipStream_t st);
+                             double *partials, int n_part, double *norm_dev, float grad_scale, hipStream_t st);
 hipError_t launch_momentum(float *z, const float *xn, const float *xo, int64_t n, float m, hipStream_t st);
 hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t st);
 hipError_t launch_scale_by_inv(float *x, int64_t n, const double *norm_dev, hipStream_t st);

@@ -28,7 +28,7 @@ typedef __attribute__((address_space(4))) const float cfloat;
 template <int CFG, int MODE>
 __global__ __launch_bounds__(256 * TILE_AG[CFG]) void bp_kernel(Tables T, const float *__restrict__ sino,
                                                                 int filtered, float *__restrict__ img, float alpha,
-                                                                float beta, int64_t n_items, int persistent,
+                                                                float beta, int64_t n_items, int *counter,
                                                                 int xcd_remap, CpPrimal cp)
 {
     constexpr int BX = TILE_BX[CFG], BY = TILE_BY[CFG];
@@ -49,8 +49,8 @@ __global__ __launch_bounds__(256 * TILE_AG[CFG]) void bp_kernel(Tables T, const 
 
     for (int64_t round = 0;; ++round) {
         int64_t item;
-        if (persistent) {
-            if (tid == 0) s_item = atomicAdd(T.counter, 1);
+        if (counter) {   // persistent: take the next item of the cost-sorted list
+            if (tid == 0) s_item = atomicAdd(counter, 1);
             __syncthreads();
             item = s_item;
             __syncthreads();
@@ -208,19 +208,20 @@ hipError_t launch_cfg(const pyhst_plan &p, const float *sino, int filtered, floa
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    if (p.persistent) {
-        zero_counter<<<1, 1, 0, st>>>(p.t.counter);
+    int *counter = p.persistent ? stream_counter(p, st) : nullptr;
+    if (counter) {
+        zero_counter<<<1, 1, 0, st>>>(counter);
         int per_cu = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bp_kernel<CFG, MODE>, 256 * AG, lds);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
         int64_t grid = (int64_t)per_cu * p.cu_count;
         if (grid > n) grid = n;
-        bp_kernel<CFG, MODE><<<(unsigned)grid, 256 * AG, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n, 1, 0,
-                                                                    cp);
+        bp_kernel<CFG, MODE><<<(unsigned)grid, 256 * AG, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n,
+                                                                    counter, 0, cp);
     } else {
-        bp_kernel<CFG, MODE><<<(unsigned)n, 256 * AG, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n, 0,
-                                                                 p.uniform ? 1 : 0, cp);
+        bp_kernel<CFG, MODE><<<(unsigned)n, 256 * AG, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n,
+                                                                 nullptr, p.uniform ? 1 : 0, cp);
     }
     return hipGetLastError();
 }

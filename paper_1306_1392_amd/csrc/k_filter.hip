@@ -80,7 +80,10 @@ __global__ __launch_bounds__(256) void normalize_kernel(const uint16_t *__restri
 // Hot-spot removal on the flat-field-corrected transmission (section 2.3): a pixel whose 3x3
 // neighbours' median (up to 8 neighbours of the same radiograph, mean of the middle two for an
 // even count) is below it by more than thr takes that median; then -log as above.  One thread per
-// pixel; the 9 transmissions are recomputed per thread (neighbours come from L1/L2).
+// pixel; the 9 transmissions are recomputed per thread (neighbours come from L1/L2).  The input
+// rows are R_in = h0 + R + (halo after): output row r reads input row h0 + r, and the halo rows
+// serve only as neighbours, so a volume reconstructed in chunks of rows gives the same result as
+// in one piece.
 __device__ inline float transmission(const uint16_t *raw, const float *f0, const float *f1, const float *dk, float a,
                                      int64_t o, bool &dead)
 {
@@ -100,19 +103,21 @@ __device__ inline void cswap(float &a, float &b)
 __global__ __launch_bounds__(256) void normalize_hotspot_kernel(const uint16_t *__restrict__ raw,
                                                                 const float *__restrict__ flats, FlatInfo fi,
                                                                 const float *__restrict__ dark, float eps, float thr,
-                                                                int K, int R, int nb, float *__restrict__ out)
+                                                                int K, int R, int R_in, int h0, int nb,
+                                                                float *__restrict__ out)
 {
-    const int row = blockIdx.x;          // raw row order: k * R + r
+    const int row = blockIdx.x;          // output row order: k * R + r
     const int k = row / R, r = row - k * R;
+    const int ri = r + h0;               // its input row
     int i0, i1;
     float a;
     flat_interp(fi, k, i0, i1, a);
-    const uint16_t *img = raw + (int64_t)k * R * nb;      // radiograph k, [R][nb]
-    const float *f0 = flats + (int64_t)i0 * R * nb, *f1 = flats + (int64_t)i1 * R * nb;
+    const uint16_t *img = raw + (int64_t)k * R_in * nb;      // radiograph k, [R_in][nb]
+    const float *f0 = flats + (int64_t)i0 * R_in * nb, *f1 = flats + (int64_t)i1 * R_in * nb;
     float *dst = out + ((int64_t)r * K + k) * nb;
     for (int j = threadIdx.x; j < nb; j += blockDim.x) {
         bool dead;
-        float t = transmission(img, f0, f1, dark, a, (int64_t)r * nb + j, dead);
+        float t = transmission(img, f0, f1, dark, a, (int64_t)ri * nb + j, dead);
         if (dead) {
             dst[j] = 0.0f;
             continue;
@@ -123,8 +128,8 @@ __global__ __launch_bounds__(256) void normalize_hotspot_kernel(const uint16_t *
         for (int q = 0; q < 9; ++q) {
             const int dr = q / 3 - 1, dj = q % 3 - 1;
             if (q == 4) continue;
-            const int rr = r + dr, jj = j + dj;
-            const bool in = rr >= 0 && rr < R && jj >= 0 && jj < nb;
+            const int rr = ri + dr, jj = j + dj;
+            const bool in = rr >= 0 && rr < R_in && jj >= 0 && jj < nb;
             bool dd;
             const float tv = in ? transmission(img, f0, f1, dark, a, (int64_t)rr * nb + jj, dd) : INFINITY;
             v[q < 4 ? q : q - 1] = tv;
@@ -555,12 +560,13 @@ FlatInfo make_flats(const double *pos, int n)
 
 hipError_t launch_normalize_hotspot(const pyhst_plan &p, const uint16_t *raw, const float *flats,
                                     const double *flat_pos, int n_flats, const float *dark, float eps, float thr,
-                                    float *sino, hipStream_t st)
+                                    int halo_lo, int halo_hi, float *sino, hipStream_t st)
 {
     const GeoDev &g = p.gd[0];
     const int R = p.n_slices;
     normalize_hotspot_kernel<<<(unsigned)((int64_t)g.K * R), 256, 0, st>>>(
-        raw, flats, make_flats(flat_pos, n_flats), dark, eps, thr, g.K, R, g.nb, sino);
+        raw, flats, make_flats(flat_pos, n_flats), dark, eps, thr, g.K, R, halo_lo + R + halo_hi, halo_lo, g.nb,
+        sino);
     return hipGetLastError();
 }
 

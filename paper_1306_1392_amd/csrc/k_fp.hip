@@ -118,6 +118,28 @@ __device__ __forceinline__ void fp_block_lines(const float *stage, int seg_len, 
 
 // NC > 0: a fixed number of candidates per line (the surplus ones get zero weight), so the reads of
 // a line are independent and issue together; NC == 0: the exact count, ceil(2/|a|), at run time.
+// Epilogue of every projector kernel for the value v = alpha (A x)[o]:
+//   MODE 0: out[o] = v
+//   MODE 1: Chambolle-Pock dual step p = (p + sigma (v - y)) / (1 + sigma)
+//   MODE 2: residual p = v - y (gradient step of ISTA/FISTA)
+//   MODE 3: one projection's residual row per slice, p[row_o] = v - y
+// In modes 1 and 2 a non-null cp.ax is updated to ax_a v + ax_b ax: the projection of the
+// primal iterate, carried by linearity from the projection of the extrapolated point, for
+// the energy of eq. (3) without a projector call of its own.
+template <int MODE>
+__device__ __forceinline__ void fp_store(const CpDual &cp, float *out, int64_t o, float v, int64_t row_o)
+{
+    if (MODE == 0) {
+        out[o] = v;
+    } else if (MODE == 3) {
+        cp.p[row_o] = v - cp.y[o];
+    } else {
+        if (MODE == 1) cp.p[o] = (cp.p[o] + cp.sigma * (v - cp.y[o])) / (1.0f + cp.sigma);
+        else cp.p[o] = v - cp.y[o];
+        if (cp.ax) cp.ax[o] = cp.ax_a * v + cp.ax_b * cp.ax[o];
+    }
+}
+
 template <int MODE, int NC, bool UNIT>
 __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restrict__ img, float *__restrict__ out,
                                                  float alpha, CpDual cp, int k_single, int seg_len)
@@ -249,16 +271,7 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
     for (int i = 0; i < AW; ++i) {
         if (i >= mine) break;
         const int64_t o = sd.sino_off + (int64_t)kk[i] * nb + j;
-        const float v = sc * acc[i];
-        if (MODE == 0) {
-            out[o] = v;
-        } else if (MODE == 1) {
-            cp.p[o] = (cp.p[o] + cp.sigma * (v - cp.y[o])) / (1.0f + cp.sigma);
-        } else if (MODE == 2) {
-            cp.p[o] = v - cp.y[o];   // residual A x - y of the gradient step of ISTA/FISTA
-        } else {
-            cp.p[(int64_t)slice * nb + j] = v - cp.y[o];   // one projection's residual row per slice
-        }
+        fp_store<MODE>(cp, out, o, sc * acc[i], (int64_t)slice * nb + j);
     }
 }
 
@@ -327,16 +340,7 @@ __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__
     if (wv > 0 || j >= nb) return;
     acc = ((acc + part[0][lane]) + part[1][lane]) + part[2][lane];
     const int64_t o = sd.sino_off + (int64_t)k * nb + j;
-    const float v = alpha * (float)(s * s) * acc;
-    if (MODE == 0) {
-        out[o] = v;
-    } else if (MODE == 1) {
-        cp.p[o] = (cp.p[o] + cp.sigma * (v - cp.y[o])) / (1.0f + cp.sigma);
-    } else if (MODE == 2) {
-        cp.p[o] = v - cp.y[o];
-    } else {
-        cp.p[(int64_t)slice * nb + j] = v - cp.y[o];
-    }
+    fp_store<MODE>(cp, out, o, alpha * (float)(s * s) * acc, (int64_t)slice * nb + j);
 }
 
 // Pixel size >= 0.5 (NC > 0): one to FP_SGRP = 4 projections per workgroup, staged through LDS.
@@ -498,16 +502,7 @@ __device__ __forceinline__ void fp_staged_body(const Tables &T, const SliceDev &
     for (int p = 0; p < P; ++p) {
         const float sum = ((acc[p] + part[p][0][lane]) + part[p][1][lane]) + part[p][2][lane];
         const int64_t o = sd.sino_off + (int64_t)pr[p].k * nb + j;
-        const float val = sc * sum;
-        if (MODE == 0) {
-            out[o] = val;
-        } else if (MODE == 1) {
-            cp.p[o] = (cp.p[o] + cp.sigma * (val - cp.y[o])) / (1.0f + cp.sigma);
-        } else if (MODE == 2) {
-            cp.p[o] = val - cp.y[o];
-        } else {
-            cp.p[(int64_t)slice * nb + j] = val - cp.y[o];
-        }
+        fp_store<MODE>(cp, out, o, sc * sum, (int64_t)slice * nb + j);
     }
 }
 

@@ -5,7 +5,7 @@
 // last corner moved to n - m); patch p = row-corner index * n_cx + column-corner
 // index.  The core of a pixel is its L1-nearest patch centre (lowest index on
 // ties); with a separable corner grid that is the pair of per-axis nearest
-// corners, tabulated once per call on the host.
+// corners, tabulated by a small kernel at the start of every call.
 //
 // One gradient evaluation at coefficients Z (eq. (9)):
 //   X = Z D                      (GEMM, [S*N_p][n_atoms] x [n_atoms][m*m])
@@ -337,44 +337,188 @@ hipError_t sgemm(const float *A, const float *B, float *C, int64_t M, int N, int
     return hipGetLastError();
 }
 
-std::vector<int> axis_corners(int n, int m, int stride)
+// Per-axis patch tables on the device (so that a call enqueues them instead of copying host
+// memory): corners c_a = min(a stride, n - m) for a < nc; for every pixel i the core corner
+// (the nearest centre c_a + (m - 1)/2, lowest index on ties) and the first / last corner whose
+// patch covers i.  One thread per pixel; ties and distances in exact integer arithmetic
+// (|2 i - 2 c_a - (m - 1)| orders the centre distances).
+__global__ void axis_tables_kernel(int n, int m, int stride, int nc, int *__restrict__ corner, int *__restrict__ core,
+                                   int *__restrict__ first, int *__restrict__ last)
 {
-    std::vector<int> c;
-    for (int v = 0; v + m <= n; v += stride) c.push_back(v);
-    if (c.empty() || c.back() != n - m) c.push_back(n - m);
-    return c;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc) corner[i] = min(i * stride, n - m);
+    if (i >= n) return;
+    int best = 0x7fffffff, bi = 0, f = -1, l = -1;
+    for (int a = 0; a < nc; ++a) {
+        const int c = min(a * stride, n - m);
+        const int d = abs(2 * (i - c) - (m - 1));
+        if (d < best) {
+            best = d;
+            bi = a;
+        }
+        if (c <= i && i < c + m) {
+            if (f < 0) f = a;
+            l = a;
+        }
+    }
+    core[i] = bi;
+    first[i] = f;
+    last[i] = l;
 }
 
-// per pixel along one axis: nearest corner's centre (L1 per axis; lowest index on ties),
-// and the range of corners whose patch covers the pixel
-void axis_tables(int n, int m, const std::vector<int> &c, std::vector<int> &core, std::vector<int> &first,
-                 std::vector<int> &last)
+// DT[l][k] = D[k][l]  (D [na][mm])
+__global__ void transpose_kernel(const float *__restrict__ D, int na, int mm, float *__restrict__ DT)
 {
-    core.assign(n, 0);
-    first.assign(n, 0);
-    last.assign(n, -1);
-    for (int i = 0; i < n; ++i) {
-        double best = 1e300;
-        for (size_t a = 0; a < c.size(); ++a) {
-            const double d = std::fabs(i - (c[a] + 0.5 * (m - 1)));
-            if (d < best) {
-                best = d;
-                core[i] = (int)a;
-            }
-        }
-        int f = -1, l = -1;
-        for (size_t a = 0; a < c.size(); ++a)
-            if (c[a] <= i && i < c[a] + m) {
-                if (f < 0) f = (int)a;
-                l = (int)a;
-            }
-        first[i] = f;
-        last[i] = l;
+    const int64_t n = (int64_t)na * mm;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e / mm), l = (int)(e - (int64_t)k * mm);
+        DT[(int64_t)l * na + k] = D[e];
     }
 }
 
+// start vector of the power iteration: a hash of the index mapped to [-0.5, 0.5)
+__global__ void seed_kernel(float *__restrict__ z, int64_t n)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)e * 0x9e3779b9u + 0x7f4a7c15u;
+        h ^= h >> 16;
+        h *= 0x21f0aaadu;
+        h ^= h >> 15;
+        h *= 0x735a2d97u;
+        h ^= h >> 15;
+        z[e] = (float)((h >> 8) * (1.0 / 16777216.0) - 0.5);
+    }
+}
+
+int n_corners(int n, int m, int stride) { return (n - m) / stride + 1 + ((n - m) % stride ? 1 : 0); }
+
 struct PatchLayout {
-    size_t tables, X, x, r, R, G, grad, W, Z, dt, partials, res, energy, total;
+    size_t tables, X, x, r, R, G, grad, Z, dt, partials, res, total;
+};
+
+}  // namespace
+}  // namespace pyhst
+
+using namespace pyhst;
+
+namespace pyhst {
+namespace {
+
+// Everything one patch call needs: sizes, the work layout, the device tables and the gradient of
+// eq. (9).  Construction only checks arguments and computes the layout.
+struct PatchCall {
+    const pyhst_plan &p;
+    pyhst_patch_args &a;
+    int rc = PYHST_OK;
+    int S = 0, ny = 0, nx = 0, m = 0, na = 0, ncy = 0, ncx = 0, np = 0, mm = 0;
+    int64_t ni = 0, nw = 0, nX = 0, ns = 0;
+    static constexpr int nblk = 1024;
+    PatchLayout L{};
+    PatchGeo g{};
+    float *X = nullptr, *x = nullptr, *r = nullptr, *R = nullptr, *G = nullptr, *grad = nullptr, *Z = nullptr,
+          *DT = nullptr;
+    double *partials = nullptr, *res = nullptr;
+    float s2 = 1.0f;
+
+    PatchCall(const pyhst_plan &plan, pyhst_patch_args &args, const char *who) : p(plan), a(args)
+    {
+        if (!p.uniform) {
+            rc = fail(PYHST_EARG, std::string(who) + ": needs a uniform plan");
+            return;
+        }
+        const GeoDev &geo = p.gd[0];
+        S = p.n_slices;
+        ny = geo.ny;
+        nx = geo.nx;
+        m = a.m;
+        na = a.n_atoms;
+        const int st_ = a.stride;
+        if (m < 1 || m > ny || m > nx || st_ < 1 || st_ > m || na < 1 || a.n_iter < 0 || !(a.rho >= 0.0f) ||
+            !(a.beta >= 0.0f)) {
+            rc = fail(PYHST_EARG, std::string(who) + ": bad patch size, stride, atoms, iterations, rho or beta");
+            return;
+        }
+        ncy = n_corners(ny, m, st_);
+        ncx = n_corners(nx, m, st_);
+        np = ncy * ncx;
+        mm = m * m;
+        ni = (int64_t)S * ny * nx;
+        nw = (int64_t)S * np * na;
+        nX = (int64_t)S * np * mm;
+        ns = a.identity ? ni : (int64_t)p.sino_elems;
+        s2 = (float)(geo.s * geo.s);
+        size_t o = 0;
+        auto take = [&](size_t bytes) {
+            size_t r0 = o;
+            o = (o + bytes + 255) & ~(size_t)255;
+            return r0;
+        };
+        L.tables = take((size_t)4 * (ncy + ncx + 3 * (size_t)(ny + nx)));
+        L.X = take((size_t)nX * 4);
+        L.x = take((size_t)ni * 4);
+        L.r = take((size_t)ns * 4);
+        L.R = take((size_t)ni * 4);
+        L.G = take((size_t)nX * 4);
+        L.grad = take((size_t)nw * 4);
+        L.Z = take((size_t)nw * 4);
+        L.dt = take((size_t)na * mm * 4);
+        L.partials = take(sizeof(double) * 2 * nblk);
+        L.res = take(sizeof(double) * 2);
+        L.total = o;
+    }
+
+    // bind the work buffer and enqueue the tables and D^T
+    int bind(hipStream_t st, const char *who)
+    {
+        if (!a.dict) return fail(PYHST_EARG, std::string(who) + ": NULL dict");
+        if (!a.work || a.work_bytes < L.total) {
+            set_error(std::string(who) + ": work buffer too small");
+            return PYHST_ENOMEM;
+        }
+        unsigned char *w = (unsigned char *)a.work;
+        int *t = (int *)(w + L.tables);
+        int *cy = t, *cx = cy + ncy, *core_y = cx + ncx, *core_x = core_y + ny, *first_y = core_x + nx,
+            *last_y = first_y + ny, *first_x = last_y + ny, *last_x = first_x + nx;
+        axis_tables_kernel<<<(ny + 255) / 256, 256, 0, st>>>(ny, m, a.stride, ncy, cy, core_y, first_y, last_y);
+        axis_tables_kernel<<<(nx + 255) / 256, 256, 0, st>>>(nx, m, a.stride, ncx, cx, core_x, first_x, last_x);
+        DT = (float *)(w + L.dt);
+        transpose_kernel<<<grid_n((int64_t)na * mm), 256, 0, st>>>(a.dict, na, mm, DT);
+        g = PatchGeo{cy, cx, core_y, core_x, first_y, last_y, first_x, last_x, ny, nx, m, ncy, ncx, np};
+        X = (float *)(w + L.X);
+        x = (float *)(w + L.x);
+        r = (float *)(w + L.r);
+        R = (float *)(w + L.R);
+        G = (float *)(w + L.G);
+        grad = (float *)(w + L.grad);
+        Z = (float *)(w + L.Z);
+        partials = (double *)(w + L.partials);
+        res = (double *)(w + L.res);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? PYHST_OK : hip_fail(e, who);
+    }
+
+    // gradient of eq. (9) at coefficients C into grad (data term dropped when with_y is false)
+    hipError_t gradient(const float *C, bool with_y, hipStream_t st)
+    {
+        hipError_t er = sgemm(C, a.dict, X, (int64_t)S * np, mm, na, 1.0f, st);
+        if (er != hipSuccess) return er;
+        assemble_kernel<<<grid_n(ni), 256, 0, st>>>(g, X, x, S);
+        if (a.identity) {
+            diff_kernel<<<grid_n(ni), 256, 0, st>>>(x, with_y ? a.y : nullptr, R, ni);
+        } else {
+            if (with_y) {
+                CpDual rd{r, a.y, 0.0f, 1};
+                er = launch_forward(p, x, nullptr, 1.0f, &rd, st);
+            } else {
+                er = launch_forward(p, x, r, 1.0f, nullptr, st);
+            }
+            if (er == hipSuccess) er = launch_backproject(p, r, 0, R, s2, 0.0f, nullptr, st);
+            if (er != hipSuccess) return er;
+        }
+        similarity_kernel<<<grid_n(ni), 256, 0, st>>>(g, X, x, R, a.rho, S);
+        patch_grad_kernel<<<grid_n(nX), 256, 0, st>>>(g, X, x, R, a.rho, G, S);
+        return sgemm(G, DT, grad, (int64_t)S * np, na, mm, 2.0f, st);
+    }
 };
 
 }  // namespace
@@ -385,188 +529,82 @@ using namespace pyhst;
 extern "C" int pyhst_patch_fista(const pyhst_plan *pc, pyhst_patch_args *a, hipStream_t st)
 {
     if (!pc || !a) return fail(PYHST_EARG, "patch_fista: NULL argument");
-    const pyhst_plan &p = *pc;
-    if (!p.uniform) return fail(PYHST_EARG, "patch_fista: needs a uniform plan");
-    const GeoDev &geo = p.gd[0];
-    const int S = p.n_slices, ny = geo.ny, nx = geo.nx, m = a->m, st_ = a->stride, na = a->n_atoms;
-    if (m < 1 || m > ny || m > nx || st_ < 1 || st_ > m || na < 1 || a->n_iter < 0 || !(a->rho >= 0.0f) ||
-        !(a->beta >= 0.0f))
-        return fail(PYHST_EARG, "patch_fista: bad patch size, stride, atoms, iterations, rho or beta");
-    const std::vector<int> cy = axis_corners(ny, m, st_), cx = axis_corners(nx, m, st_);
-    const int ncy = (int)cy.size(), ncx = (int)cx.size(), np = ncy * ncx, mm = m * m;
-    const int64_t ni = (int64_t)S * ny * nx, nw = (int64_t)S * np * na, nX = (int64_t)S * np * mm;
-    const int64_t ns = a->identity ? ni : (int64_t)p.sino_elems;
-    const int nblk = 1024;
-
-    PatchLayout L{};
-    size_t o = 0;
-    auto take = [&](size_t bytes) {
-        size_t r = o;
-        o = (o + bytes + 255) & ~(size_t)255;
-        return r;
-    };
-    const size_t tab_ints = 2 * (cy.size() + cx.size()) + 3 * (size_t)(ny + nx);
-    L.tables = take(tab_ints * 4);
-    L.X = take((size_t)nX * 4);
-    L.x = take((size_t)ni * 4);
-    L.r = take((size_t)ns * 4);
-    L.R = take((size_t)ni * 4);
-    L.G = take((size_t)nX * 4);
-    L.grad = take((size_t)nw * 4);
-    L.Z = take((size_t)nw * 4);
-    L.dt = take((size_t)na * mm * 4);
-    L.partials = take(sizeof(double) * 2 * nblk);
-    L.res = take(sizeof(double) * 2);
-    L.energy = take(sizeof(float) * (size_t)std::max(1, a->n_iter));
-    L.total = o;
+    PatchCall c(*pc, *a, "patch_fista");
+    if (c.rc) return c.rc;
     if (!a->w) {
-        a->work_bytes = L.total;
-        a->n_patches = np;
+        a->work_bytes = c.L.total;
+        a->n_patches = c.np;
         return PYHST_OK;
     }
-    if (!a->y || !a->dict || !a->out) return fail(PYHST_EARG, "patch_fista: NULL y, dict or out");
-    if (!a->work || a->work_bytes < L.total) {
-        set_error("patch_fista: work buffer too small");
-        return PYHST_ENOMEM;
-    }
-    unsigned char *w = (unsigned char *)a->work;
-    // host tables: corners, per-pixel cores and covering ranges
-    std::vector<int> core_y, first_y, last_y, core_x, first_x, last_x;
-    axis_tables(ny, m, cy, core_y, first_y, last_y);
-    axis_tables(nx, m, cx, core_x, first_x, last_x);
-    std::vector<int> tab;
-    tab.insert(tab.end(), cy.begin(), cy.end());
-    tab.insert(tab.end(), cx.begin(), cx.end());
-    const size_t o_core_y = tab.size();
-    tab.insert(tab.end(), core_y.begin(), core_y.end());
-    const size_t o_core_x = tab.size();
-    tab.insert(tab.end(), core_x.begin(), core_x.end());
-    const size_t o_first_y = tab.size();
-    tab.insert(tab.end(), first_y.begin(), first_y.end());
-    const size_t o_last_y = tab.size();
-    tab.insert(tab.end(), last_y.begin(), last_y.end());
-    const size_t o_first_x = tab.size();
-    tab.insert(tab.end(), first_x.begin(), first_x.end());
-    const size_t o_last_x = tab.size();
-    tab.insert(tab.end(), last_x.begin(), last_x.end());
-    // D^T [m*m][n_atoms], built on the host from the caller's dictionary
-    std::vector<float> dict_host((size_t)na * mm), dt_host((size_t)na * mm);
-    int *dtab = (int *)(w + L.tables);
-    hipError_t e = hipMemcpyAsync(dtab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(dict_host.data(), a->dict, dict_host.size() * 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "patch_fista: tables");
-    for (int k = 0; k < na; ++k)
-        for (int l = 0; l < mm; ++l) dt_host[(size_t)l * na + k] = dict_host[(size_t)k * mm + l];
-    float *DT = (float *)(w + L.dt);
-    e = hipMemcpyAsync(DT, dt_host.data(), dt_host.size() * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);   // dt_host must outlive the copy
-    if (e != hipSuccess) return hip_fail(e, "patch_fista: dictionary transpose");
-
-    PatchGeo g{dtab, dtab + cy.size(), dtab + o_core_y, dtab + o_core_x, dtab + o_first_y, dtab + o_last_y,
-               dtab + o_first_x, dtab + o_last_x, ny, nx, m, ncy, ncx, np};
-    float *X = (float *)(w + L.X), *x = (float *)(w + L.x), *r = (float *)(w + L.r), *R = (float *)(w + L.R);
-    float *G = (float *)(w + L.G), *grad = (float *)(w + L.grad), *Z = (float *)(w + L.Z), *W = a->w;
-    double *partials = (double *)(w + L.partials), *res = (double *)(w + L.res);
-    float *edev = (float *)(w + L.energy);
-    const float s2 = (float)(geo.s * geo.s);
-
-    // gradient of eq. (9) at coefficients C (data term dropped when with_y is false)
-    auto gradient = [&](const float *C, bool with_y) -> hipError_t {
-        hipError_t er = sgemm(C, a->dict, X, (int64_t)S * np, mm, na, 1.0f, st);
-        if (er != hipSuccess) return er;
-        assemble_kernel<<<grid_n(ni), 256, 0, st>>>(g, X, x, S);
-        if (a->identity) {
-            diff_kernel<<<grid_n(ni), 256, 0, st>>>(x, with_y ? a->y : nullptr, R, ni);
-        } else {
-            if (with_y) {
-                CpDual rd{r, a->y, 0.0f, 1};
-                er = launch_forward(p, x, nullptr, 1.0f, &rd, st);
-            } else {
-                er = launch_forward(p, x, r, 1.0f, nullptr, st);
-            }
-            if (er == hipSuccess) er = launch_backproject(p, r, 0, R, s2, 0.0f, nullptr, st);
-            if (er != hipSuccess) return er;
-        }
-        similarity_kernel<<<grid_n(ni), 256, 0, st>>>(g, X, x, R, a->rho, S);
-        patch_grad_kernel<<<grid_n(nX), 256, 0, st>>>(g, X, x, R, a->rho, G, S);
-        return sgemm(G, DT, grad, (int64_t)S * np, na, mm, 2.0f, st);
-    };
-
-    double Lf = a->lipschitz;
-    if (!(Lf > 0.0)) {
-        // power iteration on the (linear) gradient map with y = 0; Z holds the iterate
-        std::vector<float> seed((size_t)nw);
-        uint32_t h = 0x9e3779b9u;
-        for (auto &v : seed) {
-            h ^= h << 13;
-            h ^= h >> 17;
-            h ^= h << 5;
-            v = (float)((h >> 8) * (1.0 / 16777216.0) - 0.5);
-        }
-        e = hipMemcpyAsync(Z, seed.data(), seed.size() * 4, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        double lam = 0.0;
-        for (int it = 0; it < 60 && e == hipSuccess; ++it) {
-            dot2_kernel<<<nblk, 256, 0, st>>>(Z, Z, nw, partials);
-            power_norm_kernel<<<1, 64, 0, st>>>(partials, nblk, res);
-            scale_by_norm_kernel<<<grid_n(nw), 256, 0, st>>>(Z, Z, nw, res);
-            e = gradient(Z, false);
-            if (e != hipSuccess) break;
-            dot2_kernel<<<nblk, 256, 0, st>>>(grad, Z, nw, partials);
-            power_norm_kernel<<<1, 64, 0, st>>>(partials, nblk, res);
-            e = hipMemcpyAsync(Z, grad, (size_t)nw * 4, hipMemcpyDeviceToDevice, st);
-        }
-        double hr[2] = {0.0, 0.0};
-        if (e == hipSuccess) e = hipMemcpyAsync(hr, res, sizeof(hr), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "patch_fista: Lipschitz estimate");
-        lam = hr[0];
-        if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PYHST_ENUM, "patch_fista: Lipschitz estimate failed");
-        Lf = 1.02 * lam;
-        a->lipschitz = Lf;
-    }
-
-    e = launch_fill(W, nw, 0.0f, st);
-    if (e == hipSuccess) e = launch_fill(Z, nw, 0.0f, st);
+    if (!a->y || !a->out) return fail(PYHST_EARG, "patch_fista: NULL y or out");
+    if (!(a->lipschitz > 0.0) || !std::isfinite(a->lipschitz))
+        return fail(PYHST_EARG, "patch_fista: lipschitz must be > 0 (see pyhst_patch_lipschitz)");
+    int rc = c.bind(st, "patch_fista");
+    if (rc) return rc;
+    const double Lf = a->lipschitz;
+    float *W = a->w;
+    hipError_t e = launch_fill(W, c.nw, 0.0f, st);
+    if (e == hipSuccess) e = launch_fill(c.Z, c.nw, 0.0f, st);
     if (e != hipSuccess) return hip_fail(e, "patch_fista: clear");
     double t = 1.0;
     for (int it = 0; it < a->n_iter; ++it) {
-        e = gradient(Z, true);
+        e = c.gradient(c.Z, true, st);
         if (e != hipSuccess) return hip_fail(e, "patch_fista: gradient");
         double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
         const float mom = (float)((t - 1.0) / tn);
-        shrink_kernel<<<grid_n(nw), 256, 0, st>>>(grad, Z, W, nw, (float)(1.0 / Lf), (float)(a->beta / Lf), mom,
-                                                   a->fast);
+        shrink_kernel<<<grid_n(c.nw), 256, 0, st>>>(c.grad, c.Z, W, c.nw, (float)(1.0 / Lf), (float)(a->beta / Lf),
+                                                     mom, a->fast);
         t = tn;
         if (a->energy) {
-            e = sgemm(W, a->dict, X, (int64_t)S * np, mm, na, 1.0f, st);
+            e = sgemm(W, a->dict, c.X, (int64_t)c.S * c.np, c.mm, c.na, 1.0f, st);
             if (e != hipSuccess) return hip_fail(e, "patch_fista: energy");
-            assemble_kernel<<<grid_n(ni), 256, 0, st>>>(g, X, x, S);
+            assemble_kernel<<<grid_n(c.ni), 256, 0, st>>>(c.g, c.X, c.x, c.S);
             if (a->identity) {
-                diff_kernel<<<grid_n(ni), 256, 0, st>>>(x, a->y, r, ni);
+                diff_kernel<<<grid_n(c.ni), 256, 0, st>>>(c.x, a->y, c.r, c.ni);
             } else {
-                CpDual rd{r, a->y, 0.0f, 1};
-                e = launch_forward(p, x, nullptr, 1.0f, &rd, st);
+                CpDual rd{c.r, a->y, 0.0f, 1};
+                e = launch_forward(*pc, c.x, nullptr, 1.0f, &rd, st);
                 if (e != hipSuccess) return hip_fail(e, "patch_fista: energy");
             }
-            patch_energy_kernel<<<nblk, 256, 0, st>>>(g, r, ns, X, x, W, nw, a->rho, a->beta, S, partials);
-            patch_final_kernel<<<1, 64, 0, st>>>(partials, nblk, edev + it);
+            patch_energy_kernel<<<c.nblk, 256, 0, st>>>(c.g, c.r, c.ns, c.X, c.x, W, c.nw, a->rho, a->beta, c.S,
+                                                         c.partials);
+            patch_final_kernel<<<1, 64, 0, st>>>(c.partials, c.nblk, a->energy + it);
         }
     }
     // final image from the final coefficients
-    e = sgemm(W, a->dict, X, (int64_t)S * np, mm, na, 1.0f, st);
+    e = sgemm(W, a->dict, c.X, (int64_t)c.S * c.np, c.mm, c.na, 1.0f, st);
     if (e != hipSuccess) return hip_fail(e, "patch_fista: image");
-    assemble_kernel<<<grid_n(ni), 256, 0, st>>>(g, X, a->out, S);
+    assemble_kernel<<<grid_n(c.ni), 256, 0, st>>>(c.g, c.X, a->out, c.S);
     e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "patch_fista: image");
-    if (a->energy && a->n_iter > 0) {
-        e = hipMemcpyAsync(a->energy, edev, sizeof(float) * a->n_iter, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "patch_fista: energy copy");
-        for (int i = 0; i < a->n_iter; ++i)
-            if (!std::isfinite(a->energy[i])) return fail(PYHST_ENUM, "patch_fista: non-finite energy");
+    return e == hipSuccess ? PYHST_OK : hip_fail(e, "patch_fista: image");
+}
+
+extern "C" int pyhst_patch_lipschitz(const pyhst_plan *pc, pyhst_patch_args *a, hipStream_t st)
+{
+    if (!pc || !a) return fail(PYHST_EARG, "patch_lipschitz: NULL argument");
+    PatchCall c(*pc, *a, "patch_lipschitz");
+    if (c.rc) return c.rc;
+    int rc = c.bind(st, "patch_lipschitz");
+    if (rc) return rc;
+    // power iteration on the (linear) gradient map with y = 0; Z holds the iterate
+    seed_kernel<<<grid_n(c.nw), 256, 0, st>>>(c.Z, c.nw);
+    hipError_t e = hipGetLastError();
+    for (int it = 0; it < 60 && e == hipSuccess; ++it) {
+        dot2_kernel<<<c.nblk, 256, 0, st>>>(c.Z, c.Z, c.nw, c.partials);
+        power_norm_kernel<<<1, 64, 0, st>>>(c.partials, c.nblk, c.res);
+        scale_by_norm_kernel<<<grid_n(c.nw), 256, 0, st>>>(c.Z, c.Z, c.nw, c.res);
+        e = c.gradient(c.Z, false, st);
+        if (e != hipSuccess) break;
+        dot2_kernel<<<c.nblk, 256, 0, st>>>(c.grad, c.Z, c.nw, c.partials);
+        power_norm_kernel<<<1, 64, 0, st>>>(c.partials, c.nblk, c.res);
+        e = hipMemcpyAsync(c.Z, c.grad, (size_t)c.nw * 4, hipMemcpyDeviceToDevice, st);
     }
+    double hr[2] = {0.0, 0.0};
+    if (e == hipSuccess) e = hipMemcpyAsync(hr, c.res, sizeof(hr), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "patch_lipschitz");
+    if (!(hr[0] > 0.0) || !std::isfinite(hr[0])) return fail(PYHST_ENUM, "patch_lipschitz: estimate failed");
+    a->lipschitz = 1.02 * hr[0];
+    a->n_patches = c.np;
     return PYHST_OK;
 }

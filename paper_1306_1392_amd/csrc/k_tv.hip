@@ -5,6 +5,8 @@
 // ROF prox takes two dual steps per launch through LDS, the other stencils
 // read their neighbours from L1/L2.  Reductions are deterministic:
 // per-workgroup FP64 partials, then one workgroup sums them in a fixed order.
+#include <cmath>
+
 #include "internal.hpp"
 
 namespace pyhst {
@@ -261,9 +263,9 @@ __global__ __launch_bounds__(256) void cp_q_kernel(int ny, int nx, const float *
     }
 }
 
-// out -= div(grad x)  (so that out = A^T A x + grad^T grad x)
+// out -= c div(grad x)  (so that out = A^T A x + c grad^T grad x)
 __global__ __launch_bounds__(256) void sub_divgrad_kernel(int ny, int nx, const float *__restrict__ x,
-                                                          float *__restrict__ out)
+                                                          float *__restrict__ out, float c)
 {
     const int ix = blockIdx.x * TTX + (threadIdx.x & 63);
     if (ix >= nx) return;
@@ -286,7 +288,7 @@ __global__ __launch_bounds__(256) void sub_divgrad_kernel(int ny, int nx, const 
         else if (iy == 0) b = gy;
         else if (iy == ny - 1) b = -gyu;
         else b = gy - gyu;
-        out[o] -= a + b;
+        out[o] -= c * (a + b);
     }
 }
 
@@ -452,9 +454,10 @@ hipError_t launch_cp_energy(const pyhst_plan &p, const float *ax, const float *y
     return hipGetLastError();
 }
 
-// out = K^T K x = A^T A x - div grad x (with_grad) or A^T A x ; then norm_dev = |out|^2
+// out = K^T K x = A^T A x - mu^2 div grad x (grad_scale = mu^2 > 0) or A^T A x (grad_scale = 0);
+// then norm_dev = |out|^2
 hipError_t launch_power_step(const pyhst_plan &p, const float *x, float *out, float *tmp_sino, double *partials,
-                             int n_part, double *norm_dev, int with_grad, hipStream_t st)
+                             int n_part, double *norm_dev, float grad_scale, hipStream_t st)
 {
     const GeoDev &g = p.gd[0];
     const float s2 = (float)(g.s * g.s);
@@ -463,7 +466,8 @@ hipError_t launch_power_step(const pyhst_plan &p, const float *x, float *out, fl
     e = launch_backproject(p, tmp_sino, 0, out, s2, 0.0f, nullptr, st);
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)p.n_slices * g.ny * g.nx;
-    if (with_grad) sub_divgrad_kernel<<<grid_img(p.n_slices, g.ny, g.nx), 256, 0, st>>>(g.ny, g.nx, x, out);
+    if (grad_scale > 0.0f)
+        sub_divgrad_kernel<<<grid_img(p.n_slices, g.ny, g.nx), 256, 0, st>>>(g.ny, g.nx, x, out, grad_scale);
     sumsq_partial_kernel<<<n_part, 256, 0, st>>>(n, out, partials);
     final_sum_kernel<<<1, 256, 0, st>>>(partials, n_part, nullptr, norm_dev);
     return hipGetLastError();
@@ -499,15 +503,16 @@ __global__ __launch_bounds__(256) void residual_kernel(Tables T, const float *__
     if (threadIdx.x == 0) rel[blockIdx.x] = (float)(td > 0.0 ? sqrt(tn / td) : 0.0);
 }
 
-// err[s] = sum_j row[s][j]^2 (one workgroup per slice)
-__global__ __launch_bounds__(256) void rowsq_kernel(const float *__restrict__ row, int nb, float *__restrict__ err)
+// err[s] = weight sum_j row[s][j]^2 (+ err[s] when accumulating; one workgroup per slice)
+__global__ __launch_bounds__(256) void rowsq_kernel(const float *__restrict__ row, int nb, float *__restrict__ err,
+                                                    float weight, int accumulate)
 {
     __shared__ double sh[4];
     const float *r = row + (int64_t)blockIdx.x * nb;
     double acc = 0.0;
     for (int j = threadIdx.x; j < nb; j += blockDim.x) acc += (double)r[j] * (double)r[j];
     const double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) err[blockIdx.x] = (float)t;
+    if (threadIdx.x == 0) err[blockIdx.x] = (float)((double)weight * t + (accumulate ? (double)err[blockIdx.x] : 0.0));
 }
 
 // e[s] = cos(xb_s - x0_s, xb_s) (one workgroup per slice, FP64 sums)
@@ -535,15 +540,16 @@ __global__ __launch_bounds__(256) void decoherence_kernel(Tables T, const float 
 }  // namespace pyhst
 
 extern "C" int pyhst_cv_error(const pyhst_plan *p, const float *x, const float *y, int32_t k, float *row, float *err,
-                              hipStream_t st)
+                              float weight, int32_t accumulate, hipStream_t st)
 {
     using namespace pyhst;
     if (!p || !x || !y || !row || !err) return fail(PYHST_EARG, "cv_error: NULL argument");
+    if (!std::isfinite(weight)) return fail(PYHST_EARG, "cv_error: weight must be finite");
     if (!p->uniform) return fail(PYHST_EARG, "cv_error: needs a uniform plan");
     if (k < 0 || k >= p->gd[0].K) return fail(PYHST_EARG, "cv_error: projection index out of range");
     hipError_t e = launch_forward_row(*p, x, y, k, row, st);
     if (e == hipSuccess) {
-        rowsq_kernel<<<p->n_slices, 256, 0, st>>>(row, p->gd[0].nb, err);
+        rowsq_kernel<<<p->n_slices, 256, 0, st>>>(row, p->gd[0].nb, err, weight, accumulate ? 1 : 0);
         e = hipGetLastError();
     }
     return e == hipSuccess ? PYHST_OK : hip_fail(e, "cv_error");

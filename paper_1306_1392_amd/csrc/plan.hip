@@ -189,6 +189,18 @@ int setup_geom(const pyhst_geom &in, GeoHost &h)
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
+
+int *stream_counter(const pyhst_plan &p, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(p.mu);
+    auto it = p.counter_slot.find(st);
+    if (it == p.counter_slot.end()) {
+        if (p.counter_slot.size() >= (size_t)PYHST_MAX_STREAMS) return nullptr;
+        const int slot = (int)p.counter_slot.size();
+        it = p.counter_slot.emplace(st, slot).first;
+    }
+    return p.t.counter + it->second;
+}
 }  // namespace pyhst
 
 using namespace pyhst;
@@ -348,19 +360,27 @@ int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_
     try {
         auto *p = new pyhst_plan();
         std::unique_ptr<pyhst_plan> guard(p);
-        p->n_geom = n_geom;
-        p->n_slices = n_slices;
-        p->gh.resize(n_geom);
-        for (int i = 0; i < n_geom; ++i) {
-            int rc = setup_geom(g[i], p->gh[i]);
-            if (rc) return rc;
-        }
         std::vector<int> sg(n_slices, 0);
         for (int i = 0; i < n_slices; ++i) {
             sg[i] = slice_geom ? slice_geom[i] : 0;
             if (sg[i] < 0 || sg[i] >= n_geom) return fail(PYHST_EARG, "plan_create: slice_geom out of range");
         }
         p->uniform = std::all_of(sg.begin(), sg.end(), [&](int v) { return v == sg[0]; });
+        // A uniform plan keeps only the geometry its slices use, as geometry 0: every path that
+        // assumes one geometry reads gd[0].
+        const pyhst_geom *gsrc = g;
+        if (p->uniform) {
+            gsrc = g + sg[0];
+            n_geom = 1;
+            std::fill(sg.begin(), sg.end(), 0);
+        }
+        p->n_geom = n_geom;
+        p->n_slices = n_slices;
+        p->gh.resize(n_geom);
+        for (int i = 0; i < n_geom; ++i) {
+            int rc = setup_geom(gsrc[i], p->gh[i]);
+            if (rc) return rc;
+        }
         if (const char *f = std::getenv("PYHST_FAKE_OOM"); f && f[0] == '1')
             return fail(PYHST_ENOMEM, "plan_create: allocation failure injected by PYHST_FAKE_OOM");
 
@@ -523,7 +543,7 @@ int pyhst_plan_create(const pyhst_geom *g, int32_t n_geom, const int32_t *slice_
         const size_t o_pairs = take(sizeof(int2) * pairs.size());
         size_t o_items[N_TILE_CFG];
         for (int c = 0; c < N_TILE_CFG; ++c) o_items[c] = take(sizeof(int2) * items[c].size());
-        const size_t o_cnt = take(sizeof(int) * 64);
+        const size_t o_cnt = take(sizeof(int) * PYHST_MAX_STREAMS);
         const size_t o_fpa = take(sizeof(int) * fp_members.size());
         const size_t o_fpb = take(sizeof(int2) * fp_blocks.size());
         const size_t o_fpp = take(sizeof(int4) * fp_pairs.size());
@@ -707,8 +727,8 @@ int pyhst_normalize(const pyhst_plan *p, const uint16_t *raw, const float *flats
 }
 
 int pyhst_normalize_hotspot(const pyhst_plan *p, const uint16_t *raw, const float *flats, const double *flat_pos,
-                            int32_t n_flats, const float *dark, float eps, float threshold, float *sino,
-                            hipStream_t st)
+                            int32_t n_flats, const float *dark, float eps, float threshold, int32_t halo_lo,
+                            int32_t halo_hi, float *sino, hipStream_t st)
 {
     if (!p || !raw || !flats || !flat_pos || !dark || !sino) return fail(PYHST_EARG, "normalize_hotspot: NULL argument");
     if (!p->uniform) return fail(PYHST_EARG, "normalize_hotspot: raw radiographs need a uniform plan");
@@ -717,7 +737,10 @@ int pyhst_normalize_hotspot(const pyhst_plan *p, const uint16_t *raw, const floa
         if (!(flat_pos[i] > flat_pos[i - 1]))
             return fail(PYHST_EARG, "normalize_hotspot: flat positions must increase");
     if (!(threshold >= 0.0f)) return fail(PYHST_EARG, "normalize_hotspot: threshold must be >= 0");
-    hipError_t e = launch_normalize_hotspot(*p, raw, flats, flat_pos, n_flats, dark, eps, threshold, sino, st);
+    if (halo_lo < 0 || halo_lo > 1 || halo_hi < 0 || halo_hi > 1)
+        return fail(PYHST_EARG, "normalize_hotspot: halo rows must be 0 or 1 on each side");
+    hipError_t e = launch_normalize_hotspot(*p, raw, flats, flat_pos, n_flats, dark, eps, threshold, halo_lo, halo_hi,
+                                            sino, st);
     return e == hipSuccess ? PYHST_OK : hip_fail(e, "normalize_hotspot");
 }
 
@@ -751,10 +774,11 @@ int backproject(const pyhst_plan *p, const float *sino, int32_t filtered_layout,
     return e == hipSuccess ? PYHST_OK : hip_fail(e, "backproject");
 }
 
-int forward_project(const pyhst_plan *p, const float *img, float *sino, hipStream_t st)
+int forward_project(const pyhst_plan *p, const float *img, float *sino, float alpha, hipStream_t st)
 {
     if (!p || !img || !sino) return fail(PYHST_EARG, "forward_project: NULL argument");
-    hipError_t e = launch_forward(*p, img, sino, 1.0f, nullptr, st);
+    if (!std::isfinite(alpha)) return fail(PYHST_EARG, "forward_project: alpha must be finite");
+    hipError_t e = launch_forward(*p, img, sino, alpha, nullptr, st);
     return e == hipSuccess ? PYHST_OK : hip_fail(e, "forward_project");
 }
 

@@ -16,7 +16,7 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct CpLayout {
-    size_t y, xbar, q1, q2, p, tmp, partials, energy, norm, total;
+    size_t y, xbar, q1, q2, p, ax, partials, total;
 };
 
 // Optional preprocessing of section 2.3 (hot spots, rings): the data go through a work copy y.
@@ -62,16 +62,14 @@ CpLayout cp_layout(const pyhst_plan &p, const pyhst_recon_args &a, size_t base, 
     L.q1 = take(ni * 4);
     L.q2 = take(ni * 4);
     L.p = take(ns * 4);
-    L.tmp = take(ns * 4);
+    L.ax = a.energy ? take(ns * 4) : (size_t)-1;
     L.partials = take(sizeof(double) * 1024);
-    L.energy = take(sizeof(float) * (size_t)std::max(1, a.n_iter));
-    L.norm = take(sizeof(double) * 2);
     L.total = o;
     return L;
 }
 
 struct FiLayout {
-    size_t y, r, z, xb, prox, partials, energy, norm, total;
+    size_t y, r, ax, z, xb, prox, partials, total;
 };
 
 FiLayout fista_layout(const pyhst_plan &p, const pyhst_recon_args &a, size_t base, bool need_y)
@@ -86,11 +84,33 @@ FiLayout fista_layout(const pyhst_plan &p, const pyhst_recon_args &a, size_t bas
     const size_t ni = (size_t)p.img_elems, ns = (size_t)p.sino_elems;
     L.y = need_y ? take(ns * 4) : (size_t)-1;
     L.r = take(ns * 4);
+    L.ax = a.energy ? take(ns * 4) : (size_t)-1;
     L.z = take(ni * 4);
     L.xb = take(ni * 4);
     L.prox = take(4 * ni * 4);
     L.partials = take(sizeof(double) * 1024);
-    L.energy = take(sizeof(float) * (size_t)std::max(1, a.n_iter));
+    L.total = o;
+    return L;
+}
+
+// scratch of pyhst_opnorm: two images, one sinogram, reduction partials and the norm
+struct NormLayout {
+    size_t x, y, tmp, partials, norm, total;
+};
+
+NormLayout norm_layout(const pyhst_plan &p)
+{
+    NormLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = align256(o + bytes);
+        return r;
+    };
+    L.x = take((size_t)p.img_elems * 4);
+    L.y = take((size_t)p.img_elems * 4);
+    L.tmp = take((size_t)p.sino_elems * 4);
+    L.partials = take(sizeof(double) * 1024);
     L.norm = take(sizeof(double) * 2);
     L.total = o;
     return L;
@@ -107,7 +127,7 @@ int enqueue_pre(const pyhst_plan &p, const pyhst_recon_args &a, const PreLayout 
     hipError_t e;
     if (a.raw) {
         e = a.hot_spot ? launch_normalize_hotspot(p, a.raw, a.flats, a.flat_pos, a.n_flats, a.dark, a.eps,
-                                                  a.hot_threshold, y, st)
+                                                  a.hot_threshold, a.hot_halo_lo, a.hot_halo_hi, y, st)
                        : launch_normalize(p, a.raw, a.flats, a.flat_pos, a.n_flats, a.dark, a.eps, y, st);
     } else {
         e = launch_copy(y, a.sino, p.sino_elems, st);
@@ -149,18 +169,27 @@ int enqueue_fbp(const pyhst_plan &p, const pyhst_recon_args &a, const PreLayout 
     return PYHST_OK;
 }
 
+// Chambolle-Pock for eq. (3) with K = [A; mu grad] (mu = 1: the plain operator), tau = sigma = 1/|K|.
+// The dual field of the gradient block is kept as q~ = mu q, so its step is sigma mu^2 with the bound
+// lambda and the primal step reads div q~ (the same iterates as the textbook form with q in
+// [-lambda/mu, lambda/mu]).  With energy, A x_k is carried by linearity,
+//   A x_k = (A xbar_k + A x_{k-1}) / 2   (xbar_k = 2 x_k - x_{k-1}),
+// in the projector's epilogue, and E(x_k) is summed right after it; the last iterate gets one
+// direct projection.
 int enqueue_cp(const pyhst_plan &p, const pyhst_recon_args &a, const PreLayout &PL, const CpLayout &L,
-               double op_norm, hipStream_t st)
+               hipStream_t st)
 {
     unsigned char *w = (unsigned char *)a.work;
     const float *y = PL.on ? (const float *)(w + PL.y) : a.raw ? (const float *)(w + L.y) : a.sino;
     float *x = a.out, *xbar = (float *)(w + L.xbar), *q1 = (float *)(w + L.q1), *q2 = (float *)(w + L.q2);
-    float *pd = (float *)(w + L.p), *tmp = (float *)(w + L.tmp);
+    float *pd = (float *)(w + L.p);
+    float *ax = a.energy ? (float *)(w + L.ax) : nullptr;
     double *partials = (double *)(w + L.partials);
-    float *edev = (float *)(w + L.energy);
     const int64_t ni = p.img_elems, ns = p.sino_elems;
     const float s2 = (float)(p.gd[0].s * p.gd[0].s);
-    const float tau = (float)(1.0 / op_norm), sigma = (float)(1.0 / op_norm);
+    const double mu = a.tv_mu > 0.0 ? a.tv_mu : 1.0;
+    const float tau = (float)(1.0 / a.op_norm), sigma = (float)(1.0 / a.op_norm);
+    const float sigma_q = (float)(mu * mu / a.op_norm);
     hipError_t e;
     if (PL.on) {
         int rc = enqueue_pre(p, a, PL, st);
@@ -174,22 +203,27 @@ int enqueue_cp(const pyhst_plan &p, const pyhst_recon_args &a, const PreLayout &
         if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: fill");
     }
     e = launch_fill(pd, ns, 0.0f, st);
+    if (e == hipSuccess && ax) e = launch_fill(ax, ns, 0.0f, st);
     if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: fill");
     const int npart = energy_partials(p);
     for (int it = 0; it < a.n_iter; ++it) {
-        CpDual dual{pd, y, sigma};
+        CpDual dual{pd, y, sigma, 0, ax, 0.5f, 0.5f};
         e = launch_forward(p, xbar, nullptr, 1.0f, &dual, st);
         if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: projector");
-        e = launch_cp_dual_q(p, xbar, q1, q2, sigma, a.lambda, st);
+        if (ax && it > 0) {   // ax = A x_it, x = x_it: energy of iteration it - 1
+            e = launch_cp_energy(p, ax, y, x, a.lambda, partials, npart, a.energy + it - 1, st);
+            if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: energy");
+        }
+        e = launch_cp_dual_q(p, xbar, q1, q2, sigma_q, a.lambda, st);
         if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: tv dual");
         CpPrimal prim{x, xbar, q1, q2, tau};
         e = launch_backproject(p, pd, 0, nullptr, s2, 0.0f, &prim, st);
         if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: backprojector");
-        if (a.energy) {
-            e = launch_forward(p, x, tmp, 1.0f, nullptr, st);
-            if (e == hipSuccess) e = launch_cp_energy(p, tmp, y, x, a.lambda, partials, npart, edev + it, st);
-            if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: energy");
-        }
+    }
+    if (ax && a.n_iter > 0) {
+        e = launch_forward(p, x, ax, 1.0f, nullptr, st);
+        if (e == hipSuccess) e = launch_cp_energy(p, ax, y, x, a.lambda, partials, npart, a.energy + a.n_iter - 1, st);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: energy");
     }
     return PYHST_OK;
 }
@@ -200,19 +234,22 @@ int enqueue_cp(const pyhst_plan &p, const pyhst_recon_args &a, const PreLayout &
 //   x_k = prox_{(lambda/La) TV}(z)    (tv_prox, n_inner dual iterations from zero)
 //   ISTA: z is x itself; FISTA: z = x_k + m_k (x_k - x_{k-1}) with the t_k sequence
 // The iterates alternate between out and one work buffer; the last one is copied to out if needed.
+// With energy, the projector's epilogue also carries A x_{k} = (A z + m A x_{k-1}) / (1 + m)
+// (ISTA: A x_k = A z), and E(x_k) is summed right after it; the last iterate gets one direct
+// projection.
 int enqueue_fista(const pyhst_plan &p, const pyhst_recon_args &a, const PreLayout &PL, const FiLayout &L,
-                  double op_norm, hipStream_t st)
+                  hipStream_t st)
 {
     unsigned char *w = (unsigned char *)a.work;
     const bool fast = a.method == PYHST_FISTA;
     const float *y = PL.on ? (const float *)(w + PL.y) : a.raw ? (const float *)(w + L.y) : a.sino;
     float *r = (float *)(w + L.r), *z = (float *)(w + L.z);
+    float *ax = a.energy ? (float *)(w + L.ax) : nullptr;
     float *xa = a.out, *xb = (float *)(w + L.xb), *prox = (float *)(w + L.prox);
     double *partials = (double *)(w + L.partials);
-    float *edev = (float *)(w + L.energy);
     const GeoDev &g = p.gd[0];
-    const int64_t ni = p.img_elems;
-    const double La = op_norm * op_norm;
+    const int64_t ni = p.img_elems, ns = p.sino_elems;
+    const double La = a.op_norm * a.op_norm;
     const float s2 = (float)(g.s * g.s);
     const float step = (float)(-(double)s2 / La);
     const float plam = (float)((double)a.lambda / La);
@@ -226,14 +263,19 @@ int enqueue_fista(const pyhst_plan &p, const pyhst_recon_args &a, const PreLayou
     }
     e = launch_fill(xa, ni, 0.0f, st);
     if (e == hipSuccess && fast) e = launch_fill(z, ni, 0.0f, st);
+    if (e == hipSuccess && ax) e = launch_fill(ax, ns, 0.0f, st);
     if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: fill");
     const int npart = energy_partials(p);
-    double t = 1.0;
+    double t = 1.0, m = 0.0;   // m: momentum that made the current z
     for (int it = 0; it < a.n_iter; ++it) {
         float *zin = fast ? z : xa;
-        CpDual res{r, y, 0.0f, 1};
+        CpDual res{r, y, 0.0f, 1, ax, (float)(1.0 / (1.0 + m)), (float)(m / (1.0 + m))};
         e = launch_forward(p, zin, nullptr, 1.0f, &res, st);
         if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: projector");
+        if (ax && it > 0) {   // ax = A x_it and xa = x_it: energy of iteration it - 1
+            e = launch_cp_energy(p, ax, y, xa, a.lambda, partials, npart, a.energy + it - 1, st);
+            if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: energy");
+        }
         e = launch_backproject(p, r, 0, zin, step, 1.0f, nullptr, st);
         if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: backprojector");
         float *dst = fast ? xb : xa;
@@ -241,16 +283,17 @@ int enqueue_fista(const pyhst_plan &p, const pyhst_recon_args &a, const PreLayou
         if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: tv prox");
         if (fast) {
             const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
-            e = launch_momentum(z, xb, xa, ni, (float)((t - 1.0) / tn), st);
+            m = (double)(float)((t - 1.0) / tn);
+            e = launch_momentum(z, xb, xa, ni, (float)m, st);
             if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: momentum");
             t = tn;
             std::swap(xa, xb);   // xa = x_k
         }
-        if (a.energy) {
-            e = launch_forward(p, xa, r, 1.0f, nullptr, st);
-            if (e == hipSuccess) e = launch_cp_energy(p, r, y, xa, a.lambda, partials, npart, edev + it, st);
-            if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: energy");
-        }
+    }
+    if (ax && a.n_iter > 0) {
+        e = launch_forward(p, xa, ax, 1.0f, nullptr, st);
+        if (e == hipSuccess) e = launch_cp_energy(p, ax, y, xa, a.lambda, partials, npart, a.energy + a.n_iter - 1, st);
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: energy");
     }
     if (xa != a.out) {
         e = launch_copy(a.out, xa, ni, st);
@@ -259,35 +302,56 @@ int enqueue_fista(const pyhst_plan &p, const pyhst_recon_args &a, const PreLayou
     return PYHST_OK;
 }
 
-// |[A; grad]| (with_grad) or |A| by power iteration on K^T K or A^T A (synchronises the stream once).
-// x, y: image-sized scratch; tmp: sinogram-sized scratch.
-int estimate_opnorm(const pyhst_plan &p, float *x, float *y, float *tmp, double *partials, double *nrm,
-                    int with_grad, hipStream_t st, double *out)
+// |[A; mu grad]| (with_grad) or |A| by power iteration on K^T K or A^T A (synchronises the stream once).
+int estimate_opnorm(const pyhst_plan &p, const NormLayout &L, unsigned char *w, int with_grad, double mu,
+                    hipStream_t st, double *out)
 {
     const int64_t ni = p.img_elems;
+    float *x = (float *)(w + L.x), *y = (float *)(w + L.y), *tmp = (float *)(w + L.tmp);
+    double *partials = (double *)(w + L.partials), *nrm = (double *)(w + L.norm);
     // constant start: the leading eigenvector of K^T K (dominated by A^T A) is smooth and positive
     hipError_t e = launch_fill(x, ni, 1.0f, st);
     double sq = 0.0;
     for (int it = 0; it < 50 && e == hipSuccess; ++it) {
-        e = launch_power_step(p, x, y, tmp, partials, energy_partials(p), nrm, with_grad, st);
+        e = launch_power_step(p, x, y, tmp, partials, energy_partials(p), nrm, with_grad ? (float)(mu * mu) : 0.0f,
+                              st);
         if (e == hipSuccess) e = launch_scale_by_inv(y, ni, nrm, st);
         std::swap(x, y);
     }
-    if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: power iteration");
+    if (e != hipSuccess) return hip_fail(e, "opnorm: power iteration");
     e = hipMemcpyAsync(&sq, nrm, sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: power iteration");
-    if (!(sq > 0.0) || !std::isfinite(sq)) return fail(PYHST_ENUM, "reconstruct_slices: operator norm estimate failed");
+    if (e != hipSuccess) return hip_fail(e, "opnorm: power iteration");
+    if (!(sq > 0.0) || !std::isfinite(sq)) return fail(PYHST_ENUM, "opnorm: operator norm estimate failed");
     *out = 1.02 * std::sqrt(std::sqrt(sq));   // |K^T K x| -> |K|^2; 2 % margin keeps tau sigma |K|^2 < 1
     return PYHST_OK;
 }
 
 }  // namespace
 
+extern "C" int pyhst_opnorm(const pyhst_plan *p, int32_t with_grad, double mu, void *work, size_t *work_bytes,
+                            double *norm, hipStream_t st)
+{
+    if (!p || !work_bytes) return fail(PYHST_EARG, "opnorm: NULL argument");
+    if (!p->uniform) return fail(PYHST_EARG, "opnorm: needs a uniform plan");
+    const NormLayout L = norm_layout(*p);
+    if (!work) {
+        *work_bytes = L.total;
+        return PYHST_OK;
+    }
+    if (!norm) return fail(PYHST_EARG, "opnorm: NULL norm");
+    if (!std::isfinite(mu)) return fail(PYHST_EARG, "opnorm: mu must be finite");
+    if (*work_bytes < L.total) {
+        set_error("opnorm: work buffer too small");
+        return PYHST_ENOMEM;
+    }
+    return estimate_opnorm(*p, L, (unsigned char *)work, with_grad ? 1 : 0, mu > 0.0 ? mu : 1.0, st, norm);
+}
+
 extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hipStream_t st)
 {
     if (!pc || !a) return fail(PYHST_EARG, "reconstruct_slices: NULL argument");
-    pyhst_plan &p = const_cast<pyhst_plan &>(*pc);
+    const pyhst_plan &p = *pc;
     if (a->method != PYHST_FBP && a->method != PYHST_TV_CP && a->method != PYHST_ISTA && a->method != PYHST_FISTA)
         return fail(PYHST_EARG, "reconstruct_slices: bad method");
     if (!a->raw && !a->sino) return fail(PYHST_EARG, "reconstruct_slices: need raw or sino");
@@ -298,11 +362,15 @@ extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hip
         if (!p.uniform) return fail(PYHST_EARG, "reconstruct_slices: TV needs a uniform plan");
         if (a->n_iter < 0 || !(a->lambda >= 0.0f)) return fail(PYHST_EARG, "reconstruct_slices: bad n_iter/lambda");
         if (fi && a->n_inner < 0) return fail(PYHST_EARG, "reconstruct_slices: bad n_inner");
+        if (!std::isfinite(a->tv_mu)) return fail(PYHST_EARG, "reconstruct_slices: tv_mu must be finite");
     }
     if (a->ring_width < 0) return fail(PYHST_EARG, "reconstruct_slices: ring_width must be >= 0");
     if (a->hot_spot && !a->raw) return fail(PYHST_EARG, "reconstruct_slices: the hot-spot filter needs raw input");
     if (a->hot_spot && !(a->hot_threshold >= 0.0f))
         return fail(PYHST_EARG, "reconstruct_slices: hot_threshold must be >= 0");
+    if (a->hot_halo_lo < 0 || a->hot_halo_lo > 1 || a->hot_halo_hi < 0 || a->hot_halo_hi > 1 ||
+        ((a->hot_halo_lo || a->hot_halo_hi) && !a->hot_spot))
+        return fail(PYHST_EARG, "reconstruct_slices: halo rows (0 or 1 per side) need the hot-spot filter");
     const PreLayout PL = pre_layout(p, *a);
     if (PL.on && !p.uniform) return fail(PYHST_EARG, "reconstruct_slices: preprocessing needs a uniform plan");
     CpLayout L{};
@@ -329,54 +397,43 @@ extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hip
             if (!(a->flat_pos[i] > a->flat_pos[i - 1]))
                 return fail(PYHST_EARG, "reconstruct_slices: flat positions must increase");
     }
+    if (iterative && !(a->op_norm > 0.0 && std::isfinite(a->op_norm)))
+        return fail(PYHST_EARG, "reconstruct_slices: iterative methods need op_norm > 0 (see pyhst_opnorm)");
     if (!a->work || a->work_bytes < need) {
         set_error("reconstruct_slices: work buffer too small");
         return PYHST_ENOMEM;
     }
 
-    double op_norm = a->op_norm;
-    if (iterative && !(op_norm > 0.0)) {
-        unsigned char *w = (unsigned char *)a->work;
-        int rc = cp ? estimate_opnorm(p, (float *)(w + L.xbar), (float *)(w + L.q1), (float *)(w + L.tmp),
-                                      (double *)(w + L.partials), (double *)(w + L.norm), 1, st, &op_norm)
-                    : estimate_opnorm(p, (float *)(w + F.z), (float *)(w + F.xb), (float *)(w + F.r),
-                                      (double *)(w + F.partials), (double *)(w + F.norm), 0, st, &op_norm);
-        if (rc) return rc;
-        a->op_norm = op_norm;   // report the estimate to the caller
-    }
-
     // graphs are captured on the caller's stream; the legacy null stream cannot be captured
-    const bool graphable = a->use_graph && !(iterative && a->energy) && st != nullptr;
+    const bool graphable = a->use_graph && st != nullptr;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (graphable) {
         hipError_t e = hipStreamIsCapturing(st, &cs);
         if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: hipStreamIsCapturing");
     }
     auto enqueue = [&]() {
-        return cp ? enqueue_cp(p, *a, PL, L, op_norm, st)
-                  : fi ? enqueue_fista(p, *a, PL, F, op_norm, st) : enqueue_fbp(p, *a, PL, st);
+        return cp ? enqueue_cp(p, *a, PL, L, st) : fi ? enqueue_fista(p, *a, PL, F, st) : enqueue_fbp(p, *a, PL, st);
     };
 
     if (graphable && cs == hipStreamCaptureStatusNone) {
         std::vector<uint64_t> key = {(uint64_t)a->method, (uint64_t)(uintptr_t)a->raw, (uint64_t)(uintptr_t)a->sino,
                                      (uint64_t)(uintptr_t)a->flats, (uint64_t)(uintptr_t)a->dark,
                                      (uint64_t)(uintptr_t)a->out, (uint64_t)(uintptr_t)a->work,
+                                     (uint64_t)(uintptr_t)a->energy,
                                      (uint64_t)a->n_flats, (uint64_t)a->n_iter, (uint64_t)(uintptr_t)st,
                                      (uint64_t)(fi ? a->n_inner : 0), (uint64_t)a->hot_spot,
-                                     (uint64_t)a->ring_width, (uint64_t)a->ring_object};
-        for (float f : {a->hot_threshold, a->ring_threshold}) {
+                                     (uint64_t)a->ring_width, (uint64_t)a->ring_object,
+                                     (uint64_t)a->hot_halo_lo, (uint64_t)a->hot_halo_hi};
+        for (float f : {a->hot_threshold, a->ring_threshold, a->lambda, a->eps}) {
             uint32_t fb;
             std::memcpy(&fb, &f, 4);
             key.push_back(fb);
         }
-        uint32_t lb, eb;
-        std::memcpy(&lb, &a->lambda, 4);
-        std::memcpy(&eb, &a->eps, 4);
-        uint64_t ob;
-        std::memcpy(&ob, &op_norm, 8);
-        key.push_back(lb);
-        key.push_back(eb);
-        key.push_back(ob);
+        for (double d : {iterative ? a->op_norm : 0.0, cp ? a->tv_mu : 0.0}) {
+            uint64_t db;
+            std::memcpy(&db, &d, 8);
+            key.push_back(db);
+        }
         if (a->raw)
             for (int i = 0; i < a->n_flats; ++i) {
                 uint64_t fb;
@@ -411,17 +468,5 @@ extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hip
         hipError_t e = hipGraphLaunch(it->second, st);
         return e == hipSuccess ? PYHST_OK : hip_fail(e, "reconstruct_slices: graph launch");
     }
-
-    int rc = enqueue();
-    if (rc) return rc;
-    if (iterative && a->energy && a->n_iter > 0) {
-        unsigned char *w = (unsigned char *)a->work;
-        hipError_t e = hipMemcpyAsync(a->energy, w + (cp ? L.energy : F.energy), sizeof(float) * a->n_iter,
-                                      hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices: energy copy");
-        for (int i = 0; i < a->n_iter; ++i)
-            if (!std::isfinite(a->energy[i])) return fail(PYHST_ENUM, "reconstruct_slices: non-finite energy");
-    }
-    return PYHST_OK;
+    return enqueue();
 }

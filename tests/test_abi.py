@@ -74,7 +74,12 @@ def test_null_arguments():
     L = ph.lib()
     assert L.fbp_filter(None, None, None, None) == _lib.EARG
     assert L.backproject(None, None, 0, None, 1.0, 0.0, None) == _lib.EARG
-    assert L.forward_project(None, None, None, None) == _lib.EARG
+    assert L.forward_project(None, None, None, 1.0, None) == _lib.EARG
+    assert L.pyhst_opnorm(None, 1, 1.0, None, None, None, None) == _lib.EARG
+    assert L.pyhst_patch_fista(None, None, None) == _lib.EARG
+    assert L.pyhst_patch_lipschitz(None, None, None) == _lib.EARG
+    assert L.pyhst_unet_set_scale(None, 1.0) == _lib.EARG
+    assert L.pyhst_cv_error(None, None, None, 0, None, None, 1.0, 0, None) == _lib.EARG
     assert L.tv_prox(1, 4, 4, None, None, 0.1, 10, None, 0, None) == _lib.EARG
     # too many slices: rejected on the host before any pointer is used
     assert L.tv_prox(65536, 4, 4, 16, 16, 0.1, 10, 16, 1 << 40, None) == _lib.EARG
@@ -89,3 +94,42 @@ def test_product_path_has_no_oracle_import():
             if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt and "liboracle" not in txt, f
+
+
+class _FakePlan:
+    """Stands in for a plan on the host: the wrappers validate buffers before any device call."""
+    def __init__(self, R=2, K=6, nb=8, n=8):
+        self.geom0 = ph.Geometry(n, n, nb, ph.uniform_angles(K), (nb - 1) / 2)
+        self.n_slices = R
+        self.sino_elems = R * K * nb
+        self.img_elems = R * n * n
+        self.filt_elems = self.sino_elems
+        self.uniform = True
+
+    def sino_shape(self):
+        return (self.n_slices, self.geom0.n_angles, self.geom0.n_det)
+
+    def img_shape(self):
+        return (self.n_slices, self.geom0.n_y, self.geom0.n_x)
+
+
+def test_raw_wrappers_validate_flats_and_dark():
+    """Raw input: flats [n_flats][R][n_det] and dark [R][n_det] float32, contiguous, are checked before the
+    library is called (the kernels index them by those sizes)."""
+    import torch
+    P = _FakePlan()
+    R, K, nb = 2, 6, 8
+    raw = torch.zeros((K, R, nb), dtype=torch.uint16)
+    good_f, good_d, fp = torch.zeros((2, R, nb)), torch.zeros((R, nb)), [0.0, K - 1.0]
+    bad = [(torch.zeros((2, R, nb - 1)), good_d, "flats"), (torch.zeros((1, R, nb)), good_d, "flats"),
+           (good_f.double(), good_d, "flats"), (good_f, torch.zeros((R, nb + 1)), "dark"),
+           (good_f, torch.zeros((nb, R)).t(), "dark"), (good_f, None, "dark")]
+    for f, d, name in bad:
+        for call in (lambda: ph.api.pyhst_normalize(P, raw, f, fp, d),
+                     lambda: ph.api.normalize_hotspot(P, raw, f, fp, d, 0.1),
+                     lambda: ph.reconstruct_slices(P, raw=raw, flats=f, flat_pos=fp, dark=d)):
+            with pytest.raises((ValueError, TypeError), match=name):
+                call()
+    # halo rows: raw, flats and dark then hold R + 2 rows
+    with pytest.raises(ValueError, match="raw"):
+        ph.api.normalize_hotspot(P, raw, good_f, fp, good_d, 0.1, halo=(1, 1))

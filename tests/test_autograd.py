@@ -82,6 +82,29 @@ def test_project_gradient_matches_oracle(dev):
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5
 
 
+@pytest.mark.parametrize("s", [1.0, 0.75])
+def test_backproject_and_fbp_gradients_match_oracle(dev, s):
+    """BackProject.backward = B^T g = A g / s^2 and FBP.backward = F^T B^T g = F (A g / s^2), each with A,
+    B and F from the FP64 oracle (the backward passes run entirely in the library: forward_project with
+    alpha = 1/s^2, then fbp_filter)."""
+    g, og, plan = setup(s=s, shifts=False)
+    rng = np.random.default_rng(9)
+    q = rng.random((g.n_angles, g.n_det)).astype(np.float32)
+    t = rng.random((64, 64)).astype(np.float32)
+    qt = torch.from_numpy(q)[None].to(dev).requires_grad_(True)
+    loss = 0.5 * ((ag.backproject(qt, plan) - torch.from_numpy(t)[None].to(dev)) ** 2).sum()
+    loss.backward()
+    r = oracle.backproject(q, og) - t
+    ref = oracle.forward_project(r, og) / s ** 2
+    assert np.linalg.norm(qt.grad[0].double().cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-5
+    pt = torch.from_numpy(q)[None].to(dev).requires_grad_(True)
+    loss = 0.5 * ((ag.fbp(pt, plan) - torch.from_numpy(t)[None].to(dev)) ** 2).sum()
+    loss.backward()
+    r = oracle.fbp(q, og) - t
+    ref = oracle.fbp_filter(oracle.forward_project(r, og) / s ** 2, og)[0]
+    assert np.linalg.norm(pt.grad[0].double().cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-5
+
+
 def test_gradient_descent_through_projector_reduces_residual(dev):
     """Least-squares fitting through Project (the physics in the autograd graph)."""
     g, og, plan = setup(shifts=False)

@@ -31,6 +31,13 @@ def test_cv_error_parity(dev, kind):
         np.testing.assert_allclose(got, ref, rtol=1e-4)
     with pytest.raises(ph.PyhstError):
         ph.cv_error(plan, xt, yt, K)
+    # the average over excluded projections, accumulated in the library with weight 1/count
+    ks = (0, 7, K - 1)
+    acc = torch.empty(2, device=dev, dtype=torch.float32)
+    for n, k in enumerate(ks):
+        ph.cv_error(plan, xt, yt, k, out=acc, weight=1.0 / len(ks), accumulate=n > 0)
+    ref = [np.mean([oracle.cv_error(x[s], y[s], og, k) for k in ks]) for s in range(2)]
+    np.testing.assert_allclose(acc.cpu().numpy(), ref, rtol=1e-4)
 
 
 def test_decoherence_parity(dev):

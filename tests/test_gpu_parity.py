@@ -215,11 +215,14 @@ def test_fbp_batch_equals_single(dev, gen):
         assert torch.equal(batch[i], single[0])
 
 
-def test_uniform_plan_shared_by_two_streams(dev, gen):
+@pytest.mark.parametrize("persistent", [False, True])
+def test_uniform_plan_shared_by_two_streams(dev, gen, persistent):
     """A uniform plan may serve two streams at once when each call has its own buffers: FBP and TV-CP
-    interleaved on two streams (graph and direct launches) equal the same calls made one at a time."""
+    interleaved on two streams (graph and direct launches) equal the same calls made one at a time, also
+    with the persistent backprojector (its work counter belongs to the stream)."""
     g, _ = pair(**CASES["odd_shift"])
     plan = ph.Plan(g, n_slices=2)
+    plan.set_tiles(-1, persistent)
     y = [torch.from_numpy(gen.standard_normal((2, g.n_angles, g.n_det)).astype(np.float32)).to(dev) for _ in range(2)]
     kw = [dict(method=ph.FBP), dict(method=ph.TV_CP, lam=0.02, n_iter=15, op_norm=200.0)]   # 200 > |K| here
     ref = [ph.reconstruct_slices(plan, sino=y[i], **kw[i]) for i in range(2)]
@@ -253,6 +256,22 @@ def test_graph_cache_bound(dev, gen):
                 ph.reconstruct_slices(plan, sino=y, method=ph.FBP, out=o, use_graph=True, stream=side)
     torch.cuda.synchronize()
     assert all(torch.equal(o, ref) for o in outs)
+
+
+def test_uniform_plan_on_a_later_geometry(dev, gen):
+    """A plan whose slices all use geometry 1 of two behaves as a plan of that geometry alone: the packed
+    shapes, FBP, the projector and TV-CP use its sizes, not those of geometry 0."""
+    g0, _ = pair(**CASES["wide_det"])
+    g1, og1 = pair(**CASES["odd_shift"])
+    both = ph.Plan([g0, g1], slice_geom=[1, 1])
+    only = ph.Plan(g1, n_slices=2)
+    assert both.uniform and both.sino_shape() == only.sino_shape() and both.img_shape() == only.img_shape()
+    y = torch.from_numpy(gen.random((2, g1.n_angles, g1.n_det)).astype(np.float32)).to(dev)
+    for kw in (dict(method=ph.FBP), dict(method=ph.TV_CP, lam=0.02, n_iter=5, op_norm=200.0)):
+        assert torch.equal(ph.reconstruct_slices(both, sino=y, **kw), ph.reconstruct_slices(only, sino=y, **kw))
+    x = ph.reconstruct_slices(only, sino=y, method=ph.FBP)
+    assert torch.equal(ph.forward_project(both, x), ph.forward_project(only, x))
+    assert rel(ph.reconstruct_slices(both, sino=y, method=ph.FBP)[1], oracle.fbp(y[1:].cpu().numpy(), og1)[0]) <= TOL_PIPE
 
 
 def test_uneven_plan_matches_oracle(dev, gen):

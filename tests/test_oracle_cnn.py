@@ -66,9 +66,13 @@ def test_conv_and_upconv_match_explicit_loops():
                                 for ci in range(Ci):
                                     s += x[bb, yy, xs, ci] * K[co, 3 * ty + tx, ci]
                     ref[bb, y, xx, co] = s
-    np.testing.assert_allclose(UNetOracle.conv(x, K, b), ref, atol=1e-12)
+    orc = UNetOracle(8, 2)
+    np.testing.assert_allclose(orc.conv(x, K, b), ref, atol=1e-12)
+    # the FP32-accumulation mode computes the same sums up to FP32 rounding
+    np.testing.assert_allclose(UNetOracle(8, 2, acc="fp32").conv(x, K, b), ref, rtol=0,
+                               atol=1e-5 * np.abs(ref).max())
     U = rng.standard_normal((4, Co, Ci))
-    up = UNetOracle.up(x, U, b)
+    up = orc.up(x, U, b)
     for bb in range(B):
         for y in range(2 * H):
             for xx in range(2 * W):

@@ -57,6 +57,40 @@ def test_bruteforce_8x8(K, nb, axis, shift, s):
     np.testing.assert_allclose(oracle.backproject(y, g).ravel(), M.T @ y.ravel(), rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("K,nb,axis,shift,s", [(5, 12, 5.5, False, 1.0), (7, 14, 6.25, True, 1.0), (6, 20, 9.3, True, 1.6)])
+def test_backproject_points_bruteforce(K, nb, axis, shift, s):
+    """The point-wise backprojection (used to check full-size images pixel by pixel) is the column of the
+    explicit interpolation matrix at each requested pixel, for every pixel of an 8x8 image in a shuffled
+    order with repeats."""
+    rng = np.random.default_rng(K * 10 + nb)
+    g = Geom(8, 8, nb, np.sort(rng.uniform(0, math.pi, K)), axis, rng.normal(0, 0.5, K) if shift else None,
+             pixel_size=s)
+    M = lerp_matrix(g)
+    y = rng.standard_normal((K, nb))
+    pix = np.concatenate([rng.permutation(64), rng.integers(0, 64, 20)])
+    iy, ix = pix // 8, pix % 8
+    ref = (M.T @ y.ravel())[pix]
+    np.testing.assert_allclose(oracle.backproject_points(y, g, ix, iy), ref, rtol=0, atol=1e-12)
+
+
+def test_backproject_points_equals_backproject_and_half_layout():
+    """At random pixels of a larger, uneven image the point-wise form equals the whole-image form, also on
+    the extended rows of a half-acquisition scan (the layout the FBP filter writes)."""
+    rng = np.random.default_rng(5)
+    g = Geom(61, 47, 70, np.sort(rng.uniform(0, math.pi, 33)), 33.2, rng.normal(0, 0.5, 33), pixel_size=0.8)
+    y = rng.standard_normal((33, 70))
+    full = oracle.backproject(y, g)
+    ix, iy = rng.integers(0, 61, 300), rng.integers(0, 47, 300)
+    np.testing.assert_allclose(oracle.backproject_points(y, g, ix, iy), full[iy, ix], rtol=0, atol=1e-12)
+    h = Geom(40, 40, 30, synth.uniform_angles(50, 2 * math.pi), 25.0, scan=SCAN_360_HALF)
+    lay = oracle.half_acq_layout(h)
+    ye = rng.standard_normal((50, lay["L"]))
+    full = oracle.backproject(ye, h, extended=True)
+    ix, iy = rng.integers(0, 40, 200), rng.integers(0, 40, 200)
+    np.testing.assert_allclose(oracle.backproject_points(ye, h, ix, iy, extended=True), full[iy, ix], rtol=0,
+                               atol=1e-12)
+
+
 def test_adjoint_identity():
     rng = np.random.default_rng(3)
     g = Geom(37, 29, 50, np.sort(rng.uniform(0, math.pi, 23)), 24.3, rng.normal(0, 0.5, 23), pixel_size=0.9)
@@ -358,6 +392,50 @@ def test_cp_identity_equals_rof():
     assert rel(x, u) < 1e-4
 
 
+def test_opnorm_with_scaled_gradient_matches_svd():
+    """|[A; mu grad]| (the balanced Chambolle-Pock operator) from the explicit matrices."""
+    g = Geom(8, 8, 14, synth.uniform_angles(10), 6.7, pixel_size=1.0)
+    for mu in (0.5, 3.7):
+        ref = np.linalg.norm(np.vstack([lerp_matrix(g), mu * explicit_grad(8, 8)]), 2)
+        x0 = np.random.default_rng(0).standard_normal((8, 8))
+        assert abs(oracle.opnorm(g, x0, 600, mu=mu) / ref - 1) < 1e-8, mu
+
+
+def test_cp_scaled_gradient_identity_equals_rof():
+    """With A = I and a gradient block scaled by mu, CP still solves the ROF problem (lambda TV(x) =
+    (lambda/mu) sum |mu grad x|): its limit is Chambolle's projection's."""
+    rng = np.random.default_rng(13)
+    y = rng.standard_normal((12, 12)) * 0.3 + np.kron(np.eye(2), np.ones((6, 6)))
+    lam, mu = 0.2, 0.35
+    Lk = math.sqrt(1 + 8 * mu * mu)
+    x = oracle.cp_tv(y, None, lam, 6000, Lk, identity_shape=(12, 12), mu=mu)
+    u = oracle.tv_prox(y, lam, 20000)
+    assert rel(x, u) < 1e-4
+
+
+def test_cp_balanced_reaches_the_fista_minimiser_in_300_iterations():
+    """eq. (3) on a sparse-angle noisy problem.  With K = [A; grad] and tau = sigma = 1/|K|, |A| >> |grad|
+    leaves the TV dual far from its bound after 300 iterations, so the iterate barely depends on lambda.
+    Scaling the gradient block by mu = |A|/|grad| (same minimiser) brings the 300th iterate to the
+    minimiser that FISTA, a separate code path, reaches, and the iterate then changes with lambda."""
+    N, K = 24, 16
+    g = Geom(N, N, N, synth.uniform_angles(K), (N - 1) / 2)
+    ell = synth.random_ellipses(synth.rng_for(3, 5, 0), 5)
+    y = synth.ellipse_sinogram(ell, g.angles, N, g.axis, N).numpy()
+    y = y + 0.02 * y.max() * np.random.default_rng(0).standard_normal(y.shape)
+    x0 = np.random.default_rng(1).standard_normal((N, N))
+    nA = oracle.opnorm(g, x0, 300, with_grad=False)
+    mu = nA / math.sqrt(8.0)
+    xs = {}
+    for lam in (0.3, 3.0):
+        xf = oracle.fista_tv(y, g, lam, 1500, nA ** 2 * 1.0001, 60, fast=True)
+        plain = oracle.cp_tv(y, g, lam, 300, 1.01 * oracle.opnorm(g, x0, 300))
+        xs[lam] = oracle.cp_tv(y, g, lam, 300, 1.01 * oracle.opnorm(g, x0, 300, mu=mu), mu=mu)
+        assert rel(xs[lam], xf) < 5e-3, lam
+        assert rel(plain, xf) > 4 * rel(xs[lam], xf), lam
+    assert rel(xs[0.3], xs[3.0]) > 0.1
+
+
 def test_cp_lambda0_is_least_squares():
     """With beta = 0, eq. (3) is plain least squares: CP reaches numpy's lstsq solution."""
     g = Geom(6, 6, 12, synth.uniform_angles(40), 5.7)
@@ -566,6 +644,24 @@ def test_hotspot_replaces_a_spike_by_the_neighbour_median():
     assert abs(out2[2, 1, 3] + math.log(base[2, 3] + 0.3)) < 1e-13
     np.testing.assert_array_equal(oracle.normalize_hotspot(raw, flats, fp, dark, thr=np.inf),
                                   oracle.normalize(raw, flats, fp, dark))
+
+
+def test_hotspot_chunks_with_one_row_halo_equal_the_whole_volume():
+    """The hot-spot filter's neighbourhood is 3 x 3, so rows r0..r1 of a volume are reproduced exactly by
+    filtering only rows r0-1..r1+1 (one halo row per side) and dropping the halo: chunked reconstruction
+    equals the whole volume.  Without the halo the chunk's edge rows differ (fewer neighbours)."""
+    rng = np.random.default_rng(40)
+    K, R, nb = 3, 9, 11
+    trans = 0.3 + 0.4 * rng.random((K, R, nb))
+    trans[rng.random((K, R, nb)) < 0.08] += 0.4                       # scattered hot pixels
+    raw, flats, fp, dark = _flat_setup(K, R, nb, trans)
+    whole = oracle.normalize_hotspot(raw, flats, fp, dark, thr=0.15)
+    for r0, r1 in ((0, 3), (3, 6), (6, 9)):
+        lo, hi = max(r0 - 1, 0), min(r1 + 1, R)
+        part = oracle.normalize_hotspot(raw[:, lo:hi], flats[:, lo:hi], fp, dark[lo:hi], thr=0.15)
+        np.testing.assert_array_equal(part[r0 - lo:r0 - lo + (r1 - r0)], whole[r0:r1])
+    bare = oracle.normalize_hotspot(raw[:, 3:6], flats[:, 3:6], fp, dark[3:6], thr=0.15)
+    assert not np.array_equal(bare, whole[3:6])
 
 
 def test_hotspot_even_neighbour_count_and_edges():

@@ -88,3 +88,42 @@ def test_patch_prior_beats_fbp_on_sparse_angles(dev):
     _, _, E = ph.patch_fista(plan, yt, D, m, st, 5.0, 8.0, 40, fast=False, lipschitz=plan.last_lipschitz,
                              energy=True)
     assert np.all(np.diff(E) <= 1e-5 * E[0])
+
+
+def test_patch_fista_graph_replay(dev):
+    """pyhst_patch_fista only enqueues work (tables, dictionary transpose, iterations, energies), so it can be
+    captured in a HIP graph: every replay, with eager work and synchronisations in between, equals the eager
+    call bit for bit."""
+    N, K, m, st = 48, 30, 8, 4
+    ang = synth.uniform_angles(K)
+    og = oracle.Geom(N, N, N, ang, (N - 1) / 2)
+    y = oracle.forward_project(phantom(N, 3), og) + 0.2 * synth.rng_for(11, 3, 1).standard_normal((K, N))
+    yt = torch.from_numpy(y.astype(np.float32))[None].contiguous().to(dev)
+    Dt = torch.from_numpy(dct_dictionary(m, extra=32, seed=2).astype(np.float32)).to(dev)
+    plan = ph.Plan(ph.Geometry(N, N, N, ang, (N - 1) / 2))
+    L = ph.patch_lipschitz(plan, Dt, m, st, 0.3)
+    x0, W0, E0 = ph.patch_fista(plan, yt, Dt, m, st, 0.3, 0.05, 8, lipschitz=L, energy=True)
+    out, W = torch.empty_like(x0), torch.empty_like(W0)
+    a = ph.api._patch_args(plan, yt, Dt, m, st, 0.3, 0.05, 8, True, False, L)
+    work = torch.empty(a.work_bytes, device=dev, dtype=torch.uint8)
+    E = torch.zeros(8, device=dev, dtype=torch.float32)
+    a.w, a.out, a.work, a.work_bytes, a.energy = ph.api._ptr(W), ph.api._ptr(out), ph.api._ptr(work), work.numel(), \
+        ph.api._ptr(E)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
+            ph._lib.check(ph.lib().pyhst_patch_fista(plan.handle, ph.api.ctypes.byref(a), ph.api._stream(s)),
+                          "pyhst_patch_fista")
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.fill_(float("nan"))
+        W.zero_()
+        E.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, x0) and torch.equal(W, W0), rep
+        np.testing.assert_array_equal(E.cpu().numpy(), E0)
+        ph.patch_fista(plan, yt, Dt, m, st, 0.3, 0.05, 2, lipschitz=L)      # eager work between replays

@@ -49,6 +49,30 @@ def test_hotspot_normalize_parity(dev):
     assert rel(plain, ref) > 1e-2                       # the spikes were there and were removed
 
 
+def test_hotspot_chunks_with_halo_equal_whole_volume(dev):
+    """Chunks of rows given one halo row per side (raw, flats and dark of rows r0-1 .. r1) reproduce the
+    whole-volume hot-spot filtering bit for bit, and match the oracle's whole volume."""
+    R, N, K = 6, 64, 40
+    raw, flats, flat_pos, dark, ang, axis = raw_with_spikes(R, N, K, 1)
+    geo = ph.Geometry(N, N, N, ang, axis)
+    whole = ph.normalize_hotspot(ph.Plan(geo, n_slices=R), raw.to(dev), flats.to(dev), flat_pos, dark.to(dev), 0.1)
+    ref = oracle.normalize_hotspot(raw.numpy(), flats.numpy(), flat_pos, dark.numpy(), 0.1)
+    for r0, r1 in ((0, 2), (2, 4), (4, 6)):
+        lo, hi = max(r0 - 1, 0), min(r1 + 1, R)
+        halo = (r0 - lo, hi - r1)
+        part = ph.normalize_hotspot(ph.Plan(geo, n_slices=r1 - r0), raw[:, lo:hi].contiguous().to(dev),
+                                    flats[:, lo:hi].contiguous().to(dev), flat_pos, dark[lo:hi].contiguous().to(dev),
+                                    0.1, halo=halo)
+        assert torch.equal(part, whole[r0:r1]), (r0, r1)
+        assert rel(part, ref[r0:r1]) <= TOL_OP
+        plan = ph.Plan(geo, n_slices=r1 - r0)
+        x = ph.reconstruct_slices(plan, raw=raw[:, lo:hi].contiguous().to(dev), flats=flats[:, lo:hi].contiguous().to(dev),
+                                  flat_pos=flat_pos, dark=dark[lo:hi].contiguous().to(dev), hot_threshold=0.1,
+                                  halo=halo)
+        xw = ph.reconstruct_slices(plan, sino=whole[r0:r1].contiguous())
+        assert torch.equal(x, xw), (r0, r1)
+
+
 def test_ring_filter_parity(dev):
     R, N, K = 3, 96, 60
     g = ph.Geometry(N, N, N, synth.uniform_angles(K), (N - 1) / 2)
