@@ -11,5 +11,5 @@ from ._lib import FP_AUTO, FP_BLOCKS, FP_STAGED, FP_LINES  # noqa: F401
 from .api import (  # noqa: F401
     Geometry, Plan, pyhst_normalize, normalize, fbp_filter, backproject, forward_project, tv_prox,
     reconstruct_slices, work_bytes, uniform_angles, slice_residual, cv_error, decoherence,
-    normalize_hotspot, ring_filter, patch_fista,
+    normalize_hotspot, ring_filter, patch_fista, patch_lipschitz, opnorm, balanced_mu,
 )

@@ -117,7 +117,10 @@ struct pyhst_plan {
     // caches filled by const entry points (guarded by mu)
     mutable std::mutex mu;
     mutable std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
-    mutable std::map<hipStream_t, int> counter_slot;   // persistent-work counter of each stream
+    // persistent-work counter of each stream, under its own lock: a graph capture runs with mu held and
+    // takes a counter slot inside it
+    mutable std::mutex counter_mu;
+    mutable std::map<hipStream_t, int> counter_slot;
 };
 
 namespace pyhst {

@@ -192,7 +192,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int *stream_counter(const pyhst_plan &p, hipStream_t st)
 {
-    std::lock_guard<std::mutex> lk(p.mu);
+    std::lock_guard<std::mutex> lk(p.counter_mu);
     auto it = p.counter_slot.find(st);
     if (it == p.counter_slot.end()) {
         if (p.counter_slot.size() >= (size_t)PYHST_MAX_STREAMS) return nullptr;

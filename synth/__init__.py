@@ -22,5 +22,7 @@ from .configs import (  # noqa: F401
     cfg_single_slice,
     cfg_batched_raw,
     cfg_tv_sparse,
+    cfg_uneven,
+    cfg_learned,
 )
 from .dictionary import dct_dictionary  # noqa: F401,E402
