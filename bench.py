@@ -581,9 +581,10 @@ def run_tv(args):
 
 PROFILE_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/prof_trace -o bench -- "
-             "python -u bench.py --steps 5 --warmup 2 --no-cpu-baseline --quick-data",
-    "pmc": "rocprofv3 --pmc <COUNTERS> --output-format csv -d <dir>/pmc_<name> -o pmc -- "
-           "python -u bench.py --steps 1 --warmup 1 --no-cpu-baseline --quick-data --calib-copy",
+             "python -u bench.py --steps 5 --warmup 2 --no-cpu-baseline --quick-data --profile-only",
+    "pmc": "rocprofv3 --pmc <COUNTER> --output-format csv -d <dir>/pmc_<name> -o pmc -- "
+           "python -u bench.py --steps 1 --warmup 1 --no-cpu-baseline --quick-data --profile-only --calib-copy "
+           "(one pass per counter: FETCH_SIZE, then WRITE_SIZE)",
 }
 
 
@@ -595,7 +596,7 @@ def summarize_profiles(d):
     os.makedirs(out_dir, exist_ok=True)
 
     def short(name):
-        for key in ("bp_kernel", "filter_kernel", "normalize_kernel", "copyBuffer", "fp_kernel"):
+        for key in ("bp_kernel", "filter", "normalize_kernel", "copyBuffer", "fp_kernel"):
             if key in name:
                 return name.replace("pyhst::(anonymous namespace)::", "").split("(")[0].replace("void ", "")
         return None
