@@ -287,6 +287,23 @@ typedef struct {
 
 int reconstruct_slices(const pyhst_plan *plan, pyhst_recon_args *a, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as reconstruct_slices, with its scratch taken from a per-device array
+ * of PYHST_STATIC_SCRATCH_BYTES (64 MiB) that the library's code object holds
+ * on every device it runs on until the process ends.  a->work is ignored;
+ * a->work_bytes receives the scratch the call needs; a->use_graph is ignored
+ * (plain launches; a caller may capture them itself).  The caller still owns
+ * every input and output.  The plan's device must be current.  A call needing
+ * more than PYHST_STATIC_SCRATCH_BYTES returns PYHST_ENOMEM, with the sizes in
+ * pyhst_last_error(), and enqueues nothing; out == NULL only sets
+ * a->work_bytes.  The call allocates nothing and never synchronises.  Every
+ * call on one device shares that device's array, which keeps the last call's
+ * contents (each call initialises what it reads): calls that overlap on one
+ * device (other streams, other threads) race and give undefined results. */
+enum { PYHST_STATIC_SCRATCH_BYTES = 64 << 20 };
+int reconstruct_slices_static(const pyhst_plan *plan, pyhst_recon_args *a, hipStream_t stream);
+
 /* Operator norm that the iterative methods of reconstruct_slices take as
  * op_norm (uniform plans): with_grad = 0: |A|; with_grad != 0: |[A; mu grad]|
  * (mu <= 0 means 1), by 50 power iterations on A^T A (+ mu^2 grad^T grad) of

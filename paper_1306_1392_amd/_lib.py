@@ -23,7 +23,7 @@ EXPORTS = ["pyhst_plan_create", "pyhst_plan_destroy", "pyhst_plan_slice_info", "
            "pyhst_unet_backward", "pyhst_unet_adam", "pyhst_unet_train_step", "pyhst_plan_autotune", "pyhst_slice_residual", "pyhst_unet_tensor",
            "pyhst_cv_error", "pyhst_decoherence", "pyhst_normalize_hotspot", "pyhst_ring_filter",
            "pyhst_patch_fista", "pyhst_patch_lipschitz", "pyhst_opnorm", "pyhst_unet_set_scale",
-           "pyhst_unet_get_scale"]
+           "pyhst_unet_get_scale", "reconstruct_slices_static"]
 
 
 class Geom(ctypes.Structure):
@@ -84,6 +84,7 @@ def lib(path: str = LIB_PATH):
     L.forward_project.argtypes = [P, P, P, c_float, P]
     L.tv_prox.argtypes = [c_int32, c_int32, c_int32, P, P, c_float, c_int32, P, c_size_t, P]
     L.reconstruct_slices.argtypes = [P, ctypes.POINTER(ReconArgs), P]
+    L.reconstruct_slices_static.argtypes = [P, ctypes.POINTER(ReconArgs), P]
     L.pyhst_microbench.argtypes = [c_int32, c_int32, c_int32, P, P]
     L.pyhst_unet_create.argtypes = [c_int32, c_int32, c_int32, c_int32, c_int32, ctypes.POINTER(c_void_p)]
     L.pyhst_unet_destroy.argtypes = [P]

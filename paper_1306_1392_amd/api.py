@@ -298,10 +298,13 @@ def reconstruct_slices(plan: Plan, *, raw=None, sino=None, flats=None, flat_pos=
                        method: int = FBP, lam: float = 0.0, n_iter: int = 0, op_norm: float = 0.0,
                        n_inner: int = 20, energy: bool = False, out=None, work=None, use_graph: bool = False,
                        hot_threshold: float | None = None, ring_width: int = 0,
-                       ring_object_threshold: float | None = None, tv_mu: float = 1.0, halo=(0, 0), stream=None):
+                       ring_object_threshold: float | None = None, tv_mu: float = 1.0, halo=(0, 0), stream=None,
+                       no_alloc: bool = False):
     """Returns out (and the energy trace as a numpy array when energy=True).  op_norm is |[A; tv_mu grad]| for
     TV_CP and |A| for ISTA/FISTA; <= 0: computed first by opnorm() (a separate, synchronising call), then
-    available as plan.last_op_norm.  halo: raw rows before / after the plan's (hot-spot filter only)."""
+    available as plan.last_op_norm.  halo: raw rows before / after the plan's (hot-spot filter only).
+    no_alloc: call reconstruct_slices_static (scratch from the library's per-device array, at most
+    PYHST_STATIC_SCRATCH_BYTES; work and use_graph are not used)."""
     iterative = method in (TV_CP, ISTA, FISTA)
     if raw is not None:
         if flat_pos is None:
@@ -337,6 +340,13 @@ def reconstruct_slices(plan: Plan, *, raw=None, sino=None, flats=None, flat_pos=
         E = torch.zeros(max(n_iter, 1), device=dev, dtype=torch.float32)
         a.energy = _ptr(E)
     L = _lib.lib()
+    if no_alloc:
+        if out is None:
+            out = torch.empty(plan.img_shape(), device=dev, dtype=torch.float32)
+        _need(out, plan.img_elems, "out")
+        a.out = _ptr(out)
+        check(L.reconstruct_slices_static(plan.handle, ctypes.byref(a), _stream(stream)), "reconstruct_slices_static")
+        return _finish(plan, a, out, E, energy, n_iter, stream)
     # size query
     a.out = None
     check(L.reconstruct_slices(plan.handle, ctypes.byref(a), _stream(stream)), "reconstruct_slices(query)")
@@ -350,6 +360,10 @@ def reconstruct_slices(plan: Plan, *, raw=None, sino=None, flats=None, flat_pos=
     a.work = _ptr(work)
     a.work_bytes = work.numel() * work.element_size()
     check(L.reconstruct_slices(plan.handle, ctypes.byref(a), _stream(stream)), "reconstruct_slices")
+    return _finish(plan, a, out, E, energy, n_iter, stream)
+
+
+def _finish(plan, a, out, E, energy, n_iter, stream):
     plan.last_op_norm = a.op_norm
     if not energy:
         return out

@@ -470,3 +470,60 @@ extern "C" int reconstruct_slices(const pyhst_plan *pc, pyhst_recon_args *a, hip
     }
     return enqueue();
 }
+
+// ---- allocation-free variant ----------------------------------------------------------------
+// Scratch of reconstruct_slices_static: one copy per device in the code object.  In host code the
+// name is only a stand-in; the device address of each device's copy comes from hipGetSymbolAddress
+// (first call on that device, with it current) and only that address reaches kernels.
+static __device__ __align__(256) unsigned char scratch[PYHST_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+int device_scratch(int dev, void **out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(PYHST_EARG, "reconstruct_slices_static: device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "reconstruct_slices_static: hipGetSymbolAddress");
+        if (!ptr) return fail(PYHST_EHIP, "reconstruct_slices_static: no device address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PYHST_OK;
+}
+}  // namespace
+
+extern "C" int reconstruct_slices_static(const pyhst_plan *pc, pyhst_recon_args *a, hipStream_t st)
+{
+    if (!pc || !a) return fail(PYHST_EARG, "reconstruct_slices_static: NULL argument");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "reconstruct_slices_static: hipGetDevice");
+    if (dev != pc->device) return fail(PYHST_EARG, "reconstruct_slices_static: the plan's device must be current");
+    pyhst_recon_args q = *a;
+    q.out = nullptr;   // size query: validates the method and fills work_bytes, enqueues nothing
+    q.work = nullptr;
+    q.work_bytes = 0;
+    int rc = reconstruct_slices(pc, &q, st);
+    if (rc) return rc;
+    a->work_bytes = q.work_bytes;
+    if (q.work_bytes > (size_t)PYHST_STATIC_SCRATCH_BYTES)
+        return fail(PYHST_ENOMEM, "reconstruct_slices_static: the call needs " + std::to_string(q.work_bytes) +
+                                      " bytes of scratch, more than the static " +
+                                      std::to_string((size_t)PYHST_STATIC_SCRATCH_BYTES) +
+                                      " bytes; use reconstruct_slices with a work buffer");
+    if (!a->out) return PYHST_OK;
+    void *ptr = nullptr;
+    rc = device_scratch(dev, &ptr);
+    if (rc) return rc;
+    q = *a;
+    q.work = ptr;
+    q.work_bytes = (size_t)PYHST_STATIC_SCRATCH_BYTES;
+    q.use_graph = 0;
+    return reconstruct_slices(pc, &q, st);
+}
