@@ -363,8 +363,32 @@ template <int NC> struct FpStaged {
 struct StagedProj {
     double u_first, slope, rho, blk_lo;   // crossing at line 0, per line, 1/|a|; lowest first candidate
     float af, slopef, c0;                 // a, slope, a - sign(a) in FP32
+    float aa, c1, c2;                     // |a|, 2|a| - 1, 2 - 3|a| (closed-form weights of three candidates)
     int k;
 };
+
+// One line of a staged projection from v = u - 1/|a| (u: the bin's crossing, in positions from the
+// line's staged base).  The candidates are floor(v) + 1 + n, n = 0, 1, 2, at offsets
+// t - j = d_n = +-(|a| (1 + n - f) - 1), f = fract(v) (the sign is that of a, and only |d_n| enters).
+// With 2/3 <= |a| <= 1 (UNIT) the three hat weights 1 - |d_n| are, without any case:
+//   w0 = |a| (1 - f)                 (d_0 in (-1, 0])
+//   w1 = 1 - | |a| (2 - f) - 1 |     (|d_1| <= 1)
+//   w2 = max(0, 2 - 3 |a| + |a| f)   (d_2 > 0)
+// one FMA each, plus the absolute difference of w1 and the clamp of w2 as output modifiers.
+template <int NC, bool UNIT>
+__device__ __forceinline__ float staged_line(const float *line, float v, const StagedProj &q, float acc)
+{
+    int fl;   // floor(v) converted in one instruction (|v| stays below a few hundred positions)
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(fl) : "v"(v));
+    const float f = __builtin_amdgcn_fractf(v);
+    const float *row = line + fl + 1;
+    if (NC == 3 && UNIT) {
+        acc = fmaf(fmaf(-q.aa, f, q.aa), row[0], acc);
+        acc = fmaf(1.0f - fabsf(fmaf(-q.aa, f, q.c1)), row[1], acc);
+        return fmaf(__builtin_amdgcn_fmed3f(fmaf(q.aa, f, q.c2), 0.0f, 1.0f), row[2], acc);
+    }
+    return hat_line<NC, UNIT>(row, fmaf(-q.af, f, q.c0), q.af, acc);
+}
 
 __device__ __forceinline__ StagedProj staged_proj(const Tables &T, const GeoDev &g, int k, int j, int j0,
                                                   bool &rows)
@@ -388,6 +412,9 @@ __device__ __forceinline__ StagedProj staged_proj(const Tables &T, const GeoDev 
     q.af = (float)a;
     q.slopef = (float)q.slope;
     q.c0 = q.af - copysignf(1.0f, q.af);
+    q.aa = fabsf(q.af);
+    q.c1 = 2.0f * q.aa - 1.0f;
+    q.c2 = 2.0f - 3.0f * q.aa;
     return q;
 }
 
@@ -437,9 +464,11 @@ __device__ __forceinline__ void fp_staged_body(const Tables &T, const SliceDev &
         for (int i = 0; i < F::PER; ++i) stage[buf][sr * F::LD + sp + 16 * i] = v[i];
     };
 
-    float acc[P];
+    float acc[P][FP_RB / 4];
 #pragma unroll
-    for (int p = 0; p < P; ++p) acc[p] = 0.0f;
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int m = 0; m < FP_RB / 4; ++m) acc[p][m] = 0.0f;
     int seg_cur, seg_next = 0;
     load(0, seg_cur);
     store(0);
@@ -459,21 +488,16 @@ __device__ __forceinline__ void fp_staged_body(const Tables &T, const SliceDev &
             remv[p] = (float)(ub - ubase - pr[p].rho);         // u - 1/|a| at the block's first line
             base[p] = stage[b & 1] + ((int)ubase - seg_cur) + wv * F::LD;
         }
+        // one accumulation chain per (projection, line slot m): the chains of a block are independent, so
+        // the reads of all its lines (and of every projection of the group) issue together
         if (l0 + FP_RB <= n_lines) {
-            // a whole block: no branch between the lines, so the reads of all of them (and of every
-            // projection of the group) issue together; one partial sum per line, added in line order
-            float part_l[P][FP_RB / 4];
+            // a whole block: no branch between the lines
 #pragma unroll
             for (int p = 0; p < P; ++p)
 #pragma unroll
-                for (int m = 0; m < FP_RB / 4; ++m) {
-                    const FirstCand fc = first_cand(fmaf((float)(wv + 4 * m), pr[p].slopef, remv[p]), pr[p].af, pr[p].c0);
-                    part_l[p][m] = hat_line<NC, UNIT>(base[p] + 4 * m * F::LD + fc.idx, fc.d, pr[p].af, 0.0f);
-                }
-#pragma unroll
-            for (int p = 0; p < P; ++p)
-#pragma unroll
-                for (int m = 0; m < FP_RB / 4; ++m) acc[p] += part_l[p][m];
+                for (int m = 0; m < FP_RB / 4; ++m)
+                    acc[p][m] = staged_line<NC, UNIT>(base[p] + 4 * m * F::LD,
+                                                      fmaf((float)(wv + 4 * m), pr[p].slopef, remv[p]), pr[p], acc[p][m]);
         } else {
 #pragma unroll
             for (int p = 0; p < P; ++p)
@@ -481,8 +505,8 @@ __device__ __forceinline__ void fp_staged_body(const Tables &T, const SliceDev &
                 for (int m = 0; m < FP_RB / 4; ++m) {
                     const int r = wv + 4 * m;
                     if (l0 + r >= n_lines) break;             // uniform
-                    const FirstCand fc = first_cand(fmaf((float)r, pr[p].slopef, remv[p]), pr[p].af, pr[p].c0);
-                    acc[p] = hat_line<NC, UNIT>(base[p] + 4 * m * F::LD + fc.idx, fc.d, pr[p].af, acc[p]);
+                    acc[p][m] = staged_line<NC, UNIT>(base[p] + 4 * m * F::LD, fmaf((float)r, pr[p].slopef, remv[p]),
+                                                      pr[p], acc[p][m]);
                 }
         }
         if (more) {
@@ -491,16 +515,23 @@ __device__ __forceinline__ void fp_staged_body(const Tables &T, const SliceDev &
         }
         __syncthreads();
     }
+    float tot[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        tot[p] = acc[p][0];
+#pragma unroll
+        for (int m = 1; m < FP_RB / 4; ++m) tot[p] += acc[p][m];
+    }
     if (wv > 0) {
 #pragma unroll
-        for (int p = 0; p < P; ++p) part[p][wv - 1][lane] = acc[p];
+        for (int p = 0; p < P; ++p) part[p][wv - 1][lane] = tot[p];
     }
     __syncthreads();
     if (wv > 0 || j >= nb) return;
     const float sc = alpha * (float)(g.s * g.s);   // A = s^2 B^T
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const float sum = ((acc[p] + part[p][0][lane]) + part[p][1][lane]) + part[p][2][lane];
+        const float sum = ((tot[p] + part[p][0][lane]) + part[p][1][lane]) + part[p][2][lane];
         const int64_t o = sd.sino_off + (int64_t)pr[p].k * nb + j;
         fp_store<MODE>(cp, out, o, sc * sum, (int64_t)slice * nb + j);
     }

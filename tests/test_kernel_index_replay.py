@@ -128,6 +128,21 @@ def test_fp_staging_bounds(cap):
     assert paired > 100   # most cases group most of their projections
 
 
+def test_fp_three_candidate_closed_form_weights():
+    """The staged projector's weights for three candidates and 2/3 <= |a| <= 1, from f = fract(u - 1/|a|):
+    w0 = |a| (1 - f), w1 = 1 - | |a| (2 - f) - 1 |, w2 = max(0, 2 - 3|a| + |a| f) equal the hat
+    max(0, 1 - |d_n|) at the offsets d_n = |a| (1 + n - f) - 1 (in FP64, on a grid with the end points),
+    and the candidates just before and after them have zero weight."""
+    aa = np.concatenate([np.linspace(2.0 / 3.0, 1.0, 401), np.random.default_rng(1).uniform(2.0 / 3.0, 1.0, 4000)])
+    f = np.concatenate([np.linspace(0.0, 1.0 - 2.0 ** -24, 257), np.random.default_rng(2).uniform(0.0, 1.0, 4000)])
+    A, F = np.meshgrid(aa, f, indexing="ij")
+    hat = lambda n: np.maximum(0.0, 1.0 - np.abs(A * (1 + n - F) - 1.0))
+    np.testing.assert_allclose(A * (1.0 - F), hat(0), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(1.0 - np.abs(A * (2.0 - F) - 1.0), hat(1), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(np.clip(2.0 - 3.0 * A + A * F, 0.0, 1.0), hat(2), rtol=0, atol=1e-14)
+    assert hat(-1).max() < 1e-12 and hat(3).max() < 1e-12
+
+
 # ------------------------------------------------------------------ fused ROF dual steps
 FTX, FTY = 64, 16
 FRX, FRY = FTX + 4, FTY + 4
