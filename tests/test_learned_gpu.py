@@ -1,16 +1,21 @@
 """The learned corrector, trained by the library's own kernels on phantoms the
-method itself generates, improves on plain FBP; its data-consistency check
-sends inconsistent data to the TV mode."""
+method itself generates: as shipped (FBP + U-Net with its data scale, the
+data-consistency check and the TV fallback) it improves on plain FBP, matches the
+TV mode of eq. (3) with a calibrated weight within 5 % RMSE at 20 times its
+slices/s, and sends inconsistent data to the TV mode."""
 import numpy as np
 import pytest
 import torch
 
 import synth
 import paper_1306_1392_amd as ph
-from paper_1306_1392_amd.cnn import UNet, init_params
+from paper_1306_1392_amd import corrector as cr
+from paper_1306_1392_amd.cnn import UNet, init_params, layer_table
 from paper_1306_1392_amd.corrector import Corrector
 
 pytestmark = pytest.mark.gpu
+
+SCALE = 10.0
 
 
 def make(indices, stream, N, K, B, plan_hi, plan_b, dev):
@@ -24,34 +29,80 @@ def make(indices, stream, N, K, B, plan_hi, plan_b, dev):
     return torch.cat(xs), torch.cat(ts), torch.cat(ys)
 
 
-def test_trained_corrector_beats_fbp_and_falls_back(dev):
-    N, K, B, SCALE = 128, 30, 16, 10.0
+def setup(dev, N, K, B):
     ang = np.arange(K) * (np.pi / K)
     geo = ph.Geometry(N, N, N, ang, (N - 1) / 2)
     plan_b = ph.Plan(geo, n_slices=B)
     plan_hi = ph.Plan(ph.Geometry(2 * N, 2 * N, N, ang, (N - 1) / 2, pixel_size=0.5))
-    xtr, ttr, _ = make(np.arange(512), 0, N, K, B, plan_hi, plan_b, dev)
-    xte, tte, yte = make(np.arange(32), 1, N, K, B, plan_hi, plan_b, dev)
-    net = UNet(B, N, N, 16, 3)
-    net.set_params(init_params(16, 3, 0))
-    rng = np.random.default_rng(0)
-    steps = 400
-    for st in range(steps):
-        idx = torch.as_tensor(rng.choice(xtr.shape[0], B, replace=False), device=dev)
-        lr = 2e-3 * 0.5 * (1 + np.cos(np.pi * st / steps))
-        net.train_step((xtr[idx] * SCALE).contiguous(), (ttr[idx] * SCALE).contiguous(), lr)
-    out = torch.cat([net.forward((xte[i:i + B] * SCALE).contiguous()) / SCALE for i in range(0, 32, B)])
-    rmse_fbp = float(torch.sqrt(((xte - tte) ** 2).mean()))
-    rmse_cnn = float(torch.sqrt(((out - tte) ** 2).mean()))
-    assert rmse_cnn < 0.85 * rmse_fbp, (rmse_cnn, rmse_fbp)
+    return geo, plan_b, plan_hi
+
+
+def test_corrector_applies_the_network_with_its_scale(dev):
+    """Corrector output = FBP + f(SCALE FBP) / SCALE, the same numbers as the network with scale 1
+    applied to SCALE x FBP by hand (SCALE a power of two, so the scalings are exact)."""
+    N, K, B, c = 64, 24, 4, 8.0
+    geo, plan_b, plan_hi = setup(dev, N, K, B)
+    _, _, y = make(np.arange(B), 3, N, K, B, plan_hi, plan_b, dev)
+    p = init_params(8, 3, 5)
+    rows, _ = layer_table(8, 3)
+    _, _, _, _, w, b = rows[-1]                  # the 1x1 head: non-zero, so the correction is not zero
+    p[w:b + 1] = np.random.default_rng(5).normal(0.0, 0.1, b + 1 - w)
+    corr = Corrector(geo, B, p, base=8, levels=3, scale=c)
+    x, r = corr.correct(y.contiguous())
+    plain = UNet(B, N, N, 8, 3)
+    plain.set_params(p)
+    fbp = ph.reconstruct_slices(plan_b, sino=y.contiguous(), method=ph.FBP)
+    ref = plain.forward((fbp * c).contiguous()) / c
+    assert torch.equal(x, ref)
+    ax = ph.forward_project(plan_b, ref.contiguous())
+    assert torch.equal(r, ph.slice_residual(plan_b, ax, y.contiguous()))
+
+
+def test_trained_corrector_against_tv_and_fallback(dev):
+    """Reduced learned workload (128^2, 30 projections, Poisson 1e4): U-Net (4 levels, 32 base) trained
+    on 2048 phantoms for 2400 steps; TV by FISTA, 300 iterations, lambda calibrated on 32 validation
+    phantoms; 64 test phantoms.  Measured at these settings: corrector RMSE 0.94 of TV's, 23x its
+    slices/s (both sides launch-bound at this size)."""
+    N, K, B = 128, 30, 32
+    geo, plan_b, plan_hi = setup(dev, N, K, B)
+    xtr, ttr, _ = make(np.arange(2048), 0, N, K, B, plan_hi, plan_b, dev)
+    xva, tva, yva = make(np.arange(32), 2, N, K, B, plan_hi, plan_b, dev)
+    xte, tte, yte = make(np.arange(64), 1, N, K, B, plan_hi, plan_b, dev)
+    net = UNet(B, N, N, 32, 4)
+    net.set_params(init_params(32, 4, 0))
+    net.set_scale(SCALE)
+    cr.train(net, xtr, ttr, steps=2400, lr=1e-3)
+    del xtr, ttr
+    lam, cal, norm, mu = cr.calibrate_tv_lambda(geo, yva, tva, method=ph.FISTA)
+    corr = Corrector.from_net(geo, net, tv_lambda=lam, tv_iters=300, tv_method=ph.FISTA, op_norm=norm)
+    corr.calibrate(yva)
+    x_c, fell = corr.reconstruct_all(yte)
+    plan_te = ph.Plan(geo, n_slices=yte.shape[0])
+    x_tv = ph.reconstruct_slices(plan_te, sino=yte.contiguous(), method=ph.FISTA, lam=lam, n_iter=300,
+                                 op_norm=norm, n_inner=10)
+    r_fbp, r_c, r_tv = cr.rmse(xte, tte), cr.rmse(x_c, tte), cr.rmse(x_tv, tte)
+    print(f"learned: RMSE FBP {r_fbp:.4g}, corrector {r_c:.4g}, TV {r_tv:.4g} (lambda {lam}); "
+          f"{int(fell.sum())} fallbacks", flush=True)
+    assert r_c < 0.5 * r_fbp, (r_c, r_fbp)
+    assert r_c <= 1.05 * r_tv, (r_c, r_tv, lam, cal)
+
+    # throughput: the corrector as shipped over the test set vs the TV mode on it
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    e[0].record()
+    for i in range(0, yte.shape[0], B):
+        corr.reconstruct(yte[i:i + B])
+    e[1].record()
+    ph.reconstruct_slices(plan_te, sino=yte.contiguous(), method=ph.FISTA, lam=lam, n_iter=300, op_norm=norm,
+                          n_inner=10)
+    e[2].record()
+    torch.cuda.synchronize()
+    ratio = e[1].elapsed_time(e[2]) / e[0].elapsed_time(e[1])
+    print(f"learned: corrector {ratio:.1f}x the slices/s of TV", flush=True)
+    assert ratio >= 20.0, ratio
 
     # data-consistency fallback: consistent test data pass, corrupted data go to TV
-    params = net.get_params()
-    corr = Corrector(geo, B, params, base=16, levels=3, tv_lambda=1e-3, tv_iters=30)
-    corr.net = net      # same weights; the corrector applies the network to SCALE-free FBP input
     y = yte[:B].contiguous()
-    _, r = corr.correct(y * 1.0)
-    corr.dc_threshold = 1.5 * float(r.max())
     bad = y.clone()
     bad[: B // 2] += 0.5 * float(y.max()) * torch.randn_like(bad[: B // 2])
     x, fell = corr.reconstruct(bad)
