@@ -21,24 +21,45 @@ namespace {
 
 constexpr int AB = 32;   // projections staged per LDS block
 
+// Window length bound of the pipelined angle loop: the widest window of a tile at pixel size <= 1,
+// floor(sqrt((TW-1)^2 + (TH-1)^2)) + 4 rounded up to even (the plan's bp_w for that tile).  Plans
+// whose windows are longer (pixels larger than a bin) take the plain loop.
+constexpr int pipe_wmax(int c)
+{
+    int r = 0;
+    const int d2 = (tile_w(c) - 1) * (tile_w(c) - 1) + (tile_h(c) - 1) * (tile_h(c) - 1);
+    while ((r + 1) * (r + 1) <= d2) ++r;
+    return (r + 4) + ((r + 4) & 1);
+}
+// window elements each thread carries in registers from one block to the next
+constexpr int pipe_elems(int c) { return (TILE_AG[c] * AB * pipe_wmax(c) + 256 * TILE_AG[c] - 1) / (256 * TILE_AG[c]); }
+
 // The per-projection table is read through the constant address space so that
 // the wave-uniform loads become scalar loads into SGPRs.
 typedef __attribute__((address_space(4))) const float cfloat;
 
-template <int CFG, int MODE>
+// PIPE: the windows of the next block of projections are loaded into registers while the current
+// block is summed (two LDS window buffers of wstride entries, three parameter slots, one barrier per
+// block), so the L2 / HBM latency of the staging loads overlaps the sums.  It pays where a launch has
+// few workgroups per CU (a single slice in the iterative solvers, after a projector whose sweep of the
+// image has evicted the sinogram from every L2): the 32 x 32 tiles; the larger tiles, chosen when there
+// are at least four workgroups per CU, keep the plain loop (their accumulators leave few registers).
+template <int CFG, int MODE, bool PIPE>
 __global__ __launch_bounds__(256 * TILE_AG[CFG]) void bp_kernel(Tables T, const float *__restrict__ sino,
                                                                 int filtered, float *__restrict__ img, float alpha,
                                                                 float beta, int64_t n_items, int *counter,
-                                                                int xcd_remap, CpPrimal cp)
+                                                                int xcd_remap, CpPrimal cp, int wstride)
 {
     constexpr int BX = TILE_BX[CFG], BY = TILE_BY[CFG];
     constexpr int TW = 8 * BX, TH = 32 * BY;
     constexpr int PX = BX * BY;
     constexpr int AG = TILE_AG[CFG];        // angle groups; a staged block holds AG x AB projections
     constexpr int NT = 256 * AG;            // threads per workgroup
-    extern __shared__ float2 win[];   // [AG AB][W]
-    __shared__ int s_jb[AG * AB];
-    __shared__ float s_r[AG * AB];
+    constexpr int ABLK = AG * AB;           // projections per staged block
+    constexpr int NSLOT = PIPE ? 3 : 1;
+    extern __shared__ float2 win[];   // [PIPE ? 2 : 1][wstride]: [AG AB][W] per buffer
+    __shared__ int s_jb[NSLOT][ABLK];
+    __shared__ float s_r[NSLOT][ABLK];
     __shared__ int64_t s_item;
 
     const int tid = threadIdx.x;
@@ -90,34 +111,26 @@ __global__ __launch_bounds__(256 * TILE_AG[CFG]) void bp_kernel(Tables T, const 
 #pragma unroll
         for (int p = 0; p < PX; ++p) acc[p] = 0.0f;
 
-        for (int kb = 0; kb < K; kb += AG * AB) {
-            const int na = min(AG * AB, K - kb);
+        // window base and FP32 remainder of the tile origin for projections kb .. kb + ABLK - 1
+        auto params = [&](int kb, int slot) {
+            const int na = min(ABLK, K - kb);
             if (tid < na) {
                 const int k = kb + tid;
                 const double c = cosd[k], sn = sind[k];
                 const double torg = axis + shd[k] + s * (x0 * c + y0 * sn);
                 const double tmin = torg + s * ((TW - 1) * fmin(c, 0.0) + (TH - 1) * fmin(sn, 0.0));
                 const int jb = (int)floor(tmin) - 1;
-                s_jb[tid] = jb;
-                s_r[tid] = (float)(torg - (double)jb);
+                s_jb[slot][tid] = jb;
+                s_r[slot][tid] = (float)(torg - (double)jb);
             }
-            __syncthreads();
-            const int tot = na * W;
-            for (int e = tid; e < tot; e += NT) {
-                const int a = (int)(((float)e + 0.5f) * invW);
-                const int j = s_jb[a] + (e - a * W);
-                const float *row = rows + (int64_t)(kb + a) * L;
-                const float q0 = ((unsigned)j < (unsigned)L) ? row[j] : 0.0f;
-                const float q1 = ((unsigned)(j + 1) < (unsigned)L) ? row[j + 1] : 0.0f;
-                win[e] = make_float2(q0, q1 - q0);
-            }
-            __syncthreads();
-            // angle group ag sums projections [ag AB, ag AB + AB) of the staged block
+        };
+        // angle group ag sums projections [ag AB, ag AB + AB) of the staged block
+        auto sum_block = [&](const float2 *wb, const float *sr, int kb, int na) {
             const int a_end = AG > 1 ? min(na, (ag + 1) * AB) : na;
             for (int a = ag * AB; a < a_end; ++a) {
                 const cfloat *tk = tab + (int64_t)(kb + a) * BPT;
-                const float t0 = fmaf(fly, tk[1], fmaf(flx, tk[0], s_r[a]));
-                const float2 *wa = win + a * W;
+                const float t0 = fmaf(fly, tk[1], fmaf(flx, tk[0], sr[a]));
+                const float2 *wa = wb + a * W;
 #pragma unroll
                 for (int by = 0; by < BY; ++by) {
 #pragma unroll
@@ -132,7 +145,72 @@ __global__ __launch_bounds__(256 * TILE_AG[CFG]) void bp_kernel(Tables T, const 
                     }
                 }
             }
+        };
+
+        if constexpr (!PIPE) {
+            for (int kb = 0; kb < K; kb += ABLK) {
+                const int na = min(ABLK, K - kb);
+                params(kb, 0);
+                __syncthreads();
+                const int tot = na * W;
+                for (int e = tid; e < tot; e += NT) {
+                    const int a = (int)(((float)e + 0.5f) * invW);
+                    const int j = s_jb[0][a] + (e - a * W);
+                    const float *row = rows + (int64_t)(kb + a) * L;
+                    const float q0 = ((unsigned)j < (unsigned)L) ? row[j] : 0.0f;
+                    const float q1 = ((unsigned)(j + 1) < (unsigned)L) ? row[j + 1] : 0.0f;
+                    win[e] = make_float2(q0, q1 - q0);
+                }
+                __syncthreads();
+                sum_block(win, s_r[0], kb, na);
+                __syncthreads();
+            }
+        } else {
+            // W <= pipe_wmax(CFG) (checked by the host), so a block's na W <= ABLK W entries take at most
+            // E per thread
+            constexpr int E = pipe_elems(CFG);
+            float q0r[E], q1r[E];
+            const int nblk = (K + ABLK - 1) / ABLK;
+            auto gload = [&](int b, int slot) {
+                const int kb = b * ABLK, tot = min(ABLK, K - kb) * W;
+#pragma unroll
+                for (int i = 0; i < E; ++i) {
+                    const int e = tid + i * NT;
+                    q0r[i] = 0.0f;
+                    q1r[i] = 0.0f;
+                    if (e < tot) {
+                        const int a = (int)(((float)e + 0.5f) * invW);
+                        const int j = s_jb[slot][a] + (e - a * W);
+                        const float *row = rows + (int64_t)(kb + a) * L;
+                        if ((unsigned)j < (unsigned)L) q0r[i] = row[j];
+                        if ((unsigned)(j + 1) < (unsigned)L) q1r[i] = row[j + 1];
+                    }
+                }
+            };
+            auto lstore = [&](int b, float2 *wb) {
+                const int tot = min(ABLK, K - b * ABLK) * W;
+#pragma unroll
+                for (int i = 0; i < E; ++i) {
+                    const int e = tid + i * NT;
+                    if (e < tot) wb[e] = make_float2(q0r[i], q1r[i] - q0r[i]);
+                }
+            };
+            params(0, 0);
+            if (nblk > 1) params(ABLK, 1);
             __syncthreads();
+            gload(0, 0);
+            lstore(0, win);
+            __syncthreads();
+            for (int b = 0; b < nblk; ++b) {
+                // slot (b + 2) % 3 was last read before the barrier that ended block b - 1
+                if (b + 1 < nblk) gload(b + 1, (b + 1) % 3);
+                if (b + 2 < nblk) params((b + 2) * ABLK, (b + 2) % 3);
+                const int kb = b * ABLK;
+                sum_block(win + (b & 1) * wstride, s_r[b % 3], kb, min(ABLK, K - kb));
+                // buffer (b + 1) & 1 was last read while summing block b - 1, before that barrier too
+                if (b + 1 < nblk) lstore(b + 1, win + ((b + 1) & 1) * wstride);
+                __syncthreads();
+            }
         }
 
         if constexpr (AG > 1) {
@@ -191,20 +269,18 @@ __global__ __launch_bounds__(256 * TILE_AG[CFG]) void bp_kernel(Tables T, const 
 
 __global__ void zero_counter(int *c) { *c = 0; }
 
-template <int CFG, int MODE>
-hipError_t launch_cfg(const pyhst_plan &p, const float *sino, int filtered, float *img, float alpha, float beta,
-                      const CpPrimal &cp, hipStream_t st)
+template <int CFG, int MODE, bool PIPE>
+hipError_t launch_kernel(const pyhst_plan &p, const float *sino, int filtered, float *img, float alpha, float beta,
+                         const CpPrimal &cp, int wmax, hipStream_t st)
 {
-    int wmax = 0;
-    for (const auto &g : p.gd) wmax = std::max(wmax, g.bp_w[CFG]);
     constexpr int AG = TILE_AG[CFG];
-    size_t lds = (size_t)AG * AB * wmax * sizeof(float2);
+    const int wstride = AG * AB * wmax;   // float2 entries per window buffer
+    size_t lds = (size_t)(PIPE ? 2 : 1) * wstride * sizeof(float2);
     if (AG > 1) lds = std::max(lds, (size_t)(AG - 1) * TILE_BX[CFG] * TILE_BY[CFG] * 256 * sizeof(float));
     const int64_t n = p.n_items[CFG];
-    if (n == 0) return hipSuccess;
     if (lds > 65536) {
         if (lds > 160 * 1024) return hipErrorInvalidValue;
-        hipError_t e = hipFuncSetAttribute((const void *)bp_kernel<CFG, MODE>,
+        hipError_t e = hipFuncSetAttribute((const void *)bp_kernel<CFG, MODE, PIPE>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
@@ -212,18 +288,32 @@ hipError_t launch_cfg(const pyhst_plan &p, const float *sino, int filtered, floa
     if (counter) {
         zero_counter<<<1, 1, 0, st>>>(counter);
         int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bp_kernel<CFG, MODE>, 256 * AG, lds);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bp_kernel<CFG, MODE, PIPE>, 256 * AG, lds);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
         int64_t grid = (int64_t)per_cu * p.cu_count;
         if (grid > n) grid = n;
-        bp_kernel<CFG, MODE><<<(unsigned)grid, 256 * AG, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n,
-                                                                    counter, 0, cp);
+        bp_kernel<CFG, MODE, PIPE><<<(unsigned)grid, 256 * AG, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n,
+                                                                          counter, 0, cp, wstride);
     } else {
-        bp_kernel<CFG, MODE><<<(unsigned)n, 256 * AG, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n,
-                                                                 nullptr, p.uniform ? 1 : 0, cp);
+        bp_kernel<CFG, MODE, PIPE><<<(unsigned)n, 256 * AG, lds, st>>>(p.t, sino, filtered, img, alpha, beta, n,
+                                                                       nullptr, p.uniform ? 1 : 0, cp, wstride);
     }
     return hipGetLastError();
+}
+
+template <int CFG, int MODE>
+hipError_t launch_cfg(const pyhst_plan &p, const float *sino, int filtered, float *img, float alpha, float beta,
+                      const CpPrimal &cp, hipStream_t st)
+{
+    int wmax = 0;
+    for (const auto &g : p.gd) wmax = std::max(wmax, g.bp_w[CFG]);
+    if (p.n_items[CFG] == 0) return hipSuccess;
+    if constexpr (CFG == 3 || CFG == 5) {   // the tiles chosen when a launch has few workgroups per CU
+        if (wmax <= pipe_wmax(CFG))
+            return launch_kernel<CFG, MODE, true>(p, sino, filtered, img, alpha, beta, cp, wmax, st);
+    }
+    return launch_kernel<CFG, MODE, false>(p, sino, filtered, img, alpha, beta, cp, wmax, st);
 }
 
 template <int MODE>

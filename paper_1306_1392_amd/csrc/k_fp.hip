@@ -55,6 +55,20 @@ namespace {
 
 constexpr int AW = FP_AMAX / 4;   // projections per wavefront
 
+// Bin chunk (64 bins) of workgroup column i of n.  The hardware deals consecutive workgroups
+// round-robin to the 8 XCDs, so column i runs on XCD i % 8 (n is a multiple of 8 whenever the remap
+// applies, whatever the other grid dimensions).  Each XCD gets whole pairs (c, n - 1 - c) of chunks at
+// the same distance from the detector centre: over all projections the bins of such a pair see one
+// annulus of the image, so an XCD's projector sweep touches that annulus rather than the whole image
+// and leaves the rest of its L2 (the backprojector's sinogram in the iterative solvers) in place.
+__device__ __forceinline__ int fp_chunk(int i, int n)
+{
+    if (n & 15) return i;
+    const int x = i & 7, k = i >> 3;            // XCD; k-th column of this XCD
+    const int pair = x * (n >> 4) + (k >> 1);   // n / 16 consecutive pairs per XCD
+    return (k & 1) ? n - 1 - pair : pair;
+}
+
 // The NC candidates of one line: weights hat(d), hat(d + a), ... with d the signed offset t - j of the
 // first one.  With 2/3 <= |a| <= 1 (UNIT: pixel size in [0.943, 1], three candidates) the first candidate
 // lies in (u - 1/|a|, u - 1/|a| + 1], so |d| < 1 and |d + a| <= 1: only the third weight can be
@@ -157,10 +171,11 @@ __global__ __launch_bounds__(256) void fp_kernel(Tables T, const float *__restri
         start = bk.x;
         count = bk.y;
     }
-    if ((int)blockIdx.x * 64 >= nb) return;                  // whole workgroup
+    const int chunk = fp_chunk(blockIdx.x, gridDim.x);
+    if (chunk * 64 >= nb) return;                            // whole workgroup
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-    const int j = blockIdx.x * 64 + lane;
+    const int j = chunk * 64 + lane;
     const double s = g.s;
     const double cx = 0.5 * (nx - 1), cy = 0.5 * (ny - 1);
     const int k_first = MODE == 3 ? k_single : T.fp_ang[start];
@@ -290,8 +305,9 @@ __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__
     const int K = g.K, nb = g.nb, nx = g.nx, ny = g.ny;
     const int k = k0 + blockIdx.y;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int j = blockIdx.x * 64 + lane;
-    if (k >= K || blockIdx.x * 64 >= nb) return;   // uniform over the workgroup
+    const int chunk = fp_chunk(blockIdx.x, gridDim.x);
+    const int j = chunk * 64 + lane;
+    if (k >= K || chunk * 64 >= nb) return;        // uniform over the workgroup
 
     const double c = T.cosd[g.ang_off + k], sn = T.sind[g.ang_off + k];
     const double s = g.s;
@@ -549,7 +565,7 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
     const int slice = blockIdx.z;
     const SliceDev sd = T.slc[slice];
     const GeoDev &g = T.geo[sd.g];
-    const int j0 = blockIdx.x * 64;
+    const int j0 = fp_chunk(blockIdx.x, gridDim.x) * 64;
     int kk[FP_SGRP] = {k0, -1, -1, -1};
     if (MODE != 3) {
         if ((int)blockIdx.y >= g.fp_npair) return;   // uniform over the workgroup

@@ -143,6 +143,26 @@ def test_fp_three_candidate_closed_form_weights():
     assert hat(-1).max() < 1e-12 and hat(3).max() < 1e-12
 
 
+def _fp_chunk(i, n):
+    if n % 16:
+        return i
+    x, k = i % 8, i // 8
+    pair = x * (n // 16) + k // 2
+    return n - 1 - pair if k % 2 else pair
+
+
+@pytest.mark.parametrize("n", [1, 4, 8, 12, 16, 24, 32, 48, 64, 96])
+def test_fp_chunk_remap(n):
+    """The projector's column -> bin-chunk map is a permutation; when it remaps (n a multiple of 16),
+    the columns that run on one XCD (i % 8) hold whole pairs of chunks symmetric about the centre."""
+    chunks = [_fp_chunk(i, n) for i in range(n)]
+    assert sorted(chunks) == list(range(n))
+    if n % 16 == 0:
+        for x in range(8):
+            mine = {_fp_chunk(i, n) for i in range(x, n, 8)}
+            assert mine == {n - 1 - c for c in mine}
+
+
 # ------------------------------------------------------------------ fused ROF dual steps
 FTX, FTY = 64, 16
 FRX, FRY = FTX + 4, FTY + 4
