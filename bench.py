@@ -728,18 +728,18 @@ def learned_data(indices, stream, plan_hi, plan_b, N, K, B, dev):
     return torch.cat(xs), torch.cat(ts), torch.cat(ys)
 
 
-def run_learned(args):
+def learned_experiment(N, K, B, n_train, epochs, n_test, n_val, dev, save_params=None):
     """Learned sparse-angle corrector: U-Net (4 levels, 32 base) trained on ellipse + Perlin
-    phantoms (512^2, 90 projections, Poisson 1e4) by the library's own MFMA kernels, compared
-    against TV (the better of Chambolle-Pock and FISTA, 300 iterations, lambda calibrated on
-    validation phantoms) on test phantoms."""
+    phantoms (N^2, K projections, Poisson 1e4) by the library's own MFMA kernels, then applied as
+    the product ships it (Corrector: FBP, U-Net, data-consistency check against a threshold
+    calibrated on validation phantoms, TV for the slices that fail it), against TV (the better of
+    Chambolle-Pock with the balanced gradient block and FISTA, 300 iterations, lambda calibrated on
+    the validation phantoms) on test phantoms."""
     import numpy as np
     import torch
     import paper_1306_1392_amd as ph
     from paper_1306_1392_amd.cnn import UNet, init_params
-    from paper_1306_1392_amd.corrector import Corrector
-    dev = torch.device("cuda:0")
-    N, K, B = args.learned_n, 90, 32
+    from paper_1306_1392_amd import corrector as cr
     SCALE = 10.0
     ang = np.arange(K) * (np.pi / K)
     axis = (N - 1) / 2.0
@@ -747,135 +747,86 @@ def run_learned(args):
     plan_b = ph.Plan(geo, n_slices=B)
     plan_hi = ph.Plan(ph.Geometry(2 * N, 2 * N, N, ang, axis, pixel_size=0.5))
     t0 = time.perf_counter()
-    log(f"learned: generating {args.learned_train} training phantoms ...")
-    xtr, ttr, _ = learned_data(np.arange(args.learned_train), 0, plan_hi, plan_b, N, K, B, dev)
-    xva, tva, yva = learned_data(np.arange(16), 2, plan_hi, plan_b, N, K, B, dev)
-    xte, tte, yte = learned_data(np.arange(args.learned_test), 1, plan_hi, plan_b, N, K, B, dev)
+    log(f"learned: generating {n_train} training phantoms ({N}^2, {K} angles) ...")
+    xtr, ttr, _ = learned_data(np.arange(n_train), 0, plan_hi, plan_b, N, K, B, dev)
+    xva, tva, yva = learned_data(np.arange(n_val), 2, plan_hi, plan_b, N, K, B, dev)
+    xte, tte, yte = learned_data(np.arange(n_test), 1, plan_hi, plan_b, N, K, B, dev)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     log(f"learned: data in {t_gen:.1f} s")
     net = UNet(B, N, N, 32, 4)
     net.set_params(init_params(32, 4, 0))
-    xs, ts = (xtr * SCALE).contiguous(), (ttr * SCALE).contiguous()
-    n_tr = xs.shape[0]
-    steps = args.learned_epochs * (n_tr // B)
-    rng = np.random.default_rng(11)
+    net.set_scale(SCALE)
+    steps = epochs * (xtr.shape[0] // B)
     t1 = time.perf_counter()
-    losses = []
-    for st in range(steps):
-        if st % (n_tr // B) == 0:
-            perm = torch.as_tensor(rng.permutation(n_tr), device=dev)
-        idx = perm[(st % (n_tr // B)) * B:(st % (n_tr // B)) * B + B]
-        lr = 1e-3 * 0.5 * (1 + np.cos(np.pi * st / steps))
-        loss = net.train_step(xs[idx].contiguous(), ts[idx].contiguous(), lr)
-        if st % 100 == 0 or st == steps - 1:
-            losses.append((st, float(loss)))
-            log(f"learned: step {st}/{steps} loss {losses[-1][1]:.5f}")
+    losses = cr.train(net, xtr, ttr, steps, lr=1e-3, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
-    params = net.get_params()
+    del xtr, ttr
 
-    def rmse(a, b):
-        return float(torch.sqrt(torch.mean((a.double() - b.double()) ** 2)))
-
-    def cnn_apply(x):
-        out = torch.empty_like(x)
-        for i in range(0, x.shape[0], B):
-            xi = (x[i:i + B] * SCALE).contiguous()
-            out[i:i + B] = net.forward(xi) / SCALE
-        return out
-
-    # TV reference.  Both TV solvers (Chambolle-Pock, and the paper's FISTA with 10 inner prox steps), 300
-    # iterations each; lambda by minimum RMSE on the validation phantoms (ground-truth calibration,
-    # section 3.1) over a half-decade grid widened until the minimum is interior.  The solver with the
-    # lower validation RMSE is the reference.
-    plan_va = ph.Plan(geo, n_slices=yva.shape[0])
+    # TV reference (section 3.1: lambda by ground-truth calibration on validation phantoms)
+    t2 = time.perf_counter()
     plan_te = ph.Plan(geo, n_slices=yte.shape[0])
-    solvers = {"cp": ph.TV_CP, "fista": ph.FISTA}
-
-    def calibrate(method):
-        norm = [0.0]
-
-        def ev(lam):
-            x = ph.reconstruct_slices(plan_va, sino=yva.contiguous(), method=method, lam=lam, n_iter=300,
-                                      op_norm=norm[0], n_inner=10)
-            norm[0] = plan_va.last_op_norm
-            return rmse(x, tva)
-
-        cal = {lam: ev(lam) for lam in [float(f"{v:.3g}") for v in 10.0 ** np.arange(-3.0, 0.51, 0.5)]}
-        for _ in range(4):
-            best = min(cal, key=cal.get)
-            if best == min(cal):
-                lam = float(f"{best / 10 ** 0.5:.3g}")
-            elif best == max(cal):
-                lam = float(f"{best * 10 ** 0.5:.3g}")
-            else:
-                break
-            cal[lam] = ev(lam)
-        return min(cal, key=cal.get), cal, norm[0]
-
     tvres = {}
-    for name, meth in solvers.items():
-        lam, cal, norm = calibrate(meth)
+    for name, meth in (("fista", ph.FISTA), ("cp", ph.TV_CP)):
+        lam, cal, norm, mu = cr.calibrate_tv_lambda(geo, yva, tva, method=meth)
         x_tv = ph.reconstruct_slices(plan_te, sino=yte.contiguous(), method=meth, lam=lam, n_iter=300, op_norm=norm,
-                                     n_inner=10)
-        tvres[name] = {"method": meth, "lambda": lam, "op_norm": norm, "val_rmse": cal[lam], "test_rmse": rmse(x_tv, tte),
-                       "calibration": {str(k): v for k, v in sorted(cal.items())}}
+                                     n_inner=10, tv_mu=mu)
+        tvres[name] = {"method": meth, "lambda": lam, "op_norm": norm, "tv_mu": mu, "val_rmse": cal[lam],
+                       "test_rmse": cr.rmse(x_tv, tte), "calibration": {str(k): v for k, v in sorted(cal.items())}}
+        log(f"learned: TV {name}: lambda {lam}, validation RMSE {cal[lam]:.4g}")
+    t_cal = time.perf_counter() - t2
     ref = min(tvres, key=lambda k: tvres[k]["val_rmse"])
     J = tvres[ref]
-    # data-consistency threshold of the corrector: 1.5 x the 95th percentile on validation
-    corr = Corrector(geo, B, params, tv_lambda=J["lambda"], tv_iters=300, tv_method=J["method"])
-    corr.op_norm = J["op_norm"]
-    res_va = []
-    for i in range(0, yva.shape[0], B):
-        yb = yva[i:i + B]
-        if yb.shape[0] < B:
-            yb = torch.cat([yb, yb[:1].expand(B - yb.shape[0], -1, -1)])
-        xh = cnn_apply(ph.reconstruct_slices(plan_b, sino=yb.contiguous(), method=ph.FBP))
-        ax = ph.forward_project(plan_b, xh.contiguous())
-        res_va.append(ph.slice_residual(plan_b, ax, yb.contiguous())[:min(B, yva.shape[0] - i)])
-    tau = 1.5 * float(torch.quantile(torch.cat(res_va), 0.95))
-    # test set: FBP, FBP + CNN, TV
-    x_cnn = cnn_apply(xte)
-    r_fbp, r_cnn, r_tv = rmse(xte, tte), rmse(x_cnn, tte), J["test_rmse"]
-    # throughput: FBP + CNN in batches of 32 vs the TV reference (300 iterations) on the whole test batch
+
+    # the corrector as shipped: FBP + U-Net, data-consistency check, TV for the slices that fail it
+    corr = cr.Corrector.from_net(geo, net, tv_lambda=J["lambda"], tv_iters=300, tv_method=J["method"],
+                                 op_norm=J["op_norm"], tv_mu=J["tv_mu"])
+    tau = corr.calibrate(yva)
+    x_c, fell = corr.reconstruct_all(yte)
+    r_fbp, r_cnn, r_tv = cr.rmse(xte, tte), cr.rmse(x_c, tte), J["test_rmse"]
+    # throughput: the corrector over the test set in batches of B vs the TV reference on the whole test set
     stream = torch.cuda.current_stream()
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    out = torch.empty((B, N, N), device=dev)
-    work = torch.empty(ph.work_bytes(plan_b, sino=yte[:B].contiguous(), method=ph.FBP), device=dev,
-                       dtype=torch.uint8)
-    ycs = [yte[i:i + B].contiguous() for i in range(0, yte.shape[0] - B + 1, B)]
+    ycs = [yte[i:i + B].contiguous() for i in range(0, yte.shape[0], B)]
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
     e[0].record(stream)
     for yb in ycs:
-        ph.reconstruct_slices(plan_b, sino=yb, method=ph.FBP, out=out, work=work)
-        out.mul_(SCALE)
-        net.forward(out, out=out)
+        corr.reconstruct(yb)
     e[1].record(stream)
     ph.reconstruct_slices(plan_te, sino=yte.contiguous(), method=J["method"], lam=J["lambda"], n_iter=300,
-                          op_norm=J["op_norm"], n_inner=10)
+                          op_norm=J["op_norm"], n_inner=10, tv_mu=J["tv_mu"])
     e[2].record(stream)
     torch.cuda.synchronize()
-    sps_cnn = len(ycs) * B / (e[0].elapsed_time(e[1]) * 1e-3)
+    sps_cnn = yte.shape[0] / (e[0].elapsed_time(e[1]) * 1e-3)
     sps_tv = yte.shape[0] / (e[1].elapsed_time(e[2]) * 1e-3)
     for v in tvres.values():
         del v["method"]
-    res = {"metric": "learned vs TV RMSE (sparse-angle 512^2, 90 angles)", "value": round(r_cnn / r_tv, 4),
-           "unit": "RMSE_CNN / RMSE_TV", "higher_is_better": False, "n_gpus": 1, "dtype": "bf16 CNN, f32 TV",
-           "data": "synthetic",
-           "config": {"workload": f"ellipse+Perlin phantoms {N}^2, {K} angles, Poisson 1e4; train "
-                                  f"{args.learned_train} x {args.learned_epochs} epochs, batch {B}; test "
-                                  f"{args.learned_test}; TV reference: best of Chambolle-Pock and FISTA, 300 "
-                                  f"iterations, calibrated lambda"},
-           "rmse": {"fbp": r_fbp, "cnn": r_cnn, "tv": r_tv}, "tv_reference": ref, "tv_solvers": tvres,
-           "slices_per_s": {"fbp_cnn": round(sps_cnn, 1), "tv": round(sps_tv, 2),
-                            "ratio": round(sps_cnn / sps_tv, 1)},
-           "pass": {"rmse_within_5pct_of_tv": r_cnn <= 1.05 * r_tv, "speed_20x": sps_cnn >= 20 * sps_tv,
-                    "gain_over_fbp": r_cnn < r_fbp},
-           "dc_threshold": tau, "train_seconds": round(t_train, 1), "data_seconds": round(t_gen, 1),
-           "train_steps": steps, "loss_trace": losses[::max(1, len(losses) // 20)]}
-    if args.save_params:
-        np.save(args.save_params, params.cpu().numpy())
+    if save_params:
+        cr.save_weights(save_params, net.get_params(), SCALE, 32, 4)
+    return {"rmse_ratio": round(r_cnn / r_tv, 4),
+            "workload": f"ellipse+Perlin phantoms {N}^2, {K} angles, Poisson 1e4; train {n_train} x {epochs} "
+                        f"epochs, batch {B}; validation {n_val}; test {n_test}; corrector: FBP + U-Net (4 levels, "
+                        f"32 base, BF16) with the data-consistency check and TV fallback; TV reference: better "
+                        f"of Chambolle-Pock and FISTA on validation, 300 iterations, calibrated lambda",
+            "rmse": {"fbp": r_fbp, "corrector": r_cnn, "tv": r_tv}, "tv_reference": ref, "tv_solvers": tvres,
+            "slices_per_s": {"corrector": round(sps_cnn, 1), "tv": round(sps_tv, 2),
+                             "ratio": round(sps_cnn / sps_tv, 1)},
+            "fallback_slices": int(fell.sum()), "dc_threshold": tau,
+            "pass": {"rmse_within_5pct_of_tv": r_cnn <= 1.05 * r_tv, "speed_20x": sps_cnn >= 20 * sps_tv,
+                     "gain_over_fbp": r_cnn < r_fbp},
+            "seconds": {"data": round(t_gen, 1), "train": round(t_train, 1), "tv_calibration": round(t_cal, 1)},
+            "train_steps": steps, "loss_trace": losses[::max(1, len(losses) // 20)]}
+
+
+def run_learned(args):
+    import torch
+    L = learned_experiment(args.learned_n, 90, 32, args.learned_train, args.learned_epochs, args.learned_test,
+                           args.learned_val, torch.device("cuda:0"), save_params=args.save_params)
+    res = {"metric": f"learned vs TV RMSE (sparse-angle {args.learned_n}^2, 90 angles)", "value": L["rmse_ratio"],
+           "unit": "RMSE_corrector / RMSE_TV", "higher_is_better": False, "n_gpus": 1, "dtype": "bf16 CNN, f32 TV",
+           "data": "synthetic", "config": {"workload": L.pop("workload")}}
+    res.update(L)
     print(json.dumps(res), flush=True)
 
 
@@ -900,8 +851,12 @@ def main():
     ap.add_argument("--uneven-slices", type=int, default=500)
     ap.add_argument("--learned-train", type=int, default=10000)
     ap.add_argument("--learned-test", type=int, default=256)
-    ap.add_argument("--learned-epochs", type=int, default=4)
+    ap.add_argument("--learned-epochs", type=int, default=6)
     ap.add_argument("--learned-n", type=int, default=512)
+    ap.add_argument("--learned-val", type=int, default=32)
+    ap.add_argument("--no-learned", action="store_true", help="leave the learned-corrector record out of the line")
+    ap.add_argument("--line-learned-train", type=int, default=10000)
+    ap.add_argument("--line-learned-epochs", type=int, default=6)
     ap.add_argument("--save-params", default=None)
     ap.add_argument("--summarize", metavar="DIR", help="write profiles/ summaries from rocprofv3 output in DIR")
     args = ap.parse_args()
@@ -1052,6 +1007,16 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline on a bounded sample ...")
         res["cpu_baseline"] = cpu_baseline(R, N, K, cfg)
+    if not args.no_learned:
+        # second half of the metric, outside the timed region: the learned corrector against TV on the
+        # sparse-angle workload, with a bounded training set
+        del raw, flats, dark, out, work, filt, cfg
+        torch.cuda.empty_cache()
+        log(f"bench: learned corrector vs TV ({args.line_learned_train} training phantoms) ...")
+        t0 = time.perf_counter()
+        res["learned"] = learned_experiment(512, 90, 32, args.line_learned_train, args.line_learned_epochs,
+                                            256, 32, dev)
+        res["learned"]["seconds"]["total"] = round(time.perf_counter() - t0, 1)
     print(json.dumps(res), flush=True)
 
 
