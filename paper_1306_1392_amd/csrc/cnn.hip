@@ -15,6 +15,7 @@
 #include <cstring>
 #include <vector>
 
+#include "cnn_conv.hpp"
 #include "cnn_gemm.hpp"
 #include "internal.hpp"
 
@@ -48,6 +49,7 @@ constexpr int TKW = 64;
 
 struct pyhst_unet {
     int B, H, W, base, L;
+    int cu_count = 256;
     float scale = 1.0f;   // data scale: the network sees scale x and returns x + f(scale x) / scale
     int64_t n_params = 0;
     float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
@@ -363,12 +365,45 @@ __global__ void fill_i32_kernel(int *p, int v) { *p = v; }
 // ---------------------------------------------------------------- layer drivers
 Act act(const Buf &b, int n, int co = 0, bool grad = false) { return Act{grad ? b.g : b.a, n, b.H, b.W, b.C, co}; }
 
+// 3x3 convolution of x (cin channels) with weights w [n][9 cin] by the direct kernel, for the channel
+// counts it is built for; false: not handled (the caller runs the implicit GEMM)
+template <int TN, class EP>
+bool conv_direct(int cin, const Act &x, const WeightB &w, const EP &e, int n, int cu, hipStream_t st, hipError_t &err)
+{
+    switch (cin) {
+    case 8: err = run_conv3x3<8, TN>(x, w, e, n, cu, st); return true;
+    case 16: err = run_conv3x3<16, TN>(x, w, e, n, cu, st); return true;
+    case 32: err = run_conv3x3<32, TN>(x, w, e, n, cu, st); return true;
+    case 64: err = run_conv3x3<64, TN>(x, w, e, n, cu, st); return true;
+    case 128: err = run_conv3x3<128, TN>(x, w, e, n, cu, st); return true;
+    case 256: err = run_conv3x3<256, TN>(x, w, e, n, cu, st); return true;
+    default: return false;
+    }
+}
+
+// N tile: the GEMM's, narrowed to 32 outputs where that lets the persistent form keep the weights
+// (64 input channels)
+template <class EP>
+bool conv_direct_tn(int cin, const Act &x, const WeightB &w, const EP &e, int n, int cu, hipStream_t st,
+                    hipError_t &err)
+{
+    int tn = tn_for(n);
+    while (tn > 32 && tn * 9 * cin > 20480 && 32 * 9 * cin <= 20480) tn >>= 1;
+    switch (tn) {
+    case 128: return conv_direct<128>(cin, x, w, e, n, cu, st, err);
+    case 64: return conv_direct<64>(cin, x, w, e, n, cu, st, err);
+    default: return conv_direct<32>(cin, x, w, e, n, cu, st, err);
+    }
+}
+
 hipError_t conv_fwd(const pyhst_unet &net, const Conv &L, Act in, bf16_t *out, int ocs, int oco, hipStream_t st)
 {
     const int M = in.B * in.H * in.W;
     StoreAct E{out, ocs, oco, net.params + L.b, 1};
-    Im2colA A = im2col_a(in, L.cin);
     WeightB Bw{L.wf, 9 * L.cin};
+    hipError_t err = hipSuccess;
+    if (conv_direct_tn(L.cin, in, Bw, E, L.cout, net.cu_count, st, err)) return err;
+    Im2colA A = im2col_a(in, L.cin);
     switch (tn_for(L.cout)) {
     case 128: return run_gemm<Im2colA, WeightB, StoreAct, 128>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
     case 64: return run_gemm<Im2colA, WeightB, StoreAct, 64>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
@@ -436,8 +471,9 @@ hipError_t conv_bwd(const pyhst_unet &net, const Conv &L, Act x, Act dz, bf16_t 
         // dX[pix][ci] = sum_{tap', co} dZ[pix + off(tap')][co] Wb[ci][tap'][co], masked by X > 0
         const int M = npix, N = L.cin;
         StoreMasked E{dx, dxcs, dxco, x.p, x.cs, x.co};
-        Im2colA A = im2col_a(dz, L.cout);
         WeightB Bw{L.wb, 9 * L.cout};
+        if (conv_direct_tn(L.cout, dz, Bw, E, N, net.cu_count, st, e)) return e;
+        Im2colA A = im2col_a(dz, L.cout);
         switch (tn_for(N)) {
         case 128: e = run_gemm<Im2colA, WeightB, StoreMasked, 128>(A, Bw, E, M, N, 9 * L.cout, 1, st); break;
         case 64: e = run_gemm<Im2colA, WeightB, StoreMasked, 64>(A, Bw, E, M, N, 9 * L.cout, 1, st); break;
@@ -613,6 +649,12 @@ int pyhst_unet_create(int32_t batch, int32_t height, int32_t width, int32_t base
     if (height <= 0 || width <= 0 || height % div || width % div)
         return fail(PYHST_EARG, "unet_create: height and width must be divisible by 2^(levels-1)");
     auto *net = new pyhst_unet();
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            net->cu_count = cus;
+    }
     net->B = batch;
     net->H = height;
     net->W = width;

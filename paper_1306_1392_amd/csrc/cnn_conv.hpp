@@ -1,0 +1,375 @@
+// Direct 3x3 convolution (zero padding 1, stride 1) on the MFMA BF16 units, for the U-Net layers:
+//   C[m = pixel][n] = sum_{tap, c} X[pixel + (ty - 1, tx - 1)][c] W[n][tap CIN + c]
+// the same sums as the implicit GEMM of cnn_gemm.hpp (Im2colA x WeightB), with the input read
+// once per output tile instead of once per tap.
+//
+// Output tile = CT_H x CT_W = 4 x 32 pixels of one image (one 32-pixel MFMA block per tile row) x TN
+// output channels.  The tile's input patch, (CT_H + 2) x (CT_W + 2) pixels with zeros outside the
+// image, and the weights of the TN outputs are staged in LDS; the MFMA K steps of the nine taps then
+// read the patch at shifted positions.  The weights are the MFMA A operand and the patch the B
+// operand, so each lane's accumulators hold four groups of four consecutive output channels of one
+// pixel (8-byte stores, bias and ReLU on four values at a time).  Every LDS address of a step is a
+// per-lane base plus a compile-time offset (the steps are unrolled).
+// Two forms (run_conv3x3 picks): a persistent one that keeps its outputs' weights in LDS and streams
+// the patches of many tiles (layers whose weights for TN outputs fit), and a general one that stages
+// patch and weights per chunk of input channels, the next chunk loaded into registers meanwhile.
+// K order: chunk, tap, channel within the chunk; with one chunk that is the GEMM's k = tap CIN + c.
+//
+// LDS layouts: patch pixel p = py (CT_W + 2) + px at 16-byte slots p CPP + chunk, CPP = CPX | 1 odd,
+// so the 8 lanes of a pass (8 consecutive pixels, one chunk) fall in 8 distinct four-bank groups;
+// weights of output n at slots n WS + tap CPX + chunk, WS = 1 mod 8 for the same reason.
+#pragma once
+
+#include <algorithm>
+#include <utility>
+
+#include "cnn_gemm.hpp"
+
+namespace pyhst {
+namespace cnn {
+
+constexpr int CT_H = 4, CT_W = 32;
+constexpr int CT_PW = CT_W + 2, CT_PIX = (CT_H + 2) * CT_PW;   // patch width, patch pixels
+
+// weight row stride in 16-byte slots: at least 9 CPX and 1 mod 8, so 8 consecutive output channels
+// (the lanes of a pass of a B operand read) fall in 8 distinct four-bank groups
+constexpr int conv_ws(int cpx)
+{
+    int s = 9 * cpx;
+    while (s % 8 != 1) ++s;
+    return s;
+}
+
+// Output tile t of an image batch: image b, first row y0, first column x0.
+struct ConvTile {
+    int b, y0, x0;
+};
+__device__ inline ConvTile conv_tile(const Act &x, int t)
+{
+    const int tiles_x = (x.W + CT_W - 1) / CT_W, tiles_y = (x.H + CT_H - 1) / CT_H;
+    const int b = t / (tiles_x * tiles_y), r = t - b * tiles_x * tiles_y;
+    return ConvTile{b, (r / tiles_x) * CT_H, (r % tiles_x) * CT_W};
+}
+
+// ---- persistent form --------------------------------------------------------------------------
+// Patch layout of the persistent form: pixel p at slots p CPP .. p CPP + CPX - 1, CPP = CPX | 1 (odd),
+// so 8 consecutive pixels at one chunk fall in 8 distinct four-bank groups and every operand address
+// is a per-lane base plus a compile-time offset.
+__device__ inline uint32_t pack_bf16x2(float a, float b)   // round to nearest even (v_cvt_pk_bf16_f32)
+{
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    const b2 r = __builtin_convertvector((f2){a, b}, b2);
+    uint32_t u;
+    __builtin_memcpy(&u, &r, 4);
+    return u;
+}
+
+// Epilogues of four consecutive output channels n .. n + 3 of output pixel m.
+struct ConvStoreAct {    // y = bf16(relu(v + bias))
+    static constexpr bool BIAS = true;
+    bf16_t *y;
+    int cs, co;
+    const float *bias;
+    __device__ void store4(int m, int n, const float *v, const float4 &b) const
+    {
+        const uint2 w = make_uint2(pack_bf16x2(fmaxf(v[0] + b.x, 0.0f), fmaxf(v[1] + b.y, 0.0f)),
+                                   pack_bf16x2(fmaxf(v[2] + b.z, 0.0f), fmaxf(v[3] + b.w, 0.0f)));
+        *(uint2 *)(y + (int64_t)m * cs + co + n) = w;
+    }
+};
+struct ConvStoreMasked { // dx = bf16(v) where act > 0, else 0
+    static constexpr bool BIAS = false;
+    bf16_t *dx;
+    int cs, co;
+    const bf16_t *act;
+    int acs, aco;
+    const float *bias;   // unused
+    __device__ void store4(int m, int n, const float *v, const float4 &) const
+    {
+        const uint2 a = *(const uint2 *)(act + (int64_t)m * acs + aco + n);
+        float o[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t h = ((q & 2) ? a.y : a.x) >> (16 * (q & 1));
+            const uint32_t mag = h & 0x7fffu;
+            o[q] = !(h & 0x8000u) && mag != 0 && mag <= 0x7f80u ? v[q] : 0.0f;   // act > 0 (BF16 bits)
+        }
+        *(uint2 *)(dx + (int64_t)m * cs + co + n) = make_uint2(pack_bf16x2(o[0], o[1]), pack_bf16x2(o[2], o[3]));
+    }
+};
+
+// One MFMA K step S (16 K values) of the persistent form: weights as the A operand, the patch as the
+// B operand, so accumulator register r holds output channel 8 (r / 4) + 4 (lane / 32) + r % 4 of
+// pixel lane % 32.  la[i]: patch slot of this lane's pixel in row block i (plus its half of the step's
+// channels when CIN >= 16); lw[j]: weight slot of its output channel in column block j (likewise).
+template <int CIN, int TN, int S>
+__device__ __forceinline__ void pconv_step(const uint4 *sP, const uint4 *sW, const int *la, const int *lw, int half,
+                                           f32x16 (&acc)[TN / WaveGrid<TN>::WN / 32][TM / WaveGrid<TN>::WM / 32])
+{
+    constexpr int CPX = CIN / 8, CPP = CPX | 1;
+    constexpr int BM = TM / WaveGrid<TN>::WM / 32, BN = TN / WaveGrid<TN>::WN / 32;
+    int oa, ow;
+    bool live = true;
+    if constexpr (CIN >= 16) {    // both halves of the step read one tap
+        constexpr int tap = (16 * S) / CIN, c8 = ((16 * S) % CIN) / 8;
+        oa = ((tap / 3) * CT_PW + tap % 3) * CPP + c8;
+        ow = tap * CPX + c8;
+    } else {                      // CIN == 8: the halves read taps 2S and 2S + 1
+        constexpr int t0 = 2 * S, t1 = 2 * S + 1;
+        oa = half ? ((t1 / 3) * CT_PW + t1 % 3) : ((t0 / 3) * CT_PW + t0 % 3);
+        ow = half ? t1 : t0;
+        live = !(half && t1 >= 9);
+    }
+    bf16x8 wf[BN], pf[BM];
+#pragma unroll
+    for (int j = 0; j < BN; ++j) {
+        const uint4 v = live ? sW[lw[j] + ow] : zero8();
+        wf[j] = *(const bf16x8 *)&v;
+    }
+#pragma unroll
+    for (int i = 0; i < BM; ++i) {
+        const uint4 v = live ? sP[la[i] + oa] : zero8();
+        pf[i] = *(const bf16x8 *)&v;
+    }
+#pragma unroll
+    for (int j = 0; j < BN; ++j)
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+            acc[j][i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[j], pf[i], acc[j][i], 0, 0, 0);
+}
+
+template <int CIN, int TN, int... S>
+__device__ __forceinline__ void pconv_steps(std::integer_sequence<int, S...>, const uint4 *sP, const uint4 *sW,
+                                            const int *la, const int *lw, int half,
+                                            f32x16 (&acc)[TN / WaveGrid<TN>::WN / 32][TM / WaveGrid<TN>::WM / 32])
+{
+    (pconv_step<CIN, TN, S>(sP, sW, la, lw, half, acc), ...);
+}
+
+// Four-channel epilogue of one output tile, shared by both forms: accumulator register 4 g + q of
+// column block j, row block i holds output channel 8 g + 4 (lane / 32) + q of the block, pixel lane % 32.
+template <int TN, class EP>
+__device__ __forceinline__ void pconv_store(const Act &x, const ConvTile &c, int n0, int N, int wm, int wn, int col,
+                                            int half, const EP &E, const float4 *sBias,
+                                            f32x16 (&acc)[TN / WaveGrid<TN>::WN / 32][TM / WaveGrid<TN>::WM / 32])
+{
+    constexpr int BM = TM / WaveGrid<TN>::WM / 32, BN = TN / WaveGrid<TN>::WN / 32;
+    constexpr int WTN = TN / WaveGrid<TN>::WN;
+    const int xx = c.x0 + col;
+#pragma unroll
+    for (int i = 0; i < BM; ++i) {
+        const int yy = c.y0 + wm * BM + i;
+        if (yy >= x.H || xx >= x.W) continue;
+        const int m = (c.b * x.H + yy) * x.W + xx;
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int nl = wn * WTN + j * 32 + 8 * g + 4 * half;
+                if (n0 + nl >= N) continue;
+                const float4 bb = EP::BIAS ? sBias[nl >> 2] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                const float v[4] = {acc[j][i][4 * g], acc[j][i][4 * g + 1], acc[j][i][4 * g + 2], acc[j][i][4 * g + 3]};
+                E.store4(m, n0 + nl, v, bb);
+            }
+    }
+}
+
+// Persistent form for layers whose weights for TN outputs fit in LDS (TN x 9 x CIN <= 20480 values):
+// the workgroup stages its outputs' weights (and biases) once and then walks output tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's patch is loaded into registers while the
+// current one is summed.  One chunk, K steps in the GEMM's order k = tap CIN + c.
+template <int CIN, int TN, class EP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
+{
+    constexpr int CPX = CIN / 8, CPP = CPX | 1, WS = conv_ws(CPX);
+    constexpr int NPS = CT_PIX * CPX;             // patch vectors
+    constexpr int NPV = (NPS + 255) / 256;        // patch vectors per thread
+    constexpr int NSTEP = (9 * CIN + 15) / 16;
+    constexpr int WMW = WaveGrid<TN>::WM, WNW = WaveGrid<TN>::WN;
+    constexpr int BM = TM / WMW / 32, BN = TN / WNW / 32, WTN = TN / WNW;
+    static_assert(TN * 9 * CIN <= 20480, "weights of the workgroup's outputs fit in LDS");
+    __shared__ uint4 sP[CT_PIX * CPP];
+    __shared__ uint4 sW[TN * WS];
+    __shared__ float4 sBias[TN / 4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / WNW, wn = wave % WNW;
+    const int col = lane & 31, half = lane >> 5;
+    const int n0 = blockIdx.y * TN;
+    for (int i = threadIdx.x; i < TN * 9 * CPX; i += 256) {
+        const int n = i / (9 * CPX), rr = i - n * (9 * CPX);
+        const int tap = rr / CPX, c8 = rr - tap * CPX;
+        sW[n * WS + tap * CPX + c8] = n0 + n < N ? ld8(B.w + (int64_t)(n0 + n) * B.K + tap * CIN + 8 * c8) : zero8();
+    }
+    if (EP::BIAS && threadIdx.x < TN) ((float *)sBias)[threadIdx.x] = n0 + (int)threadIdx.x < N ? E.bias[n0 + threadIdx.x] : 0.0f;
+    // this thread's patch vectors, the same for every tile: pixel (py, px), chunk c8, LDS slot
+    int spos[NPV], sdst[NPV];
+#pragma unroll
+    for (int v = 0; v < NPV; ++v) {
+        const int i = threadIdx.x + 256 * v;
+        const int p = i / CPX, c8 = i - p * CPX, py = p / CT_PW, px = p - py * CT_PW;
+        spos[v] = i < NPS ? (py << 16) | (px << 8) | c8 : -1;
+        sdst[v] = p * CPP + c8;
+    }
+    uint4 pv[NPV];
+    auto load = [&](int t) {
+        const ConvTile c = conv_tile(x, t);
+        const bf16_t *img = x.p + (int64_t)c.b * x.H * x.W * x.cs + x.co;
+#pragma unroll
+        for (int v = 0; v < NPV; ++v) {
+            const int yy = c.y0 - 1 + (spos[v] >> 16), xx = c.x0 - 1 + ((spos[v] >> 8) & 255);
+            pv[v] = spos[v] >= 0 && (unsigned)yy < (unsigned)x.H && (unsigned)xx < (unsigned)x.W
+                        ? ld8(img + (int64_t)(yy * x.W + xx) * x.cs + 8 * (spos[v] & 255))
+                        : zero8();
+        }
+    };
+    int la[BM], lw[BN];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) la[i] = ((wm * BM + i) * CT_PW + col) * CPP + (CIN >= 16 ? half : 0);
+#pragma unroll
+    for (int j = 0; j < BN; ++j) lw[j] = (wn * WTN + j * 32 + col) * WS + (CIN >= 16 ? half : 0);
+
+    int t = blockIdx.x;
+    if (t < tiles) load(t);
+    for (; t < tiles; t += gridDim.x) {
+        __syncthreads();   // the previous tile's reads of the patch are done (the weights are visible)
+#pragma unroll
+        for (int v = 0; v < NPV; ++v)
+            if (spos[v] >= 0) sP[sdst[v]] = pv[v];
+        __syncthreads();
+        if (t + (int)gridDim.x < tiles) load(t + gridDim.x);   // in flight while this tile is summed
+        f32x16 acc[BN][BM];
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+#pragma unroll
+            for (int i = 0; i < BM; ++i)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[j][i][q] = 0.0f;
+        pconv_steps<CIN, TN>(std::make_integer_sequence<int, NSTEP>{}, sP, sW, la, lw, half, acc);
+        pconv_store<TN>(x, conv_tile(x, t), n0, N, wm, wn, col, half, E, sBias, acc);
+    }
+}
+
+// channels per chunk of the general form: the chunk's weights [TN][9][CC] take at most 36 KB
+template <int CIN, int TN>
+constexpr int conv_cc()
+{
+    constexpr int cap = TN >= 128 ? 16 : (TN >= 64 ? 32 : 64);
+    return CIN < cap ? CIN : cap;
+}
+
+// General form (the layers whose weights do not fit the persistent form): one output tile per
+// workgroup; per chunk of CC input channels the tile's patch and the chunk's weights for the TN
+// outputs are staged in LDS (the layouts of the persistent form, for CC channels), the K steps of
+// the chunk run from LDS, and the next chunk is meanwhile loaded into registers.  Two barriers per
+// chunk.  K order: chunk, tap, channel within the chunk.
+template <int CIN, int TN, class EP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void conv3x3_kernel(Act x, WeightB B, EP E, int N)
+{
+    constexpr int CC = conv_cc<CIN, TN>(), CPX = CC / 8, CPP = CPX | 1, WS = conv_ws(CPX);
+    constexpr int NCH = CIN / CC;
+    constexpr int NPS = CT_PIX * CPX, NWS = TN * 9 * CPX;   // patch and weight vectors per chunk
+    constexpr int NV = (NPS + NWS + 255) / 256;             // per thread
+    constexpr int NSTEP = (9 * CC + 15) / 16;
+    constexpr int WMW = WaveGrid<TN>::WM, WNW = WaveGrid<TN>::WN;
+    constexpr int BM = TM / WMW / 32, BN = TN / WNW / 32, WTN = TN / WNW;
+    static_assert(CIN % CC == 0 && CC % 8 == 0, "channels in chunks of 8");
+    __shared__ uint4 sP[CT_PIX * CPP];
+    __shared__ uint4 sW[TN * WS];
+    __shared__ float4 sBias[TN / 4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / WNW, wn = wave % WNW;
+    const int col = lane & 31, half = lane >> 5;
+    const ConvTile c = conv_tile(x, blockIdx.x);
+    const int n0 = blockIdx.y * TN;
+    if (EP::BIAS && threadIdx.x < TN) ((float *)sBias)[threadIdx.x] = n0 + (int)threadIdx.x < N ? E.bias[n0 + threadIdx.x] : 0.0f;
+
+    // this thread's vectors of a chunk (the same for every chunk up to the channel offset ch CC):
+    // source element offset (-1: zero) from the tile's image or from the weights, LDS slot
+    const bf16_t *img = x.p + (int64_t)c.b * x.H * x.W * x.cs + x.co;
+    int src[NV], dst[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int i = threadIdx.x + 256 * v;
+        if (i < NPS) {
+            const int p = i / CPX, c8 = i - p * CPX, py = p / CT_PW, px = p - py * CT_PW;
+            const int yy = c.y0 - 1 + py, xx = c.x0 - 1 + px;
+            src[v] = (unsigned)yy < (unsigned)x.H && (unsigned)xx < (unsigned)x.W ? (yy * x.W + xx) * x.cs + 8 * c8 : -1;
+            dst[v] = p * CPP + c8;
+        } else {
+            const int j = i - NPS, n = j / (9 * CPX), rr = j - n * (9 * CPX);
+            const int tap = rr / CPX, c8 = rr - tap * CPX;
+            src[v] = j < NWS && n0 + n < N ? (n0 + n) * B.K + tap * CIN + 8 * c8 : -1;
+            dst[v] = j < NWS ? n * WS + tap * CPX + c8 : -1;
+        }
+    }
+    uint4 rv[NV];
+    auto load = [&](int ch) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const bool patch = (int)threadIdx.x + 256 * v < NPS;
+            rv[v] = src[v] >= 0 ? ld8((patch ? img : B.w) + src[v] + ch * CC) : zero8();
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const bool patch = (int)threadIdx.x + 256 * v < NPS;
+            if (patch) sP[dst[v]] = rv[v];
+            else if (dst[v] >= 0) sW[dst[v]] = rv[v];
+        }
+    };
+    int la[BM], lw[BN];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) la[i] = ((wm * BM + i) * CT_PW + col) * CPP + (CC >= 16 ? half : 0);
+#pragma unroll
+    for (int j = 0; j < BN; ++j) lw[j] = (wn * WTN + j * 32 + col) * WS + (CC >= 16 ? half : 0);
+
+    f32x16 acc[BN][BM];
+#pragma unroll
+    for (int j = 0; j < BN; ++j)
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[j][i][q] = 0.0f;
+    load(0);
+    store();
+    __syncthreads();
+    for (int ch = 0; ch < NCH; ++ch) {
+        if (ch + 1 < NCH) load(ch + 1);   // in flight while this chunk is summed
+        pconv_steps<CC, TN>(std::make_integer_sequence<int, NSTEP>{}, sP, sW, la, lw, half, acc);
+        if (ch + 1 < NCH) {
+            __syncthreads();   // every wave is done with this chunk
+            store();
+            __syncthreads();
+        }
+    }
+    pconv_store<TN>(x, c, n0, N, wm, wn, col, half, E, sBias, acc);
+}
+
+// the persistent form's four-channel epilogue of a GEMM epilogue
+inline ConvStoreAct conv_ep(const StoreAct &e) { return ConvStoreAct{e.y, e.cs, e.co, e.bias}; }
+inline ConvStoreMasked conv_ep(const StoreMasked &e) { return ConvStoreMasked{e.dx, e.cs, e.co, e.act, e.acs, e.aco, nullptr}; }
+
+template <int CIN, int TN, class EP>
+inline hipError_t run_conv3x3(const Act &x, const WeightB &w, const EP &e, int N, int cu_count, hipStream_t st)
+{
+    const int tiles = x.B * ((x.H + CT_H - 1) / CT_H) * ((x.W + CT_W - 1) / CT_W);
+    using CE = decltype(conv_ep(e));
+    if constexpr (TN * 9 * CIN <= 20480) {
+        int per_cu = 0;
+        const hipError_t oc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, conv3x3_persist_kernel<CIN, TN, CE>,
+                                                                           256, 0);
+        if (oc != hipSuccess) return oc;
+        const int wgs = std::min(tiles, std::max(1, per_cu) * cu_count);
+        conv3x3_persist_kernel<CIN, TN, CE><<<dim3(wgs, (N + TN - 1) / TN), 256, 0, st>>>(x, w, conv_ep(e), N, tiles);
+    } else {
+        conv3x3_kernel<CIN, TN, CE><<<dim3(tiles, (N + TN - 1) / TN), 256, 0, st>>>(x, w, conv_ep(e), N);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cnn
+}  // namespace pyhst

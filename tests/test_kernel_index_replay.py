@@ -163,6 +163,117 @@ def test_fp_chunk_remap(n):
             assert mine == {n - 1 - c for c in mine}
 
 
+# ------------------------------------------------------------------ direct 3x3 convolution (U-Net)
+CT_H, CT_W = 4, 32
+CT_PW, CT_PIX = CT_W + 2, (CT_H + 2) * (CT_W + 2)
+
+
+def _conv_ws(cpx):
+    s = 9 * cpx
+    while s % 8 != 1:
+        s += 1
+    return s
+
+
+def _tap_row(tap):
+    return (tap * 11) >> 5
+
+
+def _conv_tn(cin, n):
+    tn = 128 if n >= 128 else (64 if n >= 64 else 32)
+    while tn > 32 and tn * 9 * cin > 20480 and 32 * 9 * cin <= 20480:
+        tn //= 2
+    return tn
+
+
+@pytest.mark.parametrize("cin,H,W,n", [(8, 16, 16, 32), (16, 9, 40, 64), (32, 12, 33, 32), (64, 8, 64, 128),
+                                       (128, 5, 31, 64), (256, 6, 20, 128), (64, 7, 35, 32), (8, 4, 8, 128),
+                                       (32, 5, 70, 64), (128, 4, 32, 128), (256, 3, 9, 32)])
+def test_conv3x3_patch_replay(cin, H, W, n):
+    """The direct convolution's LDS staging and MFMA operand reads, replayed index by index for the form
+    the library picks (persistent, CC = CIN, when TN x 9 x CIN <= 20480; else general with chunks of CC =
+    min(CIN, 16 / 32 / 64 for TN = 128 / 64 / 32) channels).  Patch slot p CPP + c8 (CPP = CPX | 1) holds
+    the input vector of pixel p, channels ch CC + 8 c8 (zeros outside the image); weight slot n WS + tap
+    CPX + c8 holds W[n][tap CIN + ch CC + 8 c8].  Every lane of every (chunk, K step, row block, column
+    block) reads, at its per-lane base plus the step's offset, the im2col value X[pixel + (ty-1, tx-1)][c]
+    of its pixel and the weight of its output channel at one K index; every K index is read once, in the
+    global order with one chunk; the 8 lanes of a pass hit 8 distinct four-bank groups."""
+    rng = np.random.default_rng(cin + H)
+    B, N = 2, n
+    X = rng.integers(1, 1000, (B, H, W, cin))
+    Wt = rng.integers(1, 1000, (N, 9 * cin))
+    tn = _conv_tn(cin, N)
+    persist = tn * 9 * cin <= 20480
+    cap = 16 if tn >= 128 else (32 if tn >= 64 else 64)
+    CC = cin if persist else min(cin, cap)
+    CPX, NCH = CC // 8, cin // CC
+    CPP, WS = CPX | 1, _conv_ws(CPX)
+    NSTEP = (9 * CC + 15) // 16
+    wm_n = 2 if tn >= 128 else 4
+    wn_n = 4 // wm_n
+    BM, BN, WTN = (128 // wm_n) // 32, (tn // wn_n) // 32, tn // wn_n
+    tiles_x, tiles_y = -(-W // CT_W), -(-H // CT_H)
+    for t in range(B * tiles_x * tiles_y):
+        b, r = divmod(t, tiles_x * tiles_y)
+        y0, x0 = (r // tiles_x) * CT_H, (r % tiles_x) * CT_W
+        for n0 in range(0, N, tn):
+            seen_k = []
+            for ch in range(NCH):
+                sP = np.full((CT_PIX * CPP, 8), -1, dtype=np.int64)
+                for i in range(CT_PIX * CPX):
+                    p, c8 = divmod(i, CPX)
+                    py, px = divmod(p, CT_PW)
+                    yy, xx = y0 - 1 + py, x0 - 1 + px
+                    v = X[b, yy, xx, ch * CC + 8 * c8: ch * CC + 8 * c8 + 8] if (0 <= yy < H and 0 <= xx < W) \
+                        else np.zeros(8, dtype=np.int64)
+                    sP[p * CPP + c8] = v
+                sW = np.full((tn * WS, 8), -1, dtype=np.int64)
+                for j in range(tn * 9 * CPX):
+                    nn, rr = divmod(j, 9 * CPX)
+                    tap, c8 = divmod(rr, CPX)
+                    k0 = tap * cin + ch * CC + 8 * c8
+                    sW[nn * WS + tap * CPX + c8] = Wt[n0 + nn, k0:k0 + 8] if n0 + nn < N else 0
+                for S in range(NSTEP):
+                    for wave in range(4):
+                        wm, wn = divmod(wave, wn_n)
+                        for i in range(BM):
+                            for j in range(BN):
+                                ga, gw = {}, {}
+                                for lane in range(64):
+                                    col, half = lane & 31, lane >> 5
+                                    la = ((wm * BM + i) * CT_PW + col) * CPP + (half if CC >= 16 else 0)
+                                    lw = (wn * WTN + j * 32 + col) * WS + (half if CC >= 16 else 0)
+                                    if CC >= 16:
+                                        tap, c8b = (16 * S) // CC, ((16 * S) % CC) // 8
+                                        oa = ((tap // 3) * CT_PW + tap % 3) * CPP + c8b
+                                        ow = tap * CPX + c8b
+                                        c8 = c8b + half
+                                    else:
+                                        tap = 2 * S + half
+                                        if tap >= 9:
+                                            continue
+                                        oa, ow, c8 = (tap // 3) * CT_PW + tap % 3, tap, 0
+                                    assert _tap_row(tap) == tap // 3
+                                    k = tap * cin + ch * CC + 8 * c8
+                                    if wave == 0 and i == 0 and j == 0 and col == 0:
+                                        seen_k.append(k)
+                                    yy = y0 + wm * BM + i + tap // 3 - 1
+                                    xx = x0 + col + tap % 3 - 1
+                                    ref = X[b, yy, xx, k - tap * cin: k - tap * cin + 8] if (
+                                        0 <= yy < H and 0 <= xx < W) else np.zeros(8)
+                                    assert np.array_equal(sP[la + oa], ref), (t, ch, S, lane)
+                                    nn = wn * WTN + j * 32 + col
+                                    wref = Wt[n0 + nn, k:k + 8] if n0 + nn < N else np.zeros(8)
+                                    assert np.array_equal(sW[lw + ow], wref), (t, ch, S, lane)
+                                    ga.setdefault(lane // 8, set()).add((la + oa) % 8)
+                                    gw.setdefault(lane // 8, set()).add((lw + ow) % 8)
+                                for g in list(ga.values()) + list(gw.values()):
+                                    assert len(g) == len([1 for _ in g]) and len(g) in (8,)
+            assert sorted(seen_k) == list(range(0, 9 * cin, 8))
+            if NCH == 1:
+                assert seen_k == sorted(seen_k)
+
+
 # ------------------------------------------------------------------ fused ROF dual steps
 FTX, FTY = 64, 16
 FRX, FRY = FTX + 4, FTY + 4
