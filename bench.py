@@ -409,6 +409,69 @@ def run_fp(args):
     print(json.dumps(res), flush=True)
 
 
+def run_bpcache(args):
+    """Backprojector of one 1024^2 slice x 128 projections (the solvers' launch) timed right after
+    different predecessor kernels: what its time depends on (the L2 contents it inherits)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1306_1392_amd as ph
+    dev = torch.device("cuda:0")
+    N, K = 1024, 128
+    plan = ph.Plan(ph.Geometry(N, N, N, synth.uniform_angles(K), (N - 1) / 2 + 3.5))
+    small = ph.Plan(ph.Geometry(256, 256, 256, synth.uniform_angles(K), 127.5 + 3.5))
+    small.set_tiles(plan.get_tiles()[0], False)
+    g = torch.Generator(device=dev)
+    g.manual_seed(3)
+    img, img2, img3 = [torch.rand(plan.img_shape(), device=dev, generator=g) for _ in range(3)]
+    sino, sino2 = [torch.rand(plan.sino_shape(), device=dev, generator=g) for _ in range(2)]
+    simg = torch.rand(small.img_shape(), device=dev, generator=g)
+    ssino = torch.rand(small.sino_shape(), device=dev, generator=g)
+    big = torch.rand(16 << 20, device=dev, generator=g)
+    big2 = torch.empty_like(big)
+    st = torch.cuda.current_stream()
+
+    def bp():
+        ph.backproject(plan, sino, 0, out=img, alpha=1e-6)
+
+    def fp_then_small_bp():
+        ph.forward_project(plan, img3, out=sino2)
+        ph.backproject(small, ssino, 0, out=simg, alpha=1e-6)
+
+    variants = {
+        "after_backprojection": lambda: ph.backproject(plan, sino2, 0, out=img3, alpha=1e-6),
+        "after_projector": lambda: ph.forward_project(plan, img3, out=sino2),
+        "after_projector_reading_the_output_image": lambda: ph.forward_project(plan, img, out=sino2),
+        "after_64MB_copy": lambda: big2.copy_(big),
+        "after_projector_on_256sq_image": lambda: ph.forward_project(small, simg, out=ssino),
+        "after_projector_then_small_backprojection": fp_then_small_bp,
+        "after_sum_of_the_output_image": lambda: img.sum(),
+        "after_copy_of_the_output_image": lambda: img2.copy_(img),
+    }
+    res = {}
+    for name, pre in variants.items():
+        for _ in range(3):
+            pre()
+            bp()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(30):
+            pre()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            bp()
+            e1.record(st)
+            ts.append((e0, e1))
+        torch.cuda.synchronize()
+        res[name] = round(1e3 * float(np.median([a.elapsed_time(b) for a, b in ts])), 1)
+        log(f"bpcache: {name} {res[name]} us")
+    out = {"metric": "backprojector time after a predecessor kernel (median of 30)", "value": res["after_projector"],
+           "unit": "us", "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic (uniform random)",
+           "config": {"workload": "backprojection of one 1024x1024 slice, 1024 bins, 128 projections (32x32 tiles)"},
+           "us_by_predecessor": res}
+    print(json.dumps(out), flush=True)
+
+
 def run_beta(args):
     """Choice of beta (section 3.1) on the TV workload (1024^2, 128 angles, Poisson 1e4): FISTA (300
     iterations, 10 inner prox steps) at 8 beta values, cross-validation over 3 excluded projections
@@ -846,7 +909,8 @@ def main():
                     help="also run a plain 2 GiB device copy (reference kernel for HBM byte counters)")
     ap.add_argument("--tile-sweep", action="store_true", help="time the backprojector for every tile shape")
     ap.add_argument("--peaks", action="store_true", help="run the roofline microbenchmarks")
-    ap.add_argument("--workload", default="fbp2048", choices=["fbp2048", "single", "uneven", "tv", "cnn", "learned", "preproc", "beta", "patch", "fp"],
+    ap.add_argument("--workload", default="fbp2048", choices=["fbp2048", "single", "uneven", "tv", "cnn", "learned", "preproc", "beta", "patch", "fp",
+                             "bpcache"],
                     help="fbp2048: the headline batch; uneven / tv: the other measured workloads")
     ap.add_argument("--uneven-slices", type=int, default=500)
     ap.add_argument("--learned-train", type=int, default=10000)
@@ -880,6 +944,8 @@ def main():
         return run_beta(args)
     if args.workload == "fp":
         return run_fp(args)
+    if args.workload == "bpcache":
+        return run_bpcache(args)
     if args.workload == "patch":
         return run_patch(args)
     if args.workload == "uneven":

@@ -177,8 +177,8 @@ __device__ __forceinline__ void pconv_store(const Act &x, const ConvTile &c, int
 
 // Persistent form for layers whose weights for TN outputs fit in LDS (TN x 9 x CIN <= 20480 values):
 // the workgroup stages its outputs' weights (and biases) once and then walks output tiles
-// blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's patch is loaded into registers while the
-// current one is summed.  One chunk, K steps in the GEMM's order k = tap CIN + c.
+// blockIdx.x, blockIdx.x + gridDim.x, ...; the patches of the next two tiles are in flight in
+// registers while the current one is summed.  One chunk, K steps in the GEMM's order k = tap CIN + c.
 template <int CIN, int TN, class EP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
@@ -212,8 +212,11 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
         spos[v] = i < NPS ? (py << 16) | (px << 8) | c8 : -1;
         sdst[v] = p * CPP + c8;
     }
-    uint4 pv[NPV];
-    auto load = [&](int t) {
+    // two patches in flight: the patch of tile t + 2 G (G = gridDim.x) is loaded into the registers
+    // that held tile t's once those are in LDS, while tile t is summed
+    uint4 pa[NPV], pb[NPV];
+    auto load = [&](uint4 (&pv)[NPV], int t) {
+        if (t >= tiles) return;
         const ConvTile c = conv_tile(x, t);
         const bf16_t *img = x.p + (int64_t)c.b * x.H * x.W * x.cs + x.co;
 #pragma unroll
@@ -230,15 +233,13 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
 #pragma unroll
     for (int j = 0; j < BN; ++j) lw[j] = (wn * WTN + j * 32 + col) * WS + (CIN >= 16 ? half : 0);
 
-    int t = blockIdx.x;
-    if (t < tiles) load(t);
-    for (; t < tiles; t += gridDim.x) {
+    auto tile = [&](uint4 (&pv)[NPV], int t) {
         __syncthreads();   // the previous tile's reads of the patch are done (the weights are visible)
 #pragma unroll
         for (int v = 0; v < NPV; ++v)
             if (spos[v] >= 0) sP[sdst[v]] = pv[v];
         __syncthreads();
-        if (t + (int)gridDim.x < tiles) load(t + gridDim.x);   // in flight while this tile is summed
+        load(pv, t + 2 * (int)gridDim.x);   // in flight while this tile and the next are summed
         f32x16 acc[BN][BM];
 #pragma unroll
         for (int j = 0; j < BN; ++j)
@@ -248,6 +249,13 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
                 for (int q = 0; q < 16; ++q) acc[j][i][q] = 0.0f;
         pconv_steps<CIN, TN>(std::make_integer_sequence<int, NSTEP>{}, sP, sW, la, lw, half, acc);
         pconv_store<TN>(x, conv_tile(x, t), n0, N, wm, wn, col, half, E, sBias, acc);
+    };
+    const int G = gridDim.x;
+    load(pa, blockIdx.x);
+    load(pb, blockIdx.x + G);
+    for (int t = blockIdx.x; t < tiles; t += 2 * G) {
+        tile(pa, t);
+        if (t + G < tiles) tile(pb, t + G);
     }
 }
 
