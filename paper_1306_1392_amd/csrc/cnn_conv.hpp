@@ -3,8 +3,8 @@
 // the same sums as the implicit GEMM of cnn_gemm.hpp (Im2colA x WeightB), with the input read
 // once per output tile instead of once per tap.
 //
-// Output tile = CT_H x CT_W = 4 x 32 pixels of one image (one 32-pixel MFMA block per tile row) x TN
-// output channels.  The tile's input patch, (CT_H + 2) x (CT_W + 2) pixels with zeros outside the
+// Output tile = CTH x CT_W = 4 or 8 x 32 pixels of one image (one 32-pixel MFMA block per tile row) x
+// TN output channels.  The tile's input patch, (CTH + 2) x (CT_W + 2) pixels with zeros outside the
 // image, and the weights of the TN outputs are staged in LDS; the MFMA K steps of the nine taps then
 // read the patch at shifted positions.  The weights are the MFMA A operand and the patch the B
 // operand, so each lane's accumulators hold four groups of four consecutive output channels of one
@@ -28,8 +28,17 @@
 namespace pyhst {
 namespace cnn {
 
-constexpr int CT_H = 4, CT_W = 32;
-constexpr int CT_PW = CT_W + 2, CT_PIX = (CT_H + 2) * CT_PW;   // patch width, patch pixels
+constexpr int CT_W = 32, CT_PW = CT_W + 2;   // tile width; patch width
+
+// wave layout of a CTH x 32-pixel, TN-channel tile: WM x WN wavefronts, each with BM row blocks (tile
+// rows) and BN column blocks of 32
+template <int TN, int CTH>
+struct ConvGrid {
+    static constexpr int WM = WaveGrid<TN>::WM, WN = WaveGrid<TN>::WN;
+    static constexpr int BM = CTH / WM, BN = TN / WN / 32, WTN = TN / WN;
+    static constexpr int PIX = (CTH + 2) * CT_PW;   // patch pixels
+    static_assert(CTH % WM == 0, "whole tile rows per wavefront");
+};
 
 // weight row stride in 16-byte slots: at least 9 CPX and 1 mod 8, so 8 consecutive output channels
 // (the lanes of a pass of a B operand read) fall in 8 distinct four-bank groups
@@ -44,11 +53,12 @@ constexpr int conv_ws(int cpx)
 struct ConvTile {
     int b, y0, x0;
 };
+template <int CTH>
 __device__ inline ConvTile conv_tile(const Act &x, int t)
 {
-    const int tiles_x = (x.W + CT_W - 1) / CT_W, tiles_y = (x.H + CT_H - 1) / CT_H;
+    const int tiles_x = (x.W + CT_W - 1) / CT_W, tiles_y = (x.H + CTH - 1) / CTH;
     const int b = t / (tiles_x * tiles_y), r = t - b * tiles_x * tiles_y;
-    return ConvTile{b, (r / tiles_x) * CT_H, (r % tiles_x) * CT_W};
+    return ConvTile{b, (r / tiles_x) * CTH, (r % tiles_x) * CT_W};
 }
 
 // ---- persistent form --------------------------------------------------------------------------
@@ -103,12 +113,12 @@ struct ConvStoreMasked { // dx = bf16(v) where act > 0, else 0
 // B operand, so accumulator register r holds output channel 8 (r / 4) + 4 (lane / 32) + r % 4 of
 // pixel lane % 32.  la[i]: patch slot of this lane's pixel in row block i (plus its half of the step's
 // channels when CIN >= 16); lw[j]: weight slot of its output channel in column block j (likewise).
-template <int CIN, int TN, int S>
+template <int CIN, int TN, int CTH, int S>
 __device__ __forceinline__ void pconv_step(const uint4 *sP, const uint4 *sW, const int *la, const int *lw, int half,
-                                           f32x16 (&acc)[TN / WaveGrid<TN>::WN / 32][TM / WaveGrid<TN>::WM / 32])
+                                           f32x16 (&acc)[ConvGrid<TN, CTH>::BN][ConvGrid<TN, CTH>::BM])
 {
     constexpr int CPX = CIN / 8, CPP = CPX | 1;
-    constexpr int BM = TM / WaveGrid<TN>::WM / 32, BN = TN / WaveGrid<TN>::WN / 32;
+    constexpr int BM = ConvGrid<TN, CTH>::BM, BN = ConvGrid<TN, CTH>::BN;
     int oa, ow;
     bool live = true;
     if constexpr (CIN >= 16) {    // both halves of the step read one tap
@@ -139,23 +149,22 @@ __device__ __forceinline__ void pconv_step(const uint4 *sP, const uint4 *sW, con
             acc[j][i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[j], pf[i], acc[j][i], 0, 0, 0);
 }
 
-template <int CIN, int TN, int... S>
+template <int CIN, int TN, int CTH, int... S>
 __device__ __forceinline__ void pconv_steps(std::integer_sequence<int, S...>, const uint4 *sP, const uint4 *sW,
                                             const int *la, const int *lw, int half,
-                                            f32x16 (&acc)[TN / WaveGrid<TN>::WN / 32][TM / WaveGrid<TN>::WM / 32])
+                                            f32x16 (&acc)[ConvGrid<TN, CTH>::BN][ConvGrid<TN, CTH>::BM])
 {
-    (pconv_step<CIN, TN, S>(sP, sW, la, lw, half, acc), ...);
+    (pconv_step<CIN, TN, CTH, S>(sP, sW, la, lw, half, acc), ...);
 }
 
 // Four-channel epilogue of one output tile, shared by both forms: accumulator register 4 g + q of
 // column block j, row block i holds output channel 8 g + 4 (lane / 32) + q of the block, pixel lane % 32.
-template <int TN, class EP>
+template <int TN, int CTH, class EP>
 __device__ __forceinline__ void pconv_store(const Act &x, const ConvTile &c, int n0, int N, int wm, int wn, int col,
                                             int half, const EP &E, const float4 *sBias,
-                                            f32x16 (&acc)[TN / WaveGrid<TN>::WN / 32][TM / WaveGrid<TN>::WM / 32])
+                                            f32x16 (&acc)[ConvGrid<TN, CTH>::BN][ConvGrid<TN, CTH>::BM])
 {
-    constexpr int BM = TM / WaveGrid<TN>::WM / 32, BN = TN / WaveGrid<TN>::WN / 32;
-    constexpr int WTN = TN / WaveGrid<TN>::WN;
+    constexpr int BM = ConvGrid<TN, CTH>::BM, BN = ConvGrid<TN, CTH>::BN, WTN = ConvGrid<TN, CTH>::WTN;
     const int xx = c.x0 + col;
 #pragma unroll
     for (int i = 0; i < BM; ++i) {
@@ -179,18 +188,18 @@ __device__ __forceinline__ void pconv_store(const Act &x, const ConvTile &c, int
 // the workgroup stages its outputs' weights (and biases) once and then walks output tiles
 // blockIdx.x, blockIdx.x + gridDim.x, ...; the patches of the next two tiles are in flight in
 // registers while the current one is summed.  One chunk, K steps in the GEMM's order k = tap CIN + c.
-template <int CIN, int TN, class EP>
+template <int CIN, int TN, int CTH, class EP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
 {
+    using G_ = ConvGrid<TN, CTH>;
     constexpr int CPX = CIN / 8, CPP = CPX | 1, WS = conv_ws(CPX);
-    constexpr int NPS = CT_PIX * CPX;             // patch vectors
+    constexpr int NPS = G_::PIX * CPX;            // patch vectors
     constexpr int NPV = (NPS + 255) / 256;        // patch vectors per thread
     constexpr int NSTEP = (9 * CIN + 15) / 16;
-    constexpr int WMW = WaveGrid<TN>::WM, WNW = WaveGrid<TN>::WN;
-    constexpr int BM = TM / WMW / 32, BN = TN / WNW / 32, WTN = TN / WNW;
+    constexpr int WNW = G_::WN, BM = G_::BM, BN = G_::BN, WTN = G_::WTN;
     static_assert(TN * 9 * CIN <= 20480, "weights of the workgroup's outputs fit in LDS");
-    __shared__ uint4 sP[CT_PIX * CPP];
+    __shared__ uint4 sP[G_::PIX * CPP];
     __shared__ uint4 sW[TN * WS];
     __shared__ float4 sBias[TN / 4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -217,7 +226,7 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
     uint4 pa[NPV], pb[NPV];
     auto load = [&](uint4 (&pv)[NPV], int t) {
         if (t >= tiles) return;
-        const ConvTile c = conv_tile(x, t);
+        const ConvTile c = conv_tile<CTH>(x, t);
         const bf16_t *img = x.p + (int64_t)c.b * x.H * x.W * x.cs + x.co;
 #pragma unroll
         for (int v = 0; v < NPV; ++v) {
@@ -247,8 +256,8 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
             for (int i = 0; i < BM; ++i)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) acc[j][i][q] = 0.0f;
-        pconv_steps<CIN, TN>(std::make_integer_sequence<int, NSTEP>{}, sP, sW, la, lw, half, acc);
-        pconv_store<TN>(x, conv_tile(x, t), n0, N, wm, wn, col, half, E, sBias, acc);
+        pconv_steps<CIN, TN, CTH>(std::make_integer_sequence<int, NSTEP>{}, sP, sW, la, lw, half, acc);
+        pconv_store<TN, CTH>(x, conv_tile<CTH>(x, t), n0, N, wm, wn, col, half, E, sBias, acc);
     };
     const int G = gridDim.x;
     load(pa, blockIdx.x);
@@ -276,21 +285,22 @@ template <int CIN, int TN, class EP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void conv3x3_kernel(Act x, WeightB B, EP E, int N)
 {
+    constexpr int CTH = 4;
+    using G_ = ConvGrid<TN, CTH>;
     constexpr int CC = conv_cc<CIN, TN>(), CPX = CC / 8, CPP = CPX | 1, WS = conv_ws(CPX);
     constexpr int NCH = CIN / CC;
-    constexpr int NPS = CT_PIX * CPX, NWS = TN * 9 * CPX;   // patch and weight vectors per chunk
+    constexpr int NPS = G_::PIX * CPX, NWS = TN * 9 * CPX;  // patch and weight vectors per chunk
     constexpr int NV = (NPS + NWS + 255) / 256;             // per thread
     constexpr int NSTEP = (9 * CC + 15) / 16;
-    constexpr int WMW = WaveGrid<TN>::WM, WNW = WaveGrid<TN>::WN;
-    constexpr int BM = TM / WMW / 32, BN = TN / WNW / 32, WTN = TN / WNW;
+    constexpr int WNW = G_::WN, BM = G_::BM, BN = G_::BN, WTN = G_::WTN;
     static_assert(CIN % CC == 0 && CC % 8 == 0, "channels in chunks of 8");
-    __shared__ uint4 sP[CT_PIX * CPP];
+    __shared__ uint4 sP[G_::PIX * CPP];
     __shared__ uint4 sW[TN * WS];
     __shared__ float4 sBias[TN / 4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WNW, wn = wave % WNW;
     const int col = lane & 31, half = lane >> 5;
-    const ConvTile c = conv_tile(x, blockIdx.x);
+    const ConvTile c = conv_tile<CTH>(x, blockIdx.x);
     const int n0 = blockIdx.y * TN;
     if (EP::BIAS && threadIdx.x < TN) ((float *)sBias)[threadIdx.x] = n0 + (int)threadIdx.x < N ? E.bias[n0 + threadIdx.x] : 0.0f;
 
@@ -347,33 +357,46 @@ void conv3x3_kernel(Act x, WeightB B, EP E, int N)
     __syncthreads();
     for (int ch = 0; ch < NCH; ++ch) {
         if (ch + 1 < NCH) load(ch + 1);   // in flight while this chunk is summed
-        pconv_steps<CC, TN>(std::make_integer_sequence<int, NSTEP>{}, sP, sW, la, lw, half, acc);
+        pconv_steps<CC, TN, CTH>(std::make_integer_sequence<int, NSTEP>{}, sP, sW, la, lw, half, acc);
         if (ch + 1 < NCH) {
             __syncthreads();   // every wave is done with this chunk
             store();
             __syncthreads();
         }
     }
-    pconv_store<TN>(x, c, n0, N, wm, wn, col, half, E, sBias, acc);
+    pconv_store<TN, CTH>(x, c, n0, N, wm, wn, col, half, E, sBias, acc);
 }
 
 // the persistent form's four-channel epilogue of a GEMM epilogue
 inline ConvStoreAct conv_ep(const StoreAct &e) { return ConvStoreAct{e.y, e.cs, e.co, e.bias}; }
 inline ConvStoreMasked conv_ep(const StoreMasked &e) { return ConvStoreMasked{e.dx, e.cs, e.co, e.act, e.acs, e.aco, nullptr}; }
 
+// tile rows of the persistent form: 8 (two row blocks per wavefront, a weight operand serves two
+// MFMAs) where the patch and weights of a workgroup fit in about 56 KB of LDS, else 4
+template <int CIN, int TN>
+constexpr int persist_cth()
+{
+    constexpr int cpx = CIN / 8;
+    constexpr int lds8 = (10 * CT_PW * (cpx | 1) + TN * conv_ws(cpx)) * 16;
+    return (TN <= 64 && lds8 <= 57344) ? 8 : 4;
+}
+
 template <int CIN, int TN, class EP>
 inline hipError_t run_conv3x3(const Act &x, const WeightB &w, const EP &e, int N, int cu_count, hipStream_t st)
 {
-    const int tiles = x.B * ((x.H + CT_H - 1) / CT_H) * ((x.W + CT_W - 1) / CT_W);
     using CE = decltype(conv_ep(e));
     if constexpr (TN * 9 * CIN <= 20480) {
+        constexpr int CTH = persist_cth<CIN, TN>();
+        const int tiles = x.B * ((x.H + CTH - 1) / CTH) * ((x.W + CT_W - 1) / CT_W);
         int per_cu = 0;
-        const hipError_t oc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, conv3x3_persist_kernel<CIN, TN, CE>,
-                                                                           256, 0);
+        const hipError_t oc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                                           conv3x3_persist_kernel<CIN, TN, CTH, CE>, 256, 0);
         if (oc != hipSuccess) return oc;
         const int wgs = std::min(tiles, std::max(1, per_cu) * cu_count);
-        conv3x3_persist_kernel<CIN, TN, CE><<<dim3(wgs, (N + TN - 1) / TN), 256, 0, st>>>(x, w, conv_ep(e), N, tiles);
+        conv3x3_persist_kernel<CIN, TN, CTH, CE><<<dim3(wgs, (N + TN - 1) / TN), 256, 0, st>>>(x, w, conv_ep(e), N,
+                                                                                            tiles);
     } else {
+        const int tiles = x.B * ((x.H + 3) / 4) * ((x.W + CT_W - 1) / CT_W);
         conv3x3_kernel<CIN, TN, CE><<<dim3(tiles, (N + TN - 1) / TN), 256, 0, st>>>(x, w, conv_ep(e), N);
     }
     return hipGetLastError();

@@ -164,8 +164,8 @@ def test_fp_chunk_remap(n):
 
 
 # ------------------------------------------------------------------ direct 3x3 convolution (U-Net)
-CT_H, CT_W = 4, 32
-CT_PW, CT_PIX = CT_W + 2, (CT_H + 2) * (CT_W + 2)
+CT_W = 32
+CT_PW = CT_W + 2
 
 
 def _conv_ws(cpx):
@@ -177,6 +177,12 @@ def _conv_ws(cpx):
 
 def _tap_row(tap):
     return (tap * 11) >> 5
+
+
+def _persist_cth(cin, tn):
+    cpx = cin // 8
+    lds8 = (10 * CT_PW * (cpx | 1) + tn * _conv_ws(cpx)) * 16
+    return 8 if (tn <= 64 and lds8 <= 57344) else 4
 
 
 def _conv_tn(cin, n):
@@ -191,7 +197,8 @@ def _conv_tn(cin, n):
                                        (32, 5, 70, 64), (128, 4, 32, 128), (256, 3, 9, 32)])
 def test_conv3x3_patch_replay(cin, H, W, n):
     """The direct convolution's LDS staging and MFMA operand reads, replayed index by index for the form
-    the library picks (persistent, CC = CIN, when TN x 9 x CIN <= 20480; else general with chunks of CC =
+    the library picks (persistent, CC = CIN, 8- or 4-row tiles, when TN x 9 x CIN <= 20480; else general
+    with 4-row tiles and chunks of CC =
     min(CIN, 16 / 32 / 64 for TN = 128 / 64 / 32) channels).  Patch slot p CPP + c8 (CPP = CPX | 1) holds
     the input vector of pixel p, channels ch CC + 8 c8 (zeros outside the image); weight slot n WS + tap
     CPX + c8 holds W[n][tap CIN + ch CC + 8 c8].  Every lane of every (chunk, K step, row block, column
@@ -204,6 +211,8 @@ def test_conv3x3_patch_replay(cin, H, W, n):
     Wt = rng.integers(1, 1000, (N, 9 * cin))
     tn = _conv_tn(cin, N)
     persist = tn * 9 * cin <= 20480
+    CT_H = _persist_cth(cin, tn) if persist else 4
+    CT_PIX = (CT_H + 2) * CT_PW
     cap = 16 if tn >= 128 else (32 if tn >= 64 else 64)
     CC = cin if persist else min(cin, cap)
     CPX, NCH = CC // 8, cin // CC
@@ -211,7 +220,7 @@ def test_conv3x3_patch_replay(cin, H, W, n):
     NSTEP = (9 * CC + 15) // 16
     wm_n = 2 if tn >= 128 else 4
     wn_n = 4 // wm_n
-    BM, BN, WTN = (128 // wm_n) // 32, (tn // wn_n) // 32, tn // wn_n
+    BM, BN, WTN = CT_H // wm_n, (tn // wn_n) // 32, tn // wn_n
     tiles_x, tiles_y = -(-W // CT_W), -(-H // CT_H)
     for t in range(B * tiles_x * tiles_y):
         b, r = divmod(t, tiles_x * tiles_y)
