@@ -414,6 +414,10 @@ hipError_t conv_fwd(const pyhst_unet &net, const Conv &L, Act in, bf16_t *out, i
 hipError_t up_fwd(const pyhst_unet &net, const Up &L, Act in, bf16_t *out, int H2, int W2, int ocs, int oco,
                   hipStream_t st)
 {
+    hipError_t err = hipSuccess;
+    if (H2 == 2 * in.H && W2 == 2 * in.W &&
+        run_up2x2(in, L.uf, net.params + L.b, L.cin, L.cout, out, ocs, oco, net.cu_count, st, err))
+        return err;
     const int M = in.B * in.H * in.W;
     PlainA A{in};
     WeightB Bw{L.uf, L.cin};

@@ -367,6 +367,186 @@ void conv3x3_kernel(Act x, WeightB B, EP E, int N)
     pconv_store<TN, CTH>(x, c, n0, N, wm, wn, col, half, E, sBias, acc);
 }
 
+// ---- transposed 2x2 convolution, stride 2 (the U-Net's up-sampling) ------------------------------
+// out[(b, 2y + dy, 2x + dx)][co] = relu(bias[co] + sum_ci U[d][co][ci] X[(b, y, x)][ci]), d = 2 dy + dx:
+// the GEMM M = input pixels, N = 4 cout (n = d cout + co), K = cin, in the persistent form of the
+// convolutions (the workgroup's TN outputs' weights in LDS, input tiles of 4 x 32 pixels streamed with
+// two in flight, weights as the A operand) with an epilogue that sends each lane's four consecutive
+// channels (one d, four co) to their output pixel as one 8-byte store.
+
+// weight row stride in 16-byte slots of the 1x1 form: at least CPX and 1 mod 8
+constexpr int up_ws(int cpx)
+{
+    int s = cpx;
+    while (s % 8 != 1) ++s;
+    return s;
+}
+
+template <int CIN, int TN, int S>
+__device__ __forceinline__ void up_step(const uint4 *sP, const uint4 *sW, const int *la, const int *lw,
+                                        f32x16 (&acc)[ConvGrid<TN, 4>::BN][ConvGrid<TN, 4>::BM])
+{
+    constexpr int BM = ConvGrid<TN, 4>::BM, BN = ConvGrid<TN, 4>::BN;
+    bf16x8 wf[BN], pf[BM];
+#pragma unroll
+    for (int j = 0; j < BN; ++j) {
+        const uint4 v = sW[lw[j] + 2 * S];
+        wf[j] = *(const bf16x8 *)&v;
+    }
+#pragma unroll
+    for (int i = 0; i < BM; ++i) {
+        const uint4 v = sP[la[i] + 2 * S];
+        pf[i] = *(const bf16x8 *)&v;
+    }
+#pragma unroll
+    for (int j = 0; j < BN; ++j)
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+            acc[j][i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[j], pf[i], acc[j][i], 0, 0, 0);
+}
+
+template <int CIN, int TN, int... S>
+__device__ __forceinline__ void up_steps(std::integer_sequence<int, S...>, const uint4 *sP, const uint4 *sW,
+                                         const int *la, const int *lw,
+                                         f32x16 (&acc)[ConvGrid<TN, 4>::BN][ConvGrid<TN, 4>::BM])
+{
+    (up_step<CIN, TN, S>(sP, sW, la, lw, acc), ...);
+}
+
+// x: input (cin channels at x.co of stride x.cs); w: U as [(d, co)][ci]; y: output of 2 x.H x 2 x.W
+// pixels, channels yco .. yco + cout - 1 of stride ycs; N = 4 cout, cout = 1 << lgc
+template <int CIN, int TN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void up2x2_kernel(Act x, const bf16_t *w, const float *bias, int lgc, bf16_t *y, int ycs, int yco, int N, int tiles)
+{
+    constexpr int CTH = 4;
+    using G_ = ConvGrid<TN, CTH>;
+    constexpr int CPX = CIN / 8, CPP = CPX | 1, WS = up_ws(CPX);
+    constexpr int NPS = CTH * CT_W * CPX;          // tile vectors (no halo)
+    constexpr int NPV = (NPS + 255) / 256;
+    constexpr int WNW = G_::WN, BM = G_::BM, BN = G_::BN, WTN = G_::WTN;
+    static_assert(CIN % 16 == 0, "whole MFMA K steps");
+    __shared__ uint4 sP[CTH * CT_W * CPP];
+    __shared__ uint4 sW[TN * WS];
+    __shared__ float4 sBias[TN / 4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / WNW, wn = wave % WNW;
+    const int col = lane & 31, half = lane >> 5;
+    const int n0 = blockIdx.y * TN;
+    const int cmask = (1 << lgc) - 1;
+    for (int i = threadIdx.x; i < TN * CPX; i += 256) {
+        const int n = i / CPX, c8 = i - n * CPX;
+        sW[n * WS + c8] = n0 + n < N ? ld8(w + (int64_t)(n0 + n) * CIN + 8 * c8) : zero8();
+    }
+    if (threadIdx.x < TN) ((float *)sBias)[threadIdx.x] = n0 + (int)threadIdx.x < N ? bias[(n0 + threadIdx.x) & cmask] : 0.0f;
+    int spos[NPV], sdst[NPV];
+#pragma unroll
+    for (int v = 0; v < NPV; ++v) {
+        const int i = threadIdx.x + 256 * v;
+        const int p = i / CPX, c8 = i - p * CPX, py = p / CT_W, px = p - py * CT_W;
+        spos[v] = i < NPS ? (py << 16) | (px << 8) | c8 : -1;
+        sdst[v] = p * CPP + c8;
+    }
+    uint4 pa[NPV], pb[NPV];
+    auto load = [&](uint4 (&pv)[NPV], int t) {
+        if (t >= tiles) return;
+        const ConvTile c = conv_tile<CTH>(x, t);
+        const bf16_t *img = x.p + (int64_t)c.b * x.H * x.W * x.cs + x.co;
+#pragma unroll
+        for (int v = 0; v < NPV; ++v) {
+            const int yy = c.y0 + (spos[v] >> 16), xx = c.x0 + ((spos[v] >> 8) & 255);
+            pv[v] = spos[v] >= 0 && yy < x.H && xx < x.W ? ld8(img + (int64_t)(yy * x.W + xx) * x.cs + 8 * (spos[v] & 255))
+                                                         : zero8();
+        }
+    };
+    int la[BM], lw[BN];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) la[i] = ((wm * BM + i) * CT_W + col) * CPP + half;
+#pragma unroll
+    for (int j = 0; j < BN; ++j) lw[j] = (wn * WTN + j * 32 + col) * WS + half;
+    const int H2 = 2 * x.H, W2 = 2 * x.W;
+
+    auto tile = [&](uint4 (&pv)[NPV], int t) {
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < NPV; ++v)
+            if (spos[v] >= 0) sP[sdst[v]] = pv[v];
+        __syncthreads();
+        load(pv, t + 2 * (int)gridDim.x);
+        f32x16 acc[BN][BM];
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+#pragma unroll
+            for (int i = 0; i < BM; ++i)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[j][i][q] = 0.0f;
+        up_steps<CIN, TN>(std::make_integer_sequence<int, CIN / 16>{}, sP, sW, la, lw, acc);
+        const ConvTile c = conv_tile<CTH>(x, t);
+        const int xx = c.x0 + col;
+#pragma unroll
+        for (int i = 0; i < BM; ++i) {
+            const int yy = c.y0 + wm * BM + i;
+            if (yy >= x.H || xx >= x.W) continue;
+#pragma unroll
+            for (int j = 0; j < BN; ++j)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int nl = wn * WTN + j * 32 + 8 * g + 4 * half;
+                    const int n = n0 + nl;
+                    if (n >= N) continue;
+                    const int d = n >> lgc, co = n & cmask;
+                    const int m2 = (c.b * H2 + 2 * yy + (d >> 1)) * W2 + 2 * xx + (d & 1);
+                    const float4 bb = sBias[nl >> 2];
+                    const float a0 = acc[j][i][4 * g], a1 = acc[j][i][4 * g + 1];
+                    const float a2 = acc[j][i][4 * g + 2], a3 = acc[j][i][4 * g + 3];
+                    *(uint2 *)(y + (int64_t)m2 * ycs + yco + co) =
+                        make_uint2(pack_bf16x2(fmaxf(a0 + bb.x, 0.0f), fmaxf(a1 + bb.y, 0.0f)),
+                                   pack_bf16x2(fmaxf(a2 + bb.z, 0.0f), fmaxf(a3 + bb.w, 0.0f)));
+                }
+        }
+    };
+    const int G = gridDim.x;
+    load(pa, blockIdx.x);
+    load(pb, blockIdx.x + G);
+    for (int t = blockIdx.x; t < tiles; t += 2 * G) {
+        tile(pa, t);
+        if (t + G < tiles) tile(pb, t + G);
+    }
+}
+
+// the up-sampling by the kernel above for the channel counts it is built for; false: not handled
+inline bool run_up2x2(const Act &x, const bf16_t *w, const float *bias, int cin, int cout, bf16_t *y, int ycs, int yco,
+                      int cu_count, hipStream_t st, hipError_t &err)
+{
+    if (cout < 4 || (cout & (cout - 1))) return false;
+    int lgc = 0;
+    while ((1 << lgc) < cout) ++lgc;
+    const int N = 4 * cout, tn = N >= 128 ? 128 : (N >= 64 ? 64 : 32);
+    const int tiles = x.B * ((x.H + 3) / 4) * ((x.W + CT_W - 1) / CT_W);
+    auto go = [&](auto kernel) {
+        int per_cu = 0;
+        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0);
+        if (err != hipSuccess) return;
+        const int wgs = std::min(tiles, std::max(1, per_cu) * cu_count);
+        kernel<<<dim3(wgs, (N + tn - 1) / tn), 256, 0, st>>>(x, w, bias, lgc, y, ycs, yco, N, tiles);
+        err = hipGetLastError();
+    };
+#define PYHST_UP_CASE(CI)                                              \
+    case CI:                                                          \
+        if (tn == 128) go(up2x2_kernel<CI, 128>);                     \
+        else if (tn == 64) go(up2x2_kernel<CI, 64>);                  \
+        else go(up2x2_kernel<CI, 32>);                                \
+        return true;
+    switch (cin) {
+        PYHST_UP_CASE(16)
+        PYHST_UP_CASE(32)
+        PYHST_UP_CASE(64)
+        PYHST_UP_CASE(128)
+    default: return false;
+    }
+#undef PYHST_UP_CASE
+}
+
 // the persistent form's four-channel epilogue of a GEMM epilogue
 inline ConvStoreAct conv_ep(const StoreAct &e) { return ConvStoreAct{e.y, e.cs, e.co, e.bias}; }
 inline ConvStoreMasked conv_ep(const StoreMasked &e) { return ConvStoreMasked{e.dx, e.cs, e.co, e.act, e.acs, e.aco, nullptr}; }

@@ -283,6 +283,87 @@ def test_conv3x3_patch_replay(cin, H, W, n):
                 assert seen_k == sorted(seen_k)
 
 
+def _up_ws(cpx):
+    s = cpx
+    while s % 8 != 1:
+        s += 1
+    return s
+
+
+@pytest.mark.parametrize("cin,cout,H,W", [(64, 32, 8, 40), (128, 64, 5, 32), (32, 16, 4, 9), (16, 8, 6, 70)])
+def test_up2x2_replay(cin, cout, H, W):
+    """The up-sampling kernel's staging and reads, replayed: tile slot p CPP + c8 holds X[pixel p][8 c8..],
+    weight slot n WS + c8 holds U[n][8 c8..]; every lane of every (K step, row block, column block) reads
+    its pixel's and its output's vectors at the step's K; 8 lanes of a pass hit 8 distinct four-bank
+    groups; the epilogue sends (pixel, n = d cout + co) to output pixel (2y + d / 2, 2x + d % 2), channel
+    co, covering every output value exactly once."""
+    rng = np.random.default_rng(cin + W)
+    B, N = 2, 4 * cout
+    X = rng.integers(1, 1000, (B, H, W, cin))
+    U = rng.integers(1, 1000, (N, cin))
+    tn = 128 if N >= 128 else (64 if N >= 64 else 32)
+    CPX = cin // 8
+    CPP, WS = CPX | 1, _up_ws(CPX)
+    wm_n = 2 if tn >= 128 else 4
+    wn_n = 4 // wm_n
+    BM, BN, WTN = 4 // wm_n, (tn // wn_n) // 32, tn // wn_n
+    lgc = cout.bit_length() - 1
+    hit = np.zeros((B, 2 * H, 2 * W, cout), dtype=np.int64)
+    tiles_x, tiles_y = -(-W // CT_W), -(-H // 4)
+    for t in range(B * tiles_x * tiles_y):
+        b, r = divmod(t, tiles_x * tiles_y)
+        y0, x0 = (r // tiles_x) * 4, (r % tiles_x) * CT_W
+        sP = np.full((4 * CT_W * CPP, 8), -1, dtype=np.int64)
+        for i in range(4 * CT_W * CPX):
+            p, c8 = divmod(i, CPX)
+            py, px = divmod(p, CT_W)
+            yy, xx = y0 + py, x0 + px
+            sP[p * CPP + c8] = X[b, yy, xx, 8 * c8:8 * c8 + 8] if (yy < H and xx < W) else 0
+        for n0 in range(0, N, tn):
+            sW = np.full((tn * WS, 8), -1, dtype=np.int64)
+            for i in range(tn * CPX):
+                n, c8 = divmod(i, CPX)
+                sW[n * WS + c8] = U[n0 + n, 8 * c8:8 * c8 + 8] if n0 + n < N else 0
+            for S in range(cin // 16):
+                for wave in range(4):
+                    wm, wn = divmod(wave, wn_n)
+                    for i in range(BM):
+                        for j in range(BN):
+                            ga, gw = {}, {}
+                            for lane in range(64):
+                                col, half = lane & 31, lane >> 5
+                                la = ((wm * BM + i) * CT_W + col) * CPP + half
+                                lw = (wn * WTN + j * 32 + col) * WS + half
+                                c0 = 16 * S + 8 * half
+                                yy, xx = y0 + wm * BM + i, x0 + col
+                                ref = X[b, yy, xx, c0:c0 + 8] if (yy < H and xx < W) else np.zeros(8)
+                                assert np.array_equal(sP[la + 2 * S], ref)
+                                nn = wn * WTN + j * 32 + col
+                                wref = U[n0 + nn, c0:c0 + 8] if n0 + nn < N else np.zeros(8)
+                                assert np.array_equal(sW[lw + 2 * S], wref)
+                                ga.setdefault(lane // 8, set()).add((la + 2 * S) % 8)
+                                gw.setdefault(lane // 8, set()).add((lw + 2 * S) % 8)
+                            for g in list(ga.values()) + list(gw.values()):
+                                assert len(g) == 8
+            # epilogue: register 4 g + q of block (j, i) = channel 8 g + 4 half + q of the block, pixel col
+            for wave in range(4):
+                wm, wn = divmod(wave, wn_n)
+                for i in range(BM):
+                    for j in range(BN):
+                        for lane in range(64):
+                            col, half = lane & 31, lane >> 5
+                            yy, xx = y0 + wm * BM + i, x0 + col
+                            if yy >= H or xx >= W:
+                                continue
+                            for g in range(4):
+                                n = n0 + wn * WTN + j * 32 + 8 * g + 4 * half
+                                if n >= N:
+                                    continue
+                                d, co = n >> lgc, n & (cout - 1)
+                                hit[b, 2 * yy + (d >> 1), 2 * xx + (d & 1), co:co + 4] += 1
+    assert (hit == 1).all()
+
+
 # ------------------------------------------------------------------ fused ROF dual steps
 FTX, FTY = 64, 16
 FRX, FRY = FTX + 4, FTY + 4
