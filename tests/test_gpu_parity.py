@@ -124,6 +124,36 @@ FILTER_CASES = {
 }
 
 
+DEGENERATE = {
+    "one_pixel": dict(nx=1, ny=1, nb=1, K=2, axis=0.0),        # one pixel, one bin, two projections
+    "one_row": dict(nx=9, ny=1, nb=5, K=3, axis=2.0),
+    "one_col": dict(nx=1, ny=7, nb=4, K=3, axis=1.5),
+    "two_angles": dict(nx=16, ny=16, nb=16, K=2, axis=7.5),    # the fewest projections a plan accepts
+}
+
+
+@pytest.mark.parametrize("case", list(DEGENERATE))
+def test_degenerate_geometries(dev, gen, case):
+    """The smallest plans the boundary accepts: backprojection (every tile shape, direct and persistent),
+    projection (every projector kernel), ramp filter and the whole FBP against the oracle."""
+    g, og = pair(**DEGENERATE[case])
+    plan = ph.Plan(g, n_slices=2)
+    y = gen.standard_normal((2, g.n_angles, g.n_det)).astype(np.float32)
+    x = gen.standard_normal((2, g.n_y, g.n_x)).astype(np.float32)
+    yt, xt = torch.from_numpy(y).to(dev), torch.from_numpy(x).to(dev)
+    ref_bp, ref_fp = oracle.backproject(y, og), oracle.forward_project(x, og)
+    for tile, pers in [(-1, False), (0, False), (3, True), (4, False), (5, False), (5, True)]:
+        plan.set_tiles(tile, pers)
+        assert rel(ph.backproject(plan, yt), ref_bp) <= TOL_OP, (case, tile, pers)
+    plan.set_tiles(-1, False)
+    for kind in FP_KINDS.values():
+        plan.set_fp_kernel(kind)
+        assert rel(ph.forward_project(plan, xt), ref_fp) <= TOL_OP, (case, kind)
+    plan.set_fp_kernel(ph.FP_AUTO)
+    assert rel(ph.fbp_filter(plan, yt), oracle.fbp_filter(y, og)) <= TOL_OP, case
+    assert rel(ph.reconstruct_slices(plan, sino=yt, method=ph.FBP), oracle.fbp(y, og)) <= TOL_PIPE, case
+
+
 @pytest.mark.parametrize("case", list(FILTER_CASES))
 def test_fbp_filter_parity(dev, gen, case):
     g, og = pair(**FILTER_CASES[case])
