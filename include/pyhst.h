@@ -421,6 +421,10 @@ int pyhst_unet_set_params(pyhst_unet *net, const float *params, hipStream_t stre
 int pyhst_unet_get_params(const pyhst_unet *net, float *params, hipStream_t stream);
 /* Gradients of the last pyhst_unet_backward (device FP32 [n_params]). */
 int pyhst_unet_get_grads(const pyhst_unet *net, float *grads, hipStream_t stream);
+/* Inference: out = x_hat for the n inputs (device FP32 [n][height][width]).
+ * The output head runs in the epilogue of the last decoder convolution, whose
+ * activation this call does not store (pyhst_unet_tensor kind 5, level 0
+ * holds it after pyhst_unet_backward only). */
 int pyhst_unet_forward(pyhst_unet *net, const float *in, int32_t n, float *out, hipStream_t stream);
 /* Forward, mean-squared-error loss against target (device float *loss, may be
  * NULL) and backward into the gradient buffer. */

@@ -58,6 +58,7 @@ struct pyhst_unet {
     std::vector<Up> up;                             // up[l]: level l+1 -> l
     int64_t head_w = 0, head_b = 0;
     Buf x8;
+    float *w0 = nullptr;                            // first conv's weights, BF16-rounded, as FP32 [co][tap]
     std::vector<Buf> ea, cat, pool, da, db;         // ea[l]: enc conv a out; cat[l]: [enc b out | up out]
     Buf bott_b;                                     // bottleneck conv b out
     float *out = nullptr, *dout = nullptr;
@@ -88,20 +89,115 @@ __global__ void input_pad_kernel(const float *x, int64_t npix, bf16_t *x8, float
     }
 }
 
-// 2x2 max pool: in [b][H][W] (channels c at cs/co) -> out [b][H/2][W/2]
-// 2x2 max-pool; one thread per (output pixel, 8 channels): 4 loads of 16 B, one store of 16 B
-__global__ void pool_fwd_kernel(Act in, int C, bf16_t *out, int ocs, int64_t n)
+// First encoder conv (one real input channel) straight from the FP32 input:
+//   y[p][n] = bf16(relu(sum_tap w[n][tap] xs[p + tap] + bias[n])), xs = bf16(scale x), zero outside the image,
+// with the BF16-rounded weights of the MFMA path (w0, kept as FP32; FP32 sums).  One thread per pixel and
+// all C outputs: the weights are the same for every lane (scalar loads, scalar operands of the FMAs) and
+// the nine inputs are loaded once per pixel.  The outputs (C channels per pixel, contiguous in y) go
+// through LDS so that every store instruction writes 1 KB of consecutive memory.
+template <int C>
+__global__ __launch_bounds__(256) void conv_first_kernel(const float *x, FastDiv fw, FastDiv fh, int npix, float scale,
+                                                         const float *__restrict__ w0, const float *__restrict__ bias,
+                                                         bf16_t *y)
 {
-    const int h = in.H >> 1, w = in.W >> 1, G = C >> 3;
+    constexpr int Q = C / 8;   // 16-byte pieces per pixel
+    __shared__ uint4 sO[256 * Q];
+    const int W = (int)fw.d, H = (int)fh.d;
+    const int p0 = blockIdx.x * blockDim.x;   // one pixel per thread, no loop: the weights are loaded
+    const int p = p0 + threadIdx.x;           // as they are used, not held
+    if (p < npix) {
+        const uint32_t row = fdiv((uint32_t)p, fw);
+        const int xx = p - (int)(row * fw.d), yy = (int)(row - fdiv(row, fh) * fh.d);
+        // the nine loads issue together: a neighbour outside the image reads the pixel itself instead
+        // (always inside) and is then replaced by zero
+        float v[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            const int oy = (unsigned)(yy + dy) < (unsigned)H ? dy : 0, ox = (unsigned)(xx + dx) < (unsigned)W ? dx : 0;
+            v[t] = x[(int64_t)p + oy * W + ox];
+        }
+        float xs[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            const bool in = (unsigned)(yy + dy) < (unsigned)H && (unsigned)(xx + dx) < (unsigned)W;
+            xs[t] = in ? bf16_lo(pack_bf16x2(v[t] * scale, 0.0f)) : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            uint32_t o[4];
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) {
+                const int n = 8 * q + k;
+                float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    s0 = fmaf(w0[9 * n + t], xs[t], s0);
+                    s1 = fmaf(w0[9 * (n + 1) + t], xs[t], s1);
+                }
+                o[k / 2] = pack_bf16x2(fmaxf(s0 + bias[n], 0.0f), fmaxf(s1 + bias[n + 1], 0.0f));
+            }
+            // piece q of pixel t at slot t Q + (q ^ (t % Q)): the lanes of a write spread over the banks
+            sO[threadIdx.x * Q + (q ^ (threadIdx.x & (Q - 1)))] = make_uint4(o[0], o[1], o[2], o[3]);
+        }
+    }
+    __syncthreads();
+    // piece i of the block's output (pixel p0 + i / Q, piece i % Q): thread threadIdx.x takes
+    // i = threadIdx.x + 256 k, consecutive threads consecutive 16 bytes
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const int i = (int)threadIdx.x + 256 * k, t = i / Q, q = i % Q;
+        if (p0 + t < npix) *(uint4 *)(y + ((int64_t)p0 * C + 8 * (int64_t)i)) = sO[t * Q + (q ^ (t & (Q - 1)))];
+    }
+}
+
+// the first conv by conv_first_kernel for the channel counts it is built for; false: not handled
+bool conv_first(const float *x, int n, int H, int W, float scale, const float *w0, const float *bias, int cout,
+                bf16_t *y, int ycs, hipStream_t st)
+{
+    if (ycs != cout) return false;   // the kernel writes contiguous pixels
+    const int npix = n * H * W;
+    const dim3 grid((unsigned)((npix + 255) / 256));
+    const FastDiv fw = make_fastdiv((uint32_t)W), fh = make_fastdiv((uint32_t)H);
+    switch (cout) {
+    case 8: conv_first_kernel<8><<<grid, 256, 0, st>>>(x, fw, fh, npix, scale, w0, bias, y); return true;
+    case 16: conv_first_kernel<16><<<grid, 256, 0, st>>>(x, fw, fh, npix, scale, w0, bias, y); return true;
+    case 32: conv_first_kernel<32><<<grid, 256, 0, st>>>(x, fw, fh, npix, scale, w0, bias, y); return true;
+    case 64: conv_first_kernel<64><<<grid, 256, 0, st>>>(x, fw, fh, npix, scale, w0, bias, y); return true;
+    default: return false;
+    }
+}
+
+// 2x2 max pool: in [b][H][W] (C = 8 G channels at in.co, stride in.cs) -> out [b][H/2][W/2] (stride ocs);
+// one thread per (output pixel, 8 channels): four 16-byte loads, one 16-byte store.  Pixel indices
+// (below 2^31) in 32 bits, divided by multiply-shift.
+struct PoolIdx {
+    int lgG;          // G = 1 << lgG groups of 8 channels
+    FastDiv fw, fhw;  // pooled width, pooled height x width
+};
+PoolIdx pool_idx(int H, int W, int C)
+{
+    int lg = 0;
+    while ((8 << lg) < C) ++lg;
+    return PoolIdx{lg, make_fastdiv((uint32_t)(W >> 1)), make_fastdiv((uint32_t)((H >> 1) * (W >> 1)))};
+}
+__device__ __forceinline__ int64_t pool_src(const Act &in, const PoolIdx &q, uint32_t p)
+{
+    const uint32_t b = fdiv(p, q.fhw), r = p - b * q.fhw.d, y = fdiv(r, q.fw), x = r - y * q.fw.d;
+    return ((int64_t)(b * in.H + 2 * y) * in.W + 2 * x) * in.cs + in.co;
+}
+
+__global__ void pool_fwd_kernel(Act in, PoolIdx q, bf16_t *out, int ocs, int64_t n)
+{
     GRID_LOOP(i, n)
     {
-        const int g = (int)(i % G);
-        const int64_t p = i / G;
-        const int x = (int)(p % w), y = (int)((p / w) % h), b = (int)(p / ((int64_t)w * h));
-        const bf16_t *base = in.p + ((int64_t)(b * in.H + 2 * y) * in.W + 2 * x) * in.cs + in.co + 8 * g;
+        const int g = (int)(i & ((1 << q.lgG) - 1));
+        const uint32_t p = (uint32_t)(i >> q.lgG);
+        const bf16_t *base = in.p + pool_src(in, q, p) + 8 * g;
+        const int64_t row = (int64_t)in.W * in.cs;
         const uint4 q0 = *(const uint4 *)base, q1 = *(const uint4 *)(base + in.cs);
-        const uint4 q2 = *(const uint4 *)(base + (int64_t)in.W * in.cs);
-        const uint4 q3 = *(const uint4 *)(base + (int64_t)in.W * in.cs + in.cs);
+        const uint4 q2 = *(const uint4 *)(base + row), q3 = *(const uint4 *)(base + row + in.cs);
         const bf16_t *e0 = (const bf16_t *)&q0, *e1 = (const bf16_t *)&q1, *e2 = (const bf16_t *)&q2,
                      *e3 = (const bf16_t *)&q3;
         uint4 r;
@@ -109,45 +205,53 @@ __global__ void pool_fwd_kernel(Act in, int C, bf16_t *out, int ocs, int64_t n)
 #pragma unroll
         for (int c = 0; c < 8; ++c)
             er[c] = f2bf(fmaxf(fmaxf(bf2f(e0[c]), bf2f(e1[c])), fmaxf(bf2f(e2[c]), bf2f(e3[c]))));
-        *(uint4 *)(out + p * ocs + 8 * g) = r;
+        *(uint4 *)(out + (int64_t)p * ocs + 8 * g) = r;
     }
 }
 
-// route the pooled gradient to the first maximum (row-major in the 2x2 window), adding to dE;
-// one thread per (output pixel, 8 channels)
-__global__ void pool_bwd_kernel(Act e, bf16_t *de, const bf16_t *dp, int pcs, int C, int64_t n)
+// route the pooled gradient to the first maximum (row-major in the 2x2 window), adding to dE; one
+// thread per (output pixel, 8 channels), which owns those channels of the window's four pixels in dE
+// (read and written back as 16-byte vectors)
+__global__ void pool_bwd_kernel(Act e, bf16_t *de, const bf16_t *dp, int pcs, PoolIdx q, int64_t n)
 {
-    const int h = e.H >> 1, w = e.W >> 1, G = C >> 3;
     GRID_LOOP(i, n)
     {
-        const int gq = (int)(i % G);
-        const int64_t p = i / G;
-        const int x = (int)(p % w), y = (int)((p / w) % h), b = (int)(p / ((int64_t)w * h));
-        const uint4 gv = *(const uint4 *)(dp + p * pcs + 8 * gq);
+        const int gq = (int)(i & ((1 << q.lgG) - 1));
+        const uint32_t p = (uint32_t)(i >> q.lgG);
+        const uint4 gv = *(const uint4 *)(dp + (int64_t)p * pcs + 8 * gq);
         const bf16_t *ge = (const bf16_t *)&gv;
-        const int64_t o0 = ((int64_t)(b * e.H + 2 * y) * e.W + 2 * x) * e.cs + e.co + 8 * gq;
+        const int64_t o0 = pool_src(e, q, p) + 8 * gq;
         const int64_t off[4] = {0, e.cs, (int64_t)e.W * e.cs, (int64_t)e.W * e.cs + e.cs};
-        uint4 q[4];
+        uint4 a[4], d[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) q[k] = *(const uint4 *)(e.p + o0 + off[k]);
+        for (int k = 0; k < 4; ++k) {
+            a[k] = *(const uint4 *)(e.p + o0 + off[k]);
+            d[k] = *(const uint4 *)(de + o0 + off[k]);
+        }
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const float g = bf2f(ge[c]);
             int arg = 0;
-            float mx = bf2f(((const bf16_t *)&q[0])[c]);
+            float mx = bf2f(((const bf16_t *)&a[0])[c]);
 #pragma unroll
             for (int k = 1; k < 4; ++k) {
-                const float v = bf2f(((const bf16_t *)&q[k])[c]);
+                const float v = bf2f(((const bf16_t *)&a[k])[c]);
                 if (v > mx) {
                     mx = v;
                     arg = k;
                 }
             }
             if (mx > 0.0f && g != 0.0f) {
-                bf16_t *t = de + o0 + off[arg] + c;
-                *t = f2bf(bf2f(*t) + g);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k == arg) {
+                        bf16_t *t = (bf16_t *)&d[k] + c;
+                        *t = f2bf(bf2f(*t) + g);
+                    }
             }
         }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) *(uint4 *)(de + o0 + off[k]) = d[k];
     }
 }
 
@@ -343,6 +447,12 @@ __global__ void cast_conv_kernel(const float *w, int cin, int cout, bf16_t *wf, 
     }
 }
 
+// first conv (cin 8, of which channel 0 is real): w0[co][tap] = bf16(W[co][tap][0]) as FP32
+__global__ void cast_first_kernel(const float *w, int cout, float *w0)
+{
+    GRID_LOOP(i, (int64_t)cout * 9) w0[i] = bf2f(f2bf(w[i * 8]));
+}
+
 // master U[d][co][ci] -> uf (same layout) and ub[ci][(d, co)]
 __global__ void cast_up_kernel(const float *u, int cin, int cout, bf16_t *uf, bf16_t *ub)
 {
@@ -381,15 +491,59 @@ bool conv_direct(int cin, const Act &x, const WeightB &w, const EP &e, int n, in
     }
 }
 
-// N tile: the GEMM's, narrowed to 32 outputs where that lets the persistent form keep the weights
-// (64 input channels)
+// N tile of the direct kernels: the GEMM's
+int direct_tn(int, int n) { return tn_for(n); }
+
+template <int TN>
+bool direct_layout(int cin, int &bm, int &wn)
+{
+    switch (cin) {
+#define PYHST_LAYOUT_CASE(C)         \
+    case C:                          \
+        bm = conv_bm<C, TN>();       \
+        wn = conv_wn<C, TN>();       \
+        return true;
+        PYHST_LAYOUT_CASE(8)
+        PYHST_LAYOUT_CASE(16)
+        PYHST_LAYOUT_CASE(32)
+        PYHST_LAYOUT_CASE(64)
+        PYHST_LAYOUT_CASE(128)
+        PYHST_LAYOUT_CASE(256)
+#undef PYHST_LAYOUT_CASE
+    default: return false;
+    }
+}
+
+// wave layout of the direct kernel for (cin, n): row blocks per wavefront, wavefront columns, N tile
+bool direct_kernel_layout(int cin, int n, int &bm, int &wn, int &tn)
+{
+    tn = direct_tn(cin, n);
+    switch (tn) {
+    case 128: return direct_layout<128>(cin, bm, wn);
+    case 64: return direct_layout<64>(cin, bm, wn);
+    default: return direct_layout<32>(cin, bm, wn);
+    }
+}
+
+// the 2x2 max pool fits the epilogue of the layer's direct kernel (a wavefront holds both rows of
+// its windows)
+bool pool_fusable(const Conv &L)
+{
+    int bm = 0, wn = 0, tn = 0;
+    return direct_kernel_layout(L.cin, L.cout, bm, wn, tn) && bm == 2;
+}
+// the head fits the epilogue (one workgroup column holds every output channel in one wavefront)
+bool head_fusable(const Conv &L)
+{
+    int bm = 0, wn = 0, tn = 0;
+    return direct_kernel_layout(L.cin, L.cout, bm, wn, tn) && wn == 1 && tn >= L.cout;
+}
+
 template <class EP>
 bool conv_direct_tn(int cin, const Act &x, const WeightB &w, const EP &e, int n, int cu, hipStream_t st,
                     hipError_t &err)
 {
-    int tn = tn_for(n);
-    while (tn > 32 && tn * 9 * cin > 20480 && 32 * 9 * cin <= 20480) tn >>= 1;
-    switch (tn) {
+    switch (direct_tn(cin, n)) {
     case 128: return conv_direct<128>(cin, x, w, e, n, cu, st, err);
     case 64: return conv_direct<64>(cin, x, w, e, n, cu, st, err);
     default: return conv_direct<32>(cin, x, w, e, n, cu, st, err);
@@ -409,6 +563,43 @@ hipError_t conv_fwd(const pyhst_unet &net, const Conv &L, Act in, bf16_t *out, i
     case 64: return run_gemm<Im2colA, WeightB, StoreAct, 64>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
     default: return run_gemm<Im2colA, WeightB, StoreAct, 32>(A, Bw, E, M, L.cout, 9 * L.cin, 1, st);
     }
+}
+
+// conv + ReLU into out and its 2x2 max pool into pool, one kernel (pool_fusable(L))
+hipError_t conv_fwd_pool(const pyhst_unet &net, const Conv &L, Act in, bf16_t *out, int ocs, bf16_t *pool, int pcs,
+                         hipStream_t st)
+{
+    ConvStoreActPool E;
+    E.y = out;
+    E.cs = ocs;
+    E.co = 0;
+    E.bias = net.params + L.b;
+    E.pool = pool;
+    E.pcs = pcs;
+    hipError_t err = hipSuccess;
+    if (!conv_direct_tn(L.cin, in, WeightB{L.wf, 9 * L.cin}, E, L.cout, net.cu_count, st, err)) return hipErrorInvalidValue;
+    return err;
+}
+
+// last decoder conv + ReLU with the head in its epilogue (head_fusable(L)): out = the network's output;
+// act (may be null) receives the conv's activation
+hipError_t conv_fwd_head(const pyhst_unet &net, const Conv &L, Act in, bf16_t *act_out, int acs, const float *x,
+                         float *out, int unscale, hipStream_t st)
+{
+    ConvStoreHead E;
+    E.y = act_out;
+    E.cs = acs;
+    E.co = 0;
+    E.bias = net.params + L.b;
+    E.wh = net.params + net.head_w;
+    E.bh = net.params + net.head_b;
+    E.xin = x;
+    E.out = out;
+    E.scale = net.scale;
+    E.unscale = unscale;
+    hipError_t err = hipSuccess;
+    if (!conv_direct_tn(L.cin, in, WeightB{L.wf, 9 * L.cin}, E, L.cout, net.cu_count, st, err)) return hipErrorInvalidValue;
+    return err;
 }
 
 hipError_t up_fwd(const pyhst_unet &net, const Up &L, Act in, bf16_t *out, int H2, int W2, int ocs, int oco,
@@ -527,6 +718,7 @@ hipError_t cast_all(const pyhst_unet &net, hipStream_t st)
                                                                                   c.wf, c.wb);
     };
     for (auto &c : net.enc_a) cc(c);
+    cast_first_kernel<<<1, 256, 0, st>>>(net.params + net.enc_a[0].w, net.enc_a[0].cout, net.w0);
     for (auto &c : net.enc_b) cc(c);
     for (auto &c : net.dec_a) cc(c);
     for (auto &c : net.dec_b) cc(c);
@@ -536,26 +728,38 @@ hipError_t cast_all(const pyhst_unet &net, hipStream_t st)
     return hipGetLastError();
 }
 
-// unscale = 1: out in the caller's units; 0: in the network's (scaled) units
-hipError_t forward(pyhst_unet &net, const float *in, int n, float *out, int unscale, hipStream_t st)
+// unscale = 1: out in the caller's units; 0: in the network's (scaled) units.  keep: store every
+// activation the backward pass reads (without it the last decoder conv's output, which only the fused
+// head reads, is not written)
+hipError_t forward(pyhst_unet &net, const float *in, int n, float *out, int unscale, bool keep, hipStream_t st)
 {
     const int L = net.L;
     hipError_t e;
-    input_pad_kernel<<<blocks_for((int64_t)n * net.H * net.W), 256, 0, st>>>(in, (int64_t)n * net.H * net.W,
-                                                                             net.x8.a, net.scale);
+    const int64_t npix = (int64_t)n * net.H * net.W;
+    const Conv &c0 = net.enc_a[0];
+    const bool first = conv_first(in, n, net.H, net.W, net.scale, net.w0, net.params + c0.b, c0.cout, net.ea[0].a,
+                                  net.ea[0].C, st);
+    if (keep || !first)   // the first conv's input as the backward pass reads it (8 channels, the first one real)
+        input_pad_kernel<<<blocks_for(npix), 256, 0, st>>>(in, npix, net.x8.a, net.scale);
     Act cur = act(net.x8, n);
     for (int l = 0; l < L; ++l) {
         const bool bott = l == L - 1;
-        if ((e = conv_fwd(net, net.enc_a[l], cur, net.ea[l].a, net.ea[l].C, 0, st)) != hipSuccess) return e;
+        if ((l > 0 || !first) && (e = conv_fwd(net, net.enc_a[l], cur, net.ea[l].a, net.ea[l].C, 0, st)) != hipSuccess)
+            return e;
         Act a = act(net.ea[l], n);
         if (bott) {
             if ((e = conv_fwd(net, net.enc_b[l], a, net.bott_b.a, net.bott_b.C, 0, st)) != hipSuccess) return e;
+        } else if (pool_fusable(net.enc_b[l])) {
+            if ((e = conv_fwd_pool(net, net.enc_b[l], a, net.cat[l].a, net.cat[l].C, net.pool[l].a, net.pool[l].C,
+                                   st)) != hipSuccess)
+                return e;
+            cur = act(net.pool[l], n);
         } else {
             if ((e = conv_fwd(net, net.enc_b[l], a, net.cat[l].a, net.cat[l].C, 0, st)) != hipSuccess) return e;
             const int c = net.enc_b[l].cout;
             const int64_t np = (int64_t)n * net.pool[l].H * net.pool[l].W * c;
-            pool_fwd_kernel<<<blocks_for(np / 8), 256, 0, st>>>(act(net.cat[l], n), c, net.pool[l].a, net.pool[l].C,
-                                                                np / 8);
+            pool_fwd_kernel<<<blocks_for(np / 8), 256, 0, st>>>(act(net.cat[l], n), pool_idx(net.cat[l].H, net.cat[l].W, c),
+                                                                net.pool[l].a, net.pool[l].C, np / 8);
             cur = act(net.pool[l], n);
         }
     }
@@ -567,11 +771,13 @@ hipError_t forward(pyhst_unet &net, const float *in, int n, float *out, int unsc
             return e;
         if ((e = conv_fwd(net, net.dec_a[l], act(net.cat[l], n), net.da[l].a, net.da[l].C, 0, st)) != hipSuccess)
             return e;
+        if (l == 0 && head_fusable(net.dec_b[0]))
+            return conv_fwd_head(net, net.dec_b[0], act(net.da[0], n), keep ? net.db[0].a : nullptr, net.db[0].C, in,
+                                 out, unscale, st);
         if ((e = conv_fwd(net, net.dec_b[l], act(net.da[l], n), net.db[l].a, net.db[l].C, 0, st)) != hipSuccess)
             return e;
         below = act(net.db[l], n);
     }
-    const int64_t npix = (int64_t)n * net.H * net.W;
     head_fwd_kernel<<<blocks_for(npix), 256, 0, st>>>(net.db[0].a, net.db[0].C, net.params + net.head_w,
                                                       net.params + net.head_b, in, out, npix, net.scale, unscale);
     return hipGetLastError();
@@ -579,7 +785,7 @@ hipError_t forward(pyhst_unet &net, const float *in, int n, float *out, int unsc
 
 hipError_t backward(pyhst_unet &net, const float *in, const float *target, int n, float *loss, hipStream_t st)
 {
-    hipError_t e = forward(net, in, n, net.out, 0, st);
+    hipError_t e = forward(net, in, n, net.out, 0, true, st);
     if (e != hipSuccess) return e;
     const int L = net.L;
     const int64_t npix = (int64_t)n * net.H * net.W;
@@ -631,7 +837,8 @@ hipError_t backward(pyhst_unet &net, const float *in, const float *target, int n
             const int c = net.enc_b[l - 1].cout;
             const int64_t np = (int64_t)n * net.pool[l - 1].H * net.pool[l - 1].W * c;
             pool_bwd_kernel<<<blocks_for(np / 8), 256, 0, st>>>(act(net.cat[l - 1], n), net.cat[l - 1].g,
-                                                                net.pool[l - 1].g, net.pool[l - 1].C, c, np / 8);
+                                                                net.pool[l - 1].g, net.pool[l - 1].C,
+                                                                pool_idx(net.cat[l - 1].H, net.cat[l - 1].W, c), np / 8);
         }
     }
     return hipGetLastError();
@@ -762,6 +969,7 @@ int pyhst_unet_create(int32_t batch, int32_t height, int32_t width, int32_t base
     part = std::max<size_t>(part, (size_t)1024 * 512);
     net->part_floats = part;
     const size_t o_part = take(4 * part), o_dpart = take(8 * 4096);
+    const size_t o_w0 = take((size_t)4 * 9 * base);
     std::vector<std::pair<bf16_t **, size_t>> wbufs;
     auto wb = [&](bf16_t **p, int64_t n) { wbufs.push_back({p, take(2 * n)}); };
     for (auto *vec : {&net->enc_a, &net->enc_b, &net->dec_a, &net->dec_b})
@@ -796,6 +1004,7 @@ int pyhst_unet_create(int32_t batch, int32_t height, int32_t width, int32_t base
     net->m = (float *)(b + o_m);
     net->v = (float *)(b + o_v);
     net->step = (int *)(b + o_step);
+    net->w0 = (float *)(b + o_w0);
     net->out = (float *)(b + o_out);
     net->dout = (float *)(b + o_dout);
     net->part = (float *)(b + o_part);
@@ -863,7 +1072,7 @@ int pyhst_unet_forward(pyhst_unet *net, const float *in, int32_t n, float *out, 
 {
     if (!net || !in || !out) return fail(PYHST_EARG, "unet_forward: NULL argument");
     if (n <= 0 || n > net->B) return fail(PYHST_EARG, "unet_forward: n must be in [1, batch]");
-    hipError_t e = forward(*net, in, n, out, 1, st);
+    hipError_t e = forward(*net, in, n, out, 1, false, st);
     return e == hipSuccess ? PYHST_OK : hip_fail(e, "unet_forward");
 }
 

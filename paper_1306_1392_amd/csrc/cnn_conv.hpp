@@ -21,6 +21,7 @@
 #pragma once
 
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 #include "cnn_gemm.hpp"
@@ -31,10 +32,11 @@ namespace cnn {
 constexpr int CT_W = 32, CT_PW = CT_W + 2;   // tile width; patch width
 
 // wave layout of a CTH x 32-pixel, TN-channel tile: WM x WN wavefronts, each with BM row blocks (tile
-// rows) and BN column blocks of 32
+// rows) and BN column blocks of 32 (8-row tiles: four wavefronts of two rows and every column, so an
+// operand read from LDS serves BN or two MFMAs)
 template <int TN, int CTH>
 struct ConvGrid {
-    static constexpr int WM = WaveGrid<TN>::WM, WN = WaveGrid<TN>::WN;
+    static constexpr int WM = CTH >= 8 ? 4 : WaveGrid<TN>::WM, WN = 4 / WM;
     static constexpr int BM = CTH / WM, BN = TN / WN / 32, WTN = TN / WN;
     static constexpr int PIX = (CTH + 2) * CT_PW;   // patch pixels
     static_assert(CTH % WM == 0, "whole tile rows per wavefront");
@@ -75,29 +77,48 @@ __device__ inline uint32_t pack_bf16x2(float a, float b)   // round to nearest e
     return u;
 }
 
-// Epilogues of four consecutive output channels n .. n + 3 of output pixel m.
+// Epilogues.  pack4 turns the accumulators of four consecutive output channels n .. n + 3 of output
+// pixel m into four BF16 values (ok: m and n are inside the output; an epilogue that reads memory reads
+// only then); store8 writes eight consecutive channels n .. n + 7 of pixel m (16 bytes).  POOL: the
+// epilogue also writes the 2x2 max pool of its output; HEAD: it applies the network's 1x1 head.
 struct ConvStoreAct {    // y = bf16(relu(v + bias))
-    static constexpr bool BIAS = true;
+    static constexpr bool BIAS = true, POOL = false, HEAD = false;
     bf16_t *y;
     int cs, co;
     const float *bias;
-    __device__ void store4(int m, int n, const float *v, const float4 &b) const
+    __device__ uint2 pack4(int, int, const float *v, const float4 &b, bool) const
     {
-        const uint2 w = make_uint2(pack_bf16x2(fmaxf(v[0] + b.x, 0.0f), fmaxf(v[1] + b.y, 0.0f)),
-                                   pack_bf16x2(fmaxf(v[2] + b.z, 0.0f), fmaxf(v[3] + b.w, 0.0f)));
-        *(uint2 *)(y + (int64_t)m * cs + co + n) = w;
+        return make_uint2(pack_bf16x2(fmaxf(v[0] + b.x, 0.0f), fmaxf(v[1] + b.y, 0.0f)),
+                          pack_bf16x2(fmaxf(v[2] + b.z, 0.0f), fmaxf(v[3] + b.w, 0.0f)));
     }
+    __device__ void store8(int m, int n, const uint4 &o) const { *(uint4 *)(y + (int64_t)m * cs + co + n) = o; }
+};
+// y as ConvStoreAct and its 2x2 max pool: pool[(b, yy / 2, xx / 2)][n] (channel stride pcs)
+struct ConvStoreActPool : ConvStoreAct {
+    static constexpr bool POOL = true;
+    bf16_t *pool;
+    int pcs;
+};
+// the head on the activation a = bf16(relu(v + bias)) of every channel (all in one workgroup):
+// r = scale xin + (bh + sum_n wh[n] a[n]); out = r / scale (unscale) or r.  y (when not null) also
+// receives a, for the backward pass.
+struct ConvStoreHead : ConvStoreAct {
+    static constexpr bool HEAD = true;
+    const float *wh, *bh, *xin;
+    float *out;
+    float scale;
+    int unscale;
 };
 struct ConvStoreMasked { // dx = bf16(v) where act > 0, else 0
-    static constexpr bool BIAS = false;
+    static constexpr bool BIAS = false, POOL = false, HEAD = false;
     bf16_t *dx;
     int cs, co;
     const bf16_t *act;
     int acs, aco;
     const float *bias;   // unused
-    __device__ void store4(int m, int n, const float *v, const float4 &) const
+    __device__ uint2 pack4(int m, int n, const float *v, const float4 &, bool ok) const
     {
-        const uint2 a = *(const uint2 *)(act + (int64_t)m * acs + aco + n);
+        const uint2 a = ok ? *(const uint2 *)(act + (int64_t)m * acs + aco + n) : make_uint2(0u, 0u);
         float o[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -105,9 +126,20 @@ struct ConvStoreMasked { // dx = bf16(v) where act > 0, else 0
             const uint32_t mag = h & 0x7fffu;
             o[q] = !(h & 0x8000u) && mag != 0 && mag <= 0x7f80u ? v[q] : 0.0f;   // act > 0 (BF16 bits)
         }
-        *(uint2 *)(dx + (int64_t)m * cs + co + n) = make_uint2(pack_bf16x2(o[0], o[1]), pack_bf16x2(o[2], o[3]));
+        return make_uint2(pack_bf16x2(o[0], o[1]), pack_bf16x2(o[2], o[3]));
     }
+    __device__ void store8(int m, int n, const uint4 &o) const { *(uint4 *)(dx + (int64_t)m * cs + co + n) = o; }
 };
+
+// Lanes l and l + 32 (half-waves 0 and 1) hold channels 8 g + 4 half .. + 3 (a) and 8 (g + 1) + 4 half
+// .. + 3 (b) of one pixel.  v_permlane32_swap exchanges lanes 32..63 of its first operand with lanes 0..31
+// of its second, after which lane half h holds the eight channels 8 (g + h) .. + 7 (16 bytes).
+__device__ __forceinline__ uint4 gather8(uint2 a, uint2 b)
+{
+    const auto x = __builtin_amdgcn_permlane32_swap(a.x, b.x, false, false);
+    const auto y = __builtin_amdgcn_permlane32_swap(a.y, b.y, false, false);
+    return make_uint4(x[0], y[0], x[1], y[1]);
+}
 
 // One MFMA K step S (16 K values) of the persistent form: weights as the A operand, the patch as the
 // B operand, so accumulator register r holds output channel 8 (r / 4) + 4 (lane / 32) + r % 4 of
@@ -157,30 +189,118 @@ __device__ __forceinline__ void pconv_steps(std::integer_sequence<int, S...>, co
     (pconv_step<CIN, TN, CTH, S>(sP, sW, la, lw, half, acc), ...);
 }
 
-// Four-channel epilogue of one output tile, shared by both forms: accumulator register 4 g + q of
-// column block j, row block i holds output channel 8 g + 4 (lane / 32) + q of the block, pixel lane % 32.
+// max of two packed pairs of BF16 values from a ReLU (compared as floats, so -0 and +0 tie)
+__device__ __forceinline__ uint32_t max_bf16x2(uint32_t a, uint32_t b)
+{
+    const float lo = fmaxf(__uint_as_float(a << 16), __uint_as_float(b << 16));
+    const float hi = fmaxf(__uint_as_float(a & 0xffff0000u), __uint_as_float(b & 0xffff0000u));
+    return (__float_as_uint(lo) >> 16) | (__float_as_uint(hi) & 0xffff0000u);
+}
+// the value held by lane ^ 1 (DPP quad permutation 1, 0, 3, 2)
+__device__ __forceinline__ uint32_t from_lane_xor1(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float bf16_lo(uint32_t u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
+
+// Epilogue of one output tile, shared by both forms: accumulator register 4 g + q of column block j,
+// row block i holds output channel 8 g + 4 (lane / 32) + q of the block, pixel lane % 32.  Groups g, g + 1
+// are packed, exchanged between the half-waves (gather8) and stored as 16 bytes per lane; every lane
+// takes part in the exchanges, and only the stores test the bounds (N is a multiple of 8).
+// POOL: the two row blocks of a wavefront are the two rows of its pooling windows (the tile and the image
+// start on even rows, H and W are even) and lanes col, col ^ 1 the two columns.  HEAD: the wavefront
+// holds every channel of its pixels (one workgroup column, WN = 1), half of them in each half-wave.
 template <int TN, int CTH, class EP>
 __device__ __forceinline__ void pconv_store(const Act &x, const ConvTile &c, int n0, int N, int wm, int wn, int col,
-                                            int half, const EP &E, const float4 *sBias,
+                                            int half, const EP &E, const float4 *sBias, const float4 *sHead,
                                             f32x16 (&acc)[ConvGrid<TN, CTH>::BN][ConvGrid<TN, CTH>::BM])
 {
     constexpr int BM = ConvGrid<TN, CTH>::BM, BN = ConvGrid<TN, CTH>::BN, WTN = ConvGrid<TN, CTH>::WTN;
     const int xx = c.x0 + col;
-#pragma unroll
-    for (int i = 0; i < BM; ++i) {
-        const int yy = c.y0 + wm * BM + i;
-        if (yy >= x.H || xx >= x.W) continue;
+    if constexpr (EP::POOL) {
+        static_assert(BM == 2, "both rows of every pooling window in one wavefront");
+        const int yy = c.y0 + 2 * wm;
+        const bool in = yy < x.H && xx < x.W;   // alike for the lanes of a window (even W) and both half-waves
         const int m = (c.b * x.H + yy) * x.W + xx;
+        const int64_t pm = ((int64_t)(c.b * (x.H >> 1) + (yy >> 1)) * (x.W >> 1) + (xx >> 1)) * E.pcs;
 #pragma unroll
         for (int j = 0; j < BN; ++j)
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int nl = wn * WTN + j * 32 + 8 * g + 4 * half;
-                if (n0 + nl >= N) continue;
-                const float4 bb = EP::BIAS ? sBias[nl >> 2] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                const float v[4] = {acc[j][i][4 * g], acc[j][i][4 * g + 1], acc[j][i][4 * g + 2], acc[j][i][4 * g + 3]};
-                E.store4(m, n0 + nl, v, bb);
+            for (int g = 0; g < 4; g += 2) {
+                const int nb = wn * WTN + j * 32 + 8 * g, nl0 = nb + 4 * half, nl1 = nl0 + 8;
+                uint2 r[2][2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int nl = h ? nl1 : nl0;
+                        const float v[4] = {acc[j][i][4 * (g + h)], acc[j][i][4 * (g + h) + 1],
+                                            acc[j][i][4 * (g + h) + 2], acc[j][i][4 * (g + h) + 3]};
+                        r[i][h] = E.pack4(m + i * x.W, n0 + nl, v, sBias[nl >> 2], in && n0 + nl < N);
+                    }
+                uint2 pool[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    uint32_t px = max_bf16x2(r[0][h].x, r[1][h].x), py = max_bf16x2(r[0][h].y, r[1][h].y);
+                    px = max_bf16x2(px, from_lane_xor1(px));
+                    py = max_bf16x2(py, from_lane_xor1(py));
+                    pool[h] = make_uint2(px, py);
+                }
+                const uint4 o0 = gather8(r[0][0], r[0][1]), o1 = gather8(r[1][0], r[1][1]);
+                const uint4 op = gather8(pool[0], pool[1]);
+                const int nc = n0 + nb + 8 * half;
+                if (in && nc < N) {
+                    E.store8(m, nc, o0);
+                    E.store8(m + x.W, nc, o1);
+                    if (!(col & 1)) *(uint4 *)(E.pool + pm + nc) = op;
+                }
             }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < BM; ++i) {
+        const int yy = c.y0 + wm * BM + i;
+        const bool in = yy < x.H && xx < x.W;   // alike in both half-waves (same pixel)
+        const int m = in ? (c.b * x.H + yy) * x.W + xx : 0;
+        float s = 0.0f;   // HEAD: this half-wave's share of the head's sum
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+#pragma unroll
+            for (int g = 0; g < 4; g += 2) {
+                const int nb = wn * WTN + j * 32 + 8 * g;
+                uint2 r[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int nl = nb + 8 * h + 4 * half;
+                    const float v[4] = {acc[j][i][4 * (g + h)], acc[j][i][4 * (g + h) + 1], acc[j][i][4 * (g + h) + 2],
+                                        acc[j][i][4 * (g + h) + 3]};
+                    const float4 bb = EP::BIAS ? sBias[nl >> 2] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    r[h] = E.pack4(m, n0 + nl, v, bb, in && n0 + nl < N);
+                    if constexpr (EP::HEAD) {
+                        const float4 w = sHead[nl >> 2];   // zero beyond N
+                        s = fmaf(bf16_lo(r[h].x), w.x, s);
+                        s = fmaf(bf16_hi(r[h].x), w.y, s);
+                        s = fmaf(bf16_lo(r[h].y), w.z, s);
+                        s = fmaf(bf16_hi(r[h].y), w.w, s);
+                    }
+                }
+                bool keep = true;
+                if constexpr (EP::HEAD) keep = E.y != nullptr;
+                if (keep) {
+                    const uint4 o = gather8(r[0], r[1]);
+                    const int nc = n0 + nb + 8 * half;
+                    if (in && nc < N) E.store8(m, nc, o);
+                }
+            }
+        if constexpr (EP::HEAD) {
+            static_assert(ConvGrid<TN, CTH>::WN == 1, "every channel of a pixel in one wavefront");
+            s += __shfl_xor(s, 32, 64);   // the other half-wave's channels (a + b = b + a: both halves agree)
+            if (in && !half) {
+                const float r = E.xin[m] * E.scale + (E.bh[0] + s);
+                E.out[m] = E.unscale ? r / E.scale : r;
+            }
+        }
     }
 }
 
@@ -202,6 +322,7 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
     __shared__ uint4 sP[G_::PIX * CPP];
     __shared__ uint4 sW[TN * WS];
     __shared__ float4 sBias[TN / 4];
+    __shared__ float4 sHead[EP::HEAD ? TN / 4 : 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WNW, wn = wave % WNW;
     const int col = lane & 31, half = lane >> 5;
@@ -212,6 +333,8 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
         sW[n * WS + tap * CPX + c8] = n0 + n < N ? ld8(B.w + (int64_t)(n0 + n) * B.K + tap * CIN + 8 * c8) : zero8();
     }
     if (EP::BIAS && threadIdx.x < TN) ((float *)sBias)[threadIdx.x] = n0 + (int)threadIdx.x < N ? E.bias[n0 + threadIdx.x] : 0.0f;
+    if constexpr (EP::HEAD)
+        if (threadIdx.x < TN) ((float *)sHead)[threadIdx.x] = n0 + (int)threadIdx.x < N ? E.wh[n0 + threadIdx.x] : 0.0f;
     // this thread's patch vectors, the same for every tile: pixel (py, px), chunk c8, LDS slot
     int spos[NPV], sdst[NPV];
 #pragma unroll
@@ -257,7 +380,7 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) acc[j][i][q] = 0.0f;
         pconv_steps<CIN, TN, CTH>(std::make_integer_sequence<int, NSTEP>{}, sP, sW, la, lw, half, acc);
-        pconv_store<TN, CTH>(x, conv_tile<CTH>(x, t), n0, N, wm, wn, col, half, E, sBias, acc);
+        pconv_store<TN, CTH>(x, conv_tile<CTH>(x, t), n0, N, wm, wn, col, half, E, sBias, sHead, acc);
     };
     const int G = gridDim.x;
     load(pa, blockIdx.x);
@@ -268,24 +391,27 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
     }
 }
 
-// channels per chunk of the general form: the chunk's weights [TN][9][CC] take at most 36 KB
+// channels per chunk of the general form: the chunk's weights [TN][9][CC] take at most 36 KB, and patch
+// plus weights about 70 KB (two workgroups per CU)
 template <int CIN, int TN>
 constexpr int conv_cc()
 {
-    constexpr int cap = TN >= 128 ? 16 : (TN >= 64 ? 32 : 64);
+    constexpr int cap = TN >= 128 ? 16 : 32;
     return CIN < cap ? CIN : cap;
 }
 
-// General form (the layers whose weights do not fit the persistent form): one output tile per
-// workgroup; per chunk of CC input channels the tile's patch and the chunk's weights for the TN
-// outputs are staged in LDS (the layouts of the persistent form, for CC channels), the K steps of
-// the chunk run from LDS, and the next chunk is meanwhile loaded into registers.  Two barriers per
-// chunk.  K order: chunk, tap, channel within the chunk.
+// General form (the layers whose weights do not fit the persistent form): one 8 x 32-pixel output
+// tile per workgroup (a staged chunk of weights serves 256 pixels); per chunk of CC input channels the
+// tile's patch and the chunk's weights for the TN outputs are staged in LDS (the layouts of the
+// persistent form, for CC channels), the K steps of the chunk run from LDS, and the next chunk is
+// meanwhile loaded into registers.  Two barriers per chunk.  K order: chunk, tap, channel within the
+// chunk.
+constexpr int CONV_GEN_CTH = 8;
 template <int CIN, int TN, class EP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void conv3x3_kernel(Act x, WeightB B, EP E, int N)
 {
-    constexpr int CTH = 4;
+    constexpr int CTH = CONV_GEN_CTH;
     using G_ = ConvGrid<TN, CTH>;
     constexpr int CC = conv_cc<CIN, TN>(), CPX = CC / 8, CPP = CPX | 1, WS = conv_ws(CPX);
     constexpr int NCH = CIN / CC;
@@ -297,12 +423,15 @@ void conv3x3_kernel(Act x, WeightB B, EP E, int N)
     __shared__ uint4 sP[G_::PIX * CPP];
     __shared__ uint4 sW[TN * WS];
     __shared__ float4 sBias[TN / 4];
+    __shared__ float4 sHead[EP::HEAD ? TN / 4 : 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WNW, wn = wave % WNW;
     const int col = lane & 31, half = lane >> 5;
     const ConvTile c = conv_tile<CTH>(x, blockIdx.x);
     const int n0 = blockIdx.y * TN;
     if (EP::BIAS && threadIdx.x < TN) ((float *)sBias)[threadIdx.x] = n0 + (int)threadIdx.x < N ? E.bias[n0 + threadIdx.x] : 0.0f;
+    if constexpr (EP::HEAD)
+        if (threadIdx.x < TN) ((float *)sHead)[threadIdx.x] = n0 + (int)threadIdx.x < N ? E.wh[n0 + threadIdx.x] : 0.0f;
 
     // this thread's vectors of a chunk (the same for every chunk up to the channel offset ch CC):
     // source element offset (-1: zero) from the tile's image or from the weights, LDS slot
@@ -364,7 +493,7 @@ void conv3x3_kernel(Act x, WeightB B, EP E, int N)
             __syncthreads();
         }
     }
-    pconv_store<TN, CTH>(x, c, n0, N, wm, wn, col, half, E, sBias, acc);
+    pconv_store<TN, CTH>(x, c, n0, N, wm, wn, col, half, E, sBias, sHead, acc);
 }
 
 // ---- transposed 2x2 convolution, stride 2 (the U-Net's up-sampling) ------------------------------
@@ -486,22 +615,27 @@ void up2x2_kernel(Act x, const bf16_t *w, const float *bias, int lgc, bf16_t *y,
 #pragma unroll
         for (int i = 0; i < BM; ++i) {
             const int yy = c.y0 + wm * BM + i;
-            if (yy >= x.H || xx >= x.W) continue;
+            const bool in = yy < x.H && xx < x.W;
 #pragma unroll
             for (int j = 0; j < BN; ++j)
 #pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const int nl = wn * WTN + j * 32 + 8 * g + 4 * half;
-                    const int n = n0 + nl;
-                    if (n >= N) continue;
+                for (int g = 0; g < 4; g += 2) {
+                    const int nb = wn * WTN + j * 32 + 8 * g;
+                    uint2 r[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const float4 bb = sBias[(nb + 8 * h + 4 * half) >> 2];
+                        const float a0 = acc[j][i][4 * (g + h)], a1 = acc[j][i][4 * (g + h) + 1];
+                        const float a2 = acc[j][i][4 * (g + h) + 2], a3 = acc[j][i][4 * (g + h) + 3];
+                        r[h] = make_uint2(pack_bf16x2(fmaxf(a0 + bb.x, 0.0f), fmaxf(a1 + bb.y, 0.0f)),
+                                          pack_bf16x2(fmaxf(a2 + bb.z, 0.0f), fmaxf(a3 + bb.w, 0.0f)));
+                    }
+                    const uint4 o = gather8(r[0], r[1]);
+                    const int n = n0 + nb + 8 * half;   // eight channels of one sub-pixel d (cout >= 8)
+                    if (!in || n >= N) continue;
                     const int d = n >> lgc, co = n & cmask;
                     const int m2 = (c.b * H2 + 2 * yy + (d >> 1)) * W2 + 2 * xx + (d & 1);
-                    const float4 bb = sBias[nl >> 2];
-                    const float a0 = acc[j][i][4 * g], a1 = acc[j][i][4 * g + 1];
-                    const float a2 = acc[j][i][4 * g + 2], a3 = acc[j][i][4 * g + 3];
-                    *(uint2 *)(y + (int64_t)m2 * ycs + yco + co) =
-                        make_uint2(pack_bf16x2(fmaxf(a0 + bb.x, 0.0f), fmaxf(a1 + bb.y, 0.0f)),
-                                   pack_bf16x2(fmaxf(a2 + bb.z, 0.0f), fmaxf(a3 + bb.w, 0.0f)));
+                    *(uint4 *)(y + (int64_t)m2 * ycs + yco + co) = o;
                 }
         }
     };
@@ -518,7 +652,7 @@ void up2x2_kernel(Act x, const bf16_t *w, const float *bias, int lgc, bf16_t *y,
 inline bool run_up2x2(const Act &x, const bf16_t *w, const float *bias, int cin, int cout, bf16_t *y, int ycs, int yco,
                       int cu_count, hipStream_t st, hipError_t &err)
 {
-    if (cout < 4 || (cout & (cout - 1))) return false;
+    if (cout < 8 || (cout & (cout - 1))) return false;
     int lgc = 0;
     while ((1 << lgc) < cout) ++lgc;
     const int N = 4 * cout, tn = N >= 128 ? 128 : (N >= 64 ? 64 : 32);
@@ -547,12 +681,20 @@ inline bool run_up2x2(const Act &x, const bf16_t *w, const float *bias, int cin,
 #undef PYHST_UP_CASE
 }
 
-// the persistent form's four-channel epilogue of a GEMM epilogue
+// the direct kernels' four-channel epilogue of a GEMM epilogue
 inline ConvStoreAct conv_ep(const StoreAct &e) { return ConvStoreAct{e.y, e.cs, e.co, e.bias}; }
 inline ConvStoreMasked conv_ep(const StoreMasked &e) { return ConvStoreMasked{e.dx, e.cs, e.co, e.act, e.acs, e.aco, nullptr}; }
+inline const ConvStoreActPool &conv_ep(const ConvStoreActPool &e) { return e; }
+inline const ConvStoreHead &conv_ep(const ConvStoreHead &e) { return e; }
 
-// tile rows of the persistent form: 8 (two row blocks per wavefront, a weight operand serves two
-// MFMAs) where the patch and weights of a workgroup fit in about 56 KB of LDS, else 4
+// The persistent form where the weights of TN outputs fit in LDS (TN x 9 x CIN <= 20480 values), with
+// 8-row tiles (two row blocks per wavefront, a weight operand serves two MFMAs) where the patch and the
+// weights of a workgroup fit in about 56 KB, else 4-row tiles; every other layer takes the general form.
+template <int CIN, int TN>
+constexpr bool use_persist()
+{
+    return TN * 9 * CIN <= 20480;
+}
 template <int CIN, int TN>
 constexpr int persist_cth()
 {
@@ -561,11 +703,29 @@ constexpr int persist_cth()
     return (TN <= 64 && lds8 <= 57344) ? 8 : 4;
 }
 
+// row blocks per wavefront and wavefront columns of the kernel run_conv3x3 launches for CIN, TN
+template <int CIN, int TN>
+constexpr int conv_bm()
+{
+    if constexpr (use_persist<CIN, TN>()) return ConvGrid<TN, persist_cth<CIN, TN>()>::BM;
+    else return ConvGrid<TN, CONV_GEN_CTH>::BM;
+}
+template <int CIN, int TN>
+constexpr int conv_wn()
+{
+    if constexpr (use_persist<CIN, TN>()) return ConvGrid<TN, persist_cth<CIN, TN>()>::WN;
+    else return ConvGrid<TN, CONV_GEN_CTH>::WN;
+}
+
+// hipErrorInvalidValue: the fused pool or head does not fit the launched kernel's wave layout
+// (callers check conv_bm / conv_wn and the N tile first)
 template <int CIN, int TN, class EP>
 inline hipError_t run_conv3x3(const Act &x, const WeightB &w, const EP &e, int N, int cu_count, hipStream_t st)
 {
-    using CE = decltype(conv_ep(e));
-    if constexpr (TN * 9 * CIN <= 20480) {
+    using CE = std::decay_t<decltype(conv_ep(e))>;
+    if constexpr ((CE::POOL && conv_bm<CIN, TN>() != 2) || (CE::HEAD && conv_wn<CIN, TN>() != 1)) {
+        return hipErrorInvalidValue;
+    } else if constexpr (use_persist<CIN, TN>()) {
         constexpr int CTH = persist_cth<CIN, TN>();
         const int tiles = x.B * ((x.H + CTH - 1) / CTH) * ((x.W + CT_W - 1) / CT_W);
         int per_cu = 0;
@@ -576,7 +736,8 @@ inline hipError_t run_conv3x3(const Act &x, const WeightB &w, const EP &e, int N
         conv3x3_persist_kernel<CIN, TN, CTH, CE><<<dim3(wgs, (N + TN - 1) / TN), 256, 0, st>>>(x, w, conv_ep(e), N,
                                                                                             tiles);
     } else {
-        const int tiles = x.B * ((x.H + 3) / 4) * ((x.W + CT_W - 1) / CT_W);
+        constexpr int CTH = CONV_GEN_CTH;
+        const int tiles = x.B * ((x.H + CTH - 1) / CTH) * ((x.W + CT_W - 1) / CT_W);
         conv3x3_kernel<CIN, TN, CE><<<dim3(tiles, (N + TN - 1) / TN), 256, 0, st>>>(x, w, conv_ep(e), N);
     }
     return hipGetLastError();

@@ -186,10 +186,7 @@ def _persist_cth(cin, tn):
 
 
 def _conv_tn(cin, n):
-    tn = 128 if n >= 128 else (64 if n >= 64 else 32)
-    while tn > 32 and tn * 9 * cin > 20480 and 32 * 9 * cin <= 20480:
-        tn //= 2
-    return tn
+    return 128 if n >= 128 else (64 if n >= 64 else 32)
 
 
 @pytest.mark.parametrize("cin,H,W,n", [(8, 16, 16, 32), (16, 9, 40, 64), (32, 12, 33, 32), (64, 8, 64, 128),
@@ -198,8 +195,8 @@ def _conv_tn(cin, n):
 def test_conv3x3_patch_replay(cin, H, W, n):
     """The direct convolution's LDS staging and MFMA operand reads, replayed index by index for the form
     the library picks (persistent, CC = CIN, 8- or 4-row tiles, when TN x 9 x CIN <= 20480; else general
-    with 4-row tiles and chunks of CC =
-    min(CIN, 16 / 32 / 64 for TN = 128 / 64 / 32) channels).  Patch slot p CPP + c8 (CPP = CPX | 1) holds
+    with 8-row tiles and chunks of CC =
+    min(CIN, 16 / 32 for TN = 128 / less) channels).  Patch slot p CPP + c8 (CPP = CPX | 1) holds
     the input vector of pixel p, channels ch CC + 8 c8 (zeros outside the image); weight slot n WS + tap
     CPX + c8 holds W[n][tap CIN + ch CC + 8 c8].  Every lane of every (chunk, K step, row block, column
     block) reads, at its per-lane base plus the step's offset, the im2col value X[pixel + (ty-1, tx-1)][c]
@@ -211,14 +208,14 @@ def test_conv3x3_patch_replay(cin, H, W, n):
     Wt = rng.integers(1, 1000, (N, 9 * cin))
     tn = _conv_tn(cin, N)
     persist = tn * 9 * cin <= 20480
-    CT_H = _persist_cth(cin, tn) if persist else 4
+    CT_H = _persist_cth(cin, tn) if persist else 8
     CT_PIX = (CT_H + 2) * CT_PW
-    cap = 16 if tn >= 128 else (32 if tn >= 64 else 64)
+    cap = 16 if tn >= 128 else 32
     CC = cin if persist else min(cin, cap)
     CPX, NCH = CC // 8, cin // CC
     CPP, WS = CPX | 1, _conv_ws(CPX)
     NSTEP = (9 * CC + 15) // 16
-    wm_n = 2 if tn >= 128 else 4
+    wm_n = 4 if (CT_H >= 8 or tn < 128) else 2
     wn_n = 4 // wm_n
     BM, BN, WTN = CT_H // wm_n, (tn // wn_n) // 32, tn // wn_n
     tiles_x, tiles_y = -(-W // CT_W), -(-H // CT_H)
@@ -283,6 +280,30 @@ def test_conv3x3_patch_replay(cin, H, W, n):
                 assert seen_k == sorted(seen_k)
 
 
+def _permlane32_swap(x, y):
+    """v_permlane32_swap: lanes 32..63 of the first operand trade places with lanes 0..31 of the second."""
+    return x[:32] + y[:32], x[32:] + y[32:]
+
+
+def _gather8(a, b):
+    """The epilogues' half-wave exchange of (a, b) per lane: the first four and last four channels a lane
+    stores (16 bytes), here as the first channel of each four-channel piece."""
+    x, y = _permlane32_swap(a, b)
+    return x, y
+
+
+def test_gather8_lane_map():
+    """After the exchange lane half h of pixel col holds channels 8 (g + h) .. 8 (g + h) + 7 in order, for
+    every lane, given a = channels 8 g + 4 half .. + 3 and b = 8 (g + 1) + 4 half .. + 3."""
+    for g in (0, 2):
+        a = [(ln & 31, 8 * g + 4 * (ln >> 5)) for ln in range(64)]
+        b = [(ln & 31, 8 * (g + 1) + 4 * (ln >> 5)) for ln in range(64)]
+        lo, hi = _gather8(a, b)
+        for ln in range(64):
+            col, half = ln & 31, ln >> 5
+            assert lo[ln] == (col, 8 * (g + half)) and hi[ln] == (col, 8 * (g + half) + 4)
+
+
 def _up_ws(cpx):
     s = cpx
     while s % 8 != 1:
@@ -290,7 +311,7 @@ def _up_ws(cpx):
     return s
 
 
-@pytest.mark.parametrize("cin,cout,H,W", [(64, 32, 8, 40), (128, 64, 5, 32), (32, 16, 4, 9), (16, 8, 6, 70)])
+@pytest.mark.parametrize("cin,cout,H,W", [(64, 32, 8, 40), (128, 64, 5, 32), (32, 16, 4, 9), (16, 8, 6, 70), (128, 128, 3, 36)])
 def test_up2x2_replay(cin, cout, H, W):
     """The up-sampling kernel's staging and reads, replayed: tile slot p CPP + c8 holds X[pixel p][8 c8..],
     weight slot n WS + c8 holds U[n][8 c8..]; every lane of every (K step, row block, column block) reads
@@ -345,7 +366,9 @@ def test_up2x2_replay(cin, cout, H, W):
                                 gw.setdefault(lane // 8, set()).add((lw + 2 * S) % 8)
                             for g in list(ga.values()) + list(gw.values()):
                                 assert len(g) == 8
-            # epilogue: register 4 g + q of block (j, i) = channel 8 g + 4 half + q of the block, pixel col
+            # epilogue: register 4 g + q of block (j, i) = channel 8 g + 4 half + q of the block, pixel col;
+            # groups g, g + 1 exchanged between the half-waves, after which lane half h stores the eight
+            # channels 8 (g + h) .. + 7 of the block
             for wave in range(4):
                 wm, wn = divmod(wave, wn_n)
                 for i in range(BM):
@@ -355,12 +378,17 @@ def test_up2x2_replay(cin, cout, H, W):
                             yy, xx = y0 + wm * BM + i, x0 + col
                             if yy >= H or xx >= W:
                                 continue
-                            for g in range(4):
-                                n = n0 + wn * WTN + j * 32 + 8 * g + 4 * half
+                            for g in (0, 2):
+                                a = [8 * g + 4 * (ln >> 5) for ln in range(64)]          # first channel held
+                                bb = [8 * (g + 1) + 4 * (ln >> 5) for ln in range(64)]
+                                lo, hi = _gather8(a, bb)
+                                assert (lo[lane], hi[lane]) == (8 * (g + half), 8 * (g + half) + 4)
+                                n = n0 + wn * WTN + j * 32 + 8 * g + 8 * half
                                 if n >= N:
                                     continue
                                 d, co = n >> lgc, n & (cout - 1)
-                                hit[b, 2 * yy + (d >> 1), 2 * xx + (d & 1), co:co + 4] += 1
+                                assert (n + 7) >> lgc == d   # eight channels of one sub-pixel (cout >= 8)
+                                hit[b, 2 * yy + (d >> 1), 2 * xx + (d & 1), co:co + 8] += 1
     assert (hit == 1).all()
 
 
