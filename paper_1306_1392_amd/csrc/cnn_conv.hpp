@@ -304,34 +304,79 @@ __device__ __forceinline__ void pconv_store(const Act &x, const ConvTile &c, int
     }
 }
 
-// Persistent form for layers whose weights for TN outputs fit in LDS (TN x 9 x CIN <= 20480 values):
-// the workgroup stages its outputs' weights (and biases) once and then walks output tiles
-// blockIdx.x, blockIdx.x + gridDim.x, ...; the patches of the next two tiles are in flight in
-// registers while the current one is summed.  One chunk, K steps in the GEMM's order k = tap CIN + c.
+// One MFMA K step S of the persistent form, whose weight operands wr[S][j] are held in registers: only
+// the patch operands come from LDS (one read per MFMA when BM = 1).
+template <int CIN, int TN, int CTH, int NSTEP, int S>
+__device__ __forceinline__ void rconv_step(const uint4 *sP, const int *la, int half,
+                                           const uint4 (&wr)[NSTEP][ConvGrid<TN, CTH>::BN],
+                                           f32x16 (&acc)[ConvGrid<TN, CTH>::BN][ConvGrid<TN, CTH>::BM])
+{
+    constexpr int CPX = CIN / 8, CPP = CPX | 1;
+    constexpr int BM = ConvGrid<TN, CTH>::BM, BN = ConvGrid<TN, CTH>::BN;
+    int oa;
+    bool live = true;
+    if constexpr (CIN >= 16) {    // both halves of the step read one tap
+        constexpr int tap = (16 * S) / CIN, c8 = ((16 * S) % CIN) / 8;
+        oa = ((tap / 3) * CT_PW + tap % 3) * CPP + c8;
+    } else {                      // CIN == 8: the halves read taps 2S and 2S + 1
+        constexpr int t0 = 2 * S, t1 = 2 * S + 1;
+        oa = half ? ((t1 / 3) * CT_PW + t1 % 3) : ((t0 / 3) * CT_PW + t0 % 3);
+        live = !(half && t1 >= 9);
+    }
+    bf16x8 pf[BM];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) {
+        const uint4 v = live ? sP[la[i] + oa] : zero8();
+        pf[i] = *(const bf16x8 *)&v;
+    }
+#pragma unroll
+    for (int j = 0; j < BN; ++j) {
+        const bf16x8 wf = *(const bf16x8 *)&wr[S][j];
+#pragma unroll
+        for (int i = 0; i < BM; ++i) acc[j][i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf, pf[i], acc[j][i], 0, 0, 0);
+    }
+}
+
+template <int CIN, int TN, int CTH, int NSTEP, int... S>
+__device__ __forceinline__ void rconv_steps(std::integer_sequence<int, S...>, const uint4 *sP, const int *la, int half,
+                                            const uint4 (&wr)[NSTEP][ConvGrid<TN, CTH>::BN],
+                                            f32x16 (&acc)[ConvGrid<TN, CTH>::BN][ConvGrid<TN, CTH>::BM])
+{
+    (rconv_step<CIN, TN, CTH, NSTEP, S>(sP, la, half, wr, acc), ...);
+}
+
+// Persistent form for layers whose weights for TN outputs fit in registers (TN x 9 x CIN <= 20480
+// values: at most 144 VGPRs per lane): every lane loads the weight operands of its K steps and column
+// blocks once, straight from memory, and the workgroup then walks output tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ...; the patches of the next two tiles are in flight in registers while the
+// current one is summed from LDS.  One chunk, K steps in the GEMM's order k = tap CIN + c.
 template <int CIN, int TN, int CTH, class EP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
 {
     using G_ = ConvGrid<TN, CTH>;
-    constexpr int CPX = CIN / 8, CPP = CPX | 1, WS = conv_ws(CPX);
+    constexpr int CPX = CIN / 8, CPP = CPX | 1;
     constexpr int NPS = G_::PIX * CPX;            // patch vectors
     constexpr int NPV = (NPS + 255) / 256;        // patch vectors per thread
     constexpr int NSTEP = (9 * CIN + 15) / 16;
     constexpr int WNW = G_::WN, BM = G_::BM, BN = G_::BN, WTN = G_::WTN;
-    static_assert(TN * 9 * CIN <= 20480, "weights of the workgroup's outputs fit in LDS");
+    static_assert(TN * 9 * CIN <= 20480, "weights of the workgroup's outputs fit in registers");
     __shared__ uint4 sP[G_::PIX * CPP];
-    __shared__ uint4 sW[TN * WS];
     __shared__ float4 sBias[TN / 4];
     __shared__ float4 sHead[EP::HEAD ? TN / 4 : 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WNW, wn = wave % WNW;
     const int col = lane & 31, half = lane >> 5;
     const int n0 = blockIdx.y * TN;
-    for (int i = threadIdx.x; i < TN * 9 * CPX; i += 256) {
-        const int n = i / (9 * CPX), rr = i - n * (9 * CPX);
-        const int tap = rr / CPX, c8 = rr - tap * CPX;
-        sW[n * WS + tap * CPX + c8] = n0 + n < N ? ld8(B.w + (int64_t)(n0 + n) * B.K + tap * CIN + 8 * c8) : zero8();
-    }
+    // A operand of step S, column block j: output n0 + wn WTN + 32 j + col, K values 16 S + 8 half .. + 7
+    uint4 wr[NSTEP][BN];
+#pragma unroll
+    for (int S = 0; S < NSTEP; ++S)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+            const int n = n0 + wn * WTN + 32 * j + col, k = 16 * S + 8 * half;
+            wr[S][j] = n < N && k < 9 * CIN ? ld8(B.w + (int64_t)n * B.K + k) : zero8();
+        }
     if (EP::BIAS && threadIdx.x < TN) ((float *)sBias)[threadIdx.x] = n0 + (int)threadIdx.x < N ? E.bias[n0 + threadIdx.x] : 0.0f;
     if constexpr (EP::HEAD)
         if (threadIdx.x < TN) ((float *)sHead)[threadIdx.x] = n0 + (int)threadIdx.x < N ? E.wh[n0 + threadIdx.x] : 0.0f;
@@ -359,14 +404,12 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
                         : zero8();
         }
     };
-    int la[BM], lw[BN];
+    int la[BM];
 #pragma unroll
     for (int i = 0; i < BM; ++i) la[i] = ((wm * BM + i) * CT_PW + col) * CPP + (CIN >= 16 ? half : 0);
-#pragma unroll
-    for (int j = 0; j < BN; ++j) lw[j] = (wn * WTN + j * 32 + col) * WS + (CIN >= 16 ? half : 0);
 
     auto tile = [&](uint4 (&pv)[NPV], int t) {
-        __syncthreads();   // the previous tile's reads of the patch are done (the weights are visible)
+        __syncthreads();   // the previous tile's reads of the patch are done (the biases are visible)
 #pragma unroll
         for (int v = 0; v < NPV; ++v)
             if (spos[v] >= 0) sP[sdst[v]] = pv[v];
@@ -379,7 +422,7 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
             for (int i = 0; i < BM; ++i)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) acc[j][i][q] = 0.0f;
-        pconv_steps<CIN, TN, CTH>(std::make_integer_sequence<int, NSTEP>{}, sP, sW, la, lw, half, acc);
+        rconv_steps<CIN, TN, CTH, NSTEP>(std::make_integer_sequence<int, NSTEP>{}, sP, la, half, wr, acc);
         pconv_store<TN, CTH>(x, conv_tile<CTH>(x, t), n0, N, wm, wn, col, half, E, sBias, sHead, acc);
     };
     const int G = gridDim.x;
@@ -687,20 +730,22 @@ inline ConvStoreMasked conv_ep(const StoreMasked &e) { return ConvStoreMasked{e.
 inline const ConvStoreActPool &conv_ep(const ConvStoreActPool &e) { return e; }
 inline const ConvStoreHead &conv_ep(const ConvStoreHead &e) { return e; }
 
-// The persistent form where the weights of TN outputs fit in LDS (TN x 9 x CIN <= 20480 values), with
-// 8-row tiles (two row blocks per wavefront, a weight operand serves two MFMAs) where the patch and the
-// weights of a workgroup fit in about 56 KB, else 4-row tiles; every other layer takes the general form.
+// The persistent form where the weights of TN outputs fit in registers (TN x 9 x CIN <= 20480 values),
+// with 8-row tiles (two row blocks per wavefront) where the registers allow, else 4-row tiles; every
+// other layer takes the general form.
 template <int CIN, int TN>
 constexpr bool use_persist()
 {
     return TN * 9 * CIN <= 20480;
 }
+// 8-row tiles where the registers of the 8-row form (weights, accumulators, two patches in flight, about
+// 24 more) stay within 240 per lane, else 4-row tiles
 template <int CIN, int TN>
 constexpr int persist_cth()
 {
-    constexpr int cpx = CIN / 8;
-    constexpr int lds8 = (10 * CT_PW * (cpx | 1) + TN * conv_ws(cpx)) * 16;
-    return (TN <= 64 && lds8 <= 57344) ? 8 : 4;
+    constexpr int nstep = (9 * CIN + 15) / 16, bm = ConvGrid<TN, 8>::BM, bn = ConvGrid<TN, 8>::BN;
+    constexpr int npv = (ConvGrid<TN, 8>::PIX * (CIN / 8) + 255) / 256;
+    return 4 * nstep * bn + 16 * bm * bn + 8 * npv + 24 <= 240 ? 8 : 4;
 }
 
 // row blocks per wavefront and wavefront columns of the kernel run_conv3x3 launches for CIN, TN

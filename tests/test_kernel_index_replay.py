@@ -180,9 +180,13 @@ def _tap_row(tap):
 
 
 def _persist_cth(cin, tn):
-    cpx = cin // 8
-    lds8 = (10 * CT_PW * (cpx | 1) + tn * _conv_ws(cpx)) * 16
-    return 8 if (tn <= 64 and lds8 <= 57344) else 4
+    """8-row tiles where the 8-row form's registers (weights, accumulators, two patches in flight, 24 more)
+    stay within 240 per lane."""
+    nstep = (9 * cin + 15) // 16
+    wm = 4                                   # 8-row tiles: four wavefronts of two rows
+    bm, bn = 8 // wm, tn // (4 // wm) // 32
+    npv = (10 * CT_PW * (cin // 8) + 255) // 256
+    return 8 if 4 * nstep * bn + 16 * bm * bn + 8 * npv + 24 <= 240 else 4
 
 
 def _conv_tn(cin, n):
@@ -200,7 +204,8 @@ def test_conv3x3_patch_replay(cin, H, W, n):
     the input vector of pixel p, channels ch CC + 8 c8 (zeros outside the image); weight slot n WS + tap
     CPX + c8 holds W[n][tap CIN + ch CC + 8 c8].  Every lane of every (chunk, K step, row block, column
     block) reads, at its per-lane base plus the step's offset, the im2col value X[pixel + (ty-1, tx-1)][c]
-    of its pixel and the weight of its output channel at one K index; every K index is read once, in the
+    of its pixel and the weight of its output channel at one K index (the persistent form holds that
+    weight in its register operand of the step); every K index is read once, in the
     global order with one chunk; the 8 lanes of a pass hit 8 distinct four-bank groups."""
     rng = np.random.default_rng(cin + H)
     B, N = 2, n
@@ -270,7 +275,14 @@ def test_conv3x3_patch_replay(cin, H, W, n):
                                     assert np.array_equal(sP[la + oa], ref), (t, ch, S, lane)
                                     nn = wn * WTN + j * 32 + col
                                     wref = Wt[n0 + nn, k:k + 8] if n0 + nn < N else np.zeros(8)
-                                    assert np.array_equal(sW[lw + ow], wref), (t, ch, S, lane)
+                                    if persist:
+                                        # register operand wr[S][j]: W[n][16 S + 8 half ..], zero past 9 CIN
+                                        kr = 16 * S + 8 * half
+                                        wreg = Wt[n0 + nn, kr:kr + 8] if (n0 + nn < N and kr < 9 * cin) \
+                                            else np.zeros(8)
+                                        assert np.array_equal(wreg, wref), (t, S, lane)
+                                    else:
+                                        assert np.array_equal(sW[lw + ow], wref), (t, ch, S, lane)
                                     ga.setdefault(lane // 8, set()).add((la + oa) % 8)
                                     gw.setdefault(lane // 8, set()).add((lw + ow) % 8)
                                 for g in list(ga.values()) + list(gw.values()):
