@@ -553,6 +553,106 @@ __device__ __forceinline__ void fp_staged_body(const Tables &T, const SliceDev &
     }
 }
 
+// Groups of one, two or four projections: 4 / P wavefronts per projection, wavefront w serving projection
+// w / (4 / P) on lines w % (4 / P), + 4 / P, ... of every block (16, 8 or 4 lines).  The crossing is
+// anchored in FP64 once per (lane, block) for the wavefront's one projection, so a group of four pays a
+// quarter of the anchors of fp_staged_body; partial sums of a projection's wavefronts are added in a fixed
+// order through LDS.  Staging, segment and line arithmetic as in fp_staged_body.
+template <int MODE, int NC, bool UNIT, int P>
+__device__ __forceinline__ void fp_staged_body_wp(const Tables &T, const SliceDev &sd, const GeoDev &g,
+                                                  const StagedProj *pr, bool rows, int j, const float *img,
+                                                  float *out, float alpha, const CpDual &cp, int slice,
+                                                  float (*stage)[FP_RB * FpStaged<NC>::LD], float (*part)[3][64])
+{
+    using F = FpStaged<NC>;
+    static_assert(P == 1 || P == 2 || P == 4, "whole wavefronts per projection");
+    constexpr int WPP = 4 / P, LPW = FP_RB / WPP;   // wavefronts per projection, lines per wavefront and block
+    const int nb = g.nb, nx = g.nx, ny = g.ny;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int pw = wv / WPP, ph = wv % WPP;          // this wavefront's projection and line phase
+    const int n_lines = rows ? ny : nx, n_pos = rows ? nx : ny;
+    const float *im = img + sd.img_off;
+    const int sr = rows ? tid >> 4 : tid & 15;
+    const int sp = rows ? tid & 15 : tid >> 4;
+    const int step_line = rows ? nx : 1, step_pos = rows ? 1 : nx;
+    const int n_blk = (n_lines + FP_RB - 1) / FP_RB;
+    StagedProj q = pr[0];
+#pragma unroll
+    for (int m = 1; m < P; ++m)
+        if (pw == m) q = pr[m];   // wave-uniform
+
+    float v[F::PER];
+    auto load = [&](int b, int &seg0) {
+        const int l0 = b * FP_RB;
+        double lo = fma((double)l0, pr[0].slope, pr[0].blk_lo);
+#pragma unroll
+        for (int m = 1; m < P; ++m) lo = fmin(lo, fma((double)l0, pr[m].slope, pr[m].blk_lo));
+        seg0 = (int)floor(lo) - 2;
+        const int line = l0 + sr;
+        if (line < n_lines && seg0 >= 0 && seg0 + F::SEG <= n_pos) {
+            const float *src = im + (line * step_line + (seg0 + sp) * step_pos);
+            const int d16 = 16 * step_pos;
+#pragma unroll
+            for (int i = 0; i < F::PER; ++i) v[i] = src[i * d16];
+        } else {
+#pragma unroll
+            for (int i = 0; i < F::PER; ++i) {
+                const int pos = seg0 + sp + 16 * i;
+                v[i] = (line < n_lines && (unsigned)pos < (unsigned)n_pos) ? im[line * step_line + pos * step_pos] : 0.0f;
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < F::PER; ++i) stage[buf][sr * F::LD + sp + 16 * i] = v[i];
+    };
+
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    int seg_cur, seg_next = 0;
+    load(0, seg_cur);
+    store(0);
+    __syncthreads();
+    for (int b = 0; b < n_blk; ++b) {
+        const bool more = b + 1 < n_blk;
+        if (more) load(b + 1, seg_next);
+        const int l0 = b * FP_RB;
+        const double ub = fma((double)l0, q.slope, q.u_first);
+        const double ubase = floor(ub);
+        const float remv = (float)(ub - ubase - q.rho);            // u - 1/|a| at the block's first line
+        const float *base = stage[b & 1] + ((int)ubase - seg_cur) + ph * F::LD;
+        if (l0 + FP_RB <= n_lines) {
+#pragma unroll
+            for (int k = 0; k < LPW; ++k)
+                acc[k & 3] = staged_line<NC, UNIT>(base + k * WPP * F::LD, fmaf((float)(ph + WPP * k), q.slopef, remv), q,
+                                                   acc[k & 3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < LPW; ++k) {
+                if (l0 + ph + WPP * k >= n_lines) break;              // uniform
+                acc[k & 3] = staged_line<NC, UNIT>(base + k * WPP * F::LD, fmaf((float)(ph + WPP * k), q.slopef, remv), q,
+                                                   acc[k & 3]);
+            }
+        }
+        if (more) {
+            store((b + 1) & 1);
+            seg_cur = seg_next;
+        }
+        __syncthreads();
+    }
+    float tot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    if constexpr (WPP > 1) {
+        if (ph > 0) part[pw][ph - 1][lane] = tot;
+        __syncthreads();
+        if (ph > 0) return;
+#pragma unroll
+        for (int m = 1; m < WPP; ++m) tot += part[pw][m - 1][lane];
+    }
+    if (j >= nb) return;
+    const int64_t o = sd.sino_off + (int64_t)q.k * nb + j;
+    fp_store<MODE>(cp, out, o, alpha * (float)(g.s * g.s) * tot, (int64_t)slice * nb + j);
+}
+
 // grid: (bin chunks, staged groups of the geometry with the most, slices); MODE 3: one projection k0.
 // GMAX: the largest group the plan formed, 2 or 4 (the 4-wide build needs more VGPRs, so plans with
 // groups of at most two keep the occupancy of the 2-wide one).
@@ -587,13 +687,13 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
     for (int m = 1; m < FP_SGRP; ++m)
         if (m < n) pr[m] = staged_proj(T, g, kk[m], j, j0, rows_m);   // same walking axis (the plan groups only such)
     if (GMAX > 2 && n == 4) {   // uniform over the workgroup
-        fp_staged_body<MODE, NC, UNIT, 4>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
+        fp_staged_body_wp<MODE, NC, UNIT, 4>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
     } else if (GMAX > 2 && n == 3) {
         fp_staged_body<MODE, NC, UNIT, 3>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
     } else if (n == 2) {
-        fp_staged_body<MODE, NC, UNIT, 2>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
+        fp_staged_body_wp<MODE, NC, UNIT, 2>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
     } else {
-        fp_staged_body<MODE, NC, UNIT, 1>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
+        fp_staged_body_wp<MODE, NC, UNIT, 1>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
     }
 }
 

@@ -128,6 +128,24 @@ def test_fp_staging_bounds(cap):
     assert paired > 100   # most cases group most of their projections
 
 
+@pytest.mark.parametrize("P", [1, 2, 4])
+def test_fp_wave_line_map(P):
+    """Groups of one, two or four projections: wavefront w serves projection w / (4 / P) on lines
+    w % (4 / P) + (4 / P) k of a block; every (projection, line) of a block is summed by exactly one
+    wavefront, with accumulator k % 4, and a projection's partial sums meet in phase order."""
+    wpp = 4 // P
+    seen = {}
+    for w in range(4):
+        pw, ph = w // wpp, w % wpp
+        for k in range(RB // wpp):
+            line = ph + wpp * k
+            assert 0 <= line < RB
+            key = (pw, line)
+            assert key not in seen
+            seen[key] = (w, k & 3)
+    assert sorted(seen) == [(p, r) for p in range(P) for r in range(RB)]
+
+
 def test_fp_three_candidate_closed_form_weights():
     """The staged projector's weights for three candidates and 2/3 <= |a| <= 1, from f = fract(u - 1/|a|):
     w0 = |a| (1 - f), w1 = 1 - | |a| (2 - f) - 1 |, w2 = max(0, 2 - 3|a| + |a| f) equal the hat
