@@ -526,11 +526,11 @@ bool direct_kernel_layout(int cin, int n, int &bm, int &wn, int &tn)
 }
 
 // the 2x2 max pool fits the epilogue of the layer's direct kernel (a wavefront holds both rows of
-// its windows)
+// its windows: an even number of consecutive tile rows)
 bool pool_fusable(const Conv &L)
 {
     int bm = 0, wn = 0, tn = 0;
-    return direct_kernel_layout(L.cin, L.cout, bm, wn, tn) && bm == 2;
+    return direct_kernel_layout(L.cin, L.cout, bm, wn, tn) && bm % 2 == 0;
 }
 // the head fits the epilogue (one workgroup column holds every output channel in one wavefront)
 bool head_fusable(const Conv &L)

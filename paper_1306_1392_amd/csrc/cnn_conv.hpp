@@ -211,16 +211,18 @@ __device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u 
 // POOL: the two row blocks of a wavefront are the two rows of its pooling windows (the tile and the image
 // start on even rows, H and W are even) and lanes col, col ^ 1 the two columns.  HEAD: the wavefront
 // holds every channel of its pixels (one workgroup column, WN = 1), half of them in each half-wave.
-template <int TN, int CTH, class EP>
+template <class G_, class EP>
 __device__ __forceinline__ void pconv_store(const Act &x, const ConvTile &c, int n0, int N, int wm, int wn, int col,
                                             int half, const EP &E, const float4 *sBias, const float4 *sHead,
-                                            f32x16 (&acc)[ConvGrid<TN, CTH>::BN][ConvGrid<TN, CTH>::BM])
+                                            f32x16 (&acc)[G_::BN][G_::BM])
 {
-    constexpr int BM = ConvGrid<TN, CTH>::BM, BN = ConvGrid<TN, CTH>::BN, WTN = ConvGrid<TN, CTH>::WTN;
+    constexpr int BM = G_::BM, BN = G_::BN, WTN = G_::WTN;
     const int xx = c.x0 + col;
     if constexpr (EP::POOL) {
-        static_assert(BM == 2, "both rows of every pooling window in one wavefront");
-        const int yy = c.y0 + 2 * wm;
+        static_assert(BM % 2 == 0, "both rows of every pooling window in one wavefront");
+#pragma unroll
+        for (int ip = 0; ip < BM; ip += 2) {
+        const int yy = c.y0 + wm * BM + ip;
         const bool in = yy < x.H && xx < x.W;   // alike for the lanes of a window (even W) and both half-waves
         const int m = (c.b * x.H + yy) * x.W + xx;
         const int64_t pm = ((int64_t)(c.b * (x.H >> 1) + (yy >> 1)) * (x.W >> 1) + (xx >> 1)) * E.pcs;
@@ -235,8 +237,8 @@ __device__ __forceinline__ void pconv_store(const Act &x, const ConvTile &c, int
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         const int nl = h ? nl1 : nl0;
-                        const float v[4] = {acc[j][i][4 * (g + h)], acc[j][i][4 * (g + h) + 1],
-                                            acc[j][i][4 * (g + h) + 2], acc[j][i][4 * (g + h) + 3]};
+                        const float v[4] = {acc[j][ip + i][4 * (g + h)], acc[j][ip + i][4 * (g + h) + 1],
+                                            acc[j][ip + i][4 * (g + h) + 2], acc[j][ip + i][4 * (g + h) + 3]};
                         r[i][h] = E.pack4(m + i * x.W, n0 + nl, v, sBias[nl >> 2], in && n0 + nl < N);
                     }
                 uint2 pool[2];
@@ -256,6 +258,7 @@ __device__ __forceinline__ void pconv_store(const Act &x, const ConvTile &c, int
                     if (!(col & 1)) *(uint4 *)(E.pool + pm + nc) = op;
                 }
             }
+        }
         return;
     }
 #pragma unroll
@@ -294,7 +297,7 @@ __device__ __forceinline__ void pconv_store(const Act &x, const ConvTile &c, int
                 }
             }
         if constexpr (EP::HEAD) {
-            static_assert(ConvGrid<TN, CTH>::WN == 1, "every channel of a pixel in one wavefront");
+            static_assert(G_::WN == 1, "every channel of a pixel in one wavefront");
             s += __shfl_xor(s, 32, 64);   // the other half-wave's channels (a + b = b + a: both halves agree)
             if (in && !half) {
                 const float r = E.xin[m] * E.scale + (E.bh[0] + s);
@@ -423,7 +426,7 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) acc[j][i][q] = 0.0f;
         rconv_steps<CIN, TN, CTH, NSTEP>(std::make_integer_sequence<int, NSTEP>{}, sP, la, half, wr, acc);
-        pconv_store<TN, CTH>(x, conv_tile<CTH>(x, t), n0, N, wm, wn, col, half, E, sBias, sHead, acc);
+        pconv_store<G_>(x, conv_tile<CTH>(x, t), n0, N, wm, wn, col, half, E, sBias, sHead, acc);
     };
     const int G = gridDim.x;
     load(pa, blockIdx.x);
@@ -432,6 +435,49 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
         tile(pa, t);
         if (t + G < tiles) tile(pb, t + G);
     }
+}
+
+// wave layout of the general form's CTH x 32-pixel, TN-channel tile: each wavefront owns one column
+// block of 32 output channels (WN = min(4, TN / 32)) and CTH / WM consecutive tile rows (BM)
+template <int TN, int CTH>
+struct GenGrid {
+    static constexpr int WN = TN >= 128 ? 4 : TN / 32, WM = 4 / WN;
+    static constexpr int BM = CTH / WM, BN = 1, WTN = 32;
+    static constexpr int PIX = (CTH + 2) * CT_PW;
+    static_assert(TN <= 128 && TN % 32 == 0 && CTH % WM == 0, "whole column blocks and tile rows per wavefront");
+};
+
+// The K steps of one staged chunk (CC >= 16 channels) in the general form, ordered so that a patch row
+// read from LDS serves every tap row that needs it: per 16-channel slice s and tap column tx the
+// wavefront reads patch rows R = r0 .. r0 + BM + 1 (BM + 2 reads) and the weights of taps (ty, tx),
+// ty = 0, 1, 2 (3 reads), then output row r0 + i takes W[ty] x P[i + ty] (3 BM MFMAs).  lp: this lane's
+// patch slot of row r0, column col (plus its half of the slice); lw: its weight slot.
+template <int CC, int BM, int SL, int TX>
+__device__ __forceinline__ void gconv_taps(const uint4 *sP, const uint4 *sW, int lp, int lw, f32x16 (&acc)[1][BM])
+{
+    constexpr int CPX = CC / 8, CPP = CPX | 1;
+    bf16x8 pf[BM + 2], wf[3];
+#pragma unroll
+    for (int R = 0; R < BM + 2; ++R) {
+        const uint4 v = sP[lp + (R * CT_PW + TX) * CPP + 2 * SL];
+        pf[R] = *(const bf16x8 *)&v;
+    }
+#pragma unroll
+    for (int ty = 0; ty < 3; ++ty) {
+        const uint4 v = sW[lw + (3 * ty + TX) * CPX + 2 * SL];
+        wf[ty] = *(const bf16x8 *)&v;
+    }
+#pragma unroll
+    for (int ty = 0; ty < 3; ++ty)
+#pragma unroll
+        for (int i = 0; i < BM; ++i) acc[0][i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[ty], pf[i + ty], acc[0][i], 0, 0, 0);
+}
+
+template <int CC, int BM, int... Q>
+__device__ __forceinline__ void gconv_chunk(std::integer_sequence<int, Q...>, const uint4 *sP, const uint4 *sW, int lp,
+                                            int lw, f32x16 (&acc)[1][BM])
+{
+    (gconv_taps<CC, BM, Q / 3, Q % 3>(sP, sW, lp, lw, acc), ...);   // Q = 3 slice + tap column
 }
 
 // channels per chunk of the general form: the chunk's weights [TN][9][CC] take at most 36 KB, and patch
@@ -446,23 +492,22 @@ constexpr int conv_cc()
 // General form (the layers whose weights do not fit the persistent form): one 8 x 32-pixel output
 // tile per workgroup (a staged chunk of weights serves 256 pixels); per chunk of CC input channels the
 // tile's patch and the chunk's weights for the TN outputs are staged in LDS (the layouts of the
-// persistent form, for CC channels), the K steps of the chunk run from LDS, and the next chunk is
-// meanwhile loaded into registers.  Two barriers per chunk.  K order: chunk, tap, channel within the
-// chunk.
+// persistent form, for CC channels), the chunk's K steps run from LDS in the row-reusing order of
+// gconv_taps, and the next chunk is meanwhile loaded into registers.  Two barriers per chunk.
+// K order: chunk, 16-channel slice, tap column, tap row.
 constexpr int CONV_GEN_CTH = 8;
 template <int CIN, int TN, class EP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void conv3x3_kernel(Act x, WeightB B, EP E, int N)
 {
     constexpr int CTH = CONV_GEN_CTH;
-    using G_ = ConvGrid<TN, CTH>;
+    using G_ = GenGrid<TN, CTH>;
     constexpr int CC = conv_cc<CIN, TN>(), CPX = CC / 8, CPP = CPX | 1, WS = conv_ws(CPX);
     constexpr int NCH = CIN / CC;
     constexpr int NPS = G_::PIX * CPX, NWS = TN * 9 * CPX;  // patch and weight vectors per chunk
     constexpr int NV = (NPS + NWS + 255) / 256;             // per thread
-    constexpr int NSTEP = (9 * CC + 15) / 16;
     constexpr int WNW = G_::WN, BM = G_::BM, BN = G_::BN, WTN = G_::WTN;
-    static_assert(CIN % CC == 0 && CC % 8 == 0, "channels in chunks of 8");
+    static_assert(CIN % CC == 0 && CC % 16 == 0, "channels in chunks of 16-channel slices");
     __shared__ uint4 sP[G_::PIX * CPP];
     __shared__ uint4 sW[TN * WS];
     __shared__ float4 sBias[TN / 4];
@@ -511,11 +556,7 @@ void conv3x3_kernel(Act x, WeightB B, EP E, int N)
             else if (dst[v] >= 0) sW[dst[v]] = rv[v];
         }
     };
-    int la[BM], lw[BN];
-#pragma unroll
-    for (int i = 0; i < BM; ++i) la[i] = ((wm * BM + i) * CT_PW + col) * CPP + (CC >= 16 ? half : 0);
-#pragma unroll
-    for (int j = 0; j < BN; ++j) lw[j] = (wn * WTN + j * 32 + col) * WS + (CC >= 16 ? half : 0);
+    const int lp = (wm * BM * CT_PW + col) * CPP + half, lw = (wn * WTN + col) * WS + half;
 
     f32x16 acc[BN][BM];
 #pragma unroll
@@ -529,14 +570,14 @@ void conv3x3_kernel(Act x, WeightB B, EP E, int N)
     __syncthreads();
     for (int ch = 0; ch < NCH; ++ch) {
         if (ch + 1 < NCH) load(ch + 1);   // in flight while this chunk is summed
-        pconv_steps<CC, TN, CTH>(std::make_integer_sequence<int, NSTEP>{}, sP, sW, la, lw, half, acc);
+        gconv_chunk<CC, BM>(std::make_integer_sequence<int, 3 * (CC / 16)>{}, sP, sW, lp, lw, acc);
         if (ch + 1 < NCH) {
             __syncthreads();   // every wave is done with this chunk
             store();
             __syncthreads();
         }
     }
-    pconv_store<TN, CTH>(x, c, n0, N, wm, wn, col, half, E, sBias, sHead, acc);
+    pconv_store<G_>(x, c, n0, N, wm, wn, col, half, E, sBias, sHead, acc);
 }
 
 // ---- transposed 2x2 convolution, stride 2 (the U-Net's up-sampling) ------------------------------
@@ -753,13 +794,13 @@ template <int CIN, int TN>
 constexpr int conv_bm()
 {
     if constexpr (use_persist<CIN, TN>()) return ConvGrid<TN, persist_cth<CIN, TN>()>::BM;
-    else return ConvGrid<TN, CONV_GEN_CTH>::BM;
+    else return GenGrid<TN, CONV_GEN_CTH>::BM;
 }
 template <int CIN, int TN>
 constexpr int conv_wn()
 {
     if constexpr (use_persist<CIN, TN>()) return ConvGrid<TN, persist_cth<CIN, TN>()>::WN;
-    else return ConvGrid<TN, CONV_GEN_CTH>::WN;
+    else return GenGrid<TN, CONV_GEN_CTH>::WN;
 }
 
 // hipErrorInvalidValue: the fused pool or head does not fit the launched kernel's wave layout
@@ -768,7 +809,7 @@ template <int CIN, int TN, class EP>
 inline hipError_t run_conv3x3(const Act &x, const WeightB &w, const EP &e, int N, int cu_count, hipStream_t st)
 {
     using CE = std::decay_t<decltype(conv_ep(e))>;
-    if constexpr ((CE::POOL && conv_bm<CIN, TN>() != 2) || (CE::HEAD && conv_wn<CIN, TN>() != 1)) {
+    if constexpr ((CE::POOL && conv_bm<CIN, TN>() % 2 != 0) || (CE::HEAD && conv_wn<CIN, TN>() != 1)) {
         return hipErrorInvalidValue;
     } else if constexpr (use_persist<CIN, TN>()) {
         constexpr int CTH = persist_cth<CIN, TN>();

@@ -211,14 +211,52 @@ def _conv_tn(cin, n):
     return 128 if n >= 128 else (64 if n >= 64 else 32)
 
 
+def _replay_general_chunk(X, Wt, sP, sW, b, y0, x0, n0, ch, cin, CC, CPX, CPP, WS, tn, N, H, W, seen_k):
+    """One staged chunk of the general form: wavefront (wm, wn) owns output channels wn 32 .. + 31 and
+    tile rows wm BM .. + BM - 1; per 16-channel slice and tap column it reads patch rows R = 0 .. BM + 1
+    and the weights of the three tap rows, and output row i takes W[ty] x P[i + ty]."""
+    wn_n = 4 if tn >= 128 else tn // 32
+    wm_n = 4 // wn_n
+    BM = 8 // wm_n
+    for sl in range(CC // 16):
+        for tx in range(3):
+            for wave in range(4):
+                wm, wn = divmod(wave, wn_n)
+                gp, gw = {}, {}
+                for lane in range(64):
+                    col, half = lane & 31, lane >> 5
+                    lp = (wm * BM * CT_PW + col) * CPP + half
+                    lw = (wn * 32 + col) * WS + half
+                    P = [sP[lp + (R * CT_PW + tx) * CPP + 2 * sl] for R in range(BM + 2)]
+                    Wv = [sW[lw + (3 * ty + tx) * CPX + 2 * sl] for ty in range(3)]
+                    for R in range(BM + 2):
+                        gp.setdefault((R, lane // 8), set()).add((lp + (R * CT_PW + tx) * CPP + 2 * sl) % 8)
+                    for ty in range(3):
+                        gw.setdefault((ty, lane // 8), set()).add((lw + (3 * ty + tx) * CPX + 2 * sl) % 8)
+                    c0 = ch * CC + 16 * sl + 8 * half
+                    nn = wn * 32 + col
+                    for ty in range(3):
+                        k = (3 * ty + tx) * cin + c0
+                        wref = Wt[n0 + nn, k:k + 8] if n0 + nn < N else np.zeros(8)
+                        assert np.array_equal(Wv[ty], wref), (ch, sl, tx, ty, lane)
+                        if wave == 0 and col == 0:
+                            seen_k.append(k)
+                        for i in range(BM):
+                            yy, xx = y0 + wm * BM + i + ty - 1, x0 + col + tx - 1
+                            ref = X[b, yy, xx, c0:c0 + 8] if (0 <= yy < H and 0 <= xx < W) else np.zeros(8)
+                            assert np.array_equal(P[i + ty], ref), (ch, sl, tx, ty, i, lane)
+                for g in list(gp.values()) + list(gw.values()):
+                    assert len(g) == 8
+
+
 @pytest.mark.parametrize("cin,H,W,n", [(8, 16, 16, 32), (16, 9, 40, 64), (32, 12, 33, 32), (64, 8, 64, 128),
                                        (128, 5, 31, 64), (256, 6, 20, 128), (64, 7, 35, 32), (8, 4, 8, 128),
                                        (32, 5, 70, 64), (128, 4, 32, 128), (256, 3, 9, 32)])
 def test_conv3x3_patch_replay(cin, H, W, n):
     """The direct convolution's LDS staging and MFMA operand reads, replayed index by index for the form
     the library picks (persistent, CC = CIN, 8- or 4-row tiles, when TN x 9 x CIN <= 20480; else general
-    with 8-row tiles and chunks of CC =
-    min(CIN, 16 / 32 for TN = 128 / less) channels).  Patch slot p CPP + c8 (CPP = CPX | 1) holds
+    with 8-row tiles, chunks of CC = min(CIN, 16 / 32 for TN = 128 / less) channels and the row-reusing
+    read order of _replay_general_chunk).  Patch slot p CPP + c8 (CPP = CPX | 1) holds
     the input vector of pixel p, channels ch CC + 8 c8 (zeros outside the image); weight slot n WS + tap
     CPX + c8 holds W[n][tap CIN + ch CC + 8 c8].  Every lane of every (chunk, K step, row block, column
     block) reads, at its per-lane base plus the step's offset, the im2col value X[pixel + (ty-1, tx-1)][c]
@@ -238,7 +276,7 @@ def test_conv3x3_patch_replay(cin, H, W, n):
     CPX, NCH = CC // 8, cin // CC
     CPP, WS = CPX | 1, _conv_ws(CPX)
     NSTEP = (9 * CC + 15) // 16
-    wm_n = 4 if (CT_H >= 8 or tn < 128) else 2
+    wm_n = 4 if (CT_H >= 8 or tn < 128) else 2   # persistent form (the general form: _replay_general_chunk)
     wn_n = 4 // wm_n
     BM, BN, WTN = CT_H // wm_n, (tn // wn_n) // 32, tn // wn_n
     tiles_x, tiles_y = -(-W // CT_W), -(-H // CT_H)
@@ -262,6 +300,10 @@ def test_conv3x3_patch_replay(cin, H, W, n):
                     tap, c8 = divmod(rr, CPX)
                     k0 = tap * cin + ch * CC + 8 * c8
                     sW[nn * WS + tap * CPX + c8] = Wt[n0 + nn, k0:k0 + 8] if n0 + nn < N else 0
+                if not persist:
+                    _replay_general_chunk(X, Wt, sP, sW, b, y0, x0, n0, ch, cin, CC, CPX, CPP, WS, tn, N, H, W,
+                                          seen_k)
+                    continue
                 for S in range(NSTEP):
                     for wave in range(4):
                         wm, wn = divmod(wave, wn_n)
