@@ -737,13 +737,34 @@ hipError_t forward(pyhst_unet &net, const float *in, int n, float *out, int unsc
     hipError_t e;
     const int64_t npix = (int64_t)n * net.H * net.W;
     const Conv &c0 = net.enc_a[0];
-    const bool first = conv_first(in, n, net.H, net.W, net.scale, net.w0, net.params + c0.b, c0.cout, net.ea[0].a,
-                                  net.ea[0].C, st);
+    // inference: the first conv runs inside the second's kernel (its activation is never stored), with
+    // the level's pool in the epilogue
+    bool pair0 = false;
+    if (!keep && L > 1 && net.enc_b[0].cin == c0.cout) {
+        ConvStoreActPool E;
+        E.y = net.cat[0].a;
+        E.cs = net.cat[0].C;
+        E.co = 0;
+        E.bias = net.params + net.enc_b[0].b;
+        E.pool = net.pool[0].a;
+        E.pcs = net.pool[0].C;
+        hipError_t err = hipSuccess;
+        pair0 = run_conv_pair0(in, net.scale, net.w0, net.params + c0.b, act(net.x8, n),
+                               WeightB{net.enc_b[0].wf, 9 * net.enc_b[0].cin}, E, c0.cout, net.enc_b[0].cout,
+                               net.cu_count, st, err);
+        if (err != hipSuccess) return err;
+    }
+    const bool first = pair0 || conv_first(in, n, net.H, net.W, net.scale, net.w0, net.params + c0.b, c0.cout,
+                                           net.ea[0].a, net.ea[0].C, st);
     if (keep || !first)   // the first conv's input as the backward pass reads it (8 channels, the first one real)
         input_pad_kernel<<<blocks_for(npix), 256, 0, st>>>(in, npix, net.x8.a, net.scale);
     Act cur = act(net.x8, n);
     for (int l = 0; l < L; ++l) {
         const bool bott = l == L - 1;
+        if (l == 0 && pair0) {   // enc0a + enc0b + pool done
+            cur = act(net.pool[0], n);
+            continue;
+        }
         if ((l > 0 || !first) && (e = conv_fwd(net, net.enc_a[l], cur, net.ea[l].a, net.ea[l].C, 0, st)) != hipSuccess)
             return e;
         Act a = act(net.ea[l], n);

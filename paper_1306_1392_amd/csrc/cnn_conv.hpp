@@ -437,6 +437,161 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
     }
 }
 
+// The first two encoder convolutions of an inference pass in one persistent kernel.  Conv A (one real
+// input channel; w0 [C][9]: its BF16 weights as FP32, b0: bias) is evaluated for every pixel of the patch
+// that a tile of conv B needs, straight into the LDS patch, and is never stored: one MFMA per 32 patch
+// pixels (weights of the C <= 32 channels x 9 taps padded to 16 as the A operand, the pixels' 3 x 3 input
+// neighbourhoods as the B operand), bias, ReLU and BF16 rounding as in conv_first_kernel (the FP32 sums
+// may round differently in the last place).  Conv B (C -> N <= 32 outputs, weights in registers, 8 x 32-
+// pixel tiles) then runs as in the persistent form.  The next tile's 12 x 36 input pixels are in flight
+// in registers while the current tile is summed.  xin: FP32 input [B][H][W] (x gives the batch geometry).
+template <int C, class EP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void conv_pair0_kernel(const float *xin, float scale, const float *w0, const float *b0, Act x, WeightB B, EP E, int N,
+                       int tiles)
+{
+    constexpr int TN = 32, CTH = 8, CIN = C;
+    using G_ = ConvGrid<TN, CTH>;
+    constexpr int CPX = CIN / 8, CPP = CPX | 1;
+    constexpr int NSTEP = (9 * CIN + 15) / 16;
+    constexpr int WNW = G_::WN, BM = G_::BM, BN = G_::BN, WTN = G_::WTN;
+    constexpr int IH = CTH + 4, IW = CT_W + 4, NIN = IH * IW, NINV = (NIN + 255) / 256;
+    constexpr int NPB = (G_::PIX + 31) / 32;   // 32-pixel blocks of the patch
+    static_assert(C % 8 == 0 && C <= 32, "conv A's channels in one MFMA block");
+    __shared__ uint4 sP[G_::PIX * CPP];
+    __shared__ unsigned short sIn[NIN];        // bf16(scale x), zero outside the image
+    __shared__ float sBiasA[32];
+    __shared__ float4 sBias[TN / 4];
+    __shared__ float4 sHead[EP::HEAD ? TN / 4 : 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / WNW, wn = wave % WNW;
+    const int col = lane & 31, half = lane >> 5;
+    const int n0 = blockIdx.y * TN;
+    uint4 wr[NSTEP][BN];
+#pragma unroll
+    for (int S = 0; S < NSTEP; ++S)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+            const int n = n0 + wn * WTN + 32 * j + col, k = 16 * S + 8 * half;
+            wr[S][j] = n < N && k < 9 * CIN ? ld8(B.w + (int64_t)n * B.K + k) : zero8();
+        }
+    if (EP::BIAS && threadIdx.x < TN) ((float *)sBias)[threadIdx.x] = n0 + (int)threadIdx.x < N ? E.bias[n0 + threadIdx.x] : 0.0f;
+    if constexpr (EP::HEAD)
+        if (threadIdx.x < TN) ((float *)sHead)[threadIdx.x] = n0 + (int)threadIdx.x < N ? E.wh[n0 + threadIdx.x] : 0.0f;
+    if (threadIdx.x < 32) sBiasA[threadIdx.x] = (int)threadIdx.x < C ? b0[threadIdx.x] : 0.0f;
+    // conv A's A operand: channel col, taps 8 half .. 8 half + 7 (zero past tap 8 and channel C); the FP32
+    // weights hold BF16 values, so their upper 16 bits are the BF16 encoding
+    bf16x8 wa;
+    {
+        uint32_t u[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t0 = 8 * half + 2 * q, t1 = t0 + 1;
+            const uint32_t lo = col < C && t0 < 9 ? __float_as_uint(w0[9 * col + t0]) >> 16 : 0u;
+            const uint32_t hi = col < C && t1 < 9 ? __float_as_uint(w0[9 * col + t1]) >> 16 : 0u;
+            u[q] = lo | (hi << 16);
+        }
+        const uint4 v = make_uint4(u[0], u[1], u[2], u[3]);
+        wa = *(const bf16x8 *)&v;
+    }
+    unsigned short pin[NINV];
+    auto load = [&](int t) {
+        if (t >= tiles) return;
+        const ConvTile c = conv_tile<CTH>(x, t);
+#pragma unroll
+        for (int v = 0; v < NINV; ++v) {
+            const int i = threadIdx.x + 256 * v, iy = i / IW, ix = i - iy * IW;
+            const int yy = c.y0 - 2 + iy, xx = c.x0 - 2 + ix;
+            pin[v] = i < NIN && (unsigned)yy < (unsigned)x.H && (unsigned)xx < (unsigned)x.W
+                         ? (unsigned short)pack_bf16x2(xin[((int64_t)c.b * x.H + yy) * x.W + xx] * scale, 0.0f)
+                         : (unsigned short)0;
+        }
+    };
+    int la[BM];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) la[i] = ((wm * BM + i) * CT_PW + col) * CPP + (CIN >= 16 ? half : 0);
+
+    load(blockIdx.x);
+    for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const ConvTile c = conv_tile<CTH>(x, t);
+        __syncthreads();   // the previous tile's reads of the input and the patch are done
+#pragma unroll
+        for (int v = 0; v < NINV; ++v) {
+            const int i = threadIdx.x + 256 * v;
+            if (i < NIN) sIn[i] = pin[v];
+        }
+        __syncthreads();
+        load(t + (int)gridDim.x);   // in flight while this tile is computed
+        // conv A: wavefront w takes patch blocks w, w + 4, ...; lane col is patch pixel 32 pb + col
+        for (int pb = wave; pb < NPB; pb += 4) {   // uniform over the wavefront
+            const int p = 32 * pb + col;
+            const int pp = p < G_::PIX ? p : G_::PIX - 1;
+            const int py = pp / CT_PW, px = pp - py * CT_PW;
+            uint32_t u[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t0 = 8 * half + 2 * q, t1 = t0 + 1;
+                const uint32_t lo = t0 < 9 ? sIn[(py + t0 / 3) * IW + px + t0 % 3] : 0u;
+                const uint32_t hi = t1 < 9 ? sIn[(py + t1 / 3) * IW + px + t1 % 3] : 0u;
+                u[q] = lo | (hi << 16);
+            }
+            const uint4 bv = make_uint4(u[0], u[1], u[2], u[3]);
+            f32x16 a = {};
+            a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, *(const bf16x8 *)&bv, a, 0, 0, 0);
+            const int yy = c.y0 - 1 + py, xx = c.x0 - 1 + px;
+            const bool live = p < G_::PIX && (unsigned)yy < (unsigned)x.H && (unsigned)xx < (unsigned)x.W;
+#pragma unroll
+            for (int g = 0; g < 4; g += 2) {
+                uint2 r[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int ch = 8 * (g + h) + 4 * half;   // accumulator 4 (g + h) + q: channel ch + q
+                    r[h] = make_uint2(pack_bf16x2(fmaxf(a[4 * (g + h)] + sBiasA[ch], 0.0f),
+                                                  fmaxf(a[4 * (g + h) + 1] + sBiasA[ch + 1], 0.0f)),
+                                      pack_bf16x2(fmaxf(a[4 * (g + h) + 2] + sBiasA[ch + 2], 0.0f),
+                                                  fmaxf(a[4 * (g + h) + 3] + sBiasA[ch + 3], 0.0f)));
+                }
+                const uint4 o = gather8(r[0], r[1]);   // lane half h: channels 8 (g + h) .. + 7
+                const int grp = g + half;
+                if (p < G_::PIX && grp < CPX) sP[p * CPP + grp] = live ? o : zero8();
+            }
+        }
+        __syncthreads();
+        f32x16 acc[BN][BM];
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+#pragma unroll
+            for (int i = 0; i < BM; ++i)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[j][i][q] = 0.0f;
+        rconv_steps<CIN, TN, CTH, NSTEP>(std::make_integer_sequence<int, NSTEP>{}, sP, la, half, wr, acc);
+        pconv_store<G_>(x, c, n0, N, wm, wn, col, half, E, sBias, sHead, acc);
+    }
+}
+
+// conv_pair0_kernel for C = 8, 16 or 32 channels and N <= 32 outputs; false: not handled
+template <class EP>
+inline bool run_conv_pair0(const float *xin, float scale, const float *w0, const float *b0, const Act &x,
+                           const WeightB &w, const EP &e, int C, int N, int cu_count, hipStream_t st, hipError_t &err)
+{
+    if (N > 32) return false;
+    const int tiles = x.B * ((x.H + 7) / 8) * ((x.W + CT_W - 1) / CT_W);
+    auto go = [&](auto kernel) {
+        int per_cu = 0;
+        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0);
+        if (err != hipSuccess) return;
+        const int wgs = std::min(tiles, std::max(1, per_cu) * cu_count);
+        kernel<<<dim3(wgs, 1), 256, 0, st>>>(xin, scale, w0, b0, x, w, e, N, tiles);
+        err = hipGetLastError();
+    };
+    switch (C) {
+    case 8: go(conv_pair0_kernel<8, EP>); return true;
+    case 16: go(conv_pair0_kernel<16, EP>); return true;
+    case 32: go(conv_pair0_kernel<32, EP>); return true;
+    default: return false;
+    }
+}
+
 // wave layout of the general form's CTH x 32-pixel, TN-channel tile: each wavefront owns one column
 // block of 32 output channels (WN = min(4, TN / 32)) and CTH / WM consecutive tile rows (BM)
 template <int TN, int CTH>

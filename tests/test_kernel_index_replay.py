@@ -352,6 +352,51 @@ def test_conv3x3_patch_replay(cin, H, W, n):
                 assert seen_k == sorted(seen_k)
 
 
+@pytest.mark.parametrize("C,H,W", [(32, 16, 64), (16, 12, 40), (8, 8, 33)])
+def test_conv_pair0_patch_replay(C, H, W):
+    """The fused first two convolutions: the 12 x 36 input tile staged per 8 x 32 output tile holds input
+    pixel (y0 - 2 + iy, x0 - 2 + ix) (zero outside the image).  Wavefront w computes conv A for patch
+    blocks pb = w, w + 4, ...: lane (col, half) is patch pixel 32 pb + col and supplies taps 8 half ..
+    8 half + 7 of its B operand from input (py + t / 3, px + t % 3) of the tile, the neighbour
+    (t / 3 - 1, t % 3 - 1) of activation pixel (y0 - 1 + py, x0 - 1 + px); after the half-wave exchange
+    lane half h writes channel group g + h (g = 0, 2) of its pixel, so every (patch pixel, group < C / 8)
+    is written exactly once and every read stays inside the tile."""
+    CPX, IW, IH, PW = C // 8, CT_W + 4, 8 + 4, CT_PW
+    PIX = 10 * PW
+    rng = np.random.default_rng(C + H)
+    X = rng.integers(1, 1000, (2, H, W))
+    tiles_x, tiles_y = -(-W // CT_W), -(-H // 8)
+    for t in range(2 * tiles_x * tiles_y):
+        b, r = divmod(t, tiles_x * tiles_y)
+        y0, x0 = (r // tiles_x) * 8, (r % tiles_x) * CT_W
+        sIn = np.zeros(IH * IW, dtype=np.int64)
+        for i in range(IH * IW):
+            iy, ix = divmod(i, IW)
+            yy, xx = y0 - 2 + iy, x0 - 2 + ix
+            sIn[i] = X[b, yy, xx] if (0 <= yy < H and 0 <= xx < W) else 0
+        written = np.zeros((PIX, CPX), dtype=np.int64)
+        for wave in range(4):
+            for pb in range(wave, -(-PIX // 32), 4):
+                for lane in range(64):
+                    col, half = lane & 31, lane >> 5
+                    p = 32 * pb + col
+                    pp = min(p, PIX - 1)
+                    py, px = divmod(pp, PW)
+                    ay, ax = y0 - 1 + py, x0 - 1 + px
+                    for tp in range(8 * half, min(8 * half + 8, 9)):
+                        k = (py + tp // 3) * IW + px + tp % 3
+                        assert 0 <= k < IH * IW
+                        ny, nx = ay + tp // 3 - 1, ax + tp % 3 - 1
+                        ref = X[b, ny, nx] if (0 <= ny < H and 0 <= nx < W) else 0
+                        if p < PIX:
+                            assert sIn[k] == ref
+                    for g in (0, 2):
+                        grp = g + half
+                        if p < PIX and grp < CPX:
+                            written[p, grp] += 1
+        assert (written == 1).all()
+
+
 def _permlane32_swap(x, y):
     """v_permlane32_swap: lanes 32..63 of the first operand trade places with lanes 0..31 of the second."""
     return x[:32] + y[:32], x[32:] + y[32:]
