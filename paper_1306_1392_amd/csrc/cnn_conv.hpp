@@ -446,7 +446,7 @@ void conv3x3_persist_kernel(Act x, WeightB B, EP E, int N, int tiles)
 // pixel tiles) then runs as in the persistent form.  The next tile's 12 x 36 input pixels are in flight
 // in registers while the current tile is summed.  xin: FP32 input [B][H][W] (x gives the batch geometry).
 template <int C, class EP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 void conv_pair0_kernel(const float *xin, float scale, const float *w0, const float *b0, Act x, WeightB B, EP E, int N,
                        int tiles)
 {
