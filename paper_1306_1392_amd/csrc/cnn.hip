@@ -17,6 +17,7 @@
 
 #include "cnn_conv.hpp"
 #include "cnn_gemm.hpp"
+#include "cnn_wgrad.hpp"
 #include "internal.hpp"
 
 using namespace pyhst;
@@ -645,7 +646,15 @@ hipError_t conv_bwd(const pyhst_unet &net, const Conv &L, Act x, Act dz, bf16_t 
     const int npix = x.B * x.H * x.W;
     hipError_t e;
     // weight gradient: C[m = (tap, ci)][n = co] = sum_pix X[pix + off][ci] dZ[pix][co]
-    {
+    const int wtiles = x.B * ((x.H + 7) / 8) * ((x.W + CT_W - 1) / CT_W);
+    if (const int ws = wgrad_splits(L.cin, L.cout, wtiles, net.cu_count, net.part_floats)) {
+        const int M = 9 * L.cin, N = L.cout;
+        const int tps = (wtiles + ws - 1) / ws;
+        wgrad3x3_kernel<<<dim3(ws, N / 32, L.cin / 32), 256, 0, st>>>(x, dz, net.part, L.cin, N, wtiles, tps);
+        reduce_splitk_T_kernel<<<(unsigned)(((int64_t)M * N + 63) / 64), 64 * RSK_WAVES, 0, st>>>(net.part, 4 * ws, M,
+                                                                                                N, net.grads + L.w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
         const int M = 9 * L.cin, N = L.cout, tn = tn_for(N);
         const int s = splits_for(M, N, tn, npix, net.part_floats);
         Im2colT A = im2col_t(x, L.cin);

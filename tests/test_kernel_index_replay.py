@@ -397,6 +397,101 @@ def test_conv_pair0_patch_replay(C, H, W):
         assert (written == 1).all()
 
 
+def _perm_b32(s0, s1, sel):
+    """v_perm_b32: byte k of the result is byte sel[k] of the 8 bytes {s0 (bytes 4-7), s1 (bytes 0-3)}."""
+    pool = [(s1 >> (8 * i)) & 255 for i in range(4)] + [(s0 >> (8 * i)) & 255 for i in range(4)]
+    return sum(pool[(sel >> (8 * k)) & 255] << (8 * k) for k in range(4))
+
+
+def _transpose8x8(inp):
+    """The kernel's register transpose: inp[i] = 4 dwords (8 channels of pixel i, two per dword);
+    out[j] = 4 dwords (8 pixels of channel j)."""
+    out = []
+    for j in range(8):
+        sel = 0x07060302 if j & 1 else 0x05040100
+        out.append([_perm_b32(inp[2 * q + 1][j >> 1], inp[2 * q][j >> 1], sel) for q in range(4)])
+    return out
+
+
+@pytest.mark.parametrize("cin,N,H,W", [(32, 32, 8, 32), (64, 32, 12, 40), (32, 64, 9, 33)])
+def test_wgrad3x3_replay(cin, N, H, W):
+    """The direct weight-gradient kernel, replayed in exact integers: the channel-major LDS staging of
+    the input patch (three copies shifted by tx) and of dZ through the 8 x 8 register transpose, the
+    MFMA operands each wavefront reads (A = dZ[8 pixels][n], B = X[8 shifted pixels][c]), and the sums
+    of the nine 32 x 32 tap blocks over the tiles of a split, against dW computed from the definition."""
+    ZLD, XLD = 8 * CT_W + 8, 10 * CT_W + 8
+    rng = np.random.default_rng(cin + N + H)
+    B = 2
+    X = rng.integers(0, 50, (B, H, W, cin))
+    Z = rng.integers(0, 50, (B, H, W, N))
+    # dW from the definition
+    Xp = np.zeros((B, H + 2, W + 2, cin), dtype=np.int64)
+    Xp[:, 1:-1, 1:-1] = X
+    ref = np.zeros((N, 9, cin), dtype=np.int64)
+    for t in range(9):
+        ty, tx = divmod(t, 3)
+        ref[:, t] = np.einsum("byxn,byxc->nc", Z, Xp[:, ty:ty + H, tx:tx + W])
+    got = np.zeros_like(ref)
+    tiles_x, tiles_y = -(-W // CT_W), -(-H // 8)
+    pack = lambda v: [int(v[2 * d]) | (int(v[2 * d + 1]) << 16) for d in range(4)]
+    for t in range(B * tiles_x * tiles_y):
+        b, r0 = divmod(t, tiles_x * tiles_y)
+        y0, x0 = (r0 // tiles_x) * 8, (r0 % tiles_x) * CT_W
+        for n0 in range(0, N, 32):
+            for c0 in range(0, cin, 32):
+                sX = np.full(3 * 32 * XLD, -1, dtype=np.int64)
+                sZ = np.full(32 * ZLD, -1, dtype=np.int64)
+                for task in range(3 * 10 * 4 * 4):
+                    g, q, rr = task & 3, (task >> 2) & 3, task >> 4
+                    tx, r = divmod(rr, 10)
+                    yy = y0 - 1 + r
+                    inp = []
+                    for i in range(8):
+                        xx = x0 - 1 + tx + 8 * g + i
+                        v = X[b, yy, xx, c0 + 8 * q:c0 + 8 * q + 8] if (0 <= yy < H and 0 <= xx < W) else [0] * 8
+                        inp.append(pack(v))
+                    out = _transpose8x8(inp)
+                    for j in range(8):
+                        base = (tx * 32 + 8 * q + j) * XLD + r * CT_W + 8 * g
+                        for d in range(4):
+                            sX[base + 2 * d] = out[j][d] & 0xFFFF
+                            sX[base + 2 * d + 1] = out[j][d] >> 16
+                for tid in range(128):
+                    g, q, y = tid & 3, (tid >> 2) & 3, tid >> 4
+                    yy = y0 + y
+                    inp = []
+                    for i in range(8):
+                        xx = x0 + 8 * g + i
+                        v = Z[b, yy, xx, n0 + 8 * q:n0 + 8 * q + 8] if (yy < H and xx < W) else [0] * 8
+                        inp.append(pack(v))
+                    out = _transpose8x8(inp)
+                    for j in range(8):
+                        base = (8 * q + j) * ZLD + y * CT_W + 8 * g
+                        for d in range(4):
+                            sZ[base + 2 * d] = out[j][d] & 0xFFFF
+                            sZ[base + 2 * d + 1] = out[j][d] >> 16
+                for wave in range(4):
+                    for kk in range(4):
+                        y = 2 * wave + (kk >> 1)
+                        A = np.zeros((32, 16), dtype=np.int64)
+                        Bm = {t9: np.zeros((16, 32), dtype=np.int64) for t9 in range(9)}
+                        for lane in range(64):
+                            col, half = lane & 31, lane >> 5
+                            cofs = 16 * (kk & 1) + 8 * half
+                            a = sZ[col * ZLD + y * CT_W + cofs:col * ZLD + y * CT_W + cofs + 8]
+                            assert (a >= 0).all()
+                            A[col, 8 * half:8 * half + 8] = a
+                            for ty in range(3):
+                                for tx in range(3):
+                                    o = (tx * 32 + col) * XLD + (y + ty) * CT_W + cofs
+                                    bv = sX[o:o + 8]
+                                    assert (bv >= 0).all()
+                                    Bm[3 * ty + tx][8 * half:8 * half + 8, col] = bv
+                        for t9 in range(9):
+                            got[n0:n0 + 32, t9, c0:c0 + 32] += A @ Bm[t9]
+    assert np.array_equal(got, ref)
+
+
 def _permlane32_swap(x, y):
     """v_permlane32_swap: lanes 32..63 of the first operand trade places with lanes 0..31 of the second."""
     return x[:32] + y[:32], x[32:] + y[32:]
