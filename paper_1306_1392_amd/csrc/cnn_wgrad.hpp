@@ -10,8 +10,9 @@
 // B = X[pixels shifted by the tap][c] (c = lane % 32).  Both operands need eight consecutive pixels of
 // one channel per lane, so a tile's dZ (8 x 32 pixels x 32 n) and input patch (10 rows x 32 pixels x 32 c,
 // in three copies shifted by tx = 0, 1, 2 columns so that every read is 16-byte aligned) are staged in
-// LDS channel-major: each thread loads eight 16-byte pixel vectors (8 channels each), transposes the
-// 8 x 8 block in registers (v_perm_b32) and writes eight 16-byte channel rows.  Channel strides of
+// LDS channel-major: a thread loads 16-byte pixel vectors (8 channels each; ten consecutive pixels give
+// all three copies of an 8-pixel group), transposes 8 x 8 blocks in registers (v_perm_b32) and writes
+// 16-byte channel rows; a task's loads are issued together.  Channel strides of
 // 264 and 328 elements (4 mod 32 dwords) put the 8 lanes of an LDS pass in 8 different bank groups.
 // Each wavefront writes its nine 32 x 32 blocks as one split-K partial (4 partials per workgroup), in
 // the partial layout of the GEMM path ([split][m = tap cin + c][n]); the partials are added in a fixed
@@ -26,17 +27,11 @@ namespace cnn {
 constexpr int WG_ZLD = 8 * CT_W + 8;    // dZ channel stride in LDS (elements): 256 pixels + 8
 constexpr int WG_XLD = 10 * CT_W + 8;   // patch channel stride: 10 rows x 32 pixels + 8
 
-// in[i]: 8 channels of pixel i (BF16 pairs per dword); out[j]: 8 pixels of channel j
-__device__ __forceinline__ void transpose8x8(const uint4 (&in)[8], uint4 (&out)[8])
+// in[I0 + i], i = 0..7: 8 channels of pixel i (BF16 pairs per dword); store(j, v): v = 8 pixels of
+// channel j, each row handed over as soon as it is formed
+template <int I0, int NIN, class Store>
+__device__ __forceinline__ void transpose8x8(const uint4 (&in)[NIN], Store store)
 {
-    uint32_t a[8][4];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        a[i][0] = in[i].x;
-        a[i][1] = in[i].y;
-        a[i][2] = in[i].z;
-        a[i][3] = in[i].w;
-    }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         // channel j of pixels 2d (low half) and 2d + 1 (high half): v_perm_b32 takes bytes 0-3 from its
@@ -44,8 +39,13 @@ __device__ __forceinline__ void transpose8x8(const uint4 (&in)[8], uint4 (&out)[
         const uint32_t sel = (j & 1) ? 0x07060302u : 0x05040100u;
         uint32_t d[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) d[q] = __builtin_amdgcn_perm(a[2 * q + 1][j >> 1], a[2 * q][j >> 1], sel);
-        out[j] = make_uint4(d[0], d[1], d[2], d[3]);
+        for (int q = 0; q < 4; ++q) {
+            const uint4 lo = in[I0 + 2 * q], hi = in[I0 + 2 * q + 1];
+            const uint32_t wl = (j >> 1) == 0 ? lo.x : (j >> 1) == 1 ? lo.y : (j >> 1) == 2 ? lo.z : lo.w;
+            const uint32_t wh = (j >> 1) == 0 ? hi.x : (j >> 1) == 1 ? hi.y : (j >> 1) == 2 ? hi.z : hi.w;
+            d[q] = __builtin_amdgcn_perm(wh, wl, sel);
+        }
+        store(j, make_uint4(d[0], d[1], d[2], d[3]));
     }
 }
 
@@ -69,38 +69,42 @@ void wgrad3x3_kernel(Act x, Act dz, float *part, int cin, int N, int tiles, int 
     for (int t = blockIdx.x * tps; t < t_end; ++t) {
         const ConvTile c = conv_tile<8>(x, t);
         __syncthreads();   // the previous tile's reads of sX and sZ are done
-        // input patch: task = (copy tx, patch row r, column group g of 8, channel group q of 8)
-        for (int task = tid; task < 3 * 10 * 4 * 4; task += 256) {
-            const int g = task & 3, q = (task >> 2) & 3, rr = task >> 4, tx = rr / 10, r = rr - 10 * tx;
+        // staging tasks, a task's loads issued together: threads 0..159 take the input patch task (patch
+        // row r, column group g, channel group q): pixels x0 - 1 + 8 g + i, i = 0..9, give the three copies
+        // tx (pixels 8 g + tx + 0..7 of the copy); dZ task d = (row y, column group g, output group q) goes
+        // to thread 160 + d (d < 96), and d = 96 + t to thread t < 32 after its patch task
+        uint4 in[10];
+        if (tid < 160) {
+            const int q = tid & 3, g = (tid >> 2) & 3, r = tid >> 4;
             const int yy = c.y0 - 1 + r;
             const bool rowin = (unsigned)yy < (unsigned)x.H;
             const bf16_t *src = x.p + ((int64_t)c.b * x.H + (rowin ? yy : 0)) * x.W * x.cs + x.co + c0 + 8 * q;
-            uint4 in[8], out[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int xx = c.x0 - 1 + tx + 8 * g + i;
+            for (int i = 0; i < 10; ++i) {
+                const int xx = c.x0 - 1 + 8 * g + i;
                 in[i] = rowin && (unsigned)xx < (unsigned)x.W ? ld8(src + (int64_t)xx * x.cs) : zero8();
             }
-            transpose8x8(in, out);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) *(uint4 *)&sX[(tx * 32 + 8 * q + j) * WG_XLD + r * CT_W + 8 * g] = out[j];
+            bf16_t *dst = sX + (8 * q) * WG_XLD + r * CT_W + 8 * g;
+            transpose8x8<0>(in, [&](int j, uint4 v) { *(uint4 *)&dst[j * WG_XLD] = v; });
+            transpose8x8<1>(in, [&](int j, uint4 v) { *(uint4 *)&dst[(32 + j) * WG_XLD] = v; });
+            transpose8x8<2>(in, [&](int j, uint4 v) { *(uint4 *)&dst[(64 + j) * WG_XLD] = v; });
         }
-        // dZ of the tile: task = (row y, column group g, output group q), threads 0..127
-        if (tid < 8 * 4 * 4) {
-            const int g = tid & 3, q = (tid >> 2) & 3, y = tid >> 4;
+        auto stage_dz = [&](int d) {
+            const int g = d & 3, q = (d >> 2) & 3, y = d >> 4;
             const int yy = c.y0 + y;
             const bool rowin = yy < x.H;
             const bf16_t *src = dz.p + ((int64_t)c.b * x.H + (rowin ? yy : 0)) * x.W * dz.cs + dz.co + n0 + 8 * q;
-            uint4 in[8], out[8];
+            uint4 in8[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int xx = c.x0 + 8 * g + i;
-                in[i] = rowin && xx < x.W ? ld8(src + (int64_t)xx * dz.cs) : zero8();
+                in8[i] = rowin && xx < x.W ? ld8(src + (int64_t)xx * dz.cs) : zero8();
             }
-            transpose8x8(in, out);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) *(uint4 *)&sZ[(8 * q + j) * WG_ZLD + y * CT_W + 8 * g] = out[j];
-        }
+            bf16_t *dst = sZ + (8 * q) * WG_ZLD + y * CT_W + 8 * g;
+            transpose8x8<0>(in8, [&](int j, uint4 v) { *(uint4 *)&dst[j * WG_ZLD] = v; });
+        };
+        if (tid >= 160) stage_dz(tid - 160);
+        else if (tid < 32) stage_dz(96 + tid);
         __syncthreads();
         // wavefront w: output rows 2w, 2w + 1; K step kk = 16 pixels of one row
 #pragma unroll

@@ -416,7 +416,8 @@ def _transpose8x8(inp):
 @pytest.mark.parametrize("cin,N,H,W", [(32, 32, 8, 32), (64, 32, 12, 40), (32, 64, 9, 33)])
 def test_wgrad3x3_replay(cin, N, H, W):
     """The direct weight-gradient kernel, replayed in exact integers: the channel-major LDS staging of
-    the input patch (three copies shifted by tx) and of dZ through the 8 x 8 register transpose, the
+    the input patch (three copies shifted by tx, from ten pixels per task) and of dZ (task d on thread
+    160 + d or d - 96) through the 8 x 8 register transpose, the
     MFMA operands each wavefront reads (A = dZ[8 pixels][n], B = X[8 shifted pixels][c]), and the sums
     of the nine 32 x 32 tap blocks over the tiles of a split, against dW computed from the definition."""
     ZLD, XLD = 8 * CT_W + 8, 10 * CT_W + 8
@@ -441,21 +442,24 @@ def test_wgrad3x3_replay(cin, N, H, W):
             for c0 in range(0, cin, 32):
                 sX = np.full(3 * 32 * XLD, -1, dtype=np.int64)
                 sZ = np.full(32 * ZLD, -1, dtype=np.int64)
-                for task in range(3 * 10 * 4 * 4):
-                    g, q, rr = task & 3, (task >> 2) & 3, task >> 4
-                    tx, r = divmod(rr, 10)
+                for tid in range(160):   # patch tasks: ten pixels give the three shifted copies
+                    q, g, r = tid & 3, (tid >> 2) & 3, tid >> 4
                     yy = y0 - 1 + r
                     inp = []
-                    for i in range(8):
-                        xx = x0 - 1 + tx + 8 * g + i
+                    for i in range(10):
+                        xx = x0 - 1 + 8 * g + i
                         v = X[b, yy, xx, c0 + 8 * q:c0 + 8 * q + 8] if (0 <= yy < H and 0 <= xx < W) else [0] * 8
                         inp.append(pack(v))
-                    out = _transpose8x8(inp)
-                    for j in range(8):
-                        base = (tx * 32 + 8 * q + j) * XLD + r * CT_W + 8 * g
-                        for d in range(4):
-                            sX[base + 2 * d] = out[j][d] & 0xFFFF
-                            sX[base + 2 * d + 1] = out[j][d] >> 16
+                    for tx in range(3):
+                        out = _transpose8x8(inp[tx:tx + 8])
+                        for j in range(8):
+                            base = (tx * 32 + 8 * q + j) * XLD + r * CT_W + 8 * g
+                            assert (sX[base:base + 8] == -1).all()   # every slot written once
+                            for d in range(4):
+                                sX[base + 2 * d] = out[j][d] & 0xFFFF
+                                sX[base + 2 * d + 1] = out[j][d] >> 16
+                dtasks = sorted([t - 160 for t in range(160, 256)] + [96 + t for t in range(32)])
+                assert dtasks == list(range(128))
                 for tid in range(128):
                     g, q, y = tid & 3, (tid >> 2) & 3, tid >> 4
                     yy = y0 + y
