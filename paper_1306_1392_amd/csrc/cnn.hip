@@ -650,9 +650,11 @@ hipError_t conv_bwd(const pyhst_unet &net, const Conv &L, Act x, Act dz, bf16_t 
     if (const int ws = wgrad_splits(L.cin, L.cout, wtiles, net.cu_count, net.part_floats)) {
         const int M = 9 * L.cin, N = L.cout;
         const int tps = (wtiles + ws - 1) / ws;
-        wgrad3x3_kernel<<<dim3(ws, N / 32, L.cin / 32), 256, 0, st>>>(x, dz, net.part, L.cin, N, wtiles, tps);
+        float *bpart = net.part + (size_t)4 * ws * M * N;
+        wgrad3x3_kernel<<<dim3(ws, N / 32, L.cin / 32), 256, 0, st>>>(x, dz, net.part, bpart, L.cin, N, wtiles, tps);
         reduce_splitk_T_kernel<<<(unsigned)(((int64_t)M * N + 63) / 64), 64 * RSK_WAVES, 0, st>>>(net.part, 4 * ws, M,
                                                                                                 N, net.grads + L.w);
+        reduce_rows_kernel<<<N, 256, 0, st>>>(bpart, ws, N, net.grads + L.b);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else {
         const int M = 9 * L.cin, N = L.cout, tn = tn_for(N);
@@ -669,8 +671,8 @@ hipError_t conv_bwd(const pyhst_unet &net, const Conv &L, Act x, Act dz, bf16_t 
         else gemm_kernel<Im2colT, PlainT, StorePartial, 32, TM, TKW><<<grid, 256, 0, st>>>(A, Bz, E, M, N, npix, ks);
         reduce_splitk_T_kernel<<<(unsigned)(((int64_t)M * N + 63) / 64), 64 * RSK_WAVES, 0, st>>>(net.part, sp, M, N, net.grads + L.w);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = chan_sum(net, dz, L.cout, nullptr, net.grads + L.b, st)) != hipSuccess) return e;
     }
-    if ((e = chan_sum(net, dz, L.cout, nullptr, net.grads + L.b, st)) != hipSuccess) return e;
     if (dx) {
         // dX[pix][ci] = sum_{tap', co} dZ[pix + off(tap')][co] Wb[ci][tap'][co], masked by X > 0
         const int M = npix, N = L.cin;

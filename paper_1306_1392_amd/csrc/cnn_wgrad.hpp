@@ -50,9 +50,12 @@ __device__ __forceinline__ void transpose8x8(const uint4 (&in)[NIN], Store store
 }
 
 // grid: (splits, N / 32 output blocks, cin / 32 input blocks); part: [4 splits][9 cin][N] floats per
-// split index s (partials 4 s .. 4 s + 3); tiles: 8 x 32-pixel output tiles of the batch, tps per split
+// split index s (partials 4 s .. 4 s + 3); tiles: 8 x 32-pixel output tiles of the batch, tps per split.
+// bpart (may be null): the bias gradient's partial sums [split][N], sum over the split's pixels of
+// dZ[p][n], taken by the workgroups of input block 0 from the staged dZ (thread t: output n0 + t / 8,
+// pixels 32 (t % 8) .. + 31 of every tile; the 8 partial sums meet in a fixed order by lane exchanges).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-void wgrad3x3_kernel(Act x, Act dz, float *part, int cin, int N, int tiles, int tps)
+void wgrad3x3_kernel(Act x, Act dz, float *part, float *bpart, int cin, int N, int tiles, int tps)
 {
     __shared__ uint4 sXv[3 * 32 * WG_XLD / 8];
     __shared__ uint4 sZv[32 * WG_ZLD / 8];
@@ -65,6 +68,8 @@ void wgrad3x3_kernel(Act x, Act dz, float *part, int cin, int N, int tiles, int 
     for (int k = 0; k < 9; ++k)
 #pragma unroll
         for (int q = 0; q < 16; ++q) acc[k][q] = 0.0f;
+    const bool bias = bpart != nullptr && blockIdx.z == 0;   // uniform over the workgroup
+    float bacc = 0.0f;
     const int t_end = min(tiles, (int)(blockIdx.x + 1) * tps);
     for (int t = blockIdx.x * tps; t < t_end; ++t) {
         const ConvTile c = conv_tile<8>(x, t);
@@ -106,6 +111,16 @@ void wgrad3x3_kernel(Act x, Act dz, float *part, int cin, int N, int tiles, int 
         if (tid >= 160) stage_dz(tid - 160);
         else if (tid < 32) stage_dz(96 + tid);
         __syncthreads();
+        if (bias) {
+            const uint4 *row = (const uint4 *)&sZ[(tid >> 3) * WG_ZLD + 32 * (tid & 7)];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint4 u = row[v];
+                const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) bacc += bf16_lo(w[e]) + bf16_hi(w[e]);
+            }
+        }
         // wavefront w: output rows 2w, 2w + 1; K step kk = 16 pixels of one row
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
@@ -120,6 +135,12 @@ void wgrad3x3_kernel(Act x, Act dz, float *part, int cin, int N, int tiles, int 
                 }
         }
     }
+    if (bias) {
+        bacc += __shfl_xor(bacc, 1, 64);
+        bacc += __shfl_xor(bacc, 2, 64);
+        bacc += __shfl_xor(bacc, 4, 64);
+        if ((tid & 7) == 0) bpart[(int64_t)blockIdx.x * N + n0 + (tid >> 3)] = bacc;
+    }
     // accumulator 4 g + q of tap k: D[n = 8 g + 4 half + q][c = col] -> part[m = k cin + c0 + col][n0 + n]
     const int M = 9 * cin;
     float *P = part + (int64_t)(4 * blockIdx.x + wave) * M * N;
@@ -132,14 +153,15 @@ void wgrad3x3_kernel(Act x, Act dz, float *part, int cin, int N, int tiles, int 
 }
 
 // splits (workgroups along the batch) for the direct weight gradient: about two workgroups per CU in
-// all, within the partial buffer (4 partials of 9 cin x N floats per split); 0: not handled
+// all, within the partial buffer (4 partials of 9 cin x N floats and a bias partial of N per split);
+// 0: not handled
 inline int wgrad_splits(int cin, int N, int tiles, int cu_count, size_t part_floats)
 {
     if (cin % 32 || N % 32) return 0;
     const int blocks = (N / 32) * (cin / 32);
     int s = std::max(1, (2 * cu_count + blocks - 1) / blocks);
     s = std::min(s, tiles);
-    const size_t per = (size_t)4 * 9 * cin * N;
+    const size_t per = (size_t)4 * 9 * cin * N + N;   // weight partials and the bias partial
     while (s > 1 && (size_t)s * per > part_floats) --s;
     if ((size_t)s * per > part_floats) return 0;
     return s;

@@ -419,7 +419,8 @@ def test_wgrad3x3_replay(cin, N, H, W):
     the input patch (three copies shifted by tx, from ten pixels per task) and of dZ (task d on thread
     160 + d or d - 96) through the 8 x 8 register transpose, the
     MFMA operands each wavefront reads (A = dZ[8 pixels][n], B = X[8 shifted pixels][c]), and the sums
-    of the nine 32 x 32 tap blocks over the tiles of a split, against dW computed from the definition."""
+    of the nine 32 x 32 tap blocks over the tiles of a split, against dW computed from the definition;
+    the bias partials read from the staged dZ against the sums of dZ."""
     ZLD, XLD = 8 * CT_W + 8, 10 * CT_W + 8
     rng = np.random.default_rng(cin + N + H)
     B = 2
@@ -433,6 +434,7 @@ def test_wgrad3x3_replay(cin, N, H, W):
         ty, tx = divmod(t, 3)
         ref[:, t] = np.einsum("byxn,byxc->nc", Z, Xp[:, ty:ty + H, tx:tx + W])
     got = np.zeros_like(ref)
+    bsum = np.zeros(N, dtype=np.int64)
     tiles_x, tiles_y = -(-W // CT_W), -(-H // 8)
     pack = lambda v: [int(v[2 * d]) | (int(v[2 * d + 1]) << 16) for d in range(4)]
     for t in range(B * tiles_x * tiles_y):
@@ -474,6 +476,11 @@ def test_wgrad3x3_replay(cin, N, H, W):
                         for d in range(4):
                             sZ[base + 2 * d] = out[j][d] & 0xFFFF
                             sZ[base + 2 * d + 1] = out[j][d] >> 16
+                if c0 == 0:   # bias partials: thread t sums pixels 32 (t % 8) .. + 31 of dZ row n0 + t / 8
+                    for t8 in range(256):
+                        seg = sZ[(t8 >> 3) * ZLD + 32 * (t8 & 7):(t8 >> 3) * ZLD + 32 * (t8 & 7) + 32]
+                        assert (seg >= 0).all()
+                        bsum[n0 + (t8 >> 3)] += int(seg.sum())
                 for wave in range(4):
                     for kk in range(4):
                         y = 2 * wave + (kk >> 1)
@@ -494,6 +501,7 @@ def test_wgrad3x3_replay(cin, N, H, W):
                         for t9 in range(9):
                             got[n0:n0 + 32, t9, c0:c0 + 32] += A @ Bm[t9]
     assert np.array_equal(got, ref)
+    assert np.array_equal(bsum, Z.sum(axis=(0, 1, 2)))
 
 
 def _permlane32_swap(x, y):
