@@ -422,10 +422,13 @@ int pyhst_unet_get_params(const pyhst_unet *net, float *params, hipStream_t stre
 /* Gradients of the last pyhst_unet_backward (device FP32 [n_params]). */
 int pyhst_unet_get_grads(const pyhst_unet *net, float *grads, hipStream_t stream);
 /* Inference: out = x_hat for the n inputs (device FP32 [n][height][width]).
- * The output head runs in the epilogue of the last decoder convolution and the
- * first encoder convolution inside the second one's kernel, so this call stores
- * neither of their activations (pyhst_unet_tensor kind 5 and kind 1, level 0,
- * and the 8-channel input, kind 0, hold them after pyhst_unet_backward only). */
+ * The output head runs in the epilogue of the last decoder convolution, the
+ * first encoder convolution inside the second one's kernel, and the
+ * up-sampling of every decoder level whose first convolution has at most 32
+ * channels per concatenated half and 32 outputs inside that convolution, so
+ * this call stores none of those activations (pyhst_unet_tensor kind 5 and
+ * kind 1 at level 0, the up half of kind 2 at those levels, and the 8-channel
+ * input, kind 0, hold them after pyhst_unet_backward only). */
 int pyhst_unet_forward(pyhst_unet *net, const float *in, int32_t n, float *out, hipStream_t stream);
 /* Forward, mean-squared-error loss against target (device float *loss, may be
  * NULL) and backward into the gradient buffer. */

@@ -798,11 +798,23 @@ hipError_t forward(pyhst_unet &net, const float *in, int n, float *out, int unsc
     Act below = act(net.bott_b, n);
     for (int l = L - 2; l >= 0; --l) {
         const Up &u = net.up[l];
-        if ((e = up_fwd(net, u, below, net.cat[l].a, net.cat[l].H, net.cat[l].W, net.cat[l].C, u.cout, st)) !=
-            hipSuccess)
-            return e;
-        if ((e = conv_fwd(net, net.dec_a[l], act(net.cat[l], n), net.da[l].a, net.da[l].C, 0, st)) != hipSuccess)
-            return e;
+        const Conv &da = net.dec_a[l];
+        // inference: the up-sampling inside the first decoder conv where that conv takes the persistent
+        // form (the concatenation's up half is then never stored)
+        bool fused = false;
+        if (!keep && net.enc_b[l].cout == u.cout && da.cin == 2 * u.cout) {
+            hipError_t err = hipSuccess;
+            fused = run_conv_upcat(act(net.cat[l], n), below, u.uf, net.params + u.b, WeightB{da.wf, 9 * da.cin},
+                                   ConvStoreAct{net.da[l].a, net.da[l].C, 0, net.params + da.b}, u.cout, u.cin,
+                                   da.cout, net.cu_count, st, err);
+            if (err != hipSuccess) return err;
+        }
+        if (!fused) {
+            if ((e = up_fwd(net, u, below, net.cat[l].a, net.cat[l].H, net.cat[l].W, net.cat[l].C, u.cout, st)) !=
+                hipSuccess)
+                return e;
+            if ((e = conv_fwd(net, da, act(net.cat[l], n), net.da[l].a, net.da[l].C, 0, st)) != hipSuccess) return e;
+        }
         if (l == 0 && head_fusable(net.dec_b[0]))
             return conv_fwd_head(net, net.dec_b[0], act(net.da[0], n), keep ? net.db[0].a : nullptr, net.db[0].C, in,
                                  out, unscale, st);

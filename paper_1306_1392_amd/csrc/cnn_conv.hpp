@@ -592,6 +592,225 @@ inline bool run_conv_pair0(const float *xin, float scale, const float *w0, const
     }
 }
 
+// One MFMA K step S of conv_upcat_kernel with the up half's weights in LDS (CU = 32): the skip half's
+// weight operands are in registers (wr, tap by tap), the up half's at slots n WSU + tap CSX + chunk of sW.
+template <int CU, int NR, int S>
+__device__ __forceinline__ void upcat_step(const uint4 *sP, const uint4 *sW, int la, int lw, const uint4 (&wr)[NR],
+                                           f32x16 &acc)
+{
+    constexpr int CIN = 2 * CU, CPP = (CIN / 8) | 1, CSX = CU / 8;
+    constexpr int tap = (16 * S) / CIN, c8 = ((16 * S) % CIN) / 8;   // both halves read one tap (CIN >= 32)
+    constexpr int oa = ((tap / 3) * CT_PW + tap % 3) * CPP + c8;
+    uint4 w;
+    if constexpr (c8 >= CSX) w = sW[lw + tap * CSX + c8 - CSX];
+    else w = wr[tap * (CU / 16) + c8 / 2];
+    const uint4 v = sP[la + oa];
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8 *)&w, *(const bf16x8 *)&v, acc, 0, 0, 0);
+}
+template <int CU, int NR, int... S>
+__device__ __forceinline__ void upcat_steps(std::integer_sequence<int, S...>, const uint4 *sP, const uint4 *sW, int la,
+                                            int lw, const uint4 (&wr)[NR], f32x16 &acc)
+{
+    (upcat_step<CU, NR, S>(sP, sW, la, lw, wr, acc), ...);
+}
+
+// Inference: the first convolution of a decoder level with the level's 2x2 up-sampling inside it, so the
+// concatenation [skip | up(lo)] that the convolution reads is never stored.  The skip half of a tile's
+// patch is loaded as in the persistent form; the up half is computed straight into the LDS patch from the
+// low-resolution input lo: up[2 Y + dy][2 X + dx][co] = relu(ub[co] + sum_ci lo[Y][X][ci] U[(2 dy + dx) CU +
+// co][ci]), zero outside the image.  The patch pixels of one sub-pixel parity d = (dy, dx) are 3 rows x 17
+// columns of the tile's low-resolution footprint (4 x 18 pixels, staged in LDS); wavefront d sums them in
+// two blocks of 32 MFMA columns with the parity's up weights (in LDS) as the A operand.  The convolution
+// (CIN = 2 CU inputs, N <= 32 outputs, weights in registers, 4 x 32-pixel tiles) then runs as in the
+// persistent form.  Both sums are those of up2x2_kernel and the persistent form, term for term in the
+// same order with the same roundings, so the output equals the unfused pair's bit for bit.  The next
+// tile's patch and footprint are in flight in registers while the current one is summed (two tiles in
+// flight measured slower).
+// xs: the skip activation (CU channels, the output geometry); uw: U as [(d, co)][ci] (CL inputs); ub: its
+// bias.
+template <int CU, int CL, class EP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void conv_upcat_kernel(Act xs, Act lo, const bf16_t *uw, const float *ub, WeightB B, EP E, int N, int tiles)
+{
+    constexpr int TN = 32, CTH = 4, CIN = 2 * CU;
+    using G_ = ConvGrid<TN, CTH>;
+    constexpr int CPX = CIN / 8, CPP = CPX | 1, CSX = CU / 8;
+    constexpr int CLX = CL / 8, LPP = CLX | 1;                        // footprint and up-weight slot stride
+    constexpr int FH = CTH / 2 + 2, FW = CT_W / 2 + 2;               // low-resolution footprint
+    constexpr int PR = (CTH + 2) / 2, PC = CT_PW / 2, NE = PR * PC;  // patch pixels of one parity
+    constexpr int NSS = G_::PIX * CSX;                               // skip vectors of the patch
+    constexpr int NLS = FH * FW * CLX;                               // footprint vectors
+    constexpr int NV = (NSS + NLS + 255) / 256;
+    constexpr int NSTEP = (9 * CIN + 15) / 16;
+    constexpr int WNW = G_::WN, BM = G_::BM, BN = G_::BN, WTN = G_::WTN;
+    static_assert(CU % 8 == 0 && CU <= 32 && CL % 16 == 0, "whole MFMA blocks and K steps of the up-sampling");
+    static_assert(TN * 9 * CIN <= 20480, "weights of the workgroup's outputs fit in registers");
+    static_assert(NE <= 64, "two 32-column MFMA blocks per parity");
+    static_assert(BM == 1 && BN == 1, "one 32 x 32 block per wavefront and tile");
+    // CU = 32: the up half's conv weights in LDS (the registers hold the skip half's), else all in registers
+    constexpr bool WL = CU == 32;
+    constexpr int WSU = conv_ws(CSX), NR = WL ? 9 * (CU / 16) : NSTEP;
+    __shared__ uint4 sP[G_::PIX * CPP];
+    __shared__ uint4 sL[FH * FW * LPP];
+    __shared__ uint4 sU[4 * CU * LPP];
+    __shared__ uint4 sW[WL ? TN * WSU : 1];
+    __shared__ float sBU[32];
+    __shared__ float4 sBias[TN / 4];
+    __shared__ float4 sHead[EP::HEAD ? TN / 4 : 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / WNW, wn = wave % WNW;
+    const int col = lane & 31, half = lane >> 5;
+    const int n0 = blockIdx.y * TN;
+    uint4 wr[NR][1];
+    {
+        const int n = n0 + col;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            // register r: step S = r (all in registers) or tap r / (CU / 16), sub-step r % (CU / 16)
+            const int S = WL ? (r / (CU / 16)) * (CIN / 16) + r % (CU / 16) : r;
+            const int k = 16 * S + 8 * half;
+            wr[r][0] = n < N && k < 9 * CIN ? ld8(B.w + (int64_t)n * B.K + k) : zero8();
+        }
+    }
+    if constexpr (WL)
+        for (int i = threadIdx.x; i < TN * 9 * CSX; i += 256) {
+            const int n = i / (9 * CSX), r = i - n * (9 * CSX), tap = r / CSX, u8 = r - tap * CSX;
+            sW[n * WSU + r] = n0 + n < N ? ld8(B.w + (int64_t)(n0 + n) * B.K + tap * CIN + CU + 8 * u8) : zero8();
+        }
+    for (int i = threadIdx.x; i < 4 * CU * CLX; i += 256) {
+        const int r = i / CLX, c8 = i - r * CLX;
+        sU[r * LPP + c8] = ld8(uw + (int64_t)r * CL + 8 * c8);
+    }
+    if (threadIdx.x < 32) sBU[threadIdx.x] = (int)threadIdx.x < CU ? ub[threadIdx.x] : 0.0f;
+    if (EP::BIAS && threadIdx.x < TN) ((float *)sBias)[threadIdx.x] = n0 + (int)threadIdx.x < N ? E.bias[n0 + threadIdx.x] : 0.0f;
+    if constexpr (EP::HEAD)
+        if (threadIdx.x < TN) ((float *)sHead)[threadIdx.x] = n0 + (int)threadIdx.x < N ? E.wh[n0 + threadIdx.x] : 0.0f;
+    // this thread's staged vectors, the same for every tile: index i < NSS a skip vector of the patch
+    // (pixel (py, px), chunk c8), else footprint vector i - NSS (row fr, column fc, chunk c8); -1: none
+    int spos[NV], sdst[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int i = threadIdx.x + 256 * v;
+        if (i < NSS) {
+            const int p = i / CSX, c8 = i - p * CSX, py = p / CT_PW, px = p - py * CT_PW;
+            spos[v] = (py << 16) | (px << 8) | c8;
+            sdst[v] = p * CPP + c8;
+        } else {
+            const int k = i - NSS, f = k / CLX, c8 = k - f * CLX, fr = f / FW, fc = f - fr * FW;
+            spos[v] = k < NLS ? (1 << 24) | (fr << 16) | (fc << 8) | c8 : -1;
+            sdst[v] = f * LPP + c8;
+        }
+    }
+    uint4 pv[NV];
+    auto load = [&](int t) {
+        if (t >= tiles) return;
+        const ConvTile c = conv_tile<CTH>(xs, t);
+        const bf16_t *img = xs.p + (int64_t)c.b * xs.H * xs.W * xs.cs + xs.co;
+        const bf16_t *limg = lo.p + (int64_t)c.b * lo.H * lo.W * lo.cs + lo.co;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int r = (spos[v] >> 16) & 255, q = (spos[v] >> 8) & 255, c8 = spos[v] & 255;
+            const bool foot = spos[v] >> 24;
+            const int yy = foot ? (c.y0 >> 1) - 1 + r : c.y0 - 1 + r, xx = foot ? (c.x0 >> 1) - 1 + q : c.x0 - 1 + q;
+            const int h = foot ? lo.H : xs.H, w = foot ? lo.W : xs.W;
+            const bf16_t *src = foot ? limg + (int64_t)(yy * lo.W + xx) * lo.cs : img + (int64_t)(yy * xs.W + xx) * xs.cs;
+            pv[v] = spos[v] >= 0 && (unsigned)yy < (unsigned)h && (unsigned)xx < (unsigned)w ? ld8(src + 8 * c8) : zero8();
+        }
+    };
+    int la[BM];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) la[i] = ((wm * BM + i) * CT_PW + col) * CPP + (CIN >= 16 ? half : 0);
+    // the up-sampling of wavefront d = (dy, dx): A operand rows (d CU + col) of U (zero past CU)
+    const int dy = wave >> 1, dx = wave & 1;
+    const int lu = (wave * CU + (col < CU ? col : 0)) * LPP + half;
+
+    load(blockIdx.x);
+    for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const ConvTile c = conv_tile<CTH>(xs, t);
+        __syncthreads();   // the previous tile's reads of the patch and the footprint are done
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (spos[v] >= 0) (spos[v] >> 24 ? sL : sP)[sdst[v]] = pv[v];
+        __syncthreads();
+        load(t + (int)gridDim.x);   // in flight while this tile is summed
+        // up half of the patch: MFMA column e of block blk is parity pixel e = 32 blk + col (row e / PC,
+        // column e % PC of the parity), i.e. patch pixel (2 (e / PC) + 1 - dy, 2 (e % PC) + 1 - dx) and
+        // footprint pixel (e / PC + 1 - dy, e % PC + 1 - dx)
+#pragma unroll
+        for (int blk = 0; blk < 2; ++blk) {
+            const int e = 32 * blk + col, ee = e < NE ? e : NE - 1;
+            const int r3 = ee / PC, c17 = ee - r3 * PC;
+            const int py = 2 * r3 + 1 - dy, px = 2 * c17 + 1 - dx;
+            const int lb = ((r3 + 1 - dy) * FW + c17 + 1 - dx) * LPP + half;
+            f32x16 a = {};
+#pragma unroll
+            for (int s = 0; s < CL / 16; ++s) {
+                const uint4 wv = col < CU ? sU[lu + 2 * s] : zero8();
+                const uint4 bv = sL[lb + 2 * s];
+                a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8 *)&wv, *(const bf16x8 *)&bv, a, 0, 0, 0);
+            }
+            const int yy = c.y0 - 1 + py, xx = c.x0 - 1 + px;
+            const bool live = (unsigned)yy < (unsigned)xs.H && (unsigned)xx < (unsigned)xs.W;
+#pragma unroll
+            for (int g = 0; g < 4; g += 2) {
+                uint2 r[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int ch = 8 * (g + h) + 4 * half;   // accumulator 4 (g + h) + q: channel ch + q
+                    r[h] = make_uint2(pack_bf16x2(fmaxf(a[4 * (g + h)] + sBU[ch], 0.0f),
+                                                  fmaxf(a[4 * (g + h) + 1] + sBU[ch + 1], 0.0f)),
+                                      pack_bf16x2(fmaxf(a[4 * (g + h) + 2] + sBU[ch + 2], 0.0f),
+                                                  fmaxf(a[4 * (g + h) + 3] + sBU[ch + 3], 0.0f)));
+                }
+                const uint4 o = gather8(r[0], r[1]);   // lane half h: channels 8 (g + h) .. + 7
+                const int grp = g + half;
+                if (e < NE && grp < CSX) sP[(py * CT_PW + px) * CPP + CSX + grp] = live ? o : zero8();
+            }
+        }
+        __syncthreads();
+        f32x16 acc[BN][BM];
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+#pragma unroll
+            for (int i = 0; i < BM; ++i)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[j][i][q] = 0.0f;
+        if constexpr (WL) {
+            uint4 wk[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) wk[r] = wr[r][0];
+            upcat_steps<CU, NR>(std::make_integer_sequence<int, NSTEP>{}, sP, sW, la[0], col * WSU + half, wk, acc[0][0]);
+        } else {
+            rconv_steps<CIN, TN, CTH, NSTEP>(std::make_integer_sequence<int, NSTEP>{}, sP, la, half, wr, acc);
+        }
+        pconv_store<G_>(xs, c, n0, N, wm, wn, col, half, E, sBias, sHead, acc);
+    }
+}
+
+// conv_upcat_kernel for CU = 8, 16 or 32 skip and up channels, CL = 2 CU low-resolution channels and
+// N <= 32 outputs, the output twice lo's size; false: not handled
+template <class EP>
+inline bool run_conv_upcat(const Act &xs, const Act &lo, const bf16_t *uw, const float *ub, const WeightB &w,
+                           const EP &e, int CU, int CL, int N, int cu_count, hipStream_t st, hipError_t &err)
+{
+    if (N > 32 || CL != 2 * CU || xs.B != lo.B || xs.H != 2 * lo.H || xs.W != 2 * lo.W) return false;
+    const int tiles = xs.B * ((xs.H + 3) / 4) * ((xs.W + CT_W - 1) / CT_W);
+    auto go = [&](auto kernel) {
+        int per_cu = 0;
+        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0);
+        if (err != hipSuccess) return;
+        const int wgs = std::min(tiles, std::max(1, per_cu) * cu_count);
+        kernel<<<dim3(wgs, 1), 256, 0, st>>>(xs, lo, uw, ub, w, e, N, tiles);
+        err = hipGetLastError();
+    };
+    switch (CU) {
+    case 8: go(conv_upcat_kernel<8, 16, EP>); return true;
+    case 16: go(conv_upcat_kernel<16, 32, EP>); return true;
+    case 32: go(conv_upcat_kernel<32, 64, EP>); return true;
+    default: return false;
+    }
+}
+
 // wave layout of the general form's CTH x 32-pixel, TN-channel tile: each wavefront owns one column
 // block of 32 output channels (WN = min(4, TN / 32)) and CTH / WM consecutive tile rows (BM)
 template <int TN, int CTH>
@@ -887,6 +1106,97 @@ void up2x2_kernel(Act x, const bf16_t *w, const float *bias, int lgc, bf16_t *y,
     }
 }
 
+// The up-sampling for inputs too wide for an LDS patch beside the weights (CIN = 256): wavefront w owns
+// tile row w, so no patch operand is shared between wavefronts and each lane loads its pixel's B operands
+// (channels 16 S + 8 half .. + 7 of every K step S) straight from memory, the next two tiles' in flight in
+// registers; the weights of the TN = 128 outputs (four column blocks per wavefront) are staged in LDS once
+// and the epilogue is up2x2_kernel's.  No barrier after the weights: the tiles share nothing in LDS.
+template <int CIN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void up2x2_wide_kernel(Act x, const bf16_t *w, const float *bias, int lgc, bf16_t *y, int ycs, int yco, int N,
+                       int tiles)
+{
+    constexpr int TN = 128, CTH = 4, BN = TN / 32, CPX = CIN / 8, WS = up_ws(CPX), NS = CIN / 16;
+    static_assert(CIN % 16 == 0, "whole MFMA K steps");
+    __shared__ uint4 sW[TN * WS];
+    __shared__ float4 sBias[TN / 4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 31, half = lane >> 5;
+    const int n0 = blockIdx.y * TN;
+    const int cmask = (1 << lgc) - 1;
+    for (int i = threadIdx.x; i < TN * CPX; i += 256) {
+        const int n = i / CPX, c8 = i - n * CPX;
+        sW[n * WS + c8] = n0 + n < N ? ld8(w + (int64_t)(n0 + n) * CIN + 8 * c8) : zero8();
+    }
+    if (threadIdx.x < TN) ((float *)sBias)[threadIdx.x] = n0 + (int)threadIdx.x < N ? bias[(n0 + threadIdx.x) & cmask] : 0.0f;
+    __syncthreads();
+    uint4 pa[NS], pb[NS];
+    auto load = [&](uint4 (&pv)[NS], int t) {
+        if (t >= tiles) return;
+        const ConvTile c = conv_tile<CTH>(x, t);
+        const int yy = c.y0 + wave, xx = c.x0 + col;
+        const bool in = yy < x.H && xx < x.W;
+        const bf16_t *src = x.p + ((int64_t)(c.b * x.H + (in ? yy : 0)) * x.W + (in ? xx : 0)) * x.cs + x.co + 8 * half;
+#pragma unroll
+        for (int S = 0; S < NS; ++S) pv[S] = in ? ld8(src + 16 * S) : zero8();
+    };
+    int lw[BN];
+#pragma unroll
+    for (int j = 0; j < BN; ++j) lw[j] = (j * 32 + col) * WS + half;
+    const int H2 = 2 * x.H, W2 = 2 * x.W;
+
+    auto tile = [&](uint4 (&pv)[NS], int t) {
+        // a compiler memory barrier: the weight reads below stay in the loop (hoisted out of it, as loop
+        // invariants, they would need 64 registers per K step)
+        asm volatile("" ::: "memory");
+        f32x16 acc[BN];
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[j][q] = 0.0f;
+#pragma unroll
+        for (int S = 0; S < NS; ++S)
+#pragma unroll
+            for (int j = 0; j < BN; ++j) {
+                const uint4 wv = sW[lw[j] + 2 * S];
+                acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8 *)&wv, *(const bf16x8 *)&pv[S], acc[j],
+                                                                 0, 0, 0);
+            }
+        load(pv, t + 2 * (int)gridDim.x);   // in flight while the next tile is summed
+        const ConvTile c = conv_tile<CTH>(x, t);
+        const int yy = c.y0 + wave, xx = c.x0 + col;
+        const bool in = yy < x.H && xx < x.W;
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+#pragma unroll
+            for (int g = 0; g < 4; g += 2) {
+                const int nb = j * 32 + 8 * g;
+                uint2 r[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float4 bb = sBias[(nb + 8 * h + 4 * half) >> 2];
+                    const float a0 = acc[j][4 * (g + h)], a1 = acc[j][4 * (g + h) + 1];
+                    const float a2 = acc[j][4 * (g + h) + 2], a3 = acc[j][4 * (g + h) + 3];
+                    r[h] = make_uint2(pack_bf16x2(fmaxf(a0 + bb.x, 0.0f), fmaxf(a1 + bb.y, 0.0f)),
+                                      pack_bf16x2(fmaxf(a2 + bb.z, 0.0f), fmaxf(a3 + bb.w, 0.0f)));
+                }
+                const uint4 o = gather8(r[0], r[1]);
+                const int n = n0 + nb + 8 * half;   // eight channels of one sub-pixel d (cout >= 8)
+                if (!in || n >= N) continue;
+                const int d = n >> lgc, co = n & cmask;
+                const int m2 = (c.b * H2 + 2 * yy + (d >> 1)) * W2 + 2 * xx + (d & 1);
+                *(uint4 *)(y + (int64_t)m2 * ycs + yco + co) = o;
+            }
+    };
+    const int G = gridDim.x;
+    load(pa, blockIdx.x);
+    load(pb, blockIdx.x + G);
+    for (int t = blockIdx.x; t < tiles; t += 2 * G) {
+        tile(pa, t);
+        if (t + G < tiles) tile(pb, t + G);
+    }
+}
+
 // the up-sampling by the kernel above for the channel counts it is built for; false: not handled
 inline bool run_up2x2(const Act &x, const bf16_t *w, const float *bias, int cin, int cout, bf16_t *y, int ycs, int yco,
                       int cu_count, hipStream_t st, hipError_t &err)
@@ -915,6 +1225,10 @@ inline bool run_up2x2(const Act &x, const bf16_t *w, const float *bias, int cin,
         PYHST_UP_CASE(32)
         PYHST_UP_CASE(64)
         PYHST_UP_CASE(128)
+    case 256:
+        if (tn != 128) return false;
+        go(up2x2_wide_kernel<256>);
+        return true;
     default: return false;
     }
 #undef PYHST_UP_CASE

@@ -124,6 +124,29 @@ def test_data_scale_inside_the_network(dev):
         a.set_scale(0.0)
 
 
+@pytest.mark.parametrize("base,levels,H,W", [(32, 4, 48, 80), (16, 3, 32, 72), (8, 4, 40, 56)])
+def test_inference_upsampling_fused_into_decoder_conv(dev, base, levels, H, W):
+    """Inference runs a decoder level's up-sampling inside its first conv wherever that conv has at most
+    32 inputs from each side and 32 outputs (the concatenation is never stored there): its output equals
+    the unfused up-sampling + conv of the training forward bit for bit at every level, on ragged tiles."""
+    B = 2
+    p = case_params(base, levels, 7)
+    rng = np.random.default_rng(11)
+    x = rng.random((B, H, W)).astype(np.float32)
+    t = (x + 0.1 * rng.standard_normal((B, H, W))).astype(np.float32)
+    net = UNet(B, H, W, base, levels)
+    net.set_params(p)
+    xt, tt = torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev)
+    out = net.forward(xt)
+    torch.cuda.synchronize()
+    fused = [net.tensor("da", l).clone() for l in range(levels - 1)]
+    net.backward(xt, tt)   # training forward: up-sampling kernel, concatenation, conv
+    torch.cuda.synchronize()
+    for l in range(levels - 1):
+        assert torch.equal(fused[l], net.tensor("da", l)), l
+    assert torch.isfinite(out).all()
+
+
 def test_every_layer_teacher_forced(dev):
     """Each layer of the GPU U-Net against the oracle's layer fed with the GPU's own BF16
     inputs (no compounding of rounding differences across layers): forward activations,

@@ -616,6 +616,158 @@ def test_up2x2_replay(cin, cout, H, W):
     assert (hit == 1).all()
 
 
+@pytest.mark.parametrize("cin,cout,H,W", [(256, 128, 8, 64), (256, 128, 5, 40), (256, 32, 3, 33)])
+def test_up2x2_wide_replay(cin, cout, H, W):
+    """The up-sampling for 256 input channels: wavefront w holds tile row w, lane (col, half) loads channels
+    16 S + 8 half .. + 7 of pixel (y0 + w, x0 + col) as its B operand of K step S and reads weight slot
+    (32 j + col) WS + half + 2 S = U[n0 + 32 j + col][16 S + 8 half ..] for column block j; the epilogue
+    sends (pixel, n = d cout + co) to output pixel (2y + d / 2, 2x + d % 2), channel co, covering every
+    output value exactly once over the N / 128 workgroup columns."""
+    rng = np.random.default_rng(cin + W + cout)
+    B, N, TN = 2, 4 * cout, 128
+    CPX = cin // 8
+    WS = _up_ws(CPX)
+    U = rng.integers(1, 1000, (N, cin))
+    lgc = cout.bit_length() - 1
+    hit = np.zeros((B, 2 * H, 2 * W, cout), dtype=np.int64)
+    tiles_x, tiles_y = -(-W // CT_W), -(-H // 4)
+    for n0 in range(0, N, TN):
+        sW = np.full((TN * WS, 8), -1, dtype=np.int64)
+        for i in range(TN * CPX):
+            n, c8 = divmod(i, CPX)
+            sW[n * WS + c8] = U[n0 + n, 8 * c8:8 * c8 + 8] if n0 + n < N else 0
+        for lane in range(64):
+            col, half = lane & 31, lane >> 5
+            for j in range(TN // 32):
+                lw = (j * 32 + col) * WS + half
+                for S in range(cin // 16):
+                    nn = n0 + j * 32 + col
+                    ref = U[nn, 16 * S + 8 * half:16 * S + 8 * half + 8] if nn < N else np.zeros(8)
+                    assert np.array_equal(sW[lw + 2 * S], ref)
+        for t in range(B * tiles_x * tiles_y):
+            b, r = divmod(t, tiles_x * tiles_y)
+            y0, x0 = (r // tiles_x) * 4, (r % tiles_x) * CT_W
+            for wave in range(4):
+                for lane in range(64):
+                    col, half = lane & 31, lane >> 5
+                    yy, xx = y0 + wave, x0 + col
+                    if yy >= H or xx >= W:
+                        continue
+                    for j in range(TN // 32):
+                        for g in (0, 2):
+                            n = n0 + j * 32 + 8 * g + 8 * half
+                            if n >= N:
+                                continue
+                            d, co = n >> lgc, n & (cout - 1)
+                            assert (n + 7) >> lgc == d
+                            hit[b, 2 * yy + (d >> 1), 2 * xx + (d & 1), co:co + 8] += 1
+    assert (hit == 1).all()
+
+
+@pytest.mark.parametrize("CU,H,W", [(32, 8, 64), (32, 12, 40), (16, 8, 34), (8, 4, 70)])
+def test_conv_upcat_replay(CU, H, W):
+    """The decoder conv with the up-sampling inside it: per 4 x 32 output tile, staged vector i of thread
+    tid (i = tid + 256 v) is skip vector i (patch pixel i / CSX, chunk i % CSX) or footprint vector
+    i - NSS (low-resolution pixel ((y0 / 2) - 1 + fr, (x0 / 2) - 1 + fc)), every slot written once and
+    zero outside the image.  Wavefront d = (dy, dx) sums parity pixel e = 32 blk + col (e < 51): its B
+    operand at K step s is the footprint slot of the low-resolution pixel (Y / 2, X / 2) of patch pixel
+    (Y, X) = (y0 - 1 + 2 (e / 17) + 1 - dy, x0 - 1 + 2 (e % 17) + 1 - dx), channels 16 s + 8 half; its
+    outputs (after the half-wave exchange) fill up-channel group g + half of that patch pixel, so every
+    (patch pixel, up group) is written exactly once.  With CU = 32 the conv's K step S reads its weights
+    from register tap (CU / 16) + c8 / 2 (skip half) or LDS slot n WSU + tap CSX + c8 - CSX + half (up
+    half), both holding W[n][16 S + 8 half ..]."""
+    CL, CIN = 2 * CU, 2 * CU
+    CSX, CLX, CPP, LPP = CU // 8, CL // 8, (CIN // 8) | 1, (CL // 8) | 1
+    FH, FW, PC, NE = 4, 18, 17, 51
+    PIX, PW = 6 * CT_PW, CT_PW
+    NSS, NLS = PIX * CSX, FH * FW * CLX
+    NV = -(-(NSS + NLS) // 256)
+    rng = np.random.default_rng(CU + W)
+    B = 2
+    Hl, Wl = H // 2, W // 2
+    Xs = rng.integers(1, 1000, (B, H, W, CU))
+    Lo = rng.integers(1, 1000, (B, Hl, Wl, CL))
+    tiles_x, tiles_y = -(-W // CT_W), -(-H // 4)
+    for t in range(B * tiles_x * tiles_y):
+        b, r = divmod(t, tiles_x * tiles_y)
+        y0, x0 = (r // tiles_x) * 4, (r % tiles_x) * CT_W
+        sP = np.full((PIX * CPP, 8), -1, dtype=np.int64)
+        sL = np.full((FH * FW * LPP, 8), -1, dtype=np.int64)
+        cntP = np.zeros(PIX * CPP, dtype=np.int64)
+        cntL = np.zeros(FH * FW * LPP, dtype=np.int64)
+        for tid in range(256):
+            for v in range(NV):
+                i = tid + 256 * v
+                if i < NSS:
+                    p, c8 = divmod(i, CSX)
+                    py, px = divmod(p, PW)
+                    pos, dst = (py << 16) | (px << 8) | c8, p * CPP + c8
+                else:
+                    k = i - NSS
+                    f, c8 = divmod(k, CLX)
+                    fr, fc = divmod(f, FW)
+                    pos, dst = ((1 << 24) | (fr << 16) | (fc << 8) | c8) if k < NLS else -1, f * LPP + c8
+                if pos < 0:
+                    continue
+                rr, qq, c8 = (pos >> 16) & 255, (pos >> 8) & 255, pos & 255
+                if pos >> 24:
+                    yy, xx = (y0 >> 1) - 1 + rr, (x0 >> 1) - 1 + qq
+                    val = Lo[b, yy, xx, 8 * c8:8 * c8 + 8] if (0 <= yy < Hl and 0 <= xx < Wl) else 0
+                    assert 0 <= dst < sL.shape[0]
+                    sL[dst] = val
+                    cntL[dst] += 1
+                else:
+                    yy, xx = y0 - 1 + rr, x0 - 1 + qq
+                    val = Xs[b, yy, xx, 8 * c8:8 * c8 + 8] if (0 <= yy < H and 0 <= xx < W) else 0
+                    assert 0 <= dst < sP.shape[0]
+                    sP[dst] = val
+                    cntP[dst] += 1
+        for p in range(PIX):
+            assert (cntP[p * CPP:p * CPP + CSX] == 1).all()
+        for f in range(FH * FW):
+            assert (cntL[f * LPP:f * LPP + CLX] == 1).all()
+        written = np.zeros((PIX, CSX), dtype=np.int64)
+        for d in range(4):
+            dy, dx = d >> 1, d & 1
+            for blk in range(2):
+                for lane in range(64):
+                    col, half = lane & 31, lane >> 5
+                    e = 32 * blk + col
+                    ee = min(e, NE - 1)
+                    r3, c17 = divmod(ee, PC)
+                    py, px = 2 * r3 + 1 - dy, 2 * c17 + 1 - dx
+                    lb = ((r3 + 1 - dy) * FW + c17 + 1 - dx) * LPP + half
+                    Y, X = y0 - 1 + py, x0 - 1 + px
+                    live = 0 <= Y < H and 0 <= X < W
+                    assert 0 <= py < 6 and 0 <= px < PW
+                    if e < NE:
+                        assert ((Y & 1), (X & 1)) == (dy, dx)
+                    for s_ in range(CL // 16):
+                        assert 0 <= lb + 2 * s_ < sL.shape[0]
+                        if e < NE and live:
+                            assert np.array_equal(sL[lb + 2 * s_], Lo[b, Y >> 1, X >> 1, 16 * s_ + 8 * half:16 * s_ + 8 * half + 8])
+                    for g in (0, 2):
+                        grp = g + half
+                        if e < NE and grp < CSX:
+                            written[py * PW + px, grp] += 1
+        assert (written == 1).all()
+    if CU == 32:
+        WSU = _conv_ws(CSX)
+        nr = 9 * (CU // 16)
+        reg_step = [(r // (CU // 16)) * (CIN // 16) + r % (CU // 16) for r in range(nr)]
+        for S in range(9 * CIN // 16):
+            tap, c8 = (16 * S) // CIN, ((16 * S) % CIN) // 8
+            for half in range(2):
+                k = 16 * S + 8 * half
+                if c8 < CSX:
+                    assert reg_step[tap * (CU // 16) + c8 // 2] == S
+                else:
+                    slot = tap * CSX + c8 - CSX + half        # LDS slot within row n
+                    stap, u8 = divmod(slot, CSX)
+                    assert 0 <= slot < 9 * CSX < WSU
+                    assert stap * CIN + CU + 8 * u8 == k
+
+
 # ------------------------------------------------------------------ fused ROF dual steps
 FTX, FTY = 64, 16
 FRX, FRY = FTX + 4, FTY + 4
