@@ -367,8 +367,8 @@ __global__ __launch_bounds__(256) void fp_lines_kernel(Tables T, const float *__
 // which 256 threads stage with 16-wide contiguous reads along the image rows in both walking
 // directions (so a column-walking projection reads rows of 16 neighbouring columns rather than 64
 // separate rows).  The next block is loaded into registers while the current one is summed from the
-// other LDS buffer: one barrier per block.  Wavefront w sums lines w, w + 4, ... of every block for
-// each projection of the group; the four partial sums are added in a fixed order through LDS.
+// other LDS buffer: one barrier per block.  Each wavefront serves one projection of the group on every
+// (4 / group size)-th line of a block (fp_staged_body_wp).
 template <int NC> struct FpStaged {
     static constexpr int SEG = NC == 3 ? FP_SSEG3 : FP_SSEG6;   // positions staged per line
     static constexpr int LD = SEG + 17;               // LDS row stride: 17 mod 32 spreads the banks
@@ -434,133 +434,15 @@ __device__ __forceinline__ StagedProj staged_proj(const Tables &T, const GeoDev 
     return q;
 }
 
-template <int MODE, int NC, bool UNIT, int P>
-__device__ __forceinline__ void fp_staged_body(const Tables &T, const SliceDev &sd, const GeoDev &g,
-                                               const StagedProj *pr, bool rows, int j, const float *img,
-                                               float *out, float alpha, const CpDual &cp, int slice,
-                                               float (*stage)[FP_RB * FpStaged<NC>::LD], float (*part)[3][64])
-{
-    using F = FpStaged<NC>;
-    const int nb = g.nb, nx = g.nx, ny = g.ny;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int n_lines = rows ? ny : nx, n_pos = rows ? nx : ny;
-    const float *im = img + sd.img_off;
-    // staging map: 16 consecutive threads read 16 consecutive floats of one image row
-    const int sr = rows ? tid >> 4 : tid & 15;     // staged line within the block
-    const int sp = rows ? tid & 15 : tid >> 4;     // first staged position of this thread
-    // 32-bit offsets inside one slice (the plan keeps n_x n_y below 2^31)
-    const int step_line = rows ? nx : 1, step_pos = rows ? 1 : nx;
-    const int n_blk = (n_lines + FP_RB - 1) / FP_RB;
-
-    float v[F::PER];
-    auto load = [&](int b, int &seg0) {
-        const int l0 = b * FP_RB;
-        double lo = fma((double)l0, pr[0].slope, pr[0].blk_lo);
-#pragma unroll
-        for (int p = 1; p < P; ++p) lo = fmin(lo, fma((double)l0, pr[p].slope, pr[p].blk_lo));
-        seg0 = (int)floor(lo) - 2;
-        const int line = l0 + sr;
-        if (line < n_lines && seg0 >= 0 && seg0 + F::SEG <= n_pos) {
-            // the whole staged segment lies inside the image (most blocks): no per-element test
-            const float *src = im + (line * step_line + (seg0 + sp) * step_pos);
-            const int d16 = 16 * step_pos;
-#pragma unroll
-            for (int i = 0; i < F::PER; ++i) v[i] = src[i * d16];
-        } else {
-#pragma unroll
-            for (int i = 0; i < F::PER; ++i) {
-                const int pos = seg0 + sp + 16 * i;
-                v[i] = (line < n_lines && (unsigned)pos < (unsigned)n_pos) ? im[line * step_line + pos * step_pos] : 0.0f;
-            }
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < F::PER; ++i) stage[buf][sr * F::LD + sp + 16 * i] = v[i];
-    };
-
-    float acc[P][FP_RB / 4];
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-#pragma unroll
-        for (int m = 0; m < FP_RB / 4; ++m) acc[p][m] = 0.0f;
-    int seg_cur, seg_next = 0;
-    load(0, seg_cur);
-    store(0);
-    __syncthreads();
-    for (int b = 0; b < n_blk; ++b) {
-        const bool more = b + 1 < n_blk;
-        if (more) load(b + 1, seg_next);
-        const int l0 = b * FP_RB;
-        // per projection: FP64 anchor of this lane and block, then this wavefront's first line (the
-        // others sit at constant LDS offsets from it)
-        float remv[P];
-        const float *base[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const double ub = fma((double)l0, pr[p].slope, pr[p].u_first);
-            const double ubase = floor(ub);
-            remv[p] = (float)(ub - ubase - pr[p].rho);         // u - 1/|a| at the block's first line
-            base[p] = stage[b & 1] + ((int)ubase - seg_cur) + wv * F::LD;
-        }
-        // one accumulation chain per (projection, line slot m): the chains of a block are independent, so
-        // the reads of all its lines (and of every projection of the group) issue together
-        if (l0 + FP_RB <= n_lines) {
-            // a whole block: no branch between the lines
-#pragma unroll
-            for (int p = 0; p < P; ++p)
-#pragma unroll
-                for (int m = 0; m < FP_RB / 4; ++m)
-                    acc[p][m] = staged_line<NC, UNIT>(base[p] + 4 * m * F::LD,
-                                                      fmaf((float)(wv + 4 * m), pr[p].slopef, remv[p]), pr[p], acc[p][m]);
-        } else {
-#pragma unroll
-            for (int p = 0; p < P; ++p)
-#pragma unroll
-                for (int m = 0; m < FP_RB / 4; ++m) {
-                    const int r = wv + 4 * m;
-                    if (l0 + r >= n_lines) break;             // uniform
-                    acc[p][m] = staged_line<NC, UNIT>(base[p] + 4 * m * F::LD, fmaf((float)r, pr[p].slopef, remv[p]),
-                                                      pr[p], acc[p][m]);
-                }
-        }
-        if (more) {
-            store((b + 1) & 1);
-            seg_cur = seg_next;
-        }
-        __syncthreads();
-    }
-    float tot[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        tot[p] = acc[p][0];
-#pragma unroll
-        for (int m = 1; m < FP_RB / 4; ++m) tot[p] += acc[p][m];
-    }
-    if (wv > 0) {
-#pragma unroll
-        for (int p = 0; p < P; ++p) part[p][wv - 1][lane] = tot[p];
-    }
-    __syncthreads();
-    if (wv > 0 || j >= nb) return;
-    const float sc = alpha * (float)(g.s * g.s);   // A = s^2 B^T
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const float sum = ((tot[p] + part[p][0][lane]) + part[p][1][lane]) + part[p][2][lane];
-        const int64_t o = sd.sino_off + (int64_t)pr[p].k * nb + j;
-        fp_store<MODE>(cp, out, o, sc * sum, (int64_t)slice * nb + j);
-    }
-}
-
 // Groups of one, two or four projections: 4 / P wavefronts per projection, wavefront w serving projection
 // w / (4 / P) on lines w % (4 / P), + 4 / P, ... of every block (16, 8 or 4 lines).  The crossing is
-// anchored in FP64 once per (lane, block) for the wavefront's one projection, so a group of four pays a
-// quarter of the anchors of fp_staged_body; partial sums of a projection's wavefronts are added in a fixed
-// order through LDS.  Staging, segment and line arithmetic as in fp_staged_body.
+// anchored in FP64 once per (lane, block) for the wavefront's one projection (a quarter of the anchors
+// of every wavefront serving every projection); partial sums of a projection's wavefronts are added in a
+// fixed order through LDS.  A group of n = 3 runs as P = 4 with pr[3] = pr[0]: the last wavefront repeats
+// the first projection and stores nothing.
 template <int MODE, int NC, bool UNIT, int P>
 __device__ __forceinline__ void fp_staged_body_wp(const Tables &T, const SliceDev &sd, const GeoDev &g,
-                                                  const StagedProj *pr, bool rows, int j, const float *img,
+                                                  const StagedProj *pr, int n, bool rows, int j, const float *img,
                                                   float *out, float alpha, const CpDual &cp, int slice,
                                                   float (*stage)[FP_RB * FpStaged<NC>::LD], float (*part)[3][64])
 {
@@ -628,11 +510,10 @@ __device__ __forceinline__ void fp_staged_body_wp(const Tables &T, const SliceDe
                                                    acc[k & 3]);
         } else {
 #pragma unroll
-            for (int k = 0; k < LPW; ++k) {
-                if (l0 + ph + WPP * k >= n_lines) break;              // uniform
-                acc[k & 3] = staged_line<NC, UNIT>(base + k * WPP * F::LD, fmaf((float)(ph + WPP * k), q.slopef, remv), q,
-                                                   acc[k & 3]);
-            }
+            for (int k = 0; k < LPW; ++k)   // no break: the loop stays unrolled and acc in registers
+                if (l0 + ph + WPP * k < n_lines)                      // uniform
+                    acc[k & 3] = staged_line<NC, UNIT>(base + k * WPP * F::LD, fmaf((float)(ph + WPP * k), q.slopef, remv),
+                                                       q, acc[k & 3]);
         }
         if (more) {
             store((b + 1) & 1);
@@ -648,7 +529,7 @@ __device__ __forceinline__ void fp_staged_body_wp(const Tables &T, const SliceDe
 #pragma unroll
         for (int m = 1; m < WPP; ++m) tot += part[pw][m - 1][lane];
     }
-    if (j >= nb) return;
+    if (j >= nb || pw >= n) return;
     const int64_t o = sd.sino_off + (int64_t)q.k * nb + j;
     fp_store<MODE>(cp, out, o, alpha * (float)(g.s * g.s) * tot, (int64_t)slice * nb + j);
 }
@@ -684,16 +565,207 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
     StagedProj pr[FP_SGRP];
     pr[0] = staged_proj(T, g, kk[0], j, j0, rows);
 #pragma unroll
-    for (int m = 1; m < FP_SGRP; ++m)
-        if (m < n) pr[m] = staged_proj(T, g, kk[m], j, j0, rows_m);   // same walking axis (the plan groups only such)
-    if (GMAX > 2 && n == 4) {   // uniform over the workgroup
-        fp_staged_body_wp<MODE, NC, UNIT, 4>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
-    } else if (GMAX > 2 && n == 3) {
-        fp_staged_body<MODE, NC, UNIT, 3>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
+    for (int m = 1; m < FP_SGRP; ++m) {
+        // same walking axis (the plan groups only such); members past n repeat the first
+        if (m < n) pr[m] = staged_proj(T, g, kk[m], j, j0, rows_m);
+        else pr[m] = pr[0];
+    }
+    if (GMAX > 2 && n >= 3) {   // uniform over the workgroup
+        fp_staged_body_wp<MODE, NC, UNIT, 4>(T, sd, g, pr, n, rows, j, img, out, alpha, cp, slice, stage, part);
     } else if (n == 2) {
-        fp_staged_body_wp<MODE, NC, UNIT, 2>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
+        fp_staged_body_wp<MODE, NC, UNIT, 2>(T, sd, g, pr, n, rows, j, img, out, alpha, cp, slice, stage, part);
     } else {
-        fp_staged_body_wp<MODE, NC, UNIT, 1>(T, sd, g, pr, rows, j, img, out, alpha, cp, slice, stage, part);
+        fp_staged_body_wp<MODE, NC, UNIT, 1>(T, sd, g, pr, n, rows, j, img, out, alpha, cp, slice, stage, part);
+    }
+}
+
+// Two slices of a uniform plan per workgroup (slices 2 z and 2 z + 1; pixels of 2/3 to 1 bin, three
+// candidates): the staged segment holds both slices' values of a position side by side, so one 8-byte LDS
+// read serves both, and a line's position, floor, fraction and three hat weights are computed once for
+// the two slices (about 7.5 instead of 12 VALU instructions per line and slice).  Each slice's sums are
+// staged_line's, term for term in the same order, so every value equals fp_staged_body_wp's.  Groups of
+// three run as groups of four whose last wavefronts repeat the first projection and store nothing.
+__device__ __forceinline__ float2 staged_line2(const float2 *line, float v, const StagedProj &q, float2 acc)
+{
+    int fl;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(fl) : "v"(v));
+    const float f = __builtin_amdgcn_fractf(v);
+    const float2 *row = line + fl + 1;
+    const float w0 = fmaf(-q.aa, f, q.aa);
+    const float w1 = 1.0f - fabsf(fmaf(-q.aa, f, q.c1));
+    const float w2 = __builtin_amdgcn_fmed3f(fmaf(q.aa, f, q.c2), 0.0f, 1.0f);
+    const float2 r0 = row[0], r1 = row[1], r2 = row[2];
+    acc.x = fmaf(w0, r0.x, acc.x);
+    acc.y = fmaf(w0, r0.y, acc.y);
+    acc.x = fmaf(w1, r1.x, acc.x);
+    acc.y = fmaf(w1, r1.y, acc.y);
+    acc.x = fmaf(w2, r2.x, acc.x);
+    acc.y = fmaf(w2, r2.y, acc.y);
+    return acc;
+}
+
+// One LDS buffer (the two-slice segment is twice the one-slice kernel's): the next block waits in
+// registers while the current one is summed, then two barriers around its store; the partial sums of
+// the last step reuse the buffer.  The group's segment bound needs only each member's slope and lowest
+// candidate (the same for every lane), the sums only the wavefront's own projection q.
+struct SegBound {   // slope and lowest first candidate of each member of a staged group
+    double s0, b0, s1, b1, s2, b2, s3, b3;
+};
+
+template <int MODE, int P>
+__device__ __forceinline__ void fp_staged2_body(const SliceDev &sd0, const SliceDev &sd1, bool two, const GeoDev &g,
+                                                const StagedProj &q, const SegBound &sb, int n,
+                                                bool rows, int j, const float *img, float *out, float alpha,
+                                                const CpDual &cp, int slice0, float2 *stage)
+{
+    using F = FpStaged<3>;
+    static_assert(P == 1 || P == 2 || P == 4, "whole wavefronts per projection");
+    static_assert(FP_SGRP * 3 * 64 <= FP_RB * F::LD, "partial sums fit the staging buffer");
+    constexpr int WPP = 4 / P, LPW = FP_RB / WPP;
+    const int nb = g.nb, nx = g.nx, ny = g.ny;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int pw = wv / WPP, ph = wv % WPP;
+    const int n_lines = rows ? ny : nx, n_pos = rows ? nx : ny;
+    const float *im0 = img + sd0.img_off, *im1 = img + sd1.img_off;
+    const int sr = rows ? tid >> 4 : tid & 15;
+    const int sp = rows ? tid & 15 : tid >> 4;
+    const int step_line = rows ? nx : 1, step_pos = rows ? 1 : nx;
+    const int n_blk = (n_lines + FP_RB - 1) / FP_RB;
+
+    float v0[F::PER], v1[F::PER];
+    auto load = [&](int b, int &seg0) {
+        const int l0 = b * FP_RB;
+        double lo = fma((double)l0, sb.s0, sb.b0);
+        if (P > 1) lo = fmin(lo, fma((double)l0, sb.s1, sb.b1));
+        if (P > 2) lo = fmin(fmin(lo, fma((double)l0, sb.s2, sb.b2)), fma((double)l0, sb.s3, sb.b3));
+        seg0 = (int)floor(lo) - 2;
+        const int line = l0 + sr;
+        if (line < n_lines && seg0 >= 0 && seg0 + F::SEG <= n_pos) {
+            const int off = line * step_line + (seg0 + sp) * step_pos;
+            const int d16 = 16 * step_pos;
+#pragma unroll
+            for (int i = 0; i < F::PER; ++i) {
+                v0[i] = im0[off + i * d16];
+                v1[i] = two ? im1[off + i * d16] : 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < F::PER; ++i) {
+                const int pos = seg0 + sp + 16 * i;
+                const bool in = line < n_lines && (unsigned)pos < (unsigned)n_pos;
+                const int off = in ? line * step_line + pos * step_pos : 0;
+                v0[i] = in ? im0[off] : 0.0f;
+                v1[i] = in && two ? im1[off] : 0.0f;
+            }
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int i = 0; i < F::PER; ++i) stage[sr * F::LD + sp + 16 * i] = make_float2(v0[i], v1[i]);
+    };
+
+    float2 acc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] = make_float2(0.0f, 0.0f);
+    int seg_cur, seg_next = 0;
+    load(0, seg_cur);
+    store();
+    __syncthreads();
+    for (int b = 0; b < n_blk; ++b) {
+        const bool more = b + 1 < n_blk;
+        if (more) load(b + 1, seg_next);
+        const int l0 = b * FP_RB;
+        const double ub = fma((double)l0, q.slope, q.u_first);
+        const double ubase = floor(ub);
+        const float remv = (float)(ub - ubase - q.rho);
+        const float2 *base = stage + ((int)ubase - seg_cur) + ph * F::LD;
+        if (l0 + FP_RB <= n_lines) {
+#pragma unroll
+            for (int k = 0; k < LPW; ++k)
+                acc[k & 3] = staged_line2(base + k * WPP * F::LD, fmaf((float)(ph + WPP * k), q.slopef, remv), q, acc[k & 3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < LPW; ++k)   // no break: the loop stays unrolled and acc in registers
+                if (l0 + ph + WPP * k < n_lines)                      // uniform
+                    acc[k & 3] = staged_line2(base + k * WPP * F::LD, fmaf((float)(ph + WPP * k), q.slopef, remv), q,
+                                              acc[k & 3]);
+        }
+        __syncthreads();   // every read of this block is done
+        if (more) {
+            store();
+            seg_cur = seg_next;
+            __syncthreads();
+        }
+    }
+    float2 tot = make_float2((acc[0].x + acc[1].x) + (acc[2].x + acc[3].x), (acc[0].y + acc[1].y) + (acc[2].y + acc[3].y));
+    if constexpr (WPP > 1) {
+        float2 *part = stage;   // [FP_SGRP][3][64], free after the last block's barrier
+        if (ph > 0) part[(pw * 3 + ph - 1) * 64 + lane] = tot;
+        __syncthreads();
+        if (ph > 0) return;
+#pragma unroll
+        for (int m = 1; m < WPP; ++m) {
+            const float2 o = part[(pw * 3 + m - 1) * 64 + lane];
+            tot.x += o.x;
+            tot.y += o.y;
+        }
+    }
+    if (j >= nb || pw >= n) return;
+    const float sc = alpha * (float)(g.s * g.s);
+    fp_store<MODE>(cp, out, sd0.sino_off + (int64_t)q.k * nb + j, sc * tot.x, (int64_t)slice0 * nb + j);
+    if (two) fp_store<MODE>(cp, out, sd1.sino_off + (int64_t)q.k * nb + j, sc * tot.y, (int64_t)(slice0 + 1) * nb + j);
+}
+
+// grid: (bin chunks, staged groups, slice pairs); GMAX as in fp_staged_kernel
+template <int MODE, int GMAX>
+__global__ __launch_bounds__(256) void fp_staged2_kernel(Tables T, const float *__restrict__ img,
+                                                         float *__restrict__ out, float alpha, CpDual cp, int n_slices)
+{
+    __shared__ float2 stage[FP_RB * FpStaged<3>::LD];
+    const int s0 = 2 * (int)blockIdx.z;
+    const bool two = s0 + 1 < n_slices;
+    const SliceDev sd0 = T.slc[s0], sd1 = T.slc[two ? s0 + 1 : s0];
+    const GeoDev &g = T.geo[sd0.g];
+    const int j0 = fp_chunk(blockIdx.x, gridDim.x) * 64;
+    if ((int)blockIdx.y >= g.fp_npair) return;       // uniform over the workgroup
+    const int4 grp = T.fp_pair[g.fp_pair_off + blockIdx.y];
+    if (j0 >= g.nb) return;                          // uniform over the workgroup
+    const int j = j0 + (int)(threadIdx.x & 63);
+    const int n = grp.y < 0 ? 1 : (grp.z < 0 ? 2 : (grp.w < 0 ? 3 : 4));   // members (the plan fills in order)
+    const int k1 = n > 1 ? grp.y : grp.x, k2 = n > 2 ? grp.z : grp.x, k3 = n > 3 ? grp.w : grp.x;
+    // this wavefront's projection (wave-uniform; members past n repeat the first) and every member's
+    // segment bound (scalars: no per-lane array)
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int P = (GMAX > 2 && n >= 3) ? 4 : (n == 2 ? 2 : 1);
+    const int pw = wv / (4 / P);
+    int kq = grp.x;
+    if (pw == 1) kq = k1;
+    if (pw == 2) kq = k2;
+    if (pw == 3) kq = k3;
+    bool rows, rows_m;
+    const StagedProj q = staged_proj(T, g, kq, j, j0, rows);
+    SegBound sb;
+    {
+        StagedProj e = staged_proj(T, g, grp.x, j, j0, rows_m);   // same walking axis for every member
+        sb.s0 = e.slope;
+        sb.b0 = e.blk_lo;
+        e = staged_proj(T, g, k1, j, j0, rows_m);
+        sb.s1 = e.slope;
+        sb.b1 = e.blk_lo;
+        e = staged_proj(T, g, k2, j, j0, rows_m);
+        sb.s2 = e.slope;
+        sb.b2 = e.blk_lo;
+        e = staged_proj(T, g, k3, j, j0, rows_m);
+        sb.s3 = e.slope;
+        sb.b3 = e.blk_lo;
+    }
+    if (P == 4) {   // uniform over the workgroup
+        fp_staged2_body<MODE, 4>(sd0, sd1, two, g, q, sb, n, rows, j, img, out, alpha, cp, s0, stage);
+    } else if (P == 2) {
+        fp_staged2_body<MODE, 2>(sd0, sd1, two, g, q, sb, n, rows, j, img, out, alpha, cp, s0, stage);
+    } else {
+        fp_staged2_body<MODE, 1>(sd0, sd1, two, g, q, sb, n, rows, j, img, out, alpha, cp, s0, stage);
     }
 }
 
@@ -728,6 +800,19 @@ hipError_t launch_fp_nc(const pyhst_plan &p, dim3 grid, const float *img, float 
     const dim3 g2(grid.x, MODE == 3 ? 1u : (unsigned)p.max_K, grid.z);
     if (kind == PYHST_FP_STAGED) {
         const dim3 gs(grid.x, MODE == 3 ? 1u : (unsigned)p.fp_max_pairs, grid.z);
+        if constexpr (NC == 3 && UNIT && MODE != 3) {
+            // automatic choice on a uniform plan of several slices: slice pairs, when they still give at
+            // least eight workgroups per CU
+            const int64_t pairs = (int64_t)gs.x * gs.y * ((gs.z + 1) / 2);
+            if (p.fp_kernel == PYHST_FP_AUTO && p.uniform && p.n_slices >= 2 && pairs >= 8 * (int64_t)p.cu_count) {
+                const dim3 gp(gs.x, gs.y, (gs.z + 1) / 2);
+                if (p.fp_max_grp > 2)
+                    fp_staged2_kernel<MODE, 4><<<gp, 256, 0, st>>>(p.t, img, sino, alpha, cp, p.n_slices);
+                else
+                    fp_staged2_kernel<MODE, 2><<<gp, 256, 0, st>>>(p.t, img, sino, alpha, cp, p.n_slices);
+                return hipGetLastError();
+            }
+        }
         if constexpr (NC > 0) {
             if (MODE != 3 && p.fp_max_grp > 2)
                 fp_staged_kernel<MODE, NC, UNIT, 4><<<gs, 256, 0, st>>>(p.t, img, sino, alpha, cp, 0);

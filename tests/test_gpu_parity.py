@@ -481,6 +481,29 @@ def test_fista_beats_ista_and_recovers_disc(dev):
     assert abs(xf[0].cpu().numpy()[inside].mean() - 1.0) < 0.03
 
 
+def test_fp_slice_pairs_equal_one_slice_kernel(dev, gen):
+    """The automatic projector choice on a uniform plan of several slices takes two slices per workgroup
+    (one staged segment and one set of hat weights for both); every value equals the one-slice staged
+    kernel's bit for bit: an odd slice count (the last workgroup holds one slice), groups of up to four
+    projections, the plain projection, the Chambolle-Pock dual update and the FISTA residual in the
+    projector's epilogue."""
+    N, K, S = 256, 720, 7
+    g, og = pair(nx=N, ny=N, nb=N, K=K, axis=128.2, shifts=0.3)
+    x = torch.from_numpy(gen.standard_normal((S, N, N)).astype(np.float32)).to(dev)
+    y = torch.from_numpy(gen.standard_normal((S, K, N)).astype(np.float32)).to(dev)
+    res = {}
+    for kind in (ph.FP_AUTO, ph.FP_STAGED):
+        plan = ph.Plan(g, n_slices=S)
+        plan.set_fp_kernel(kind)
+        fp = ph.forward_project(plan, x)
+        cp = ph.reconstruct_slices(plan, sino=y, method=ph.TV_CP, lam=0.01, n_iter=2, op_norm=400.0)
+        fi = ph.reconstruct_slices(plan, sino=y, method=ph.FISTA, lam=0.5, n_iter=2, op_norm=400.0, n_inner=4)
+        torch.cuda.synchronize()
+        res[kind] = (fp, cp, fi)
+    for a, b in zip(res[ph.FP_AUTO], res[ph.FP_STAGED]):
+        assert torch.equal(a, b)
+
+
 def test_fp_groups_of_four_parity(dev, gen):
     """A plan big enough for the staged projector's groups of four (8 slices x 256^2 x 720 angles with
     axis shifts: about 5800 workgroups, at least 16 per CU): the plain projection of every slice, and
