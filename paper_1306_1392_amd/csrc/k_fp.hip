@@ -579,46 +579,55 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
     }
 }
 
-// Two slices of a uniform plan per workgroup (slices 2 z and 2 z + 1; pixels of 2/3 to 1 bin, three
-// candidates): the staged segment holds both slices' values of a position side by side, so one 8-byte LDS
-// read serves both, and a line's position, floor, fraction and three hat weights are computed once for
-// the two slices (about 7.5 instead of 12 VALU instructions per line and slice).  Each slice's sums are
-// staged_line's, term for term in the same order, so every value equals fp_staged_body_wp's.  Groups of
-// three run as groups of four whose last wavefronts repeat the first projection and store nothing.
-__device__ __forceinline__ float2 staged_line2(const float2 *line, float v, const StagedProj &q, float2 acc)
+// SP = 2 or 4 slices of a uniform plan per workgroup (slices SP z .. SP z + SP - 1; pixels of 2/3 to 1
+// bin, three candidates): the staged segment holds the SP slices' values of a position side by side, so
+// one 8- or 16-byte LDS read serves them all, and a line's position, floor, fraction, address and three
+// hat weights are computed once for them (with two slices about 7.5 instead of 12 VALU instructions per
+// line and slice).  Each slice's sums are staged_line's, term for term in the same order, so every value
+// equals fp_staged_body_wp's.  Groups of three run as groups of four whose last wavefront repeats the
+// first projection and stores nothing.
+template <int SP> struct SliceVec;
+template <> struct SliceVec<2> { using T = float2; };
+template <> struct SliceVec<4> { using T = float4; };
+
+template <int SP>
+__device__ __forceinline__ void staged_line_sp(const float *line, float v, const StagedProj &q, float (&acc)[SP])
 {
+    using V = typename SliceVec<SP>::T;
     int fl;
     asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(fl) : "v"(v));
     const float f = __builtin_amdgcn_fractf(v);
-    const float2 *row = line + fl + 1;
-    const float w0 = fmaf(-q.aa, f, q.aa);
-    const float w1 = 1.0f - fabsf(fmaf(-q.aa, f, q.c1));
-    const float w2 = __builtin_amdgcn_fmed3f(fmaf(q.aa, f, q.c2), 0.0f, 1.0f);
-    const float2 r0 = row[0], r1 = row[1], r2 = row[2];
-    acc.x = fmaf(w0, r0.x, acc.x);
-    acc.y = fmaf(w0, r0.y, acc.y);
-    acc.x = fmaf(w1, r1.x, acc.x);
-    acc.y = fmaf(w1, r1.y, acc.y);
-    acc.x = fmaf(w2, r2.x, acc.x);
-    acc.y = fmaf(w2, r2.y, acc.y);
-    return acc;
+    const float *row = line + SP * (fl + 1);
+    const float w[3] = {fmaf(-q.aa, f, q.aa), 1.0f - fabsf(fmaf(-q.aa, f, q.c1)),
+                        __builtin_amdgcn_fmed3f(fmaf(q.aa, f, q.c2), 0.0f, 1.0f)};
+    V r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c] = *(const V *)(row + SP * c);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float *rv = (const float *)&r[c];
+#pragma unroll
+        for (int t = 0; t < SP; ++t) acc[t] = fmaf(w[c], rv[t], acc[t]);
+    }
 }
 
-// One LDS buffer (the two-slice segment is twice the one-slice kernel's): the next block waits in
-// registers while the current one is summed, then two barriers around its store; the partial sums of
-// the last step reuse the buffer.  The group's segment bound needs only each member's slope and lowest
-// candidate (the same for every lane), the sums only the wavefront's own projection q.
 struct SegBound {   // slope and lowest first candidate of each member of a staged group
     double s0, b0, s1, b1, s2, b2, s3, b3;
 };
 
-template <int MODE, int P>
-__device__ __forceinline__ void fp_staged2_body(const SliceDev &sd0, const SliceDev &sd1, bool two, const GeoDev &g,
-                                                const StagedProj &q, const SegBound &sb, int n,
-                                                bool rows, int j, const float *img, float *out, float alpha,
-                                                const CpDual &cp, int slice0, float2 *stage)
+// One LDS buffer (the segment is SP times the one-slice kernel's): the next block waits in registers
+// while the current one is summed, then two barriers around its store; the partial sums of the last
+// step reuse the buffer.  The group's segment bound needs only each member's slope and lowest candidate
+// (the same for every lane), the sums only the wavefront's own projection q.  ns: slices present (the
+// last workgroup of a plan whose slice count SP does not divide holds fewer).
+template <int MODE, int SP, int P>
+__device__ __forceinline__ void fp_staged_sp_body(const Tables &T, int slice0, int ns, const GeoDev &g,
+                                                  const StagedProj &q, const SegBound &sb, int n, bool rows, int j,
+                                                  const float *img, float *out, float alpha, const CpDual &cp,
+                                                  float *stage)
 {
     using F = FpStaged<3>;
+    using V = typename SliceVec<SP>::T;
     static_assert(P == 1 || P == 2 || P == 4, "whole wavefronts per projection");
     static_assert(FP_SGRP * 3 * 64 <= FP_RB * F::LD, "partial sums fit the staging buffer");
     constexpr int WPP = 4 / P, LPW = FP_RB / WPP;
@@ -627,13 +636,15 @@ __device__ __forceinline__ void fp_staged2_body(const SliceDev &sd0, const Slice
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int pw = wv / WPP, ph = wv % WPP;
     const int n_lines = rows ? ny : nx, n_pos = rows ? nx : ny;
-    const float *im0 = img + sd0.img_off, *im1 = img + sd1.img_off;
+    const float *im[SP];
+#pragma unroll
+    for (int t = 0; t < SP; ++t) im[t] = img + T.slc[slice0 + (t < ns ? t : 0)].img_off;
     const int sr = rows ? tid >> 4 : tid & 15;
     const int sp = rows ? tid & 15 : tid >> 4;
     const int step_line = rows ? nx : 1, step_pos = rows ? 1 : nx;
     const int n_blk = (n_lines + FP_RB - 1) / FP_RB;
 
-    float v0[F::PER], v1[F::PER];
+    float vv[SP][F::PER];
     auto load = [&](int b, int &seg0) {
         const int l0 = b * FP_RB;
         double lo = fma((double)l0, sb.s0, sb.b0);
@@ -645,29 +656,36 @@ __device__ __forceinline__ void fp_staged2_body(const SliceDev &sd0, const Slice
             const int off = line * step_line + (seg0 + sp) * step_pos;
             const int d16 = 16 * step_pos;
 #pragma unroll
-            for (int i = 0; i < F::PER; ++i) {
-                v0[i] = im0[off + i * d16];
-                v1[i] = two ? im1[off + i * d16] : 0.0f;
-            }
+            for (int i = 0; i < F::PER; ++i)
+#pragma unroll
+                for (int t = 0; t < SP; ++t) vv[t][i] = t < ns ? im[t][off + i * d16] : 0.0f;
         } else {
 #pragma unroll
             for (int i = 0; i < F::PER; ++i) {
                 const int pos = seg0 + sp + 16 * i;
                 const bool in = line < n_lines && (unsigned)pos < (unsigned)n_pos;
                 const int off = in ? line * step_line + pos * step_pos : 0;
-                v0[i] = in ? im0[off] : 0.0f;
-                v1[i] = in && two ? im1[off] : 0.0f;
+#pragma unroll
+                for (int t = 0; t < SP; ++t) vv[t][i] = in && t < ns ? im[t][off] : 0.0f;
             }
         }
     };
     auto store = [&]() {
 #pragma unroll
-        for (int i = 0; i < F::PER; ++i) stage[sr * F::LD + sp + 16 * i] = make_float2(v0[i], v1[i]);
+        for (int i = 0; i < F::PER; ++i) {
+            V o;
+            float *ov = (float *)&o;
+#pragma unroll
+            for (int t = 0; t < SP; ++t) ov[t] = vv[t][i];
+            *(V *)&stage[SP * (sr * F::LD + sp + 16 * i)] = o;
+        }
     };
 
-    float2 acc[4];
+    float acc[4][SP];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] = make_float2(0.0f, 0.0f);
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int t = 0; t < SP; ++t) acc[k][t] = 0.0f;
     int seg_cur, seg_next = 0;
     load(0, seg_cur);
     store();
@@ -679,17 +697,17 @@ __device__ __forceinline__ void fp_staged2_body(const SliceDev &sd0, const Slice
         const double ub = fma((double)l0, q.slope, q.u_first);
         const double ubase = floor(ub);
         const float remv = (float)(ub - ubase - q.rho);
-        const float2 *base = stage + ((int)ubase - seg_cur) + ph * F::LD;
+        const float *base = stage + SP * (((int)ubase - seg_cur) + ph * F::LD);
         if (l0 + FP_RB <= n_lines) {
 #pragma unroll
             for (int k = 0; k < LPW; ++k)
-                acc[k & 3] = staged_line2(base + k * WPP * F::LD, fmaf((float)(ph + WPP * k), q.slopef, remv), q, acc[k & 3]);
+                staged_line_sp<SP>(base + SP * k * WPP * F::LD, fmaf((float)(ph + WPP * k), q.slopef, remv), q, acc[k & 3]);
         } else {
 #pragma unroll
             for (int k = 0; k < LPW; ++k)   // no break: the loop stays unrolled and acc in registers
                 if (l0 + ph + WPP * k < n_lines)                      // uniform
-                    acc[k & 3] = staged_line2(base + k * WPP * F::LD, fmaf((float)(ph + WPP * k), q.slopef, remv), q,
-                                              acc[k & 3]);
+                    staged_line_sp<SP>(base + SP * k * WPP * F::LD, fmaf((float)(ph + WPP * k), q.slopef, remv), q,
+                                       acc[k & 3]);
         }
         __syncthreads();   // every read of this block is done
         if (more) {
@@ -698,35 +716,47 @@ __device__ __forceinline__ void fp_staged2_body(const SliceDev &sd0, const Slice
             __syncthreads();
         }
     }
-    float2 tot = make_float2((acc[0].x + acc[1].x) + (acc[2].x + acc[3].x), (acc[0].y + acc[1].y) + (acc[2].y + acc[3].y));
+    float tot[SP];
+#pragma unroll
+    for (int t = 0; t < SP; ++t) tot[t] = (acc[0][t] + acc[1][t]) + (acc[2][t] + acc[3][t]);
     if constexpr (WPP > 1) {
-        float2 *part = stage;   // [FP_SGRP][3][64], free after the last block's barrier
-        if (ph > 0) part[(pw * 3 + ph - 1) * 64 + lane] = tot;
+        float *part = stage;   // [FP_SGRP][3][64][SP], free after the last block's barrier
+        if (ph > 0) {
+            V o;
+            float *ov = (float *)&o;
+#pragma unroll
+            for (int t = 0; t < SP; ++t) ov[t] = tot[t];
+            *(V *)&part[SP * ((pw * 3 + ph - 1) * 64 + lane)] = o;
+        }
         __syncthreads();
         if (ph > 0) return;
 #pragma unroll
         for (int m = 1; m < WPP; ++m) {
-            const float2 o = part[(pw * 3 + m - 1) * 64 + lane];
-            tot.x += o.x;
-            tot.y += o.y;
+            const V o = *(const V *)&part[SP * ((pw * 3 + m - 1) * 64 + lane)];
+            const float *ov = (const float *)&o;
+#pragma unroll
+            for (int t = 0; t < SP; ++t) tot[t] += ov[t];
         }
     }
     if (j >= nb || pw >= n) return;
     const float sc = alpha * (float)(g.s * g.s);
-    fp_store<MODE>(cp, out, sd0.sino_off + (int64_t)q.k * nb + j, sc * tot.x, (int64_t)slice0 * nb + j);
-    if (two) fp_store<MODE>(cp, out, sd1.sino_off + (int64_t)q.k * nb + j, sc * tot.y, (int64_t)(slice0 + 1) * nb + j);
+#pragma unroll
+    for (int t = 0; t < SP; ++t)
+        if (t < ns)
+            fp_store<MODE>(cp, out, T.slc[slice0 + t].sino_off + (int64_t)q.k * nb + j, sc * tot[t],
+                           (int64_t)(slice0 + t) * nb + j);
 }
 
-// grid: (bin chunks, staged groups, slice pairs); GMAX as in fp_staged_kernel
-template <int MODE, int GMAX>
-__global__ __launch_bounds__(256) void fp_staged2_kernel(Tables T, const float *__restrict__ img,
-                                                         float *__restrict__ out, float alpha, CpDual cp, int n_slices)
+// grid: (bin chunks, staged groups, slice groups of SP); GMAX as in fp_staged_kernel
+template <int MODE, int SP, int GMAX>
+__global__ __launch_bounds__(256) void fp_staged_sp_kernel(Tables T, const float *__restrict__ img,
+                                                           float *__restrict__ out, float alpha, CpDual cp,
+                                                           int n_slices)
 {
-    __shared__ float2 stage[FP_RB * FpStaged<3>::LD];
-    const int s0 = 2 * (int)blockIdx.z;
-    const bool two = s0 + 1 < n_slices;
-    const SliceDev sd0 = T.slc[s0], sd1 = T.slc[two ? s0 + 1 : s0];
-    const GeoDev &g = T.geo[sd0.g];
+    __shared__ __attribute__((aligned(16))) float stage[SP * FP_RB * FpStaged<3>::LD];
+    const int s0 = SP * (int)blockIdx.z;
+    const int ns = min(SP, n_slices - s0);
+    const GeoDev &g = T.geo[T.slc[s0].g];
     const int j0 = fp_chunk(blockIdx.x, gridDim.x) * 64;
     if ((int)blockIdx.y >= g.fp_npair) return;       // uniform over the workgroup
     const int4 grp = T.fp_pair[g.fp_pair_off + blockIdx.y];
@@ -761,13 +791,15 @@ __global__ __launch_bounds__(256) void fp_staged2_kernel(Tables T, const float *
         sb.b3 = e.blk_lo;
     }
     if (P == 4) {   // uniform over the workgroup
-        fp_staged2_body<MODE, 4>(sd0, sd1, two, g, q, sb, n, rows, j, img, out, alpha, cp, s0, stage);
+        fp_staged_sp_body<MODE, SP, 4>(T, s0, ns, g, q, sb, n, rows, j, img, out, alpha, cp, stage);
     } else if (P == 2) {
-        fp_staged2_body<MODE, 2>(sd0, sd1, two, g, q, sb, n, rows, j, img, out, alpha, cp, s0, stage);
+        fp_staged_sp_body<MODE, SP, 2>(T, s0, ns, g, q, sb, n, rows, j, img, out, alpha, cp, stage);
     } else {
-        fp_staged2_body<MODE, 1>(sd0, sd1, two, g, q, sb, n, rows, j, img, out, alpha, cp, s0, stage);
+        fp_staged_sp_body<MODE, SP, 1>(T, s0, ns, g, q, sb, n, rows, j, img, out, alpha, cp, stage);
     }
 }
+
+constexpr int FP_SLICES_MAX = 4;   // slices per workgroup of the automatic staged projector
 
 int fp_nc(const pyhst_plan &p)
 {
@@ -803,13 +835,21 @@ hipError_t launch_fp_nc(const pyhst_plan &p, dim3 grid, const float *img, float 
         if constexpr (NC == 3 && UNIT && MODE != 3) {
             // automatic choice on a uniform plan of several slices: slice pairs, when they still give at
             // least eight workgroups per CU
-            const int64_t pairs = (int64_t)gs.x * gs.y * ((gs.z + 1) / 2);
-            if (p.fp_kernel == PYHST_FP_AUTO && p.uniform && p.n_slices >= 2 && pairs >= 8 * (int64_t)p.cu_count) {
-                const dim3 gp(gs.x, gs.y, (gs.z + 1) / 2);
-                if (p.fp_max_grp > 2)
-                    fp_staged2_kernel<MODE, 4><<<gp, 256, 0, st>>>(p.t, img, sino, alpha, cp, p.n_slices);
-                else
-                    fp_staged2_kernel<MODE, 2><<<gp, 256, 0, st>>>(p.t, img, sino, alpha, cp, p.n_slices);
+            const int64_t per4 = (int64_t)gs.x * gs.y * ((gs.z + 3) / 4), per2 = (int64_t)gs.x * gs.y * ((gs.z + 1) / 2);
+            const int64_t enough = 8 * (int64_t)p.cu_count;
+            if (p.fp_kernel == PYHST_FP_AUTO && p.uniform && p.n_slices >= 2 && per2 >= enough) {
+                const bool four = p.n_slices >= 4 && per4 >= enough && FP_SLICES_MAX >= 4;
+                const dim3 gp(gs.x, gs.y, four ? (gs.z + 3) / 4 : (gs.z + 1) / 2);
+                if (four) {
+                    if (p.fp_max_grp > 2)
+                        fp_staged_sp_kernel<MODE, 4, 4><<<gp, 256, 0, st>>>(p.t, img, sino, alpha, cp, p.n_slices);
+                    else
+                        fp_staged_sp_kernel<MODE, 4, 2><<<gp, 256, 0, st>>>(p.t, img, sino, alpha, cp, p.n_slices);
+                } else if (p.fp_max_grp > 2) {
+                    fp_staged_sp_kernel<MODE, 2, 4><<<gp, 256, 0, st>>>(p.t, img, sino, alpha, cp, p.n_slices);
+                } else {
+                    fp_staged_sp_kernel<MODE, 2, 2><<<gp, 256, 0, st>>>(p.t, img, sino, alpha, cp, p.n_slices);
+                }
                 return hipGetLastError();
             }
         }

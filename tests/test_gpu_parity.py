@@ -481,13 +481,14 @@ def test_fista_beats_ista_and_recovers_disc(dev):
     assert abs(xf[0].cpu().numpy()[inside].mean() - 1.0) < 0.03
 
 
-def test_fp_slice_pairs_equal_one_slice_kernel(dev, gen):
-    """The automatic projector choice on a uniform plan of several slices takes two slices per workgroup
-    (one staged segment and one set of hat weights for both); every value equals the one-slice staged
-    kernel's bit for bit: an odd slice count (the last workgroup holds one slice), groups of up to four
-    projections, the plain projection, the Chambolle-Pock dual update and the FISTA residual in the
-    projector's epilogue."""
-    N, K, S = 256, 720, 7
+@pytest.mark.parametrize("S", [7, 11])
+def test_fp_slice_pairs_equal_one_slice_kernel(dev, gen, S):
+    """The automatic projector choice on a uniform plan of several slices takes two (7 slices of 256^2 x
+    720) or four (11 slices) slices per workgroup (one staged segment and one set of hat weights for all);
+    every value equals the one-slice staged kernel's bit for bit: a slice count that the group size does
+    not divide (the last workgroup holds fewer), groups of up to four projections, the plain projection,
+    the Chambolle-Pock dual update and the FISTA residual in the projector's epilogue."""
+    N, K = 256, 720
     g, og = pair(nx=N, ny=N, nb=N, K=K, axis=128.2, shifts=0.3)
     x = torch.from_numpy(gen.standard_normal((S, N, N)).astype(np.float32)).to(dev)
     y = torch.from_numpy(gen.standard_normal((S, K, N)).astype(np.float32)).to(dev)
