@@ -799,8 +799,6 @@ __global__ __launch_bounds__(256) void fp_staged_sp_kernel(Tables T, const float
     }
 }
 
-constexpr int FP_SLICES_MAX = 4;   // slices per workgroup of the automatic staged projector
-
 int fp_nc(const pyhst_plan &p)
 {
     double s_min = 1e300;
@@ -833,12 +831,12 @@ hipError_t launch_fp_nc(const pyhst_plan &p, dim3 grid, const float *img, float 
     if (kind == PYHST_FP_STAGED) {
         const dim3 gs(grid.x, MODE == 3 ? 1u : (unsigned)p.fp_max_pairs, grid.z);
         if constexpr (NC == 3 && UNIT && MODE != 3) {
-            // automatic choice on a uniform plan of several slices: slice pairs, when they still give at
-            // least eight workgroups per CU
+            // automatic choice on a uniform plan of several slices: four slices per workgroup, or two,
+            // when that still gives at least eight workgroups per CU
             const int64_t per4 = (int64_t)gs.x * gs.y * ((gs.z + 3) / 4), per2 = (int64_t)gs.x * gs.y * ((gs.z + 1) / 2);
             const int64_t enough = 8 * (int64_t)p.cu_count;
             if (p.fp_kernel == PYHST_FP_AUTO && p.uniform && p.n_slices >= 2 && per2 >= enough) {
-                const bool four = p.n_slices >= 4 && per4 >= enough && FP_SLICES_MAX >= 4;
+                const bool four = p.n_slices >= 4 && per4 >= enough;
                 const dim3 gp(gs.x, gs.y, four ? (gs.z + 3) / 4 : (gs.z + 1) / 2);
                 if (four) {
                     if (p.fp_max_grp > 2)
