@@ -130,8 +130,11 @@ int pyhst_plan_set_tiles(pyhst_plan *plan, int32_t bp_tile, int32_t persistent);
 int pyhst_plan_get_tiles(const pyhst_plan *plan, int32_t *bp_tile, int32_t *persistent);
 /* Forward-projector kernel for every projection this plan makes (forward_project,
  * the iterative solvers, pyhst_cv_error): PYHST_FP_AUTO (the default) picks
- * PYHST_FP_STAGED for pixel sizes >= 0.5; for smaller pixels, angle blocks when
- * they give at least 8 workgroups per compute unit, else PYHST_FP_LINES;
+ * PYHST_FP_STAGED for pixel sizes >= 0.5 (on a uniform plan of several slices
+ * with pixels of 0.943 to 1 bin, four or two slices per workgroup sharing the
+ * staged segment and the hat weights, with results equal bit for bit to one
+ * slice per workgroup); for smaller pixels, angle blocks when they give at
+ * least 8 workgroups per compute unit, else PYHST_FP_LINES;
  * PYHST_FP_BLOCKS: up to 16 projections of similar direction per workgroup
  * sharing LDS-staged line segments; PYHST_FP_STAGED: one to four neighbouring
  * projections whose candidates share the segment per workgroup, line segments

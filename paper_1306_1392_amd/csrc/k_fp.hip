@@ -579,8 +579,8 @@ __global__ __launch_bounds__(256) void fp_staged_kernel(Tables T, const float *_
     }
 }
 
-// SP = 2 or 4 slices of a uniform plan per workgroup (slices SP z .. SP z + SP - 1; pixels of 2/3 to 1
-// bin, three candidates): the staged segment holds the SP slices' values of a position side by side, so
+// SP = 2 or 4 slices of a uniform plan per workgroup (slices SP z .. SP z + SP - 1; three candidates with
+// 2/3 <= |a| <= 1): the staged segment holds the SP slices' values of a position side by side, so
 // one 8- or 16-byte LDS read serves them all, and a line's position, floor, fraction, address and three
 // hat weights are computed once for them (with two slices about 7.5 instead of 12 VALU instructions per
 // line and slice).  Each slice's sums are staged_line's, term for term in the same order, so every value
