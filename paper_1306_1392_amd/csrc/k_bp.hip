@@ -57,9 +57,12 @@ __global__ __launch_bounds__(256 * TILE_AG[CFG]) void bp_kernel(Tables T, const 
     constexpr int NT = 256 * AG;            // threads per workgroup
     constexpr int ABLK = AG * AB;           // projections per staged block
     constexpr int NSLOT = PIPE ? 3 : 1;
+    constexpr int NTAB = 2 + 8 * (BY - 1) + BX;   // table entries a tile reads per projection
+    static_assert(!PIPE || ABLK * NTAB <= NT, "one thread per staged table entry of a block");
     extern __shared__ float2 win[];   // [PIPE ? 2 : 1][wstride]: [AG AB][W] per buffer
     __shared__ int s_jb[NSLOT][ABLK];
     __shared__ float s_r[NSLOT][ABLK];
+    __shared__ float s_tab[PIPE ? NSLOT : 1][PIPE ? ABLK * NTAB : 1];
     __shared__ int64_t s_item;
 
     const int tid = threadIdx.x;
@@ -125,17 +128,20 @@ __global__ __launch_bounds__(256 * TILE_AG[CFG]) void bp_kernel(Tables T, const 
             }
         };
         // angle group ag sums projections [ag AB, ag AB + AB) of the staged block
-        auto sum_block = [&](const float2 *wb, const float *sr, int kb, int na) {
+        // tl: the block's table entries staged in LDS (pipelined loop), else null (scalar loads of tab)
+        auto sum_block = [&](const float2 *wb, const float *sr, const float *tl, int kb, int na) {
             const int a_end = AG > 1 ? min(na, (ag + 1) * AB) : na;
             for (int a = ag * AB; a < a_end; ++a) {
-                const cfloat *tk = tab + (int64_t)(kb + a) * BPT;
-                const float t0 = fmaf(fly, tk[1], fmaf(flx, tk[0], sr[a]));
+                const cfloat *tg = tab + (int64_t)(kb + a) * BPT;
+                const float *tt = tl + a * NTAB;
+                auto tk = [&](int c) { return PIPE ? tt[c] : tg[c]; };
+                const float t0 = fmaf(fly, tk(1), fmaf(flx, tk(0), sr[a]));
                 const float2 *wa = wb + a * W;
 #pragma unroll
                 for (int by = 0; by < BY; ++by) {
 #pragma unroll
                     for (int bx = 0; bx < BX; ++bx) {
-                        const float t = t0 + tk[2 + 8 * by + bx];
+                        const float t = t0 + tk(2 + 8 * by + bx);
                         const int i = (int)t;
                         const float f = __builtin_amdgcn_fractf(t);
                         const float2 v = wa[i];
@@ -162,7 +168,7 @@ __global__ __launch_bounds__(256 * TILE_AG[CFG]) void bp_kernel(Tables T, const 
                     win[e] = make_float2(q0, q1 - q0);
                 }
                 __syncthreads();
-                sum_block(win, s_r[0], kb, na);
+                sum_block(win, s_r[0], nullptr, kb, na);
                 __syncthreads();
             }
         } else {
@@ -195,20 +201,53 @@ __global__ __launch_bounds__(256 * TILE_AG[CFG]) void bp_kernel(Tables T, const 
                     if (e < tot) wb[e] = make_float2(q0r[i], q1r[i] - q0r[i]);
                 }
             };
-            params(0, 0);
-            if (nblk > 1) params(ABLK, 1);
+            // a block's parameters (the projections' cos, sin and shift; NTAB table entries each) are
+            // loaded into registers two blocks ahead and stored into their slot after the current block's
+            // sums, so their L2 / memory latency overlaps two blocks of work
+            double pc = 0.0, ps = 0.0, ph = 0.0;
+            float pt = 0.0f;
+            auto pload = [&](int kb) {
+                const int na = min(ABLK, K - kb);
+                if (tid < na) {
+                    pc = cosd[kb + tid];
+                    ps = sind[kb + tid];
+                    ph = shd[kb + tid];
+                }
+                if (tid < na * NTAB) {
+                    const int a = tid / NTAB;
+                    pt = T.bpt[(int64_t)(g.ang_off + kb + a) * BPT + (tid - a * NTAB)];
+                }
+            };
+            auto pstore = [&](int kb, int slot) {
+                const int na = min(ABLK, K - kb);
+                if (tid < na) {
+                    const double torg = axis + ph + s * (x0 * pc + y0 * ps);
+                    const double tmin = torg + s * ((TW - 1) * fmin(pc, 0.0) + (TH - 1) * fmin(ps, 0.0));
+                    const int jb = (int)floor(tmin) - 1;
+                    s_jb[slot][tid] = jb;
+                    s_r[slot][tid] = (float)(torg - (double)jb);
+                }
+                if (tid < na * NTAB) s_tab[slot][tid] = pt;
+            };
+            pload(0);
+            pstore(0, 0);
+            if (nblk > 1) {
+                pload(ABLK);
+                pstore(ABLK, 1);
+            }
             __syncthreads();
             gload(0, 0);
             lstore(0, win);
             __syncthreads();
             for (int b = 0; b < nblk; ++b) {
-                // slot (b + 2) % 3 was last read before the barrier that ended block b - 1
                 if (b + 1 < nblk) gload(b + 1, (b + 1) % 3);
-                if (b + 2 < nblk) params((b + 2) * ABLK, (b + 2) % 3);
+                if (b + 2 < nblk) pload((b + 2) * ABLK);
                 const int kb = b * ABLK;
-                sum_block(win + (b & 1) * wstride, s_r[b % 3], kb, min(ABLK, K - kb));
-                // buffer (b + 1) & 1 was last read while summing block b - 1, before that barrier too
+                sum_block(win + (b & 1) * wstride, s_r[b % 3], s_tab[b % 3], kb, min(ABLK, K - kb));
+                // buffer (b + 1) & 1 was last read while summing block b - 1, and slot (b + 2) % 3 while
+                // summing block b - 1 too, both before the barrier that ended it
                 if (b + 1 < nblk) lstore(b + 1, win + ((b + 1) & 1) * wstride);
+                if (b + 2 < nblk) pstore((b + 2) * ABLK, (b + 2) % 3);
                 __syncthreads();
             }
         }
