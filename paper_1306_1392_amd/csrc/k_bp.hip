@@ -11,8 +11,9 @@
 // FP32 coordinate stays below ~100 bins (ulp < 8e-6 bin).  Lanes of a wave own
 // one 8x8 pixel block per register slot, so one ds_read_b64 of a wave touches
 // at most ~13 consecutive window entries (no bank conflicts).  The per-block
-// coordinate offsets are wave-uniform and come from a scalar table.  The bound
-// is the LDS read port: 8 B per update against 128 B/clk/CU.
+// coordinate offsets are wave-uniform and come from a scalar table (the
+// pipelined loop stages them in LDS with each block's other parameters).  The
+// bound is the LDS read port: 8 B per update against 128 B/clk/CU.
 #include "internal.hpp"
 
 namespace pyhst {
@@ -40,7 +41,8 @@ typedef __attribute__((address_space(4))) const float cfloat;
 
 // PIPE: the windows of the next block of projections are loaded into registers while the current
 // block is summed (two LDS window buffers of wstride entries, three parameter slots, one barrier per
-// block), so the L2 / HBM latency of the staging loads overlaps the sums.  It pays where a launch has
+// block), so the L2 / HBM latency of the staging loads overlaps the sums; the parameters of the block
+// after that (cos, sin, shift, table entries) are in flight in registers at the same time.  It pays where a launch has
 // few workgroups per CU (a single slice in the iterative solvers, after a projector whose sweep of the
 // image has evicted the sinogram from every L2): the 32 x 32 tiles; the larger tiles, chosen when there
 // are at least four workgroups per CU, keep the plain loop (their accumulators leave few registers).
