@@ -1,15 +1,21 @@
-"""CPU replays of the index arithmetic of two GPU kernels (host logic, no GPU).
+"""CPU replays of the index arithmetic of the GPU kernels (host logic, no GPU).
 
-* fp_staged_kernel (one to four projections x 64 bins per workgroup, 16-line blocks staged in LDS;
-  the groups chosen by the plan's rule, replayed here): every candidate a lane reads lies inside the
-  staged segment of its line, [0, SEG) with SEG = 128 for three candidates per line and 224 for six,
-  over random geometries at the edges of both pixel-size classes.
-  The replay follows the kernel's FP64 block anchor and FP32 per-line offsets (first candidate
-  floor(v) + 1 and its offset a - sign(a) - a fract(v), v = u - 1/|a|), and checks both against FP64:
-  the offset to 2e-5, and no position outside the candidates has a hat weight above 1e-5.
+* fp_staged_kernel and fp_staged_sp_kernel (one to four projections x 64 bins per workgroup, 16-line
+  blocks staged in LDS; the groups chosen by the plan's rule, replayed here): every candidate a lane
+  reads lies inside the staged segment of its line, [0, SEG) with SEG = 128 for three candidates per
+  line and 224 for six, over random geometries at the edges of both pixel-size classes.  The replay
+  follows the kernel's FP64 block anchor and FP32 per-line offsets (first candidate floor(v) + 1 and
+  its offset a - sign(a) - a fract(v), v = u - 1/|a|), and checks both against FP64: the offset to
+  2e-5, and no position outside the candidates has a hat weight above 1e-5.  Also the wavefront-to-
+  line map of each group size, the closed-form hat weights and the bin-chunk-to-XCD map.
+* The U-Net's direct convolutions: every staged patch and weight slot and every MFMA operand read of
+  the persistent and general forms, the fused first two convolutions, the fused level-0 up-sampling,
+  the weight-gradient kernel (staging, 8 x 8 transposes, operands, bias sums), the up-sampling kernels
+  (operands and output coverage) and the half-wave exchange of the epilogues.
 * prox_step2_kernel (two fused ROF dual steps on a 64 x 16 tile with a two-pixel halo): its loops,
   replayed with NaN-initialised LDS so that a read of an unset entry fails, equal two plain single steps
   exactly, on ragged and degenerate image shapes.
+* filter4096_kernel: its index arithmetic, LDS layout and table lookups against numpy's FFT.
 """
 import math
 
