@@ -110,7 +110,9 @@ __global__ __launch_bounds__(256 * TILE_AG[CFG]) void bp_kernel(Tables T, const 
         const double x0 = ix0 - 0.5 * (nx - 1), y0 = iy0 - 0.5 * (ny - 1);
         const double s = g.s;
         const double *cosd = T.cosd + g.ang_off, *sind = T.sind + g.ang_off, *shd = T.shiftd + g.ang_off;
-        const cfloat *tab = (const cfloat *)(T.bpt + g.ang_off * BPT);
+        // the table offset taken as wave-uniform (readfirstlane): the per-projection addresses of the scalar
+        // table loads are then formed in SGPRs, not in VGPRs read back every projection
+        const cfloat *tab = (const cfloat *)(T.bpt + (int64_t)__builtin_amdgcn_readfirstlane(g.ang_off) * BPT);
 
         float acc[PX];
 #pragma unroll
