@@ -27,10 +27,14 @@ METRIC = "backprojection GUPS (voxel·angle/s) + slices/s at 2048²; learned vs 
 # MI355X FP32 vector peak 157.3 TFLOP/s = 256 CU x 2.4 GHz x 128 FMA lanes/clk x 2 flops:
 # one VALU lane-op per FMA slot gives 78.6 T lane-ops/s.
 VALU_LANE_OPS_PEAK = 157.3e12 / 2
-BP_OPS_PER_UPDATE = 6   # t = t0 + off, trunc, fract, LDS address, acc += q, acc = fma(f, dq, acc)
-BP_LDS_BYTES_PER_UPDATE = 8   # one ds_read_b64 of (q[j], q[j+1] - q[j])
-# LDS read port: 128 B/clk/CU x 256 CU x 2.4 GHz
-LDS_PEAK_GBS = 128 * 256 * 2.4
+# The headline batch runs the two-slice backprojector: per pixel and projection one 16-byte LDS read of
+# both slices' (q[j], q[j+1] - q[j]) pairs (8 B per update) and t = t0 + off, trunc, fract, LDS address
+# shared by the two slices plus acc += q, acc = fma(f, dq, acc) per slice (4 lane-ops per update).
+BP_OPS_PER_UPDATE = 4
+BP_LDS_BYTES_PER_UPDATE = 8
+# LDS read port for 16-byte reads: 256 B/clk/CU x 256 CU x 2.4 GHz (ds_read_b128 measures 136 TB/s on the
+# chip, ds_read_b64 78 TB/s, i.e. 128 B/clk)
+LDS_PEAK_GBS = 256 * 256 * 2.4
 
 
 def log(*a):
@@ -86,7 +90,9 @@ def quick_data(R, N, K, dev):
 
 
 def measure_peaks(dev):
-    """VALU FMA rate, the backprojector's op mix rate and LDS ds_read_b64 bandwidth."""
+    """VALU FMA rate, the backprojector's op mix rate and LDS read bandwidth (ds_read_b64,
+    ds_read_b128, ds_read_b128 with lanes 1.25 entries apart as in the projector, and
+    ds_read_b128 with half of the lanes masked off; bytes count active lanes only)."""
     import torch
     import paper_1306_1392_amd as ph
     from paper_1306_1392_amd import _lib
@@ -96,7 +102,10 @@ def measure_peaks(dev):
     st = torch.cuda.current_stream()
     out = {}
     for kind, name, per in ((0, "valu_fma_lane_ops_per_s", 8), (1, "bp_mix_lane_ops_per_s", 64),
-                            (2, "lds_read_bytes_per_s", 64)):
+                            (2, "lds_read_bytes_per_s", 64), (3, "lds_read128_bytes_per_s", 128),
+                            (4, "lds_read128_spread_bytes_per_s", 128),
+                            (5, "lds_read128_even_lanes_bytes_per_s", 64),
+                            (6, "lds_read128_low_half_bytes_per_s", 64)):
         _lib.check(L.pyhst_microbench(kind, blocks, iters, ctypes_ptr(sink), ctypes_stream(st)), "microbench")
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -659,7 +668,7 @@ def summarize_profiles(d):
     os.makedirs(out_dir, exist_ok=True)
 
     def short(name):
-        for key in ("bp_kernel", "filter", "normalize_kernel", "copyBuffer", "fp_kernel"):
+        for key in ("bp2_kernel", "bp_kernel", "filter", "normalize_kernel", "copyBuffer", "fp_kernel"):
             if key in name:
                 return name.replace("pyhst::(anonymous namespace)::", "").split("(")[0].replace("void ", "")
         return None
@@ -693,7 +702,7 @@ def summarize_profiles(d):
     log(f"wrote {txt}")
     # traffic: FETCH_SIZE / WRITE_SIZE (KiB) scaled by the same counters on a 2 GiB device copy
     cp = [k for k in counters if "copyBuffer" in k[0]]
-    bp = [k for k in counters if "bp_kernel" in k[0]]
+    bp = [k for k in counters if "bp2_kernel" in k[0]] or [k for k in counters if "bp_kernel" in k[0]]
     if cp and bp:
         copy_bytes = 2 * 2 ** 29 * 4
         cf = sum(counters[(cp[0][0], "FETCH_SIZE")]) / len(counters[(cp[0][0], "FETCH_SIZE")]) * 1024
@@ -1051,8 +1060,9 @@ def main():
     stream.synchronize()
     filt_ms = ev2[0].elapsed_time(ev2[1]) / nbp
     del sino_f
-    # roofline: the backprojector reads one 8-byte (q, dq) pair from LDS per update; the LDS
-    # read port (128 B/clk/CU) is the binding resource, the VALU mix (6 lane-ops/update) the next one
+    # roofline: the two-slice backprojector reads 8 LDS bytes per update (one 16-byte read per pixel,
+    # projection and slice pair) against the 16-byte read port (256 B/clk/CU); the VALU mix
+    # (4 lane-ops/update) is the other bound
     lds_achieved = BP_LDS_BYTES_PER_UPDATE * U / (bp_ms * 1e-3) / 1e9
     valu_achieved = U * BP_OPS_PER_UPDATE / (bp_ms * 1e-3) / 1e12
     res["roofline"] = {"bound": "lds", "achieved": round(lds_achieved, 1), "peak": round(LDS_PEAK_GBS, 1),
@@ -1060,7 +1070,7 @@ def main():
                        "traffic": traffic_for(os.path.join(ROOT, "paper_1306_1392_amd", "csrc", "k_bp.hip"),
                                               "hbm_bytes_per_launch"),
                        "algorithmic_hbm_bytes": (plan.filt_elems + plan.img_elems) * 4,
-                       "kernel": "bp_kernel (backprojection)", "kernel_ms": round(bp_ms, 3),
+                       "kernel": "bp2_kernel (backprojection, two slices per workgroup)", "kernel_ms": round(bp_ms, 3),
                        "lds_bytes_per_update": BP_LDS_BYTES_PER_UPDATE, "updates_per_launch": U,
                        "bp_gups": round(U / (bp_ms * 1e-3) / 1e9, 2),
                        "valu": {"achieved_tops": round(valu_achieved, 2), "ops_per_update": BP_OPS_PER_UPDATE,

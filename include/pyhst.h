@@ -29,7 +29,8 @@
  *   - Once a plan exists no entry point allocates device memory; scratch is
  *     passed in by the caller (tv_prox, reconstruct_slices).
  *   - A plan is immutable after creation except for its tile and projector
- *     choices (pyhst_plan_set_tiles, pyhst_plan_set_fp_kernel, not to be called
+ *     choices (pyhst_plan_set_tiles, pyhst_plan_set_fp_kernel,
+ *     pyhst_plan_set_bp_slices, not to be called
  *     while other calls use the plan) and its caches (graphs, stream slots),
  *     which are guarded by a lock.  Calls on one plan may run concurrently on
  *     different streams when each has its own output and work buffers; the
@@ -144,6 +145,15 @@ int pyhst_plan_get_tiles(const pyhst_plan *plan, int32_t *bp_tile, int32_t *pers
  * another value. */
 int pyhst_plan_set_fp_kernel(pyhst_plan *plan, int32_t kind);
 int pyhst_plan_get_fp_kernel(const pyhst_plan *plan, int32_t *kind);
+/* Slices per backprojector workgroup (section 2.3's tiles) for plain backprojections
+ * (backproject, the FBP, the ISTA / FISTA and patch-prior steps; the
+ * Chambolle-Pock step with its fused primal update keeps one): 0 = automatic
+ * (two on a uniform plan of at least two slices without the persistent work
+ * queue), 1 = one, 2 = two where the plan allows it.  Two slices share each
+ * staged window entry (one 16-byte LDS read per pixel update of both) and the
+ * coordinate arithmetic; the images equal one slice per workgroup bit for bit.
+ * EARG for another value. */
+int pyhst_plan_set_bp_slices(pyhst_plan *plan, int32_t per_workgroup);
 /* Autotuner: times the backprojector of this plan for every tile shape, with
  * and without the persistent work queue (reps launches each, HIP events on
  * `stream`), on filt (filtered layout) -> img, and keeps the fastest.  Writes
@@ -457,7 +467,13 @@ int pyhst_unet_tensor(const pyhst_unet *net, int32_t kind, int32_t level, int32_
  * kind 1: the backprojector's per-update VALU sequence without LDS, 8 updates x
  *         8 lane-ops per thread and iteration;
  * kind 2: LDS ds_read_b64 in a conflict-free pattern, 8 x 8 bytes per thread
- *         and iteration.
+ *         and iteration;
+ * kind 3: LDS ds_read_b128 in a conflict-free pattern, 8 x 16 bytes per thread
+ *         and iteration;
+ * kind 4: as kind 3 with consecutive lanes 1.25 entries apart (the projector's
+ *         spread of reads along a line);
+ * kind 5 / 6: as kind 3 with only the even lanes / lanes 0..31 active
+ *         (8 x 16 bytes per active thread and iteration).
  * blocks x 256 threads; sink: device float buffer of blocks*256 elements (only
  * written if a result takes an impossible value, which keeps the work live). */
 int pyhst_microbench(int32_t kind, int32_t blocks, int32_t iters, float *sink, hipStream_t stream);

@@ -16,7 +16,7 @@ FBP, TV_CP, ISTA, FISTA = 0, 1, 2, 3
 FP_AUTO, FP_BLOCKS, FP_STAGED, FP_LINES = 0, 1, 2, 3
 
 EXPORTS = ["pyhst_plan_create", "pyhst_plan_destroy", "pyhst_plan_slice_info", "pyhst_plan_sizes",
-           "pyhst_plan_set_tiles", "pyhst_plan_get_tiles", "pyhst_plan_set_fp_kernel", "pyhst_plan_get_fp_kernel", "pyhst_normalize", "fbp_filter", "backproject",
+           "pyhst_plan_set_tiles", "pyhst_plan_get_tiles", "pyhst_plan_set_fp_kernel", "pyhst_plan_get_fp_kernel", "pyhst_plan_set_bp_slices", "pyhst_normalize", "fbp_filter", "backproject",
            "forward_project", "tv_prox", "reconstruct_slices", "pyhst_microbench", "pyhst_strerror",
            "pyhst_last_error", "pyhst_unet_create", "pyhst_unet_destroy", "pyhst_unet_num_params",
            "pyhst_unet_set_params", "pyhst_unet_get_params", "pyhst_unet_get_grads", "pyhst_unet_forward",
@@ -78,6 +78,7 @@ def lib(path: str = LIB_PATH):
     L.pyhst_plan_get_tiles.argtypes = [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]
     L.pyhst_plan_set_fp_kernel.argtypes = [P, c_int32]
     L.pyhst_plan_get_fp_kernel.argtypes = [P, ctypes.POINTER(c_int32)]
+    L.pyhst_plan_set_bp_slices.argtypes = [P, c_int32]
     L.pyhst_normalize.argtypes = [P, P, P, ctypes.POINTER(c_double), c_int32, P, c_float, P, P]
     L.fbp_filter.argtypes = [P, P, P, P]
     L.backproject.argtypes = [P, P, c_int32, P, c_float, c_float, P]

@@ -108,6 +108,10 @@ class Plan:
         """Forward-projector kernel: FP_AUTO, FP_BLOCKS, FP_STAGED or FP_LINES."""
         check(self._L.pyhst_plan_set_fp_kernel(self.handle, int(kind)), "pyhst_plan_set_fp_kernel")
 
+    def set_bp_slices(self, per_workgroup: int = 0):
+        """Slices per backprojector workgroup: 0 automatic, 1 or 2."""
+        check(self._L.pyhst_plan_set_bp_slices(self.handle, int(per_workgroup)), "pyhst_plan_set_bp_slices")
+
     def get_fp_kernel(self) -> int:
         k = ctypes.c_int32()
         check(self._L.pyhst_plan_get_fp_kernel(self.handle, ctypes.byref(k)), "pyhst_plan_get_fp_kernel")

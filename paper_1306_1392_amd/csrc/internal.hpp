@@ -110,6 +110,7 @@ struct pyhst_plan {
     int fp_seg = 0, fp_max_blocks = 0, fp_max_pairs = 0, fp_max_grp = 1;
     int64_t n_items[pyhst::N_TILE_CFG] = {};
     int bp_tile = -1, persistent = 0;
+    int bp_slices = 0;   // slices per backprojector workgroup: 0 automatic, 1, 2
     int fp_kernel = PYHST_FP_AUTO;
     void *dev_block = nullptr;
     pyhst::Tables t{};
@@ -131,6 +132,8 @@ int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *where);
 
 int choose_tile(const pyhst_plan &p);
+// whether plain backprojections (no fused primal step) of this plan run two slices per workgroup
+bool two_slice_bp(const pyhst_plan &p);
 // persistent-work counter of `st` on this plan (nullptr once every slot is taken)
 int *stream_counter(const pyhst_plan &p, hipStream_t st);
 

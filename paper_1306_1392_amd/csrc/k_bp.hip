@@ -13,7 +13,11 @@
 // at most ~13 consecutive window entries (no bank conflicts).  The per-block
 // coordinate offsets are wave-uniform and come from a scalar table (the
 // pipelined loop stages them in LDS with each block's other parameters).  The
-// bound is the LDS read port: 8 B per update against 128 B/clk/CU.
+// bound is the LDS read port: 8 B per update against 128 B/clk/CU for 8-byte
+// reads.  On uniform plans of several slices bp2_kernel serves two slices per
+// workgroup with 16-byte reads, which the LDS delivers at about twice the rate
+// (136 against 78 TB/s measured on the whole chip), and shares the coordinate
+// arithmetic between them: 4 VALU lane-ops and 8 LDS bytes per update.
 #include "internal.hpp"
 
 namespace pyhst {
@@ -310,6 +314,134 @@ __global__ __launch_bounds__(256 * TILE_AG[CFG]) void bp_kernel(Tables T, const 
     }
 }
 
+// Two slices of a uniform plan per workgroup (slices 2z and 2z + 1, one angle group, the plain loop):
+// the staged window holds both slices' (q[j], q[j+1] - q[j]) pairs of a bin side by side, so one
+// 16-byte LDS read (which the LDS serves at twice the bytes per clock of an 8-byte one) feeds the
+// two slices' updates of a pixel, and the coordinate, truncation, fraction and address are computed
+// once for both: 4 + 2 x 2 VALU lane-ops per two updates.  Each slice's sum takes bp_kernel's
+// operations in bp_kernel's order, so the images equal bp_kernel's with the same tile bit for bit.
+// Work item z n_tiles + tile; an odd last slice runs as a pair with itself and stores once.
+// projections staged per LDS block of the two-slice kernel: 16 keep a 64 x 64 tile's block at 24 KB, so
+// its 92 VGPRs, not the LDS, set the occupancy (five workgroups per CU; 32 projections, 48 KB, allow three
+// and measured 56 instead of 41 ms on 64 x 2048^2 x 1800)
+constexpr int AB2 = 16;
+
+template <int CFG>
+__global__ __launch_bounds__(256) void bp2_kernel(Tables T, const float *__restrict__ sino, int filtered,
+                                                  float *__restrict__ img, float alpha, float beta,
+                                                  int n_slices, int n_tiles, int64_t n_items)
+{
+    constexpr int BX = TILE_BX[CFG], BY = TILE_BY[CFG];
+    constexpr int TW = 8 * BX, TH = 32 * BY;
+    constexpr int PX = BX * BY;
+    static_assert(TILE_AG[CFG] == 1, "one angle group");
+    extern __shared__ float4 win4[];   // [AB2][W]
+    __shared__ int s_jb[AB2];
+    __shared__ float s_r[AB2];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int lx = lane & 7, ly = lane >> 3;
+    const float flx = (float)lx, fly = (float)(ly + 8 * BY * wv);
+
+    // workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous range of the work list
+    const int64_t b = blockIdx.x, qn = n_items >> 3, rn = n_items & 7, xc = b & 7;
+    const int64_t item = xc * qn + min(xc, rn) + (b >> 3);
+    if (item >= n_items) return;
+    const int z = (int)(item / n_tiles), tile = (int)(item - (int64_t)z * n_tiles);
+    const int sl0 = 2 * z;
+    const bool two = sl0 + 1 < n_slices;
+    const SliceDev sd0 = T.slc[sl0], sd1 = T.slc[two ? sl0 + 1 : sl0];
+    const GeoDev &g = T.geo[sd0.g];
+    const int nx = g.nx, ny = g.ny, K = g.K;
+    const int L = filtered ? g.Lf : g.nb;
+    const double axis = filtered ? g.axis_f : g.axis;
+    const float *rows0 = sino + (filtered ? sd0.filt_off : sd0.sino_off);
+    const float *rows1 = sino + (filtered ? sd1.filt_off : sd1.sino_off);
+    const int W = g.bp_w[CFG];
+    const float invW = 1.0f / (float)W;
+    const int ntx = g.ntx[CFG];
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int ix0 = tx * TW, iy0 = ty * TH;
+    const double x0 = ix0 - 0.5 * (nx - 1), y0 = iy0 - 0.5 * (ny - 1);
+    const double s = g.s;
+    const double *cosd = T.cosd + g.ang_off, *sind = T.sind + g.ang_off, *shd = T.shiftd + g.ang_off;
+    const cfloat *tab = (const cfloat *)(T.bpt + (int64_t)__builtin_amdgcn_readfirstlane(g.ang_off) * BPT);
+
+    float acc0[PX], acc1[PX];
+#pragma unroll
+    for (int p = 0; p < PX; ++p) {
+        acc0[p] = 0.0f;
+        acc1[p] = 0.0f;
+    }
+    for (int kb = 0; kb < K; kb += AB2) {
+        const int na = min(AB2, K - kb);
+        if (tid < na) {
+            const int k = kb + tid;
+            const double c = cosd[k], sn = sind[k];
+            const double torg = axis + shd[k] + s * (x0 * c + y0 * sn);
+            const double tmin = torg + s * ((TW - 1) * fmin(c, 0.0) + (TH - 1) * fmin(sn, 0.0));
+            const int jb = (int)floor(tmin) - 1;
+            s_jb[tid] = jb;
+            s_r[tid] = (float)(torg - (double)jb);
+        }
+        __syncthreads();
+        const int tot = na * W;
+        for (int e = tid; e < tot; e += 256) {
+            const int a = (int)(((float)e + 0.5f) * invW);
+            const int j = s_jb[a] + (e - a * W);
+            const int64_t ro = (int64_t)(kb + a) * L;
+            const bool in0 = (unsigned)j < (unsigned)L, in1 = (unsigned)(j + 1) < (unsigned)L;
+            const float a0 = in0 ? rows0[ro + j] : 0.0f, a1 = in1 ? rows0[ro + j + 1] : 0.0f;
+            const float b0 = in0 ? rows1[ro + j] : 0.0f, b1 = in1 ? rows1[ro + j + 1] : 0.0f;
+            win4[e] = make_float4(a0, a1 - a0, b0, b1 - b0);
+        }
+        __syncthreads();
+        for (int a = 0; a < na; ++a) {
+            const cfloat *tg = tab + (int64_t)(kb + a) * BPT;
+            const float t0 = fmaf(fly, tg[1], fmaf(flx, tg[0], s_r[a]));
+            const float4 *wa = win4 + a * W;
+#pragma unroll
+            for (int by = 0; by < BY; ++by) {
+#pragma unroll
+                for (int bx = 0; bx < BX; ++bx) {
+                    const float t = t0 + tg[2 + 8 * by + bx];
+                    const int i = (int)t;
+                    const float f = __builtin_amdgcn_fractf(t);
+                    const float4 v = wa[i];
+                    float &A = acc0[by * BX + bx];
+                    A += v.x;
+                    A = fmaf(f, v.y, A);
+                    float &B = acc1[by * BX + bx];
+                    B += v.z;
+                    B = fmaf(f, v.w, B);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int by = 0; by < BY; ++by) {
+#pragma unroll
+        for (int bx = 0; bx < BX; ++bx) {
+            const int ix = ix0 + 8 * bx + lx;
+            const int iy = iy0 + 8 * BY * wv + 8 * by + ly;
+            if (ix < nx && iy < ny) {
+                const int64_t pix = (int64_t)iy * nx + ix;
+                const int64_t o0 = sd0.img_off + pix;
+                const float v0 = alpha * acc0[by * BX + bx];
+                img[o0] = (beta != 0.0f) ? fmaf(beta, img[o0], v0) : v0;
+                if (two) {
+                    const int64_t o1 = sd1.img_off + pix;
+                    const float v1 = alpha * acc1[by * BX + bx];
+                    img[o1] = (beta != 0.0f) ? fmaf(beta, img[o1], v1) : v1;
+                }
+            }
+        }
+    }
+}
+
 __global__ void zero_counter(int *c) { *c = 0; }
 
 template <int CFG, int MODE, bool PIPE>
@@ -345,6 +477,24 @@ hipError_t launch_kernel(const pyhst_plan &p, const float *sino, int filtered, f
     return hipGetLastError();
 }
 
+template <int CFG>
+hipError_t launch_bp2(const pyhst_plan &p, const float *sino, int filtered, float *img, float alpha, float beta,
+                      int wmax, hipStream_t st)
+{
+    const size_t lds = (size_t)AB2 * wmax * sizeof(float4);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)bp2_kernel<CFG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    // a uniform plan lists every slice's tiles, slice by slice
+    const int n_tiles = (int)(p.n_items[CFG] / p.n_slices);
+    const int64_t n = (int64_t)((p.n_slices + 1) / 2) * n_tiles;
+    bp2_kernel<CFG><<<(unsigned)n, 256, lds, st>>>(p.t, sino, filtered, img, alpha, beta, p.n_slices, n_tiles, n);
+    return hipGetLastError();
+}
+
 template <int CFG, int MODE>
 hipError_t launch_cfg(const pyhst_plan &p, const float *sino, int filtered, float *img, float alpha, float beta,
                       const CpPrimal &cp, hipStream_t st)
@@ -352,6 +502,11 @@ hipError_t launch_cfg(const pyhst_plan &p, const float *sino, int filtered, floa
     int wmax = 0;
     for (const auto &g : p.gd) wmax = std::max(wmax, g.bp_w[CFG]);
     if (p.n_items[CFG] == 0) return hipSuccess;
+    if constexpr (MODE == 0 && TILE_AG[CFG] == 1) {
+        // (windows of large pixels that would not fit the LDS twice over keep one slice)
+        if (two_slice_bp(p) && (size_t)AB2 * wmax * sizeof(float4) <= 160 * 1024)
+            return launch_bp2<CFG>(p, sino, filtered, img, alpha, beta, wmax, st);
+    }
     if constexpr (CFG == 3 || CFG == 5) {   // the tiles chosen when a launch has few workgroups per CU
         if (wmax <= pipe_wmax(CFG))
             return launch_kernel<CFG, MODE, true>(p, sino, filtered, img, alpha, beta, cp, wmax, st);

@@ -26,12 +26,24 @@ int hip_fail(hipError_t e, const char *where)
     return PYHST_EHIP;
 }
 
+bool two_slice_bp(const pyhst_plan &p)
+{
+    return p.uniform && p.n_slices >= 2 && !p.persistent && p.bp_slices != 1;
+}
+
 int choose_tile(const pyhst_plan &p)
 {
     if (p.bp_tile >= 0 && p.bp_tile < N_TILE_CFG) return p.bp_tile;
     // the largest tile that still gives 4 workgroups per CU (a single 1024^2 slice measures 32 us with
     // 32x32 tiles against 43 us with 64x32 ones, which give only 2)
     const int64_t want = 4LL * p.cu_count;
+    if (two_slice_bp(p)) {
+        // two slices per workgroup: 64 x 64 tiles (64 x 2048^2 x 1800: 41.0 ms, against 41.5 with 64 x 128
+        // and 44.2 with 64 x 32), while their pairs still give 4 workgroups per CU
+        if (p.n_items[0] >= 2 * want) return 0;
+        if (p.n_items[1] >= 2 * want) return 1;
+        if (p.n_items[3] >= 2 * want) return 3;
+    }
     if (p.n_items[4] >= want) return 4;
     if (p.n_items[0] >= want) return 0;
     if (p.n_items[1] >= want) return 1;
@@ -694,6 +706,16 @@ int pyhst_plan_set_fp_kernel(pyhst_plan *p, int32_t kind)
     if (!p || kind < PYHST_FP_AUTO || kind > PYHST_FP_LINES) return fail(PYHST_EARG, "set_fp_kernel: bad argument");
     std::lock_guard<std::mutex> lk(p->mu);
     p->fp_kernel = kind;
+    for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+    p->graphs.clear();
+    return PYHST_OK;
+}
+
+int pyhst_plan_set_bp_slices(pyhst_plan *p, int32_t per_workgroup)
+{
+    if (!p || per_workgroup < 0 || per_workgroup > 2) return fail(PYHST_EARG, "set_bp_slices: bad argument");
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->bp_slices = per_workgroup;
     for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
     p->graphs.clear();
     return PYHST_OK;

@@ -67,6 +67,29 @@ def test_backproject_parity(dev, gen, case, tile, persistent):
     assert rel(out, ref) <= TOL_OP, (case, tile, persistent, rel(out, ref))
 
 
+@pytest.mark.parametrize("case", ["odd_shift", "pix_0p7", "pix_1p6", "tiny", "scan360"])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+def test_bp_two_slices_equal_one_slice_kernel(dev, gen, case, tile):
+    """Two slices per backprojector workgroup (the automatic choice on uniform plans) against one
+    slice per workgroup with the same tile: equal bit for bit, with an odd slice count (the last
+    slice runs as a pair with itself) and an accumulating beta."""
+    g, og = pair(**CASES[case])
+    plan = ph.Plan(g, n_slices=3)
+    y = torch.from_numpy(gen.standard_normal((3, g.n_angles, g.n_det)).astype(np.float32)).to(dev)
+    base = torch.from_numpy(gen.standard_normal((3, g.n_y, g.n_x)).astype(np.float32)).to(dev)
+    outs = []
+    for per in (1, 2):
+        plan.set_tiles(tile, False)
+        plan.set_bp_slices(per)
+        o = base.clone()
+        ph.backproject(plan, y, out=o, alpha=0.75, beta=0.5)
+        outs.append(o)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1]), (case, tile, float((outs[0] - outs[1]).abs().max()))
+    ref = 0.75 * oracle.backproject(y.cpu().numpy(), og) + 0.5 * base.double().cpu().numpy()
+    assert rel(outs[1], ref) <= TOL_OP, (case, tile, rel(outs[1], ref))
+
+
 FP_KINDS = {"auto": ph.FP_AUTO, "blocks": ph.FP_BLOCKS, "staged": ph.FP_STAGED, "lines": ph.FP_LINES}
 
 
