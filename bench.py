@@ -656,7 +656,8 @@ PROFILE_CMDS = {
              "python -u bench.py --steps 5 --warmup 2 --no-cpu-baseline --quick-data --profile-only",
     "pmc": "rocprofv3 --pmc <COUNTER> --output-format csv -d <dir>/pmc_<name> -o pmc -- "
            "python -u bench.py --steps 1 --warmup 1 --no-cpu-baseline --quick-data --profile-only --calib-copy "
-           "(one pass per counter: FETCH_SIZE, then WRITE_SIZE)",
+           "(one pass per counter: FETCH_SIZE, then WRITE_SIZE; then one pass of SQ_INSTS_VALU SQ_INSTS_LDS "
+           "SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_LDS SQ_WAVES without --calib-copy, into <dir>/pmc_sq)",
 }
 
 
