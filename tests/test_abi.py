@@ -76,6 +76,7 @@ def test_null_arguments():
     assert L.backproject(None, None, 0, None, 1.0, 0.0, None) == _lib.EARG
     assert L.forward_project(None, None, None, 1.0, None) == _lib.EARG
     assert L.pyhst_opnorm(None, 1, 1.0, None, None, None, None) == _lib.EARG
+    assert L.pyhst_plan_set_bp_slices(None, 2) == _lib.EARG
     assert L.pyhst_patch_fista(None, None, None) == _lib.EARG
     assert L.pyhst_patch_lipschitz(None, None, None) == _lib.EARG
     assert L.pyhst_unet_set_scale(None, 1.0) == _lib.EARG
